@@ -1,0 +1,297 @@
+/*
+ * Oracle: trap and wall forces, direct Coulomb sum, the cyclotronic
+ * integrator, Philox4x32-10 and the Poisson photon-recoil kicks.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Plain FP64 loops; OpenMP only
+ * splits independent per-ion loops, never a reduction.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+/* ---------------------------------------------------------------------
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies with the
+ * published multipliers, the key bumped by the published Weyl constants
+ * between rounds.  The paper under test only asks for Poisson-distributed
+ * photon counts and random unit vectors (Sec. 2.2); the counter-based
+ * generator makes the draws a pure function of (seed, ion, step, slot).
+ * ------------------------------------------------------------------- */
+void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        if (round < 9) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* A double in [0,1) from 53 bits of two words: 27 high bits of w0, 26 of w1. */
+static double or_u53(uint32_t w0, uint32_t w1)
+{
+    double hi = (double)(w0 >> 5);
+    double lo = (double)(w1 >> 6);
+    return (hi * 67108864.0 + lo) * (1.0 / 9007199254740992.0);
+}
+
+static void or_draw(uint64_t seed, uint32_t ion, uint64_t step, uint32_t slot, uint32_t w[4])
+{
+    uint32_t ctr[4] = {ion, (uint32_t)step, (uint32_t)(step >> 32), slot};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    or_philox4x32_10(ctr, key, w);
+}
+
+/* Cumulative Poisson table F_0..F_16 for mean lam, accumulated term by term:
+ * p_0 = exp(-lam), p_k = p_{k-1} lam / k, F_k = F_{k-1} + p_k. */
+void or_poisson_cdf(double lam, double F[17])
+{
+    double pk = exp(-lam);
+    double acc = pk;
+    F[0] = acc;
+    for (int k = 1; k <= 16; ++k) {
+        pk = pk * lam / (double)k;
+        acc = acc + pk;
+        F[k] = acc;
+    }
+}
+
+/* Photon count by inversion: the smallest k with u < F_k, capped at 16. */
+static int or_poisson_count(double u, const double F[17])
+{
+    for (int k = 0; k <= 16; ++k)
+        if (u < F[k]) return k;
+    return 16;
+}
+
+/* Photon counts for every ion at one step (slot 0 of each ion's stream). */
+void or_photon_counts(int n, uint64_t seed, uint64_t step, double mean, int32_t *counts)
+{
+    double F[17];
+    or_poisson_cdf(mean, F);
+    for (int i = 0; i < n; ++i) {
+        uint32_t w[4];
+        or_draw(seed, (uint32_t)i, step, 0u, w);
+        counts[i] = or_poisson_count(or_u53(w[0], w[1]), F);
+    }
+}
+
+/* Sum of n isotropic unit vectors of ion `ion` at `step`, slots 1..n
+ * (cos(theta) uniform in [-1,1], azimuth uniform in [0, 2 pi)). */
+static void or_recoil_dirs(uint64_t seed, uint32_t ion, uint64_t step, int n, double acc[3])
+{
+    acc[0] = acc[1] = acc[2] = 0.0;
+    for (int j = 1; j <= n; ++j) {
+        uint32_t w[4];
+        or_draw(seed, ion, step, (uint32_t)j, w);
+        double ct = 2.0 * or_u53(w[0], w[1]) - 1.0;
+        double ph = 2.0 * OR_PI * or_u53(w[2], w[3]);
+        double st = sqrt(1.0 - ct * ct);
+        acc[0] += st * cos(ph);
+        acc[1] += st * sin(ph);
+        acc[2] += ct;
+    }
+}
+
+/* ---------------------------------------------------------------------
+ * External forces (Sec. 2.1).  phi_trap = k_z (2z^2 - x^2 - y^2)/4 with
+ * k_z = m omega_z^2 / q; the force on charge q is -q grad(phi).
+ * phi_wall = k_z delta (x^2 + y^2) cos(2(varphi + omega_r t)) / 4, and
+ * r^2 cos(2 varphi + 2 omega_r t) = (x^2 - y^2) C - 2 x y S with
+ * C = cos(2 omega_r t), S = sin(2 omega_r t).
+ * ------------------------------------------------------------------- */
+void or_external_force(double q, double m, const or_trap *tr, double t, const double x[3], double F[3])
+{
+    double kz = m * tr->omega_z * tr->omega_z / q;
+    double C = cos(2.0 * tr->omega_r * t);
+    double S = sin(2.0 * tr->omega_r * t);
+    /* -q d/dx of the trap term, then of the wall term */
+    F[0] = 0.5 * q * kz * x[0] - 0.5 * q * kz * tr->delta * (x[0] * C - x[1] * S);
+    F[1] = 0.5 * q * kz * x[1] + 0.5 * q * kz * tr->delta * (x[1] * C + x[0] * S);
+    F[2] = -q * kz * x[2];
+}
+
+/* Coulomb force by the direct pairwise sum: the gradient of the pair term of
+ * eq. (hamiltonian); the 1/(8 pi eps0) there counts each pair twice, so the
+ * force on i is k_e q^2 sum_{j != i} (x_i - x_j)/|x_i - x_j|^3.  A pair at
+ * zero separation contributes nothing.  pos, F: n x 3 row-major. */
+void or_coulomb_direct(int n, const double *pos, double q, double *F)
+{
+    double ke = 1.0 / (4.0 * OR_PI * OR_EPS0);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < n; ++i) {
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = pos[3 * i] - pos[3 * j];
+            double dy = pos[3 * i + 1] - pos[3 * j + 1];
+            double dz = pos[3 * i + 2] - pos[3 * j + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;
+            double r = sqrt(r2);
+            double w = 1.0 / (r2 * r);
+            fx += dx * w;
+            fy += dy * w;
+            fz += dz * w;
+        }
+        F[3 * i] = ke * q * q * fx;
+        F[3 * i + 1] = ke * q * q * fy;
+        F[3 * i + 2] = ke * q * q * fz;
+    }
+}
+
+/* Direct Coulomb sum for a subset of target ions (used for sampled checks
+ * at sizes where the full sum is too slow). */
+void or_coulomb_direct_sampled(int n, const double *pos, double q, int ns, const int32_t *idx, double *F)
+{
+    double ke = 1.0 / (4.0 * OR_PI * OR_EPS0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int a = 0; a < ns; ++a) {
+        int i = idx[a];
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = pos[3 * i] - pos[3 * j];
+            double dy = pos[3 * i + 1] - pos[3 * j + 1];
+            double dz = pos[3 * i + 2] - pos[3 * j + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;
+            double r = sqrt(r2);
+            double w = 1.0 / (r2 * r);
+            fx += dx * w;
+            fy += dy * w;
+            fz += dz * w;
+        }
+        F[3 * a] = ke * q * q * fx;
+        F[3 * a + 1] = ke * q * q * fy;
+        F[3 * a + 2] = ke * q * q * fz;
+    }
+}
+
+/* Coulomb potential energy (1/2) sum_i q phi_coul(x_i) = k_e q^2 sum_{i<j} 1/r_ij. */
+double or_coulomb_energy(int n, const double *pos, double q)
+{
+    double ke = 1.0 / (4.0 * OR_PI * OR_EPS0);
+    double e = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            double dx = pos[3 * i] - pos[3 * j];
+            double dy = pos[3 * i + 1] - pos[3 * j + 1];
+            double dz = pos[3 * i + 2] - pos[3 * j + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r > 0.0) e += 1.0 / r;
+        }
+    return ke * q * q * e;
+}
+
+/* Lab-frame energy of eq. (hamiltonian) with delta = 0: kinetic energy
+ * (p - qA)^2/2m = m v^2/2, trap energy q phi_trap, Coulomb pair energy. */
+double or_energy(int n, const double *pos, const double *vel, double q, double m, const or_trap *tr)
+{
+    double kz = m * tr->omega_z * tr->omega_z / q;
+    double ek = 0.0, et = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double *x = pos + 3 * i, *v = vel + 3 * i;
+        ek += 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        et += q * 0.25 * kz * (2.0 * x[2] * x[2] - x[0] * x[0] - x[1] * x[1]);
+    }
+    return ek + et + or_coulomb_energy(n, pos, q);
+}
+
+/* ---------------------------------------------------------------------
+ * U0(tau), eq. (U0): exact motion of a charge in the uniform field B z-hat
+ * with no electric field.  m dv/dt = q v x B gives dvx/dt = wc vy,
+ * dvy/dt = -wc vx (wc = qB/m), i.e. clockwise gyration for q B > 0; the
+ * printed matrix has the opposite rotation sense and a zero (6,6) entry,
+ * read here as the Lorentz solution with v_z conserved.  z drifts freely.
+ * ------------------------------------------------------------------- */
+void or_u0(int n, double *pos, double *vel, double wc, double tau)
+{
+    for (int i = 0; i < n; ++i) {
+        double *x = pos + 3 * i, *v = vel + 3 * i;
+        double vx = v[0], vy = v[1];
+        if (wc == 0.0) {
+            x[0] += vx * tau;
+            x[1] += vy * tau;
+        } else {
+            double c = cos(wc * tau), s = sin(wc * tau);
+            x[0] += (vx * s + vy * (1.0 - c)) / wc;
+            x[1] += (vx * (c - 1.0) + vy * s) / wc;
+            v[0] = vx * c + vy * s;
+            v[1] = -vx * s + vy * c;
+        }
+        x[2] += v[2] * tau;
+    }
+}
+
+/* Coulomb force by the FMM (fmm.c). */
+int or_fmm_coulomb(int n, const double *pos, double q, int p, int leaf_size, double *F);
+
+/* One full step per eqs. (time_ev2) and (velocity_kick): U0(dt/2), kick with
+ * trap + wall + Coulomb forces at the midpoint time t + dt/2 plus photon
+ * recoils, U0(dt/2).  The step index `step` keys the photon streams and the
+ * time is t = t0 + step dt.  photons (nullable) receives the counts. */
+int or_step(int n, double *pos, double *vel, double q, double m, const or_trap *tr, const or_laser *la,
+            const or_force *fo, double t0, double dt, uint64_t seed, uint64_t step, int32_t *photons)
+{
+    double wc = q * tr->B / m;
+    double t = t0 + (double)step * dt;
+    double tm = t + 0.5 * dt;
+    double *Fc = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!Fc) return -2;
+    or_u0(n, pos, vel, wc, 0.5 * dt);
+    if (fo->method == 0) {
+        or_coulomb_direct(n, pos, q, Fc);
+    } else {
+        int rc = or_fmm_coulomb(n, pos, q, fo->p, fo->leaf_size, Fc);
+        if (rc) { free(Fc); return rc; }
+    }
+    double F[17];
+    int laser_on = la && la->mean_per_step > 0.0;
+    if (laser_on) or_poisson_cdf(la->mean_per_step, F);
+    double recoil = laser_on ? OR_H_PLANCK / (la->wavelength * m) : 0.0;
+    for (int i = 0; i < n; ++i) {
+        double fe[3];
+        or_external_force(q, m, tr, tm, pos + 3 * i, fe);
+        for (int d = 0; d < 3; ++d) vel[3 * i + d] += (fe[d] + Fc[3 * i + d]) * dt / m;
+        int cnt = 0;
+        if (laser_on) {
+            uint32_t w[4];
+            or_draw(seed, (uint32_t)i, step, 0u, w);
+            cnt = or_poisson_count(or_u53(w[0], w[1]), F);
+            double acc[3];
+            or_recoil_dirs(seed, (uint32_t)i, step, cnt, acc);
+            for (int d = 0; d < 3; ++d) vel[3 * i + d] += recoil * acc[d];
+        }
+        if (photons) photons[i] = cnt;
+    }
+    or_u0(n, pos, vel, wc, 0.5 * dt);
+    free(Fc);
+    return 0;
+}
+
+/* nsteps consecutive steps starting at step index step0. */
+int or_run(int n, double *pos, double *vel, double q, double m, const or_trap *tr, const or_laser *la,
+           const or_force *fo, double t0, double dt, uint64_t seed, uint64_t step0, int nsteps, int32_t *photons)
+{
+    for (int s = 0; s < nsteps; ++s) {
+        int rc = or_step(n, pos, vel, q, m, tr, la, fo, t0, dt, seed, step0 + (uint64_t)s, photons);
+        if (rc) return rc;
+    }
+    return 0;
+}

@@ -1,0 +1,529 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against a value it does not compute itself: a
+closed form, a published known-answer vector, a library routine in a special
+case, brute force on a tiny input, or an invariant.  Citations name the
+section / equation of Zaris et al., arXiv 2405.13973.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, linalg, special, stats
+
+from oracle import oracle as O
+from paper_2405_13973_amd import inputs
+
+Q = O.E_CHARGE
+M = 9.0 * O.AMU
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ Philox
+def test_philox_known_answers():
+    """Philox4x32-10 against the generator's published known-answer vectors."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) if l.strip() and l[0] != "#"]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = O.philox4x32_10(v[0:4], v[4:6])
+        assert out.tolist() == v[6:10]
+
+
+# ------------------------------------------------- Poisson photon model
+@pytest.mark.parametrize("lam", [0.0, 0.01, 0.05, 0.7, 3.0])
+def test_poisson_cdf_matches_library(lam):
+    """Inversion table = Poisson CDF (scipy.stats) for k <= 16 (Sec. 2.2: counts are Poisson)."""
+    F = O.poisson_cdf(lam)
+    ref = stats.poisson.cdf(np.arange(17), lam) if lam > 0 else np.ones(17)
+    np.testing.assert_allclose(F, ref, rtol=1e-13, atol=1e-15)
+
+
+def test_photon_counts_statistics():
+    """Counts have mean and variance lambda (CLT bounds) and Poisson frequencies (chi-square)."""
+    lam, n = 0.05, 200000
+    c = O.photon_counts(n, seed=12345, step=7, mean=lam)
+    assert abs(c.mean() - lam) < 5 * math.sqrt(lam / n)
+    assert abs(c.var() - lam) < 5 * math.sqrt(2 * lam * lam / n + lam / n)
+    obs = np.bincount(c, minlength=3)[:3].astype(float)
+    obs = np.append(obs, n - obs.sum())
+    pk = stats.poisson.pmf([0, 1, 2], lam)
+    exp = n * np.append(pk, 1 - pk.sum())
+    keep = exp > 5
+    chi2 = (((obs - exp) ** 2) / exp)[keep].sum()
+    assert chi2 < stats.chi2.ppf(0.9999, keep.sum() - 1)
+    # counter-based: a different step gives different draws, the same step the same
+    assert not np.array_equal(c, O.photon_counts(n, 12345, 8, lam))
+    assert np.array_equal(c, O.photon_counts(n, 12345, 7, lam))
+
+
+def test_recoil_heating_closed_form():
+    """eq. (laser_kick), isotropic part: with no other force each photon adds a
+    random unit vector times h/(lambda m), so <|dv|^2> per ion per step = lambda (h/lambda m)^2
+    and <dv> = 0 (B only, ions 1 m apart so Coulomb is negligible)."""
+    n, steps, lam, wl = 400, 50, 0.05, 313e-9
+    pos = np.zeros((n, 3))
+    pos[:, 0] = np.arange(n) * 1.0
+    vel = np.zeros((n, 3))
+    trap = dict(B=4.5, omega_z=0.0)
+    p1, v1 = O.run(pos, vel, Q, M, trap, 1e-9, steps, seed=99, laser=dict(mean_per_step=lam, wavelength=wl))
+    k = O.H_PLANCK / (wl * M)
+    assert abs(k - 0.14165) < 1e-4
+    # B rotates v but preserves |v|^2 and the sum of independent isotropic kicks
+    dv2 = (v1 ** 2).sum(axis=1)
+    expected = steps * lam * k * k
+    draws = n * steps * lam
+    assert abs(dv2.mean() - expected) < 6 * expected / math.sqrt(draws)
+    assert np.abs(v1.mean(axis=0)).max() < 6 * k * math.sqrt(steps * lam / 3 / n)
+
+
+def test_recoil_direction_isotropic():
+    """Random unit vectors: each component has mean 0 and variance 1/3 (uniform on the sphere)."""
+    n, lam, wl = 20000, 1.0, 313e-9
+    pos = np.zeros((n, 3))
+    pos[:, 0] = np.arange(n) * 10.0
+    trap = dict(B=0.0, omega_z=0.0)
+    # one step, B = 0: v = k * (sum of n_i unit vectors); use ions with exactly one photon
+    _, v1, ph = O.run(pos, np.zeros((n, 3)), Q, M, trap, 1e-9, 1, seed=5,
+                      laser=dict(mean_per_step=lam, wavelength=wl), return_photons=True)
+    k = O.H_PLANCK / (wl * M)
+    u = v1[ph == 1] / k
+    np.testing.assert_allclose(np.linalg.norm(u, axis=1), 1.0, rtol=1e-6)
+    m = len(u)
+    assert np.abs(u.mean(axis=0)).max() < 5 / math.sqrt(3 * m)
+    assert np.abs((u ** 2).mean(axis=0) - 1 / 3).max() < 5 * math.sqrt(4 / 45 / m)
+
+
+# ---------------------------------------------------------- forces
+def test_two_ion_force():
+    """eq. (hamiltonian) pair term: F = k_e q^2 / r^2 along the separation."""
+    a = np.array([1e-5, -2e-5, 3e-5])
+    b = np.array([4e-5, 2e-5, -1e-5])
+    F = O.coulomb_direct(np.stack([a, b]), Q)
+    r = a - b
+    ref = 8.9875517862e9 * Q * Q / np.dot(r, r) * r / np.linalg.norm(r)
+    np.testing.assert_allclose(F[0], ref, rtol=1e-9)
+    np.testing.assert_allclose(F[1], -ref, rtol=1e-9)
+
+
+def test_direct_newton_third_law():
+    g = inputs.rng(3)
+    pos = inputs.uniform_ball(500, 1e-4, g)
+    F = O.coulomb_direct(pos, Q)
+    assert np.linalg.norm(F.sum(axis=0)) / np.linalg.norm(F, axis=1).sum() < 1e-13
+
+
+def test_gauss_sphere_interior_field():
+    """A uniformly charged ball: interior field k_e Q r / R^3, radial (Gauss's law).
+    Lattice ions fill the ball; the discreteness error is a few (a/R)."""
+    a = 1e-6
+    R = 12 * a
+    g = np.arange(-13, 14) * a
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    pos = pos[np.linalg.norm(pos, axis=1) <= R]
+    Qtot = len(pos) * Q
+    Reff = (3 * len(pos) * a ** 3 / (4 * math.pi)) ** (1 / 3)
+    F = O.coulomb_direct(pos, Q)
+    r = np.linalg.norm(pos, axis=1)
+    inner = (r > 2 * a) & (r < 0.6 * R)
+    ref = O.K_E * Qtot * Q / Reff ** 3 * pos[inner]
+    err = np.linalg.norm(F[inner] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert np.median(err) < 0.1
+
+
+def test_wall_force_is_gradient_of_polar_form():
+    """eq. (pot_wall) in polar form; force = -q grad, by central differences."""
+    trap = dict(B=4.5, omega_z=2 * math.pi * 1.5e6, delta=0.01, omega_r=2 * math.pi * 180e3)
+    kz = M * trap["omega_z"] ** 2 / Q
+    t = 3.7e-7
+
+    def phi(x):
+        r2 = x[0] ** 2 + x[1] ** 2
+        ang = math.atan2(x[1], x[0])
+        return 0.25 * kz * (2 * x[2] ** 2 - r2) + 0.25 * kz * trap["delta"] * r2 * math.cos(2 * (ang + trap["omega_r"] * t))
+
+    x = np.array([3e-5, -4e-5, 2e-5])
+    h = 1e-9
+    grad = np.array([(phi(x + h * e) - phi(x - h * e)) / (2 * h) for e in np.eye(3)])
+    np.testing.assert_allclose(O.external_force(Q, M, trap, t, x), -Q * grad, rtol=1e-6)
+
+
+# ------------------------------------------------------ expansions
+def _ylm_gr(n, m, theta, phi):
+    """Y_n^m of eq. (FMM_coul): sqrt((n-|m|)!/(n+|m|)!) P_n^|m| e^{im phi}, from scipy's lpmv
+    (which carries the Condon-Shortley sign, removed here)."""
+    am = abs(m)
+    P = (-1) ** am * special.lpmv(am, n, np.cos(theta))
+    return math.sqrt(math.factorial(n - am) / math.factorial(n + am)) * P * np.exp(1j * m * phi)
+
+
+def _cluster(nq=12, seed=0):
+    g = np.random.default_rng(seed)
+    return g.uniform(-0.5, 0.5, (nq, 3)), g.uniform(0.5, 1.5, nq)
+
+
+def test_multipole_error_bound():
+    """eq. (multipole_error): |phi - phi_p| <= A/(rho - sqrt(3/4) a) (sqrt(3/4) a / rho)^(p+1),
+    A = sum |q|, charges in a cube of side a centred on the origin."""
+    src, q = _cluster()
+    A = q.sum()
+    g = np.random.default_rng(1)
+    for p in (2, 4, 8, 12):
+        Mc = O.p2m(src, q, np.zeros(3), p)
+        for _ in range(20):
+            d = g.normal(size=3)
+            x = d / np.linalg.norm(d) * g.uniform(1.0, 4.0)
+            rho = np.linalg.norm(x)
+            exact = (q / np.linalg.norm(x[None] - src, axis=1)).sum()
+            err = abs(O.eval_me(Mc, np.zeros(3), x, p) - exact)
+            s = math.sqrt(0.75)
+            assert err <= A / (rho - s) * (s / rho) ** (p + 1) * (1 + 1e-9) + 1e-13
+
+
+def test_m2m_equals_p2m_of_union():
+    """M2M is exact: shifting a child's expansion to the parent centre equals P2M about the parent."""
+    src, q = _cluster()
+    p = 10
+    c_child = np.array([0.0, 0.0, 0.0])
+    c_par = np.array([0.5, -0.5, 0.5])
+    shifted = O.m2m(O.p2m(src, q, c_child, p), c_child, c_par, p)
+    direct = O.p2m(src, q, c_par, p)
+    assert np.abs(shifted - direct).max() <= 1e-12 * np.abs(direct).max()
+
+
+def test_l2l_is_exact_recentring():
+    """L2L re-centres the degree-p local polynomial exactly: same potential and gradient."""
+    src, q = _cluster()
+    p = 10
+    cS = np.array([4.0, 0.0, 0.0])
+    cT = np.zeros(3)
+    L = O.m2l(O.p2m(src + cS, q, cS, p), cS, cT, p)
+    cN = np.array([0.25, -0.25, 0.25])
+    L2 = O.l2l(L, cT, cN, p)
+    for x in ([0.3, -0.1, 0.2], [0.1, 0.4, -0.3]):
+        a, ga = O.eval_le(L, cT, np.array(x), p)
+        b, gb = O.eval_le(L2, cN, np.array(x), p)
+        assert abs(a - b) < 1e-13 * abs(a)
+        np.testing.assert_allclose(ga, gb, rtol=1e-11, atol=1e-13 * np.abs(ga).max())
+
+
+def test_m2l_monopole_special_case():
+    """One charge at the source centre: L_n^m = q Y_n^{-m}(alpha, beta) / rho^{n+1}, where
+    (rho, alpha, beta) is the source centre relative to the target centre
+    (the Legendre addition theorem)."""
+    p = 8
+    cS = np.array([1.3, -2.1, 2.7])
+    Mc = np.zeros((p + 1) ** 2, complex)
+    Mc[0] = 2.5
+    L = O.m2l(Mc, cS, np.zeros(3), p)
+    rho = np.linalg.norm(cS)
+    al = math.acos(cS[2] / rho)
+    be = math.atan2(cS[1], cS[0])
+    for n in range(p + 1):
+        for m in range(-n, n + 1):
+            ref = 2.5 * _ylm_gr(n, -m, al, be) / rho ** (n + 1)
+            assert abs(L[n * n + n + m] - ref) < 1e-13 * max(1.0, abs(ref))
+
+
+def test_m2l_quadrature_projection():
+    """eq. (FMM_local): the local coefficients of the truncated multipole potential f
+    equal its projection on a small sphere of radius r about the target centre,
+    L_n^m r^n = (2n+1)/(4 pi) * integral f conj(Y_n^m) dOmega (orthogonality of Y_n^m
+    with norm 4 pi/(2n+1)); Gauss-Legendre in cos(theta) x trapezoid in phi."""
+    src, q = _cluster(8, 3)
+    p = 6
+    cS = np.array([0.0, 0.0, 0.0])
+    cT = np.array([2.0, -1.0, 1.0])
+    Mc = O.p2m(src, q, cS, p)
+    L = O.m2l(Mc, cS, cT, p)
+    r = 0.5  # f is analytic for |x - cT| < 1.58 (cluster radius 0.87, centres 2.45 apart)
+    nq = 2 * p + 40
+    xg, wg = special.roots_legendre(nq)
+    phis = np.arange(2 * nq) * (2 * math.pi / (2 * nq))
+    TH, PH = np.meshgrid(np.arccos(xg), phis, indexing="ij")
+    W = np.repeat(wg[:, None], len(phis), 1) * (2 * math.pi / (2 * nq))
+    pts = cT + r * np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], -1)
+    f = np.array([[O.eval_me(Mc, cS, x, p) for x in row] for row in pts])
+    for n in range(p + 1):
+        for m in range(-n, n + 1):
+            proj = (2 * n + 1) / (4 * math.pi) * (W * f * np.conj(_ylm_gr(n, m, TH, PH))).sum() / r ** n
+            ref = L[n * n + n + m]
+            assert abs(proj - ref) * r ** n < 1e-12 * abs(L[0])
+
+
+def test_local_gradient_matches_finite_difference():
+    src, q = _cluster()
+    p = 10
+    cS = np.array([0.0, 3.0, 0.0])
+    L = O.m2l(O.p2m(src + cS, q, cS, p), cS, np.zeros(3), p)
+    x = np.array([0.2, -0.15, 0.1])
+    _, g = O.eval_le(L, np.zeros(3), x, p)
+    h = 1e-5
+    fd = np.array([(O.eval_le(L, np.zeros(3), x + h * e, p)[0] - O.eval_le(L, np.zeros(3), x - h * e, p)[0]) / (2 * h)
+                   for e in np.eye(3)])
+    np.testing.assert_allclose(g, fd, rtol=1e-7)
+    # and it is the field of the source cluster to truncation accuracy
+    d = x[None] - (src + cS)
+    exact = -(q[:, None] * d / np.linalg.norm(d, axis=1)[:, None] ** 3).sum(0)
+    np.testing.assert_allclose(g, exact, rtol=1e-5)
+
+
+# ------------------------------------------------------------- FMM
+def test_fmm_error_decreases_geometrically_in_p():
+    g = inputs.rng(11)
+    pos = inputs.uniform_ball(200, 1e-4, g)
+    Fd = O.coulomb_direct(pos, Q)
+    errs = []
+    for p in (2, 4, 6, 8, 10, 14, 18):
+        Ff = O.fmm_coulomb(pos, Q, p, 4)
+        errs.append(math.sqrt(((Ff - Fd) ** 2).sum() / (Fd ** 2).sum()))
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    # one-box separation: worst-case ratio per degree is sqrt(3)/2, typical about 0.6
+    rate = (errs[-1] / errs[0]) ** (1.0 / 16)
+    assert 0.3 < rate < 0.75, (rate, errs)
+    assert errs[-1] < 5e-7, errs
+
+
+def test_fmm_single_leaf_is_direct():
+    """leaf_size >= N: one box, no expansions used, the direct sum exactly."""
+    g = inputs.rng(12)
+    pos = inputs.uniform_ball(300, 1e-4, g)
+    Fd = O.coulomb_direct(pos, Q)
+    Ff = O.fmm_coulomb(pos, Q, 4, 300)
+    np.testing.assert_allclose(Ff, Fd, rtol=1e-12, atol=1e-12 * np.abs(Fd).max())
+
+
+def test_fmm_net_force_near_zero():
+    g = inputs.rng(13)
+    pos = inputs.uniform_ball(2000, 1e-4, g)
+    F = O.fmm_coulomb(pos, Q, 8, 32)
+    assert np.linalg.norm(F.sum(0)) / np.linalg.norm(F, axis=1).sum() < 1e-5
+
+
+def test_fmm_sampled_equals_full():
+    g = inputs.rng(14)
+    pos = inputs.uniform_ball(1500, 1e-4, g)
+    F = O.fmm_coulomb(pos, Q, 6, 16)
+    idx = np.array([0, 17, 400, 1499, 777])
+    Fs = O.fmm_coulomb_sampled(pos, Q, 6, 16, idx)
+    np.testing.assert_array_equal(Fs, F[idx])
+
+
+# ------------------------------------------------------------- tree
+def _interleave(k):
+    """Bit interleave of three 21-bit ints, x highest of each triple (numpy, bit by bit)."""
+    key = np.zeros(len(k), np.uint64)
+    for b in range(21):
+        for d in range(3):
+            bit = (k[:, d].astype(np.uint64) >> np.uint64(b)) & np.uint64(1)
+            key |= bit << np.uint64(3 * b + (2 - d))
+    return key
+
+
+def test_morton_keys_match_numpy_interleave():
+    g = inputs.rng(21)
+    pos = inputs.uniform_ellipsoid(10000, (3e-4, 3e-4, 1.5e-4), g)
+    keys, root = O.morton_keys(pos)
+    lo, hi = pos.min(0), pos.max(0)
+    W = (hi - lo).max()
+    o = 0.5 * (lo + hi) - 0.5 * W
+    assert np.array_equal(o, root[:3]) and W == root[3]
+    kq = np.clip(np.floor((pos - o) * (2.0 ** 21 / W)), 0, 2 ** 21 - 1).astype(np.int64)
+    assert np.array_equal(keys, _interleave(kq))
+
+
+def _ancestor(T, b, lev):
+    while T["level"][b] > lev:
+        b = T["parent"][b]
+    return b
+
+
+@pytest.mark.parametrize("n,s,kind", [(1, 1, "ball"), (7, 2, "ball"), (700, 8, "ball"), (2000, 32, "ell"),
+                                       (600, 4, "clumps")])
+def test_tree_and_lists(n, s, kind):
+    g = inputs.rng(100 + n)
+    if kind == "ball":
+        pos = inputs.uniform_ball(n, 1e-4, g)
+    elif kind == "ell":
+        pos = inputs.uniform_ellipsoid(n, (3e-4, 3e-4, 1.5e-4), g)
+    else:  # strongly non-uniform: three clumps of different scale (adaptive W/X lists)
+        pos = np.concatenate([inputs.uniform_ball(n // 3, 1e-4, g), 3e-4 + inputs.uniform_ball(n // 3, 3e-6, g),
+                              -2e-4 + inputs.uniform_ball(n - 2 * (n // 3), 2e-5, g)])
+    T = O.tree(pos, s)
+    keys = T["key"]
+    perm = T["perm"]
+    # permutation sorts by (key, id)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    assert np.array_equal(perm, np.lexsort((np.arange(n), keys)))
+    nb = len(T["level"])
+    # boxes: ranges, prefixes, split rule
+    for b in range(nb):
+        lv = T["level"][b]
+        ids = perm[T["ion_begin"][b]:T["ion_end"][b]]
+        assert len(ids) > 0
+        pref = keys[ids] >> np.uint64(3 * (21 - lv))
+        assert (pref == pref[0]).all()
+        c = T["coords"][b]
+        assert int(pref[0]) == int(_interleave(c[None].astype(np.int64))[0]) if lv > 0 else True
+        if T["is_leaf"][b]:
+            assert len(ids) <= s or lv == 21
+        else:
+            assert len(ids) > s
+        if b > 0:
+            pa = T["parent"][b]
+            assert T["level"][pa] == lv - 1
+            assert T["ion_begin"][pa] <= T["ion_begin"][b] < T["ion_end"][b] <= T["ion_end"][pa]
+    leaves = np.nonzero(T["is_leaf"])[0]
+    covered = np.zeros(n, int)
+    for b in leaves:
+        covered[T["ion_begin"][b]:T["ion_end"][b]] += 1
+    assert (covered == 1).all()
+    # list constructions agree as sets
+    v1 = {(b, int(s_)) for b in range(nb) for s_ in T["v_src"][T["v_off"][b]:T["v_off"][b + 1]]}
+    v2 = {tuple(x) for x in T["dual_v_pairs"].tolist()}
+    assert v1 == v2
+    n1 = {(b, int(s_)) for b in leaves for s_ in T["near_src"][T["near_off"][b]:T["near_off"][b + 1]]}
+    n2 = {tuple(x) for x in T["dual_near_pairs"].tolist()}
+    assert n1 == n2
+    # every ordered ion pair covered exactly once: by one V pair between ancestors, or by P2P
+    if n <= 2000:
+        slot_leaf = np.zeros(n, int)
+        for b in leaves:
+            slot_leaf[T["ion_begin"][b]:T["ion_end"][b]] = b
+        leafpair_cnt = {}
+        for (t_, s_) in v1:
+            pass
+        anc = {}
+        for b in leaves:
+            chain = []
+            x = b
+            while x >= 0:
+                chain.append(x)
+                x = T["parent"][x]
+            anc[b] = chain
+        cover = {}
+        for a in leaves:
+            for b in leaves:
+                c = sum((x, y) in v1 for x in anc[a] for y in anc[b]) + ((a, b) in n1)
+                cover[(a, b)] = c
+        assert all(v == 1 for v in cover.values())
+
+
+def test_tree_coincident_ions_terminate_at_level_21():
+    """Q11-type degenerate input: many identical positions cannot be split; leaves stop at level 21."""
+    pos = np.zeros((40, 3))
+    pos[:20] = 1e-5
+    T = O.tree(pos, 4)
+    assert T["level"].max() == 21
+    assert T["is_leaf"][T["level"] == 21].all()
+    F = O.fmm_coulomb(pos, Q, 4, 4)
+    assert np.isfinite(F).all()
+
+
+# ------------------------------------------------------- integrator
+def _lorentz_rhs(q, m, B, wz):
+    """Continuous equations of motion for one ion: trap force + v x B (Sec. 2.1)."""
+    wc = q * B / m
+
+    def f(t, y):
+        x, v = y[:3], y[3:]
+        a = np.array([0.5 * wz ** 2 * x[0], 0.5 * wz ** 2 * x[1], -wz ** 2 * x[2]])
+        a += wc * np.array([v[1], -v[0], 0.0])
+        return np.concatenate([v, a])
+    return f
+
+
+def test_u0_free_gyration_matches_ode():
+    """U0 (eq. U0) is the exact flow of m dv/dt = q v x B: compare with a tight ODE solve."""
+    B = 4.5
+    wc = Q * B / M
+    x0 = np.array([[1e-5, -2e-5, 3e-5]])
+    v0 = np.array([[3.0, -1.5, 2.0]])
+    tau = 7.3e-7
+    x1, v1 = O.u0(x0, v0, wc, tau)
+    sol = integrate.solve_ivp(_lorentz_rhs(Q, M, B, 0.0), (0, tau), np.concatenate([x0[0], v0[0]]), rtol=1e-13,
+                              atol=1e-18, method="DOP853")
+    np.testing.assert_allclose(x1[0], sol.y[:3, -1], rtol=1e-9, atol=1e-16)
+    np.testing.assert_allclose(v1[0], sol.y[3:, -1], rtol=1e-9)
+
+
+def test_free_ion_steps_are_exact_helix():
+    """No electric field: every step is U0(dt/2) U0(dt/2) = U0(dt), so n steps give the
+    closed-form helix at t = n dt to rounding."""
+    B, dt, nst = 3.0, 1e-9, 2000
+    wc = Q * B / M
+    x0 = np.array([[2e-5, 1e-5, -1e-5]])
+    v0 = np.array([[1.0, 2.0, -0.5]])
+    x1, v1 = O.run(x0, v0, Q, M, dict(B=B, omega_z=0.0), dt, nst)
+    t = nst * dt
+    c, s = math.cos(wc * t), math.sin(wc * t)
+    vx, vy, vz = v0[0]
+    ref_x = x0[0] + np.array([(vx * s + vy * (1 - c)) / wc, (vx * (c - 1) + vy * s) / wc, vz * t])
+    np.testing.assert_allclose(x1[0], ref_x, rtol=1e-11, atol=1e-17)
+    np.testing.assert_allclose(v1[0], [vx * c + vy * s, -vx * s + vy * c, vz], rtol=1e-11)
+
+
+def test_axial_discrete_frequency():
+    """Single ion, axial motion: drift-kick-drift of a harmonic oscillator is a linear map with
+    det 1 and trace 2 cos(theta), cos(theta) = 1 - (w_z dt)^2 / 2, so
+    z_n = z_0 cos(n theta) + (z_1 - z_0 cos theta) sin(n theta) / sin theta."""
+    wz = 2 * math.pi * 1.5e6
+    dt = 5e-9
+    x = np.array([[0.0, 0.0, 4e-6]])
+    v = np.array([[0.0, 0.0, 1.0]])
+    zs = [x[0, 2]]
+    for k in range(200):
+        x, v = O.run(x, v, Q, M, dict(B=4.5, omega_z=wz), dt, 1, step0=k)
+        zs.append(x[0, 2])
+    zs = np.array(zs)
+    th = math.acos(1 - (wz * dt) ** 2 / 2)
+    n = np.arange(len(zs))
+    ref = zs[0] * np.cos(n * th) + (zs[1] - zs[0] * math.cos(th)) * np.sin(n * th) / math.sin(th)
+    np.testing.assert_allclose(zs, ref, rtol=0, atol=1e-12 * np.abs(zs).max())
+
+
+def test_planar_motion_second_order_vs_exact_flow():
+    """Single ion in trap + B: the split-operator step (eq. time_ev2) converges to the exact
+    linear flow exp(A t) at second order in dt (error ratio ~4 per halving)."""
+    B, wz = 4.5, 2 * math.pi * 1.5e6
+    wc = Q * B / M
+    A = np.zeros((6, 6))
+    A[0:3, 3:6] = np.eye(3)
+    A[3, 0] = A[4, 1] = 0.5 * wz ** 2
+    A[5, 2] = -wz ** 2
+    A[3, 4] = wc
+    A[4, 3] = -wc
+    y0 = np.array([2e-5, -1e-5, 5e-6, 1.0, 0.5, -0.3])
+    T = 2e-6
+    exact = linalg.expm(A * T) @ y0
+    errs = []
+    for dt in (4e-9, 2e-9, 1e-9):
+        nst = int(round(T / dt))
+        x, v = O.run(y0[None, :3], y0[None, 3:], Q, M, dict(B=B, omega_z=wz), dt, nst)
+        errs.append(np.linalg.norm(x[0] - exact[:3]) / np.linalg.norm(exact[:3]))
+    assert 3.3 < errs[0] / errs[1] < 4.7 and 3.3 < errs[1] / errs[2] < 4.7, errs
+    assert errs[-1] < 1e-3
+
+
+def test_energy_conservation_second_order():
+    """Static fields, delta = 0, no laser: the lab-frame energy of eq. (hamiltonian) is
+    conserved with a bounded oscillation that shrinks like dt^2 (symplectic, Sec. 2.2)."""
+    B, wz = 4.5, 2 * math.pi * 1.0e6
+    g = np.arange(-2, 2) * 8e-6
+    X, Y, Z = np.meshgrid(g, g, g[1:3], indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1) + 1e-7
+    vel = inputs.thermal_velocities(len(pos), 10e-3, M, inputs.rng(9))
+    trap = dict(B=B, omega_z=wz)
+    E0 = O.energy(pos, vel, Q, M, trap)
+    devs = []
+    for dt, nst in ((4e-9, 500), (2e-9, 1000)):
+        x, v = pos, vel
+        d = 0.0
+        for k in range(10):
+            x, v = O.run(x, v, Q, M, trap, dt, nst // 10, step0=k * nst // 10)
+            d = max(d, abs(O.energy(x, v, Q, M, trap) - E0) / abs(E0))
+        devs.append(d)
+    assert devs[0] < 1e-3, devs
+    assert 2.8 < devs[0] / devs[1] < 5.5, devs
