@@ -1,0 +1,167 @@
+/*
+ * penning.h -- C ABI of the MI355X (gfx950) Penning-trap ion-crystal library.
+ *
+ * The library advances N ions of one species (charge q, mass m) in a Penning
+ * trap: a uniform field B z-hat, the harmonic trap potential
+ * phi_trap = k_z (2z^2 - x^2 - y^2)/4 with k_z = m omega_z^2 / q, and the
+ * rotating-wall potential phi_wall = k_z delta (x^2+y^2) cos(2(varphi + omega_r t))/4
+ * (Zaris et al., arXiv 2405.13973, Sec. 2.1, eqs. pot_trap, pot_wall,
+ * hamiltonian), with Coulomb interactions between all ions.  Time stepping is
+ * the split operator U(t, dt) = U0(dt/2) Ukick(t + dt/2; dt) U0(dt/2) of
+ * Sec. 2.2 (eqs. time_ev2, U0, velocity_kick), U0 being the exact gyration in
+ * B.  Coulomb forces come from a direct O(N^2) sum or from a 3D Laplace fast
+ * multipole method (Sec. 2.3); photon recoils are Poisson-distributed
+ * isotropic kicks (eq. laser_kick).
+ *
+ * Conventions
+ *   - SI units.  Positions in m, velocities in m/s, forces in N, time in s.
+ *   - Host arrays are n x 3, row-major (x0 y0 z0 x1 y1 z1 ...), in ion-id
+ *     (creation) order; every output is in ion-id order.
+ *   - The caller owns every buffer it passes; create copies the state into
+ *     device memory owned by the library until pt_destroy_crystal.
+ *   - Every call returns a pt_status; on failure pt_last_error() gives a
+ *     message (thread-local, valid until the next failing call on the thread).
+ *     No call throws across the ABI.  Calls on one context are not
+ *     thread-safe: serialise them.
+ *   - Work is queued on the context's HIP stream.  pt_step and
+ *     pt_step_batch return once their work is queued (a force evaluation
+ *     with the FMM waits once per step for the tree's size); pt_read_state,
+ *     pt_compute_forces and pt_synchronize wait for completion.
+ */
+#ifndef PENNING_H
+#define PENNING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PT_OK = 0,
+    PT_EINVAL = -1,    /* invalid argument (NULL, size, non-finite value, unconfined trap, ...) */
+    PT_ENOMEM = -2,    /* the context's HBM budget or the device ran out of memory */
+    PT_EDEVICE = -3,   /* a HIP runtime call failed */
+    PT_ENUMERIC = -4,  /* non-finite state detected after a step */
+    PT_EBUSY = -5      /* object still in use (e.g. destroying a context that owns crystals) */
+} pt_status;
+
+typedef struct pt_ctx pt_ctx;
+typedef struct pt_crystal pt_crystal;
+
+/* Trap parameters (Sec. 2.1).  omega_z and omega_r in rad/s.  dt_s is the
+ * step length and t0_s the time of step 0: step k runs from t0 + k dt to
+ * t0 + (k+1) dt.  Requires dt > 0 and radial confinement of a single ion,
+ * omega_c^2 > 2 omega_z^2 with omega_c = qB/m (else PT_EINVAL). */
+typedef struct {
+    double B_T;
+    double omega_z;
+    double delta;
+    double omega_r;
+    double dt_s;
+    double t0_s;
+} pt_trap_params;
+
+/* Photon-recoil model (Sec. 2.2, eq. laser_kick).  mode 0: off.  mode 1:
+ * every ion scatters a Poisson number of photons per step with mean
+ * mean_per_step (0 <= mean <= 2), each giving a recoil h/(wavelength m) in
+ * a uniformly random direction.  Draws come from Philox4x32-10 keyed by the
+ * crystal seed, counter (ion id, step, slot): slot 0 decides the count by
+ * inversion of the Poisson CDF (capped at 16), slot j >= 1 the j-th direction. */
+typedef struct {
+    int mode;
+    double mean_per_step;
+    double wavelength_m;
+} pt_laser_params;
+
+/* Coulomb solver.  method 0: direct pairwise sum (FP64).  method 1: FMM with
+ * maximum expansion degree p (1 <= p <= 20) and leaf size leaf_size (a box
+ * is divided while it holds more than leaf_size ions, down to level 16).
+ * precision 0: FP64 throughout.  precision 1: mixed -- FP32 expansions,
+ * FP32 matrix-core M2L, FP32 near field with compensated sums; positions,
+ * box-centre offsets and the integrator stay FP64. */
+typedef struct {
+    int method;
+    int p;
+    int leaf_size;
+    int precision;
+} pt_force_params;
+
+/* Context: one HIP device and stream.  hbm_budget_bytes caps the device
+ * memory the context allocates (0 = no cap).  hip_stream is a hipStream_t
+ * (for example torch.cuda.current_stream().cuda_stream) or NULL for a
+ * stream the context creates.  The stream must outlive the context. */
+pt_status pt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, void *hip_stream, pt_ctx **out);
+/* PT_EBUSY while crystals created on it still exist. */
+pt_status pt_ctx_destroy(pt_ctx *ctx);
+/* Device bytes currently allocated by the context. */
+pt_status pt_ctx_memory(pt_ctx *ctx, uint64_t *bytes_in_use, uint64_t *budget);
+
+/* Crystal of n >= 1 ions with positions pos_xyz and velocities vel_xyz
+ * (host, n x 3).  Default parameters: B = 4.5 T, omega_z = 2 pi 1.5 MHz,
+ * delta = omega_r = 0, dt = 1 ns, t0 = 0, laser off, direct method.  Step
+ * counter starts at 0.  PT_ENOMEM if the context budget would be exceeded. */
+pt_status pt_create_crystal(pt_ctx *ctx, int64_t n, const double *pos_xyz, const double *vel_xyz, double charge_C,
+                            double mass_kg, uint64_t seed, pt_crystal **out);
+/* Same, from device buffers (n x 3, FP64, e.g. torch tensors' data_ptr()),
+ * read on the context stream. */
+pt_status pt_create_crystal_device(pt_ctx *ctx, int64_t n, const double *pos_xyz_dev, const double *vel_xyz_dev,
+                                   double charge_C, double mass_kg, uint64_t seed, pt_crystal **out);
+pt_status pt_destroy_crystal(pt_crystal *c);
+
+pt_status pt_set_trap_params(pt_crystal *c, const pt_trap_params *p);
+pt_status pt_set_laser_params(pt_crystal *c, const pt_laser_params *p);
+pt_status pt_set_force_params(pt_crystal *c, const pt_force_params *p);
+/* Overwrite the state (host, n x 3) and the step counter. */
+pt_status pt_set_state(pt_crystal *c, const double *pos_xyz, const double *vel_xyz, int64_t step);
+
+/* Coulomb force k_e q^2 sum_{j != i} (x_i - x_j)/|x_i - x_j|^3 on every ion
+ * at the current positions, with the crystal's force parameters (host
+ * output, n x 3, ion-id order).  Trap and wall forces are not included. */
+pt_status pt_compute_forces(pt_crystal *c, double *F_out);
+/* Same for several crystals evaluated together in one batch (each crystal's
+ * result identical to its own pt_compute_forces); F_out[k] is crystal k's
+ * host output.  All crystals must share the context and force parameters. */
+pt_status pt_compute_forces_batch(pt_crystal *const *cs, int n_crystals, double *const *F_out);
+
+/* Advance n_steps >= 0 steps (eq. time_ev2 with eq. velocity_kick). */
+pt_status pt_step(pt_crystal *c, int64_t n_steps);
+/* Advance crystal k by n_steps[k] steps; crystals still stepping are
+ * batched together so that each phase of a step is one launch for all of
+ * them.  Results are identical to stepping each crystal alone. */
+pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_steps);
+pt_status pt_synchronize(pt_ctx *ctx);
+
+/* Copy out the state (host, n x 3; pos/vel/step/t/photons may be NULL).
+ * photons receives each ion's photon count of the last step taken. */
+pt_status pt_read_state(pt_crystal *c, double *pos, double *vel, int64_t *step, double *t, int32_t *photons);
+
+/* Octree and interaction lists of the last FMM evaluation of crystal c.
+ * sizes[0..3] = boxes, levels, V entries, near entries.  With the array
+ * arguments NULL only sizes is filled.  Boxes are in (level, Morton prefix)
+ * order; keys (n, 48-bit Morton) and perm (n, ion ids in (key, id) order)
+ * follow ion id / sorted order; coords n_box x 3 integer box coordinates at
+ * the box's level; v_off/v_src and near_off/near_src are CSR lists with
+ * sources in ascending box order; root = lower corner xyz and side. */
+pt_status pt_debug_export_tree(pt_crystal *c, int64_t sizes[4], uint64_t *keys, int32_t *perm, int32_t *level,
+                               int32_t *parent, int32_t *ion_begin, int32_t *ion_end, int32_t *coords,
+                               uint8_t *is_leaf, int32_t *v_off, int32_t *v_src, int32_t *near_off,
+                               int32_t *near_src, double *root);
+
+/* Per-phase GPU time (ms) of the last force evaluation on the context,
+ * measured with HIP events: [0] sort+tree+lists, [1] P2M+M2M, [2] M2L,
+ * [3] L2L, [4] L2P+P2P (or direct), [5] total.  Filled only when timing was
+ * enabled with pt_ctx_set_timing(ctx, 1). */
+pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable);
+pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[6]);
+
+/* Work counts of the last FMM evaluation: [0] boxes, [1] leaves, [2] M2L
+ * pairs, [3] P2P pairs (ordered, i != j counted), [4] levels, [5] ions. */
+pt_status pt_ctx_work_counts(pt_ctx *ctx, int64_t counts[6]);
+
+const char *pt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

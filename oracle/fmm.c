@@ -35,15 +35,15 @@
 
 #include "oracle.h"
 
-#define OR_MAXLEV 21
+#define OR_MAXLEV 16
 
 /* ---------------------------------------------------------------- keys */
 
 /* Root cube and Morton keys.  lo/hi are the per-axis extremes, W the largest
  * extent, the cube is centred on the bounding box: o = (lo + hi)/2 - W/2.
- * Each coordinate is quantised to 21 bits, floor((x - o) * 2^21 / W) clamped
- * to [0, 2^21 - 1], and the three integers are bit-interleaved with x in
- * the most significant position of each triple.  Built with
+ * Each coordinate is quantised to 16 bits, floor((x - o) * 2^16 / W) clamped
+ * to [0, 2^16 - 1], and the three integers are bit-interleaved with x in
+ * the most significant position of each triple (48-bit keys; 16 levels).  Built with
  * -ffp-contract=off so no multiply-add is fused. */
 void or_root_cube(int n, const double *pos, double lo_out[3], double *W_out)
 {
@@ -72,7 +72,7 @@ void or_root_cube(int n, const double *pos, double lo_out[3], double *W_out)
 static uint64_t or_spread3(uint32_t v)
 {
     uint64_t r = 0;
-    for (int b = 0; b < 21; ++b)
+    for (int b = 0; b < OR_MAXLEV; ++b)
         if (v & (1u << b)) r |= (uint64_t)1 << (3 * b);
     return r;
 }
@@ -81,13 +81,13 @@ void or_morton_keys(int n, const double *pos, uint64_t *keys, double root_out[4]
 {
     double o[3], W;
     or_root_cube(n, pos, o, &W);
-    double S = 2097152.0 / W;
+    double S = 65536.0 / W;
     for (int i = 0; i < n; ++i) {
         uint32_t k[3];
         for (int d = 0; d < 3; ++d) {
             double f = floor((pos[3 * i + d] - o[d]) * S);
             if (f < 0.0) f = 0.0;
-            if (f > 2097151.0) f = 2097151.0;
+            if (f > 65535.0) f = 65535.0;
             k[d] = (uint32_t)f;
         }
         keys[i] = (or_spread3(k[0]) << 2) | (or_spread3(k[1]) << 1) | or_spread3(k[2]);

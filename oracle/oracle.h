@@ -59,7 +59,7 @@ typedef struct {
     int nbox;
     int nlevels;           /* deepest level + 1 */
     double lo[3], W;       /* root cube: lower corner and side */
-    uint64_t *key;         /* Morton key of each ion, in ion-id order */
+    uint64_t *key;         /* 48-bit Morton key of each ion, in ion-id order */
     int32_t *perm;         /* perm[k] = id of the k-th ion in (key, id) order */
     /* per box */
     int32_t *level, *parent, *child_first, *nchild, *ion_begin, *ion_end;

@@ -1,0 +1,155 @@
+// Solid harmonics and expansion storage of the GPU fast multipole method.
+//
+// Expansions follow the paper's Sec. 2.3 (multipole expansion eq. FMM_coul,
+// local expansion eq. FMM_local, truncation at degree p) in a basis chosen
+// for the GPU: normalised regular solid harmonics
+//     Rh_n^m(u) = sqrt((n-m)!/(n+m)!) (-1)^m r^n P_n^m(cos theta) e^{i m phi},  m >= 0
+// (P without the Condon-Shortley sign), Rh_n^{-m} = (-1)^m conj(Rh_n^m), and
+// irregular ones Ih_n^m(u) = Rh_n^m(u) / r^{2n+1}.  With these,
+//     1/|x - a| = sum_{n,m} conj(Rh_n^m(a)) Ih_n^m(x)            (|a| < |x|).
+// A box of side h and centre c stores
+//     multipole  Mh_n^m = sum_i conj(Rh_n^m((x_i - c)/h))        (unit charges)
+//                phi(x) = (1/h) sum Mh_n^m Ih_n^m((x - c)/h)
+//     local      phi(x) = (1/h) sum Lh_n^m conj(Rh_n^m((x - c)/h))
+// i.e. coefficients scaled by the box size, so that every translation
+// operator between boxes of one level is independent of the level and all
+// entries are O(1) (what makes FP32 usable).
+//
+// Real storage: for degree n, [Re c_n^0, Re c_n^1, Im c_n^1, ..., Re c_n^n, Im c_n^n]
+// at offset n^2; K = (p+1)^2 reals per expansion, padded to a multiple of 16.
+#pragma once
+
+#include <cmath>
+
+#include "pt_common.hpp"
+
+namespace pt {
+
+__host__ __device__ inline int kcoef(int p) { return (p + 1) * (p + 1); }
+__host__ __device__ inline int kpad(int p) { return (kcoef(p) + 15) & ~15; }
+__host__ __device__ inline int sidx_re(int n, int m) { return m == 0 ? n * n : n * n + 2 * m - 1; }
+__host__ __device__ inline int sidx_im(int n, int m) { return n * n + 2 * m; }  // m > 0
+
+// Rh_n^m(u) for 0 <= m <= n <= p, packed at n(n+1)/2 + m.  Recurrences:
+//   Rh_m^m     = -sqrt((2m-1)/(2m)) (x + i y) Rh_{m-1}^{m-1}
+//   Rh_{m+1}^m = sqrt(2m+1) z Rh_m^m
+//   Rh_n^m     = ((2n-1) z Rh_{n-1}^m - sqrt((n+m-1)(n-m-1)) r^2 Rh_{n-2}^m) / sqrt((n+m)(n-m))
+template <typename T>
+__host__ __device__ inline void rhat_all(int p, T x, T y, T z, T *re, T *im)
+{
+    const T r2 = x * x + y * y + z * z;
+    T dre = 1, dim = 0;  // Rh_m^m
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) {
+            const T f = -sqrt(T(2 * m - 1) / T(2 * m));
+            const T nre = f * (x * dre - y * dim);
+            const T nim = f * (x * dim + y * dre);
+            dre = nre;
+            dim = nim;
+        }
+        int i0 = m * (m + 1) / 2 + m;
+        re[i0] = dre;
+        im[i0] = dim;
+        if (m + 1 > p) continue;
+        const T f1 = sqrt(T(2 * m + 1)) * z;
+        int i1 = (m + 1) * (m + 2) / 2 + m;
+        re[i1] = f1 * dre;
+        im[i1] = f1 * dim;
+        for (int n = m + 2; n <= p; ++n) {
+            const T a = T(2 * n - 1) * z;
+            const T b = sqrt(T((n + m - 1) * (n - m - 1))) * r2;
+            const T inv = T(1) / sqrt(T((n + m) * (n - m)));
+            const int in = n * (n + 1) / 2 + m, i1_ = (n - 1) * n / 2 + m, i2 = (n - 2) * (n - 1) / 2 + m;
+            re[in] = (a * re[i1_] - b * re[i2]) * inv;
+            im[in] = (a * im[i1_] - b * im[i2]) * inv;
+        }
+    }
+}
+
+// Field of a local expansion (L2P).  The expansion is re-centred exactly at
+// the evaluation point u (box units); its degree-1 coefficients are
+//   L'_1^k = sum_{n>=1,m} Lh_n^m conj(Rh_{n-1}^{m-k}(u)) nu_n^m / nu_{n-1}^{m-k},  k = 0, 1,
+// and with R_1^0 = z, R_1^{+-1} = -+(x +- i y)/2 the field is
+//   E h^2 = (Re L'_1^1, Im L'_1^1, -L'_1^0).
+// Every Rh_{n'}^mu (mu >= 0) enters L'_1^1 twice: with Lh_{n'+1}^{mu+1} and,
+// through the mirrored order -mu, with -conj(Lh_{n'+1}^{mu-1}).
+// L is the real storage; the result is E * h^2 (caller divides by h^2).
+template <typename T>
+__host__ __device__ inline void l2p_field(int p, const T *L, T x, T y, T z, T &ex, T &ey, T &ez)
+{
+    const T r2 = x * x + y * y + z * z;
+    T g0 = 0, g1r = 0, g1i = 0;
+    T dre = 1, dim = 0;  // Rh_mu^mu
+    for (int mu = 0; mu <= p - 1; ++mu) {
+        if (mu > 0) {
+            const T f = -sqrt(T(2 * mu - 1) / T(2 * mu));
+            const T nre = f * (x * dre - y * dim);
+            const T nim = f * (x * dim + y * dre);
+            dre = nre;
+            dim = nim;
+        }
+        T r1re = 0, r1im = 0, r0re = dre, r0im = dim;  // Rh_{n-2}, Rh_{n-1} along the column
+        for (int np = mu; np <= p - 1; ++np) {
+            T cre, cim;  // Rh_np^mu
+            if (np == mu) {
+                cre = dre;
+                cim = dim;
+            } else if (np == mu + 1) {
+                const T f1 = sqrt(T(2 * mu + 1)) * z;
+                cre = f1 * dre;
+                cim = f1 * dim;
+            } else {
+                const T a = T(2 * np - 1) * z;
+                const T b = sqrt(T((np + mu - 1) * (np - mu - 1))) * r2;
+                const T inv = T(1) / sqrt(T((np + mu) * (np - mu)));
+                cre = (a * r0re - b * r1re) * inv;
+                cim = (a * r0im - b * r1im) * inv;
+            }
+            if (np > mu) {
+                r1re = r0re;
+                r1im = r0im;
+            }
+            r0re = cre;
+            r0im = cim;
+            const int n = np + 1;
+            // k = 0: Lh_n^mu conj(Rh), doubled for mu > 0 (mirror term)
+            {
+                const T lre = L[sidx_re(n, mu)];
+                const T lim = mu > 0 ? L[sidx_im(n, mu)] : T(0);
+                const T w = sqrt(T((n + mu) * (n - mu))) * (mu > 0 ? T(2) : T(1));
+                g0 += w * (lre * cre + lim * cim);
+            }
+            // k = 1, (a): Lh_n^{mu+1} conj(Rh_np^mu)
+            {
+                const T lre = L[sidx_re(n, mu + 1)];
+                const T lim = L[sidx_im(n, mu + 1)];
+                const T w = sqrt(T((n + mu + 1) * (n + mu)));
+                g1r += w * (lre * cre + lim * cim);
+                g1i += w * (lim * cre - lre * cim);
+            }
+            // k = 1, (b): -conj(Lh_n^{mu-1}) Rh_np^mu, mu >= 1
+            if (mu >= 1) {
+                const T lre = L[sidx_re(n, mu - 1)];
+                const T lim = mu - 1 > 0 ? L[sidx_im(n, mu - 1)] : T(0);
+                const T w = sqrt(T((n - mu + 1) * (n - mu)));
+                g1r -= w * (lre * cre + lim * cim);
+                g1i -= w * (lre * cim - lim * cre);
+            }
+        }
+    }
+    ex = g1r;
+    ey = g1i;
+    ez = -g0;
+}
+
+// Host-only: the dense real operator matrices (row = output coefficient,
+// column = input coefficient, K x K each, row-major) for degree p:
+//   m2m[8]  child octant o -> parent  (child centre at parent centre + ((2o-1)/4) h_parent)
+//   l2l[8]  parent -> child octant o
+//   m2l[343] source box at integer offset d = (dx,dy,dz) in [-3,3]^3 from the
+//            target box (same level), index (dx+3)*49 + (dy+3)*7 + (dz+3);
+//            entries of touching offsets are left zero.
+// Returns 0 on success.
+int build_operator_tables(int p, double *m2m, double *l2l, double *m2l);
+
+}  // namespace pt

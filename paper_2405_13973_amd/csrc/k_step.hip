@@ -1,0 +1,350 @@
+// Integrator, photon kicks, bounding boxes, Morton keys and the direct
+// Coulomb sum.  All kernels are batched: a launch covers every ion of every
+// crystal in the batch; ion_crystal[g] maps a batch index to its crystal.
+//
+// Step (Zaris et al., Sec. 2.2, eq. time_ev2):
+//   U0(dt/2) -> kick at t + dt/2 (eq. velocity_kick: trap + wall + Coulomb,
+//   plus Poisson photon recoils of eq. laser_kick) -> U0(dt/2),
+// U0 the exact gyration about B z-hat (eq. U0, rotation sense of the
+// Lorentz force on q B > 0: clockwise) with free flight along z.
+#include "pt_common.hpp"
+#include "pt_kernels.hpp"
+
+namespace pt {
+
+// Exact U0(dt/2): v rotates by -omega_c dt/2 about z; x moves along the arc.
+__device__ inline void u0_half(const CrystalDev &c, double &x, double &y, double &z, double &vx, double &vy,
+                               double vz)
+{
+    const double nx = x + vx * c.a_half + vy * c.b_half;
+    const double ny = y - vx * c.b_half + vy * c.a_half;
+    const double nvx = vx * c.c_half + vy * c.s_half;
+    const double nvy = -vx * c.s_half + vy * c.c_half;
+    x = nx;
+    y = ny;
+    z = z + vz * (0.5 * c.dt);
+    vx = nvx;
+    vy = nvy;
+}
+
+__global__ void k_ion_crystal(const CrystalDev *__restrict__ cs, int nc, int ntot, int32_t *__restrict__ ion_crystal)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ntot) return;
+    int lo = 0, hi = nc - 1;  // last crystal with ion_off <= g
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cs[mid].ion_off <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    ion_crystal[g] = lo;
+}
+
+__global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t v0, uint64_t v1, int n_pairs)
+{
+    // pattern: six words per crystal, three v0 then three v1
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_pairs * 6) p[i] = (i % 6) < 3 ? v0 : v1;
+}
+
+// Optional half drift, then per-crystal min/max of x, y, z (ordered-integer
+// atomics; min/max is exact, so the result does not depend on the order).
+__global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
+                             int do_drift, unsigned long long *__restrict__ bbox)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = g < ntot;
+    int c = 0;
+    unsigned long long v[6] = {~0ull, ~0ull, ~0ull, 0ull, 0ull, 0ull};
+    if (active) {
+        c = ion_crystal[g];
+        const CrystalDev &cd = cs[c];
+        const int i = g - cd.ion_off;
+        const int n = cd.n;
+        double *s = cd.state;
+        double x = s[i], y = s[n + i], z = s[2 * n + i];
+        if (do_drift) {
+            double vx = s[3 * n + i], vy = s[4 * n + i];
+            const double vz = s[5 * n + i];
+            u0_half(cd, x, y, z, vx, vy, vz);
+            s[i] = x;
+            s[n + i] = y;
+            s[2 * n + i] = z;
+            s[3 * n + i] = vx;
+            s[4 * n + i] = vy;
+        }
+        v[0] = dbl_to_ordered(x);
+        v[1] = dbl_to_ordered(y);
+        v[2] = dbl_to_ordered(z);
+        v[3] = v[0];
+        v[4] = v[1];
+        v[5] = v[2];
+    }
+    const unsigned long long act = __ballot(active);
+    if (act == 0) return;
+    const int first = __ffsll((long long)act) - 1;
+    const int cref = __shfl(c, first);
+    const bool uniform = __ballot(active && c != cref) == 0;
+    if (uniform) {
+        for (int off = 32; off > 0; off >>= 1)
+            for (int k = 0; k < 6; ++k) {
+                const unsigned long long o = __shfl_xor(v[k], off);
+                v[k] = k < 3 ? (o < v[k] ? o : v[k]) : (o > v[k] ? o : v[k]);
+            }
+        if ((threadIdx.x & 63) == 0)
+            for (int k = 0; k < 6; ++k) {
+                if (k < 3) atomicMin(&bbox[6 * cref + k], v[k]);
+                else atomicMax(&bbox[6 * cref + k], v[k]);
+            }
+    } else if (active) {
+        for (int k = 0; k < 6; ++k) {
+            if (k < 3) atomicMin(&bbox[6 * c + k], v[k]);
+            else atomicMax(&bbox[6 * c + k], v[k]);
+        }
+    }
+}
+
+// Root cube per crystal, in the exact operation order of the tree contract:
+// W = max extent (1e-9 m if zero), o = (lo + hi)/2 - W/2, S = 2^16 / W.
+// Resets the bounding box for its next use.
+__global__ void k_root(unsigned long long *__restrict__ bbox, int nc, RootCube *__restrict__ roots)
+{
+#pragma clang fp contract(off)
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = ordered_to_dbl(bbox[6 * c + d]);
+        hi[d] = ordered_to_dbl(bbox[6 * c + 3 + d]);
+    }
+    double W = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double e = hi[d] - lo[d];
+        if (e > W) W = e;
+    }
+    if (W == 0.0) W = 1e-9;
+    RootCube r;
+    for (int d = 0; d < 3; ++d) {
+        const double ctr = 0.5 * (lo[d] + hi[d]);
+        r.o[d] = ctr - 0.5 * W;
+    }
+    r.W = W;
+    r.S = 65536.0 / W;
+    r.pad[0] = r.pad[1] = r.pad[2] = 0.0;
+    roots[c] = r;
+    for (int d = 0; d < 3; ++d) {
+        bbox[6 * c + d] = ~0ull;
+        bbox[6 * c + 3 + d] = 0ull;
+    }
+}
+
+// 64-bit sort key per ion: crystal index above a 48-bit Morton key of the
+// position quantised to the crystal's root cube (floor((x - o) S), clamped
+// to [0, 2^16 - 1]; subtract then multiply, never fused).
+__global__ void k_keys(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal,
+                       const RootCube *__restrict__ roots, int ntot, uint64_t *__restrict__ keys,
+                       uint32_t *__restrict__ vals)
+{
+#pragma clang fp contract(off)
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ntot) return;
+    const int c = ion_crystal[g];
+    const CrystalDev &cd = cs[c];
+    const int i = g - cd.ion_off;
+    const int n = cd.n;
+    const RootCube r = roots[c];
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        double f = floor((cd.state[d * n + i] - r.o[d]) * r.S);
+        if (!(f >= 0.0)) f = 0.0;
+        if (f > 65535.0) f = 65535.0;
+        q[d] = (uint32_t)f;
+    }
+    keys[g] = ((uint64_t)c << 48) | morton3(q[0], q[1], q[2]);
+    vals[g] = (uint32_t)g;
+}
+
+// Kick at the midpoint time and the second half drift.  E holds the Coulomb
+// field per unit charge (sum_j (x_i - x_j)/r^3) in batch order, SoA.
+__global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
+                             int kstep, const double *__restrict__ E)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ntot) return;
+    const int c = ion_crystal[g];
+    const CrystalDev &cd = cs[c];
+    const int i = g - cd.ion_off;
+    const int n = cd.n;
+    double *s = cd.state;
+    double x = s[i], y = s[n + i], z = s[2 * n + i];
+    double vx = s[3 * n + i], vy = s[4 * n + i], vz = s[5 * n + i];
+    const uint64_t step = cd.step0 + (uint64_t)kstep;
+    const double t = cd.t0 + (double)step * cd.dt;
+    const double tm = t + 0.5 * cd.dt;
+    // trap: -q grad(k_z (2z^2 - x^2 - y^2)/4)
+    double fx = 0.5 * cd.qkz * x, fy = 0.5 * cd.qkz * y, fz = -cd.qkz * z;
+    if (cd.delta != 0.0) {  // rotating wall at the midpoint time
+        const double C = cos(2.0 * cd.omega_r * tm), S = sin(2.0 * cd.omega_r * tm);
+        const double w = 0.5 * cd.qkz * cd.delta;
+        fx -= w * (x * C - y * S);
+        fy += w * (y * C + x * S);
+    }
+    fx += cd.coul * E[g];
+    fy += cd.coul * E[ntot + g];
+    fz += cd.coul * E[2 * ntot + g];
+    const double kdt = cd.dt * cd.inv_m;
+    vx += fx * kdt;
+    vy += fy * kdt;
+    vz += fz * kdt;
+    int32_t nph = 0;
+    if (cd.laser_on) {
+        uint32_t w[4] = {(uint32_t)i, (uint32_t)step, (uint32_t)(step >> 32), 0u};
+        const uint32_t k0 = (uint32_t)cd.seed, k1 = (uint32_t)(cd.seed >> 32);
+        philox4x32_10(w, k0, k1);
+        const double u = u53(w[0], w[1]);
+        nph = 16;
+        for (int k = 0; k <= 16; ++k)
+            if (u < cd.poisson_F[k]) {
+                nph = k;
+                break;
+            }
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int j = 1; j <= nph; ++j) {
+            uint32_t d[4] = {(uint32_t)i, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)j};
+            philox4x32_10(d, k0, k1);
+            const double ct = 2.0 * u53(d[0], d[1]) - 1.0;
+            const double ph = 2.0 * kPi * u53(d[2], d[3]);
+            const double st = sqrt(1.0 - ct * ct);
+            double sp, cp;
+            sincos(ph, &sp, &cp);
+            ax += st * cp;
+            ay += st * sp;
+            az += ct;
+        }
+        vx += cd.recoil * ax;
+        vy += cd.recoil * ay;
+        vz += cd.recoil * az;
+    }
+    cd.photons[i] = nph;
+    u0_half(cd, x, y, z, vx, vy, vz);
+    s[i] = x;
+    s[n + i] = y;
+    s[2 * n + i] = z;
+    s[3 * n + i] = vx;
+    s[4 * n + i] = vy;
+    s[5 * n + i] = vz;
+}
+
+// Direct Coulomb field E_i = sum_{j != i} (x_i - x_j)/|x_i - x_j|^3 (FP64).
+// A block takes kDirTB targets of one crystal (blk_crystal/blk_first) and
+// streams that crystal's ions through LDS in tiles; every thread owns two
+// targets.  Sources are summed in ascending index order, so the result does
+// not depend on the batch.
+constexpr int kDirTB = 256;
+constexpr int kDirT = 2;
+
+__global__ __launch_bounds__(kDirTB) void k_direct(const CrystalDev *__restrict__ cs,
+                                                   const int32_t *__restrict__ blk_crystal,
+                                                   const int32_t *__restrict__ blk_first, int ntot,
+                                                   double *__restrict__ E)
+{
+    __shared__ double sx[kDirTB], sy[kDirTB], sz[kDirTB];
+    const int c = blk_crystal[blockIdx.x];
+    const CrystalDev &cd = cs[c];
+    const int n = cd.n;
+    const double *s = cd.state;
+    double xi[kDirT], yi[kDirT], zi[kDirT], ax[kDirT], ay[kDirT], az[kDirT];
+    int ti[kDirT];
+#pragma unroll
+    for (int t = 0; t < kDirT; ++t) {
+        ti[t] = blk_first[blockIdx.x] + t * kDirTB + threadIdx.x;
+        const int ii = ti[t] < n ? ti[t] : 0;
+        xi[t] = s[ii];
+        yi[t] = s[n + ii];
+        zi[t] = s[2 * n + ii];
+        ax[t] = ay[t] = az[t] = 0.0;
+    }
+    for (int base = 0; base < n; base += kDirTB) {
+        const int j = base + threadIdx.x;
+        __syncthreads();
+        if (j < n) {
+            sx[threadIdx.x] = s[j];
+            sy[threadIdx.x] = s[n + j];
+            sz[threadIdx.x] = s[2 * n + j];
+        }
+        __syncthreads();
+        const int cnt = min(kDirTB, n - base);
+        for (int k = 0; k < cnt; ++k) {
+            const double x = sx[k], y = sy[k], z = sz[k];
+#pragma unroll
+            for (int t = 0; t < kDirT; ++t) {
+                const double dx = xi[t] - x, dy = yi[t] - y, dz = zi[t] - z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double ri = (r2 > 0.0 && base + k != ti[t]) ? rsqrt(r2) : 0.0;
+                const double w = ri * ri * ri;
+                ax[t] += dx * w;
+                ay[t] += dy * w;
+                az[t] += dz * w;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kDirT; ++t)
+        if (ti[t] < n) {
+            const int g = cd.ion_off + ti[t];
+            E[g] = ax[t];
+            E[ntot + g] = ay[t];
+            E[2 * ntot + g] = az[t];
+        }
+}
+
+// ---------------------------------------------------------------- launchers
+
+void launch_ion_crystal(const CrystalDev *cs, int nc, int ntot, int32_t *ion_crystal, hipStream_t st)
+{
+    if (ntot > 0) k_ion_crystal<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, nc, ntot, ion_crystal);
+}
+
+void launch_bbox_reset(unsigned long long *bbox, int nc, hipStream_t st)
+{
+    k_fill_u64<<<ceil_div(6 * nc, 256), 256, 0, st>>>((uint64_t *)bbox, ~0ull, 0ull, nc);
+}
+
+void launch_zero_u64(uint64_t *p, int n, hipStream_t st)
+{
+    // n < 6 words: one "crystal" worth of the fill pattern with both halves zero
+    k_fill_u64<<<1, 64, 0, st>>>(p, 0ull, 0ull, (n + 5) / 6);
+}
+
+void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int do_drift,
+                       unsigned long long *bbox, hipStream_t st)
+{
+    if (ntot > 0) k_drift_bbox<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, do_drift, bbox);
+}
+
+void launch_root(unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st)
+{
+    k_root<<<ceil_div(nc, 64), 64, 0, st>>>(bbox, nc, roots);
+}
+
+void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCube *roots, int ntot, uint64_t *keys,
+                 uint32_t *vals, hipStream_t st)
+{
+    if (ntot > 0) k_keys<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, roots, ntot, keys, vals);
+}
+
+void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
+                       hipStream_t st)
+{
+    if (ntot > 0) k_kick_drift<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E);
+}
+
+int direct_targets_per_block() { return kDirTB * kDirT; }
+
+void launch_direct(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int ntot,
+                   double *E, hipStream_t st)
+{
+    if (nblk > 0) k_direct<<<nblk, kDirTB, 0, st>>>(cs, blk_crystal, blk_first, ntot, E);
+}
+
+}  // namespace pt

@@ -1,0 +1,434 @@
+// Morton sort, adaptive octree and interaction lists (Zaris et al., Sec. 2.3,
+// "Algorithm": smallest enclosing cube, recursive octants, a box divided only
+// when it holds more than leaf_size ions).
+//
+// Contract shared with the reference tree: ions sorted by (crystal, 48-bit
+// key, batch index); boxes ordered by (level, crystal, Morton prefix); a box
+// is split iff it holds more than leaf_size ions and its level is below 16;
+// only non-empty children exist.
+//
+// Lists, for box B at level l with integer coordinates b:
+//   colleagues  the (up to) 27 same-level boxes with |b' - b| <= 1 (B included)
+//   V(B)        children of the parent's colleagues that do not touch B; they
+//               are stored densely in a 6x6x6 window (index from the offset and
+//               B's octant) so that targets of one octant share operators
+//   near(T)     for a leaf T: the ion ranges of T's colleagues (leaf or not) and
+//               of the leaf colleagues of T's ancestors -- every ion pair not
+//               served by a multipole-to-local conversion
+#include "pt_common.hpp"
+#include "pt_kernels.hpp"
+
+namespace pt {
+
+// --------------------------------------------------------------- scan
+
+// Exclusive prefix sum of n uint32 in place by one workgroup; *total gets the sum.
+__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t *__restrict__ a, int n, uint32_t *__restrict__ total)
+{
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int b = t * chunk, e = min(n, b + chunk);
+    uint32_t s = 0;
+    for (int i = b; i < e; ++i) s += a[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;
+    for (int i = b; i < e; ++i) {
+        const uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    if (t == 1023 && total) *total = part[1023];
+}
+
+// --------------------------------------------------------------- radix sort
+
+constexpr int kSortTB = 256;
+constexpr int kSortItems = 4;
+constexpr int kSortTile = kSortTB * kSortItems;
+
+__global__ __launch_bounds__(kSortTB) void k_radix_hist(const uint64_t *__restrict__ keys, int n, int shift,
+                                                        uint32_t *__restrict__ hist, int nblk)
+{
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int r = 0; r < kSortItems; ++r) {
+        const int i = blockIdx.x * kSortTile + r * kSortTB + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter: items are ranked in tile order (round, wave, lane); equal
+// digits within a wave are found with eight ballots.
+__global__ __launch_bounds__(kSortTB) void k_radix_scatter(const uint64_t *__restrict__ kin,
+                                                           const uint32_t *__restrict__ vin,
+                                                           uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                           int n, int shift, const uint32_t *__restrict__ hist,
+                                                           int nblk)
+{
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[kSortTB / 64][256];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    base[tid] = hist[tid * nblk + blockIdx.x];
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int r = 0; r < kSortItems; ++r) {
+        for (int k = 0; k < kSortTB / 64; ++k) wcnt[k][tid] = 0;
+        __syncthreads();
+        const int i = blockIdx.x * kSortTile + r * kSortTB + tid;
+        const bool valid = i < n;
+        const uint64_t key = valid ? kin[i] : 0ull;
+        const uint32_t val = valid ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1u;
+            const unsigned long long bb = __ballot(on);
+            peers &= on ? bb : ~bb;
+        }
+        const int rank = __popcll(peers & lt);
+        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[d] + rank;
+            for (int k = 0; k < w; ++k) pos += wcnt[k][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int k = 0; k < kSortTB / 64; ++k) add += wcnt[k][tid];
+        base[tid] += add;
+        __syncthreads();
+    }
+}
+
+// Sorted positions: slot k takes the position of batch ion vals[k].
+__global__ void k_gather(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal,
+                         const uint32_t *__restrict__ vals, int ntot, double *__restrict__ sp)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ntot) return;
+    const int g = (int)vals[k];
+    const CrystalDev &cd = cs[ion_crystal[g]];
+    const int i = g - cd.ion_off;
+    sp[k] = cd.state[i];
+    sp[ntot + k] = cd.state[cd.n + i];
+    sp[2 * ntot + k] = cd.state[2 * cd.n + i];
+}
+
+// --------------------------------------------------------------- octree
+
+// Range [lo, hi) of the level-l box holding slot k, narrowed from the
+// range of its parent; keys are sorted so the box is the run of equal
+// (key >> shift) values around k.
+__device__ inline void narrow(const uint64_t *__restrict__ keys, int k, int shift, int &lo, int &hi)
+{
+    const uint64_t pre = keys[k] >> shift;
+    int a = lo, b = k;  // first index in [lo, k] with equal prefix
+    while (a < b) {
+        const int m = (a + b) >> 1;
+        if ((keys[m] >> shift) < pre) a = m + 1;
+        else b = m;
+    }
+    int c = k + 1, d = hi;  // first index in [k+1, hi) with a larger prefix
+    while (c < d) {
+        const int m = (c + d) >> 1;
+        if ((keys[m] >> shift) <= pre) c = m + 1;
+        else d = m;
+    }
+    lo = a;
+    hi = c;
+}
+
+// For every sorted slot: the levels at which it is the first ion of an
+// existing box (bit l of rep_mask).
+__global__ void k_tree_levels(const CrystalDev *__restrict__ cs, const uint64_t *__restrict__ keys, int ntot,
+                              int leaf_size, uint32_t *__restrict__ rep_mask)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ntot) return;
+    const int c = (int)(keys[k] >> 48);
+    int lo = cs[c].ion_off, hi = lo + cs[c].n;
+    uint32_t mask = (lo == k) ? 1u : 0u;
+    for (int l = 1; l <= kMaxLevel && hi - lo > leaf_size; ++l) {
+        narrow(keys, k, 3 * (kMaxLevel - l), lo, hi);
+        if (lo == k) mask |= 1u << l;
+    }
+    rep_mask[k] = mask;
+}
+
+__global__ __launch_bounds__(256) void k_tree_count(const uint32_t *__restrict__ rep_mask, int ntot,
+                                                    uint32_t *__restrict__ blockcnt, int nblk)
+{
+    __shared__ uint32_t wc[4][kMaxLevel + 1];
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t mask = k < ntot ? rep_mask[k] : 0u;
+    const int w = threadIdx.x >> 6;
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        const int c = __popcll(__ballot((mask >> l) & 1u));
+        if ((threadIdx.x & 63) == 0) wc[w][l] = (uint32_t)c;
+    }
+    __syncthreads();
+    if (threadIdx.x <= kMaxLevel)
+        blockcnt[threadIdx.x * nblk + blockIdx.x] = wc[0][threadIdx.x] + wc[1][threadIdx.x] + wc[2][threadIdx.x] +
+                                                    wc[3][threadIdx.x];
+}
+
+__global__ void k_tree_summary(const uint32_t *__restrict__ scanned, int nblk, const uint32_t *__restrict__ total,
+                               TreeSummary *__restrict__ sum)
+{
+    if (threadIdx.x != 0) return;
+    for (int l = 0; l <= kMaxLevel; ++l) sum->level_start[l] = (int32_t)scanned[l * nblk];
+    sum->level_start[kMaxLevel + 1] = (int32_t)*total;
+    sum->nbox = (int32_t)*total;
+}
+
+// Writes one box record per (slot, level) representative.
+__global__ __launch_bounds__(256) void k_tree_emit(const CrystalDev *__restrict__ cs,
+                                                   const RootCube *__restrict__ roots,
+                                                   const uint64_t *__restrict__ keys, int ntot, int leaf_size,
+                                                   const uint32_t *__restrict__ rep_mask,
+                                                   const uint32_t *__restrict__ scanned, int nblk, BoxTable bt)
+{
+    __shared__ uint32_t wc[4][kMaxLevel + 1];
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t mask = k < ntot ? rep_mask[k] : 0u;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int rank[kMaxLevel + 1];
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        const unsigned long long b = __ballot((mask >> l) & 1u);
+        rank[l] = __popcll(b & lt);
+        if (lane == 0) wc[w][l] = (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    if (mask == 0) return;
+    const uint64_t key = keys[k];
+    const int c = (int)(key >> 48);
+    const RootCube rc = roots[c];
+    int lo = cs[c].ion_off, hi = lo + cs[c].n;
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        if (l > 0) {
+            if (hi - lo <= leaf_size) break;
+            narrow(keys, k, 3 * (kMaxLevel - l), lo, hi);
+        }
+        if (!((mask >> l) & 1u)) continue;
+        uint32_t idx = scanned[l * nblk + blockIdx.x] + (uint32_t)rank[l];
+        for (int q = 0; q < w; ++q) idx += wc[q][l];
+        const int sh = 3 * (kMaxLevel - l);
+        const uint64_t mort = (key & 0xFFFFFFFFFFFFull) >> sh;
+        const uint32_t ix = compact3_16(mort >> 2), iy = compact3_16(mort >> 1), iz = compact3_16(mort);
+        const double h = ldexp(rc.W, -l);
+        bt.level[idx] = l;
+        bt.crystal[idx] = c;
+        bt.key[idx] = key >> sh;
+        bt.begin[idx] = lo;
+        bt.end[idx] = hi;
+        bt.ix[idx] = (int32_t)ix;
+        bt.iy[idx] = (int32_t)iy;
+        bt.iz[idx] = (int32_t)iz;
+        bt.leaf[idx] = (hi - lo <= leaf_size || l == kMaxLevel) ? 1 : 0;
+        bt.geo[idx] = make_double4(rc.o[0] + ((double)ix + 0.5) * h, rc.o[1] + ((double)iy + 0.5) * h,
+                                   rc.o[2] + ((double)iz + 0.5) * h, h);
+    }
+}
+
+// Parent / children by binary search over the neighbouring levels (boxes of
+// one level are ordered by their first ion).
+__global__ void k_tree_links(BoxTable bt, const TreeSummary *__restrict__ sum)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= sum->nbox) return;
+    const int l = bt.level[b];
+    const int beg = bt.begin[b];
+    int parent = -1;
+    if (l > 0) {
+        int lo = sum->level_start[l - 1], hi = sum->level_start[l] - 1;  // last with begin <= beg
+        while (lo < hi) {
+            const int m = (lo + hi + 1) >> 1;
+            if (bt.begin[m] <= beg) lo = m;
+            else hi = m - 1;
+        }
+        parent = lo;
+    }
+    bt.parent[b] = parent;
+    int child = -1, nch = 0;
+    if (!bt.leaf[b] && l < kMaxLevel) {
+        int lo = sum->level_start[l + 1], hi = sum->level_start[l + 2];
+        int a = lo, e = hi;
+        while (a < e) {  // first with begin >= beg
+            const int m = (a + e) >> 1;
+            if (bt.begin[m] < beg) a = m + 1;
+            else e = m;
+        }
+        child = a;
+        const int end = bt.end[b];
+        int c2 = a, e2 = hi;
+        while (c2 < e2) {  // first with begin >= end
+            const int m = (c2 + e2) >> 1;
+            if (bt.begin[m] < end) c2 = m + 1;
+            else e2 = m;
+        }
+        nch = c2 - a;
+    }
+    bt.child[b] = child;
+    bt.nchild[b] = nch;
+}
+
+// Same-level neighbours (offsets in [-1,1]^3, slot (dx+1)*9 + (dy+1)*3 + (dz+1)).
+__global__ void k_colleagues(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ coll)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= sum->nbox) return;
+    const int l = bt.level[b];
+    const int c = bt.crystal[b];
+    const int lim = 1 << l;
+    const int x = bt.ix[b], y = bt.iy[b], z = bt.iz[b];
+    const int l0 = sum->level_start[l], l1 = sum->level_start[l + 1];
+    for (int s = 0; s < kNeigh; ++s) {
+        const int nx = x + s / 9 - 1, ny = y + (s / 3) % 3 - 1, nz = z + s % 3 - 1;
+        int found = -1;
+        if (s == 13) {
+            found = b;
+        } else if (nx >= 0 && ny >= 0 && nz >= 0 && nx < lim && ny < lim && nz < lim) {
+            const uint64_t want = ((uint64_t)c << (3 * l)) | morton3(nx, ny, nz);
+            int a = l0, e = l1;
+            while (a < e) {
+                const int m = (a + e) >> 1;
+                if (bt.key[m] < want) a = m + 1;
+                else e = m;
+            }
+            if (a < l1 && bt.key[a] == want) found = a;
+        }
+        coll[(size_t)b * kNeigh + s] = found;
+    }
+}
+
+// V lists into the dense window table (-1 = no source).
+__global__ void k_vlist(BoxTable bt, const TreeSummary *__restrict__ sum, const int32_t *__restrict__ coll,
+                        int32_t *__restrict__ vtab, unsigned long long *__restrict__ counter)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= sum->nbox) return;
+    int32_t *row = vtab + (size_t)b * kWin;
+    for (int w = 0; w < kWin; ++w) row[w] = -1;
+    const int l = bt.level[b];
+    if (l < 2) return;
+    const int x = bt.ix[b], y = bt.iy[b], z = bt.iz[b];
+    const int cx = x & 1, cy = y & 1, cz = z & 1;
+    const int P = bt.parent[b];
+    int cnt = 0;
+    for (int s = 0; s < kNeigh; ++s) {
+        const int Q = coll[(size_t)P * kNeigh + s];
+        if (Q < 0 || bt.leaf[Q]) continue;
+        const int c0 = bt.child[Q], c1 = c0 + bt.nchild[Q];
+        for (int ch = c0; ch < c1; ++ch) {
+            const int dx = bt.ix[ch] - x, dy = bt.iy[ch] - y, dz = bt.iz[ch] - z;
+            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
+            const int wx = dx + 2 + cx, wy = dy + 2 + cy, wz = dz + 2 + cz;
+            if (wx < 0 || wx > 5 || wy < 0 || wy > 5 || wz < 0 || wz > 5) continue;  // cannot happen in a valid tree
+            row[wx * 36 + wy * 6 + wz] = ch;
+            ++cnt;
+        }
+    }
+    if (cnt) atomicAdd(counter, (unsigned long long)cnt);
+}
+
+// Near lists of the leaves: ion ranges, stride entries per box.
+__global__ void k_nearlist(BoxTable bt, const TreeSummary *__restrict__ sum, const int32_t *__restrict__ coll,
+                           int stride, int2 *__restrict__ near, int32_t *__restrict__ near_cnt,
+                           unsigned long long *__restrict__ pair_counter)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= sum->nbox) return;
+    if (!bt.leaf[b]) {
+        near_cnt[b] = 0;
+        return;
+    }
+    int2 *row = near + (size_t)b * stride;
+    int cnt = 0;
+    long long srcs = 0;
+    for (int s = 0; s < kNeigh; ++s) {
+        const int Q = coll[(size_t)b * kNeigh + s];
+        if (Q < 0 || cnt >= stride) continue;
+        row[cnt++] = make_int2(bt.begin[Q], bt.end[Q]);
+        srcs += bt.end[Q] - bt.begin[Q];
+    }
+    for (int A = bt.parent[b]; A >= 0; A = bt.parent[A])
+        for (int s = 0; s < kNeigh; ++s) {
+            if (s == 13) continue;
+            const int Q = coll[(size_t)A * kNeigh + s];
+            if (Q < 0 || !bt.leaf[Q] || cnt >= stride) continue;
+            row[cnt++] = make_int2(bt.begin[Q], bt.end[Q]);
+            srcs += bt.end[Q] - bt.begin[Q];
+        }
+    near_cnt[b] = cnt;
+    const long long nt = bt.end[b] - bt.begin[b];
+    atomicAdd(pair_counter, (unsigned long long)(nt * srcs - nt));
+}
+
+// ---------------------------------------------------------------- launchers
+
+void launch_scan(uint32_t *a, int n, uint32_t *total, hipStream_t st)
+{
+    k_scan_excl<<<1, 1024, 0, st>>>(a, n, total);
+}
+
+int sort_blocks(int n) { return ceil_div(n, kSortTile); }
+
+void launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, int n, int shift,
+                       uint32_t *hist, hipStream_t st)
+{
+    const int nblk = sort_blocks(n);
+    k_radix_hist<<<nblk, kSortTB, 0, st>>>(kin, n, shift, hist, nblk);
+    k_scan_excl<<<1, 1024, 0, st>>>(hist, 256 * nblk, nullptr);
+    k_radix_scatter<<<nblk, kSortTB, 0, st>>>(kin, vin, kout, vout, n, shift, hist, nblk);
+}
+
+void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint32_t *vals, int ntot, double *sp,
+                   hipStream_t st)
+{
+    k_gather<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, vals, ntot, sp);
+}
+
+int tree_blocks(int ntot) { return ceil_div(ntot, 256); }
+
+void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
+                       uint32_t *blockcnt, uint32_t *total, TreeSummary *sum, hipStream_t st)
+{
+    const int nblk = tree_blocks(ntot);
+    k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask);
+    k_tree_count<<<nblk, 256, 0, st>>>(rep_mask, ntot, blockcnt, nblk);
+    k_scan_excl<<<1, 1024, 0, st>>>(blockcnt, (kMaxLevel + 1) * nblk, total);
+    k_tree_summary<<<1, 64, 0, st>>>(blockcnt, nblk, total, sum);
+}
+
+void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
+                       const uint32_t *rep_mask, const uint32_t *scanned, const BoxTable &bt, const TreeSummary *sum,
+                       int nbox, hipStream_t st)
+{
+    const int nblk = tree_blocks(ntot);
+    k_tree_emit<<<nblk, 256, 0, st>>>(cs, roots, keys, ntot, leaf_size, rep_mask, scanned, nblk, bt);
+    k_tree_links<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum);
+}
+
+void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
+                  int2 *near, int32_t *near_cnt, unsigned long long *counters, hipStream_t st)
+{
+    k_colleagues<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll);
+    k_vlist<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll, vtab, counters);
+    k_nearlist<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll, stride, near, near_cnt, counters + 1);
+}
+
+}  // namespace pt

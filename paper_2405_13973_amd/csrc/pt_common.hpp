@@ -1,0 +1,154 @@
+// Internal declarations shared by the HIP sources of libpenning.
+//
+// Data layout in HBM (one context, one batch of crystals per launch):
+//   - each crystal owns its state: one FP64 block x[n] y[n] z[n] vx[n] vy[n] vz[n]
+//     (structure of arrays, ion-id order) and photons[n];
+//   - a batch numbers all its ions consecutively, crystal by crystal; the
+//     per-ion workspace (keys, sorted positions, field) is indexed by that
+//     batch index or by the sorted slot;
+//   - boxes of all crystals of a batch live in one table ordered by
+//     (level, crystal, Morton prefix), so one launch per level covers the
+//     whole batch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/penning.h"
+
+namespace pt {
+
+constexpr int kMaxLevel = 16;   // keys hold 16 bits per axis
+constexpr int kMaxP = 20;
+constexpr int kWin = 216;       // 6x6x6 window of M2L source offsets per target box
+constexpr int kNeigh = 27;      // 3x3x3 colleague slots
+constexpr double kPi = 3.14159265358979323846;
+
+// Physical constants (CODATA 2022, SI).
+constexpr double kECharge = 1.602176634e-19;
+constexpr double kPlanck = 6.62607015e-34;
+constexpr double kEps0 = 8.8541878188e-12;
+
+// Everything a batched kernel needs to know about one crystal.  Built on
+// the host each time a batch is formed and copied to the device.
+struct CrystalDev {
+    double *state;        // 6 n doubles, see above
+    int32_t *photons;     // n
+    int32_t n;
+    int32_t ion_off;      // first batch index of this crystal
+    // integrator (host-computed in FP64)
+    double dt, t0;
+    double c_half, s_half;  // cos / sin of omega_c dt/2
+    double a_half, b_half;  // sin(omega_c dt/2)/omega_c, (1 - cos)/omega_c  (dt/2, 0 when B = 0)
+    double qkz;             // q k_z = m omega_z^2
+    double delta, omega_r;
+    double inv_m;
+    double coul;            // k_e q^2
+    double recoil;          // h / (lambda m), 0 when the laser is off
+    double poisson_F[17];   // cumulative Poisson table of the photon mean
+    int32_t laser_on;
+    int32_t pad;
+    uint64_t seed;
+    uint64_t step0;         // step index of the first step of the current call
+};
+
+// Root cube of a crystal: lower corner o, side W, quantisation scale 2^16/W.
+struct RootCube {
+    double o[3];
+    double W;
+    double S;
+    double pad[3];
+};
+
+// Device copy of the size summary read back after the tree count.
+struct TreeSummary {
+    int32_t level_start[kMaxLevel + 2];  // boxes of level l: [level_start[l], level_start[l+1])
+    int32_t nbox;
+    int32_t pad[3];
+};
+
+// ---------------------------------------------------------------- helpers
+
+__host__ __device__ inline uint64_t spread3_16(uint64_t x)
+{
+    x &= 0xFFFFull;
+    x = (x | (x << 16)) & 0x0000FF0000FFull;
+    x = (x | (x << 8)) & 0x00F00F00F00Full;
+    x = (x | (x << 4)) & 0x0C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x249249249249ull;
+    return x;
+}
+
+__host__ __device__ inline uint32_t compact3_16(uint64_t x)
+{
+    x &= 0x249249249249ull;
+    x = (x | (x >> 2)) & 0x0C30C30C30C3ull;
+    x = (x | (x >> 4)) & 0x00F00F00F00Full;
+    x = (x | (x >> 8)) & 0x0000FF0000FFull;
+    x = (x | (x >> 16)) & 0xFFFFull;
+    return (uint32_t)x;
+}
+
+// Morton code of integer coordinates: x in the top bit of each triple.
+__host__ __device__ inline uint64_t morton3(uint32_t ix, uint32_t iy, uint32_t iz)
+{
+    return (spread3_16(ix) << 2) | (spread3_16(iy) << 1) | spread3_16(iz);
+}
+
+// Monotone map of a double onto uint64 so that integer min/max order doubles.
+__host__ __device__ inline uint64_t dbl_to_ordered(double v)
+{
+    uint64_t u;
+    __builtin_memcpy(&u, &v, sizeof(u));
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__host__ __device__ inline double ordered_to_dbl(uint64_t u)
+{
+    uint64_t b = (u & 0x8000000000000000ull) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u;
+    double d;
+    __builtin_memcpy(&d, &b, sizeof(d));
+    return d;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32 -> 64 bit
+// products with multipliers 0xD2511F53 and 0xCD9E8D57; the key advances by
+// the Weyl increments 0x9E3779B9, 0xBB67AE85 between rounds.
+__host__ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t x0 = (uint32_t)(pb >> 32) ^ c[1] ^ k0;
+        const uint32_t x2 = (uint32_t)(pa >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)pb;
+        c[3] = (uint32_t)pa;
+        c[0] = x0;
+        c[2] = x2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Uniform double in [0,1) from the high 27 bits of a and the high 26 of b.
+__host__ __device__ inline double u53(uint32_t a, uint32_t b)
+{
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace pt
+
+// Error plumbing for host code.
+void pt_set_error(const char *fmt, ...);
+#define PT_HIP(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            pt_set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return PT_EDEVICE;                                                                    \
+        }                                                                                         \
+    } while (0)

@@ -1,0 +1,61 @@
+// Launch wrappers of the HIP kernels (one translation unit per group).
+#pragma once
+
+#include "pt_common.hpp"
+
+namespace pt {
+
+// Box table of a batch, structure of arrays, boxes ordered by
+// (level, crystal, Morton prefix).
+struct BoxTable {
+    int32_t *level, *crystal, *begin, *end, *parent, *child, *nchild, *ix, *iy, *iz;
+    uint64_t *key;    // crystal << 3l | Morton prefix
+    uint8_t *leaf;
+    double4 *geo;     // centre xyz, side h
+};
+
+// k_step.hip
+void launch_ion_crystal(const CrystalDev *cs, int nc, int ntot, int32_t *ion_crystal, hipStream_t st);
+void launch_bbox_reset(unsigned long long *bbox, int nc, hipStream_t st);
+void launch_zero_u64(uint64_t *p, int n, hipStream_t st);
+void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int do_drift,
+                       unsigned long long *bbox, hipStream_t st);
+void launch_root(unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st);
+void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCube *roots, int ntot, uint64_t *keys,
+                 uint32_t *vals, hipStream_t st);
+void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
+                       hipStream_t st);
+int direct_targets_per_block();
+void launch_direct(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int ntot,
+                   double *E, hipStream_t st);
+
+// k_tree.hip
+void launch_scan(uint32_t *a, int n, uint32_t *total, hipStream_t st);
+int sort_blocks(int n);
+void launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, int n, int shift,
+                       uint32_t *hist, hipStream_t st);
+void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint32_t *vals, int ntot, double *sp,
+                   hipStream_t st);
+int tree_blocks(int ntot);
+void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
+                       uint32_t *blockcnt, uint32_t *total, TreeSummary *sum, hipStream_t st);
+void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
+                       const uint32_t *rep_mask, const uint32_t *scanned, const BoxTable &bt, const TreeSummary *sum,
+                       int nbox, hipStream_t st);
+void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
+                  int2 *near, int32_t *near_cnt, unsigned long long *counters, hipStream_t st);
+
+// k_fmm.hip
+template <typename T>
+void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *m2m_t,
+                   T *M, hipStream_t st);
+template <typename T>
+void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t *vtab, const T *m2l_t, const T *M,
+                T *L, hipStream_t st);
+template <typename T>
+void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_t, T *L, hipStream_t st);
+template <typename T>
+void launch_eval(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const int2 *near,
+                 const int32_t *near_cnt, int stride, const uint32_t *vals, int use_far, double *E, hipStream_t st);
+
+}  // namespace pt

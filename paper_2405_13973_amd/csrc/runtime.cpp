@@ -1,0 +1,1005 @@
+// Host runtime of libpenning: contexts, crystals, device memory under an HBM
+// budget, the batched step loop and the force-evaluation pipeline.
+//
+// Per force evaluation of a batch (all crystals of one pt_step_batch /
+// pt_compute_forces_batch call that are still active):
+//   bbox (fused with the first half drift when stepping) -> root cubes ->
+//   keys -> LSD radix sort (8-bit digits over crystal + 48 key bits) ->
+//   gather sorted positions -> per-level box counts -> [one host read-back of
+//   the box count per level] -> box table + links -> colleagues, V windows,
+//   near lists -> P2M, M2M per level -> M2L -> L2L per level -> L2P + P2P.
+// The direct method replaces everything after the bbox by one kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "fmm_math.hpp"
+#include "pt_common.hpp"
+#include "pt_kernels.hpp"
+
+using namespace pt;
+
+// ---------------------------------------------------------------- errors
+
+static thread_local char g_err[512] = "";
+
+void pt_set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+#define PT_REQUIRE(cond, ...)          \
+    do {                               \
+        if (!(cond)) {                 \
+            pt_set_error(__VA_ARGS__); \
+            return PT_EINVAL;          \
+        }                              \
+    } while (0)
+
+#define PT_TRY(expr)                  \
+    do {                              \
+        pt_status s_ = (expr);        \
+        if (s_ != PT_OK) return s_;   \
+    } while (0)
+
+// ---------------------------------------------------------------- objects
+
+namespace {
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Tables {
+    int p = -1;
+    double *m2m_d = nullptr, *l2l_d = nullptr, *m2l_d = nullptr;
+    float *m2m_f = nullptr, *l2l_f = nullptr, *m2l_f = nullptr;
+};
+
+}  // namespace
+
+struct pt_crystal {
+    pt_ctx *ctx = nullptr;
+    int64_t n = 0;
+    double q = 0, m = 0;
+    uint64_t seed = 0;
+    pt_trap_params trap{};
+    pt_laser_params laser{};
+    pt_force_params force{};
+    int64_t step = 0;
+    double *d_state = nullptr;   // 6 n
+    int32_t *d_photons = nullptr;
+};
+
+struct pt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t budget = 0, used = 0;
+    int live = 0;
+    std::map<void *, size_t> allocs;
+    // workspace (grow-only)
+    std::map<std::string, DevBuf> ws;
+    Tables tables;
+    // pinned host staging
+    CrystalDev *h_desc = nullptr;
+    int h_desc_cap = 0;
+    TreeSummary *h_sum = nullptr;
+    unsigned long long *h_counters = nullptr;
+    // last force evaluation (for the debug export and statistics)
+    std::vector<pt_crystal *> last_batch;
+    std::vector<int32_t> last_off;
+    uint64_t *last_keys = nullptr;
+    uint32_t *last_vals = nullptr;
+    int last_ntot = 0, last_was_fmm = 0, last_stride = 0, last_p = 0, last_prec = 0;
+    TreeSummary last_sum{};
+    // timing
+    int timing = 0;
+    hipEvent_t ev[7] = {};
+    double phase_ms[6] = {0, 0, 0, 0, 0, 0};
+};
+
+// ---------------------------------------------------------------- memory
+
+static pt_status ctx_alloc(pt_ctx *ctx, void **out, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (ctx->budget && ctx->used + bytes > ctx->budget) {
+        pt_set_error("HBM budget exceeded: %llu + %llu > %llu bytes", (unsigned long long)ctx->used,
+                     (unsigned long long)bytes, (unsigned long long)ctx->budget);
+        return PT_ENOMEM;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        pt_set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? PT_ENOMEM : PT_EDEVICE;
+    }
+    ctx->used += bytes;
+    ctx->allocs[p] = bytes;
+    *out = p;
+    return PT_OK;
+}
+
+static void ctx_free(pt_ctx *ctx, void *p)
+{
+    if (!p) return;
+    auto it = ctx->allocs.find(p);
+    if (it != ctx->allocs.end()) {
+        ctx->used -= it->second;
+        ctx->allocs.erase(it);
+    }
+    (void)hipFree(p);
+}
+
+// Workspace buffer `name` of at least `bytes` (contents not preserved on growth).
+template <typename T>
+static pt_status ws_get(pt_ctx *ctx, const char *name, size_t bytes, T **out)
+{
+    DevBuf &b = ctx->ws[name];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            PT_HIP(hipStreamSynchronize(ctx->stream));
+            ctx_free(ctx, b.ptr);
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        size_t want = bytes + bytes / 4 + 256;
+        PT_TRY(ctx_alloc(ctx, &b.ptr, want));
+        b.bytes = want;
+    }
+    *out = (T *)b.ptr;
+    return PT_OK;
+}
+
+// ---------------------------------------------------------------- tables
+
+static pt_status ensure_tables(pt_ctx *ctx, int p)
+{
+    Tables &t = ctx->tables;
+    if (t.p == p) return PT_OK;
+    PT_HIP(hipStreamSynchronize(ctx->stream));
+    for (void *q : {(void *)t.m2m_d, (void *)t.l2l_d, (void *)t.m2l_d, (void *)t.m2m_f, (void *)t.l2l_f,
+                    (void *)t.m2l_f})
+        ctx_free(ctx, q);
+    t = Tables{};
+    const int K = kcoef(p);
+    const size_t KK = (size_t)K * K;
+    std::vector<double> m2m(8 * KK), l2l(8 * KK), m2l(343 * KK);
+    if (build_operator_tables(p, m2m.data(), l2l.data(), m2l.data()) != 0) {
+        pt_set_error("operator tables: unsupported p = %d", p);
+        return PT_EINVAL;
+    }
+    // column-major copies: Tt[o][j][i] = T[o][i][j]
+    auto transpose = [&](std::vector<double> &v, int count) {
+        std::vector<double> o(v.size());
+        for (int c = 0; c < count; ++c)
+            for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j) o[c * KK + (size_t)j * K + i] = v[c * KK + (size_t)i * K + j];
+        v.swap(o);
+    };
+    transpose(m2m, 8);
+    transpose(l2l, 8);
+    transpose(m2l, 343);
+    auto upload = [&](const std::vector<double> &v, double **dd, float **df) -> pt_status {
+        PT_TRY(ctx_alloc(ctx, (void **)dd, v.size() * sizeof(double)));
+        PT_HIP(hipMemcpy(*dd, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+        std::vector<float> f(v.begin(), v.end());
+        PT_TRY(ctx_alloc(ctx, (void **)df, f.size() * sizeof(float)));
+        PT_HIP(hipMemcpy(*df, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+        return PT_OK;
+    };
+    PT_TRY(upload(m2m, &t.m2m_d, &t.m2m_f));
+    PT_TRY(upload(l2l, &t.l2l_d, &t.l2l_f));
+    PT_TRY(upload(m2l, &t.m2l_d, &t.m2l_f));
+    t.p = p;
+    return PT_OK;
+}
+
+// ---------------------------------------------------------------- batch
+
+struct Batch {
+    std::vector<pt_crystal *> cs;
+    std::vector<int32_t> off;
+    int ntot = 0;
+    CrystalDev *d_desc = nullptr;
+    int32_t *ion_crystal = nullptr;
+    int32_t *blk_crystal = nullptr, *blk_first = nullptr;
+    int nblk_direct = 0;
+};
+
+static void fill_desc(const pt_crystal *c, int off, CrystalDev &d)
+{
+    std::memset(&d, 0, sizeof(d));
+    d.state = c->d_state;
+    d.photons = c->d_photons;
+    d.n = (int32_t)c->n;
+    d.ion_off = off;
+    d.dt = c->trap.dt_s;
+    d.t0 = c->trap.t0_s;
+    const double wc = c->q * c->trap.B_T / c->m;
+    const double th = wc * 0.5 * c->trap.dt_s;
+    d.c_half = std::cos(th);
+    d.s_half = std::sin(th);
+    if (wc != 0.0) {
+        d.a_half = d.s_half / wc;
+        d.b_half = (1.0 - d.c_half) / wc;
+    } else {
+        d.a_half = 0.5 * c->trap.dt_s;
+        d.b_half = 0.0;
+    }
+    d.qkz = c->m * c->trap.omega_z * c->trap.omega_z;
+    d.delta = c->trap.delta;
+    d.omega_r = c->trap.omega_r;
+    d.inv_m = 1.0 / c->m;
+    d.coul = c->q * c->q / (4.0 * kPi * kEps0);
+    const bool on = c->laser.mode == 1 && c->laser.mean_per_step > 0.0;
+    d.laser_on = on ? 1 : 0;
+    d.recoil = on ? kPlanck / (c->laser.wavelength_m * c->m) : 0.0;
+    // cumulative Poisson table p_0 = e^-lam, p_k = p_{k-1} lam / k
+    double pk = std::exp(-(on ? c->laser.mean_per_step : 0.0)), acc = pk;
+    d.poisson_F[0] = acc;
+    for (int k = 1; k <= 16; ++k) {
+        pk = pk * (on ? c->laser.mean_per_step : 0.0) / (double)k;
+        acc = acc + pk;
+        d.poisson_F[k] = acc;
+    }
+    d.seed = c->seed;
+    d.step0 = (uint64_t)c->step;
+}
+
+static pt_status form_batch(pt_ctx *ctx, const std::vector<pt_crystal *> &cs, Batch &b)
+{
+    b.cs = cs;
+    b.off.assign(cs.size() + 1, 0);
+    long long tot = 0;
+    for (size_t i = 0; i < cs.size(); ++i) {
+        b.off[i] = (int32_t)tot;
+        tot += cs[i]->n;
+    }
+    PT_REQUIRE(tot < (1ll << 31) - (1 << 20), "batch of %lld ions is too large", tot);
+    b.off[cs.size()] = (int32_t)tot;
+    b.ntot = (int)tot;
+    const int nc = (int)cs.size();
+    PT_TRY(ws_get(ctx, "desc", sizeof(CrystalDev) * nc, &b.d_desc));
+    PT_TRY(ws_get(ctx, "ion_crystal", sizeof(int32_t) * std::max(1, b.ntot), &b.ion_crystal));
+    if (ctx->h_desc_cap < nc) {
+        PT_HIP(hipStreamSynchronize(ctx->stream));
+        if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
+        ctx->h_desc = nullptr;
+        PT_HIP(hipHostMalloc((void **)&ctx->h_desc, sizeof(CrystalDev) * nc * 2));
+        ctx->h_desc_cap = nc * 2;
+    } else {
+        PT_HIP(hipStreamSynchronize(ctx->stream));  // staging buffer may still be read by a copy
+    }
+    for (int i = 0; i < nc; ++i) fill_desc(cs[i], b.off[i], ctx->h_desc[i]);
+    PT_HIP(hipMemcpyAsync(b.d_desc, ctx->h_desc, sizeof(CrystalDev) * nc, hipMemcpyHostToDevice, ctx->stream));
+    launch_ion_crystal(b.d_desc, nc, b.ntot, b.ion_crystal, ctx->stream);
+    // bounding boxes start empty; the root-cube kernel empties them again after each use
+    unsigned long long *bbox;
+    PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * 6 * nc, &bbox));
+    launch_bbox_reset(bbox, nc, ctx->stream);
+    // direct-method block table: each block serves targets of one crystal
+    const int tpb = direct_targets_per_block();
+    std::vector<int32_t> bc, bf;
+    for (int i = 0; i < nc; ++i)
+        for (int64_t f = 0; f < cs[i]->n; f += tpb) {
+            bc.push_back(i);
+            bf.push_back((int32_t)f);
+        }
+    b.nblk_direct = (int)bc.size();
+    PT_TRY(ws_get(ctx, "blk_crystal", sizeof(int32_t) * std::max<size_t>(1, bc.size()), &b.blk_crystal));
+    PT_TRY(ws_get(ctx, "blk_first", sizeof(int32_t) * std::max<size_t>(1, bf.size()), &b.blk_first));
+    if (!bc.empty()) {
+        PT_HIP(hipMemcpyAsync(b.blk_crystal, bc.data(), bc.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+        PT_HIP(hipMemcpyAsync(b.blk_first, bf.data(), bf.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+        PT_HIP(hipStreamSynchronize(ctx->stream));  // pageable sources
+    }
+    return PT_OK;
+}
+
+static void mark(pt_ctx *ctx, int i)
+{
+    if (ctx->timing) (void)hipEventRecord(ctx->ev[i], ctx->stream);
+}
+
+static BoxTable box_table(pt_ctx *ctx)
+{
+    BoxTable t{};
+    auto g = [&](const char *n) { return ctx->ws[n].ptr; };
+    t.level = (int32_t *)g("b_level");
+    t.crystal = (int32_t *)g("b_crystal");
+    t.begin = (int32_t *)g("b_begin");
+    t.end = (int32_t *)g("b_end");
+    t.parent = (int32_t *)g("b_parent");
+    t.child = (int32_t *)g("b_child");
+    t.nchild = (int32_t *)g("b_nchild");
+    t.ix = (int32_t *)g("b_ix");
+    t.iy = (int32_t *)g("b_iy");
+    t.iz = (int32_t *)g("b_iz");
+    t.key = (uint64_t *)g("b_key");
+    t.leaf = (uint8_t *)g("b_leaf");
+    t.geo = (double4 *)g("b_geo");
+    return t;
+}
+
+// Coulomb field per unit charge of every ion of the batch into E (3 x ntot,
+// batch order).  Expects the bbox of the current positions accumulated.
+static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, double *E)
+{
+    hipStream_t st = ctx->stream;
+    const int ntot = b.ntot, nc = (int)b.cs.size();
+    unsigned long long *bbox;
+    PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * 6 * nc, &bbox));
+    ctx->last_batch = b.cs;
+    ctx->last_off = b.off;
+    ctx->last_ntot = ntot;
+    ctx->last_was_fmm = fp.method == 1;
+    mark(ctx, 0);
+    if (fp.method == 0) {
+        launch_direct(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, ntot, E, st);
+        mark(ctx, 1);
+        mark(ctx, 2);
+        mark(ctx, 3);
+        mark(ctx, 4);
+        mark(ctx, 5);
+        return PT_OK;
+    }
+    const int p = fp.p, s = fp.leaf_size;
+    RootCube *roots;
+    uint64_t *k0, *k1;
+    uint32_t *v0, *v1, *hist, *rep, *bcnt, *total;
+    double *sp;
+    TreeSummary *dsum;
+    unsigned long long *counters;
+    PT_TRY(ws_get(ctx, "roots", sizeof(RootCube) * nc, &roots));
+    PT_TRY(ws_get(ctx, "keys0", sizeof(uint64_t) * ntot, &k0));
+    PT_TRY(ws_get(ctx, "keys1", sizeof(uint64_t) * ntot, &k1));
+    PT_TRY(ws_get(ctx, "vals0", sizeof(uint32_t) * ntot, &v0));
+    PT_TRY(ws_get(ctx, "vals1", sizeof(uint32_t) * ntot, &v1));
+    PT_TRY(ws_get(ctx, "hist", sizeof(uint32_t) * 256 * sort_blocks(ntot), &hist));
+    PT_TRY(ws_get(ctx, "rep", sizeof(uint32_t) * ntot, &rep));
+    PT_TRY(ws_get(ctx, "bcnt", sizeof(uint32_t) * (kMaxLevel + 1) * tree_blocks(ntot), &bcnt));
+    PT_TRY(ws_get(ctx, "total", sizeof(uint32_t) * 4, &total));
+    PT_TRY(ws_get(ctx, "sp", sizeof(double) * 3 * ntot, &sp));
+    PT_TRY(ws_get(ctx, "sum", sizeof(TreeSummary), &dsum));
+    PT_TRY(ws_get(ctx, "counters", sizeof(unsigned long long) * 2, &counters));
+    launch_root(bbox, nc, roots, st);
+    launch_keys(b.d_desc, b.ion_crystal, roots, ntot, k0, v0, st);
+    int cbits = 0;
+    while ((1 << cbits) < nc) ++cbits;
+    const int passes = (48 + cbits + 7) / 8;
+    for (int ps = 0; ps < passes; ++ps) {
+        launch_radix_pass(k0, v0, k1, v1, ntot, 8 * ps, hist, st);
+        std::swap(k0, k1);
+        std::swap(v0, v1);
+    }
+    launch_gather(b.d_desc, b.ion_crystal, v0, ntot, sp, st);
+    launch_tree_count(b.d_desc, k0, ntot, s, rep, bcnt, total, dsum, st);
+    PT_HIP(hipMemcpyAsync(ctx->h_sum, dsum, sizeof(TreeSummary), hipMemcpyDeviceToHost, st));
+    launch_zero_u64((uint64_t *)counters, 2, st);
+    PT_HIP(hipStreamSynchronize(st));
+    const TreeSummary hs = *ctx->h_sum;
+    const int nbox = hs.nbox;
+    int nlev = 0;
+    for (int l = 0; l <= kMaxLevel; ++l)
+        if (hs.level_start[l + 1] > hs.level_start[l]) nlev = l + 1;
+    const int stride = kNeigh + 26 * std::max(0, nlev - 1);
+    const int Kp = kpad(p);
+    const size_t esz = fp.precision == 1 ? sizeof(float) : sizeof(double);
+    void *scratch;
+    const char *i32names[] = {"b_level", "b_crystal", "b_begin", "b_end", "b_parent", "b_child", "b_nchild",
+                              "b_ix",    "b_iy",      "b_iz",    "near_cnt"};
+    for (const char *nm : i32names) PT_TRY(ws_get(ctx, nm, sizeof(int32_t) * nbox, (int32_t **)&scratch));
+    PT_TRY(ws_get(ctx, "b_key", sizeof(uint64_t) * nbox, (uint64_t **)&scratch));
+    PT_TRY(ws_get(ctx, "b_leaf", sizeof(uint8_t) * nbox, (uint8_t **)&scratch));
+    PT_TRY(ws_get(ctx, "b_geo", sizeof(double4) * nbox, (double4 **)&scratch));
+    int32_t *coll, *vtab, *near_cnt;
+    int2 *near;
+    void *M, *L;
+    PT_TRY(ws_get(ctx, "coll", sizeof(int32_t) * kNeigh * (size_t)nbox, &coll));
+    PT_TRY(ws_get(ctx, "vtab", sizeof(int32_t) * kWin * (size_t)nbox, &vtab));
+    PT_TRY(ws_get(ctx, "near", sizeof(int2) * (size_t)stride * nbox, &near));
+    PT_TRY(ws_get(ctx, "M", esz * Kp * (size_t)nbox, (char **)&M));
+    PT_TRY(ws_get(ctx, "L", esz * Kp * (size_t)nbox, (char **)&L));
+    near_cnt = (int32_t *)ctx->ws["near_cnt"].ptr;
+    PT_TRY(ensure_tables(ctx, p));
+    const BoxTable bt = box_table(ctx);
+    launch_tree_build(b.d_desc, roots, k0, ntot, s, rep, bcnt, bt, dsum, nbox, st);
+    launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, counters, st);
+    mark(ctx, 1);
+    const Tables &tb = ctx->tables;
+    if (fp.precision == 1) {
+        launch_upward<float>(bt, sp, ntot, p, hs, tb.m2m_f, (float *)M, st);
+        mark(ctx, 2);
+        launch_m2l<float>(bt, p, hs, vtab, tb.m2l_f, (const float *)M, (float *)L, st);
+        mark(ctx, 3);
+        launch_downward<float>(bt, p, hs, tb.l2l_f, (float *)L, st);
+        mark(ctx, 4);
+        launch_eval<float>(bt, sp, ntot, p, nbox, (const float *)L, near, near_cnt, stride, v0, 1, E, st);
+    } else {
+        launch_upward<double>(bt, sp, ntot, p, hs, tb.m2m_d, (double *)M, st);
+        mark(ctx, 2);
+        launch_m2l<double>(bt, p, hs, vtab, tb.m2l_d, (const double *)M, (double *)L, st);
+        mark(ctx, 3);
+        launch_downward<double>(bt, p, hs, tb.l2l_d, (double *)L, st);
+        mark(ctx, 4);
+        launch_eval<double>(bt, sp, ntot, p, nbox, (const double *)L, near, near_cnt, stride, v0, 1, E, st);
+    }
+    mark(ctx, 5);
+    ctx->last_sum = hs;
+    ctx->last_stride = stride;
+    ctx->last_p = p;
+    ctx->last_prec = fp.precision;
+    ctx->last_keys = k0;  // the ping-pong buffer holding the sorted result
+    ctx->last_vals = v0;
+    return PT_OK;
+}
+
+static pt_status finish_timing(pt_ctx *ctx)
+{
+    if (!ctx->timing) return PT_OK;
+    PT_HIP(hipEventSynchronize(ctx->ev[5]));
+    float ms;
+    for (int i = 0; i < 5; ++i) {
+        PT_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+        ctx->phase_ms[i] = ms;
+    }
+    PT_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[5]));
+    ctx->phase_ms[5] = ms;
+    return PT_OK;
+}
+
+// ---------------------------------------------------------------- validation
+
+static bool finite_all(const double *a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+static pt_status check_trap(const pt_crystal *c, const pt_trap_params *p)
+{
+    PT_REQUIRE(p, "trap params NULL");
+    const double v[6] = {p->B_T, p->omega_z, p->delta, p->omega_r, p->dt_s, p->t0_s};
+    PT_REQUIRE(finite_all(v, 6), "trap params must be finite");
+    PT_REQUIRE(p->dt_s > 0.0, "dt must be > 0");
+    PT_REQUIRE(p->omega_z >= 0.0, "omega_z must be >= 0");
+    const double wc = c->q * p->B_T / c->m;
+    PT_REQUIRE(p->omega_z == 0.0 || wc * wc > 2.0 * p->omega_z * p->omega_z,
+               "trap does not confine: omega_c^2 = %g <= 2 omega_z^2 = %g", wc * wc,
+               2.0 * p->omega_z * p->omega_z);
+    return PT_OK;
+}
+
+static pt_status check_force(const pt_force_params *p)
+{
+    PT_REQUIRE(p, "force params NULL");
+    PT_REQUIRE(p->method == 0 || p->method == 1, "method must be 0 (direct) or 1 (fmm)");
+    PT_REQUIRE(p->precision == 0 || p->precision == 1, "precision must be 0 or 1");
+    if (p->method == 1) {
+        PT_REQUIRE(p->p >= 1 && p->p <= kMaxP, "p must be in [1, %d]", kMaxP);
+        PT_REQUIRE(p->leaf_size >= 1 && p->leaf_size <= 4096, "leaf_size must be in [1, 4096]");
+    }
+    return PT_OK;
+}
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char *pt_last_error(void) { return g_err; }
+
+pt_status pt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, void *hip_stream, pt_ctx **out)
+{
+    PT_REQUIRE(out, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        pt_set_error("no HIP device available");
+        return PT_EDEVICE;
+    }
+    PT_REQUIRE(hip_device >= 0 && hip_device < ndev, "device %d out of range [0, %d)", hip_device, ndev);
+    PT_HIP(hipSetDevice(hip_device));
+    std::unique_ptr<pt_ctx> ctx(new pt_ctx());
+    ctx->device = hip_device;
+    ctx->budget = hbm_budget_bytes;
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        PT_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        ctx->own_stream = true;
+    }
+    PT_HIP(hipHostMalloc((void **)&ctx->h_sum, sizeof(TreeSummary)));
+    PT_HIP(hipHostMalloc((void **)&ctx->h_counters, sizeof(unsigned long long) * 2));
+    for (auto &e : ctx->ev) PT_HIP(hipEventCreate(&e));
+    *out = ctx.release();
+    return PT_OK;
+}
+
+pt_status pt_ctx_destroy(pt_ctx *ctx)
+{
+    PT_REQUIRE(ctx, "ctx is NULL");
+    if (ctx->live > 0) {
+        pt_set_error("context still owns %d crystals", ctx->live);
+        return PT_EBUSY;
+    }
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &kv : ctx->allocs) (void)hipFree(kv.first);
+    ctx->allocs.clear();
+    if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
+    if (ctx->h_sum) (void)hipHostFree(ctx->h_sum);
+    if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return PT_OK;
+}
+
+pt_status pt_ctx_memory(pt_ctx *ctx, uint64_t *bytes_in_use, uint64_t *budget)
+{
+    PT_REQUIRE(ctx, "ctx is NULL");
+    if (bytes_in_use) *bytes_in_use = ctx->used;
+    if (budget) *budget = ctx->budget;
+    return PT_OK;
+}
+
+static pt_status create_common(pt_ctx *ctx, int64_t n, double charge, double mass, uint64_t seed, pt_crystal **out)
+{
+    PT_REQUIRE(ctx && out, "NULL argument");
+    *out = nullptr;
+    PT_REQUIRE(n >= 1 && n < (1ll << 30), "n must be in [1, 2^30)");
+    PT_REQUIRE(std::isfinite(charge) && charge != 0.0, "charge must be finite and non-zero");
+    PT_REQUIRE(std::isfinite(mass) && mass > 0.0, "mass must be finite and > 0");
+    std::unique_ptr<pt_crystal> c(new pt_crystal());
+    c->ctx = ctx;
+    c->n = n;
+    c->q = charge;
+    c->m = mass;
+    c->seed = seed;
+    c->trap = {4.5, 2.0 * kPi * 1.5e6, 0.0, 0.0, 1e-9, 0.0};
+    if ((c->q * 4.5 / c->m) * (c->q * 4.5 / c->m) <= 2.0 * c->trap.omega_z * c->trap.omega_z) c->trap.omega_z = 0.0;
+    c->laser = {0, 0.0, 313e-9};
+    c->force = {0, 8, 32, 0};
+    PT_HIP(hipSetDevice(ctx->device));
+    PT_TRY(ctx_alloc(ctx, (void **)&c->d_state, sizeof(double) * 6 * (size_t)n));
+    pt_status s = ctx_alloc(ctx, (void **)&c->d_photons, sizeof(int32_t) * (size_t)n);
+    if (s != PT_OK) {
+        ctx_free(ctx, c->d_state);
+        return s;
+    }
+    PT_HIP(hipMemsetAsync(c->d_photons, 0, sizeof(int32_t) * n, ctx->stream));
+    *out = c.release();
+    ctx->live++;
+    return PT_OK;
+}
+
+// Interleaved n x 3 host array -> SoA device block (6 n doubles: pos then vel).
+static pt_status upload_state(pt_crystal *c, const double *pos, const double *vel)
+{
+    const int64_t n = c->n;
+    std::vector<double> soa(6 * (size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            soa[d * n + i] = pos[3 * i + d];
+            soa[(3 + d) * n + i] = vel[3 * i + d];
+        }
+    PT_HIP(hipMemcpy(c->d_state, soa.data(), sizeof(double) * 6 * n, hipMemcpyHostToDevice));
+    return PT_OK;
+}
+
+pt_status pt_create_crystal(pt_ctx *ctx, int64_t n, const double *pos_xyz, const double *vel_xyz, double charge_C,
+                            double mass_kg, uint64_t seed, pt_crystal **out)
+{
+    PT_REQUIRE(pos_xyz && vel_xyz, "pos/vel NULL");
+    PT_REQUIRE(n >= 1 && n < (1ll << 30), "n must be in [1, 2^30)");
+    PT_REQUIRE(finite_all(pos_xyz, 3 * n) && finite_all(vel_xyz, 3 * n), "non-finite position or velocity");
+    PT_TRY(create_common(ctx, n, charge_C, mass_kg, seed, out));
+    pt_status s = upload_state(*out, pos_xyz, vel_xyz);
+    if (s != PT_OK) {
+        pt_destroy_crystal(*out);
+        *out = nullptr;
+    }
+    return s;
+}
+
+pt_status pt_create_crystal_device(pt_ctx *ctx, int64_t n, const double *pos_dev, const double *vel_dev,
+                                   double charge_C, double mass_kg, uint64_t seed, pt_crystal **out)
+{
+    PT_REQUIRE(pos_dev && vel_dev, "pos/vel NULL");
+    PT_TRY(create_common(ctx, n, charge_C, mass_kg, seed, out));
+    std::vector<double> p(3 * (size_t)n), v(3 * (size_t)n);
+    pt_status s = PT_OK;
+    if (hipMemcpyAsync(p.data(), pos_dev, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(v.data(), vel_dev, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        pt_set_error("reading device buffers failed");
+        s = PT_EDEVICE;
+    } else if (!finite_all(p.data(), 3 * n) || !finite_all(v.data(), 3 * n)) {
+        pt_set_error("non-finite position or velocity");
+        s = PT_EINVAL;
+    } else {
+        s = upload_state(*out, p.data(), v.data());
+    }
+    if (s != PT_OK) {
+        pt_destroy_crystal(*out);
+        *out = nullptr;
+    }
+    return s;
+}
+
+pt_status pt_destroy_crystal(pt_crystal *c)
+{
+    PT_REQUIRE(c, "crystal is NULL");
+    pt_ctx *ctx = c->ctx;
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx_free(ctx, c->d_state);
+    ctx_free(ctx, c->d_photons);
+    auto &lb = ctx->last_batch;
+    if (std::find(lb.begin(), lb.end(), c) != lb.end()) lb.clear();
+    ctx->live--;
+    delete c;
+    return PT_OK;
+}
+
+pt_status pt_set_trap_params(pt_crystal *c, const pt_trap_params *p)
+{
+    PT_REQUIRE(c, "crystal is NULL");
+    PT_TRY(check_trap(c, p));
+    c->trap = *p;
+    return PT_OK;
+}
+
+pt_status pt_set_laser_params(pt_crystal *c, const pt_laser_params *p)
+{
+    PT_REQUIRE(c && p, "NULL argument");
+    PT_REQUIRE(p->mode == 0 || p->mode == 1, "laser mode must be 0 or 1");
+    if (p->mode == 1) {
+        PT_REQUIRE(std::isfinite(p->mean_per_step) && p->mean_per_step >= 0.0 && p->mean_per_step <= 2.0,
+                   "photon mean must be in [0, 2]");
+        PT_REQUIRE(std::isfinite(p->wavelength_m) && p->wavelength_m > 0.0, "wavelength must be > 0");
+    }
+    c->laser = *p;
+    return PT_OK;
+}
+
+pt_status pt_set_force_params(pt_crystal *c, const pt_force_params *p)
+{
+    PT_REQUIRE(c, "crystal is NULL");
+    PT_TRY(check_force(p));
+    c->force = *p;
+    return PT_OK;
+}
+
+pt_status pt_set_state(pt_crystal *c, const double *pos, const double *vel, int64_t step)
+{
+    PT_REQUIRE(c && pos && vel, "NULL argument");
+    PT_REQUIRE(step >= 0, "step must be >= 0");
+    PT_REQUIRE(finite_all(pos, 3 * c->n) && finite_all(vel, 3 * c->n), "non-finite position or velocity");
+    PT_HIP(hipStreamSynchronize(c->ctx->stream));
+    PT_TRY(upload_state(c, pos, vel));
+    c->step = step;
+    return PT_OK;
+}
+
+static bool same_force(const pt_force_params &a, const pt_force_params &b)
+{
+    if (a.method != b.method) return false;
+    if (a.method == 0) return true;
+    return a.p == b.p && a.leaf_size == b.leaf_size && a.precision == b.precision;
+}
+
+static pt_status check_batch(pt_crystal *const *cs, int nc)
+{
+    PT_REQUIRE(cs && nc >= 1, "empty batch");
+    for (int i = 0; i < nc; ++i) {
+        PT_REQUIRE(cs[i], "crystal %d is NULL", i);
+        PT_REQUIRE(cs[i]->ctx == cs[0]->ctx, "crystals of one batch must share the context");
+        PT_REQUIRE(same_force(cs[i]->force, cs[0]->force), "crystals of one batch must share force parameters");
+        for (int j = 0; j < i; ++j) PT_REQUIRE(cs[j] != cs[i], "crystal %d appears twice", i);
+    }
+    return PT_OK;
+}
+
+pt_status pt_compute_forces_batch(pt_crystal *const *cs, int n_crystals, double *const *F_out)
+{
+    PT_TRY(check_batch(cs, n_crystals));
+    PT_REQUIRE(F_out, "F_out NULL");
+    for (int i = 0; i < n_crystals; ++i) PT_REQUIRE(F_out[i], "F_out[%d] NULL", i);
+    pt_ctx *ctx = cs[0]->ctx;
+    PT_HIP(hipSetDevice(ctx->device));
+    Batch b;
+    PT_TRY(form_batch(ctx, std::vector<pt_crystal *>(cs, cs + n_crystals), b));
+    unsigned long long *bbox;
+    double *E;
+    PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * 6 * n_crystals, &bbox));
+    PT_TRY(ws_get(ctx, "E", sizeof(double) * 3 * (size_t)b.ntot, &E));
+    launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, 0, bbox, ctx->stream);
+    PT_TRY(eval_field(ctx, b, cs[0]->force, E));
+    std::vector<double> h(3 * (size_t)b.ntot);
+    PT_HIP(hipMemcpyAsync(h.data(), E, sizeof(double) * 3 * b.ntot, hipMemcpyDeviceToHost, ctx->stream));
+    PT_HIP(hipStreamSynchronize(ctx->stream));
+    PT_TRY(finish_timing(ctx));
+    for (int c = 0; c < n_crystals; ++c) {
+        const double coul = cs[c]->q * cs[c]->q / (4.0 * kPi * kEps0);
+        const int off = b.off[c];
+        for (int64_t i = 0; i < cs[c]->n; ++i)
+            for (int d = 0; d < 3; ++d) F_out[c][3 * i + d] = coul * h[(size_t)d * b.ntot + off + i];
+    }
+    return PT_OK;
+}
+
+pt_status pt_compute_forces(pt_crystal *c, double *F_out)
+{
+    return pt_compute_forces_batch(&c, 1, &F_out);
+}
+
+pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_steps)
+{
+    PT_TRY(check_batch(cs, n_crystals));
+    PT_REQUIRE(n_steps, "n_steps NULL");
+    int64_t kmax = 0;
+    for (int i = 0; i < n_crystals; ++i) {
+        PT_REQUIRE(n_steps[i] >= 0, "n_steps must be >= 0");
+        kmax = std::max(kmax, n_steps[i]);
+    }
+    pt_ctx *ctx = cs[0]->ctx;
+    PT_HIP(hipSetDevice(ctx->device));
+    Batch b;
+    int formed_for = -1;
+    int64_t group_start = 0;  // step at which the current batch was formed
+    for (int64_t k = 0; k < kmax; ++k) {
+        // crystals still stepping; the batch is re-formed only when one finishes
+        int nactive = 0;
+        for (int i = 0; i < n_crystals; ++i) nactive += n_steps[i] > k;
+        if (nactive != formed_for) {
+            std::vector<pt_crystal *> act;
+            for (int i = 0; i < n_crystals; ++i)
+                if (n_steps[i] > k) act.push_back(cs[i]);
+            // descriptors hold the step index of the first step of this group
+            for (auto *c : act) c->step += k;
+            pt_status s = form_batch(ctx, act, b);
+            for (auto *c : act) c->step -= k;
+            PT_TRY(s);
+            formed_for = nactive;
+            group_start = k;
+        }
+        const int nc = (int)b.cs.size();
+        unsigned long long *bbox;
+        double *E;
+        PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * 6 * nc, &bbox));
+        PT_TRY(ws_get(ctx, "E", sizeof(double) * 3 * (size_t)b.ntot, &E));
+        launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, 1, bbox, ctx->stream);
+        PT_TRY(eval_field(ctx, b, cs[0]->force, E));
+        // step index = descriptor step0 (set when the batch formed) + kstep
+        launch_kick_drift(b.d_desc, b.ion_crystal, b.ntot, (int)(k - group_start), E, ctx->stream);
+    }
+    for (int i = 0; i < n_crystals; ++i) cs[i]->step += n_steps[i];
+    PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
+pt_status pt_step(pt_crystal *c, int64_t n_steps) { return pt_step_batch(&c, 1, &n_steps); }
+
+pt_status pt_synchronize(pt_ctx *ctx)
+{
+    PT_REQUIRE(ctx, "ctx is NULL");
+    PT_HIP(hipStreamSynchronize(ctx->stream));
+    PT_HIP(hipGetLastError());
+    return PT_OK;
+}
+
+pt_status pt_read_state(pt_crystal *c, double *pos, double *vel, int64_t *step, double *t, int32_t *photons)
+{
+    PT_REQUIRE(c, "crystal is NULL");
+    pt_ctx *ctx = c->ctx;
+    const int64_t n = c->n;
+    std::vector<double> soa(6 * (size_t)n);
+    PT_HIP(hipMemcpyAsync(soa.data(), c->d_state, sizeof(double) * 6 * n, hipMemcpyDeviceToHost, ctx->stream));
+    if (photons)
+        PT_HIP(hipMemcpyAsync(photons, c->d_photons, sizeof(int32_t) * n, hipMemcpyDeviceToHost, ctx->stream));
+    PT_HIP(hipStreamSynchronize(ctx->stream));
+    bool finite = true;
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const double x = soa[d * n + i], v = soa[(3 + d) * n + i];
+            if (pos) pos[3 * i + d] = x;
+            if (vel) vel[3 * i + d] = v;
+            finite = finite && std::isfinite(x) && std::isfinite(v);
+        }
+    if (step) *step = c->step;
+    if (t) *t = c->trap.t0_s + (double)c->step * c->trap.dt_s;
+    if (!finite) {
+        pt_set_error("state holds non-finite values");
+        return PT_ENUMERIC;
+    }
+    return PT_OK;
+}
+
+pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable)
+{
+    PT_REQUIRE(ctx, "ctx is NULL");
+    ctx->timing = enable ? 1 : 0;
+    return PT_OK;
+}
+
+pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[6])
+{
+    PT_REQUIRE(ctx && ms, "NULL argument");
+    PT_TRY(finish_timing(ctx));
+    for (int i = 0; i < 6; ++i) ms[i] = ctx->phase_ms[i];
+    return PT_OK;
+}
+
+pt_status pt_ctx_work_counts(pt_ctx *ctx, int64_t counts[6])
+{
+    PT_REQUIRE(ctx && counts, "NULL argument");
+    for (int i = 0; i < 6; ++i) counts[i] = 0;
+    counts[5] = ctx->last_ntot;
+    if (!ctx->last_was_fmm) return PT_OK;
+    PT_HIP(hipStreamSynchronize(ctx->stream));
+    unsigned long long cnt[2];
+    PT_HIP(hipMemcpy(cnt, ctx->ws["counters"].ptr, sizeof(cnt), hipMemcpyDeviceToHost));
+    const int nbox = ctx->last_sum.nbox;
+    std::vector<uint8_t> leaf(nbox);
+    PT_HIP(hipMemcpy(leaf.data(), ctx->ws["b_leaf"].ptr, nbox, hipMemcpyDeviceToHost));
+    int64_t nl = 0;
+    for (uint8_t x : leaf) nl += x;
+    int nlev = 0;
+    for (int l = 0; l <= kMaxLevel; ++l)
+        if (ctx->last_sum.level_start[l + 1] > ctx->last_sum.level_start[l]) nlev = l + 1;
+    counts[0] = nbox;
+    counts[1] = nl;
+    counts[2] = (int64_t)cnt[0];
+    counts[3] = (int64_t)cnt[1];
+    counts[4] = nlev;
+    return PT_OK;
+}
+
+pt_status pt_debug_export_tree(pt_crystal *c, int64_t sizes[4], uint64_t *keys, int32_t *perm, int32_t *level,
+                               int32_t *parent, int32_t *ion_begin, int32_t *ion_end, int32_t *coords,
+                               uint8_t *is_leaf, int32_t *v_off, int32_t *v_src, int32_t *near_off,
+                               int32_t *near_src, double *root)
+{
+    PT_REQUIRE(c && sizes, "NULL argument");
+    pt_ctx *ctx = c->ctx;
+    auto &lb = ctx->last_batch;
+    auto it = std::find(lb.begin(), lb.end(), c);
+    PT_REQUIRE(ctx->last_was_fmm && it != lb.end(), "no FMM evaluation of this crystal to export");
+    const int ci = (int)(it - lb.begin());
+    const int off = ctx->last_off[ci];
+    const int n = (int)c->n;
+    const int nbox = ctx->last_sum.nbox, ntot = ctx->last_ntot, stride = ctx->last_stride;
+    PT_HIP(hipStreamSynchronize(ctx->stream));
+    auto dl = [&](const char *nm, void *dst, size_t bytes) -> pt_status {
+        PT_HIP(hipMemcpy(dst, ctx->ws[nm].ptr, bytes, hipMemcpyDeviceToHost));
+        return PT_OK;
+    };
+    std::vector<int32_t> bl(nbox), bcr(nbox), bb(nbox), be(nbox), bp(nbox), bx(nbox), by(nbox), bz(nbox), vt,
+        nc(nbox);
+    std::vector<uint8_t> blf(nbox);
+    PT_TRY(dl("b_level", bl.data(), 4 * nbox));
+    PT_TRY(dl("b_crystal", bcr.data(), 4 * nbox));
+    PT_TRY(dl("b_begin", bb.data(), 4 * nbox));
+    PT_TRY(dl("b_end", be.data(), 4 * nbox));
+    PT_TRY(dl("b_parent", bp.data(), 4 * nbox));
+    PT_TRY(dl("b_ix", bx.data(), 4 * nbox));
+    PT_TRY(dl("b_iy", by.data(), 4 * nbox));
+    PT_TRY(dl("b_iz", bz.data(), 4 * nbox));
+    PT_TRY(dl("b_leaf", blf.data(), nbox));
+    PT_TRY(dl("near_cnt", nc.data(), 4 * nbox));
+    vt.resize((size_t)kWin * nbox);
+    PT_TRY(dl("vtab", vt.data(), 4 * vt.size()));
+    std::vector<int2> nr((size_t)stride * nbox);
+    PT_TRY(dl("near", nr.data(), sizeof(int2) * nr.size()));
+    std::vector<uint64_t> sk(ntot);
+    std::vector<uint32_t> sv(ntot);
+    PT_HIP(hipMemcpy(sk.data(), ctx->last_keys, 8 * ntot, hipMemcpyDeviceToHost));
+    PT_HIP(hipMemcpy(sv.data(), ctx->last_vals, 4 * ntot, hipMemcpyDeviceToHost));
+    std::vector<RootCube> rts(lb.size());
+    PT_HIP(hipMemcpy(rts.data(), ctx->ws["roots"].ptr, sizeof(RootCube) * lb.size(), hipMemcpyDeviceToHost));
+    // boxes of this crystal, in global (level, crystal, prefix) order
+    std::vector<int32_t> g2l(nbox, -1), l2g;
+    for (int b = 0; b < nbox; ++b)
+        if (bcr[b] == ci) {
+            g2l[b] = (int32_t)l2g.size();
+            l2g.push_back(b);
+        }
+    const int nb = (int)l2g.size();
+    // leaves of this crystal by first ion (for expanding near ranges)
+    std::vector<std::pair<int, int>> leaves;
+    for (int lb_ = 0; lb_ < nb; ++lb_)
+        if (blf[l2g[lb_]]) leaves.push_back({bb[l2g[lb_]], lb_});
+    std::sort(leaves.begin(), leaves.end());
+    std::vector<std::vector<int32_t>> V(nb), NE(nb);
+    int64_t nv = 0, nn = 0;
+    int nlev = 0;
+    for (int lb_ = 0; lb_ < nb; ++lb_) {
+        const int g = l2g[lb_];
+        nlev = std::max(nlev, bl[g] + 1);
+        for (int w = 0; w < kWin; ++w) {
+            const int s = vt[(size_t)g * kWin + w];
+            if (s >= 0) V[lb_].push_back(g2l[s]);
+        }
+        std::sort(V[lb_].begin(), V[lb_].end());
+        nv += V[lb_].size();
+        if (blf[g]) {
+            for (int r = 0; r < nc[g]; ++r) {
+                const int2 rg = nr[(size_t)g * stride + r];
+                auto lo = std::lower_bound(leaves.begin(), leaves.end(), std::make_pair(rg.x, -1));
+                for (; lo != leaves.end() && lo->first < rg.y; ++lo) NE[lb_].push_back(lo->second);
+            }
+            std::sort(NE[lb_].begin(), NE[lb_].end());
+            nn += NE[lb_].size();
+        }
+    }
+    sizes[0] = nb;
+    sizes[1] = nlev;
+    sizes[2] = nv;
+    sizes[3] = nn;
+    if (keys || perm)
+        for (int k = 0; k < n; ++k) {
+            const int id = (int)sv[off + k] - off;
+            if (keys) keys[id] = sk[off + k] & 0xFFFFFFFFFFFFull;
+            if (perm) perm[k] = id;
+        }
+    for (int lb_ = 0; lb_ < nb; ++lb_) {
+        const int g = l2g[lb_];
+        if (level) level[lb_] = bl[g];
+        if (parent) parent[lb_] = bp[g] >= 0 ? g2l[bp[g]] : -1;
+        if (ion_begin) ion_begin[lb_] = bb[g] - off;
+        if (ion_end) ion_end[lb_] = be[g] - off;
+        if (coords) {
+            coords[3 * lb_] = bx[g];
+            coords[3 * lb_ + 1] = by[g];
+            coords[3 * lb_ + 2] = bz[g];
+        }
+        if (is_leaf) is_leaf[lb_] = blf[g];
+    }
+    if (v_off) {
+        int64_t a = 0;
+        for (int lb_ = 0; lb_ < nb; ++lb_) {
+            v_off[lb_] = (int32_t)a;
+            if (v_src)
+                for (int32_t s : V[lb_]) v_src[a++] = s;
+            else
+                a += V[lb_].size();
+        }
+        v_off[nb] = (int32_t)a;
+    }
+    if (near_off) {
+        int64_t a = 0;
+        for (int lb_ = 0; lb_ < nb; ++lb_) {
+            near_off[lb_] = (int32_t)a;
+            if (near_src)
+                for (int32_t s : NE[lb_]) near_src[a++] = s;
+            else
+                a += NE[lb_].size();
+        }
+        near_off[nb] = (int32_t)a;
+    }
+    if (root) {
+        root[0] = rts[ci].o[0];
+        root[1] = rts[ci].o[1];
+        root[2] = rts[ci].o[2];
+        root[3] = rts[ci].W;
+    }
+    return PT_OK;
+}
+
+}  // extern "C"

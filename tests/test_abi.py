@@ -1,0 +1,40 @@
+"""Host-side checks of the C ABI (no GPU needed)."""
+import ctypes as C
+import os
+
+import pytest
+
+from paper_2405_13973_amd import native
+
+
+def test_library_exports_every_declared_symbol():
+    lib = native.load()
+    names = native.header_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_header_declares_status_codes():
+    txt = open(native.HEADER).read()
+    for code in ("PT_OK = 0", "PT_EINVAL = -1", "PT_ENOMEM = -2", "PT_EDEVICE = -3", "PT_ENUMERIC = -4",
+                 "PT_EBUSY = -5"):
+        assert code in txt
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    lib = native.load()
+    assert lib.pt_ctx_create(0, 0, None, None) == native.PT_EINVAL
+    assert lib.pt_ctx_destroy(None) == native.PT_EINVAL
+    assert lib.pt_step(None, 1) == native.PT_EINVAL
+    assert lib.pt_read_state(None, None, None, None, None, None) == native.PT_EINVAL
+    assert lib.pt_compute_forces(None, None) == native.PT_EINVAL
+    assert b"NULL" in lib.pt_last_error() or len(lib.pt_last_error()) > 0
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is visible here")
+def test_ctx_create_without_device_fails_cleanly():
+    lib = native.load()
+    h = C.c_void_p()
+    assert lib.pt_ctx_create(0, 0, None, C.byref(h)) == native.PT_EDEVICE
+    assert not h.value

@@ -313,9 +313,9 @@ def test_fmm_sampled_equals_full():
 
 # ------------------------------------------------------------- tree
 def _interleave(k):
-    """Bit interleave of three 21-bit ints, x highest of each triple (numpy, bit by bit)."""
+    """Bit interleave of three 16-bit ints, x highest of each triple (numpy, bit by bit)."""
     key = np.zeros(len(k), np.uint64)
-    for b in range(21):
+    for b in range(16):
         for d in range(3):
             bit = (k[:, d].astype(np.uint64) >> np.uint64(b)) & np.uint64(1)
             key |= bit << np.uint64(3 * b + (2 - d))
@@ -330,7 +330,7 @@ def test_morton_keys_match_numpy_interleave():
     W = (hi - lo).max()
     o = 0.5 * (lo + hi) - 0.5 * W
     assert np.array_equal(o, root[:3]) and W == root[3]
-    kq = np.clip(np.floor((pos - o) * (2.0 ** 21 / W)), 0, 2 ** 21 - 1).astype(np.int64)
+    kq = np.clip(np.floor((pos - o) * (2.0 ** 16 / W)), 0, 2 ** 16 - 1).astype(np.int64)
     assert np.array_equal(keys, _interleave(kq))
 
 
@@ -363,12 +363,12 @@ def test_tree_and_lists(n, s, kind):
         lv = T["level"][b]
         ids = perm[T["ion_begin"][b]:T["ion_end"][b]]
         assert len(ids) > 0
-        pref = keys[ids] >> np.uint64(3 * (21 - lv))
+        pref = keys[ids] >> np.uint64(3 * (16 - lv))
         assert (pref == pref[0]).all()
         c = T["coords"][b]
         assert int(pref[0]) == int(_interleave(c[None].astype(np.int64))[0]) if lv > 0 else True
         if T["is_leaf"][b]:
-            assert len(ids) <= s or lv == 21
+            assert len(ids) <= s or lv == 16
         else:
             assert len(ids) > s
         if b > 0:
@@ -411,13 +411,14 @@ def test_tree_and_lists(n, s, kind):
         assert all(v == 1 for v in cover.values())
 
 
-def test_tree_coincident_ions_terminate_at_level_21():
-    """Q11-type degenerate input: many identical positions cannot be split; leaves stop at level 21."""
+def test_tree_coincident_ions_terminate_at_level_16():
+    """Degenerate input: identical positions cannot be separated; leaves stop at level 16
+    and the zero-separation pairs contribute nothing."""
     pos = np.zeros((40, 3))
     pos[:20] = 1e-5
     T = O.tree(pos, 4)
-    assert T["level"].max() == 21
-    assert T["is_leaf"][T["level"] == 21].all()
+    assert T["level"].max() == 16
+    assert T["is_leaf"][T["level"] == 16].all()
     F = O.fmm_coulomb(pos, Q, 4, 4)
     assert np.isfinite(F).all()
 
