@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark: ion-steps/s of FMM-force Penning-trap steps on one MI355X.
+
+Workload: 100,000 ions on a 5%-jittered simple cubic lattice in a prolate
+ellipsoid with semi-axes (400, 400, 800) um, 10 mK velocities, B = 4.5 T,
+omega_z = 2 pi 1.5 MHz, dt = 1 ns, no laser.  The expansion degree p is the
+smallest one whose RMS relative Coulomb-force error against the FP64 direct
+sum is <= 1e-6, chosen at start-up (not timed).
+
+Prints one JSON line (see the contract in the design doc): value = ion-steps/s of
+the mixed-precision form (or --precision fp64), roofline of the dominant
+kernel (M2L) from HIP events over the timed region, and the CPU oracle timed
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2405_13973_amd import inputs, native  # noqa: E402
+
+METRIC = "ion-steps/s at N=1e5, RMS rel force error≤1e-6 vs FP64; p99 latency mixed stream"
+PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "valu_fp32": 157.3, "valu_fp64": 78.6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rms_rel(F, ref):
+    return math.sqrt(((F - ref) ** 2).sum() / (ref ** 2).sum())
+
+
+def choose_p(c, F_dir, precision, leaf, p0, target=1e-6, pmax=16):
+    errs = {}
+    for p in range(p0, pmax + 1):
+        c.set_force("fmm", p, leaf, precision)
+        err = rms_rel(c.compute_forces(), F_dir)
+        errs[p] = err
+        log(f"  {precision} p={p} leaf={leaf}: rms rel force err vs direct = {err:.3e}")
+        if err <= target:
+            return p, err, errs
+    raise SystemExit(f"no p <= {pmax} reaches rms error {target} in {precision}")
+
+
+def timed_steps(ctx, c, steps, warmup, sync):
+    c.step(warmup)
+    sync()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    c.step(steps)
+    sync()
+    t1 = time.perf_counter()
+    phases, count = ctx.phase_times(with_count=True)
+    wc = ctx.work_counts()
+    ctx.set_timing(False)
+    return t1 - t0, phases, count, wc
+
+
+def cpu_baseline(cr, p, leaf, F_dir_gpu):
+    """The FP64 CPU oracle, as it stands, on the host cores: one full FMM step
+    of the same crystal (same p and leaf size).  Also ties the GPU direct sum
+    used as the accuracy reference to the oracle on sampled ions."""
+    from oracle import oracle as O
+
+    idx = np.linspace(0, cr.n - 1, 48).astype(np.int32)
+    ref = O.coulomb_direct_sampled(cr.pos, cr.charge, idx)
+    dev = np.abs(F_dir_gpu[idx] - ref).max() / np.sqrt((ref ** 2).sum(1).mean())
+    log(f"  GPU direct vs oracle direct on {len(idx)} sampled ions: max err / rms = {dev:.2e}")
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    O.run(cr.pos, cr.vel, cr.charge, cr.mass, cr.trap(), cr.dt, 1, method="fmm", p=p, leaf_size=leaf)
+    el = time.perf_counter() - t0
+    log(f"  oracle: one FMM step of {cr.n} ions (p={p}, leaf={leaf}) in {el:.1f} s on {cores} threads")
+    return {"value": cr.n / el, "unit": "ion-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"one full FP64 FMM step (p={p}, leaf {leaf}) of the same {cr.n}-ion crystal, "
+                      f"{el:.1f} s wall; direct sum checked on 48 sampled ions (max err/rms {dev:.1e})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--p0", type=int, default=10, help="first p tried when choosing p")
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU sharding is a "
+              f"design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    assert torch.cuda.is_available(), "no HIP device visible"
+    stream = torch.cuda.current_stream()
+    sync = torch.cuda.synchronize
+
+    cr = inputs.config3(n=a.n)
+    log(f"workload: {cr.n} ions, jittered lattice in ellipsoid (400,400,800) um")
+    ctx = native.Context(0, stream=stream.cuda_stream)
+    c = ctx.crystal(cr.pos, cr.vel, cr.charge, cr.mass, cr.seed)
+    c.set_trap(B=cr.B, omega_z=cr.omega_z, dt=cr.dt)
+    c.set_force("direct")
+    F_dir = c.compute_forces()
+
+    results = {}
+    forms = [a.precision] + ([] if a.no_fp64_compare or a.precision == "fp64" else ["fp64"])
+    for prec in forms:
+        c.set_state(cr.pos, cr.vel, 0)  # F_dir belongs to the initial positions
+        p, err, _ = choose_p(c, F_dir, prec, a.leaf, a.p0)
+        c.set_state(cr.pos, cr.vel, 0)
+        c.set_force("fmm", p, a.leaf, prec)
+        sync()
+        el, phases, count, wc = timed_steps(ctx, c, a.steps, a.warmup, sync)
+        results[prec] = dict(p=p, err=err, seconds=el, phases=phases, count=count, wc=wc)
+        log(f"  {prec}: p={p} {a.steps} steps in {el * 1e3:.2f} ms -> {cr.n * a.steps / el:.4g} ion-steps/s; "
+            f"phases(ms) tree {phases[0]:.3f} up {phases[1]:.3f} m2l {phases[2]:.3f} down {phases[3]:.3f} "
+            f"eval {phases[4]:.3f} total {phases[5]:.3f} over {count} evals")
+
+    # direct-sum rate on the same crystal, for the FMM/direct comparison
+    c.set_force("direct")
+    ctx.set_timing(True)
+    c.compute_forces()
+    dir_ms = ctx.phase_times()[4]
+    ctx.set_timing(False)
+
+    main_r = results[a.precision]
+    p = main_r["p"]
+    K = (p + 1) ** 2
+    m2l_flops = 2.0 * K * K * main_r["wc"][2]
+    m2l_ms = main_r["phases"][2]
+    achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12
+    peak = PEAK["mfma_fp32"] if a.precision == "mixed" else PEAK["mfma_fp64"]
+    value = cr.n * a.steps / main_r["seconds"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "ion-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": main_r["seconds"] * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if a.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{cr.n} ions, 5%-jittered cubic lattice in a (400,400,800) um prolate ellipsoid, "
+                        f"B=4.5 T, f_z=1.5 MHz, dt=1 ns, FMM p={p} leaf {a.leaf} ({a.precision})",
+            "n_ions": cr.n, "p": p, "leaf_size": a.leaf, "precision": a.precision,
+            "rms_rel_force_err": main_r["err"],
+        },
+        "roofline": {
+            "bound": "mfma", "kernel": "m2l", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None,
+            "algorithmic": f"2 K^2 flops per M2L pair, K=(p+1)^2={K}, {int(main_r['wc'][2])} pairs per launch",
+        },
+        "details": {
+            "force_evals_per_s": 1e3 / main_r["phases"][5],
+            "phase_ms": {k: float(v) for k, v in zip(["tree", "upward", "m2l", "l2l", "eval", "total"],
+                                                     main_r["phases"])},
+            "direct_sum_ms": float(dir_ms),
+            "boxes": int(main_r["wc"][0]), "leaves": int(main_r["wc"][1]), "m2l_pairs": int(main_r["wc"][2]),
+            "p2p_pairs": int(main_r["wc"][3]),
+        },
+    }
+    if "fp64" in results and a.precision == "mixed":
+        f = results["fp64"]
+        out["details"]["fp64_ion_steps_per_s"] = cr.n * a.steps / f["seconds"]
+        out["details"]["fp64_p"] = f["p"]
+        out["details"]["fp64_rms_rel_force_err"] = f["err"]
+        out["details"]["mixed_speedup_vs_fp64"] = f["seconds"] / main_r["seconds"]
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cr, p, a.leaf, F_dir)
+        out["details"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

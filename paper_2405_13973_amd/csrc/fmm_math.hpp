@@ -66,6 +66,17 @@ __host__ __device__ inline void rhat_all(int p, T x, T y, T z, T *re, T *im)
     }
 }
 
+// Recurrence factors, per packed index q = n(n+1)/2 + m (0 <= m <= n <= p),
+// stored as rec[f * Kq + q], Kq = (p+1)(p+2)/2:
+//   f = 0 (ra): n == m:   -sqrt((2m-1)/(2m))  (1 for m = 0)   Rh_m^m = ra (x + i y) Rh_{m-1}^{m-1}
+//               n == m+1: sqrt(2m+1)                          Rh_n^m = ra z Rh_{n-1}^m
+//               n >= m+2: (2n-1)/sqrt((n+m)(n-m))             Rh_n^m = ra z Rh_{n-1}^m - rb r^2 Rh_{n-2}^m
+//   f = 1 (rb): sqrt((n+m-1)(n-m-1)/((n+m)(n-m))) for n >= m+2, else 0
+//   f = 2..4: L2P weights of Rh_n^m (n < p), see l2p_field:
+//         sqrt((n+1+m)(n+1-m)) (doubled for m > 0), sqrt((n+m+2)(n+m+1)), sqrt((n-m+2)(n-m+1))
+__host__ __device__ inline int kq(int p) { return (p + 1) * (p + 2) / 2; }
+constexpr int kRecFields = 5;
+
 // Field of a local expansion (L2P).  The expansion is re-centred exactly at
 // the evaluation point u (box units); its degree-1 coefficients are
 //   L'_1^k = sum_{n>=1,m} Lh_n^m conj(Rh_{n-1}^{m-k}(u)) nu_n^m / nu_{n-1}^{m-k},  k = 0, 1,
@@ -75,63 +86,53 @@ __host__ __device__ inline void rhat_all(int p, T x, T y, T z, T *re, T *im)
 // through the mirrored order -mu, with -conj(Lh_{n'+1}^{mu-1}).
 // L is the real storage; the result is E * h^2 (caller divides by h^2).
 template <typename T>
-__host__ __device__ inline void l2p_field(int p, const T *L, T x, T y, T z, T &ex, T &ey, T &ez)
+__host__ __device__ inline void l2p_field(int p, const T *L, const T *rec, T x, T y, T z, T &ex, T &ey, T &ez)
 {
+    const int Q = kq(p);
     const T r2 = x * x + y * y + z * z;
     T g0 = 0, g1r = 0, g1i = 0;
     T dre = 1, dim = 0;  // Rh_mu^mu
     for (int mu = 0; mu <= p - 1; ++mu) {
         if (mu > 0) {
-            const T f = -sqrt(T(2 * mu - 1) / T(2 * mu));
+            const T f = rec[mu * (mu + 1) / 2 + mu];
             const T nre = f * (x * dre - y * dim);
             const T nim = f * (x * dim + y * dre);
             dre = nre;
             dim = nim;
         }
-        T r1re = 0, r1im = 0, r0re = dre, r0im = dim;  // Rh_{n-2}, Rh_{n-1} along the column
+        T r1re = 0, r1im = 0, r0re = 0, r0im = 0;  // Rh_{n-2}, Rh_{n-1} along the column
         for (int np = mu; np <= p - 1; ++np) {
+            const int q = np * (np + 1) / 2 + mu;
             T cre, cim;  // Rh_np^mu
             if (np == mu) {
                 cre = dre;
                 cim = dim;
-            } else if (np == mu + 1) {
-                const T f1 = sqrt(T(2 * mu + 1)) * z;
-                cre = f1 * dre;
-                cim = f1 * dim;
             } else {
-                const T a = T(2 * np - 1) * z;
-                const T b = sqrt(T((np + mu - 1) * (np - mu - 1))) * r2;
-                const T inv = T(1) / sqrt(T((np + mu) * (np - mu)));
-                cre = (a * r0re - b * r1re) * inv;
-                cim = (a * r0im - b * r1im) * inv;
+                const T a = rec[q] * z, b = rec[Q + q] * r2;
+                cre = a * r0re - b * r1re;
+                cim = a * r0im - b * r1im;
             }
-            if (np > mu) {
-                r1re = r0re;
-                r1im = r0im;
-            }
+            r1re = r0re;
+            r1im = r0im;
             r0re = cre;
             r0im = cim;
             const int n = np + 1;
-            // k = 0: Lh_n^mu conj(Rh), doubled for mu > 0 (mirror term)
-            {
+            {  // k = 0: Lh_n^mu conj(Rh), doubled for mu > 0 (mirror term)
                 const T lre = L[sidx_re(n, mu)];
                 const T lim = mu > 0 ? L[sidx_im(n, mu)] : T(0);
-                const T w = sqrt(T((n + mu) * (n - mu))) * (mu > 0 ? T(2) : T(1));
-                g0 += w * (lre * cre + lim * cim);
+                g0 += rec[2 * Q + q] * (lre * cre + lim * cim);
             }
-            // k = 1, (a): Lh_n^{mu+1} conj(Rh_np^mu)
-            {
+            {  // k = 1, (a): Lh_n^{mu+1} conj(Rh_np^mu)
                 const T lre = L[sidx_re(n, mu + 1)];
                 const T lim = L[sidx_im(n, mu + 1)];
-                const T w = sqrt(T((n + mu + 1) * (n + mu)));
+                const T w = rec[3 * Q + q];
                 g1r += w * (lre * cre + lim * cim);
                 g1i += w * (lim * cre - lre * cim);
             }
-            // k = 1, (b): -conj(Lh_n^{mu-1}) Rh_np^mu, mu >= 1
-            if (mu >= 1) {
+            if (mu >= 1) {  // k = 1, (b): -conj(Lh_n^{mu-1}) Rh_np^mu
                 const T lre = L[sidx_re(n, mu - 1)];
                 const T lim = mu - 1 > 0 ? L[sidx_im(n, mu - 1)] : T(0);
-                const T w = sqrt(T((n - mu + 1) * (n - mu)));
+                const T w = rec[4 * Q + q];
                 g1r -= w * (lre * cre + lim * cim);
                 g1i -= w * (lre * cim - lim * cre);
             }
@@ -141,6 +142,47 @@ __host__ __device__ inline void l2p_field(int p, const T *L, T x, T y, T z, T &e
     ey = g1i;
     ez = -g0;
 }
+
+// conj(Rh_n^m(u)) of one point in real storage order into out[s * stride]
+// (s the storage index), from the recurrence table.
+template <typename T>
+__host__ __device__ inline void p2m_terms(int p, const T *rec, T x, T y, T z, T *out, int stride)
+{
+    const int Q = kq(p);
+    const T r2 = x * x + y * y + z * z;
+    T dre = 1, dim = 0;
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) {
+            const T f = rec[m * (m + 1) / 2 + m];
+            const T nre = f * (x * dre - y * dim);
+            const T nim = f * (x * dim + y * dre);
+            dre = nre;
+            dim = nim;
+        }
+        T r1re = 0, r1im = 0, r0re = 0, r0im = 0;
+        for (int n = m; n <= p; ++n) {
+            const int q = n * (n + 1) / 2 + m;
+            T cre, cim;
+            if (n == m) {
+                cre = dre;
+                cim = dim;
+            } else {
+                const T a = rec[q] * z, b = rec[Q + q] * r2;
+                cre = a * r0re - b * r1re;
+                cim = a * r0im - b * r1im;
+            }
+            r1re = r0re;
+            r1im = r0im;
+            r0re = cre;
+            r0im = cim;
+            out[sidx_re(n, m) * stride] = cre;
+            if (m > 0) out[sidx_im(n, m) * stride] = -cim;
+        }
+    }
+}
+
+// Host-only: recurrence table (kRecFields x kq(p) doubles), see above.
+void build_recurrence_table(int p, double *rec);
 
 // Host-only: the dense real operator matrices (row = output coefficient,
 // column = input coefficient, K x K each, row-major) for degree p:

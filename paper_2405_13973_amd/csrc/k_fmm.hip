@@ -8,6 +8,8 @@
 // the mixed form.  Box centres, ion-to-centre offsets and the integrator stay
 // FP64 in both; in the mixed form the offsets are rounded to FP32 only after
 // the FP64 subtraction, and near-field sums are compensated (Kahan).
+#include <algorithm>
+
 #include "fmm_math.hpp"
 #include "pt_common.hpp"
 #include "pt_kernels.hpp"
@@ -16,142 +18,338 @@ namespace pt {
 
 __device__ inline int octant_of(int ix, int iy, int iz) { return ((ix & 1) << 2) | ((iy & 1) << 1) | (iz & 1); }
 
-// Rh_n^m(u) by its column recurrence (m >= 0).
-template <typename T>
-__device__ inline void rhat_nm(int n, int m, T x, T y, T z, T &re, T &im)
+__global__ void k_zero_i32(int32_t *__restrict__ p, int n)
 {
-    T dre = 1, dim = 0;
-    for (int k = 1; k <= m; ++k) {
-        const T f = -sqrt(T(2 * k - 1) / T(2 * k));
-        const T a = f * (x * dre - y * dim);
-        const T b = f * (x * dim + y * dre);
-        dre = a;
-        dim = b;
-    }
-    if (n == m) {
-        re = dre;
-        im = dim;
-        return;
-    }
-    const T r2 = x * x + y * y + z * z;
-    const T f1 = sqrt(T(2 * m + 1)) * z;
-    T pre = dre, pim = dim, cre = f1 * dre, cim = f1 * dim;
-    for (int k = m + 2; k <= n; ++k) {
-        const T a = T(2 * k - 1) * z;
-        const T b = sqrt(T((k + m - 1) * (k - m - 1))) * r2;
-        const T inv = T(1) / sqrt(T((k + m) * (k - m)));
-        const T nre = (a * cre - b * pre) * inv;
-        const T nim = (a * cim - b * pim) * inv;
-        pre = cre;
-        pim = cim;
-        cre = nre;
-        cim = nim;
-    }
-    re = cre;
-    im = cim;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
-// P2M: one block per box, threads over coefficients, ions in ascending order.
+// P2M: one 64-thread block per leaf.  Ions are taken 32 at a time: each of
+// the first 32 threads evaluates conj(Rh_n^m) of its ion for all (n, m) by
+// one pass of the recurrences into an LDS tile [coefficient][ion]; then every
+// thread sums its coefficients over the tile's ions in ascending order.
+constexpr int kP2MIons = 32;
+constexpr int kP2MMaxPer = 8;  // coefficients per thread: Kp <= 512
+
 template <typename T>
-__global__ __launch_bounds__(128) void k_p2m(BoxTable bt, const double *__restrict__ sp, int ntot, int p, int Kp,
-                                             T *__restrict__ M)
+__global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const double *__restrict__ sp, int ntot, int p, int Kp,
+                                            const T *__restrict__ rec, T *__restrict__ M)
 {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *C = reinterpret_cast<T *>(smem_raw);  // [Kp][kP2MIons + 1]
     const int b = blockIdx.x;
     if (!bt.leaf[b]) return;
     const double4 g = bt.geo[b];
     const double ih = 1.0 / g.w;
     const int K = kcoef(p);
     const int i0 = bt.begin[b], i1 = bt.end[b];
-    for (int s = threadIdx.x; s < Kp; s += blockDim.x) {
-        T acc = 0;
-        if (s < K) {
-            const int n = (int)sqrt((double)s);
-            const int r = s - n * n;
-            const int m = (r + 1) >> 1;
-            const bool is_im = r > 0 && !(r & 1);
-            for (int i = i0; i < i1; ++i) {
-                const T ux = (T)((sp[i] - g.x) * ih);
-                const T uy = (T)((sp[ntot + i] - g.y) * ih);
-                const T uz = (T)((sp[2 * ntot + i] - g.z) * ih);
-                T re, im;
-                rhat_nm<T>(n, m, ux, uy, uz, re, im);
-                acc += is_im ? -im : re;
+    constexpr int ld = kP2MIons + 1;
+    T acc[kP2MMaxPer];
+#pragma unroll
+    for (int r = 0; r < kP2MMaxPer; ++r) acc[r] = T(0);
+    for (int c0 = i0; c0 < i1; c0 += kP2MIons) {
+        const int cnt = min(kP2MIons, i1 - c0);
+        if ((int)threadIdx.x < cnt) {
+            const int i = c0 + threadIdx.x;
+            p2m_terms<T>(p, rec, (T)((sp[i] - g.x) * ih), (T)((sp[ntot + i] - g.y) * ih),
+                         (T)((sp[2 * ntot + i] - g.z) * ih), C + threadIdx.x, ld);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kP2MMaxPer; ++r) {
+            const int s = threadIdx.x + 64 * r;
+            if (s < K)
+                for (int j = 0; j < cnt; ++j) acc[r] += C[s * ld + j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < kP2MMaxPer; ++r) {
+        const int s = threadIdx.x + 64 * r;
+        if (s < Kp) M[(size_t)b * Kp + s] = s < K ? acc[r] : T(0);
+    }
+}
+
+// ---------------------------------------------------------------- M2L
+//
+// M2L is a dense contraction on the matrix cores.  Targets that share the
+// octant parity c = (ix, iy, iz) & 1 see a given slot w of the 6x6x6 source
+// window at the same offset d = w - 2 - c, hence through the same operator
+// T_d; the scaled operators do not depend on level or crystal, so one
+// parity's targets from every level >= 2 and every crystal form the columns
+// of one GEMM
+//     L[:, targets] = sum_w T_{d(w)} (Kp x Kp) * M[src(w, targets)] (Kp x n)
+// over the 189 non-touching slots.  A workgroup of 4 waves takes 64 targets
+// (16 per wave) and a group of slots; per slot it stages Kp x 16 chunks of
+// T_d (column-major, zero padded) and the matching 16 x 64 chunk of source
+// expansions in LDS, and every wave runs v_mfma 16x16x4 over all row blocks
+// of its 16 columns -- each operator chunk is read from L2 once per 64
+// targets.  Slot groups write separate partial sums that a second kernel adds
+// in group order, so every target's sum has a fixed order whatever tile it
+// landed in (batch-invariant, deterministic).  Workgroup ids are laid out
+// with id mod 8 = parity: under round-robin dispatch over the 8 XCDs, each
+// XCD's L2 serves a single parity's operators.
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 op(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int r) { return 4 * r + (lane >> 4); }  // output row of element r
+};
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// Buckets the boxes of level >= 2 by octant parity.
+__global__ void k_m2l_bucket(BoxTable bt, int nbox, int32_t *__restrict__ cnt, int32_t *__restrict__ list)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox || bt.level[b] < 2) return;
+    const int o = octant_of(bt.ix[b], bt.iy[b], bt.iz[b]);
+    const int pos = atomicAdd(&cnt[o], 1);
+    list[(size_t)o * nbox + pos] = b;
+}
+
+constexpr int kM2LWaves = 4;           // 16 target columns per wave
+constexpr int kM2LCols = 16 * kM2LWaves;
+constexpr int kM2LRB = 12;             // row blocks (of 16) per workgroup: Kp <= 192 in one pass
+constexpr int kXKC = 16;               // k-chunk staged per pipeline step (divides Kp)
+
+// One translation GEMM serves M2L, M2M and L2L:
+//   out[t] (op) sum over slots s of  A[op(s)] * X[src(t, s)]
+// targets t: either bucket lists (M2L: one bucket per parity) or the box range
+// [b0, b0 + n); src(t, s) = srctab[t * src_stride + col(s)] (-1: no source).
+// Output modes: 0 partial sums per slot group, 1 overwrite (skipping targets
+// flagged in `skip`), 2 accumulate.
+struct XlateArgs {
+    const int32_t *cnt;   // bucket sizes (bucketed targets) or nullptr
+    const int32_t *list;  // bucket lists, list_stride apart
+    int list_stride;
+    int nbucket;          // 8 (by parity) or 1
+    int b0, nrange;       // target range when cnt == nullptr
+    int tile_stride, ngroup, nrowgrp, Kp;
+    const int2 *slots;    // per bucket nslot entries {source column, operator index}
+    int nslot;
+    const int32_t *srctab;
+    int src_stride;
+    const uint8_t *skip;  // mode 1 only
+    int mode;
+    int nbox;
+};
+
+constexpr int kXSlots = 32;  // slots per workgroup, at most
+
+// Software-pipelined: the (slot, k-chunk) steps of a tile run as one
+// sequence; the loads of step i+1 are issued into registers before the
+// matrix-core work of step i, so their latency overlaps it.  NRB (row blocks
+// of 16 per workgroup) is a compile-time constant so the matrix-core loop
+// has no branches.  Every load is unconditional: k-chunks of 16 divide Kp,
+// rows past Kp (PARTIAL row groups only) read an in-bounds address and are
+// replaced by zero, and a missing source reads X[zrow], an expansion row
+// kept at zero.
+template <typename T, int NRB, bool PARTIAL>
+__global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *__restrict__ At,
+                                                         const T *__restrict__ X, T *__restrict__ out)
+{
+    using MF = Mfma<T>;
+    constexpr int KC = kXKC;
+    constexpr int ROWS = NRB * 16;
+    constexpr int NT = 64 * kM2LWaves;
+    constexpr int kXA = KC * ROWS / NT;  // operator values staged per thread (exact)
+    constexpr int kXB = KC * kM2LCols / NT;
+    __shared__ T As[KC][ROWS];             // operator chunk, [k][row]
+    __shared__ T Bsh[KC][kM2LCols];        // source chunk, [k][target]
+    __shared__ int32_t tgt_s[kM2LCols];
+    __shared__ int32_t src_s[kXSlots][kM2LCols];
+    __shared__ int32_t act_s[kXSlots + 1];  // active slots (local index); act_s[kXSlots] = count
+    __shared__ int32_t op_s[kXSlots];       // operator index of each local slot
+    const int Kp = a.Kp;
+    const int zrow = a.nbox;  // all-zero expansion row
+    const int lin = blockIdx.x;
+    const int o = lin % a.nbucket;
+    int rest = lin / a.nbucket;
+    const int rg = rest % a.nrowgrp;
+    rest /= a.nrowgrp;
+    const int g = rest % a.ngroup;
+    const int tile0 = rest / a.ngroup;
+    const int n = a.cnt ? a.cnt[o] : a.nrange;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int row0 = rg * ROWS;
+    const int s0 = (a.nslot * g) / a.ngroup, s1 = (a.nslot * (g + 1)) / a.ngroup;
+    const int ns = s1 - s0;  // <= kXSlots (the launcher guarantees it)
+    const int nchunk = Kp / KC;
+    // per-thread staging map (fixed for the kernel)
+    int a_off[kXA], a_lds[kXA];
+    bool a_ok[kXA];
+#pragma unroll
+    for (int j = 0; j < kXA; ++j) {
+        const int e = tid + NT * j;
+        const int kk = e / ROWS, r = e - kk * ROWS;
+        a_ok[j] = !PARTIAL || row0 + r < Kp;
+        a_off[j] = a_ok[j] ? kk * Kp + r : 0;
+        a_lds[j] = e;
+    }
+    const int b_t = tid / KC, b_k = tid - (tid / KC) * KC;  // kXB == 4: targets b_t + 16 j
+    T ra[kXA], rb_[kXB];
+    auto load_step = [&](int step) {
+        const int q = step / nchunk;
+        const int sl = act_s[q];
+        const int k0 = (step - q * nchunk) * KC;
+        const T *Ad = At + (size_t)op_s[sl] * Kp * Kp + (size_t)k0 * Kp + row0;
+#pragma unroll
+        for (int j = 0; j < kXA; ++j) {
+            const T v = Ad[a_off[j]];
+            ra[j] = PARTIAL ? (a_ok[j] ? v : T(0)) : v;
+        }
+#pragma unroll
+        for (int j = 0; j < kXB; ++j) rb_[j] = X[(size_t)src_s[sl][b_t + 16 * j] * Kp + k0 + b_k];
+    };
+    for (int tile = tile0; tile * kM2LCols < n; tile += a.tile_stride) {
+        __syncthreads();  // previous tile finished with the shared arrays
+        if (tid < kM2LCols) {
+            const int t = tile * kM2LCols + tid;
+            tgt_s[tid] = t < n ? (a.cnt ? a.list[(size_t)o * a.list_stride + t] : a.b0 + t) : -1;
+        }
+        if (tid < ns) op_s[tid] = a.slots[o * a.nslot + s0 + tid].y;
+        __syncthreads();
+        for (int e = tid; e < ns * kM2LCols; e += NT) {
+            const int sl = e / kM2LCols, t = e - sl * kM2LCols;
+            const int tg = tgt_s[t];
+            const int sidx = tg >= 0 ? a.srctab[(size_t)tg * a.src_stride + a.slots[o * a.nslot + s0 + sl].x] : -1;
+            src_s[sl][t] = sidx >= 0 ? sidx : zrow;
+        }
+        __syncthreads();
+        if (wave == 0) {  // compact the slots that have at least one source, in slot order
+            int cnt = 0;
+            for (int sl = 0; sl < ns; ++sl) {
+                const bool has = __ballot(src_s[sl][lane] != zrow) != 0ull;
+                if (has) {
+                    if (lane == 0) act_s[cnt] = sl;
+                    ++cnt;
+                }
+            }
+            if (lane == 0) act_s[kXSlots] = cnt;
+        }
+        __syncthreads();
+        const int nsteps = act_s[kXSlots] * nchunk;
+        typename MF::v4 acc[NRB];
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) acc[r] = typename MF::v4{0, 0, 0, 0};
+        if (nsteps > 0) load_step(0);
+        for (int step = 0; step < nsteps; ++step) {
+            __syncthreads();  // the previous step is done reading As / Bsh
+#pragma unroll
+            for (int j = 0; j < kXA; ++j) (&As[0][0])[a_lds[j]] = ra[j];
+#pragma unroll
+            for (int j = 0; j < kXB; ++j) Bsh[b_k][b_t + 16 * j] = rb_[j];
+            __syncthreads();
+            if (step + 1 < nsteps) load_step(step + 1);
+#pragma unroll
+            for (int k4 = 0; k4 < KC; k4 += 4) {
+                const int kk = k4 + (lane >> 4);
+                const T bv = Bsh[kk][wave * 16 + (lane & 15)];
+                T av[NRB];
+#pragma unroll
+                for (int r = 0; r < NRB; ++r) av[r] = As[kk][r * 16 + (lane & 15)];
+#pragma unroll
+                for (int r = 0; r < NRB; ++r) acc[r] = MF::op(av[r], bv, acc[r]);
             }
         }
-        M[(size_t)b * Kp + s] = acc;
+        const int tg = tgt_s[wave * 16 + (lane & 15)];
+        if (tg >= 0 && !(a.mode == 1 && a.skip[tg])) {
+            T *dst = out + (a.mode == 0 ? ((size_t)g * a.nbox + tg) * Kp : (size_t)tg * Kp) + row0;
+#pragma unroll
+            for (int r = 0; r < NRB; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = r * 16 + MF::row(lane, q);
+                    if (!PARTIAL || row0 + row < Kp) {
+                        T &d = dst[row];
+                        d = a.mode == 2 ? d + acc[r][q] : acc[r][q];
+                    }
+                }
+        }
     }
 }
 
-// M2M for the boxes [b0, b1) of one level: parent += T_m2m[octant(child)] child.
-// Tt is column-major (Tt[o][j][i] = T[o][i][j]) so that threads read rows coalesced.
-template <typename T>
-__global__ __launch_bounds__(128) void k_m2m(BoxTable bt, int b0, int K, int Kp, const T *__restrict__ Tt,
-                                             T *__restrict__ M)
+// Row blocks per workgroup for Kp: one pass when Kp <= 192, else equal groups.
+static int xlate_nrb(int Kp, int &nrowgrp)
 {
-    const int b = b0 + blockIdx.x;
-    if (bt.leaf[b]) return;
-    const int c0 = bt.child[b], c1 = c0 + bt.nchild[b];
-    for (int i = threadIdx.x; i < Kp; i += blockDim.x) {
-        T acc = 0;
-        if (i < K)
-            for (int ch = c0; ch < c1; ++ch) {
-                const T *Tm = Tt + (size_t)octant_of(bt.ix[ch], bt.iy[ch], bt.iz[ch]) * K * K;
-                const T *Mc = M + (size_t)ch * Kp;
-                for (int j = 0; j < K; ++j) acc += Tm[(size_t)j * K + i] * Mc[j];
-            }
-        M[(size_t)b * Kp + i] = acc;
-    }
+    const int blocks = Kp / 16;
+    nrowgrp = ceil_div(blocks, kM2LRB);
+    return ceil_div(blocks, nrowgrp);
 }
 
-// M2L into the boxes [b0, b1): L = sum over the window of T_m2l[offset] M_src.
-// Boxes above level 2 get zero.
 template <typename T>
-__global__ __launch_bounds__(128) void k_m2l(BoxTable bt, int b0, int K, int Kp, const int32_t *__restrict__ vtab,
-                                             const T *__restrict__ Tt, const T *__restrict__ M, T *__restrict__ L)
+static void launch_xlate(const XlateArgs &a, int grid, const T *At, const T *X, T *out, hipStream_t st)
 {
-    const int b = b0 + blockIdx.x;
-    const int cx = bt.ix[b] & 1, cy = bt.iy[b] & 1, cz = bt.iz[b] & 1;
-    const int32_t *row = vtab + (size_t)b * kWin;
-    const bool active = bt.level[b] >= 2;
-    for (int i = threadIdx.x; i < Kp; i += blockDim.x) {
-        T acc = 0;
-        if (i < K && active)
-            for (int w = 0; w < kWin; ++w) {
-                const int src = row[w];
-                if (src < 0) continue;
-                const int dx = w / 36 - 2 - cx, dy = (w / 6) % 6 - 2 - cy, dz = w % 6 - 2 - cz;
-                const T *Tm = Tt + (size_t)((dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)) * K * K;
-                const T *Ms = M + (size_t)src * Kp;
-                for (int j = 0; j < K; ++j) acc += Tm[(size_t)j * K + i] * Ms[j];
-            }
-        L[(size_t)b * Kp + i] = acc;
+    int nrg;
+    const int nrb = xlate_nrb(a.Kp, nrg);
+    const bool partial = nrb * 16 * nrg != a.Kp;
+    switch (nrb * 2 + (partial ? 1 : 0)) {
+#define PT_XL(NB)                                                                       \
+    case 2 * NB: k_xlate<T, NB, false><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break; \
+    case 2 * NB + 1: k_xlate<T, NB, true><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break;
+        PT_XL(1) PT_XL(2) PT_XL(3) PT_XL(4) PT_XL(5) PT_XL(6) PT_XL(7) PT_XL(8) PT_XL(9) PT_XL(10) PT_XL(11)
+        PT_XL(12)
+#undef PT_XL
+    default: break;
     }
 }
 
-// L2L for the boxes [b0, b1) of one level (>= 3): child += T_l2l[octant] parent.
+// Box range [b0, b0 + n): out = (mode 2: out +) sum of the slot-group partials,
+// in group order; mode 1 leaves the boxes flagged in skip untouched.
 template <typename T>
-__global__ __launch_bounds__(128) void k_l2l(BoxTable bt, int b0, int K, int Kp, const T *__restrict__ Tt,
-                                             T *__restrict__ L)
+__global__ void k_xlate_reduce(int b0, int n, int Kp, int nbox, int ngroup, int mode, const uint8_t *__restrict__ skip,
+                               const T *__restrict__ part, T *__restrict__ out)
 {
-    const int b = b0 + blockIdx.x;
-    const int P = bt.parent[b];
-    const T *Tm = Tt + (size_t)octant_of(bt.ix[b], bt.iy[b], bt.iz[b]) * K * K;
-    const T *Lp = L + (size_t)P * Kp;
-    for (int i = threadIdx.x; i < K; i += blockDim.x) {
-        T acc = 0;
-        for (int j = 0; j < K; ++j) acc += Tm[(size_t)j * K + i] * Lp[j];
-        L[(size_t)b * Kp + i] += acc;
-    }
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)n * Kp) return;
+    const int b = b0 + (int)(e / Kp);
+    const size_t off = (size_t)b * Kp + e % Kp;
+    if (mode == 1 && skip[b]) return;
+    T acc = 0;
+    for (int g = 0; g < ngroup; ++g) acc += part[(size_t)g * nbox * Kp + off];
+    out[off] = mode == 2 ? out[off] + acc : acc;
 }
 
-// Far field (L2P) + near field (P2P) of every ion of a leaf.  Writes the
-// field per unit charge in batch order.
+// L = sum of the slot-group partials, in group order; zero above level 2.
+template <typename T>
+__global__ void k_m2l_reduce(BoxTable bt, int nbox, int Kp, int ngroup, const T *__restrict__ part,
+                             T *__restrict__ L)
+{
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)nbox * Kp) return;
+    const int b = (int)(e / Kp);
+    T acc = 0;
+    if (bt.level[b] >= 2)
+        for (int g = 0; g < ngroup; ++g) acc += part[(size_t)g * nbox * Kp + e];
+    L[e] = acc;
+}
+
+// Far field (L2P) + near field (P2P) of every ion of a leaf, 64 threads per
+// leaf.  Sources are staged through LDS 64 at a time as offsets from the
+// target leaf's centre (one FP64 subtraction per source and leaf, then
+// rounded to T), so the pair loop reads only LDS.  Leaves of at most 32
+// ions get two threads per target, each taking half of every tile; the two
+// halves are added in a fixed order.  Each tile's contribution is summed
+// plainly and added to the running total with Kahan compensation.  Writes
+// the field per unit charge in batch order.
 template <typename T>
 __global__ __launch_bounds__(64) void k_eval(BoxTable bt, const double *__restrict__ sp, int ntot, int p, int Kp,
-                                             const T *__restrict__ L, const int2 *__restrict__ near,
-                                             const int32_t *__restrict__ near_cnt, int stride,
-                                             const uint32_t *__restrict__ vals, int use_far, double *__restrict__ E)
+                                             const T *__restrict__ L, const T *__restrict__ rec,
+                                             const int2 *__restrict__ near, const int32_t *__restrict__ near_cnt,
+                                             int stride, const uint32_t *__restrict__ vals, int use_far,
+                                             double *__restrict__ E)
 {
+    __shared__ T sx[64], sy[64], sz[64];
+    __shared__ int sj[64];
+    __shared__ T hx[32], hy[32], hz[32];
     const int b = blockIdx.x;
     if (!bt.leaf[b]) return;
     const double4 g = bt.geo[b];
@@ -159,108 +357,213 @@ __global__ __launch_bounds__(64) void k_eval(BoxTable bt, const double *__restri
     const T *Lb = L + (size_t)b * Kp;
     const int2 *row = near + (size_t)b * stride;
     const int nn = near_cnt[b];
-    for (int k = bt.begin[b] + threadIdx.x; k < bt.end[b]; k += blockDim.x) {
-        const double xd = sp[k], yd = sp[ntot + k], zd = sp[2 * ntot + k];
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        if (use_far) {
-            T ex, ey, ez;
-            l2p_field<T>(p, Lb, (T)((xd - g.x) * ih), (T)((yd - g.y) * ih), (T)((zd - g.z) * ih), ex, ey, ez);
-            fx = (double)ex * ih * ih;
-            fy = (double)ey * ih * ih;
-            fz = (double)ez * ih * ih;
-        }
-        // near field, offsets from the target leaf centre
+    const int i0 = bt.begin[b], i1 = bt.end[b];
+    const int split = (i1 - i0) <= 32 ? 2 : 1;
+    const int per = 64 / split;                 // targets per pass
+    const int ti = threadIdx.x % per, half = threadIdx.x / per;
+    for (int c0 = i0; c0 < i1; c0 += per) {
+        const int k = c0 + ti;
+        const bool tv = k < i1;
+        const double xd = tv ? sp[k] : g.x, yd = tv ? sp[ntot + k] : g.y, zd = tv ? sp[2 * ntot + k] : g.z;
         const T xi = (T)(xd - g.x), yi = (T)(yd - g.y), zi = (T)(zd - g.z);
-        T sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0;  // Kahan sums of per-range partials
+        T ax = 0, ay = 0, az = 0, cx = 0, cy = 0, cz = 0;  // Kahan sums of tile partials
         for (int r = 0; r < nn; ++r) {
             const int2 rg = row[r];
-            T px = 0, py = 0, pz = 0;
-            for (int j = rg.x; j < rg.y; ++j) {
-                const T dx = xi - (T)(sp[j] - g.x);
-                const T dy = yi - (T)(sp[ntot + j] - g.y);
-                const T dz = zi - (T)(sp[2 * ntot + j] - g.z);
-                const T r2 = dx * dx + dy * dy + dz * dz;
-                const T ri = (r2 > T(0) && j != k) ? rsqrt(r2) : T(0);
-                const T w = ri * ri * ri;
-                px += dx * w;
-                py += dy * w;
-                pz += dz * w;
-            }
-            {
-                T y_ = px - cx, t_ = sx + y_;
-                cx = (t_ - sx) - y_;
-                sx = t_;
+            for (int base = rg.x; base < rg.y; base += 64) {
+                __syncthreads();
+                const int j = base + threadIdx.x;
+                if (j < rg.y) {
+                    sx[threadIdx.x] = (T)(sp[j] - g.x);
+                    sy[threadIdx.x] = (T)(sp[ntot + j] - g.y);
+                    sz[threadIdx.x] = (T)(sp[2 * ntot + j] - g.z);
+                    sj[threadIdx.x] = j;
+                }
+                __syncthreads();
+                const int cnt = min(64, rg.y - base);
+                const int q0 = split == 2 ? half * 32 : 0, q1 = split == 2 ? min(cnt, q0 + 32) : cnt;
+                T px = 0, py = 0, pz = 0;
+                for (int q = q0; q < q1; ++q) {
+                    const T dx = xi - sx[q], dy = yi - sy[q], dz = zi - sz[q];
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    const T rinv = (r2 > T(0) && sj[q] != k) ? rsqrt(r2) : T(0);
+                    const T w = rinv * rinv * rinv;
+                    px += dx * w;
+                    py += dy * w;
+                    pz += dz * w;
+                }
+                T y_ = px - cx, t_ = ax + y_;
+                cx = (t_ - ax) - y_;
+                ax = t_;
                 y_ = py - cy;
-                t_ = sy + y_;
-                cy = (t_ - sy) - y_;
-                sy = t_;
+                t_ = ay + y_;
+                cy = (t_ - ay) - y_;
+                ay = t_;
                 y_ = pz - cz;
-                t_ = sz + y_;
-                cz = (t_ - sz) - y_;
-                sz = t_;
+                t_ = az + y_;
+                cz = (t_ - az) - y_;
+                az = t_;
             }
         }
-        const int gi = (int)vals[k];
-        E[gi] = fx + (double)sx;
-        E[ntot + gi] = fy + (double)sy;
-        E[2 * ntot + gi] = fz + (double)sz;
+        if (split == 2) {  // second half hands its sum to the first, added in a fixed order
+            __syncthreads();
+            if (half == 1) {
+                hx[ti] = ax;
+                hy[ti] = ay;
+                hz[ti] = az;
+            }
+            __syncthreads();
+        }
+        if (half == 0 && tv) {
+            double fx = 0.0, fy = 0.0, fz = 0.0;
+            if (use_far) {
+                T ex, ey, ez;
+                l2p_field<T>(p, Lb, rec, (T)((xd - g.x) * ih), (T)((yd - g.y) * ih), (T)((zd - g.z) * ih), ex, ey,
+                             ez);
+                fx = (double)ex * ih * ih;
+                fy = (double)ey * ih * ih;
+                fz = (double)ez * ih * ih;
+            }
+            double nx = (double)ax, ny = (double)ay, nz = (double)az;
+            if (split == 2) {
+                nx += (double)hx[ti];
+                ny += (double)hy[ti];
+                nz += (double)hz[ti];
+            }
+            const int gi = (int)vals[k];
+            E[gi] = fx + nx;
+            E[ntot + gi] = fy + ny;
+            E[2 * ntot + gi] = fz + nz;
+        }
     }
 }
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T>
-void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *m2m_t,
-                   T *M, hipStream_t st)
+static XlateArgs xlate_base(int Kp, int nbox)
 {
-    const int K = kcoef(p), Kp = kpad(p);
-    if (hs.nbox > 0) k_p2m<T><<<hs.nbox, 128, 0, st>>>(bt, sp, ntot, p, Kp, M);
+    XlateArgs a{};
+    a.nbucket = 1;
+    a.ngroup = 1;
+    xlate_nrb(Kp, a.nrowgrp);
+    a.Kp = Kp;
+    a.nbox = nbox;
+    return a;
+}
+
+// A level of M2M (mode 1) or L2L (mode 2): 8 octant slots, split into
+// groups whose partial sums a second kernel adds in group order.
+template <typename T>
+static void launch_level_xlate(const BoxTable &bt, int Kp, int nbox, int b0, int n, int mode, const T *ops,
+                               const int2 *oct_slots, const int32_t *srctab, T *X, T *part, hipStream_t st)
+{
+    const int tiles = ceil_div(n, kM2LCols);
+    XlateArgs a = xlate_base(Kp, nbox);
+    a.b0 = b0;
+    a.nrange = n;
+    a.ngroup = std::max(1, std::min(8, ceil_div(512, tiles * a.nrowgrp)));
+    a.tile_stride = tiles;
+    a.slots = oct_slots;
+    a.nslot = 8;
+    a.srctab = srctab;
+    a.src_stride = 8;
+    a.mode = 0;
+    launch_xlate<T>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, st);
+    const size_t tot = (size_t)n * Kp;
+    k_xlate_reduce<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(b0, n, Kp, nbox, a.ngroup, mode, bt.leaf, part,
+                                                                        X);
+}
+
+template <typename T>
+void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *m2m_pad,
+                   const int2 *oct_slots, const int32_t *child_oct, const T *rec, T *M, T *part, hipStream_t st)
+{
+    const int Kp = kpad(p);
+    const size_t smem = (size_t)Kp * (kP2MIons + 1) * sizeof(T);
+    if (hs.nbox > 0) k_p2m<T><<<hs.nbox, 64, smem, st>>>(bt, sp, ntot, p, Kp, rec, M);
+    // M2M level by level: parents of level l gather their children by octant
     for (int l = kMaxLevel - 1; l >= 2; --l) {
         const int b0 = hs.level_start[l], b1 = hs.level_start[l + 1];
-        if (b1 > b0) k_m2m<T><<<b1 - b0, 128, 0, st>>>(bt, b0, K, Kp, m2m_t, M);
+        if (b1 <= b0 || hs.level_start[l + 2] <= b1) continue;  // no children below
+        launch_level_xlate<T>(bt, Kp, hs.nbox, b0, b1 - b0, 1, m2m_pad, oct_slots, child_oct, M, part, st);
     }
 }
 
 template <typename T>
-void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t *vtab, const T *m2l_t, const T *M,
-                T *L, hipStream_t st)
+void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t *vtab, const int2 *slots,
+                const T *m2l_pad, const T *M, T *L, int32_t *cnt, int32_t *list, T *part, int ngroup, hipStream_t st)
 {
-    const int K = kcoef(p), Kp = kpad(p);
-    if (hs.nbox > 0) k_m2l<T><<<hs.nbox, 128, 0, st>>>(bt, 0, K, Kp, vtab, m2l_t, M, L);
+    const int Kp = kpad(p), nbox = hs.nbox;
+    if (nbox <= 0) return;
+    k_zero_i32<<<1, 64, 0, st>>>(cnt, 8);
+    k_m2l_bucket<<<ceil_div(nbox, 256), 256, 0, st>>>(bt, nbox, cnt, list);
+    const int n2 = nbox - hs.level_start[2];  // targets: boxes of level >= 2
+    if (n2 > 0) {
+        XlateArgs a = xlate_base(Kp, nbox);
+        a.cnt = cnt;
+        a.list = list;
+        a.list_stride = nbox;
+        a.nbucket = 8;  // workgroup id mod 8 = parity = XCD under round-robin dispatch
+        a.ngroup = ngroup;
+        a.tile_stride = std::max(1, ceil_div(n2, 8 * kM2LCols));
+        a.slots = slots;
+        a.nslot = 189;
+        a.srctab = vtab;
+        a.src_stride = kWin;
+        a.mode = 0;
+        launch_xlate<T>(a, 8 * a.tile_stride * ngroup * a.nrowgrp, m2l_pad, M, part, st);
+    }
+    const size_t tot = (size_t)nbox * Kp;
+    k_m2l_reduce<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(bt, nbox, Kp, ngroup, part, L);
+}
+
+int m2l_groups(int n2)
+{
+    // enough workgroups to fill 256 CUs several times over, between 6 (at most
+    // kXSlots of the 189 slots per workgroup) and 16 groups
+    const int tiles = std::max(1, ceil_div(n2, kM2LCols));
+    return std::max(ceil_div(189, kXSlots), std::min(16, ceil_div(1024, tiles)));
 }
 
 template <typename T>
-void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_t, T *L, hipStream_t st)
+void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_pad, const int2 *oct_slots,
+                     const int32_t *parent_oct, T *L, T *part, hipStream_t st)
 {
-    const int K = kcoef(p), Kp = kpad(p);
+    const int Kp = kpad(p);
+    // L2L level by level (3 and deeper): each box adds its parent's expansion
+    // shifted by the operator of its own octant (slot = octant)
     for (int l = 3; l <= kMaxLevel; ++l) {
         const int b0 = hs.level_start[l], b1 = hs.level_start[l + 1];
-        if (b1 > b0) k_l2l<T><<<b1 - b0, 128, 0, st>>>(bt, b0, K, Kp, l2l_t, L);
+        if (b1 <= b0) continue;
+        launch_level_xlate<T>(bt, Kp, hs.nbox, b0, b1 - b0, 2, l2l_pad, oct_slots, parent_oct, L, part, st);
     }
 }
 
 template <typename T>
-void launch_eval(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const int2 *near,
-                 const int32_t *near_cnt, int stride, const uint32_t *vals, int use_far, double *E, hipStream_t st)
+void launch_eval(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
+                 const int2 *near, const int32_t *near_cnt, int stride, const uint32_t *vals, int use_far, double *E,
+                 hipStream_t st)
 {
     if (nbox > 0)
-        k_eval<T><<<nbox, 64, 0, st>>>(bt, sp, ntot, p, kpad(p), L, near, near_cnt, stride, vals, use_far, E);
+        k_eval<T><<<nbox, 64, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, near, near_cnt, stride, vals, use_far, E);
 }
 
 template void launch_upward<double>(const BoxTable &, const double *, int, int, const TreeSummary &, const double *,
-                                    double *, hipStream_t);
+                                    const int2 *, const int32_t *, const double *, double *, double *, hipStream_t);
 template void launch_upward<float>(const BoxTable &, const double *, int, int, const TreeSummary &, const float *,
-                                   float *, hipStream_t);
-template void launch_m2l<double>(const BoxTable &, int, const TreeSummary &, const int32_t *, const double *,
-                                 const double *, double *, hipStream_t);
-template void launch_m2l<float>(const BoxTable &, int, const TreeSummary &, const int32_t *, const float *,
-                                const float *, float *, hipStream_t);
-template void launch_downward<double>(const BoxTable &, int, const TreeSummary &, const double *, double *,
-                                      hipStream_t);
-template void launch_downward<float>(const BoxTable &, int, const TreeSummary &, const float *, float *, hipStream_t);
-template void launch_eval<double>(const BoxTable &, const double *, int, int, int, const double *, const int2 *,
-                                  const int32_t *, int, const uint32_t *, int, double *, hipStream_t);
-template void launch_eval<float>(const BoxTable &, const double *, int, int, int, const float *, const int2 *,
-                                 const int32_t *, int, const uint32_t *, int, double *, hipStream_t);
+                                   const int2 *, const int32_t *, const float *, float *, float *, hipStream_t);
+template void launch_m2l<double>(const BoxTable &, int, const TreeSummary &, const int32_t *, const int2 *,
+                                 const double *, const double *, double *, int32_t *, int32_t *, double *, int,
+                                 hipStream_t);
+template void launch_m2l<float>(const BoxTable &, int, const TreeSummary &, const int32_t *, const int2 *,
+                                const float *, const float *, float *, int32_t *, int32_t *, float *, int,
+                                hipStream_t);
+template void launch_downward<double>(const BoxTable &, int, const TreeSummary &, const double *, const int2 *,
+                                      const int32_t *, double *, double *, hipStream_t);
+template void launch_downward<float>(const BoxTable &, int, const TreeSummary &, const float *, const int2 *,
+                                     const int32_t *, float *, float *, hipStream_t);
+template void launch_eval<double>(const BoxTable &, const double *, int, int, int, const double *, const double *,
+                                  const int2 *, const int32_t *, int, const uint32_t *, int, double *, hipStream_t);
+template void launch_eval<float>(const BoxTable &, const double *, int, int, int, const float *, const float *,
+                                 const int2 *, const int32_t *, int, const uint32_t *, int, double *, hipStream_t);
 
 }  // namespace pt

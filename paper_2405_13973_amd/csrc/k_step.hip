@@ -40,6 +40,12 @@ __global__ void k_ion_crystal(const CrystalDev *__restrict__ cs, int nc, int nto
     ion_crystal[g] = lo;
 }
 
+__global__ void k_zero_words(uint64_t *__restrict__ p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t v0, uint64_t v1, int n_pairs)
 {
     // pattern: six words per crystal, three v0 then three v1
@@ -80,26 +86,58 @@ __global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *_
         v[4] = v[1];
         v[5] = v[2];
     }
+    // wave reduction when the wave is uniform in crystal, then a block
+    // reduction through LDS when all its waves agree; else per-wave atomics
+    __shared__ unsigned long long wv[4][6];
+    __shared__ int wc[4];
     const unsigned long long act = __ballot(active);
-    if (act == 0) return;
-    const int first = __ffsll((long long)act) - 1;
+    const int first = act ? __ffsll((long long)act) - 1 : 0;
     const int cref = __shfl(c, first);
-    const bool uniform = __ballot(active && c != cref) == 0;
+    const bool uniform = act != 0 && __ballot(active && c != cref) == 0;
     if (uniform) {
         for (int off = 32; off > 0; off >>= 1)
             for (int k = 0; k < 6; ++k) {
                 const unsigned long long o = __shfl_xor(v[k], off);
                 v[k] = k < 3 ? (o < v[k] ? o : v[k]) : (o > v[k] ? o : v[k]);
             }
-        if ((threadIdx.x & 63) == 0)
-            for (int k = 0; k < 6; ++k) {
-                if (k < 3) atomicMin(&bbox[6 * cref + k], v[k]);
-                else atomicMax(&bbox[6 * cref + k], v[k]);
-            }
     } else if (active) {
         for (int k = 0; k < 6; ++k) {
             if (k < 3) atomicMin(&bbox[6 * c + k], v[k]);
             else atomicMax(&bbox[6 * c + k], v[k]);
+        }
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        wc[w] = uniform ? cref : (act ? -1 : -2);  // -2: no ion in this wave
+        for (int k = 0; k < 6; ++k) wv[w][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+        int cb = -3;
+        bool same = true;
+        for (int k = 0; k < nw; ++k) {
+            if (wc[k] == -2) continue;
+            if (wc[k] == -1 || (cb != -3 && wc[k] != cb)) same = false;
+            cb = wc[k];
+        }
+        if (same && cb >= 0) {
+            unsigned long long r[6] = {~0ull, ~0ull, ~0ull, 0ull, 0ull, 0ull};
+            for (int k = 0; k < nw; ++k)
+                if (wc[k] >= 0)
+                    for (int j = 0; j < 6; ++j) r[j] = j < 3 ? (wv[k][j] < r[j] ? wv[k][j] : r[j])
+                                                             : (wv[k][j] > r[j] ? wv[k][j] : r[j]);
+            for (int j = 0; j < 6; ++j) {
+                if (j < 3) atomicMin(&bbox[6 * cb + j], r[j]);
+                else atomicMax(&bbox[6 * cb + j], r[j]);
+            }
+        } else {
+            for (int k = 0; k < nw; ++k)
+                if (wc[k] >= 0)
+                    for (int j = 0; j < 6; ++j) {
+                        if (j < 3) atomicMin(&bbox[6 * wc[k] + j], wv[k][j]);
+                        else atomicMax(&bbox[6 * wc[k] + j], wv[k][j]);
+                    }
         }
     }
 }
@@ -312,8 +350,7 @@ void launch_bbox_reset(unsigned long long *bbox, int nc, hipStream_t st)
 
 void launch_zero_u64(uint64_t *p, int n, hipStream_t st)
 {
-    // n < 6 words: one "crystal" worth of the fill pattern with both halves zero
-    k_fill_u64<<<1, 64, 0, st>>>(p, 0ull, 0ull, (n + 5) / 6);
+    if (n > 0) k_zero_words<<<ceil_div(n, 256), 256, 0, st>>>(p, n);
 }
 
 void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int do_drift,

@@ -22,30 +22,83 @@ namespace pt {
 
 // --------------------------------------------------------------- scan
 
-// Exclusive prefix sum of n uint32 in place by one workgroup; *total gets the sum.
-__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t *__restrict__ a, int n, uint32_t *__restrict__ total)
+// Exclusive prefix sum of n uint32 in place, in three launches: block sums
+// of 4096-element chunks, a one-workgroup scan of those sums, then each
+// chunk scanned with its offset.  *total (optional) gets the sum.
+constexpr int kScanTB = 1024;
+constexpr int kScanChunk = 4 * kScanTB;
+
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *lds_w, uint32_t &block_total)
 {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int chunk = (n + 1023) / 1024;
-    const int b = t * chunk, e = min(n, b + chunk);
-    uint32_t s = 0;
-    for (int i = b; i < e; ++i) s += a[i];
-    part[t] = s;
+    // inclusive wave scan, then wave totals through LDS
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds_w[w] = x;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = t >= off ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += v;
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < nw; ++k) {
+            const uint32_t t = lds_w[k];
+            lds_w[k] = run;
+            run += t;
+        }
+        lds_w[nw] = run;
+    }
+    __syncthreads();
+    block_total = lds_w[nw];
+    return lds_w[w] + x - v;
+}
+
+__global__ __launch_bounds__(kScanTB) void k_scan_reduce(const uint32_t *__restrict__ a, int n,
+                                                         uint32_t *__restrict__ partial)
+{
+    __shared__ uint32_t w[kScanTB / 64 + 1];
+    const int base = blockIdx.x * kScanChunk + 4 * threadIdx.x;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += base + k < n ? a[base + k] : 0u;
+    uint32_t tot;
+    block_excl_scan(s, w, tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanTB) void k_scan_top(uint32_t *__restrict__ partial, int nb,
+                                                      uint32_t *__restrict__ total)
+{
+    __shared__ uint32_t w[kScanTB / 64 + 1];
+    uint32_t carry = 0;
+    for (int c = 0; c < nb; c += kScanTB) {
+        const int i = c + threadIdx.x;
+        const uint32_t v = i < nb ? partial[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, w, tot);
+        if (i < nb) partial[i] = carry + ex;
+        carry += tot;
         __syncthreads();
     }
-    uint32_t run = part[t] - s;
-    for (int i = b; i < e; ++i) {
-        const uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(kScanTB) void k_scan_down(uint32_t *__restrict__ a, int n,
+                                                       const uint32_t *__restrict__ partial)
+{
+    __shared__ uint32_t w[kScanTB / 64 + 1];
+    const int base = blockIdx.x * kScanChunk + 4 * threadIdx.x;
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = base + k < n ? a[base + k] : 0u;
+    uint32_t tot;
+    uint32_t run = partial[blockIdx.x] + block_excl_scan(v[0] + v[1] + v[2] + v[3], w, tot);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < n) a[base + k] = run;
+        run += v[k];
     }
-    if (t == 1023 && total) *total = part[1023];
 }
 
 // --------------------------------------------------------------- radix sort
@@ -286,6 +339,25 @@ __global__ void k_tree_links(BoxTable bt, const TreeSummary *__restrict__ sum)
     bt.nchild[b] = nch;
 }
 
+// Source maps of the M2M / L2L translation GEMMs, 8 slots per box indexed by
+// octant: child_oct[b][o] = child of b in octant o, parent_oct[b][o] = parent
+// of b in b's own octant slot (-1 elsewhere).
+__global__ void k_oct_tables(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ child_oct,
+                             int32_t *__restrict__ parent_oct)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= sum->nbox) return;
+    int32_t ch[8], pa[8];
+    for (int o = 0; o < 8; ++o) ch[o] = pa[o] = -1;
+    for (int c = bt.child[b], e = c + bt.nchild[b]; c < e; ++c)
+        ch[((bt.ix[c] & 1) << 2) | ((bt.iy[c] & 1) << 1) | (bt.iz[c] & 1)] = c;
+    pa[((bt.ix[b] & 1) << 2) | ((bt.iy[b] & 1) << 1) | (bt.iz[b] & 1)] = bt.parent[b];
+    for (int o = 0; o < 8; ++o) {
+        child_oct[(size_t)b * 8 + o] = ch[o];
+        parent_oct[(size_t)b * 8 + o] = pa[o];
+    }
+}
+
 // Same-level neighbours (offsets in [-1,1]^3, slot (dx+1)*9 + (dy+1)*3 + (dz+1)).
 __global__ void k_colleagues(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ coll)
 {
@@ -380,19 +452,24 @@ __global__ void k_nearlist(BoxTable bt, const TreeSummary *__restrict__ sum, con
 
 // ---------------------------------------------------------------- launchers
 
-void launch_scan(uint32_t *a, int n, uint32_t *total, hipStream_t st)
+int scan_partials(int n) { return ceil_div(n, kScanChunk); }
+
+void launch_scan(uint32_t *a, int n, uint32_t *partial, uint32_t *total, hipStream_t st)
 {
-    k_scan_excl<<<1, 1024, 0, st>>>(a, n, total);
+    const int nb = scan_partials(n);
+    k_scan_reduce<<<nb, kScanTB, 0, st>>>(a, n, partial);
+    k_scan_top<<<1, kScanTB, 0, st>>>(partial, nb, total);
+    k_scan_down<<<nb, kScanTB, 0, st>>>(a, n, partial);
 }
 
 int sort_blocks(int n) { return ceil_div(n, kSortTile); }
 
 void launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, int n, int shift,
-                       uint32_t *hist, hipStream_t st)
+                       uint32_t *hist, uint32_t *partial, hipStream_t st)
 {
     const int nblk = sort_blocks(n);
     k_radix_hist<<<nblk, kSortTB, 0, st>>>(kin, n, shift, hist, nblk);
-    k_scan_excl<<<1, 1024, 0, st>>>(hist, 256 * nblk, nullptr);
+    launch_scan(hist, 256 * nblk, partial, nullptr, st);
     k_radix_scatter<<<nblk, kSortTB, 0, st>>>(kin, vin, kout, vout, n, shift, hist, nblk);
 }
 
@@ -405,12 +482,12 @@ void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint3
 int tree_blocks(int ntot) { return ceil_div(ntot, 256); }
 
 void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
-                       uint32_t *blockcnt, uint32_t *total, TreeSummary *sum, hipStream_t st)
+                       uint32_t *blockcnt, uint32_t *partial, uint32_t *total, TreeSummary *sum, hipStream_t st)
 {
     const int nblk = tree_blocks(ntot);
     k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask);
     k_tree_count<<<nblk, 256, 0, st>>>(rep_mask, ntot, blockcnt, nblk);
-    k_scan_excl<<<1, 1024, 0, st>>>(blockcnt, (kMaxLevel + 1) * nblk, total);
+    launch_scan(blockcnt, (kMaxLevel + 1) * nblk, partial, total, st);
     k_tree_summary<<<1, 64, 0, st>>>(blockcnt, nblk, total, sum);
 }
 
@@ -424,8 +501,10 @@ void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64
 }
 
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
-                  int2 *near, int32_t *near_cnt, unsigned long long *counters, hipStream_t st)
+                  int2 *near, int32_t *near_cnt, unsigned long long *counters, int32_t *child_oct,
+                  int32_t *parent_oct, hipStream_t st)
 {
+    k_oct_tables<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, child_oct, parent_oct);
     k_colleagues<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll);
     k_vlist<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll, vtab, counters);
     k_nearlist<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll, stride, near, near_cnt, counters + 1);

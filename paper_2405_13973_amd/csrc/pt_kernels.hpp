@@ -30,32 +30,43 @@ void launch_direct(const CrystalDev *cs, const int32_t *blk_crystal, const int32
                    double *E, hipStream_t st);
 
 // k_tree.hip
-void launch_scan(uint32_t *a, int n, uint32_t *total, hipStream_t st);
+int scan_partials(int n);  // workspace entries launch_scan needs for n elements
+void launch_scan(uint32_t *a, int n, uint32_t *partial, uint32_t *total, hipStream_t st);
 int sort_blocks(int n);
 void launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, int n, int shift,
-                       uint32_t *hist, hipStream_t st);
+                       uint32_t *hist, uint32_t *partial, hipStream_t st);
 void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint32_t *vals, int ntot, double *sp,
                    hipStream_t st);
 int tree_blocks(int ntot);
 void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
-                       uint32_t *blockcnt, uint32_t *total, TreeSummary *sum, hipStream_t st);
+                       uint32_t *blockcnt, uint32_t *partial, uint32_t *total, TreeSummary *sum, hipStream_t st);
 void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
                        const uint32_t *rep_mask, const uint32_t *scanned, const BoxTable &bt, const TreeSummary *sum,
                        int nbox, hipStream_t st);
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
-                  int2 *near, int32_t *near_cnt, unsigned long long *counters, hipStream_t st);
+                  int2 *near, int32_t *near_cnt, unsigned long long *counters, int32_t *child_oct,
+                  int32_t *parent_oct, hipStream_t st);
 
 // k_fmm.hip
+// rec: recurrence table (fmm_math.hpp), kRecFields x kq(p) entries.
+// m2m_pad / l2l_pad: 8 operators, Kp x Kp column-major, zero padded;
+// oct_slots: the 8 slots {octant, octant}; child_oct / parent_oct: 8 x nbox.
 template <typename T>
-void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *m2m_t,
-                   T *M, hipStream_t st);
+void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *m2m_pad,
+                   const int2 *oct_slots, const int32_t *child_oct, const T *rec, T *M, T *part, hipStream_t st);
+// m2l_pad: 343 operators, each Kp x Kp column-major (A[j][i] = T[i][j]), zero-padded;
+// slots: per parity the 189 non-touching window slots {slot, operator index};
+// cnt: 8 ints, list: 8 x nbox ints, part: ngroup x nbox x Kp of workspace.
 template <typename T>
-void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t *vtab, const T *m2l_t, const T *M,
-                T *L, hipStream_t st);
+void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t *vtab, const int2 *slots,
+                const T *m2l_pad, const T *M, T *L, int32_t *cnt, int32_t *list, T *part, int ngroup, hipStream_t st);
+int m2l_groups(int n2);  // slot groups of M2L (partial-sum buffer: groups x nbox x Kp; M2M/L2L use <= 8)
 template <typename T>
-void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_t, T *L, hipStream_t st);
+void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_pad, const int2 *oct_slots,
+                     const int32_t *parent_oct, T *L, T *part, hipStream_t st);
 template <typename T>
-void launch_eval(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const int2 *near,
-                 const int32_t *near_cnt, int stride, const uint32_t *vals, int use_far, double *E, hipStream_t st);
+void launch_eval(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
+                 const int2 *near, const int32_t *near_cnt, int stride, const uint32_t *vals, int use_far, double *E,
+                 hipStream_t st);
 
 }  // namespace pt

@@ -66,6 +66,10 @@ struct Tables {
     int p = -1;
     double *m2m_d = nullptr, *l2l_d = nullptr, *m2l_d = nullptr;
     float *m2m_f = nullptr, *l2l_f = nullptr, *m2l_f = nullptr;
+    int2 *slots = nullptr;      // [8][189] {window slot, operator index}
+    int2 *oct_slots = nullptr;  // [8] {octant, octant}
+    double *rec_d = nullptr;
+    float *rec_f = nullptr;
 };
 
 }  // namespace
@@ -106,9 +110,10 @@ struct pt_ctx {
     int last_ntot = 0, last_was_fmm = 0, last_stride = 0, last_p = 0, last_prec = 0;
     TreeSummary last_sum{};
     // timing
-    int timing = 0;
+    int timing = 0, timing_pending = 0;
     hipEvent_t ev[7] = {};
-    double phase_ms[6] = {0, 0, 0, 0, 0, 0};
+    double phase_sum[6] = {0, 0, 0, 0, 0, 0};
+    int64_t phase_count = 0;
 };
 
 // ---------------------------------------------------------------- memory
@@ -172,27 +177,28 @@ static pt_status ensure_tables(pt_ctx *ctx, int p)
     if (t.p == p) return PT_OK;
     PT_HIP(hipStreamSynchronize(ctx->stream));
     for (void *q : {(void *)t.m2m_d, (void *)t.l2l_d, (void *)t.m2l_d, (void *)t.m2m_f, (void *)t.l2l_f,
-                    (void *)t.m2l_f})
+                    (void *)t.m2l_f, (void *)t.slots, (void *)t.oct_slots, (void *)t.rec_d, (void *)t.rec_f})
         ctx_free(ctx, q);
     t = Tables{};
     const int K = kcoef(p);
     const size_t KK = (size_t)K * K;
+    const int Kp = kpad(p);
     std::vector<double> m2m(8 * KK), l2l(8 * KK), m2l(343 * KK);
     if (build_operator_tables(p, m2m.data(), l2l.data(), m2l.data()) != 0) {
         pt_set_error("operator tables: unsupported p = %d", p);
         return PT_EINVAL;
     }
-    // column-major copies: Tt[o][j][i] = T[o][i][j]
-    auto transpose = [&](std::vector<double> &v, int count) {
-        std::vector<double> o(v.size());
+    // for the matrix cores: column-major (A[j][i] = T[i][j]), zero-padded to Kp x Kp
+    auto pad_cm = [&](std::vector<double> &v, int count) {
+        std::vector<double> pad((size_t)count * Kp * Kp, 0.0);
         for (int c = 0; c < count; ++c)
             for (int i = 0; i < K; ++i)
-                for (int j = 0; j < K; ++j) o[c * KK + (size_t)j * K + i] = v[c * KK + (size_t)i * K + j];
-        v.swap(o);
+                for (int j = 0; j < K; ++j) pad[(size_t)c * Kp * Kp + (size_t)j * Kp + i] = v[c * KK + (size_t)i * K + j];
+        v.swap(pad);
     };
-    transpose(m2m, 8);
-    transpose(l2l, 8);
-    transpose(m2l, 343);
+    pad_cm(m2m, 8);
+    pad_cm(l2l, 8);
+    pad_cm(m2l, 343);
     auto upload = [&](const std::vector<double> &v, double **dd, float **df) -> pt_status {
         PT_TRY(ctx_alloc(ctx, (void **)dd, v.size() * sizeof(double)));
         PT_HIP(hipMemcpy(*dd, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -204,6 +210,29 @@ static pt_status ensure_tables(pt_ctx *ctx, int p)
     PT_TRY(upload(m2m, &t.m2m_d, &t.m2m_f));
     PT_TRY(upload(l2l, &t.l2l_d, &t.l2l_f));
     PT_TRY(upload(m2l, &t.m2l_d, &t.m2l_f));
+    std::vector<double> rec((size_t)kRecFields * kq(p));
+    build_recurrence_table(p, rec.data());
+    PT_TRY(upload(rec, &t.rec_d, &t.rec_f));
+    // the 189 non-touching slots of each parity's 6x6x6 window
+    std::vector<int2> sl;
+    for (int o = 0; o < 8; ++o) {
+        const int cx = (o >> 2) & 1, cy = (o >> 1) & 1, cz = o & 1;
+        for (int w = 0; w < kWin; ++w) {
+            const int dx = w / 36 - 2 - cx, dy = (w / 6) % 6 - 2 - cy, dz = w % 6 - 2 - cz;
+            if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+            sl.push_back(make_int2(w, (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)));
+        }
+    }
+    if (sl.size() != 8 * 189) {
+        pt_set_error("window slot table has %zu entries", sl.size());
+        return PT_EDEVICE;
+    }
+    PT_TRY(ctx_alloc(ctx, (void **)&t.slots, sl.size() * sizeof(int2)));
+    PT_HIP(hipMemcpy(t.slots, sl.data(), sl.size() * sizeof(int2), hipMemcpyHostToDevice));
+    int2 os[8];
+    for (int o = 0; o < 8; ++o) os[o] = make_int2(o, o);
+    PT_TRY(ctx_alloc(ctx, (void **)&t.oct_slots, sizeof(os)));
+    PT_HIP(hipMemcpy(t.oct_slots, os, sizeof(os), hipMemcpyHostToDevice));
     t.p = p;
     return PT_OK;
 }
@@ -310,6 +339,8 @@ static pt_status form_batch(pt_ctx *ctx, const std::vector<pt_crystal *> &cs, Ba
     return PT_OK;
 }
 
+static pt_status finish_timing(pt_ctx *ctx);
+
 static void mark(pt_ctx *ctx, int i)
 {
     if (ctx->timing) (void)hipEventRecord(ctx->ev[i], ctx->stream);
@@ -347,6 +378,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     ctx->last_off = b.off;
     ctx->last_ntot = ntot;
     ctx->last_was_fmm = fp.method == 1;
+    PT_TRY(finish_timing(ctx));  // the event set is reused: collect the previous evaluation first
     mark(ctx, 0);
     if (fp.method == 0) {
         launch_direct(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, ntot, E, st);
@@ -355,6 +387,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         mark(ctx, 3);
         mark(ctx, 4);
         mark(ctx, 5);
+        ctx->timing_pending = ctx->timing;
         return PT_OK;
     }
     const int p = fp.p, s = fp.leaf_size;
@@ -373,6 +406,9 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "rep", sizeof(uint32_t) * ntot, &rep));
     PT_TRY(ws_get(ctx, "bcnt", sizeof(uint32_t) * (kMaxLevel + 1) * tree_blocks(ntot), &bcnt));
     PT_TRY(ws_get(ctx, "total", sizeof(uint32_t) * 4, &total));
+    uint32_t *scan_part;
+    const int scan_n = std::max(256 * sort_blocks(ntot), (kMaxLevel + 1) * tree_blocks(ntot));
+    PT_TRY(ws_get(ctx, "scan_part", sizeof(uint32_t) * (scan_partials(scan_n) + 1), &scan_part));
     PT_TRY(ws_get(ctx, "sp", sizeof(double) * 3 * ntot, &sp));
     PT_TRY(ws_get(ctx, "sum", sizeof(TreeSummary), &dsum));
     PT_TRY(ws_get(ctx, "counters", sizeof(unsigned long long) * 2, &counters));
@@ -382,12 +418,12 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     while ((1 << cbits) < nc) ++cbits;
     const int passes = (48 + cbits + 7) / 8;
     for (int ps = 0; ps < passes; ++ps) {
-        launch_radix_pass(k0, v0, k1, v1, ntot, 8 * ps, hist, st);
+        launch_radix_pass(k0, v0, k1, v1, ntot, 8 * ps, hist, scan_part, st);
         std::swap(k0, k1);
         std::swap(v0, v1);
     }
     launch_gather(b.d_desc, b.ion_crystal, v0, ntot, sp, st);
-    launch_tree_count(b.d_desc, k0, ntot, s, rep, bcnt, total, dsum, st);
+    launch_tree_count(b.d_desc, k0, ntot, s, rep, bcnt, scan_part, total, dsum, st);
     PT_HIP(hipMemcpyAsync(ctx->h_sum, dsum, sizeof(TreeSummary), hipMemcpyDeviceToHost, st));
     launch_zero_u64((uint64_t *)counters, 2, st);
     PT_HIP(hipStreamSynchronize(st));
@@ -412,33 +448,52 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "coll", sizeof(int32_t) * kNeigh * (size_t)nbox, &coll));
     PT_TRY(ws_get(ctx, "vtab", sizeof(int32_t) * kWin * (size_t)nbox, &vtab));
     PT_TRY(ws_get(ctx, "near", sizeof(int2) * (size_t)stride * nbox, &near));
-    PT_TRY(ws_get(ctx, "M", esz * Kp * (size_t)nbox, (char **)&M));
-    PT_TRY(ws_get(ctx, "L", esz * Kp * (size_t)nbox, (char **)&L));
+    // one extra row each (index nbox), kept at zero: the translation GEMMs
+    // read it for missing sources
+    PT_TRY(ws_get(ctx, "M", esz * Kp * (size_t)(nbox + 1), (char **)&M));
+    PT_TRY(ws_get(ctx, "L", esz * Kp * (size_t)(nbox + 1), (char **)&L));
     near_cnt = (int32_t *)ctx->ws["near_cnt"].ptr;
     PT_TRY(ensure_tables(ctx, p));
     const BoxTable bt = box_table(ctx);
     launch_tree_build(b.d_desc, roots, k0, ntot, s, rep, bcnt, bt, dsum, nbox, st);
-    launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, counters, st);
+    int32_t *child_oct, *parent_oct;
+    PT_TRY(ws_get(ctx, "child_oct", sizeof(int32_t) * 8 * (size_t)nbox, &child_oct));
+    PT_TRY(ws_get(ctx, "parent_oct", sizeof(int32_t) * 8 * (size_t)nbox, &parent_oct));
+    launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, counters, child_oct, parent_oct, st);
+    int32_t *m2l_cnt, *m2l_list;
+    void *m2l_part;
+    const int ngroup = m2l_groups(nbox - hs.level_start[2]);
+    PT_TRY(ws_get(ctx, "m2l_cnt", sizeof(int32_t) * 8, &m2l_cnt));
+    PT_TRY(ws_get(ctx, "m2l_list", sizeof(int32_t) * 8 * (size_t)nbox, &m2l_list));
+    PT_TRY(ws_get(ctx, "m2l_part", esz * Kp * (size_t)nbox * std::max(ngroup, 8), (char **)&m2l_part));
     mark(ctx, 1);
     const Tables &tb = ctx->tables;
+    launch_zero_u64((uint64_t *)((char *)M + esz * Kp * (size_t)nbox), (int)(esz * Kp / 8), st);
+    launch_zero_u64((uint64_t *)((char *)L + esz * Kp * (size_t)nbox), (int)(esz * Kp / 8), st);
     if (fp.precision == 1) {
-        launch_upward<float>(bt, sp, ntot, p, hs, tb.m2m_f, (float *)M, st);
+        launch_upward<float>(bt, sp, ntot, p, hs, tb.m2m_f, tb.oct_slots, child_oct, tb.rec_f, (float *)M,
+                             (float *)m2l_part, st);
         mark(ctx, 2);
-        launch_m2l<float>(bt, p, hs, vtab, tb.m2l_f, (const float *)M, (float *)L, st);
+        launch_m2l<float>(bt, p, hs, vtab, tb.slots, tb.m2l_f, (const float *)M, (float *)L, m2l_cnt, m2l_list,
+                          (float *)m2l_part, ngroup, st);
         mark(ctx, 3);
-        launch_downward<float>(bt, p, hs, tb.l2l_f, (float *)L, st);
+        launch_downward<float>(bt, p, hs, tb.l2l_f, tb.oct_slots, parent_oct, (float *)L, (float *)m2l_part, st);
         mark(ctx, 4);
-        launch_eval<float>(bt, sp, ntot, p, nbox, (const float *)L, near, near_cnt, stride, v0, 1, E, st);
+        launch_eval<float>(bt, sp, ntot, p, nbox, (const float *)L, tb.rec_f, near, near_cnt, stride, v0, 1, E, st);
     } else {
-        launch_upward<double>(bt, sp, ntot, p, hs, tb.m2m_d, (double *)M, st);
+        launch_upward<double>(bt, sp, ntot, p, hs, tb.m2m_d, tb.oct_slots, child_oct, tb.rec_d, (double *)M,
+                              (double *)m2l_part, st);
         mark(ctx, 2);
-        launch_m2l<double>(bt, p, hs, vtab, tb.m2l_d, (const double *)M, (double *)L, st);
+        launch_m2l<double>(bt, p, hs, vtab, tb.slots, tb.m2l_d, (const double *)M, (double *)L, m2l_cnt, m2l_list,
+                           (double *)m2l_part, ngroup, st);
         mark(ctx, 3);
-        launch_downward<double>(bt, p, hs, tb.l2l_d, (double *)L, st);
+        launch_downward<double>(bt, p, hs, tb.l2l_d, tb.oct_slots, parent_oct, (double *)L, (double *)m2l_part, st);
         mark(ctx, 4);
-        launch_eval<double>(bt, sp, ntot, p, nbox, (const double *)L, near, near_cnt, stride, v0, 1, E, st);
+        launch_eval<double>(bt, sp, ntot, p, nbox, (const double *)L, tb.rec_d, near, near_cnt, stride, v0, 1, E,
+                            st);
     }
     mark(ctx, 5);
+    ctx->timing_pending = ctx->timing;
     ctx->last_sum = hs;
     ctx->last_stride = stride;
     ctx->last_p = p;
@@ -448,17 +503,20 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     return PT_OK;
 }
 
+// Adds the phase times of the last timed evaluation to the running sums.
 static pt_status finish_timing(pt_ctx *ctx)
 {
-    if (!ctx->timing) return PT_OK;
+    if (!ctx->timing || !ctx->timing_pending) return PT_OK;
     PT_HIP(hipEventSynchronize(ctx->ev[5]));
     float ms;
     for (int i = 0; i < 5; ++i) {
         PT_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
-        ctx->phase_ms[i] = ms;
+        ctx->phase_sum[i] += ms;
     }
     PT_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[5]));
-    ctx->phase_ms[5] = ms;
+    ctx->phase_sum[5] += ms;
+    ctx->phase_count++;
+    ctx->timing_pending = 0;
     return PT_OK;
 }
 
@@ -834,15 +892,20 @@ pt_status pt_read_state(pt_crystal *c, double *pos, double *vel, int64_t *step, 
 pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable)
 {
     PT_REQUIRE(ctx, "ctx is NULL");
+    PT_TRY(finish_timing(ctx));
     ctx->timing = enable ? 1 : 0;
+    ctx->timing_pending = 0;
+    for (double &v : ctx->phase_sum) v = 0.0;
+    ctx->phase_count = 0;
     return PT_OK;
 }
 
-pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[6])
+pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[6], int64_t *count)
 {
     PT_REQUIRE(ctx && ms, "NULL argument");
     PT_TRY(finish_timing(ctx));
-    for (int i = 0; i < 6; ++i) ms[i] = ctx->phase_ms[i];
+    for (int i = 0; i < 6; ++i) ms[i] = ctx->phase_count ? ctx->phase_sum[i] / (double)ctx->phase_count : 0.0;
+    if (count) *count = ctx->phase_count;
     return PT_OK;
 }
 

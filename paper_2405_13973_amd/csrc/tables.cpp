@@ -146,4 +146,25 @@ int build_operator_tables(int p, double *m2m, double *l2l, double *m2l)
     return 0;
 }
 
+void build_recurrence_table(int p, double *rec)
+{
+    const int Q = kq(p);
+    for (int i = 0; i < kRecFields * Q; ++i) rec[i] = 0.0;
+    for (int n = 0; n <= p; ++n)
+        for (int m = 0; m <= n; ++m) {
+            const int q = n * (n + 1) / 2 + m;
+            if (n == m) rec[q] = m == 0 ? 1.0 : -std::sqrt((2.0 * m - 1.0) / (2.0 * m));
+            else if (n == m + 1) rec[q] = std::sqrt(2.0 * m + 1.0);
+            else {
+                rec[q] = (2.0 * n - 1.0) / std::sqrt((double)(n + m) * (n - m));
+                rec[Q + q] = std::sqrt((double)(n + m - 1) * (n - m - 1) / ((double)(n + m) * (n - m)));
+            }
+            if (n < p) {
+                rec[2 * Q + q] = std::sqrt((double)(n + 1 + m) * (n + 1 - m)) * (m > 0 ? 2.0 : 1.0);
+                rec[3 * Q + q] = std::sqrt((double)(n + m + 2) * (n + m + 1));
+                rec[4 * Q + q] = std::sqrt((double)(n - m + 2) * (n - m + 1));
+            }
+        }
+}
+
 }  // namespace pt

@@ -76,7 +76,7 @@ def load():
         "pt_read_state": [_vp, _dp, _dp, C.POINTER(C.c_int64), _dp, C.POINTER(C.c_int32)],
         "pt_debug_export_tree": [_vp, C.POINTER(C.c_int64)] + [_vp] * 13,
         "pt_ctx_set_timing": [_vp, C.c_int],
-        "pt_ctx_phase_times": [_vp, _dp],
+        "pt_ctx_phase_times": [_vp, _dp, C.POINTER(C.c_int64)],
         "pt_ctx_work_counts": [_vp, C.POINTER(C.c_int64)],
     }
     for name, args in sig.items():
@@ -141,10 +141,12 @@ class Context:
     def set_timing(self, on: bool):
         _check(load().pt_ctx_set_timing(self.h, 1 if on else 0))
 
-    def phase_times(self):
+    def phase_times(self, with_count=False):
+        """Mean per-evaluation phase times (ms) since set_timing(True)."""
         ms = np.zeros(6)
-        _check(load().pt_ctx_phase_times(self.h, _ptr(ms)))
-        return ms
+        cnt = C.c_int64()
+        _check(load().pt_ctx_phase_times(self.h, _ptr(ms), C.byref(cnt)))
+        return (ms, cnt.value) if with_count else ms
 
     def work_counts(self):
         c = np.zeros(6, np.int64)
