@@ -32,6 +32,24 @@ METRIC = "ion-steps/s at N=1e5, RMS rel force error≤1e-6 vs FP64; p99 latency 
 PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "valu_fp32": 157.3, "valu_fp64": 78.6}
 
 
+def measured_traffic(p, leaf, precision, n):
+    """HBM bytes per M2L launch from the committed rocprofv3 counter runs, or
+    None when the kernel source or the workload differs from the one profiled."""
+    import hashlib
+
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "m2l_traffic.json")))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    w = rec.get("workload", {})
+    if hashlib.sha256(src).hexdigest() != rec.get("sha256"):
+        return None
+    if (w.get("p"), w.get("leaf_size"), w.get("precision"), w.get("n_ions")) != (p, leaf, precision, n):
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -92,11 +110,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--leaf", type=int, default=32)
     ap.add_argument("--p0", type=int, default=10, help="first p tried when choosing p")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run one plain device copy of MIB MiB first (reference kernel for HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU sharding is a "
@@ -108,6 +128,15 @@ def main():
     assert torch.cuda.is_available(), "no HIP device visible"
     stream = torch.cuda.current_stream()
     sync = torch.cuda.synchronize
+
+    if a.copy_calibration:
+        src = torch.empty(a.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        sync()
+        dst.copy_(src)
+        sync()
+        log(f"  copy calibration: {a.copy_calibration} MiB read + {a.copy_calibration} MiB written")
+        del src, dst
 
     cr = inputs.config3(n=a.n)
     log(f"workload: {cr.n} ions, jittered lattice in ellipsoid (400,400,800) um")
@@ -135,7 +164,7 @@ def main():
     c.set_force("direct")
     ctx.set_timing(True)
     c.compute_forces()
-    dir_ms = ctx.phase_times()[4]
+    dir_ms = ctx.phase_times()[5]
     ctx.set_timing(False)
 
     main_r = results[a.precision]
@@ -167,12 +196,12 @@ def main():
         },
         "roofline": {
             "bound": "mfma", "kernel": "m2l", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None,
+            "frac": achieved / peak, "traffic": measured_traffic(p, a.leaf, a.precision, cr.n),
             "algorithmic": f"2 K^2 flops per M2L pair, K=(p+1)^2={K}, {int(main_r['wc'][2])} pairs per launch",
         },
         "details": {
             "force_evals_per_s": 1e3 / main_r["phases"][5],
-            "phase_ms": {k: float(v) for k, v in zip(["tree", "upward", "m2l", "l2l", "eval", "total"],
+            "phase_ms": {k: float(v) for k, v in zip(["tree", "upward", "m2l_kernel", "m2l_reduce_l2l", "eval", "total"],
                                                      main_r["phases"])},
             "direct_sum_ms": float(dir_ms),
             "boxes": int(main_r["wc"][0]), "leaves": int(main_r["wc"][1]), "m2l_pairs": int(main_r["wc"][2]),

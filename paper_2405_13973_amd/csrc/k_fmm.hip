@@ -152,7 +152,9 @@ constexpr int kXSlots = 32;  // slots per workgroup, at most
 // rows past Kp (PARTIAL row groups only) read an in-bounds address and are
 // replaced by zero, and a missing source reads X[zrow], an expansion row
 // kept at zero.
-template <typename T, int NRB, bool PARTIAL>
+// ROLE only names the kernel symbol (0 M2L, 1 M2M, 2 L2L) so that profiles
+// tell the three uses apart.
+template <typename T, int NRB, bool PARTIAL, int ROLE>
 __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *__restrict__ At,
                                                          const T *__restrict__ X, T *__restrict__ out)
 {
@@ -285,7 +287,7 @@ static int xlate_nrb(int Kp, int &nrowgrp)
     return ceil_div(blocks, nrowgrp);
 }
 
-template <typename T>
+template <typename T, int ROLE>
 static void launch_xlate(const XlateArgs &a, int grid, const T *At, const T *X, T *out, hipStream_t st)
 {
     int nrg;
@@ -293,8 +295,8 @@ static void launch_xlate(const XlateArgs &a, int grid, const T *At, const T *X, 
     const bool partial = nrb * 16 * nrg != a.Kp;
     switch (nrb * 2 + (partial ? 1 : 0)) {
 #define PT_XL(NB)                                                                       \
-    case 2 * NB: k_xlate<T, NB, false><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break; \
-    case 2 * NB + 1: k_xlate<T, NB, true><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break;
+    case 2 * NB: k_xlate<T, NB, false, ROLE><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break; \
+    case 2 * NB + 1: k_xlate<T, NB, true, ROLE><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break;
         PT_XL(1) PT_XL(2) PT_XL(3) PT_XL(4) PT_XL(5) PT_XL(6) PT_XL(7) PT_XL(8) PT_XL(9) PT_XL(10) PT_XL(11)
         PT_XL(12)
 #undef PT_XL
@@ -332,64 +334,76 @@ __global__ void k_m2l_reduce(BoxTable bt, int nbox, int Kp, int ngroup, const T 
     L[e] = acc;
 }
 
-// Far field (L2P) + near field (P2P) of every ion of a leaf, 64 threads per
-// leaf.  Sources are staged through LDS 64 at a time as offsets from the
-// target leaf's centre (one FP64 subtraction per source and leaf, then
-// rounded to T), so the pair loop reads only LDS.  Leaves of at most 32
-// ions get two threads per target, each taking half of every tile; the two
-// halves are added in a fixed order.  Each tile's contribution is summed
-// plainly and added to the running total with Kahan compensation.  Writes
-// the field per unit charge in batch order.
+// Near field (P2P) of one work item per 64-thread workgroup (grid-stride over
+// the items): up to 64 targets of a leaf against the sources of a run of its
+// near ranges.  Sources are staged through LDS 64 at a time as offsets from
+// the target leaf's centre (one FP64 subtraction per source and item, then
+// rounded to T), so the pair loop reads only LDS.  Items with at most 32
+// targets use two threads per target, each taking half of every tile; the
+// two halves are added in a fixed order.  Each tile's contribution is summed
+// plainly and added to the running total with Kahan compensation.  Partial
+// fields go to part[item][target][3].
 template <typename T>
-__global__ __launch_bounds__(64) void k_eval(BoxTable bt, const double *__restrict__ sp, int ntot, int p, int Kp,
-                                             const T *__restrict__ L, const T *__restrict__ rec,
-                                             const int2 *__restrict__ near, const int32_t *__restrict__ near_cnt,
-                                             int stride, const uint32_t *__restrict__ vals, int use_far,
-                                             double *__restrict__ E)
+struct Vec4;
+template <>
+struct Vec4<float> {
+    typedef float4 type;
+};
+template <>
+struct Vec4<double> {
+    typedef double4 type;
+};
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restrict__ sp, int ntot,
+                                            const int2 *__restrict__ near, int stride, const int4 *__restrict__ work,
+                                            int n_items, T *__restrict__ part)
 {
-    __shared__ T sx[64], sy[64], sz[64];
-    __shared__ int sj[64];
+    using V4 = typename Vec4<T>::type;
+    __shared__ V4 src[64];
     __shared__ T hx[32], hy[32], hz[32];
-    const int b = blockIdx.x;
-    if (!bt.leaf[b]) return;
-    const double4 g = bt.geo[b];
-    const double ih = 1.0 / g.w;
-    const T *Lb = L + (size_t)b * Kp;
-    const int2 *row = near + (size_t)b * stride;
-    const int nn = near_cnt[b];
-    const int i0 = bt.begin[b], i1 = bt.end[b];
-    const int split = (i1 - i0) <= 32 ? 2 : 1;
-    const int per = 64 / split;                 // targets per pass
-    const int ti = threadIdx.x % per, half = threadIdx.x / per;
-    for (int c0 = i0; c0 < i1; c0 += per) {
-        const int k = c0 + ti;
-        const bool tv = k < i1;
-        const double xd = tv ? sp[k] : g.x, yd = tv ? sp[ntot + k] : g.y, zd = tv ? sp[2 * ntot + k] : g.z;
-        const T xi = (T)(xd - g.x), yi = (T)(yd - g.y), zi = (T)(zd - g.z);
-        T ax = 0, ay = 0, az = 0, cx = 0, cy = 0, cz = 0;  // Kahan sums of tile partials
-        for (int r = 0; r < nn; ++r) {
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int4 w = work[it];
+        const int b = w.x;
+        const double4 g = bt.geo[b];
+        const int2 *row = near + (size_t)b * stride;
+        const int nt = min(64, bt.end[b] - w.y);
+        const int split = nt <= 32 ? 2 : 1;
+        const int per = 64 / split;
+        const int ti = threadIdx.x % per, half = threadIdx.x / per;
+        const int k = w.y + ti;
+        const bool tv = ti < nt;
+        const T xi = tv ? (T)(sp[k] - g.x) : T(0), yi = tv ? (T)(sp[ntot + k] - g.y) : T(0),
+                zi = tv ? (T)(sp[2 * ntot + k] - g.z) : T(0);
+        T ax = 0, ay = 0, az = 0, cx = 0, cy = 0, cz = 0;
+        for (int r = w.z; r < w.w; ++r) {
             const int2 rg = row[r];
             for (int base = rg.x; base < rg.y; base += 64) {
                 __syncthreads();
                 const int j = base + threadIdx.x;
                 if (j < rg.y) {
-                    sx[threadIdx.x] = (T)(sp[j] - g.x);
-                    sy[threadIdx.x] = (T)(sp[ntot + j] - g.y);
-                    sz[threadIdx.x] = (T)(sp[2 * ntot + j] - g.z);
-                    sj[threadIdx.x] = j;
+                    V4 v;
+                    v.x = (T)(sp[j] - g.x);
+                    v.y = (T)(sp[ntot + j] - g.y);
+                    v.z = (T)(sp[2 * ntot + j] - g.z);
+                    v.w = T(0);
+                    src[threadIdx.x] = v;
                 }
                 __syncthreads();
                 const int cnt = min(64, rg.y - base);
                 const int q0 = split == 2 ? half * 32 : 0, q1 = split == 2 ? min(cnt, q0 + 32) : cnt;
                 T px = 0, py = 0, pz = 0;
                 for (int q = q0; q < q1; ++q) {
-                    const T dx = xi - sx[q], dy = yi - sy[q], dz = zi - sz[q];
+                    const V4 v = src[q];
+                    const T dx = xi - v.x, dy = yi - v.y, dz = zi - v.z;
                     const T r2 = dx * dx + dy * dy + dz * dz;
-                    const T rinv = (r2 > T(0) && sj[q] != k) ? rsqrt(r2) : T(0);
-                    const T w = rinv * rinv * rinv;
-                    px += dx * w;
-                    py += dy * w;
-                    pz += dz * w;
+                    // r2 == 0: the target itself (offsets are bit-identical) or a
+                    // coincident ion, both contribute nothing
+                    const T rinv = r2 > T(0) ? rsqrt(r2) : T(0);
+                    const T ww = rinv * rinv * rinv;
+                    px += dx * ww;
+                    py += dy * ww;
+                    pz += dz * ww;
                 }
                 T y_ = px - cx, t_ = ax + y_;
                 cx = (t_ - ax) - y_;
@@ -412,28 +426,53 @@ __global__ __launch_bounds__(64) void k_eval(BoxTable bt, const double *__restri
                 hz[ti] = az;
             }
             __syncthreads();
+            if (half == 0) {
+                ax += hx[ti];
+                ay += hy[ti];
+                az += hz[ti];
+            }
         }
         if (half == 0 && tv) {
-            double fx = 0.0, fy = 0.0, fz = 0.0;
-            if (use_far) {
-                T ex, ey, ez;
-                l2p_field<T>(p, Lb, rec, (T)((xd - g.x) * ih), (T)((yd - g.y) * ih), (T)((zd - g.z) * ih), ex, ey,
-                             ez);
-                fx = (double)ex * ih * ih;
-                fy = (double)ey * ih * ih;
-                fz = (double)ez * ih * ih;
-            }
-            double nx = (double)ax, ny = (double)ay, nz = (double)az;
-            if (split == 2) {
-                nx += (double)hx[ti];
-                ny += (double)hy[ti];
-                nz += (double)hz[ti];
-            }
-            const int gi = (int)vals[k];
-            E[gi] = fx + nx;
-            E[ntot + gi] = fy + ny;
-            E[2 * ntot + gi] = fz + nz;
+            T *dst = part + ((size_t)it * 64 + ti) * 3;
+            dst[0] = ax;
+            dst[1] = ay;
+            dst[2] = az;
         }
+    }
+}
+
+// Far field (L2P) of every ion of a leaf plus its near-field item partials,
+// added in item order.  Writes the field per unit charge in batch order.
+template <typename T>
+__global__ __launch_bounds__(64) void k_far(BoxTable bt, const double *__restrict__ sp, int ntot, int p, int Kp,
+                                            const T *__restrict__ L, const T *__restrict__ rec,
+                                            const uint32_t *__restrict__ item_off,
+                                            const int32_t *__restrict__ src_items, const T *__restrict__ part,
+                                            const uint32_t *__restrict__ vals, double *__restrict__ E)
+{
+    const int b = blockIdx.x;
+    if (!bt.leaf[b]) return;
+    const double4 g = bt.geo[b];
+    const double ih = 1.0 / g.w;
+    const T *Lb = L + (size_t)b * Kp;
+    const int si = src_items[b];
+    const uint32_t base = item_off[b];
+    for (int k = bt.begin[b] + threadIdx.x; k < bt.end[b]; k += 64) {
+        const int tl = k - bt.begin[b];
+        const double xd = sp[k], yd = sp[ntot + k], zd = sp[2 * ntot + k];
+        T ex, ey, ez;
+        l2p_field<T>(p, Lb, rec, (T)((xd - g.x) * ih), (T)((yd - g.y) * ih), (T)((zd - g.z) * ih), ex, ey, ez);
+        double fx = (double)ex * ih * ih, fy = (double)ey * ih * ih, fz = (double)ez * ih * ih;
+        const T *pp = part + ((size_t)(base + (tl >> 6) * si) * 64 + (tl & 63)) * 3;
+        for (int j = 0; j < si; ++j, pp += 64 * 3) {
+            fx += (double)pp[0];
+            fy += (double)pp[1];
+            fz += (double)pp[2];
+        }
+        const int gi = (int)vals[k];
+        E[gi] = fx;
+        E[ntot + gi] = fy;
+        E[2 * ntot + gi] = fz;
     }
 }
 
@@ -467,7 +506,8 @@ static void launch_level_xlate(const BoxTable &bt, int Kp, int nbox, int b0, int
     a.srctab = srctab;
     a.src_stride = 8;
     a.mode = 0;
-    launch_xlate<T>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, st);
+    if (mode == 1) launch_xlate<T, 1>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, st);
+    else launch_xlate<T, 2>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, st);
     const size_t tot = (size_t)n * Kp;
     k_xlate_reduce<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(b0, n, Kp, nbox, a.ngroup, mode, bt.leaf, part,
                                                                         X);
@@ -488,32 +528,42 @@ void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const 
     }
 }
 
-template <typename T>
-void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t *vtab, const int2 *slots,
-                const T *m2l_pad, const T *M, T *L, int32_t *cnt, int32_t *list, T *part, int ngroup, hipStream_t st)
+void launch_m2l_bucket(const BoxTable &bt, int nbox, int32_t *cnt, int32_t *list, hipStream_t st)
 {
-    const int Kp = kpad(p), nbox = hs.nbox;
     if (nbox <= 0) return;
     k_zero_i32<<<1, 64, 0, st>>>(cnt, 8);
     k_m2l_bucket<<<ceil_div(nbox, 256), 256, 0, st>>>(bt, nbox, cnt, list);
+}
+
+template <typename T>
+void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t *vtab, const int2 *slots,
+                const T *m2l_pad, const T *M, const int32_t *cnt, const int32_t *list, T *part, int ngroup,
+                hipStream_t st)
+{
+    const int Kp = kpad(p), nbox = hs.nbox;
     const int n2 = nbox - hs.level_start[2];  // targets: boxes of level >= 2
-    if (n2 > 0) {
-        XlateArgs a = xlate_base(Kp, nbox);
-        a.cnt = cnt;
-        a.list = list;
-        a.list_stride = nbox;
-        a.nbucket = 8;  // workgroup id mod 8 = parity = XCD under round-robin dispatch
-        a.ngroup = ngroup;
-        a.tile_stride = std::max(1, ceil_div(n2, 8 * kM2LCols));
-        a.slots = slots;
-        a.nslot = 189;
-        a.srctab = vtab;
-        a.src_stride = kWin;
-        a.mode = 0;
-        launch_xlate<T>(a, 8 * a.tile_stride * ngroup * a.nrowgrp, m2l_pad, M, part, st);
-    }
+    if (nbox <= 0 || n2 <= 0) return;
+    XlateArgs a = xlate_base(Kp, nbox);
+    a.cnt = cnt;
+    a.list = list;
+    a.list_stride = nbox;
+    a.nbucket = 8;  // workgroup id mod 8 = parity = XCD under round-robin dispatch
+    a.ngroup = ngroup;
+    a.tile_stride = std::max(1, ceil_div(n2, 8 * kM2LCols));
+    a.slots = slots;
+    a.nslot = 189;
+    a.srctab = vtab;
+    a.src_stride = kWin;
+    a.mode = 0;
+    launch_xlate<T, 0>(a, 8 * a.tile_stride * ngroup * a.nrowgrp, m2l_pad, M, part, st);
+}
+
+template <typename T>
+void launch_m2l_reduce(const BoxTable &bt, int p, int nbox, const T *part, int ngroup, T *L, hipStream_t st)
+{
+    const int Kp = kpad(p);
     const size_t tot = (size_t)nbox * Kp;
-    k_m2l_reduce<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(bt, nbox, Kp, ngroup, part, L);
+    if (tot) k_m2l_reduce<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(bt, nbox, Kp, ngroup, part, L);
 }
 
 int m2l_groups(int n2)
@@ -540,11 +590,12 @@ void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *
 
 template <typename T>
 void launch_eval(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
-                 const int2 *near, const int32_t *near_cnt, int stride, const uint32_t *vals, int use_far, double *E,
-                 hipStream_t st)
+                 const int2 *near, int stride, const int4 *work, int n_items, const uint32_t *item_off,
+                 const int32_t *src_items, T *part, const uint32_t *vals, double *E, hipStream_t st)
 {
-    if (nbox > 0)
-        k_eval<T><<<nbox, 64, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, near, near_cnt, stride, vals, use_far, E);
+    if (n_items > 0)
+        k_p2p<T><<<std::min(n_items, 16384), 64, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part);
+    if (nbox > 0) k_far<T><<<nbox, 64, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E);
 }
 
 template void launch_upward<double>(const BoxTable &, const double *, int, int, const TreeSummary &, const double *,
@@ -552,18 +603,22 @@ template void launch_upward<double>(const BoxTable &, const double *, int, int, 
 template void launch_upward<float>(const BoxTable &, const double *, int, int, const TreeSummary &, const float *,
                                    const int2 *, const int32_t *, const float *, float *, float *, hipStream_t);
 template void launch_m2l<double>(const BoxTable &, int, const TreeSummary &, const int32_t *, const int2 *,
-                                 const double *, const double *, double *, int32_t *, int32_t *, double *, int,
+                                 const double *, const double *, const int32_t *, const int32_t *, double *, int,
                                  hipStream_t);
 template void launch_m2l<float>(const BoxTable &, int, const TreeSummary &, const int32_t *, const int2 *,
-                                const float *, const float *, float *, int32_t *, int32_t *, float *, int,
+                                const float *, const float *, const int32_t *, const int32_t *, float *, int,
                                 hipStream_t);
+template void launch_m2l_reduce<double>(const BoxTable &, int, int, const double *, int, double *, hipStream_t);
+template void launch_m2l_reduce<float>(const BoxTable &, int, int, const float *, int, float *, hipStream_t);
 template void launch_downward<double>(const BoxTable &, int, const TreeSummary &, const double *, const int2 *,
                                       const int32_t *, double *, double *, hipStream_t);
 template void launch_downward<float>(const BoxTable &, int, const TreeSummary &, const float *, const int2 *,
                                      const int32_t *, float *, float *, hipStream_t);
 template void launch_eval<double>(const BoxTable &, const double *, int, int, int, const double *, const double *,
-                                  const int2 *, const int32_t *, int, const uint32_t *, int, double *, hipStream_t);
+                                  const int2 *, int, const int4 *, int, const uint32_t *, const int32_t *, double *,
+                                  const uint32_t *, double *, hipStream_t);
 template void launch_eval<float>(const BoxTable &, const double *, int, int, int, const float *, const float *,
-                                 const int2 *, const int32_t *, int, const uint32_t *, int, double *, hipStream_t);
+                                 const int2 *, int, const int4 *, int, const uint32_t *, const int32_t *, float *,
+                                 const uint32_t *, double *, hipStream_t);
 
 }  // namespace pt

@@ -417,15 +417,35 @@ __global__ void k_vlist(BoxTable bt, const TreeSummary *__restrict__ sum, const 
     if (cnt) atomicAdd(counter, (unsigned long long)cnt);
 }
 
-// Near lists of the leaves: ion ranges, stride entries per box.
+// Near lists of the leaves: ion ranges, stride entries per box.  The near
+// field of a leaf is then cut into work items of at most kP2PChunk sources
+// (cut at range boundaries) times chunks of 64 targets, so that no single
+// workgroup carries a coarse boundary leaf with thousands of near sources.
+__device__ inline int p2p_src_items(const int2 *row, int cnt)
+{
+    int items = 0, acc = 0;
+    for (int r = 0; r < cnt; ++r) {
+        const int len = row[r].y - row[r].x;
+        if (acc > 0 && acc + len > kP2PChunk) {
+            ++items;
+            acc = 0;
+        }
+        acc += len;
+    }
+    return items + (acc > 0 ? 1 : 0);
+}
+
 __global__ void k_nearlist(BoxTable bt, const TreeSummary *__restrict__ sum, const int32_t *__restrict__ coll,
                            int stride, int2 *__restrict__ near, int32_t *__restrict__ near_cnt,
+                           uint32_t *__restrict__ items, int32_t *__restrict__ src_items,
                            unsigned long long *__restrict__ pair_counter)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= sum->nbox) return;
     if (!bt.leaf[b]) {
         near_cnt[b] = 0;
+        items[b] = 0;
+        src_items[b] = 0;
         return;
     }
     int2 *row = near + (size_t)b * stride;
@@ -447,7 +467,37 @@ __global__ void k_nearlist(BoxTable bt, const TreeSummary *__restrict__ sum, con
         }
     near_cnt[b] = cnt;
     const long long nt = bt.end[b] - bt.begin[b];
+    const int si = p2p_src_items(row, cnt);
+    src_items[b] = si;
+    items[b] = (uint32_t)(si * ((nt + 63) / 64));
     atomicAdd(pair_counter, (unsigned long long)(nt * srcs - nt));
+}
+
+// Work items {leaf, first target, first range, end range} at the scanned offsets.
+__global__ void k_p2p_items(BoxTable bt, const TreeSummary *__restrict__ sum, const int2 *__restrict__ near,
+                            const int32_t *__restrict__ near_cnt, int stride, const uint32_t *__restrict__ item_off,
+                            const int32_t *__restrict__ src_items, int4 *__restrict__ work)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= sum->nbox || !bt.leaf[b]) return;
+    const int2 *row = near + (size_t)b * stride;
+    const int cnt = near_cnt[b], si = src_items[b];
+    const int nt = bt.end[b] - bt.begin[b];
+    uint32_t w = item_off[b];
+    for (int t0 = 0; t0 < nt; t0 += 64) {
+        int r0 = 0, acc = 0;
+        for (int r = 0; r < cnt; ++r) {
+            const int len = row[r].y - row[r].x;
+            if (acc > 0 && acc + len > kP2PChunk) {
+                work[w++] = make_int4(b, bt.begin[b] + t0, r0, r);
+                r0 = r;
+                acc = 0;
+            }
+            acc += len;
+        }
+        if (acc > 0) work[w++] = make_int4(b, bt.begin[b] + t0, r0, cnt);
+    }
+    (void)si;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -502,12 +552,21 @@ void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64
 
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
                   int2 *near, int32_t *near_cnt, unsigned long long *counters, int32_t *child_oct,
-                  int32_t *parent_oct, hipStream_t st)
+                  int32_t *parent_oct, uint32_t *item_off, int32_t *src_items, uint32_t *scan_part,
+                  uint32_t *n_items, hipStream_t st)
 {
     k_oct_tables<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, child_oct, parent_oct);
     k_colleagues<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll);
     k_vlist<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll, vtab, counters);
-    k_nearlist<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll, stride, near, near_cnt, counters + 1);
+    k_nearlist<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll, stride, near, near_cnt, item_off, src_items,
+                                                    counters + 1);
+    launch_scan(item_off, nbox, scan_part, n_items, st);
+}
+
+void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, const int2 *near, const int32_t *near_cnt,
+                      int stride, const uint32_t *item_off, const int32_t *src_items, int4 *work, hipStream_t st)
+{
+    k_p2p_items<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, near, near_cnt, stride, item_off, src_items, work);
 }
 
 }  // namespace pt

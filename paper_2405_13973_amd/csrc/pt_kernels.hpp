@@ -43,9 +43,15 @@ void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int
 void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
                        const uint32_t *rep_mask, const uint32_t *scanned, const BoxTable &bt, const TreeSummary *sum,
                        int nbox, hipStream_t st);
+// Also counts the near-field work items {leaf, first target, range begin,
+// range end}: item_off (nbox, scanned in place to offsets), src_items (nbox),
+// n_items (device total).  launch_p2p_items then writes them into work.
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
                   int2 *near, int32_t *near_cnt, unsigned long long *counters, int32_t *child_oct,
-                  int32_t *parent_oct, hipStream_t st);
+                  int32_t *parent_oct, uint32_t *item_off, int32_t *src_items, uint32_t *scan_part,
+                  uint32_t *n_items, hipStream_t st);
+void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, const int2 *near, const int32_t *near_cnt,
+                      int stride, const uint32_t *item_off, const int32_t *src_items, int4 *work, hipStream_t st);
 
 // k_fmm.hip
 // rec: recurrence table (fmm_math.hpp), kRecFields x kq(p) entries.
@@ -57,16 +63,22 @@ void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const 
 // m2l_pad: 343 operators, each Kp x Kp column-major (A[j][i] = T[i][j]), zero-padded;
 // slots: per parity the 189 non-touching window slots {slot, operator index};
 // cnt: 8 ints, list: 8 x nbox ints, part: ngroup x nbox x Kp of workspace.
+void launch_m2l_bucket(const BoxTable &bt, int nbox, int32_t *cnt, int32_t *list, hipStream_t st);
 template <typename T>
 void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t *vtab, const int2 *slots,
-                const T *m2l_pad, const T *M, T *L, int32_t *cnt, int32_t *list, T *part, int ngroup, hipStream_t st);
+                const T *m2l_pad, const T *M, const int32_t *cnt, const int32_t *list, T *part, int ngroup,
+                hipStream_t st);
+template <typename T>
+void launch_m2l_reduce(const BoxTable &bt, int p, int nbox, const T *part, int ngroup, T *L, hipStream_t st);
 int m2l_groups(int n2);  // slot groups of M2L (partial-sum buffer: groups x nbox x Kp; M2M/L2L use <= 8)
 template <typename T>
 void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_pad, const int2 *oct_slots,
                      const int32_t *parent_oct, T *L, T *part, hipStream_t st);
+// Near field over the work items into part (item x 64 x 3), then far field +
+// item partials per ion into E (batch order).
 template <typename T>
 void launch_eval(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
-                 const int2 *near, const int32_t *near_cnt, int stride, const uint32_t *vals, int use_far, double *E,
-                 hipStream_t st);
+                 const int2 *near, int stride, const int4 *work, int n_items, const uint32_t *item_off,
+                 const int32_t *src_items, T *part, const uint32_t *vals, double *E, hipStream_t st);
 
 }  // namespace pt

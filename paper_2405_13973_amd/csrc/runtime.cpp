@@ -456,10 +456,24 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ensure_tables(ctx, p));
     const BoxTable bt = box_table(ctx);
     launch_tree_build(b.d_desc, roots, k0, ntot, s, rep, bcnt, bt, dsum, nbox, st);
-    int32_t *child_oct, *parent_oct;
+    int32_t *child_oct, *parent_oct, *src_items;
+    uint32_t *item_off;
     PT_TRY(ws_get(ctx, "child_oct", sizeof(int32_t) * 8 * (size_t)nbox, &child_oct));
     PT_TRY(ws_get(ctx, "parent_oct", sizeof(int32_t) * 8 * (size_t)nbox, &parent_oct));
-    launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, counters, child_oct, parent_oct, st);
+    PT_TRY(ws_get(ctx, "item_off", sizeof(uint32_t) * (size_t)nbox, &item_off));
+    PT_TRY(ws_get(ctx, "src_items", sizeof(int32_t) * (size_t)nbox, &src_items));
+    PT_TRY(ws_get(ctx, "scan_part", sizeof(uint32_t) * (scan_partials(std::max(scan_n, nbox)) + 1), &scan_part));
+    launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, counters, child_oct, parent_oct, item_off,
+                 src_items, scan_part, total + 1, st);
+    // near-field work items: their number sizes the item and partial buffers
+    PT_HIP(hipMemcpyAsync(ctx->h_counters, total + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    PT_HIP(hipStreamSynchronize(st));
+    const int n_items = (int)*(uint32_t *)ctx->h_counters;
+    int4 *work;
+    void *ppart;
+    PT_TRY(ws_get(ctx, "p2p_work", sizeof(int4) * (size_t)std::max(1, n_items), &work));
+    PT_TRY(ws_get(ctx, "p2p_part", esz * 64 * 3 * (size_t)std::max(1, n_items), (char **)&ppart));
+    launch_p2p_items(bt, dsum, nbox, near, near_cnt, stride, item_off, src_items, work, st);
     int32_t *m2l_cnt, *m2l_list;
     void *m2l_part;
     const int ngroup = m2l_groups(nbox - hs.level_start[2]);
@@ -470,28 +484,26 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     const Tables &tb = ctx->tables;
     launch_zero_u64((uint64_t *)((char *)M + esz * Kp * (size_t)nbox), (int)(esz * Kp / 8), st);
     launch_zero_u64((uint64_t *)((char *)L + esz * Kp * (size_t)nbox), (int)(esz * Kp / 8), st);
-    if (fp.precision == 1) {
-        launch_upward<float>(bt, sp, ntot, p, hs, tb.m2m_f, tb.oct_slots, child_oct, tb.rec_f, (float *)M,
-                             (float *)m2l_part, st);
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        const bool f = sizeof(T) == sizeof(float);
+        const T *m2m = f ? (const T *)tb.m2m_f : (const T *)tb.m2m_d;
+        const T *m2l = f ? (const T *)tb.m2l_f : (const T *)tb.m2l_d;
+        const T *l2l = f ? (const T *)tb.l2l_f : (const T *)tb.l2l_d;
+        const T *rec = f ? (const T *)tb.rec_f : (const T *)tb.rec_d;
+        launch_upward<T>(bt, sp, ntot, p, hs, m2m, tb.oct_slots, child_oct, rec, (T *)M, (T *)m2l_part, st);
+        launch_m2l_bucket(bt, nbox, m2l_cnt, m2l_list, st);
         mark(ctx, 2);
-        launch_m2l<float>(bt, p, hs, vtab, tb.slots, tb.m2l_f, (const float *)M, (float *)L, m2l_cnt, m2l_list,
-                          (float *)m2l_part, ngroup, st);
+        launch_m2l<T>(bt, p, hs, vtab, tb.slots, m2l, (const T *)M, m2l_cnt, m2l_list, (T *)m2l_part, ngroup, st);
         mark(ctx, 3);
-        launch_downward<float>(bt, p, hs, tb.l2l_f, tb.oct_slots, parent_oct, (float *)L, (float *)m2l_part, st);
+        launch_m2l_reduce<T>(bt, p, nbox, (const T *)m2l_part, ngroup, (T *)L, st);
+        launch_downward<T>(bt, p, hs, l2l, tb.oct_slots, parent_oct, (T *)L, (T *)m2l_part, st);
         mark(ctx, 4);
-        launch_eval<float>(bt, sp, ntot, p, nbox, (const float *)L, tb.rec_f, near, near_cnt, stride, v0, 1, E, st);
-    } else {
-        launch_upward<double>(bt, sp, ntot, p, hs, tb.m2m_d, tb.oct_slots, child_oct, tb.rec_d, (double *)M,
-                              (double *)m2l_part, st);
-        mark(ctx, 2);
-        launch_m2l<double>(bt, p, hs, vtab, tb.slots, tb.m2l_d, (const double *)M, (double *)L, m2l_cnt, m2l_list,
-                           (double *)m2l_part, ngroup, st);
-        mark(ctx, 3);
-        launch_downward<double>(bt, p, hs, tb.l2l_d, tb.oct_slots, parent_oct, (double *)L, (double *)m2l_part, st);
-        mark(ctx, 4);
-        launch_eval<double>(bt, sp, ntot, p, nbox, (const double *)L, tb.rec_d, near, near_cnt, stride, v0, 1, E,
-                            st);
-    }
+        launch_eval<T>(bt, sp, ntot, p, nbox, (const T *)L, rec, near, stride, work, n_items, item_off, src_items,
+                       (T *)ppart, v0, E, st);
+    };
+    if (fp.precision == 1) run(float(0));
+    else run(double(0));
     mark(ctx, 5);
     ctx->timing_pending = ctx->timing;
     ctx->last_sum = hs;
