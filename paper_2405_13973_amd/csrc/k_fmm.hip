@@ -499,7 +499,7 @@ static void launch_level_xlate(const BoxTable &bt, int Kp, int nbox, int b0, int
     XlateArgs a = xlate_base(Kp, nbox);
     a.b0 = b0;
     a.nrange = n;
-    a.ngroup = std::max(1, std::min(8, ceil_div(512, tiles * a.nrowgrp)));
+    a.ngroup = 8;  // one octant slot per group: summation order independent of the batch
     a.tile_stride = tiles;
     a.slots = oct_slots;
     a.nslot = 8;
@@ -566,12 +566,11 @@ void launch_m2l_reduce(const BoxTable &bt, int p, int nbox, const T *part, int n
     if (tot) k_m2l_reduce<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(bt, nbox, Kp, ngroup, part, L);
 }
 
-int m2l_groups(int n2)
+int m2l_groups(int)
 {
-    // enough workgroups to fill 256 CUs several times over, between 6 (at most
-    // kXSlots of the 189 slots per workgroup) and 16 groups
-    const int tiles = std::max(1, ceil_div(n2, kM2LCols));
-    return std::max(ceil_div(189, kXSlots), std::min(16, ceil_div(1024, tiles)));
+    // A constant: the grouping fixes the order in which a target's slots are
+    // summed, so it must not depend on the batch (12 groups of <= 16 slots).
+    return 12;
 }
 
 template <typename T>
