@@ -104,6 +104,85 @@ def cpu_baseline(cr, p, leaf, F_dir_gpu):
                       f"{el:.1f} s wall; direct sum checked on 48 sampled ions (max err/rms {dev:.1e})"}
 
 
+def bench_ensemble(a, ctx, sync):
+    """Batched ensemble: independent crystals stepped together, one launch per
+    phase per step for all of them."""
+    crs = inputs.ensemble(count=a.crystals, seed=4)
+    ntot = sum(c.n for c in crs)
+    log(f"ensemble: {len(crs)} crystals, {ntot} ions (N {min(c.n for c in crs)}..{max(c.n for c in crs)})")
+    cs = []
+    for cr in crs:
+        c = ctx.crystal(cr.pos, cr.vel, cr.charge, cr.mass, cr.seed)
+        c.set_trap(B=cr.B, omega_z=cr.omega_z, dt=cr.dt)
+        c.set_laser(cr.photon_mean)
+        cs.append(c)
+    # accuracy of the chosen p on the largest crystals, against the FP64 direct sum
+    errs = []
+    for c in sorted(cs, key=lambda c: -c.n)[:3]:
+        c.set_force("direct")
+        F_dir = c.compute_forces()
+        c.set_force("fmm", a.p, a.leaf, a.precision)
+        errs.append(rms_rel(c.compute_forces(), F_dir))
+    for c in cs:
+        c.set_force("fmm", a.p, a.leaf, a.precision)
+    native.step_batch(cs, [a.warmup] * len(cs))
+    sync()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    native.step_batch(cs, [a.steps] * len(cs))
+    sync()
+    el = time.perf_counter() - t0
+    phases = ctx.phase_times()
+    ctx.set_timing(False)
+    value = ntot * a.steps / el
+    log(f"  {a.steps} batched steps in {el * 1e3:.1f} ms -> {value:.4g} ion-steps/s; max rms err {max(errs):.2e}")
+    return {
+        "metric": "ensemble ion-steps/s (256 crystals, N log-uniform 100..20000, one launch per phase per step)",
+        "value": value, "unit": "ion-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": el * 1e3 / a.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if a.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": f"{len(crs)} crystals, {ntot} ions, spheres at 1000 ions/(100 um)^3, B~U[2,5] T, "
+                               f"f_z~U[1,2] MHz, photon mean~U[0,0.05], FMM p={a.p} leaf {a.leaf} ({a.precision})",
+                   "crystals": len(crs), "ions": ntot, "p": a.p, "leaf_size": a.leaf,
+                   "max_rms_rel_force_err_largest3": max(errs)},
+        "details": {"phase_ms": {k: float(v) for k, v in zip(
+            ["tree", "upward", "m2l_kernel", "m2l_reduce_l2l", "eval", "total"], phases)}},
+    }
+
+
+def bench_serving(a, ctx, sync):
+    """Serving stream: Poisson arrivals, continuous batching, admission by HBM footprint."""
+    from paper_2405_13973_amd import serving
+
+    reqs = inputs.serving_stream(count=a.requests, rate_hz=50.0, seed=5)
+    offered = sum(r.crystal.n * r.steps for r in reqs) / max(r.arrival_s for r in reqs)
+    log(f"serving: {len(reqs)} requests over {max(r.arrival_s for r in reqs):.1f} s, offered "
+        f"{offered:.3g} ion-steps/s")
+    srv = serving.Server(ctx, native, budget_bytes=a.budget_gb << 30, precision=a.precision, p=a.p, leaf=a.leaf,
+                         chunk=a.chunk)
+    rep = srv.run(reqs)
+    p50, p99 = rep.latency_percentiles()
+    log(f"  done in {rep.wall_s:.1f} s: {rep.ion_steps_per_s:.4g} ion-steps/s, latency p50 {p50:.2f} s "
+        f"p99 {p99:.2f} s, max resident {rep.max_resident}")
+    return {
+        "metric": "serving: aggregate ion-steps/s with p50/p99 request latency (Poisson 50/s, N 200..50000, "
+                  "K 100..2000)",
+        "value": rep.ion_steps_per_s, "unit": "ion-steps/s", "n_gpus": 1, "steps": None, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if a.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} requests, Poisson arrivals 50/s, N log-uniform [200, 50000], "
+                               f"K ~ U{{100..2000}}, photon mean 0.01, FMM p={a.p} leaf {a.leaf} ({a.precision}), "
+                               f"tick {a.chunk} steps, budget {a.budget_gb} GiB",
+                   "requests": len(reqs)},
+        "latency_s": {"p50": p50, "p99": p99},
+        "details": {"offered_ion_steps_per_s": offered, "achieved_ion_steps_per_s": rep.ion_steps_per_s,
+                    "wall_s": rep.wall_s, "max_resident": rep.max_resident,
+                    "max_resident_bytes": rep.max_resident_bytes,
+                    "note": "offered load above achieved: p99 is queue-dominated"
+                    if offered > rep.ion_steps_per_s else "offered load below achieved"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +194,13 @@ def main():
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--workload", choices=["config3", "ensemble", "serving"], default="config3",
+                    help="config3: 1e5-ion crystal (default); ensemble: 256 crystals batched; serving: request stream")
+    ap.add_argument("--p", type=int, default=12, help="expansion degree for the ensemble / serving workloads")
+    ap.add_argument("--crystals", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--chunk", type=int, default=50, help="serving: steps per tick")
+    ap.add_argument("--budget-gb", type=int, default=64, help="serving: HBM budget for resident crystals")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB first (reference kernel for HBM byte counters)")
     a = ap.parse_args()
@@ -137,6 +223,13 @@ def main():
         sync()
         log(f"  copy calibration: {a.copy_calibration} MiB read + {a.copy_calibration} MiB written")
         del src, dst
+
+    if a.workload != "config3":
+        ctx = native.Context(0, hbm_budget=(a.budget_gb << 30) + (4 << 30), stream=stream.cuda_stream)
+        out = bench_ensemble(a, ctx, sync) if a.workload == "ensemble" else bench_serving(a, ctx, sync)
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
 
     cr = inputs.config3(n=a.n)
     log(f"workload: {cr.n} ions, jittered lattice in ellipsoid (400,400,800) um")

@@ -1,0 +1,155 @@
+"""Continuous-batching server for crystal-simulation requests.
+
+Requests (a crystal and a number of steps) arrive over time.  Each tick the
+server admits waiting requests while their estimated device footprint fits the
+budget, then advances every resident crystal by up to `chunk` steps in one
+pt_step_batch call -- every phase of a step is one launch for all resident
+crystals, whatever their sizes -- and retires the finished ones.  A request's
+state stays in HBM from admission to completion.  Results do not depend on
+which other requests share a tick (every kernel is batch invariant), so a
+request run alone or in the mix ends in the same state, bit for bit.
+
+The stepping backend is the C ABI binding (`native`); a stand-in with the
+same methods can be passed for host-only tests of the scheduling logic.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+# Device bytes per ion held while a crystal is resident: its state (52 B) plus
+# its share of the batch workspace (keys, sorted positions, field, boxes, lists
+# and expansions; about 350 B per ion at p = 11, leaf 32), rounded up.
+BYTES_PER_ION = 512
+BYTES_FIXED = 1 << 20
+
+
+def footprint(n_ions: int) -> int:
+    return BYTES_FIXED + BYTES_PER_ION * int(n_ions)
+
+
+@dataclasses.dataclass
+class Done:
+    index: int
+    n_ions: int
+    steps: int
+    arrival_s: float
+    admit_s: float
+    finish_s: float
+    pos: np.ndarray
+    vel: np.ndarray
+    photons: np.ndarray
+
+    @property
+    def latency_s(self) -> float:
+        return self.finish_s - self.arrival_s
+
+
+@dataclasses.dataclass
+class Report:
+    done: list
+    wall_s: float
+    ion_steps: int
+    max_resident: int
+    max_resident_bytes: int
+
+    def latency_percentiles(self):
+        lat = np.array([d.latency_s for d in self.done])
+        return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+    @property
+    def ion_steps_per_s(self) -> float:
+        return self.ion_steps / self.wall_s if self.wall_s > 0 else 0.0
+
+
+class Server:
+    def __init__(self, ctx, native_mod, budget_bytes: int, precision: str = "mixed", p: int = 11, leaf: int = 32,
+                 chunk: int = 50, clock=time.perf_counter, sleep=time.sleep):
+        self.ctx, self.native = ctx, native_mod
+        self.budget = int(budget_bytes)
+        self.force = ("fmm", p, leaf, precision)
+        self.chunk = int(chunk)
+        self.clock, self.sleep = clock, sleep
+
+    def _admit(self, req):
+        cr = req.crystal
+        c = self.ctx.crystal(cr.pos, cr.vel, cr.charge, cr.mass, cr.seed)
+        c.set_trap(B=cr.B, omega_z=cr.omega_z, delta=cr.delta, omega_r=cr.omega_r, dt=cr.dt)
+        c.set_laser(cr.photon_mean)
+        c.set_force(*self.force)
+        return c
+
+    def run(self, requests, time_scale: float = 1.0) -> Report:
+        """Serve `requests` (objects with arrival_s, crystal, steps) in real time;
+        arrival times are multiplied by time_scale."""
+        order = sorted(range(len(requests)), key=lambda i: requests[i].arrival_s)
+        pending = collections.deque(order)
+        waiting = collections.deque()
+        active = []  # [index, crystal, remaining, admit_s]
+        done = []
+        used = 0
+        ion_steps = 0
+        max_res = max_bytes = 0
+        t0 = self.clock()
+        while pending or waiting or active:
+            now = self.clock() - t0
+            while pending and requests[pending[0]].arrival_s * time_scale <= now:
+                waiting.append(pending.popleft())
+            while waiting:
+                i = waiting[0]
+                need = footprint(requests[i].crystal.n)
+                if used + need > self.budget and active:
+                    break  # wait for memory to free up
+                try:
+                    c = self._admit(requests[i])
+                except self.native.PTError as e:
+                    if e.code == self.native.PT_ENOMEM and active:
+                        break
+                    raise
+                waiting.popleft()
+                used += need
+                active.append([i, c, requests[i].steps, now])
+            max_res = max(max_res, len(active))
+            max_bytes = max(max_bytes, used)
+            if not active:
+                if pending:
+                    wait = requests[pending[0]].arrival_s * time_scale - (self.clock() - t0)
+                    if wait > 0:
+                        self.sleep(min(wait, 0.05))
+                continue
+            n = [min(a[2], self.chunk) for a in active]
+            self.native.step_batch([a[1] for a in active], n)
+            self.ctx.synchronize()
+            for a, k in zip(active, n):
+                a[2] -= k
+                ion_steps += k * a[1].n
+            still = []
+            for a in active:
+                if a[2] > 0:
+                    still.append(a)
+                    continue
+                st = a[1].read_state()
+                fin = self.clock() - t0
+                req = requests[a[0]]
+                done.append(Done(a[0], a[1].n, req.steps, req.arrival_s * time_scale, a[3], fin, st["pos"], st["vel"],
+                                 st["photons"]))
+                a[1].destroy()
+                used -= footprint(req.crystal.n)
+            active = still
+        return Report(done, self.clock() - t0, ion_steps, max_res, max_bytes)
+
+
+def run_alone(ctx, native_mod, req, precision="mixed", p=11, leaf=32):
+    """The same request stepped on its own (reference for the alone-vs-mix check)."""
+    cr = req.crystal
+    c = ctx.crystal(cr.pos, cr.vel, cr.charge, cr.mass, cr.seed)
+    c.set_trap(B=cr.B, omega_z=cr.omega_z, delta=cr.delta, omega_r=cr.omega_r, dt=cr.dt)
+    c.set_laser(cr.photon_mean)
+    c.set_force("fmm", p, leaf, precision)
+    c.step(req.steps)
+    st = c.read_state()
+    c.destroy()
+    return st
