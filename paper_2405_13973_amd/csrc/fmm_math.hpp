@@ -181,6 +181,25 @@ __host__ __device__ inline void p2m_terms(int p, const T *rec, T x, T y, T z, T 
     }
 }
 
+// Reflections of space act on the coefficients as diagonal +-1 matrices S:
+// z -> -z multiplies c_n^m by (-1)^(n+m); y -> -y conjugates (Im -> -Im);
+// x -> -x gives (-1)^m conj.  Hence the M2L operator of source offset
+// d = (dx, dy, dz) is T_d = S T_|d| S with S the reflections of the negative
+// components, and only the 56 operators of offsets with non-negative
+// components are stored.  refl_bits(i) packs, for storage index i, whether
+// the x (bit 0), y (bit 1), z (bit 2) reflection flips its sign; a mask of
+// reflections flips it iff popcount(mask & refl_bits) is odd.
+__host__ __device__ inline int refl_bits(int i)
+{
+    const int n = (int)sqrt((double)i + 0.5);
+    const int r = i - n * n;
+    const int m = (r + 1) >> 1;
+    const int im = (r > 0 && !(r & 1)) ? 1 : 0;
+    return ((m & 1) ^ im) | (im << 1) | (((n + m) & 1) << 2);
+}
+// index of the stored M2L operator for |offset| (each component 0..3)
+__host__ __device__ inline int m2l_base(int ax, int ay, int az) { return ax * 16 + ay * 4 + az; }
+
 // Host-only: recurrence table (kRecFields x kq(p) doubles), see above.
 void build_recurrence_table(int p, double *rec);
 

@@ -165,13 +165,15 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
     constexpr int kXA = KC * ROWS / NT;  // operator values staged per thread (exact)
     constexpr int kXB = KC * kM2LCols / NT;
     __shared__ T As[KC][ROWS];             // operator chunk, [k][row]
-    __shared__ T Bsh[KC][kM2LCols];        // source chunk, [k][target]
+    __shared__ T Bsh[kM2LCols][KC + 1];    // source chunk, [target][k] (padded: no bank conflicts)
     __shared__ int32_t tgt_s[kM2LCols];
     __shared__ int32_t src_s[kXSlots][kM2LCols];
     __shared__ int32_t act_s[kXSlots + 1];  // active slots (local index); act_s[kXSlots] = count
-    __shared__ int32_t op_s[kXSlots];       // operator index of each local slot
+    __shared__ int32_t op_s[kXSlots];       // operator index (+ 256 x reflection mask) of each local slot
+    __shared__ uint8_t cbits_s[kMaxKp];     // reflection sign bits of each coefficient
     const int Kp = a.Kp;
     const int zrow = a.nbox;  // all-zero expansion row
+    for (int i = threadIdx.x; i < Kp; i += 64 * kM2LWaves) cbits_s[i] = (uint8_t)refl_bits(i);
     const int lin = blockIdx.x;
     const int o = lin % a.nbucket;
     int rest = lin / a.nbucket;
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
     const int ns = s1 - s0;  // <= kXSlots (the launcher guarantees it)
     const int nchunk = Kp / KC;
     // per-thread staging map (fixed for the kernel)
-    int a_off[kXA], a_lds[kXA];
+    int a_off[kXA];
     bool a_ok[kXA];
 #pragma unroll
     for (int j = 0; j < kXA; ++j) {
@@ -194,7 +196,6 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
         const int kk = e / ROWS, r = e - kk * ROWS;
         a_ok[j] = !PARTIAL || row0 + r < Kp;
         a_off[j] = a_ok[j] ? kk * Kp + r : 0;
-        a_lds[j] = e;
     }
     const int b_t = tid / KC, b_k = tid - (tid / KC) * KC;  // kXB == 4: targets b_t + 16 j
     T ra[kXA], rb_[kXB];
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
         const int q = step / nchunk;
         const int sl = act_s[q];
         const int k0 = (step - q * nchunk) * KC;
-        const T *Ad = At + (size_t)op_s[sl] * Kp * Kp + (size_t)k0 * Kp + row0;
+        const T *Ad = At + (size_t)(op_s[sl] & 255) * Kp * Kp + (size_t)k0 * Kp + row0;
 #pragma unroll
         for (int j = 0; j < kXA; ++j) {
             const T v = Ad[a_off[j]];
@@ -242,19 +243,41 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
         typename MF::v4 acc[NRB];
 #pragma unroll
         for (int r = 0; r < NRB; ++r) acc[r] = typename MF::v4{0, 0, 0, 0};
+        // Reflected operators A = S T_base S: the column signs S go onto the
+        // staged sources; the row signs are carried by the accumulator, which
+        // holds S(cur) times the partial result and is re-signed only when
+        // the reflection mask changes from one slot to the next.
+        auto resign = [&](int flipmask) {
+#pragma unroll
+            for (int r = 0; r < NRB; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = row0 + r * 16 + MF::row(lane, q);
+                    if ((!PARTIAL || row < Kp) && (__popc(flipmask & cbits_s[row]) & 1)) acc[r][q] = -acc[r][q];
+                }
+        };
+        int cur = 0;
         if (nsteps > 0) load_step(0);
         for (int step = 0; step < nsteps; ++step) {
+            const int q = step / nchunk;
+            const int k0 = (step - q * nchunk) * KC;
+            const int mask = op_s[act_s[q]] >> 8;
             __syncthreads();  // the previous step is done reading As / Bsh
 #pragma unroll
-            for (int j = 0; j < kXA; ++j) (&As[0][0])[a_lds[j]] = ra[j];
+            for (int j = 0; j < kXA; ++j) (&As[0][0])[tid + NT * j] = ra[j];
+            const bool bneg = __popc(mask & cbits_s[k0 + b_k]) & 1;
 #pragma unroll
-            for (int j = 0; j < kXB; ++j) Bsh[b_k][b_t + 16 * j] = rb_[j];
+            for (int j = 0; j < kXB; ++j) Bsh[b_t + 16 * j][b_k] = bneg ? -rb_[j] : rb_[j];
+            if (mask != cur) {
+                resign(mask ^ cur);
+                cur = mask;
+            }
             __syncthreads();
             if (step + 1 < nsteps) load_step(step + 1);
 #pragma unroll
             for (int k4 = 0; k4 < KC; k4 += 4) {
                 const int kk = k4 + (lane >> 4);
-                const T bv = Bsh[kk][wave * 16 + (lane & 15)];
+                const T bv = Bsh[wave * 16 + (lane & 15)][kk];
                 T av[NRB];
 #pragma unroll
                 for (int r = 0; r < NRB; ++r) av[r] = As[kk][r * 16 + (lane & 15)];
@@ -262,6 +285,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
                 for (int r = 0; r < NRB; ++r) acc[r] = MF::op(av[r], bv, acc[r]);
             }
         }
+        if (cur) resign(cur);
         const int tg = tgt_s[wave * 16 + (lane & 15)];
         if (tg >= 0 && !(a.mode == 1 && a.skip[tg])) {
             T *dst = out + (a.mode == 0 ? ((size_t)g * a.nbox + tg) * Kp : (size_t)tg * Kp) + row0;

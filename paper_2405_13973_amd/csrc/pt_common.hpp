@@ -22,6 +22,7 @@ namespace pt {
 
 constexpr int kMaxLevel = 16;   // keys hold 16 bits per axis
 constexpr int kMaxP = 20;
+constexpr int kMaxKp = ((kMaxP + 1) * (kMaxP + 1) + 15) & ~15;
 constexpr int kWin = 216;       // 6x6x6 window of M2L source offsets per target box
 constexpr int kNeigh = 27;      // 3x3x3 colleague slots
 constexpr int kP2PChunk = 2048; // near-field sources per work item (items are cut at range boundaries)

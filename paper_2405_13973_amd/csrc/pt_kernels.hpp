@@ -60,8 +60,10 @@ void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, cons
 template <typename T>
 void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *m2m_pad,
                    const int2 *oct_slots, const int32_t *child_oct, const T *rec, T *M, T *part, hipStream_t st);
-// m2l_pad: 343 operators, each Kp x Kp column-major (A[j][i] = T[i][j]), zero-padded;
-// slots: per parity the 189 non-touching window slots {slot, operator index};
+// m2l_pad: 64 base operators (offsets with non-negative components, index
+// m2l_base), each Kp x Kp column-major (A[j][i] = T[i][j]), zero-padded;
+// slots: per parity the 189 non-touching window slots {slot, base operator +
+// 256 x reflection mask (bit 0: dx < 0, bit 1: dy < 0, bit 2: dz < 0)};
 // cnt: 8 ints, list: 8 x nbox ints, part: ngroup x nbox x Kp of workspace.
 void launch_m2l_bucket(const BoxTable &bt, int nbox, int32_t *cnt, int32_t *list, hipStream_t st);
 template <typename T>

@@ -196,9 +196,19 @@ static pt_status ensure_tables(pt_ctx *ctx, int p)
                 for (int j = 0; j < K; ++j) pad[(size_t)c * Kp * Kp + (size_t)j * Kp + i] = v[c * KK + (size_t)i * K + j];
         v.swap(pad);
     };
+    // M2L: only offsets with non-negative components are kept (64 slots,
+    // index m2l_base); the others follow by reflection signs in the kernel
+    std::vector<double> base((size_t)64 * KK, 0.0);
+    for (int ax = 0; ax <= 3; ++ax)
+        for (int ay = 0; ay <= 3; ++ay)
+            for (int az = 0; az <= 3; ++az)
+                std::copy(m2l.begin() + (size_t)((ax + 3) * 49 + (ay + 3) * 7 + (az + 3)) * KK,
+                          m2l.begin() + (size_t)((ax + 3) * 49 + (ay + 3) * 7 + (az + 3) + 1) * KK,
+                          base.begin() + (size_t)m2l_base(ax, ay, az) * KK);
+    m2l.swap(base);
     pad_cm(m2m, 8);
     pad_cm(l2l, 8);
-    pad_cm(m2l, 343);
+    pad_cm(m2l, 64);
     auto upload = [&](const std::vector<double> &v, double **dd, float **df) -> pt_status {
         PT_TRY(ctx_alloc(ctx, (void **)dd, v.size() * sizeof(double)));
         PT_HIP(hipMemcpy(*dd, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -213,15 +223,21 @@ static pt_status ensure_tables(pt_ctx *ctx, int p)
     std::vector<double> rec((size_t)kRecFields * kq(p));
     build_recurrence_table(p, rec.data());
     PT_TRY(upload(rec, &t.rec_d, &t.rec_f));
-    // the 189 non-touching slots of each parity's 6x6x6 window
+    // the 189 non-touching slots of each parity's 6x6x6 window as {window
+    // index, base operator + 256 x reflection mask}, ordered by mask (the
+    // kernel re-signs its accumulators when the mask changes)
     std::vector<int2> sl;
     for (int o = 0; o < 8; ++o) {
         const int cx = (o >> 2) & 1, cy = (o >> 1) & 1, cz = o & 1;
+        std::vector<int2> par;
         for (int w = 0; w < kWin; ++w) {
             const int dx = w / 36 - 2 - cx, dy = (w / 6) % 6 - 2 - cy, dz = w % 6 - 2 - cz;
             if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
-            sl.push_back(make_int2(w, (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)));
+            const int mask = (dx < 0 ? 1 : 0) | (dy < 0 ? 2 : 0) | (dz < 0 ? 4 : 0);
+            par.push_back(make_int2(w, m2l_base(std::abs(dx), std::abs(dy), std::abs(dz)) + 256 * mask));
         }
+        std::stable_sort(par.begin(), par.end(), [](int2 a, int2 b) { return a.y < b.y; });
+        sl.insert(sl.end(), par.begin(), par.end());
     }
     if (sl.size() != 8 * 189) {
         pt_set_error("window slot table has %zu entries", sl.size());
