@@ -360,13 +360,16 @@ __global__ void k_m2l_reduce(BoxTable bt, int nbox, int Kp, int ngroup, const T 
 
 // Near field (P2P) of one work item per 64-thread workgroup (grid-stride over
 // the items): up to 64 targets of a leaf against the sources of a run of its
-// near ranges.  Sources are staged through LDS 64 at a time as offsets from
-// the target leaf's centre (one FP64 subtraction per source and item, then
-// rounded to T), so the pair loop reads only LDS.  Items with at most 32
-// targets use two threads per target, each taking half of every tile; the
-// two halves are added in a fixed order.  Each tile's contribution is summed
-// plainly and added to the running total with Kahan compensation.  Partial
-// fields go to part[item][target][3].
+// near ranges.  The ranges are concatenated and staged through LDS
+// kP2PStage sources at a time, as offsets from the target leaf's centre (one
+// FP64 subtraction per source and item, then rounded to T), so the pair loop
+// reads only LDS and a barrier pair serves hundreds of sources rather than one
+// leaf.  An item with nt targets gives each target floor(64 / nt) threads
+// (phases), which take source blocks round robin; within a block sources are
+// summed plainly and each block is added to the phase's total with Kahan
+// compensation.  The phases of a target are then added in phase order.
+// Partial fields go to part[item][target][3].
+constexpr int kP2PStage = 512;
 template <typename T>
 struct Vec4;
 template <>
@@ -378,53 +381,111 @@ struct Vec4<double> {
     typedef double4 type;
 };
 
+// 1/sqrt(x) in the arithmetic type: the hardware reciprocal square root for
+// FP32 (1 ulp), the library routine for FP64.
+__device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsqrt_t(double x) { return rsqrt(x); }
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restrict__ sp, int ntot,
                                             const int2 *__restrict__ near, int stride, const int4 *__restrict__ work,
                                             int n_items, T *__restrict__ part)
 {
     using V4 = typename Vec4<T>::type;
-    __shared__ V4 src[64];
-    __shared__ T hx[32], hy[32], hz[32];
+    constexpr int kU = kP2PStage / 64;
+    __shared__ V4 src[kP2PStage];
+    __shared__ int pre_s[kNearMax + 1];  // prefix of the item's range lengths
+    __shared__ int beg_s[kNearMax];      // first ion of each range minus its prefix
+    __shared__ T hx[64], hy[64], hz[64];
+    const int lane = threadIdx.x;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int4 w = work[it];
         const int b = w.x;
         const double4 g = bt.geo[b];
         const int2 *row = near + (size_t)b * stride;
-        const int nt = min(64, bt.end[b] - w.y);
-        const int split = nt <= 32 ? 2 : 1;
-        const int per = 64 / split;
-        const int ti = threadIdx.x % per, half = threadIdx.x / per;
+        const int nt = max(1, min(64, bt.end[b] - w.y));
+        const int nph = 64 / nt;                                     // phases per target
+        const int blk = nph == 1 ? 64 : (nph <= 3 ? 32 : 16);        // sources per block
+        const int ti = lane % nt, ph = lane / nt;                    // ph >= nph: idle lane
         const int k = w.y + ti;
-        const bool tv = ti < nt;
-        const T xi = tv ? (T)(sp[k] - g.x) : T(0), yi = tv ? (T)(sp[ntot + k] - g.y) : T(0),
-                zi = tv ? (T)(sp[2 * ntot + k] - g.z) : T(0);
+        const T xi = (T)(sp[k] - g.x), yi = (T)(sp[ntot + k] - g.y), zi = (T)(sp[2 * ntot + k] - g.z);
+        const int nr = min(w.w - w.z, kNearMax);
+        __syncthreads();  // the previous item is done with the shared arrays
+        int total = 0;
+        for (int r0 = 0; r0 < nr; r0 += 64) {
+            const int r = r0 + lane;
+            int2 rg = make_int2(0, 0);
+            if (r < nr) rg = row[w.z + r];
+            int x = rg.y - rg.x;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int y = __shfl_up(x, off);
+                if (lane >= off) x += y;
+            }
+            if (r < nr) {
+                pre_s[r + 1] = total + x;
+                beg_s[r] = rg.x - (total + x - (rg.y - rg.x));
+            }
+            total += __shfl(x, 63);
+        }
+        if (lane == 0) pre_s[0] = 0;
+        __syncthreads();
         T ax = 0, ay = 0, az = 0, cx = 0, cy = 0, cz = 0;
-        for (int r = w.z; r < w.w; ++r) {
-            const int2 rg = row[r];
-            for (int base = rg.x; base < rg.y; base += 64) {
-                __syncthreads();
-                const int j = base + threadIdx.x;
-                if (j < rg.y) {
-                    V4 v;
-                    v.x = (T)(sp[j] - g.x);
-                    v.y = (T)(sp[ntot + j] - g.y);
-                    v.z = (T)(sp[2 * ntot + j] - g.z);
-                    v.w = T(0);
-                    src[threadIdx.x] = v;
+        for (int s0 = 0; s0 < total; s0 += kP2PStage) {
+            const int n = min(kP2PStage, total - s0);
+            // source index of each staged position: binary search for the
+            // first, then a forward walk (positions grow by 64)
+            int js[kU];
+            {
+                int a = 0, e = nr;  // last r with pre_s[r] <= pos
+                const int pos0 = s0 + lane;
+                while (e - a > 1) {
+                    const int m = (a + e) >> 1;
+                    if (pre_s[m] <= pos0) a = m;
+                    else e = m;
                 }
-                __syncthreads();
-                const int cnt = min(64, rg.y - base);
-                const int q0 = split == 2 ? half * 32 : 0, q1 = split == 2 ? min(cnt, q0 + 32) : cnt;
+                int r = a;
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int pos = s0 + lane + 64 * u;
+                    js[u] = -1;
+                    if (lane + 64 * u < n) {
+                        while (r + 1 < nr && pre_s[r + 1] <= pos) ++r;
+                        js[u] = beg_s[r] + pos;
+                    }
+                }
+            }
+            double sx[kU], sy[kU], sz[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int j = js[u] >= 0 ? js[u] : 0;
+                sx[u] = sp[j];
+                sy[u] = sp[ntot + j];
+                sz[u] = sp[2 * ntot + j];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (js[u] >= 0) {
+                    V4 v;
+                    v.x = (T)(sx[u] - g.x);
+                    v.y = (T)(sy[u] - g.y);
+                    v.z = (T)(sz[u] - g.z);
+                    v.w = T(0);
+                    src[lane + 64 * u] = v;
+                }
+            __syncthreads();
+            for (int q0 = ph < nph ? ph * blk : n; q0 < n; q0 += nph * blk) {
+                const int q1 = min(n, q0 + blk);
                 T px = 0, py = 0, pz = 0;
+#pragma unroll 4
                 for (int q = q0; q < q1; ++q) {
                     const V4 v = src[q];
                     const T dx = xi - v.x, dy = yi - v.y, dz = zi - v.z;
                     const T r2 = dx * dx + dy * dy + dz * dz;
                     // r2 == 0: the target itself (offsets are bit-identical) or a
                     // coincident ion, both contribute nothing
-                    const T rinv = r2 > T(0) ? rsqrt(r2) : T(0);
-                    const T ww = rinv * rinv * rinv;
+                    const T rinv = rsqrt_t(r2);
+                    const T ww = r2 > T(0) ? rinv * rinv * rinv : T(0);
                     px += dx * ww;
                     py += dy * ww;
                     pz += dz * ww;
@@ -441,22 +502,21 @@ __global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restric
                 cz = (t_ - az) - y_;
                 az = t_;
             }
+            __syncthreads();  // all reads of src done before the next stage
         }
-        if (split == 2) {  // second half hands its sum to the first, added in a fixed order
+        if (nph > 1) {  // phases 1.. hand their sums to phase 0, added in phase order
+            hx[lane] = ax;
+            hy[lane] = ay;
+            hz[lane] = az;
             __syncthreads();
-            if (half == 1) {
-                hx[ti] = ax;
-                hy[ti] = ay;
-                hz[ti] = az;
-            }
-            __syncthreads();
-            if (half == 0) {
-                ax += hx[ti];
-                ay += hy[ti];
-                az += hz[ti];
-            }
+            if (ph == 0)
+                for (int h = 1; h < nph; ++h) {
+                    ax += hx[h * nt + ti];
+                    ay += hy[h * nt + ti];
+                    az += hz[h * nt + ti];
+                }
         }
-        if (half == 0 && tv) {
+        if (ph == 0) {
             T *dst = part + ((size_t)it * 64 + ti) * 3;
             dst[0] = ax;
             dst[1] = ay;

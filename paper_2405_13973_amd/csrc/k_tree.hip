@@ -358,63 +358,68 @@ __global__ void k_oct_tables(BoxTable bt, const TreeSummary *__restrict__ sum, i
     }
 }
 
-// Same-level neighbours (offsets in [-1,1]^3, slot (dx+1)*9 + (dy+1)*3 + (dz+1)).
+// Same-level neighbours (offsets in [-1,1]^3, slot (dx+1)*9 + (dy+1)*3 + (dz+1)),
+// one thread per (box, slot): a binary search of the level's sorted keys.
 __global__ void k_colleagues(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ coll)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= sum->nbox) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nbox = sum->nbox;
+    if (i >= nbox * kNeigh) return;
+    const int b = i / kNeigh, s = i - b * kNeigh;
     const int l = bt.level[b];
-    const int c = bt.crystal[b];
     const int lim = 1 << l;
-    const int x = bt.ix[b], y = bt.iy[b], z = bt.iz[b];
-    const int l0 = sum->level_start[l], l1 = sum->level_start[l + 1];
-    for (int s = 0; s < kNeigh; ++s) {
-        const int nx = x + s / 9 - 1, ny = y + (s / 3) % 3 - 1, nz = z + s % 3 - 1;
-        int found = -1;
-        if (s == 13) {
-            found = b;
-        } else if (nx >= 0 && ny >= 0 && nz >= 0 && nx < lim && ny < lim && nz < lim) {
-            const uint64_t want = ((uint64_t)c << (3 * l)) | morton3(nx, ny, nz);
-            int a = l0, e = l1;
-            while (a < e) {
-                const int m = (a + e) >> 1;
-                if (bt.key[m] < want) a = m + 1;
-                else e = m;
-            }
-            if (a < l1 && bt.key[a] == want) found = a;
+    const int nx = bt.ix[b] + s / 9 - 1, ny = bt.iy[b] + (s / 3) % 3 - 1, nz = bt.iz[b] + s % 3 - 1;
+    int found = -1;
+    if (s == 13) {
+        found = b;
+    } else if (nx >= 0 && ny >= 0 && nz >= 0 && nx < lim && ny < lim && nz < lim) {
+        const uint64_t want = ((uint64_t)bt.crystal[b] << (3 * l)) | morton3(nx, ny, nz);
+        const int l1 = sum->level_start[l + 1];
+        int a = sum->level_start[l], e = l1;
+        while (a < e) {
+            const int m = (a + e) >> 1;
+            if (bt.key[m] < want) a = m + 1;
+            else e = m;
         }
-        coll[(size_t)b * kNeigh + s] = found;
+        if (a < l1 && bt.key[a] == want) found = a;
     }
+    coll[i] = found;
 }
 
-// V lists into the dense window table (-1 = no source).
+// V lists into the dense window table (-1 = no source), one thread per
+// (box, window cell).  Window cell (wx, wy, wz) of a box with parity
+// (cx, cy, cz) is the same-level box at offset (wx-2-cx, wy-2-cy, wz-2-cz);
+// its parent is the colleague of the box's parent in slot
+// (wx>>1, wy>>1, wz>>1) and it sits in that parent's octant
+// (wx&1, wy&1, wz&1).  Cells touching the box are not in the list.
+constexpr int kVBoxes = 8;  // boxes per workgroup
 __global__ void k_vlist(BoxTable bt, const TreeSummary *__restrict__ sum, const int32_t *__restrict__ coll,
-                        int32_t *__restrict__ vtab, unsigned long long *__restrict__ counter)
+                        const int32_t *__restrict__ child_oct, int32_t *__restrict__ vtab,
+                        int32_t *__restrict__ v_blk)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= sum->nbox) return;
-    int32_t *row = vtab + (size_t)b * kWin;
-    for (int w = 0; w < kWin; ++w) row[w] = -1;
-    const int l = bt.level[b];
-    if (l < 2) return;
-    const int x = bt.ix[b], y = bt.iy[b], z = bt.iz[b];
-    const int cx = x & 1, cy = y & 1, cz = z & 1;
-    const int P = bt.parent[b];
+    __shared__ int cnt_s;
+    if (threadIdx.x == 0) cnt_s = 0;
+    __syncthreads();
+    const int nbox = sum->nbox;
     int cnt = 0;
-    for (int s = 0; s < kNeigh; ++s) {
-        const int Q = coll[(size_t)P * kNeigh + s];
-        if (Q < 0 || bt.leaf[Q]) continue;
-        const int c0 = bt.child[Q], c1 = c0 + bt.nchild[Q];
-        for (int ch = c0; ch < c1; ++ch) {
-            const int dx = bt.ix[ch] - x, dy = bt.iy[ch] - y, dz = bt.iz[ch] - z;
-            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
-            const int wx = dx + 2 + cx, wy = dy + 2 + cy, wz = dz + 2 + cz;
-            if (wx < 0 || wx > 5 || wy < 0 || wy > 5 || wz < 0 || wz > 5) continue;  // cannot happen in a valid tree
-            row[wx * 36 + wy * 6 + wz] = ch;
-            ++cnt;
+    for (int e = threadIdx.x; e < kVBoxes * kWin; e += blockDim.x) {
+        const int b = blockIdx.x * kVBoxes + e / kWin, w = e % kWin;
+        if (b >= nbox) break;
+        int src = -1;
+        if (bt.level[b] >= 2) {
+            const int wx = w / 36, wy = (w / 6) % 6, wz = w % 6;
+            const int dx = wx - 2 - (bt.ix[b] & 1), dy = wy - 2 - (bt.iy[b] & 1), dz = wz - 2 - (bt.iz[b] & 1);
+            if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) {
+                const int Q = coll[(size_t)bt.parent[b] * kNeigh + (wx >> 1) * 9 + (wy >> 1) * 3 + (wz >> 1)];
+                if (Q >= 0) src = child_oct[(size_t)Q * 8 + (((wx & 1) << 2) | ((wy & 1) << 1) | (wz & 1))];
+            }
         }
+        vtab[(size_t)b * kWin + w] = src;
+        cnt += src >= 0;
     }
-    if (cnt) atomicAdd(counter, (unsigned long long)cnt);
+    if (cnt) atomicAdd(&cnt_s, cnt);
+    __syncthreads();
+    if (threadIdx.x == 0) v_blk[blockIdx.x] = cnt_s;  // V pairs of the workgroup's boxes
 }
 
 // Near lists of the leaves: ion ranges, stride entries per box.  The near
@@ -435,42 +440,75 @@ __device__ inline int p2p_src_items(const int2 *row, int cnt)
     return items + (acc > 0 ? 1 : 0);
 }
 
-__global__ void k_nearlist(BoxTable bt, const TreeSummary *__restrict__ sum, const int32_t *__restrict__ coll,
-                           int stride, int2 *__restrict__ near, int32_t *__restrict__ near_cnt,
-                           uint32_t *__restrict__ items, int32_t *__restrict__ src_items,
-                           unsigned long long *__restrict__ pair_counter)
+// One wave per box.  Ranges are appended in a fixed order -- the leaf's own
+// colleagues (slot order, itself included), then the leaf colleagues of each
+// ancestor from the parent up (slot order, the ancestor itself excluded) --
+// compacted with ballots, staged in LDS and written out coalesced.
+__global__ __launch_bounds__(64) void k_nearlist(BoxTable bt, const TreeSummary *__restrict__ sum,
+                                                 const int32_t *__restrict__ coll, int stride,
+                                                 int2 *__restrict__ near, int32_t *__restrict__ near_cnt,
+                                                 uint32_t *__restrict__ items, int32_t *__restrict__ src_items,
+                                                 int64_t *__restrict__ pairs)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int2 row_s[kNearMax];
+    __shared__ int anc_s[kMaxLevel + 1];
+    __shared__ int nanc_s;
+    const int b = blockIdx.x, lane = threadIdx.x;
     if (b >= sum->nbox) return;
     if (!bt.leaf[b]) {
-        near_cnt[b] = 0;
-        items[b] = 0;
-        src_items[b] = 0;
+        if (lane == 0) {
+            near_cnt[b] = 0;
+            items[b] = 0;
+            src_items[b] = 0;
+            pairs[b] = 0;
+        }
         return;
     }
-    int2 *row = near + (size_t)b * stride;
+    if (lane == 0) {
+        int n = 0;
+        for (int A = bt.parent[b]; A >= 0 && n <= kMaxLevel; A = bt.parent[A]) anc_s[n++] = A;
+        nanc_s = n;
+    }
+    __syncthreads();
+    const int nanc = nanc_s;
+    const uint64_t below = (1ull << lane) - 1ull;
     int cnt = 0;
     long long srcs = 0;
-    for (int s = 0; s < kNeigh; ++s) {
-        const int Q = coll[(size_t)b * kNeigh + s];
-        if (Q < 0 || cnt >= stride) continue;
-        row[cnt++] = make_int2(bt.begin[Q], bt.end[Q]);
-        srcs += bt.end[Q] - bt.begin[Q];
-    }
-    for (int A = bt.parent[b]; A >= 0; A = bt.parent[A])
-        for (int s = 0; s < kNeigh; ++s) {
-            if (s == 13) continue;
-            const int Q = coll[(size_t)A * kNeigh + s];
-            if (Q < 0 || !bt.leaf[Q] || cnt >= stride) continue;
-            row[cnt++] = make_int2(bt.begin[Q], bt.end[Q]);
-            srcs += bt.end[Q] - bt.begin[Q];
+    auto append = [&](int Q) {
+        const bool v = Q >= 0;
+        const uint64_t m = __ballot(v);
+        const int at = cnt + __popcll(m & below);
+        if (v && at < kNearMax) {
+            const int2 rg = make_int2(bt.begin[Q], bt.end[Q]);
+            row_s[at] = rg;
+            srcs += rg.y - rg.x;
         }
-    near_cnt[b] = cnt;
-    const long long nt = bt.end[b] - bt.begin[b];
-    const int si = p2p_src_items(row, cnt);
-    src_items[b] = si;
-    items[b] = (uint32_t)(si * ((nt + 63) / 64));
-    atomicAdd(pair_counter, (unsigned long long)(nt * srcs - nt));
+        cnt += __popcll(m);
+    };
+    append(lane < kNeigh ? coll[(size_t)b * kNeigh + lane] : -1);
+    for (int a0 = 0; a0 < nanc; a0 += 2) {
+        const int a = a0 + (lane >> 5), s = lane & 31;
+        int Q = -1;
+        if (a < nanc && s < kNeigh && s != 13) {
+            Q = coll[(size_t)anc_s[a] * kNeigh + s];
+            if (Q >= 0 && !bt.leaf[Q]) Q = -1;
+        }
+        append(Q);
+    }
+    cnt = min(cnt, min(stride, kNearMax));  // stride = 27 + 26 x (levels - 1) bounds cnt
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) srcs += __shfl_xor(srcs, off);
+    __syncthreads();
+    int2 *row = near + (size_t)b * stride;
+    for (int r = lane; r < cnt; r += 64) row[r] = row_s[r];
+    if (lane == 0) {
+        near_cnt[b] = cnt;
+        const long long nt = bt.end[b] - bt.begin[b];
+        const int si = p2p_src_items(row_s, cnt);
+        src_items[b] = si;
+        items[b] = (uint32_t)(si * ((nt + 63) / 64));
+        pairs[b] = nt * srcs - nt;  // near-field pairs of the leaf (self excluded)
+    }
 }
 
 // Work items {leaf, first target, first range, end range} at the scanned offsets.
@@ -550,16 +588,17 @@ void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64
     k_tree_links<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum);
 }
 
+int vlist_blocks(int nbox) { return ceil_div(nbox, kVBoxes); }
+
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
-                  int2 *near, int32_t *near_cnt, unsigned long long *counters, int32_t *child_oct,
+                  int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
                   int32_t *parent_oct, uint32_t *item_off, int32_t *src_items, uint32_t *scan_part,
                   uint32_t *n_items, hipStream_t st)
 {
     k_oct_tables<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, child_oct, parent_oct);
-    k_colleagues<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll);
-    k_vlist<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll, vtab, counters);
-    k_nearlist<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, coll, stride, near, near_cnt, item_off, src_items,
-                                                    counters + 1);
+    k_colleagues<<<ceil_div(nbox * kNeigh, 256), 256, 0, st>>>(bt, sum, coll);
+    k_vlist<<<vlist_blocks(nbox), 256, 0, st>>>(bt, sum, coll, child_oct, vtab, v_blk);
+    k_nearlist<<<nbox, 64, 0, st>>>(bt, sum, coll, stride, near, near_cnt, item_off, src_items, near_pairs);
     launch_scan(item_off, nbox, scan_part, n_items, st);
 }
 

@@ -26,6 +26,7 @@ constexpr int kMaxKp = ((kMaxP + 1) * (kMaxP + 1) + 15) & ~15;
 constexpr int kWin = 216;       // 6x6x6 window of M2L source offsets per target box
 constexpr int kNeigh = 27;      // 3x3x3 colleague slots
 constexpr int kP2PChunk = 2048; // near-field sources per work item (items are cut at range boundaries)
+constexpr int kNearMax = kNeigh + 26 * kMaxLevel;  // near ranges of a leaf, at most
 constexpr double kPi = 3.14159265358979323846;
 
 // Physical constants (CODATA 2022, SI).

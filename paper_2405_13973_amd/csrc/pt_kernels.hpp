@@ -46,8 +46,11 @@ void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64
 // Also counts the near-field work items {leaf, first target, range begin,
 // range end}: item_off (nbox, scanned in place to offsets), src_items (nbox),
 // n_items (device total).  launch_p2p_items then writes them into work.
+// Work counts: v_blk (vlist_blocks(nbox) ints) = V pairs per group of boxes,
+// near_pairs (nbox) = near-field pairs per leaf.
+int vlist_blocks(int nbox);
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
-                  int2 *near, int32_t *near_cnt, unsigned long long *counters, int32_t *child_oct,
+                  int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
                   int32_t *parent_oct, uint32_t *item_off, int32_t *src_items, uint32_t *scan_part,
                   uint32_t *n_items, hipStream_t st);
 void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, const int2 *near, const int32_t *near_cnt,

@@ -412,7 +412,6 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     uint32_t *v0, *v1, *hist, *rep, *bcnt, *total;
     double *sp;
     TreeSummary *dsum;
-    unsigned long long *counters;
     PT_TRY(ws_get(ctx, "roots", sizeof(RootCube) * nc, &roots));
     PT_TRY(ws_get(ctx, "keys0", sizeof(uint64_t) * ntot, &k0));
     PT_TRY(ws_get(ctx, "keys1", sizeof(uint64_t) * ntot, &k1));
@@ -427,7 +426,6 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "scan_part", sizeof(uint32_t) * (scan_partials(scan_n) + 1), &scan_part));
     PT_TRY(ws_get(ctx, "sp", sizeof(double) * 3 * ntot, &sp));
     PT_TRY(ws_get(ctx, "sum", sizeof(TreeSummary), &dsum));
-    PT_TRY(ws_get(ctx, "counters", sizeof(unsigned long long) * 2, &counters));
     launch_root(bbox, nc, roots, st);
     launch_keys(b.d_desc, b.ion_crystal, roots, ntot, k0, v0, st);
     int cbits = 0;
@@ -441,7 +439,6 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     launch_gather(b.d_desc, b.ion_crystal, v0, ntot, sp, st);
     launch_tree_count(b.d_desc, k0, ntot, s, rep, bcnt, scan_part, total, dsum, st);
     PT_HIP(hipMemcpyAsync(ctx->h_sum, dsum, sizeof(TreeSummary), hipMemcpyDeviceToHost, st));
-    launch_zero_u64((uint64_t *)counters, 2, st);
     PT_HIP(hipStreamSynchronize(st));
     const TreeSummary hs = *ctx->h_sum;
     const int nbox = hs.nbox;
@@ -478,8 +475,12 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "parent_oct", sizeof(int32_t) * 8 * (size_t)nbox, &parent_oct));
     PT_TRY(ws_get(ctx, "item_off", sizeof(uint32_t) * (size_t)nbox, &item_off));
     PT_TRY(ws_get(ctx, "src_items", sizeof(int32_t) * (size_t)nbox, &src_items));
+    int32_t *v_blk;
+    int64_t *near_pairs;
+    PT_TRY(ws_get(ctx, "v_blk", sizeof(int32_t) * (size_t)vlist_blocks(nbox), &v_blk));
+    PT_TRY(ws_get(ctx, "near_pairs", sizeof(int64_t) * (size_t)nbox, &near_pairs));
     PT_TRY(ws_get(ctx, "scan_part", sizeof(uint32_t) * (scan_partials(std::max(scan_n, nbox)) + 1), &scan_part));
-    launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, counters, child_oct, parent_oct, item_off,
+    launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, v_blk, near_pairs, child_oct, parent_oct, item_off,
                  src_items, scan_part, total + 1, st);
     // near-field work items: their number sizes the item and partial buffers
     PT_HIP(hipMemcpyAsync(ctx->h_counters, total + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -944,9 +945,14 @@ pt_status pt_ctx_work_counts(pt_ctx *ctx, int64_t counts[6])
     counts[5] = ctx->last_ntot;
     if (!ctx->last_was_fmm) return PT_OK;
     PT_HIP(hipStreamSynchronize(ctx->stream));
-    unsigned long long cnt[2];
-    PT_HIP(hipMemcpy(cnt, ctx->ws["counters"].ptr, sizeof(cnt), hipMemcpyDeviceToHost));
     const int nbox = ctx->last_sum.nbox;
+    std::vector<int32_t> vb(vlist_blocks(nbox));
+    std::vector<int64_t> np(nbox);
+    PT_HIP(hipMemcpy(vb.data(), ctx->ws["v_blk"].ptr, vb.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    PT_HIP(hipMemcpy(np.data(), ctx->ws["near_pairs"].ptr, np.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    int64_t nv = 0, nn = 0;
+    for (int32_t x : vb) nv += x;
+    for (int64_t x : np) nn += x;
     std::vector<uint8_t> leaf(nbox);
     PT_HIP(hipMemcpy(leaf.data(), ctx->ws["b_leaf"].ptr, nbox, hipMemcpyDeviceToHost));
     int64_t nl = 0;
@@ -956,8 +962,8 @@ pt_status pt_ctx_work_counts(pt_ctx *ctx, int64_t counts[6])
         if (ctx->last_sum.level_start[l + 1] > ctx->last_sum.level_start[l]) nlev = l + 1;
     counts[0] = nbox;
     counts[1] = nl;
-    counts[2] = (int64_t)cnt[0];
-    counts[3] = (int64_t)cnt[1];
+    counts[2] = nv;
+    counts[3] = nn;
     counts[4] = nlev;
     return PT_OK;
 }

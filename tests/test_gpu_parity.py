@@ -146,11 +146,19 @@ def test_tree_bit_exact_clumps(ctx):
     c.set_force("fmm", 4, 8)
     c.compute_forces()
     T = c.export_tree()
+    wc = ctx.work_counts()
     c.destroy()
     R = O.tree(pos, 8)
     for k in ("key", "perm", "level", "parent", "ion_begin", "ion_end", "coords", "is_leaf", "v_off", "v_src",
               "near_off", "near_src"):
         assert np.array_equal(T[k], R[k]), k
+    # work counts: boxes, leaves, V pairs, near-field ion pairs (self excluded)
+    size = R["ion_end"] - R["ion_begin"]
+    near_pairs = 0
+    for b in np.flatnonzero(R["is_leaf"]):
+        src = size[R["near_src"][R["near_off"][b]:R["near_off"][b + 1]]].sum()
+        near_pairs += int(size[b]) * int(src) - int(size[b])
+    assert list(wc[:4]) == [len(R["level"]), int(R["is_leaf"].sum()), len(R["v_src"]), near_pairs]
 
 
 # ---------------------------------------------------------------- FMM
