@@ -74,7 +74,7 @@ __host__ __device__ inline void rhat_all(int p, T x, T y, T z, T *re, T *im)
 //   f = 1 (rb): sqrt((n+m-1)(n-m-1)/((n+m)(n-m))) for n >= m+2, else 0
 //   f = 2..4: L2P weights of Rh_n^m (n < p), see l2p_field:
 //         sqrt((n+1+m)(n+1-m)) (doubled for m > 0), sqrt((n+m+2)(n+m+1)), sqrt((n-m+2)(n-m+1))
-__host__ __device__ inline int kq(int p) { return (p + 1) * (p + 2) / 2; }
+__host__ __device__ constexpr int kq(int p) { return (p + 1) * (p + 2) / 2; }
 constexpr int kRecFields = 5;
 
 // Field of a local expansion (L2P).  The expansion is re-centred exactly at

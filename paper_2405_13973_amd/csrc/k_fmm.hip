@@ -37,11 +37,14 @@ __global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const double *__restric
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *C = reinterpret_cast<T *>(smem_raw);  // [Kp][kP2MIons + 1]
+    __shared__ T rec_s[2 * kq(kMaxP)];      // the recurrence fields the expansion needs
     const int b = blockIdx.x;
     if (!bt.leaf[b]) return;
     const double4 g = bt.geo[b];
     const double ih = 1.0 / g.w;
     const int K = kcoef(p);
+    for (int i = threadIdx.x; i < 2 * kq(p); i += 64) rec_s[i] = rec[i];
+    __syncthreads();
     const int i0 = bt.begin[b], i1 = bt.end[b];
     constexpr int ld = kP2MIons + 1;
     T acc[kP2MMaxPer];
@@ -51,7 +54,7 @@ __global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const double *__restric
         const int cnt = min(kP2MIons, i1 - c0);
         if ((int)threadIdx.x < cnt) {
             const int i = c0 + threadIdx.x;
-            p2m_terms<T>(p, rec, (T)((sp[i] - g.x) * ih), (T)((sp[ntot + i] - g.y) * ih),
+            p2m_terms<T>(p, rec_s, (T)((sp[i] - g.x) * ih), (T)((sp[ntot + i] - g.y) * ih),
                          (T)((sp[2 * ntot + i] - g.z) * ih), C + threadIdx.x, ld);
         }
         __syncthreads();
@@ -108,11 +111,21 @@ struct Mfma<float> {
 // Buckets the boxes of level >= 2 by octant parity.
 __global__ void k_m2l_bucket(BoxTable bt, int nbox, int32_t *__restrict__ cnt, int32_t *__restrict__ list)
 {
+    // one atomic per parity and wave; the order inside a bucket does not
+    // change any result (a target's sum runs over its own slots in slot order)
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbox || bt.level[b] < 2) return;
-    const int o = octant_of(bt.ix[b], bt.iy[b], bt.iz[b]);
-    const int pos = atomicAdd(&cnt[o], 1);
-    list[(size_t)o * nbox + pos] = b;
+    const int lane = threadIdx.x & 63;
+    const int o = (b < nbox && bt.level[b] >= 2) ? octant_of(bt.ix[b], bt.iy[b], bt.iz[b]) : -1;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int q = 0; q < 8; ++q) {
+        const uint64_t m = __ballot(o == q);
+        if (!m) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&cnt[q], __popcll(m));
+        base = __shfl(base, leader);
+        if (o == q) list[(size_t)q * nbox + base + __popcll(m & below)] = b;
+    }
 }
 
 constexpr int kM2LWaves = 4;           // 16 target columns per wave
@@ -534,18 +547,22 @@ __global__ __launch_bounds__(64) void k_far(BoxTable bt, const double *__restric
                                             const int32_t *__restrict__ src_items, const T *__restrict__ part,
                                             const uint32_t *__restrict__ vals, double *__restrict__ E)
 {
+    __shared__ T rec_s[kRecFields * kq(kMaxP)];
+    __shared__ T Lb[kMaxKp];
     const int b = blockIdx.x;
     if (!bt.leaf[b]) return;
     const double4 g = bt.geo[b];
     const double ih = 1.0 / g.w;
-    const T *Lb = L + (size_t)b * Kp;
+    for (int i = threadIdx.x; i < kRecFields * kq(p); i += 64) rec_s[i] = rec[i];
+    for (int i = threadIdx.x; i < Kp; i += 64) Lb[i] = L[(size_t)b * Kp + i];
+    __syncthreads();
     const int si = src_items[b];
     const uint32_t base = item_off[b];
     for (int k = bt.begin[b] + threadIdx.x; k < bt.end[b]; k += 64) {
         const int tl = k - bt.begin[b];
         const double xd = sp[k], yd = sp[ntot + k], zd = sp[2 * ntot + k];
         T ex, ey, ez;
-        l2p_field<T>(p, Lb, rec, (T)((xd - g.x) * ih), (T)((yd - g.y) * ih), (T)((zd - g.z) * ih), ex, ey, ez);
+        l2p_field<T>(p, Lb, rec_s, (T)((xd - g.x) * ih), (T)((yd - g.y) * ih), (T)((zd - g.z) * ih), ex, ey, ez);
         double fx = (double)ex * ih * ih, fy = (double)ey * ih * ih, fz = (double)ez * ih * ih;
         const T *pp = part + ((size_t)(base + (tl >> 6) * si) * 64 + (tl & 63)) * 3;
         for (int j = 0; j < si; ++j, pp += 64 * 3) {

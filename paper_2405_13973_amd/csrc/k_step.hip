@@ -56,8 +56,9 @@ __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t v0, uint64_t v1, i
 // Optional half drift, then per-crystal min/max of x, y, z (ordered-integer
 // atomics; min/max is exact, so the result does not depend on the order).
 __global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
-                             int do_drift, unsigned long long *__restrict__ bbox)
+                             int do_drift, unsigned long long *__restrict__ bbox_all, int bstride)
 {
+    unsigned long long *bbox = bbox_all + (size_t)(blockIdx.x % kBBoxCopies) * bstride;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = g < ntot;
     int c = 0;
@@ -145,15 +146,22 @@ __global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *_
 // Root cube per crystal, in the exact operation order of the tree contract:
 // W = max extent (1e-9 m if zero), o = (lo + hi)/2 - W/2, S = 2^16 / W.
 // Resets the bounding box for its next use.
-__global__ void k_root(unsigned long long *__restrict__ bbox, int nc, RootCube *__restrict__ roots)
+__global__ void k_root(unsigned long long *__restrict__ bbox, int nc, int bstride, RootCube *__restrict__ roots)
 {
 #pragma clang fp contract(off)
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
+    unsigned long long w[6];
+    for (int k = 0; k < 6; ++k) w[k] = bbox[6 * c + k];
+    for (int cp = 1; cp < kBBoxCopies; ++cp)
+        for (int k = 0; k < 6; ++k) {
+            const unsigned long long o = bbox[(size_t)cp * bstride + 6 * c + k];
+            w[k] = k < 3 ? (o < w[k] ? o : w[k]) : (o > w[k] ? o : w[k]);
+        }
     double lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
-        lo[d] = ordered_to_dbl(bbox[6 * c + d]);
-        hi[d] = ordered_to_dbl(bbox[6 * c + 3 + d]);
+        lo[d] = ordered_to_dbl(w[d]);
+        hi[d] = ordered_to_dbl(w[3 + d]);
     }
     double W = 0.0;
     for (int d = 0; d < 3; ++d) {
@@ -170,10 +178,11 @@ __global__ void k_root(unsigned long long *__restrict__ bbox, int nc, RootCube *
     r.S = 65536.0 / W;
     r.pad[0] = r.pad[1] = r.pad[2] = 0.0;
     roots[c] = r;
-    for (int d = 0; d < 3; ++d) {
-        bbox[6 * c + d] = ~0ull;
-        bbox[6 * c + 3 + d] = 0ull;
-    }
+    for (int cp = 0; cp < kBBoxCopies; ++cp)
+        for (int d = 0; d < 3; ++d) {
+            bbox[(size_t)cp * bstride + 6 * c + d] = ~0ull;
+            bbox[(size_t)cp * bstride + 6 * c + 3 + d] = 0ull;
+        }
 }
 
 // 64-bit sort key per ion: crystal index above a 48-bit Morton key of the
@@ -345,7 +354,8 @@ void launch_ion_crystal(const CrystalDev *cs, int nc, int ntot, int32_t *ion_cry
 
 void launch_bbox_reset(unsigned long long *bbox, int nc, hipStream_t st)
 {
-    k_fill_u64<<<ceil_div(6 * nc, 256), 256, 0, st>>>((uint64_t *)bbox, ~0ull, 0ull, nc);
+    const int pairs = (int)(bbox_words(nc) / 6);
+    k_fill_u64<<<ceil_div(6 * pairs, 256), 256, 0, st>>>((uint64_t *)bbox, ~0ull, 0ull, pairs);
 }
 
 void launch_zero_u64(uint64_t *p, int n, hipStream_t st)
@@ -353,15 +363,16 @@ void launch_zero_u64(uint64_t *p, int n, hipStream_t st)
     if (n > 0) k_zero_words<<<ceil_div(n, 256), 256, 0, st>>>(p, n);
 }
 
-void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int do_drift,
+void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int nc, int do_drift,
                        unsigned long long *bbox, hipStream_t st)
 {
-    if (ntot > 0) k_drift_bbox<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, do_drift, bbox);
+    if (ntot > 0)
+        k_drift_bbox<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, do_drift, bbox, bbox_stride(nc));
 }
 
 void launch_root(unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st)
 {
-    k_root<<<ceil_div(nc, 64), 64, 0, st>>>(bbox, nc, roots);
+    k_root<<<ceil_div(nc, 64), 64, 0, st>>>(bbox, nc, bbox_stride(nc), roots);
 }
 
 void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCube *roots, int ntot, uint64_t *keys,

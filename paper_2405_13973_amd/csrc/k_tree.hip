@@ -426,7 +426,7 @@ __global__ void k_vlist(BoxTable bt, const TreeSummary *__restrict__ sum, const 
 // field of a leaf is then cut into work items of at most kP2PChunk sources
 // (cut at range boundaries) times chunks of 64 targets, so that no single
 // workgroup carries a coarse boundary leaf with thousands of near sources.
-__device__ inline int p2p_src_items(const int2 *row, int cnt)
+__device__ inline int p2p_src_items(const int2 *row, int cnt, int32_t *cut)
 {
     int items = 0, acc = 0;
     for (int r = 0; r < cnt; ++r) {
@@ -435,6 +435,7 @@ __device__ inline int p2p_src_items(const int2 *row, int cnt)
             ++items;
             acc = 0;
         }
+        if (acc == 0) cut[items] = r;  // first range of source item `items`
         acc += len;
     }
     return items + (acc > 0 ? 1 : 0);
@@ -448,7 +449,7 @@ __global__ __launch_bounds__(64) void k_nearlist(BoxTable bt, const TreeSummary 
                                                  const int32_t *__restrict__ coll, int stride,
                                                  int2 *__restrict__ near, int32_t *__restrict__ near_cnt,
                                                  uint32_t *__restrict__ items, int32_t *__restrict__ src_items,
-                                                 int64_t *__restrict__ pairs)
+                                                 int32_t *__restrict__ cuts, int64_t *__restrict__ pairs)
 {
     __shared__ int2 row_s[kNearMax];
     __shared__ int anc_s[kMaxLevel + 1];
@@ -504,38 +505,32 @@ __global__ __launch_bounds__(64) void k_nearlist(BoxTable bt, const TreeSummary 
     if (lane == 0) {
         near_cnt[b] = cnt;
         const long long nt = bt.end[b] - bt.begin[b];
-        const int si = p2p_src_items(row_s, cnt);
+        const int si = p2p_src_items(row_s, cnt, cuts + (size_t)b * stride);
         src_items[b] = si;
         items[b] = (uint32_t)(si * ((nt + 63) / 64));
         pairs[b] = nt * srcs - nt;  // near-field pairs of the leaf (self excluded)
     }
 }
 
-// Work items {leaf, first target, first range, end range} at the scanned offsets.
-__global__ void k_p2p_items(BoxTable bt, const TreeSummary *__restrict__ sum, const int2 *__restrict__ near,
-                            const int32_t *__restrict__ near_cnt, int stride, const uint32_t *__restrict__ item_off,
-                            const int32_t *__restrict__ src_items, int4 *__restrict__ work)
+// Work items {leaf, first target, first range, end range} at the scanned
+// offsets, one wave per leaf: item tc * si + j pairs target chunk tc with
+// source item j (ranges cut[j] .. cut[j + 1]).
+__global__ __launch_bounds__(64) void k_p2p_items(BoxTable bt, const TreeSummary *__restrict__ sum,
+                                                  const int32_t *__restrict__ near_cnt, int stride,
+                                                  const uint32_t *__restrict__ item_off,
+                                                  const int32_t *__restrict__ src_items,
+                                                  const int32_t *__restrict__ cuts, int4 *__restrict__ work)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.x;
     if (b >= sum->nbox || !bt.leaf[b]) return;
-    const int2 *row = near + (size_t)b * stride;
+    const int32_t *cut = cuts + (size_t)b * stride;
     const int cnt = near_cnt[b], si = src_items[b];
     const int nt = bt.end[b] - bt.begin[b];
-    uint32_t w = item_off[b];
-    for (int t0 = 0; t0 < nt; t0 += 64) {
-        int r0 = 0, acc = 0;
-        for (int r = 0; r < cnt; ++r) {
-            const int len = row[r].y - row[r].x;
-            if (acc > 0 && acc + len > kP2PChunk) {
-                work[w++] = make_int4(b, bt.begin[b] + t0, r0, r);
-                r0 = r;
-                acc = 0;
-            }
-            acc += len;
-        }
-        if (acc > 0) work[w++] = make_int4(b, bt.begin[b] + t0, r0, cnt);
+    const uint32_t w0 = item_off[b];
+    for (int j = threadIdx.x; j < si; j += 64) {
+        const int r0 = cut[j], r1 = j + 1 < si ? cut[j + 1] : cnt;
+        for (int tc = 0; tc * 64 < nt; ++tc) work[w0 + tc * si + j] = make_int4(b, bt.begin[b] + 64 * tc, r0, r1);
     }
-    (void)si;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -592,20 +587,21 @@ int vlist_blocks(int nbox) { return ceil_div(nbox, kVBoxes); }
 
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
                   int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
-                  int32_t *parent_oct, uint32_t *item_off, int32_t *src_items, uint32_t *scan_part,
+                  int32_t *parent_oct, uint32_t *item_off, int32_t *src_items, int32_t *cuts, uint32_t *scan_part,
                   uint32_t *n_items, hipStream_t st)
 {
     k_oct_tables<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, child_oct, parent_oct);
     k_colleagues<<<ceil_div(nbox * kNeigh, 256), 256, 0, st>>>(bt, sum, coll);
     k_vlist<<<vlist_blocks(nbox), 256, 0, st>>>(bt, sum, coll, child_oct, vtab, v_blk);
-    k_nearlist<<<nbox, 64, 0, st>>>(bt, sum, coll, stride, near, near_cnt, item_off, src_items, near_pairs);
+    k_nearlist<<<nbox, 64, 0, st>>>(bt, sum, coll, stride, near, near_cnt, item_off, src_items, cuts, near_pairs);
     launch_scan(item_off, nbox, scan_part, n_items, st);
 }
 
-void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, const int2 *near, const int32_t *near_cnt,
-                      int stride, const uint32_t *item_off, const int32_t *src_items, int4 *work, hipStream_t st)
+void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *near_cnt, int stride,
+                      const uint32_t *item_off, const int32_t *src_items, const int32_t *cuts, int4 *work,
+                      hipStream_t st)
 {
-    k_p2p_items<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, near, near_cnt, stride, item_off, src_items, work);
+    k_p2p_items<<<nbox, 64, 0, st>>>(bt, sum, near_cnt, stride, item_off, src_items, cuts, work);
 }
 
 }  // namespace pt

@@ -16,9 +16,16 @@ struct BoxTable {
 
 // k_step.hip
 void launch_ion_crystal(const CrystalDev *cs, int nc, int ntot, int32_t *ion_crystal, hipStream_t st);
+// Bounding boxes: kBBoxCopies copies of [crystal][6] ordered-integer words,
+// bbox_stride(nc) words apart (a multiple of 6 and of 128 bytes), so that the
+// atomics of different workgroups spread over separate cache lines; the
+// root-cube kernel reduces the copies.  The buffer holds bbox_words(nc) words.
+constexpr int kBBoxCopies = 16;
+inline int bbox_stride(int nc) { return (6 * nc + 47) / 48 * 48; }
+inline size_t bbox_words(int nc) { return (size_t)kBBoxCopies * bbox_stride(nc); }
 void launch_bbox_reset(unsigned long long *bbox, int nc, hipStream_t st);
 void launch_zero_u64(uint64_t *p, int n, hipStream_t st);
-void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int do_drift,
+void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int nc, int do_drift,
                        unsigned long long *bbox, hipStream_t st);
 void launch_root(unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st);
 void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCube *roots, int ntot, uint64_t *keys,
@@ -51,10 +58,12 @@ void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64
 int vlist_blocks(int nbox);
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
                   int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
-                  int32_t *parent_oct, uint32_t *item_off, int32_t *src_items, uint32_t *scan_part,
+                  int32_t *parent_oct, uint32_t *item_off, int32_t *src_items, int32_t *cuts, uint32_t *scan_part,
                   uint32_t *n_items, hipStream_t st);
-void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, const int2 *near, const int32_t *near_cnt,
-                      int stride, const uint32_t *item_off, const int32_t *src_items, int4 *work, hipStream_t st);
+// cuts (stride per box): first near range of each source item of a leaf.
+void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *near_cnt, int stride,
+                      const uint32_t *item_off, const int32_t *src_items, const int32_t *cuts, int4 *work,
+                      hipStream_t st);
 
 // k_fmm.hip
 // rec: recurrence table (fmm_math.hpp), kRecFields x kq(p) entries.

@@ -334,7 +334,7 @@ static pt_status form_batch(pt_ctx *ctx, const std::vector<pt_crystal *> &cs, Ba
     launch_ion_crystal(b.d_desc, nc, b.ntot, b.ion_crystal, ctx->stream);
     // bounding boxes start empty; the root-cube kernel empties them again after each use
     unsigned long long *bbox;
-    PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * 6 * nc, &bbox));
+    PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * bbox_words(nc), &bbox));
     launch_bbox_reset(bbox, nc, ctx->stream);
     // direct-method block table: each block serves targets of one crystal
     const int tpb = direct_targets_per_block();
@@ -389,7 +389,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     hipStream_t st = ctx->stream;
     const int ntot = b.ntot, nc = (int)b.cs.size();
     unsigned long long *bbox;
-    PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * 6 * nc, &bbox));
+    PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * bbox_words(nc), &bbox));
     ctx->last_batch = b.cs;
     ctx->last_off = b.off;
     ctx->last_ntot = ntot;
@@ -479,9 +479,11 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     int64_t *near_pairs;
     PT_TRY(ws_get(ctx, "v_blk", sizeof(int32_t) * (size_t)vlist_blocks(nbox), &v_blk));
     PT_TRY(ws_get(ctx, "near_pairs", sizeof(int64_t) * (size_t)nbox, &near_pairs));
+    int32_t *cuts;
+    PT_TRY(ws_get(ctx, "p2p_cuts", sizeof(int32_t) * (size_t)stride * nbox, &cuts));
     PT_TRY(ws_get(ctx, "scan_part", sizeof(uint32_t) * (scan_partials(std::max(scan_n, nbox)) + 1), &scan_part));
     launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, v_blk, near_pairs, child_oct, parent_oct, item_off,
-                 src_items, scan_part, total + 1, st);
+                 src_items, cuts, scan_part, total + 1, st);
     // near-field work items: their number sizes the item and partial buffers
     PT_HIP(hipMemcpyAsync(ctx->h_counters, total + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     PT_HIP(hipStreamSynchronize(st));
@@ -490,7 +492,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     void *ppart;
     PT_TRY(ws_get(ctx, "p2p_work", sizeof(int4) * (size_t)std::max(1, n_items), &work));
     PT_TRY(ws_get(ctx, "p2p_part", esz * 64 * 3 * (size_t)std::max(1, n_items), (char **)&ppart));
-    launch_p2p_items(bt, dsum, nbox, near, near_cnt, stride, item_off, src_items, work, st);
+    launch_p2p_items(bt, dsum, nbox, near_cnt, stride, item_off, src_items, cuts, work, st);
     int32_t *m2l_cnt, *m2l_list;
     void *m2l_part;
     const int ngroup = m2l_groups(nbox - hs.level_start[2]);
@@ -814,9 +816,9 @@ pt_status pt_compute_forces_batch(pt_crystal *const *cs, int n_crystals, double 
     PT_TRY(form_batch(ctx, std::vector<pt_crystal *>(cs, cs + n_crystals), b));
     unsigned long long *bbox;
     double *E;
-    PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * 6 * n_crystals, &bbox));
+    PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * bbox_words(n_crystals), &bbox));
     PT_TRY(ws_get(ctx, "E", sizeof(double) * 3 * (size_t)b.ntot, &E));
-    launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, 0, bbox, ctx->stream);
+    launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, n_crystals, 0, bbox, ctx->stream);
     PT_TRY(eval_field(ctx, b, cs[0]->force, E));
     std::vector<double> h(3 * (size_t)b.ntot);
     PT_HIP(hipMemcpyAsync(h.data(), E, sizeof(double) * 3 * b.ntot, hipMemcpyDeviceToHost, ctx->stream));
@@ -869,9 +871,9 @@ pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_
         const int nc = (int)b.cs.size();
         unsigned long long *bbox;
         double *E;
-        PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * 6 * nc, &bbox));
+        PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * bbox_words(nc), &bbox));
         PT_TRY(ws_get(ctx, "E", sizeof(double) * 3 * (size_t)b.ntot, &E));
-        launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, 1, bbox, ctx->stream);
+        launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, nc, 1, bbox, ctx->stream);
         PT_TRY(eval_field(ctx, b, cs[0]->force, E));
         // step index = descriptor step0 (set when the batch formed) + kstep
         launch_kick_drift(b.d_desc, b.ion_crystal, b.ntot, (int)(k - group_start), E, ctx->stream);
