@@ -5,12 +5,14 @@ Workload: 100,000 ions on a 5%-jittered simple cubic lattice in a prolate
 ellipsoid with semi-axes (400, 400, 800) um, 10 mK velocities, B = 4.5 T,
 omega_z = 2 pi 1.5 MHz, dt = 1 ns, no laser.  The expansion degree p is the
 smallest one whose RMS relative Coulomb-force error against the FP64 direct
-sum is <= 1e-6, chosen at start-up (not timed).
+sum is <= 1e-6, chosen at start-up (not timed); with the default --leaf 0
+the leaf size is tuned too: for each candidate leaf size the smallest such
+p, then the fastest pair.
 
-Prints one JSON line (see the contract in the design doc): value = ion-steps/s of
-the mixed-precision form (or --precision fp64), roofline of the dominant
-kernel (M2L) from HIP events over the timed region, and the CPU oracle timed
-on a bounded sample of the same workload.
+Prints one JSON line: value = ion-steps/s of the mixed-precision form (or
+--precision fp64), roofline of the dominant kernel (M2L on the matrix
+cores, or the P2P kernel on the vector ALUs) from HIP events over the timed
+region, and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -30,15 +32,21 @@ from paper_2405_13973_amd import inputs, native  # noqa: E402
 
 METRIC = "ion-steps/s at N=1e5, RMS rel force error≤1e-6 vs FP64; p99 latency mixed stream"
 PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "valu_fp32": 157.3, "valu_fp64": 78.6}
+# Arithmetic of one near-field pair as the P2P kernel performs it: 3 sub
+# (offset), 3 mul + 2 add (r^2), 1 rsqrt, 2 mul (r^-3), 3 mul + 3 add (field).
+P2P_FLOPS_PER_PAIR = 17
+PHASES = ["tree", "upward", "m2l_kernel", "m2l_reduce_l2l", "p2p_kernel", "l2p_partials", "total"]
+LEAF_CANDIDATES = (32, 64, 128, 256)
 
 
-def measured_traffic(p, leaf, precision, n):
-    """HBM bytes per M2L launch from the committed rocprofv3 counter runs, or
-    None when the kernel source or the workload differs from the one profiled."""
+def measured_traffic(kernel, p, leaf, precision, n):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs, or None when the kernel source or the workload differs from the
+    one profiled."""
     import hashlib
 
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "m2l_traffic.json")))
+        rec = json.load(open(os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")))
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     except (OSError, ValueError, KeyError):
         return None
@@ -95,12 +103,19 @@ def cpu_baseline(cr, p, leaf, F_dir_gpu):
     dev = np.abs(F_dir_gpu[idx] - ref).max() / np.sqrt((ref ** 2).sum(1).mean())
     log(f"  GPU direct vs oracle direct on {len(idx)} sampled ions: max err / rms = {dev:.2e}")
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # one step, then more from the same state until about 10 s of work in all
     t0 = time.perf_counter()
     O.run(cr.pos, cr.vel, cr.charge, cr.mass, cr.trap(), cr.dt, 1, method="fmm", p=p, leaf_size=leaf)
+    first = time.perf_counter() - t0
+    steps = 1
+    if first < 10.0:
+        more = min(50, math.ceil((10.0 - first) / first))
+        O.run(cr.pos, cr.vel, cr.charge, cr.mass, cr.trap(), cr.dt, more, method="fmm", p=p, leaf_size=leaf)
+        steps += more
     el = time.perf_counter() - t0
-    log(f"  oracle: one FMM step of {cr.n} ions (p={p}, leaf={leaf}) in {el:.1f} s on {cores} threads")
-    return {"value": cr.n / el, "unit": "ion-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"one full FP64 FMM step (p={p}, leaf {leaf}) of the same {cr.n}-ion crystal, "
+    log(f"  oracle: {steps} FMM steps of {cr.n} ions (p={p}, leaf={leaf}) in {el:.1f} s on {cores} threads")
+    return {"value": cr.n * steps / el, "unit": "ion-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} full FP64 FMM steps (p={p}, leaf {leaf}) of the same {cr.n}-ion crystal, "
                       f"{el:.1f} s wall; direct sum checked on 48 sampled ions (max err/rms {dev:.1e})"}
 
 
@@ -146,7 +161,7 @@ def bench_ensemble(a, ctx, sync):
                    "crystals": len(crs), "ions": ntot, "p": a.p, "leaf_size": a.leaf,
                    "max_rms_rel_force_err_largest3": max(errs)},
         "details": {"phase_ms": {k: float(v) for k, v in zip(
-            ["tree", "upward", "m2l_kernel", "m2l_reduce_l2l", "eval", "total"], phases)}},
+            PHASES, phases)}},
     }
 
 
@@ -189,7 +204,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--leaf", type=int, default=32)
+    ap.add_argument("--leaf", type=int, default=0,
+                    help="leaf size (0: tune over %s for config3; 64 for ensemble / serving)" % (LEAF_CANDIDATES,))
     ap.add_argument("--p0", type=int, default=10, help="first p tried when choosing p")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -225,6 +241,7 @@ def main():
         del src, dst
 
     if a.workload != "config3":
+        a.leaf = a.leaf or 64
         ctx = native.Context(0, hbm_budget=(a.budget_gb << 30) + (4 << 30), stream=stream.cuda_stream)
         out = bench_ensemble(a, ctx, sync) if a.workload == "ensemble" else bench_serving(a, ctx, sync)
         ctx.close()
@@ -239,34 +256,61 @@ def main():
     c.set_force("direct")
     F_dir = c.compute_forces()
 
+    def tune(prec, leaves):
+        """Smallest p meeting the error bound per leaf size, then the fastest."""
+        best = None
+        for leaf in leaves:
+            c.set_state(cr.pos, cr.vel, 0)  # F_dir belongs to the initial positions
+            p, err, _ = choose_p(c, F_dir, prec, leaf, a.p0)
+            el = 0.0
+            if len(leaves) > 1:
+                c.set_force("fmm", p, leaf, prec)
+                el = timed_steps(ctx, c, 10, 2, sync)[0]
+                log(f"  {prec} leaf {leaf}: p={p} {10 * cr.n / el:.4g} ion-steps/s")
+            if best is None or el < best[3]:
+                best = (leaf, p, err, el)
+        return best[:3]
+
     results = {}
     forms = [a.precision] + ([] if a.no_fp64_compare or a.precision == "fp64" else ["fp64"])
     for prec in forms:
-        c.set_state(cr.pos, cr.vel, 0)  # F_dir belongs to the initial positions
-        p, err, _ = choose_p(c, F_dir, prec, a.leaf, a.p0)
+        leaves = (a.leaf,) if a.leaf else LEAF_CANDIDATES
+        if prec != a.precision:
+            leaves = (results[a.precision]["leaf"],)
+        leaf, p, err = tune(prec, leaves)
         c.set_state(cr.pos, cr.vel, 0)
-        c.set_force("fmm", p, a.leaf, prec)
+        c.set_force("fmm", p, leaf, prec)
         sync()
         el, phases, count, wc = timed_steps(ctx, c, a.steps, a.warmup, sync)
-        results[prec] = dict(p=p, err=err, seconds=el, phases=phases, count=count, wc=wc)
-        log(f"  {prec}: p={p} {a.steps} steps in {el * 1e3:.2f} ms -> {cr.n * a.steps / el:.4g} ion-steps/s; "
-            f"phases(ms) tree {phases[0]:.3f} up {phases[1]:.3f} m2l {phases[2]:.3f} down {phases[3]:.3f} "
-            f"eval {phases[4]:.3f} total {phases[5]:.3f} over {count} evals")
+        results[prec] = dict(p=p, leaf=leaf, err=err, seconds=el, phases=phases, count=count, wc=wc)
+        log(f"  {prec}: p={p} leaf={leaf} {a.steps} steps in {el * 1e3:.2f} ms -> {cr.n * a.steps / el:.4g} "
+            f"ion-steps/s; phases(ms) " + " ".join(f"{k} {v:.3f}" for k, v in zip(PHASES, phases)) +
+            f" over {count} evals")
 
     # direct-sum rate on the same crystal, for the FMM/direct comparison
     c.set_force("direct")
     ctx.set_timing(True)
     c.compute_forces()
-    dir_ms = ctx.phase_times()[5]
+    dir_ms = ctx.phase_times()[6]
     ctx.set_timing(False)
 
     main_r = results[a.precision]
-    p = main_r["p"]
+    p, leaf = main_r["p"], main_r["leaf"]
     K = (p + 1) ** 2
-    m2l_flops = 2.0 * K * K * main_r["wc"][2]
-    m2l_ms = main_r["phases"][2]
-    achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12
-    peak = PEAK["mfma_fp32"] if a.precision == "mixed" else PEAK["mfma_fp64"]
+    ph = main_r["phases"]
+    fp32 = a.precision == "mixed"
+    m2l_tflops = 2.0 * K * K * main_r["wc"][2] / (ph[2] * 1e-3) / 1e12
+    p2p_tflops = P2P_FLOPS_PER_PAIR * main_r["wc"][3] / (ph[4] * 1e-3) / 1e12
+    # roofline of the dominant kernel: M2L (matrix cores) or P2P (vector ALUs)
+    if ph[2] >= ph[4]:
+        kernel, bound, achieved = "m2l", "mfma", m2l_tflops
+        peak = PEAK["mfma_fp32" if fp32 else "mfma_fp64"]
+        algorithmic = f"2 K^2 flops per M2L pair, K=(p+1)^2={K}, {int(main_r['wc'][2])} pairs per launch"
+    else:
+        kernel, bound, achieved = "p2p", "alu", p2p_tflops
+        peak = PEAK["valu_fp32" if fp32 else "valu_fp64"]
+        algorithmic = (f"{P2P_FLOPS_PER_PAIR} flops per near-field pair, {int(main_r['wc'][3])} ordered pairs "
+                       f"(i != j) per launch")
     value = cr.n * a.steps / main_r["seconds"]
     out = {
         "metric": METRIC,
@@ -279,26 +323,27 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if a.precision == "mixed" else "f64",
+        "dtype": "f32+f64" if fp32 else "f64",
         "data": "synthetic",
         "config": {
             "workload": f"{cr.n} ions, 5%-jittered cubic lattice in a (400,400,800) um prolate ellipsoid, "
-                        f"B=4.5 T, f_z=1.5 MHz, dt=1 ns, FMM p={p} leaf {a.leaf} ({a.precision})",
-            "n_ions": cr.n, "p": p, "leaf_size": a.leaf, "precision": a.precision,
+                        f"B=4.5 T, f_z=1.5 MHz, dt=1 ns, FMM p={p} leaf {leaf} ({a.precision})",
+            "n_ions": cr.n, "p": p, "leaf_size": leaf, "precision": a.precision,
             "rms_rel_force_err": main_r["err"],
         },
         "roofline": {
-            "bound": "mfma", "kernel": "m2l", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": measured_traffic(p, a.leaf, a.precision, cr.n),
-            "algorithmic": f"2 K^2 flops per M2L pair, K=(p+1)^2={K}, {int(main_r['wc'][2])} pairs per launch",
+            "bound": bound, "kernel": kernel, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": measured_traffic(kernel, p, leaf, a.precision, cr.n),
+            "algorithmic": algorithmic,
         },
         "details": {
-            "force_evals_per_s": 1e3 / main_r["phases"][5],
-            "phase_ms": {k: float(v) for k, v in zip(["tree", "upward", "m2l_kernel", "m2l_reduce_l2l", "eval", "total"],
-                                                     main_r["phases"])},
+            "force_evals_per_s": 1e3 / ph[6],
+            "phase_ms": {k: float(v) for k, v in zip(PHASES, ph)},
             "direct_sum_ms": float(dir_ms),
             "boxes": int(main_r["wc"][0]), "leaves": int(main_r["wc"][1]), "m2l_pairs": int(main_r["wc"][2]),
             "p2p_pairs": int(main_r["wc"][3]),
+            "m2l_tflops": m2l_tflops,
+            "p2p_pairs_per_s": main_r["wc"][3] / (ph[4] * 1e-3),
         },
     }
     if "fp64" in results and a.precision == "mixed":
@@ -308,7 +353,7 @@ def main():
         out["details"]["fp64_rms_rel_force_err"] = f["err"]
         out["details"]["mixed_speedup_vs_fp64"] = f["seconds"] / main_r["seconds"]
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cr, p, a.leaf, F_dir)
+        out["cpu_baseline"] = cpu_baseline(cr, p, leaf, F_dir)
         out["details"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -149,14 +149,15 @@ pt_status pt_debug_export_tree(pt_crystal *c, int64_t sizes[4], uint64_t *keys, 
                                int32_t *near_src, double *root);
 
 /* Per-phase GPU time of force evaluations, measured with HIP events on the
- * context stream: ms[0] sort+tree+lists, [1] P2M+M2M, [2] M2L, [3] L2L,
- * [4] L2P+P2P (the direct kernel for the direct method), [5] total --
- * each the mean over the evaluations since timing was last switched on
- * (count receives their number; may be NULL).  pt_ctx_set_timing(ctx, 1)
- * starts a new measurement; with timing on, each evaluation waits for the
- * previous one's events before it is queued. */
+ * context stream: ms[0] sort+tree+lists, [1] P2M+M2M, [2] the M2L
+ * matrix-core kernel, [3] M2L reduction + L2L, [4] the P2P kernel, [5] L2P
+ * plus the near-field partial sums, [6] total (the direct method has all
+ * its time in [0]) -- each the mean over the evaluations since timing was
+ * last switched on (count receives their number; may be NULL).
+ * pt_ctx_set_timing(ctx, 1) starts a new measurement; with timing on, each
+ * evaluation waits for the previous one's events before it is queued. */
 pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable);
-pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[6], int64_t *count);
+pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[7], int64_t *count);
 
 /* Work counts of the last FMM evaluation: [0] boxes, [1] leaves, [2] M2L
  * pairs, [3] P2P pairs (ordered, i != j counted), [4] levels, [5] ions. */

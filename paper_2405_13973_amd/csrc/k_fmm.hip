@@ -24,19 +24,26 @@ __global__ void k_zero_i32(int32_t *__restrict__ p, int n)
     if (i < n) p[i] = 0;
 }
 
-// P2M: one 64-thread block per leaf.  Ions are taken 32 at a time: each of
-// the first 32 threads evaluates conj(Rh_n^m) of its ion for all (n, m) by
-// one pass of the recurrences into an LDS tile [coefficient][ion]; then every
-// thread sums its coefficients over the tile's ions in ascending order.
-constexpr int kP2MIons = 32;
+// P2M: one 64-thread block per leaf.  Ions are taken `chunk` (64, or 32 when
+// the tile would exceed 64 KiB) at a time: each thread evaluates conj(Rh_n^m) of its ion for all (n, m) by one pass of the
+// recurrences into an LDS tile [coefficient][ion]; then each thread sums its
+// coefficients over the tile's ions, in four interleaved partial sums (ions
+// j = 0, 1, 2, 3 mod 4) added in a fixed order, which keeps the LDS reads
+// independent of one another.
 constexpr int kP2MMaxPer = 8;  // coefficients per thread: Kp <= 512
 
 template <typename T>
+static int p2m_chunk(int Kp, int leaf_size)
+{
+    return leaf_size > 32 && (size_t)Kp * 65 * sizeof(T) <= 65536 ? 64 : 32;
+}
+
+template <typename T>
 __global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const double *__restrict__ sp, int ntot, int p, int Kp,
-                                            const T *__restrict__ rec, T *__restrict__ M)
+                                            int chunk, const T *__restrict__ rec, T *__restrict__ M)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *C = reinterpret_cast<T *>(smem_raw);  // [Kp][kP2MIons + 1]
+    T *C = reinterpret_cast<T *>(smem_raw);  // [Kp][chunk + 1]
     __shared__ T rec_s[2 * kq(kMaxP)];      // the recurrence fields the expansion needs
     const int b = blockIdx.x;
     if (!bt.leaf[b]) return;
@@ -46,12 +53,12 @@ __global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const double *__restric
     for (int i = threadIdx.x; i < 2 * kq(p); i += 64) rec_s[i] = rec[i];
     __syncthreads();
     const int i0 = bt.begin[b], i1 = bt.end[b];
-    constexpr int ld = kP2MIons + 1;
+    const int ld = chunk + 1;  // odd: the rows of a column fall in distinct banks
     T acc[kP2MMaxPer];
 #pragma unroll
     for (int r = 0; r < kP2MMaxPer; ++r) acc[r] = T(0);
-    for (int c0 = i0; c0 < i1; c0 += kP2MIons) {
-        const int cnt = min(kP2MIons, i1 - c0);
+    for (int c0 = i0; c0 < i1; c0 += chunk) {
+        const int cnt = min(chunk, i1 - c0);
         if ((int)threadIdx.x < cnt) {
             const int i = c0 + threadIdx.x;
             p2m_terms<T>(p, rec_s, (T)((sp[i] - g.x) * ih), (T)((sp[ntot + i] - g.y) * ih),
@@ -61,8 +68,21 @@ __global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const double *__restric
 #pragma unroll
         for (int r = 0; r < kP2MMaxPer; ++r) {
             const int s = threadIdx.x + 64 * r;
-            if (s < K)
-                for (int j = 0; j < cnt; ++j) acc[r] += C[s * ld + j];
+            if (s < K) {
+                const T *row = C + s * ld;
+                T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+                int j = 0;
+                for (; j + 4 <= cnt; j += 4) {
+                    s0 += row[j];
+                    s1 += row[j + 1];
+                    s2 += row[j + 2];
+                    s3 += row[j + 3];
+                }
+                if (j < cnt) s0 += row[j];
+                if (j + 1 < cnt) s1 += row[j + 1];
+                if (j + 2 < cnt) s2 += row[j + 2];
+                acc[r] += (s0 + s1) + (s2 + s3);
+            }
         }
         __syncthreads();
     }
@@ -131,7 +151,6 @@ __global__ void k_m2l_bucket(BoxTable bt, int nbox, int32_t *__restrict__ cnt, i
 constexpr int kM2LWaves = 4;           // 16 target columns per wave
 constexpr int kM2LCols = 16 * kM2LWaves;
 constexpr int kM2LRB = 12;             // row blocks (of 16) per workgroup: Kp <= 192 in one pass
-constexpr int kXKC = 16;               // k-chunk staged per pipeline step (divides Kp)
 
 // One translation GEMM serves M2L, M2M and L2L:
 //   out[t] (op) sum over slots s of  A[op(s)] * X[src(t, s)]
@@ -160,19 +179,21 @@ constexpr int kXSlots = 32;  // slots per workgroup, at most
 // Software-pipelined: the (slot, k-chunk) steps of a tile run as one
 // sequence; the loads of step i+1 are issued into registers before the
 // matrix-core work of step i, so their latency overlaps it.  NRB (row blocks
-// of 16 per workgroup) is a compile-time constant so the matrix-core loop
-// has no branches.  Every load is unconditional: k-chunks of 16 divide Kp,
+// of 16 per workgroup) and KC (the k-chunk of a step: 16, or 48 for small
+// grids, where the chain of steps rather than the matrix cores bounds the
+// time) are compile-time constants so the matrix-core loop has no branches;
+// neither changes the order in which a target's terms are accumulated.
+// Every load is unconditional: k-chunks divide Kp,
 // rows past Kp (PARTIAL row groups only) read an in-bounds address and are
 // replaced by zero, and a missing source reads X[zrow], an expansion row
 // kept at zero.
 // ROLE only names the kernel symbol (0 M2L, 1 M2M, 2 L2L) so that profiles
 // tell the three uses apart.
-template <typename T, int NRB, bool PARTIAL, int ROLE>
+template <typename T, int NRB, bool PARTIAL, int ROLE, int KC>
 __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *__restrict__ At,
                                                          const T *__restrict__ X, T *__restrict__ out)
 {
     using MF = Mfma<T>;
-    constexpr int KC = kXKC;
     constexpr int ROWS = NRB * 16;
     constexpr int NT = 64 * kM2LWaves;
     constexpr int kXA = KC * ROWS / NT;  // operator values staged per thread (exact)
@@ -210,7 +231,12 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
         a_ok[j] = !PARTIAL || row0 + r < Kp;
         a_off[j] = a_ok[j] ? kk * Kp + r : 0;
     }
-    const int b_t = tid / KC, b_k = tid - (tid / KC) * KC;  // kXB == 4: targets b_t + 16 j
+    int b_t[kXB], b_k[kXB];  // source values staged per thread: target, k
+#pragma unroll
+    for (int j = 0; j < kXB; ++j) {
+        b_t[j] = (tid + NT * j) / KC;
+        b_k[j] = (tid + NT * j) % KC;
+    }
     T ra[kXA], rb_[kXB];
     auto load_step = [&](int step) {
         const int q = step / nchunk;
@@ -223,7 +249,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
             ra[j] = PARTIAL ? (a_ok[j] ? v : T(0)) : v;
         }
 #pragma unroll
-        for (int j = 0; j < kXB; ++j) rb_[j] = X[(size_t)src_s[sl][b_t + 16 * j] * Kp + k0 + b_k];
+        for (int j = 0; j < kXB; ++j) rb_[j] = X[(size_t)src_s[sl][b_t[j]] * Kp + k0 + b_k[j]];
     };
     for (int tile = tile0; tile * kM2LCols < n; tile += a.tile_stride) {
         __syncthreads();  // previous tile finished with the shared arrays
@@ -278,9 +304,11 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
             __syncthreads();  // the previous step is done reading As / Bsh
 #pragma unroll
             for (int j = 0; j < kXA; ++j) (&As[0][0])[tid + NT * j] = ra[j];
-            const bool bneg = __popc(mask & cbits_s[k0 + b_k]) & 1;
 #pragma unroll
-            for (int j = 0; j < kXB; ++j) Bsh[b_t + 16 * j][b_k] = bneg ? -rb_[j] : rb_[j];
+            for (int j = 0; j < kXB; ++j) {
+                const bool bneg = __popc(mask & cbits_s[k0 + b_k[j]]) & 1;
+                Bsh[b_t[j]][b_k[j]] = bneg ? -rb_[j] : rb_[j];
+            }
             if (mask != cur) {
                 resign(mask ^ cur);
                 cur = mask;
@@ -316,27 +344,47 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
     }
 }
 
-// Row blocks per workgroup for Kp: one pass when Kp <= 192, else equal groups.
-static int xlate_nrb(int Kp, int &nrowgrp)
+// Row groups of a translation GEMM: the Kp output rows (Kp / 16 blocks of 16)
+// are split over nrowgrp workgroups, each holding ceil(blocks / nrowgrp)
+// blocks (at most kM2LRB).  Small problems take more row groups, so that the
+// grid still fills the chip (about kXMinGrid workgroups); the split does not
+// change any summation order.
+constexpr long kXMinGrid = 128;
+constexpr long kXWideGrid = 768;
+static void xlate_rows(XlateArgs &a, long base_grid)
 {
-    const int blocks = Kp / 16;
-    nrowgrp = ceil_div(blocks, kM2LRB);
-    return ceil_div(blocks, nrowgrp);
+    const int blocks = a.Kp / 16;
+    int nrg = ceil_div(blocks, kM2LRB);
+    while (nrg < blocks && base_grid * nrg < kXMinGrid) {
+        // next row-group count that shrinks the per-workgroup block count
+        const int nrb = ceil_div(blocks, nrg);
+        while (nrg < blocks && ceil_div(blocks, nrg) == nrb) ++nrg;
+    }
+    a.nrowgrp = nrg;
 }
 
 template <typename T, int ROLE>
 static void launch_xlate(const XlateArgs &a, int grid, const T *At, const T *X, T *out, hipStream_t st)
 {
-    int nrg;
-    const int nrb = xlate_nrb(a.Kp, nrg);
-    const bool partial = nrb * 16 * nrg != a.Kp;
-    switch (nrb * 2 + (partial ? 1 : 0)) {
-#define PT_XL(NB)                                                                       \
-    case 2 * NB: k_xlate<T, NB, false, ROLE><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break; \
-    case 2 * NB + 1: k_xlate<T, NB, true, ROLE><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break;
+    const int blocks = a.Kp / 16;
+    const int nrb = ceil_div(blocks, a.nrowgrp);
+    const bool partial = nrb * a.nrowgrp != blocks;
+    // k-chunks of 48 when the grid is too small to hide a step's load
+    // latency behind other workgroups' matrix-core work
+    const bool wide = a.Kp % 48 == 0 && (long)grid < kXWideGrid;
+    switch ((nrb * 2 + (partial ? 1 : 0)) * 2 + (wide ? 1 : 0)) {
+#define PT_XL(NB)                                                                                       \
+    case 4 * NB: k_xlate<T, NB, false, ROLE, 16><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break; \
+    case 4 * NB + 2: k_xlate<T, NB, true, ROLE, 16><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break;
+#define PT_XLW(NB)                                                                                      \
+    case 4 * NB + 1: k_xlate<T, NB, false, ROLE, 48><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break; \
+    case 4 * NB + 3: k_xlate<T, NB, true, ROLE, 48><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break;
         PT_XL(1) PT_XL(2) PT_XL(3) PT_XL(4) PT_XL(5) PT_XL(6) PT_XL(7) PT_XL(8) PT_XL(9) PT_XL(10) PT_XL(11)
         PT_XL(12)
+        PT_XLW(1) PT_XLW(2) PT_XLW(3) PT_XLW(4) PT_XLW(5) PT_XLW(6) PT_XLW(7) PT_XLW(8) PT_XLW(9) PT_XLW(10)
+        PT_XLW(11) PT_XLW(12)
 #undef PT_XL
+#undef PT_XLW
     default: break;
     }
 }
@@ -397,6 +445,9 @@ struct Vec4<double> {
 // 1/sqrt(x) in the arithmetic type: the hardware reciprocal square root for
 // FP32 (1 ulp), the library routine for FP64.
 __device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+// Largest 1/r (1/m) of a near-field pair: separations below 1e-12 m are taken
+// as 1e-12 m (1/r^3 stays finite in FP32); only r = 0 reaches it in practice.
+constexpr double kRinvMax = 1e12;
 __device__ inline double rsqrt_t(double x) { return rsqrt(x); }
 
 template <typename T>
@@ -495,10 +546,11 @@ __global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restric
                     const V4 v = src[q];
                     const T dx = xi - v.x, dy = yi - v.y, dz = zi - v.z;
                     const T r2 = dx * dx + dy * dy + dz * dz;
-                    // r2 == 0: the target itself (offsets are bit-identical) or a
-                    // coincident ion, both contribute nothing
-                    const T rinv = rsqrt_t(r2);
-                    const T ww = r2 > T(0) ? rinv * rinv * rinv : T(0);
+                    // r2 == 0 (the target itself: offsets are bit-identical, or a
+                    // coincident ion) gives rinv = inf, capped at kRinvMax, and
+                    // then a zero contribution since dx = dy = dz = 0
+                    const T rinv = min(rsqrt_t(r2), T(kRinvMax));
+                    const T ww = rinv * rinv * rinv;
                     px += dx * ww;
                     py += dy * ww;
                     pz += dz * ww;
@@ -541,7 +593,7 @@ __global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restric
 // Far field (L2P) of every ion of a leaf plus its near-field item partials,
 // added in item order.  Writes the field per unit charge in batch order.
 template <typename T>
-__global__ __launch_bounds__(64) void k_far(BoxTable bt, const double *__restrict__ sp, int ntot, int p, int Kp,
+__global__ __launch_bounds__(256) void k_far(BoxTable bt, const double *__restrict__ sp, int ntot, int p, int Kp,
                                             const T *__restrict__ L, const T *__restrict__ rec,
                                             const uint32_t *__restrict__ item_off,
                                             const int32_t *__restrict__ src_items, const T *__restrict__ part,
@@ -553,12 +605,12 @@ __global__ __launch_bounds__(64) void k_far(BoxTable bt, const double *__restric
     if (!bt.leaf[b]) return;
     const double4 g = bt.geo[b];
     const double ih = 1.0 / g.w;
-    for (int i = threadIdx.x; i < kRecFields * kq(p); i += 64) rec_s[i] = rec[i];
-    for (int i = threadIdx.x; i < Kp; i += 64) Lb[i] = L[(size_t)b * Kp + i];
+    for (int i = threadIdx.x; i < kRecFields * kq(p); i += blockDim.x) rec_s[i] = rec[i];
+    for (int i = threadIdx.x; i < Kp; i += blockDim.x) Lb[i] = L[(size_t)b * Kp + i];
     __syncthreads();
     const int si = src_items[b];
     const uint32_t base = item_off[b];
-    for (int k = bt.begin[b] + threadIdx.x; k < bt.end[b]; k += 64) {
+    for (int k = bt.begin[b] + threadIdx.x; k < bt.end[b]; k += blockDim.x) {
         const int tl = k - bt.begin[b];
         const double xd = sp[k], yd = sp[ntot + k], zd = sp[2 * ntot + k];
         T ex, ey, ez;
@@ -584,7 +636,7 @@ static XlateArgs xlate_base(int Kp, int nbox)
     XlateArgs a{};
     a.nbucket = 1;
     a.ngroup = 1;
-    xlate_nrb(Kp, a.nrowgrp);
+    a.nrowgrp = 1;
     a.Kp = Kp;
     a.nbox = nbox;
     return a;
@@ -607,6 +659,7 @@ static void launch_level_xlate(const BoxTable &bt, int Kp, int nbox, int b0, int
     a.srctab = srctab;
     a.src_stride = 8;
     a.mode = 0;
+    xlate_rows(a, (long)tiles * a.ngroup);
     if (mode == 1) launch_xlate<T, 1>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, st);
     else launch_xlate<T, 2>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, st);
     const size_t tot = (size_t)n * Kp;
@@ -616,11 +669,13 @@ static void launch_level_xlate(const BoxTable &bt, int Kp, int nbox, int b0, int
 
 template <typename T>
 void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *m2m_pad,
-                   const int2 *oct_slots, const int32_t *child_oct, const T *rec, T *M, T *part, hipStream_t st)
+                   const int2 *oct_slots, const int32_t *child_oct, const T *rec, T *M, T *part, int leaf_size,
+                   hipStream_t st)
 {
     const int Kp = kpad(p);
-    const size_t smem = (size_t)Kp * (kP2MIons + 1) * sizeof(T);
-    if (hs.nbox > 0) k_p2m<T><<<hs.nbox, 64, smem, st>>>(bt, sp, ntot, p, Kp, rec, M);
+    const int chunk = p2m_chunk<T>(Kp, leaf_size);
+    const size_t smem = (size_t)Kp * (chunk + 1) * sizeof(T);
+    if (hs.nbox > 0) k_p2m<T><<<hs.nbox, 64, smem, st>>>(bt, sp, ntot, p, Kp, chunk, rec, M);
     // M2M level by level: parents of level l gather their children by octant
     for (int l = kMaxLevel - 1; l >= 2; --l) {
         const int b0 = hs.level_start[l], b1 = hs.level_start[l + 1];
@@ -656,6 +711,7 @@ void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t 
     a.srctab = vtab;
     a.src_stride = kWin;
     a.mode = 0;
+    xlate_rows(a, 8L * a.tile_stride * ngroup);
     launch_xlate<T, 0>(a, 8 * a.tile_stride * ngroup * a.nrowgrp, m2l_pad, M, part, st);
 }
 
@@ -689,19 +745,28 @@ void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *
 }
 
 template <typename T>
-void launch_eval(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
-                 const int2 *near, int stride, const int4 *work, int n_items, const uint32_t *item_off,
-                 const int32_t *src_items, T *part, const uint32_t *vals, double *E, hipStream_t st)
+void launch_near(const BoxTable &bt, const double *sp, int ntot, const int2 *near, int stride, const int4 *work,
+                 int n_items, T *part, hipStream_t st)
 {
     if (n_items > 0)
         k_p2p<T><<<std::min(n_items, 16384), 64, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part);
-    if (nbox > 0) k_far<T><<<nbox, 64, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E);
+}
+
+template <typename T>
+void launch_far(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
+                const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals, double *E,
+                int leaf_size, hipStream_t st)
+{
+    // one thread per ion of a leaf where the leaf size allows
+    const int tb = std::min(256, std::max(64, (leaf_size + 63) / 64 * 64));
+    if (nbox > 0) k_far<T><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E);
 }
 
 template void launch_upward<double>(const BoxTable &, const double *, int, int, const TreeSummary &, const double *,
-                                    const int2 *, const int32_t *, const double *, double *, double *, hipStream_t);
+                                    const int2 *, const int32_t *, const double *, double *, double *, int,
+                                    hipStream_t);
 template void launch_upward<float>(const BoxTable &, const double *, int, int, const TreeSummary &, const float *,
-                                   const int2 *, const int32_t *, const float *, float *, float *, hipStream_t);
+                                   const int2 *, const int32_t *, const float *, float *, float *, int, hipStream_t);
 template void launch_m2l<double>(const BoxTable &, int, const TreeSummary &, const int32_t *, const int2 *,
                                  const double *, const double *, const int32_t *, const int32_t *, double *, int,
                                  hipStream_t);
@@ -714,11 +779,15 @@ template void launch_downward<double>(const BoxTable &, int, const TreeSummary &
                                       const int32_t *, double *, double *, hipStream_t);
 template void launch_downward<float>(const BoxTable &, int, const TreeSummary &, const float *, const int2 *,
                                      const int32_t *, float *, float *, hipStream_t);
-template void launch_eval<double>(const BoxTable &, const double *, int, int, int, const double *, const double *,
-                                  const int2 *, int, const int4 *, int, const uint32_t *, const int32_t *, double *,
-                                  const uint32_t *, double *, hipStream_t);
-template void launch_eval<float>(const BoxTable &, const double *, int, int, int, const float *, const float *,
-                                 const int2 *, int, const int4 *, int, const uint32_t *, const int32_t *, float *,
-                                 const uint32_t *, double *, hipStream_t);
+template void launch_near<double>(const BoxTable &, const double *, int, const int2 *, int, const int4 *, int,
+                                   double *, hipStream_t);
+template void launch_near<float>(const BoxTable &, const double *, int, const int2 *, int, const int4 *, int, float *,
+                                  hipStream_t);
+template void launch_far<double>(const BoxTable &, const double *, int, int, int, const double *, const double *,
+                                  const uint32_t *, const int32_t *, const double *, const uint32_t *, double *, int,
+                                  hipStream_t);
+template void launch_far<float>(const BoxTable &, const double *, int, int, int, const float *, const float *,
+                                 const uint32_t *, const int32_t *, const float *, const uint32_t *, double *, int,
+                                 hipStream_t);
 
 }  // namespace pt

@@ -71,7 +71,8 @@ void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, cons
 // oct_slots: the 8 slots {octant, octant}; child_oct / parent_oct: 8 x nbox.
 template <typename T>
 void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *m2m_pad,
-                   const int2 *oct_slots, const int32_t *child_oct, const T *rec, T *M, T *part, hipStream_t st);
+                   const int2 *oct_slots, const int32_t *child_oct, const T *rec, T *M, T *part, int leaf_size,
+                   hipStream_t st);
 // m2l_pad: 64 base operators (offsets with non-negative components, index
 // m2l_base), each Kp x Kp column-major (A[j][i] = T[i][j]), zero-padded;
 // slots: per parity the 189 non-touching window slots {slot, base operator +
@@ -88,11 +89,14 @@ int m2l_groups(int n2);  // slot groups of M2L (partial-sum buffer: groups x nbo
 template <typename T>
 void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_pad, const int2 *oct_slots,
                      const int32_t *parent_oct, T *L, T *part, hipStream_t st);
-// Near field over the work items into part (item x 64 x 3), then far field +
-// item partials per ion into E (batch order).
+// Near field over the work items into part (item x 64 x 3).
 template <typename T>
-void launch_eval(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
-                 const int2 *near, int stride, const int4 *work, int n_items, const uint32_t *item_off,
-                 const int32_t *src_items, T *part, const uint32_t *vals, double *E, hipStream_t st);
+void launch_near(const BoxTable &bt, const double *sp, int ntot, const int2 *near, int stride, const int4 *work,
+                 int n_items, T *part, hipStream_t st);
+// Far field (L2P) + the item partials per ion into E (batch order).
+template <typename T>
+void launch_far(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
+                const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals, double *E,
+                int leaf_size, hipStream_t st);
 
 }  // namespace pt

@@ -87,6 +87,10 @@ struct pt_crystal {
     int32_t *d_photons = nullptr;
 };
 
+// Timed phases of a force evaluation (events 0..6 bracket them): sort+tree+
+// lists, P2M+M2M, M2L, M2L reduce+L2L, P2P, L2P + near-field partials, total.
+constexpr int kPhases = 7;
+
 struct pt_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -111,8 +115,8 @@ struct pt_ctx {
     TreeSummary last_sum{};
     // timing
     int timing = 0, timing_pending = 0;
-    hipEvent_t ev[7] = {};
-    double phase_sum[6] = {0, 0, 0, 0, 0, 0};
+    hipEvent_t ev[kPhases] = {};
+    double phase_sum[kPhases] = {};
     int64_t phase_count = 0;
 };
 
@@ -398,11 +402,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     mark(ctx, 0);
     if (fp.method == 0) {
         launch_direct(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, ntot, E, st);
-        mark(ctx, 1);
-        mark(ctx, 2);
-        mark(ctx, 3);
-        mark(ctx, 4);
-        mark(ctx, 5);
+        for (int i = 1; i <= kPhases - 1; ++i) mark(ctx, i);
         ctx->timing_pending = ctx->timing;
         return PT_OK;
     }
@@ -510,7 +510,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         const T *m2l = f ? (const T *)tb.m2l_f : (const T *)tb.m2l_d;
         const T *l2l = f ? (const T *)tb.l2l_f : (const T *)tb.l2l_d;
         const T *rec = f ? (const T *)tb.rec_f : (const T *)tb.rec_d;
-        launch_upward<T>(bt, sp, ntot, p, hs, m2m, tb.oct_slots, child_oct, rec, (T *)M, (T *)m2l_part, st);
+        launch_upward<T>(bt, sp, ntot, p, hs, m2m, tb.oct_slots, child_oct, rec, (T *)M, (T *)m2l_part, s, st);
         launch_m2l_bucket(bt, nbox, m2l_cnt, m2l_list, st);
         mark(ctx, 2);
         launch_m2l<T>(bt, p, hs, vtab, tb.slots, m2l, (const T *)M, m2l_cnt, m2l_list, (T *)m2l_part, ngroup, st);
@@ -518,12 +518,13 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         launch_m2l_reduce<T>(bt, p, nbox, (const T *)m2l_part, ngroup, (T *)L, st);
         launch_downward<T>(bt, p, hs, l2l, tb.oct_slots, parent_oct, (T *)L, (T *)m2l_part, st);
         mark(ctx, 4);
-        launch_eval<T>(bt, sp, ntot, p, nbox, (const T *)L, rec, near, stride, work, n_items, item_off, src_items,
-                       (T *)ppart, v0, E, st);
+        launch_near<T>(bt, sp, ntot, near, stride, work, n_items, (T *)ppart, st);
+        mark(ctx, 5);
+        launch_far<T>(bt, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E, s, st);
     };
     if (fp.precision == 1) run(float(0));
     else run(double(0));
-    mark(ctx, 5);
+    mark(ctx, 6);
     ctx->timing_pending = ctx->timing;
     ctx->last_sum = hs;
     ctx->last_stride = stride;
@@ -538,14 +539,14 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
 static pt_status finish_timing(pt_ctx *ctx)
 {
     if (!ctx->timing || !ctx->timing_pending) return PT_OK;
-    PT_HIP(hipEventSynchronize(ctx->ev[5]));
+    PT_HIP(hipEventSynchronize(ctx->ev[kPhases - 1]));
     float ms;
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < kPhases - 1; ++i) {
         PT_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
         ctx->phase_sum[i] += ms;
     }
-    PT_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[5]));
-    ctx->phase_sum[5] += ms;
+    PT_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[kPhases - 1]));
+    ctx->phase_sum[kPhases - 1] += ms;
     ctx->phase_count++;
     ctx->timing_pending = 0;
     return PT_OK;
@@ -931,11 +932,11 @@ pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable)
     return PT_OK;
 }
 
-pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[6], int64_t *count)
+pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[7], int64_t *count)
 {
     PT_REQUIRE(ctx && ms, "NULL argument");
     PT_TRY(finish_timing(ctx));
-    for (int i = 0; i < 6; ++i) ms[i] = ctx->phase_count ? ctx->phase_sum[i] / (double)ctx->phase_count : 0.0;
+    for (int i = 0; i < kPhases; ++i) ms[i] = ctx->phase_count ? ctx->phase_sum[i] / (double)ctx->phase_count : 0.0;
     if (count) *count = ctx->phase_count;
     return PT_OK;
 }
