@@ -148,12 +148,14 @@ pt_status pt_debug_export_tree(pt_crystal *c, int64_t sizes[4], uint64_t *keys, 
                                uint8_t *is_leaf, int32_t *v_off, int32_t *v_src, int32_t *near_off,
                                int32_t *near_src, double *root);
 
-/* Per-phase GPU time of force evaluations, measured with HIP events on the
- * context stream: ms[0] sort+tree+lists, [1] P2M+M2M, [2] the M2L
- * matrix-core kernel, [3] M2L reduction + L2L, [4] the P2P kernel, [5] L2P
- * plus the near-field partial sums, [6] total (the direct method has all
- * its time in [0]) -- each the mean over the evaluations since timing was
- * last switched on (count receives their number; may be NULL).
+/* Per-phase GPU time of force evaluations, measured with HIP events:
+ * ms[0] sort+tree+lists, [1] P2M+M2M, [2] the M2L matrix-core kernel,
+ * [3] M2L reduction + L2L, [4] the P2P kernel (it runs on a second stream
+ * of the context, concurrently with [1]-[3]), [5] waiting for the P2P
+ * kernel plus L2P and the near-field partial sums, [6] total (the direct
+ * method has all its time in [0]) -- each the mean over the evaluations
+ * since timing was last switched on (count receives their number; may be
+ * NULL).
  * pt_ctx_set_timing(ctx, 1) starts a new measurement; with timing on, each
  * evaluation waits for the previous one's events before it is queued. */
 pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable);

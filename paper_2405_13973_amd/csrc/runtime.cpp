@@ -95,6 +95,12 @@ struct pt_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // the near field runs on its own stream, beside the far-field chain;
+    // fork / join events order it after the lists and before the L2P kernel
+    hipStream_t near_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_near[2] = {};  // timing of the P2P kernel on near_stream
+    bool near_timed = false;
     uint64_t budget = 0, used = 0;
     int live = 0;
     std::map<void *, size_t> allocs;
@@ -399,6 +405,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     ctx->last_ntot = ntot;
     ctx->last_was_fmm = fp.method == 1;
     PT_TRY(finish_timing(ctx));  // the event set is reused: collect the previous evaluation first
+    ctx->near_timed = false;
     mark(ctx, 0);
     if (fp.method == 0) {
         launch_direct(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, ntot, E, st);
@@ -503,7 +510,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     const Tables &tb = ctx->tables;
     launch_zero_u64((uint64_t *)((char *)M + esz * Kp * (size_t)nbox), (int)(esz * Kp / 8), st);
     launch_zero_u64((uint64_t *)((char *)L + esz * Kp * (size_t)nbox), (int)(esz * Kp / 8), st);
-    auto run = [&](auto tag) {
+    auto run = [&](auto tag) -> pt_status {
         using T = decltype(tag);
         const bool f = sizeof(T) == sizeof(float);
         const T *m2m = f ? (const T *)tb.m2m_f : (const T *)tb.m2m_d;
@@ -512,18 +519,28 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         const T *rec = f ? (const T *)tb.rec_f : (const T *)tb.rec_d;
         launch_upward<T>(bt, sp, ntot, p, hs, m2m, tb.oct_slots, child_oct, rec, (T *)M, (T *)m2l_part, s, st);
         launch_m2l_bucket(bt, nbox, m2l_cnt, m2l_list, st);
+        // near field on its own stream, concurrently with M2L and L2L (vector
+        // ALUs beside matrix cores); it starts once the upward pass is done,
+        // so that the two dispatch together, and joins before the L2P kernel
+        PT_HIP(hipEventRecord(ctx->ev_fork, st));
+        PT_HIP(hipStreamWaitEvent(ctx->near_stream, ctx->ev_fork, 0));
+        if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[0], ctx->near_stream));
+        launch_near<T>(bt, sp, ntot, near, stride, work, n_items, (T *)ppart, ctx->near_stream);
+        if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[1], ctx->near_stream));
+        ctx->near_timed = ctx->timing;
+        PT_HIP(hipEventRecord(ctx->ev_join, ctx->near_stream));
         mark(ctx, 2);
         launch_m2l<T>(bt, p, hs, vtab, tb.slots, m2l, (const T *)M, m2l_cnt, m2l_list, (T *)m2l_part, ngroup, st);
         mark(ctx, 3);
         launch_m2l_reduce<T>(bt, p, nbox, (const T *)m2l_part, ngroup, (T *)L, st);
         launch_downward<T>(bt, p, hs, l2l, tb.oct_slots, parent_oct, (T *)L, (T *)m2l_part, st);
         mark(ctx, 4);
-        launch_near<T>(bt, sp, ntot, near, stride, work, n_items, (T *)ppart, st);
         mark(ctx, 5);
+        PT_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
         launch_far<T>(bt, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E, s, st);
+        return PT_OK;
     };
-    if (fp.precision == 1) run(float(0));
-    else run(double(0));
+    PT_TRY(fp.precision == 1 ? run(float(0)) : run(double(0)));
     mark(ctx, 6);
     ctx->timing_pending = ctx->timing;
     ctx->last_sum = hs;
@@ -542,7 +559,9 @@ static pt_status finish_timing(pt_ctx *ctx)
     PT_HIP(hipEventSynchronize(ctx->ev[kPhases - 1]));
     float ms;
     for (int i = 0; i < kPhases - 1; ++i) {
-        PT_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+        // phase 4: the P2P kernel on its own stream (it overlaps phases 1-3)
+        if (i == 4 && ctx->near_timed) PT_HIP(hipEventElapsedTime(&ms, ctx->ev_near[0], ctx->ev_near[1]));
+        else PT_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
         ctx->phase_sum[i] += ms;
     }
     PT_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[kPhases - 1]));
@@ -616,6 +635,10 @@ pt_status pt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, void *hip_str
     PT_HIP(hipHostMalloc((void **)&ctx->h_sum, sizeof(TreeSummary)));
     PT_HIP(hipHostMalloc((void **)&ctx->h_counters, sizeof(unsigned long long) * 2));
     for (auto &e : ctx->ev) PT_HIP(hipEventCreate(&e));
+    PT_HIP(hipStreamCreateWithFlags(&ctx->near_stream, hipStreamNonBlocking));
+    PT_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    PT_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    for (auto &e : ctx->ev_near) PT_HIP(hipEventCreate(&e));
     *out = ctx.release();
     return PT_OK;
 }
@@ -629,6 +652,7 @@ pt_status pt_ctx_destroy(pt_ctx *ctx)
     }
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->near_stream) (void)hipStreamSynchronize(ctx->near_stream);
     for (auto &kv : ctx->allocs) (void)hipFree(kv.first);
     ctx->allocs.clear();
     if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
@@ -636,6 +660,9 @@ pt_status pt_ctx_destroy(pt_ctx *ctx)
     if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_near[0], ctx->ev_near[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->near_stream) (void)hipStreamDestroy(ctx->near_stream);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return PT_OK;
