@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--chunk", type=int, default=50, help="serving: steps per tick")
     ap.add_argument("--budget-gb", type=int, default=64, help="serving: HBM budget for resident crystals")
+    ap.add_argument("--roofline", choices=["auto", "m2l", "p2p"], default="auto",
+                    help="kernel of the roofline entry (auto: the one with the longer measured time)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB first (reference kernel for HBM byte counters)")
     a = ap.parse_args()
@@ -302,7 +304,7 @@ def main():
     m2l_tflops = 2.0 * K * K * main_r["wc"][2] / (ph[2] * 1e-3) / 1e12
     p2p_tflops = P2P_FLOPS_PER_PAIR * main_r["wc"][3] / (ph[4] * 1e-3) / 1e12
     # roofline of the dominant kernel: M2L (matrix cores) or P2P (vector ALUs)
-    if ph[2] >= ph[4]:
+    if a.roofline == "m2l" or (a.roofline == "auto" and ph[2] >= ph[4]):
         kernel, bound, achieved = "m2l", "mfma", m2l_tflops
         peak = PEAK["mfma_fp32" if fp32 else "mfma_fp64"]
         algorithmic = f"2 K^2 flops per M2L pair, K=(p+1)^2={K}, {int(main_r['wc'][2])} pairs per launch"

@@ -422,42 +422,35 @@ __global__ void k_m2l_reduce(BoxTable bt, int nbox, int Kp, int ngroup, const T 
 // Near field (P2P) of one work item per 64-thread workgroup (grid-stride over
 // the items): up to 64 targets of a leaf against the sources of a run of its
 // near ranges.  The ranges are concatenated and staged through LDS
-// kP2PStage sources at a time, as offsets from the target leaf's centre (one
-// FP64 subtraction per source and item, then rounded to T), so the pair loop
-// reads only LDS and a barrier pair serves hundreds of sources rather than one
-// leaf.  An item with nt targets gives each target floor(64 / nt) threads
-// (phases), which take source blocks round robin; within a block sources are
-// summed plainly and each block is added to the phase's total with Kahan
-// compensation.  The phases of a target are then added in phase order.
+// kP2PStage sources at a time as FP64 positions, so the pair loop reads only
+// LDS and a barrier pair serves hundreds of sources rather than one leaf.
+// Each pair's separation is an FP64 difference rounded once to T: close
+// pairs keep full relative precision (offsets rounded to FP32 first would
+// carry an absolute error of order 1e-7 of the box size into every
+// separation, and the rare very close pairs of random crystals dominate an
+// RMS force error).  An item with nt targets gives each target
+// floor(64 / nt) threads (phases), which take source blocks round robin;
+// within a block sources are summed plainly and each block is added to the
+// phase's total with Kahan compensation.  The phases of a target are then
+// added in phase order.
 // Partial fields go to part[item][target][3].
 constexpr int kP2PStage = 512;
-template <typename T>
-struct Vec4;
-template <>
-struct Vec4<float> {
-    typedef float4 type;
-};
-template <>
-struct Vec4<double> {
-    typedef double4 type;
-};
 
 // 1/sqrt(x) in the arithmetic type: the hardware reciprocal square root for
 // FP32 (1 ulp), the library routine for FP64.
 __device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsqrt_t(double x) { return rsqrt(x); }
 // Largest 1/r (1/m) of a near-field pair: separations below 1e-12 m are taken
 // as 1e-12 m (1/r^3 stays finite in FP32); only r = 0 reaches it in practice.
 constexpr double kRinvMax = 1e12;
-__device__ inline double rsqrt_t(double x) { return rsqrt(x); }
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restrict__ sp, int ntot,
                                             const int2 *__restrict__ near, int stride, const int4 *__restrict__ work,
                                             int n_items, T *__restrict__ part)
 {
-    using V4 = typename Vec4<T>::type;
     constexpr int kU = kP2PStage / 64;
-    __shared__ V4 src[kP2PStage];
+    __shared__ double4 src[kP2PStage];
     __shared__ int pre_s[kNearMax + 1];  // prefix of the item's range lengths
     __shared__ int beg_s[kNearMax];      // first ion of each range minus its prefix
     __shared__ T hx[64], hy[64], hz[64];
@@ -465,14 +458,13 @@ __global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restric
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int4 w = work[it];
         const int b = w.x;
-        const double4 g = bt.geo[b];
         const int2 *row = near + (size_t)b * stride;
         const int nt = max(1, min(64, bt.end[b] - w.y));
         const int nph = 64 / nt;                                     // phases per target
         const int blk = nph == 1 ? 64 : (nph <= 3 ? 32 : 16);        // sources per block
         const int ti = lane % nt, ph = lane / nt;                    // ph >= nph: idle lane
         const int k = w.y + ti;
-        const T xi = (T)(sp[k] - g.x), yi = (T)(sp[ntot + k] - g.y), zi = (T)(sp[2 * ntot + k] - g.z);
+        const double xi = sp[k], yi = sp[ntot + k], zi = sp[2 * ntot + k];
         const int nr = min(w.w - w.z, kNearMax);
         __syncthreads();  // the previous item is done with the shared arrays
         int total = 0;
@@ -529,22 +521,15 @@ __global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restric
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u)
-                if (js[u] >= 0) {
-                    V4 v;
-                    v.x = (T)(sx[u] - g.x);
-                    v.y = (T)(sy[u] - g.y);
-                    v.z = (T)(sz[u] - g.z);
-                    v.w = T(0);
-                    src[lane + 64 * u] = v;
-                }
+                if (js[u] >= 0) src[lane + 64 * u] = make_double4(sx[u], sy[u], sz[u], 0.0);
             __syncthreads();
             for (int q0 = ph < nph ? ph * blk : n; q0 < n; q0 += nph * blk) {
                 const int q1 = min(n, q0 + blk);
                 T px = 0, py = 0, pz = 0;
 #pragma unroll 4
                 for (int q = q0; q < q1; ++q) {
-                    const V4 v = src[q];
-                    const T dx = xi - v.x, dy = yi - v.y, dz = zi - v.z;
+                    const double4 v = src[q];
+                    const T dx = (T)(xi - v.x), dy = (T)(yi - v.y), dz = (T)(zi - v.z);
                     const T r2 = dx * dx + dy * dy + dz * dz;
                     // r2 == 0 (the target itself: offsets are bit-identical, or a
                     // coincident ion) gives rinv = inf, capped at kRinvMax, and
