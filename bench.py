@@ -214,7 +214,7 @@ def main():
                     help="config3: 1e5-ion crystal (default); ensemble: 256 crystals batched; serving: request stream")
     ap.add_argument("--p", type=int, default=12, help="expansion degree for the ensemble / serving workloads")
     ap.add_argument("--crystals", type=int, default=256)
-    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--chunk", type=int, default=50, help="serving: steps per tick")
     ap.add_argument("--budget-gb", type=int, default=64, help="serving: HBM budget for resident crystals")
     ap.add_argument("--roofline", choices=["auto", "m2l", "p2p"], default="auto",

@@ -1,0 +1,220 @@
+"""System tests on the GPU, through the C ABI: the benchmark configurations at
+their own sizes, checkpoint/resume, determinism, failure paths and admission
+under a small memory budget.
+
+Bars (derivations in the design doc):
+  - config 1, 100 FMM steps (FP64, p = 8, leaf 32) against the oracle run:
+    positions within 1e-10 and velocities within 1e-8 of their rms; the
+    per-step force parity is 1e-11 and 100 steps of 1 ns stay far inside
+    the crystal's divergence time.
+  - config 2: FP64 FMM error against the direct sum falls geometrically from
+    p = 4 to 8 to 12 (by more than 4x per 4 degrees; about 0.55 per degree is
+    seen), and is <= 1e-6 at p = 12 in FP64 and mixed precision.
+  - config 3 (N = 1e5) in the benchmark's launch configuration (p = 11,
+    leaf 256, and leaf 32): FP64 FMM on sampled ions within 1e-11 of the
+    oracle FMM (max |dF| over the sample / rms over the sample); the mixed
+    form within 1e-6 RMS of the FP64 direct sum; GPU direct sum on sampled
+    ions within 1e-12 of the oracle's.
+  - checkpoint / resume and repeated runs: bit-identical.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_13973_amd import inputs, native, serving
+
+pytestmark = pytest.mark.gpu
+
+Q, M = inputs.ION_CHARGE, inputs.ION_MASS
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = native.Context(0)
+    yield c
+    c.close()
+
+
+def make(ctx, cr, method="direct", p=8, leaf=32, precision="fp64"):
+    c = ctx.crystal(cr.pos, cr.vel, cr.charge, cr.mass, cr.seed)
+    c.set_trap(B=cr.B, omega_z=cr.omega_z, delta=cr.delta, omega_r=cr.omega_r, dt=cr.dt)
+    c.set_laser(cr.photon_mean)
+    c.set_force(method, p, leaf, precision)
+    return c
+
+
+def rms(a):
+    return math.sqrt((np.linalg.norm(a, axis=1) ** 2).mean())
+
+
+def rms_rel(F, ref):
+    return math.sqrt(((F - ref) ** 2).sum() / (ref ** 2).sum())
+
+
+def sample(n, k=64):
+    return np.linspace(0, n - 1, k).astype(np.int32)
+
+
+# ---------------------------------------------------------------- configurations
+def test_config1_100_fmm_steps_match_oracle(ctx):
+    say("config1 100 FMM steps")
+    cr = inputs.config1()
+    c = make(ctx, cr, "fmm", 8, 32)
+    c.step(100)
+    st = c.read_state()
+    c.destroy()
+    x, v = O.run(cr.pos, cr.vel, Q, M, cr.trap(), cr.dt, 100, seed=cr.seed, method="fmm", p=8, leaf_size=32)
+    dx = np.linalg.norm(st["pos"] - x, axis=1).max() / rms(x)
+    dv = np.linalg.norm(st["vel"] - v, axis=1).max() / rms(v)
+    say(f"   max |dx| / rms = {dx:.2e}, max |dv| / rms = {dv:.2e}")
+    assert st["step"] == 100
+    assert dx <= 1e-10 and dv <= 1e-8
+
+
+def test_config2_fmm_error_falls_with_p(ctx):
+    say("config2 error vs p")
+    cr = inputs.config2()
+    c = make(ctx, cr)
+    F_dir = c.compute_forces()
+    idx = sample(cr.n)
+    ref = O.coulomb_direct_sampled(cr.pos, Q, idx)
+    assert np.linalg.norm(F_dir[idx] - ref, axis=1).max() / rms(ref) <= 1e-12
+    errs = {}
+    for p in (4, 8, 12):
+        c.set_force("fmm", p, 32, "fp64")
+        errs[p] = rms_rel(c.compute_forces(), F_dir)
+    c.set_force("fmm", 12, 32, "mixed")
+    mixed = rms_rel(c.compute_forces(), F_dir)
+    c.destroy()
+    say(f"   fp64 {errs}, mixed p=12 {mixed:.2e}")
+    assert errs[8] < errs[4] / 4 and errs[12] < errs[8] / 4
+    assert errs[12] <= 1e-6 and mixed <= 1e-6
+
+
+@pytest.mark.parametrize("leaf", [256, 32])
+def test_config3_full_size_sampled_parity(ctx, leaf):
+    say(f"config3 N=1e5 leaf {leaf}")
+    cr = inputs.config3()
+    idx = sample(cr.n)
+    c = make(ctx, cr, "fmm", 11, leaf, "fp64")
+    F64 = c.compute_forces()
+    ref = O.fmm_coulomb_sampled(cr.pos, Q, 11, leaf, idx)
+    dev = np.linalg.norm(F64[idx] - ref, axis=1).max() / rms(ref)
+    c.set_force("fmm", 11, leaf, "mixed")
+    Fmx = c.compute_forces()
+    c.set_force("direct")
+    F_dir = c.compute_forces()
+    c.destroy()
+    ref_dir = O.coulomb_direct_sampled(cr.pos, Q, idx)
+    ddev = np.linalg.norm(F_dir[idx] - ref_dir, axis=1).max() / rms(ref_dir)
+    e64, emx = rms_rel(F64, F_dir), rms_rel(Fmx, F_dir)
+    say(f"   FP64 FMM vs oracle FMM {dev:.2e}; direct vs oracle {ddev:.2e}; rms err fp64 {e64:.2e} mixed {emx:.2e}")
+    assert dev <= 1e-11
+    assert ddev <= 1e-12
+    assert e64 <= 1e-6 and emx <= 1e-6
+
+
+# ---------------------------------------------------------------- state
+def test_checkpoint_resume_is_bit_identical(ctx):
+    say("checkpoint / resume")
+    cr = inputs.config1(seed=11)
+    cr.photon_mean = 0.05
+    a = make(ctx, cr, "fmm", 8, 32, "mixed")
+    a.step(20)
+    mid = a.read_state()
+    b = make(ctx, cr, "fmm", 8, 32, "mixed")
+    b.set_state(mid["pos"], mid["vel"], mid["step"])
+    a.step(20)
+    b.step(20)
+    sa, sb = a.read_state(), b.read_state()
+    a.destroy()
+    b.destroy()
+    assert sa["step"] == sb["step"] == 40 and sa["t"] == sb["t"]
+    assert np.array_equal(sa["pos"], sb["pos"]) and np.array_equal(sa["vel"], sb["vel"])
+    assert np.array_equal(sa["photons"], sb["photons"])
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_repeated_runs_are_bit_identical(ctx, precision):
+    say(f"determinism {precision}")
+    cr = inputs.config2(seed=12)
+    out = []
+    for _ in range(2):
+        c = make(ctx, cr, "fmm", 10, 64, precision)
+        F = c.compute_forces()
+        c.step(5)
+        out.append((F, c.read_state()))
+        c.destroy()
+    (F0, s0), (F1, s1) = out
+    assert np.array_equal(F0, F1)
+    assert np.array_equal(s0["pos"], s1["pos"]) and np.array_equal(s0["vel"], s1["vel"])
+
+
+# ---------------------------------------------------------------- failure paths
+def expect(code, fn, *a, **k):
+    with pytest.raises(native.PTError) as e:
+        fn(*a, **k)
+    assert e.value.code == code, e.value
+
+
+def test_invalid_inputs_return_status_codes(ctx):
+    say("failure paths")
+    cr = inputs.config1(seed=13)
+    bad = cr.pos.copy()
+    bad[5, 1] = np.nan
+    expect(native.PT_EINVAL, ctx.crystal, bad, cr.vel, Q, M)
+    expect(native.PT_EINVAL, ctx.crystal, cr.pos, cr.vel, Q, -M)
+    expect(native.PT_EINVAL, ctx.crystal, cr.pos, cr.vel, 0.0, M)
+    c = make(ctx, cr)
+    expect(native.PT_EINVAL, c.set_trap, dt=0.0)
+    expect(native.PT_EINVAL, c.set_trap, B=float("nan"))
+    # unconfined: omega_c^2 <= 2 omega_z^2 (B = 0.1 T, f_z = 1.5 MHz for 9 u)
+    expect(native.PT_EINVAL, c.set_trap, B=0.1)
+    for p, leaf in ((0, 32), (21, 32), (8, 0), (8, 5000)):
+        expect(native.PT_EINVAL, c.set_force, "fmm", p, leaf)
+    expect(native.PT_EINVAL, c.set_laser, 5.0)
+    expect(native.PT_EINVAL, c.set_state, bad, cr.vel, 0)
+    expect(native.PT_EINVAL, c.set_state, cr.pos, cr.vel, -1)
+    d = make(ctx, cr, "fmm", 6, 32)
+    expect(native.PT_EINVAL, native.step_batch, [c, d], [1, 1])  # different force parameters
+    expect(native.PT_EINVAL, native.step_batch, [c, c], [1, 1])  # the same crystal twice
+    expect(native.PT_EINVAL, native.step_batch, [c], [-1])
+    # the parameters in force before the rejected calls still work
+    c.step(2)
+    assert c.read_state()["step"] == 2
+    c.destroy()
+    d.destroy()
+
+
+def test_budget_exhaustion_and_busy_context():
+    say("budget / busy")
+    cr = inputs.config1(seed=14)
+    with native.Context(0, hbm_budget=1 << 20) as small:
+        big = inputs.config3(n=50000)
+        expect(native.PT_ENOMEM, small.crystal, big.pos, big.vel, Q, M)
+        c = small.crystal(cr.pos, cr.vel, Q, M)  # 52 B per ion fits
+        rc = native.load().pt_ctx_destroy(small.h)
+        assert rc == native.PT_EBUSY
+        c.set_force("fmm", 8, 32)
+        with pytest.raises(native.PTError) as e:  # the FMM workspace does not fit
+            c.compute_forces()
+        assert e.value.code == native.PT_ENOMEM
+
+
+def test_serving_admission_under_a_small_budget():
+    say("serving admission")
+    reqs = inputs.serving_stream(count=12, rate_hz=1e4, seed=15, n_lo=500, n_hi=3000, k_lo=5, k_hi=20)
+    budget = 3 * serving.footprint(3000)
+    with native.Context(0) as c:
+        srv = serving.Server(c, native, budget_bytes=budget, precision="mixed", p=8, leaf=32, chunk=5)
+        rep = srv.run(reqs)
+    assert sorted(d.index for d in rep.done) == list(range(len(reqs)))
+    assert rep.max_resident_bytes <= budget
+    assert all(d.steps == reqs[d.index].steps for d in rep.done)
