@@ -18,12 +18,6 @@ namespace pt {
 
 __device__ inline int octant_of(int ix, int iy, int iz) { return ((ix & 1) << 2) | ((iy & 1) << 1) | (iz & 1); }
 
-__global__ void k_zero_i32(int32_t *__restrict__ p, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
 // P2M: one 64-thread block per leaf.  Ions are taken `chunk` (64, or 32 when
 // the tile would exceed 64 KiB) at a time: each thread evaluates conj(Rh_n^m) of its ion for all (n, m) by one pass of the
 // recurrences into an LDS tile [coefficient][ion]; then each thread sums its
@@ -672,7 +666,6 @@ void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const 
 void launch_m2l_bucket(const BoxTable &bt, int nbox, int32_t *cnt, int32_t *list, hipStream_t st)
 {
     if (nbox <= 0) return;
-    k_zero_i32<<<1, 64, 0, st>>>(cnt, 8);
     k_m2l_bucket<<<ceil_div(nbox, 256), 256, 0, st>>>(bt, nbox, cnt, list);
 }
 

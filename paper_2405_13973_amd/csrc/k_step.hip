@@ -7,6 +7,8 @@
 //   plus Poisson photon recoils of eq. laser_kick) -> U0(dt/2),
 // U0 the exact gyration about B z-hat (eq. U0, rotation sense of the
 // Lorentz force on q B > 0: clockwise) with free flight along z.
+#include <algorithm>
+
 #include "pt_common.hpp"
 #include "pt_kernels.hpp"
 
@@ -356,6 +358,20 @@ void launch_bbox_reset(unsigned long long *bbox, int nc, hipStream_t st)
 {
     const int pairs = (int)(bbox_words(nc) / 6);
     k_fill_u64<<<ceil_div(6 * pairs, 256), 256, 0, st>>>((uint64_t *)bbox, ~0ull, 0ull, pairs);
+}
+
+// Up to kZeroRegions regions of 64-bit words zeroed by one launch.
+__global__ void k_zero_regions(ZeroRegions z)
+{
+    const int r = blockIdx.y;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < z.n[r]; i += gridDim.x * blockDim.x) z.p[r][i] = 0ull;
+}
+
+void launch_zero_regions(const ZeroRegions &z, hipStream_t st)
+{
+    int most = 0;
+    for (int r = 0; r < kZeroRegions; ++r) most = std::max(most, z.n[r]);
+    if (most > 0) k_zero_regions<<<dim3(std::min(ceil_div(most, 256), 64), kZeroRegions), 256, 0, st>>>(z);
 }
 
 void launch_zero_u64(uint64_t *p, int n, hipStream_t st)

@@ -22,9 +22,10 @@ namespace pt {
 
 // --------------------------------------------------------------- scan
 
-// Exclusive prefix sum of n uint32 in place, in three launches: block sums
-// of 4096-element chunks, a one-workgroup scan of those sums, then each
-// chunk scanned with its offset.  *total (optional) gets the sum.
+// Exclusive prefix sum of n uint32 in place, in two launches: block sums of
+// 4096-element chunks, then each chunk scanned with its offset, which each
+// block adds up itself from the sums of the chunks before it (a few dozen
+// at the sizes here).  *total (optional) gets the sum.
 constexpr int kScanTB = 1024;
 constexpr int kScanChunk = 4 * kScanTB;
 
@@ -54,6 +55,8 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *lds_w, uint32_t
     return lds_w[w] + x - v;
 }
 
+__global__ void k_set_u32(uint32_t *__restrict__ p, uint32_t v) { *p = v; }
+
 __global__ __launch_bounds__(kScanTB) void k_scan_reduce(const uint32_t *__restrict__ a, int n,
                                                          uint32_t *__restrict__ partial)
 {
@@ -67,33 +70,24 @@ __global__ __launch_bounds__(kScanTB) void k_scan_reduce(const uint32_t *__restr
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kScanTB) void k_scan_top(uint32_t *__restrict__ partial, int nb,
-                                                      uint32_t *__restrict__ total)
-{
-    __shared__ uint32_t w[kScanTB / 64 + 1];
-    uint32_t carry = 0;
-    for (int c = 0; c < nb; c += kScanTB) {
-        const int i = c + threadIdx.x;
-        const uint32_t v = i < nb ? partial[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, w, tot);
-        if (i < nb) partial[i] = carry + ex;
-        carry += tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && total) *total = carry;
-}
-
 __global__ __launch_bounds__(kScanTB) void k_scan_down(uint32_t *__restrict__ a, int n,
-                                                       const uint32_t *__restrict__ partial)
+                                                       const uint32_t *__restrict__ partial,
+                                                       uint32_t *__restrict__ total)
 {
     __shared__ uint32_t w[kScanTB / 64 + 1];
+    // offset of this chunk: the sum of the chunk sums before it
+    uint32_t pre = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kScanTB) pre += partial[i];
+    uint32_t off;
+    block_excl_scan(pre, w, off);
+    __syncthreads();  // w is reused below
     const int base = blockIdx.x * kScanChunk + 4 * threadIdx.x;
     uint32_t v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = base + k < n ? a[base + k] : 0u;
     uint32_t tot;
-    uint32_t run = partial[blockIdx.x] + block_excl_scan(v[0] + v[1] + v[2] + v[3], w, tot);
+    uint32_t run = off + block_excl_scan(v[0] + v[1] + v[2] + v[3], w, tot);
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (base + k < n) a[base + k] = run;
@@ -206,31 +200,30 @@ __device__ inline void narrow(const uint64_t *__restrict__ keys, int k, int shif
 
 // For every sorted slot: the levels at which it is the first ion of an
 // existing box (bit l of rep_mask).
-__global__ void k_tree_levels(const CrystalDev *__restrict__ cs, const uint64_t *__restrict__ keys, int ntot,
-                              int leaf_size, uint32_t *__restrict__ rep_mask)
+__global__ __launch_bounds__(256) void k_tree_levels(const CrystalDev *__restrict__ cs,
+                                                     const uint64_t *__restrict__ keys, int ntot, int leaf_size,
+                                                     uint32_t *__restrict__ rep_mask, uint32_t *__restrict__ blockcnt,
+                                                     int nblk)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ntot) return;
-    const int c = (int)(keys[k] >> 48);
-    int lo = cs[c].ion_off, hi = lo + cs[c].n;
-    uint32_t mask = (lo == k) ? 1u : 0u;
-    for (int l = 1; l <= kMaxLevel && hi - lo > leaf_size; ++l) {
-        narrow(keys, k, 3 * (kMaxLevel - l), lo, hi);
-        if (lo == k) mask |= 1u << l;
-    }
-    rep_mask[k] = mask;
-}
-
-__global__ __launch_bounds__(256) void k_tree_count(const uint32_t *__restrict__ rep_mask, int ntot,
-                                                    uint32_t *__restrict__ blockcnt, int nblk)
-{
+    // rep_mask[k]: the levels at which slot k is the first ion of a box;
+    // blockcnt[l][block]: how many such slots of this block start a level-l box
     __shared__ uint32_t wc[4][kMaxLevel + 1];
     const int k = blockIdx.x * 256 + threadIdx.x;
-    const uint32_t mask = k < ntot ? rep_mask[k] : 0u;
+    uint32_t mask = 0u;
+    if (k < ntot) {
+        const int c = (int)(keys[k] >> 48);
+        int lo = cs[c].ion_off, hi = lo + cs[c].n;
+        mask = (lo == k) ? 1u : 0u;
+        for (int l = 1; l <= kMaxLevel && hi - lo > leaf_size; ++l) {
+            narrow(keys, k, 3 * (kMaxLevel - l), lo, hi);
+            if (lo == k) mask |= 1u << l;
+        }
+        rep_mask[k] = mask;
+    }
     const int w = threadIdx.x >> 6;
     for (int l = 0; l <= kMaxLevel; ++l) {
-        const int c = __popcll(__ballot((mask >> l) & 1u));
-        if ((threadIdx.x & 63) == 0) wc[w][l] = (uint32_t)c;
+        const int cnt = __popcll(__ballot((mask >> l) & 1u));
+        if ((threadIdx.x & 63) == 0) wc[w][l] = (uint32_t)cnt;
     }
     __syncthreads();
     if (threadIdx.x <= kMaxLevel)
@@ -539,10 +532,13 @@ int scan_partials(int n) { return ceil_div(n, kScanChunk); }
 
 void launch_scan(uint32_t *a, int n, uint32_t *partial, uint32_t *total, hipStream_t st)
 {
+    if (n <= 0) {
+        if (total) k_set_u32<<<1, 1, 0, st>>>(total, 0u);
+        return;
+    }
     const int nb = scan_partials(n);
     k_scan_reduce<<<nb, kScanTB, 0, st>>>(a, n, partial);
-    k_scan_top<<<1, kScanTB, 0, st>>>(partial, nb, total);
-    k_scan_down<<<nb, kScanTB, 0, st>>>(a, n, partial);
+    k_scan_down<<<nb, kScanTB, 0, st>>>(a, n, partial, total);
 }
 
 int sort_blocks(int n) { return ceil_div(n, kSortTile); }
@@ -568,8 +564,7 @@ void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int
                        uint32_t *blockcnt, uint32_t *partial, uint32_t *total, TreeSummary *sum, hipStream_t st)
 {
     const int nblk = tree_blocks(ntot);
-    k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask);
-    k_tree_count<<<nblk, 256, 0, st>>>(rep_mask, ntot, blockcnt, nblk);
+    k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask, blockcnt, nblk);
     launch_scan(blockcnt, (kMaxLevel + 1) * nblk, partial, total, st);
     k_tree_summary<<<1, 64, 0, st>>>(blockcnt, nblk, total, sum);
 }

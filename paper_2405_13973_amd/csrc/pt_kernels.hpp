@@ -25,6 +25,13 @@ inline int bbox_stride(int nc) { return (6 * nc + 47) / 48 * 48; }
 inline size_t bbox_words(int nc) { return (size_t)kBBoxCopies * bbox_stride(nc); }
 void launch_bbox_reset(unsigned long long *bbox, int nc, hipStream_t st);
 void launch_zero_u64(uint64_t *p, int n, hipStream_t st);
+// Several small regions of 64-bit words (n[r] = 0: unused slot) zeroed in one launch.
+constexpr int kZeroRegions = 4;
+struct ZeroRegions {
+    uint64_t *p[kZeroRegions];
+    int n[kZeroRegions];
+};
+void launch_zero_regions(const ZeroRegions &z, hipStream_t st);
 void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int nc, int do_drift,
                        unsigned long long *bbox, hipStream_t st);
 void launch_root(unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st);
@@ -77,7 +84,8 @@ void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const 
 // m2l_base), each Kp x Kp column-major (A[j][i] = T[i][j]), zero-padded;
 // slots: per parity the 189 non-touching window slots {slot, base operator +
 // 256 x reflection mask (bit 0: dx < 0, bit 1: dy < 0, bit 2: dz < 0)};
-// cnt: 8 ints, list: 8 x nbox ints, part: ngroup x nbox x Kp of workspace.
+// cnt: 8 ints (zero on entry to launch_m2l_bucket), list: 8 x nbox ints,
+// part: ngroup x nbox x Kp of workspace.
 void launch_m2l_bucket(const BoxTable &bt, int nbox, int32_t *cnt, int32_t *list, hipStream_t st);
 template <typename T>
 void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t *vtab, const int2 *slots,

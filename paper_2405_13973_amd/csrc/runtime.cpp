@@ -508,8 +508,14 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "m2l_part", esz * Kp * (size_t)nbox * std::max(ngroup, 8), (char **)&m2l_part));
     mark(ctx, 1);
     const Tables &tb = ctx->tables;
-    launch_zero_u64((uint64_t *)((char *)M + esz * Kp * (size_t)nbox), (int)(esz * Kp / 8), st);
-    launch_zero_u64((uint64_t *)((char *)L + esz * Kp * (size_t)nbox), (int)(esz * Kp / 8), st);
+    // the zero rows of M and L and the M2L bucket counters, in one launch
+    ZeroRegions zr{};
+    zr.p[0] = (uint64_t *)((char *)M + esz * Kp * (size_t)nbox);
+    zr.p[1] = (uint64_t *)((char *)L + esz * Kp * (size_t)nbox);
+    zr.p[2] = (uint64_t *)m2l_cnt;
+    zr.n[0] = zr.n[1] = (int)(esz * Kp / 8);
+    zr.n[2] = 4;  // 8 int32 counters
+    launch_zero_regions(zr, st);
     auto run = [&](auto tag) -> pt_status {
         using T = decltype(tag);
         const bool f = sizeof(T) == sizeof(float);
