@@ -319,6 +319,17 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
 #pragma unroll
                 for (int r = 0; r < NRB; ++r) acc[r] = MF::op(av[r], bv, acc[r]);
             }
+            // Schedule: the LDS reads of k-step i + 1 issue as one group ahead
+            // of the matrix-core instructions of step i, so that their latency
+            // hides behind matrix work instead of stalling every instruction
+            // pair (the default schedule reuses one register pair and waits).
+            __builtin_amdgcn_sched_group_barrier(0x100, NRB + 1, 0);
+#pragma unroll
+            for (int k4 = 4; k4 < KC; k4 += 4) {
+                __builtin_amdgcn_sched_group_barrier(0x100, NRB + 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NRB, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, NRB, 0);
         }
         if (cur) resign(cur);
         const int tg = tgt_s[wave * 16 + (lane & 15)];
@@ -413,9 +424,9 @@ __global__ void k_m2l_reduce(BoxTable bt, int nbox, int Kp, int ngroup, const T 
     L[e] = acc;
 }
 
-// Near field (P2P) of one work item per 64-thread workgroup (grid-stride over
-// the items): up to 64 targets of a leaf against the sources of a run of its
-// near ranges.  The ranges are concatenated and staged through LDS
+// Near field (P2P) of one work item per 256-thread workgroup (grid-stride
+// over the items): up to 64 targets of a leaf against the sources of a run of
+// its near ranges.  The ranges are concatenated and staged through LDS
 // kP2PStage sources at a time as FP64 positions, so the pair loop reads only
 // LDS and a barrier pair serves hundreds of sources rather than one leaf.
 // Each pair's separation is an FP64 difference rounded once to T: close
@@ -423,12 +434,14 @@ __global__ void k_m2l_reduce(BoxTable bt, int nbox, int Kp, int ngroup, const T 
 // carry an absolute error of order 1e-7 of the box size into every
 // separation, and the rare very close pairs of random crystals dominate an
 // RMS force error).  An item with nt targets gives each target
-// floor(64 / nt) threads (phases), which take source blocks round robin;
+// floor(256 / nt) threads (phases), which take source blocks round robin;
 // within a block sources are summed plainly and each block is added to the
 // phase's total with Kahan compensation.  The phases of a target are then
-// added in phase order.
+// added in phase order.  Four waves share one staged tile, so that a compute
+// unit holds enough waves to hide the latency of the pair arithmetic.
 // Partial fields go to part[item][target][3].
 constexpr int kP2PStage = 512;
+constexpr int kP2PThreads = 256;  // four waves share one staged source tile
 
 // 1/sqrt(x) in the arithmetic type: the hardware reciprocal square root for
 // FP32 (1 ulp), the library routine for FP64.
@@ -439,56 +452,64 @@ __device__ inline double rsqrt_t(double x) { return rsqrt(x); }
 constexpr double kRinvMax = 1e12;
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restrict__ sp, int ntot,
-                                            const int2 *__restrict__ near, int stride, const int4 *__restrict__ work,
-                                            int n_items, T *__restrict__ part)
+__global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *__restrict__ sp, int ntot,
+                                                     const int2 *__restrict__ near, int stride,
+                                                     const int4 *__restrict__ work, int n_items, T *__restrict__ part)
 {
-    constexpr int kU = kP2PStage / 64;
+    constexpr int NT = kP2PThreads;
+    constexpr int kU = kP2PStage / NT;
     __shared__ double4 src[kP2PStage];
     __shared__ int pre_s[kNearMax + 1];  // prefix of the item's range lengths
     __shared__ int beg_s[kNearMax];      // first ion of each range minus its prefix
-    __shared__ T hx[64], hy[64], hz[64];
-    const int lane = threadIdx.x;
+    __shared__ int total_s;
+    __shared__ T hx[NT], hy[NT], hz[NT];
+    const int tid = threadIdx.x, lane = tid & 63;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int4 w = work[it];
         const int b = w.x;
         const int2 *row = near + (size_t)b * stride;
         const int nt = max(1, min(64, bt.end[b] - w.y));
-        const int nph = 64 / nt;                                     // phases per target
-        const int blk = nph == 1 ? 64 : (nph <= 3 ? 32 : 16);        // sources per block
-        const int ti = lane % nt, ph = lane / nt;                    // ph >= nph: idle lane
+        const int nph = NT / nt;                            // phases per target (>= 4)
+        const int blk = nph <= 4 ? 32 : 16;                 // sources per block
+        const int ti = tid % nt, ph = tid / nt;             // ph >= nph: idle thread
         const int k = w.y + ti;
         const double xi = sp[k], yi = sp[ntot + k], zi = sp[2 * ntot + k];
         const int nr = min(w.w - w.z, kNearMax);
         __syncthreads();  // the previous item is done with the shared arrays
-        int total = 0;
-        for (int r0 = 0; r0 < nr; r0 += 64) {
-            const int r = r0 + lane;
-            int2 rg = make_int2(0, 0);
-            if (r < nr) rg = row[w.z + r];
-            int x = rg.y - rg.x;
+        if (tid < 64) {   // prefix of the range lengths, by the first wave
+            int total = 0;
+            for (int r0 = 0; r0 < nr; r0 += 64) {
+                const int r = r0 + lane;
+                int2 rg = make_int2(0, 0);
+                if (r < nr) rg = row[w.z + r];
+                int x = rg.y - rg.x;
 #pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int y = __shfl_up(x, off);
-                if (lane >= off) x += y;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int y = __shfl_up(x, off);
+                    if (lane >= off) x += y;
+                }
+                if (r < nr) {
+                    pre_s[r + 1] = total + x;
+                    beg_s[r] = rg.x - (total + x - (rg.y - rg.x));
+                }
+                total += __shfl(x, 63);
             }
-            if (r < nr) {
-                pre_s[r + 1] = total + x;
-                beg_s[r] = rg.x - (total + x - (rg.y - rg.x));
+            if (lane == 0) {
+                pre_s[0] = 0;
+                total_s = total;
             }
-            total += __shfl(x, 63);
         }
-        if (lane == 0) pre_s[0] = 0;
         __syncthreads();
+        const int total = total_s;
         T ax = 0, ay = 0, az = 0, cx = 0, cy = 0, cz = 0;
         for (int s0 = 0; s0 < total; s0 += kP2PStage) {
             const int n = min(kP2PStage, total - s0);
             // source index of each staged position: binary search for the
-            // first, then a forward walk (positions grow by 64)
+            // first, then a forward walk (positions grow by NT)
             int js[kU];
             {
                 int a = 0, e = nr;  // last r with pre_s[r] <= pos
-                const int pos0 = s0 + lane;
+                const int pos0 = s0 + tid;
                 while (e - a > 1) {
                     const int m = (a + e) >> 1;
                     if (pre_s[m] <= pos0) a = m;
@@ -497,9 +518,9 @@ __global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restric
                 int r = a;
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
-                    const int pos = s0 + lane + 64 * u;
+                    const int pos = s0 + tid + NT * u;
                     js[u] = -1;
-                    if (lane + 64 * u < n) {
+                    if (tid + NT * u < n) {
                         while (r + 1 < nr && pre_s[r + 1] <= pos) ++r;
                         js[u] = beg_s[r] + pos;
                     }
@@ -515,7 +536,7 @@ __global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restric
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u)
-                if (js[u] >= 0) src[lane + 64 * u] = make_double4(sx[u], sy[u], sz[u], 0.0);
+                if (js[u] >= 0) src[tid + NT * u] = make_double4(sx[u], sy[u], sz[u], 0.0);
             __syncthreads();
             for (int q0 = ph < nph ? ph * blk : n; q0 < n; q0 += nph * blk) {
                 const int q1 = min(n, q0 + blk);
@@ -548,19 +569,17 @@ __global__ __launch_bounds__(64) void k_p2p(BoxTable bt, const double *__restric
             }
             __syncthreads();  // all reads of src done before the next stage
         }
-        if (nph > 1) {  // phases 1.. hand their sums to phase 0, added in phase order
-            hx[lane] = ax;
-            hy[lane] = ay;
-            hz[lane] = az;
-            __syncthreads();
-            if (ph == 0)
-                for (int h = 1; h < nph; ++h) {
-                    ax += hx[h * nt + ti];
-                    ay += hy[h * nt + ti];
-                    az += hz[h * nt + ti];
-                }
-        }
+        // phases 1.. hand their sums to phase 0, added in phase order
+        hx[tid] = ax;
+        hy[tid] = ay;
+        hz[tid] = az;
+        __syncthreads();
         if (ph == 0) {
+            for (int h = 1; h < nph; ++h) {
+                ax += hx[h * nt + ti];
+                ay += hy[h * nt + ti];
+                az += hz[h * nt + ti];
+            }
             T *dst = part + ((size_t)it * 64 + ti) * 3;
             dst[0] = ax;
             dst[1] = ay;
@@ -727,7 +746,7 @@ void launch_near(const BoxTable &bt, const double *sp, int ntot, const int2 *nea
                  int n_items, T *part, hipStream_t st)
 {
     if (n_items > 0)
-        k_p2p<T><<<std::min(n_items, 16384), 64, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part);
+        k_p2p<T><<<std::min(n_items, 16384), kP2PThreads, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part);
 }
 
 template <typename T>

@@ -202,10 +202,11 @@ __device__ inline void narrow(const uint64_t *__restrict__ keys, int k, int shif
 // existing box (bit l of rep_mask).
 __global__ __launch_bounds__(256) void k_tree_levels(const CrystalDev *__restrict__ cs,
                                                      const uint64_t *__restrict__ keys, int ntot, int leaf_size,
-                                                     uint32_t *__restrict__ rep_mask, uint32_t *__restrict__ blockcnt,
-                                                     int nblk)
+                                                     uint32_t *__restrict__ rep_mask, int32_t *__restrict__ box_end,
+                                                     uint32_t *__restrict__ blockcnt, int nblk)
 {
     // rep_mask[k]: the levels at which slot k is the first ion of a box;
+    // box_end[k][l]: the end of that level-l box (written for those levels only);
     // blockcnt[l][block]: how many such slots of this block start a level-l box
     __shared__ uint32_t wc[4][kMaxLevel + 1];
     const int k = blockIdx.x * 256 + threadIdx.x;
@@ -213,10 +214,15 @@ __global__ __launch_bounds__(256) void k_tree_levels(const CrystalDev *__restric
     if (k < ntot) {
         const int c = (int)(keys[k] >> 48);
         int lo = cs[c].ion_off, hi = lo + cs[c].n;
+        int32_t *end = box_end + (size_t)k * (kMaxLevel + 1);
         mask = (lo == k) ? 1u : 0u;
+        if (lo == k) end[0] = hi;
         for (int l = 1; l <= kMaxLevel && hi - lo > leaf_size; ++l) {
             narrow(keys, k, 3 * (kMaxLevel - l), lo, hi);
-            if (lo == k) mask |= 1u << l;
+            if (lo == k) {
+                mask |= 1u << l;
+                end[l] = hi;
+            }
         }
         rep_mask[k] = mask;
     }
@@ -245,6 +251,7 @@ __global__ __launch_bounds__(256) void k_tree_emit(const CrystalDev *__restrict_
                                                    const RootCube *__restrict__ roots,
                                                    const uint64_t *__restrict__ keys, int ntot, int leaf_size,
                                                    const uint32_t *__restrict__ rep_mask,
+                                                   const int32_t *__restrict__ box_end,
                                                    const uint32_t *__restrict__ scanned, int nblk, BoxTable bt)
 {
     __shared__ uint32_t wc[4][kMaxLevel + 1];
@@ -263,13 +270,10 @@ __global__ __launch_bounds__(256) void k_tree_emit(const CrystalDev *__restrict_
     const uint64_t key = keys[k];
     const int c = (int)(key >> 48);
     const RootCube rc = roots[c];
-    int lo = cs[c].ion_off, hi = lo + cs[c].n;
+    const int lo = k;  // the box starts at its representative
     for (int l = 0; l <= kMaxLevel; ++l) {
-        if (l > 0) {
-            if (hi - lo <= leaf_size) break;
-            narrow(keys, k, 3 * (kMaxLevel - l), lo, hi);
-        }
         if (!((mask >> l) & 1u)) continue;
+        const int hi = box_end[(size_t)k * (kMaxLevel + 1) + l];
         uint32_t idx = scanned[l * nblk + blockIdx.x] + (uint32_t)rank[l];
         for (int q = 0; q < w; ++q) idx += wc[q][l];
         const int sh = 3 * (kMaxLevel - l);
@@ -561,20 +565,21 @@ void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint3
 int tree_blocks(int ntot) { return ceil_div(ntot, 256); }
 
 void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
-                       uint32_t *blockcnt, uint32_t *partial, uint32_t *total, TreeSummary *sum, hipStream_t st)
+                       int32_t *box_end, uint32_t *blockcnt, uint32_t *partial, uint32_t *total, TreeSummary *sum,
+                       hipStream_t st)
 {
     const int nblk = tree_blocks(ntot);
-    k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask, blockcnt, nblk);
+    k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask, box_end, blockcnt, nblk);
     launch_scan(blockcnt, (kMaxLevel + 1) * nblk, partial, total, st);
     k_tree_summary<<<1, 64, 0, st>>>(blockcnt, nblk, total, sum);
 }
 
 void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
-                       const uint32_t *rep_mask, const uint32_t *scanned, const BoxTable &bt, const TreeSummary *sum,
-                       int nbox, hipStream_t st)
+                       const uint32_t *rep_mask, const int32_t *box_end, const uint32_t *scanned, const BoxTable &bt,
+                       const TreeSummary *sum, int nbox, hipStream_t st)
 {
     const int nblk = tree_blocks(ntot);
-    k_tree_emit<<<nblk, 256, 0, st>>>(cs, roots, keys, ntot, leaf_size, rep_mask, scanned, nblk, bt);
+    k_tree_emit<<<nblk, 256, 0, st>>>(cs, roots, keys, ntot, leaf_size, rep_mask, box_end, scanned, nblk, bt);
     k_tree_links<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum);
 }
 

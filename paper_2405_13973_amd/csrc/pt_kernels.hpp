@@ -52,11 +52,14 @@ void launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
 void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint32_t *vals, int ntot, double *sp,
                    hipStream_t st);
 int tree_blocks(int ntot);
+// box_end: ntot x (kMaxLevel + 1) ints, the end of every box at its first ion
+// (filled by launch_tree_count, read by launch_tree_build).
 void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
-                       uint32_t *blockcnt, uint32_t *partial, uint32_t *total, TreeSummary *sum, hipStream_t st);
+                       int32_t *box_end, uint32_t *blockcnt, uint32_t *partial, uint32_t *total, TreeSummary *sum,
+                       hipStream_t st);
 void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
-                       const uint32_t *rep_mask, const uint32_t *scanned, const BoxTable &bt, const TreeSummary *sum,
-                       int nbox, hipStream_t st);
+                       const uint32_t *rep_mask, const int32_t *box_end, const uint32_t *scanned, const BoxTable &bt,
+                       const TreeSummary *sum, int nbox, hipStream_t st);
 // Also counts the near-field work items {leaf, first target, range begin,
 // range end}: item_off (nbox, scanned in place to offsets), src_items (nbox),
 // n_items (device total).  launch_p2p_items then writes them into work.

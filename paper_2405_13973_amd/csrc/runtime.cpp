@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -90,6 +91,8 @@ struct pt_crystal {
 // Timed phases of a force evaluation (events 0..6 bracket them): sort+tree+
 // lists, P2M+M2M, M2L, M2L reduce+L2L, P2P, L2P + near-field partials, total.
 constexpr int kPhases = 7;
+// Leaf size from which the near field runs concurrently with M2L / L2L.
+constexpr int kConcurrentLeaf = 128;
 
 struct pt_ctx {
     int device = 0;
@@ -99,8 +102,9 @@ struct pt_ctx {
     // fork / join events order it after the lists and before the L2P kernel
     hipStream_t near_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipEvent_t ev_near[2] = {};  // timing of the P2P kernel on near_stream
+    hipEvent_t ev_near[2] = {};  // timing of the P2P kernel
     bool near_timed = false;
+    int near_concurrent = -1;  // -1: by leaf size; 0 / 1: forced (PT_NEAR_CONCURRENT)
     uint64_t budget = 0, used = 0;
     int live = 0;
     std::map<void *, size_t> allocs;
@@ -426,6 +430,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "vals1", sizeof(uint32_t) * ntot, &v1));
     PT_TRY(ws_get(ctx, "hist", sizeof(uint32_t) * 256 * sort_blocks(ntot), &hist));
     PT_TRY(ws_get(ctx, "rep", sizeof(uint32_t) * ntot, &rep));
+    int32_t *box_end;
+    PT_TRY(ws_get(ctx, "box_end", sizeof(int32_t) * (kMaxLevel + 1) * (size_t)ntot, &box_end));
     PT_TRY(ws_get(ctx, "bcnt", sizeof(uint32_t) * (kMaxLevel + 1) * tree_blocks(ntot), &bcnt));
     PT_TRY(ws_get(ctx, "total", sizeof(uint32_t) * 4, &total));
     uint32_t *scan_part;
@@ -444,7 +450,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         std::swap(v0, v1);
     }
     launch_gather(b.d_desc, b.ion_crystal, v0, ntot, sp, st);
-    launch_tree_count(b.d_desc, k0, ntot, s, rep, bcnt, scan_part, total, dsum, st);
+    launch_tree_count(b.d_desc, k0, ntot, s, rep, box_end, bcnt, scan_part, total, dsum, st);
     PT_HIP(hipMemcpyAsync(ctx->h_sum, dsum, sizeof(TreeSummary), hipMemcpyDeviceToHost, st));
     PT_HIP(hipStreamSynchronize(st));
     const TreeSummary hs = *ctx->h_sum;
@@ -475,7 +481,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     near_cnt = (int32_t *)ctx->ws["near_cnt"].ptr;
     PT_TRY(ensure_tables(ctx, p));
     const BoxTable bt = box_table(ctx);
-    launch_tree_build(b.d_desc, roots, k0, ntot, s, rep, bcnt, bt, dsum, nbox, st);
+    launch_tree_build(b.d_desc, roots, k0, ntot, s, rep, box_end, bcnt, bt, dsum, nbox, st);
     int32_t *child_oct, *parent_oct, *src_items;
     uint32_t *item_off;
     PT_TRY(ws_get(ctx, "child_oct", sizeof(int32_t) * 8 * (size_t)nbox, &child_oct));
@@ -526,23 +532,35 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         launch_upward<T>(bt, sp, ntot, p, hs, m2m, tb.oct_slots, child_oct, rec, (T *)M, (T *)m2l_part, s, st);
         launch_m2l_bucket(bt, nbox, m2l_cnt, m2l_list, st);
         // near field on its own stream, concurrently with M2L and L2L (vector
-        // ALUs beside matrix cores); it starts once the upward pass is done,
-        // so that the two dispatch together, and joins before the L2P kernel
-        PT_HIP(hipEventRecord(ctx->ev_fork, st));
-        PT_HIP(hipStreamWaitEvent(ctx->near_stream, ctx->ev_fork, 0));
-        if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[0], ctx->near_stream));
-        launch_near<T>(bt, sp, ntot, near, stride, work, n_items, (T *)ppart, ctx->near_stream);
-        if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[1], ctx->near_stream));
-        ctx->near_timed = ctx->timing;
-        PT_HIP(hipEventRecord(ctx->ev_join, ctx->near_stream));
+        // ALUs beside matrix cores) when leaves are large enough for the near
+        // field to rival the far field; it starts once the upward pass is
+        // done, so that the two dispatch together, and joins before L2P.
+        // With small leaves M2L dominates and sharing the chip only slows it:
+        // the near field then runs after L2L on the main stream.
+        const bool concurrent = ctx->near_concurrent > 0 || (ctx->near_concurrent < 0 && s >= kConcurrentLeaf);
+        hipStream_t ns = concurrent ? ctx->near_stream : st;
+        if (concurrent) {
+            PT_HIP(hipEventRecord(ctx->ev_fork, st));
+            PT_HIP(hipStreamWaitEvent(ns, ctx->ev_fork, 0));
+        }
+        auto near_field = [&]() -> pt_status {
+            if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[0], ns));
+            launch_near<T>(bt, sp, ntot, near, stride, work, n_items, (T *)ppart, ns);
+            if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[1], ns));
+            ctx->near_timed = ctx->timing;
+            if (concurrent) PT_HIP(hipEventRecord(ctx->ev_join, ns));
+            return PT_OK;
+        };
+        if (concurrent) PT_TRY(near_field());
         mark(ctx, 2);
         launch_m2l<T>(bt, p, hs, vtab, tb.slots, m2l, (const T *)M, m2l_cnt, m2l_list, (T *)m2l_part, ngroup, st);
         mark(ctx, 3);
         launch_m2l_reduce<T>(bt, p, nbox, (const T *)m2l_part, ngroup, (T *)L, st);
         launch_downward<T>(bt, p, hs, l2l, tb.oct_slots, parent_oct, (T *)L, (T *)m2l_part, st);
         mark(ctx, 4);
+        if (!concurrent) PT_TRY(near_field());
         mark(ctx, 5);
-        PT_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+        if (concurrent) PT_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
         launch_far<T>(bt, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E, s, st);
         return PT_OK;
     };
@@ -642,6 +660,7 @@ pt_status pt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, void *hip_str
     PT_HIP(hipHostMalloc((void **)&ctx->h_counters, sizeof(unsigned long long) * 2));
     for (auto &e : ctx->ev) PT_HIP(hipEventCreate(&e));
     PT_HIP(hipStreamCreateWithFlags(&ctx->near_stream, hipStreamNonBlocking));
+    if (const char *e = getenv("PT_NEAR_CONCURRENT")) ctx->near_concurrent = atoi(e) ? 1 : 0;
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
     for (auto &e : ctx->ev_near) PT_HIP(hipEventCreate(&e));
