@@ -666,15 +666,21 @@ static void launch_level_xlate(const BoxTable &bt, int Kp, int nbox, int b0, int
 }
 
 template <typename T>
-void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *m2m_pad,
-                   const int2 *oct_slots, const int32_t *child_oct, const T *rec, T *M, T *part, int leaf_size,
-                   hipStream_t st)
+void launch_p2m(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *rec, T *M,
+                int leaf_size, hipStream_t st)
 {
     const int Kp = kpad(p);
     const int chunk = p2m_chunk<T>(Kp, leaf_size);
     const size_t smem = (size_t)Kp * (chunk + 1) * sizeof(T);
     if (hs.nbox > 0) k_p2m<T><<<hs.nbox, 64, smem, st>>>(bt, sp, ntot, p, Kp, chunk, rec, M);
-    // M2M level by level: parents of level l gather their children by octant
+}
+
+template <typename T>
+void launch_m2m(const BoxTable &bt, int p, const TreeSummary &hs, const T *m2m_pad, const int2 *oct_slots,
+                const int32_t *child_oct, T *M, T *part, hipStream_t st)
+{
+    // level by level: parents of level l gather their children by octant
+    const int Kp = kpad(p);
     for (int l = kMaxLevel - 1; l >= 2; --l) {
         const int b0 = hs.level_start[l], b1 = hs.level_start[l + 1];
         if (b1 <= b0 || hs.level_start[l + 2] <= b1) continue;  // no children below
@@ -759,11 +765,14 @@ void launch_far(const BoxTable &bt, const double *sp, int ntot, int p, int nbox,
     if (nbox > 0) k_far<T><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E);
 }
 
-template void launch_upward<double>(const BoxTable &, const double *, int, int, const TreeSummary &, const double *,
-                                    const int2 *, const int32_t *, const double *, double *, double *, int,
-                                    hipStream_t);
-template void launch_upward<float>(const BoxTable &, const double *, int, int, const TreeSummary &, const float *,
-                                   const int2 *, const int32_t *, const float *, float *, float *, int, hipStream_t);
+template void launch_p2m<double>(const BoxTable &, const double *, int, int, const TreeSummary &, const double *,
+                                 double *, int, hipStream_t);
+template void launch_p2m<float>(const BoxTable &, const double *, int, int, const TreeSummary &, const float *,
+                                float *, int, hipStream_t);
+template void launch_m2m<double>(const BoxTable &, int, const TreeSummary &, const double *, const int2 *,
+                                 const int32_t *, double *, double *, hipStream_t);
+template void launch_m2m<float>(const BoxTable &, int, const TreeSummary &, const float *, const int2 *,
+                                const int32_t *, float *, float *, hipStream_t);
 template void launch_m2l<double>(const BoxTable &, int, const TreeSummary &, const int32_t *, const int2 *,
                                  const double *, const double *, const int32_t *, const int32_t *, double *, int,
                                  hipStream_t);

@@ -80,9 +80,11 @@ void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, cons
 // m2m_pad / l2l_pad: 8 operators, Kp x Kp column-major, zero padded;
 // oct_slots: the 8 slots {octant, octant}; child_oct / parent_oct: 8 x nbox.
 template <typename T>
-void launch_upward(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *m2m_pad,
-                   const int2 *oct_slots, const int32_t *child_oct, const T *rec, T *M, T *part, int leaf_size,
-                   hipStream_t st);
+void launch_p2m(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *rec, T *M,
+                int leaf_size, hipStream_t st);
+template <typename T>
+void launch_m2m(const BoxTable &bt, int p, const TreeSummary &hs, const T *m2m_pad, const int2 *oct_slots,
+                const int32_t *child_oct, T *M, T *part, hipStream_t st);
 // m2l_pad: 64 base operators (offsets with non-negative components, index
 // m2l_base), each Kp x Kp column-major (A[j][i] = T[i][j]), zero-padded;
 // slots: per parity the 189 non-touching window slots {slot, base operator +

@@ -529,14 +529,15 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         const T *m2l = f ? (const T *)tb.m2l_f : (const T *)tb.m2l_d;
         const T *l2l = f ? (const T *)tb.l2l_f : (const T *)tb.l2l_d;
         const T *rec = f ? (const T *)tb.rec_f : (const T *)tb.rec_d;
-        launch_upward<T>(bt, sp, ntot, p, hs, m2m, tb.oct_slots, child_oct, rec, (T *)M, (T *)m2l_part, s, st);
+        launch_p2m<T>(bt, sp, ntot, p, hs, rec, (T *)M, s, st);
+        launch_m2m<T>(bt, p, hs, m2m, tb.oct_slots, child_oct, (T *)M, (T *)m2l_part, st);
         launch_m2l_bucket(bt, nbox, m2l_cnt, m2l_list, st);
         // near field on its own stream, concurrently with M2L and L2L (vector
         // ALUs beside matrix cores) when leaves are large enough for the near
-        // field to rival the far field; it starts once the upward pass is
-        // done, so that the two dispatch together, and joins before L2P.
-        // With small leaves M2L dominates and sharing the chip only slows it:
-        // the near field then runs after L2L on the main stream.
+        // field to rival the far field; it starts once the upward pass is done
+        // (P2M and M2M would starve beside it) and joins before L2P.  With
+        // small leaves M2L dominates and sharing the chip only slows it: the
+        // near field then runs after L2L on the main stream.
         const bool concurrent = ctx->near_concurrent > 0 || (ctx->near_concurrent < 0 && s >= kConcurrentLeaf);
         hipStream_t ns = concurrent ? ctx->near_stream : st;
         if (concurrent) {
