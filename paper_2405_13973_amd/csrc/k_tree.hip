@@ -160,6 +160,139 @@ __global__ __launch_bounds__(kSortTB) void k_radix_scatter(const uint64_t *__res
     }
 }
 
+// ------------------------------------------- single-pass-per-digit radix sort
+//
+// One kernel counts all digits of all passes over the keys (global digit
+// histograms) and clears the look-back flags; then every pass is one kernel
+// with decoupled look-back: a workgroup takes the next tile number from a
+// counter (tiles are therefore numbered in the order their workgroups
+// started, so every tile a workgroup waits for is already running), counts
+// its tile's digits, publishes them, and adds up the counts published by the
+// tiles before it (stopping at the first tile that has published its
+// inclusive prefix), then publishes its own inclusive prefix and scatters.
+// Ranking inside a tile is the stable order (round, wave, lane) of the
+// multi-kernel sort above, so both sorts give the same result.  A bounded
+// spin sets *err instead of waiting forever.
+//
+// Workspace (RadixState, radix_state_words): ghist[kMaxPasses][256] uint32,
+// ctr[kMaxPasses] uint32, err uint32, then flags[kMaxPasses][ntile][256]
+// uint64 (status in the top two bits, count below); ghist, ctr and err must
+// be zero before k_radix_prepare.
+constexpr int kMaxPasses = 8;
+constexpr uint64_t kFlagAgg = 1ull << 62, kFlagIncl = 2ull << 62, kFlagCount = (1ull << 62) - 1;
+constexpr int kSpinMax = 1 << 20;
+
+__global__ __launch_bounds__(kSortTB) void k_radix_prepare(const uint64_t *__restrict__ keys, int n, int passes,
+                                                           uint32_t *__restrict__ ghist, uint64_t *__restrict__ flags,
+                                                           int ntile)
+{
+    __shared__ uint32_t cnt[kMaxPasses][256];
+    const int tid = threadIdx.x;
+    for (int p = 0; p < passes; ++p) {
+        cnt[p][tid] = 0;
+        flags[((size_t)p * ntile + blockIdx.x) * 256 + tid] = 0ull;
+    }
+    __syncthreads();
+    for (int r = 0; r < kSortItems; ++r) {
+        const int i = blockIdx.x * kSortTile + r * kSortTB + tid;
+        if (i < n) {
+            const uint64_t key = keys[i];
+            for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][(key >> (8 * p)) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < passes; ++p)
+        if (cnt[p][tid]) atomicAdd(&ghist[p * 256 + tid], cnt[p][tid]);
+}
+
+__global__ __launch_bounds__(kSortTB) void k_radix_pass(const uint64_t *__restrict__ kin,
+                                                        const uint32_t *__restrict__ vin,
+                                                        uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                        int n, int pass, const uint32_t *__restrict__ ghist,
+                                                        uint64_t *__restrict__ flags, int ntile,
+                                                        uint32_t *__restrict__ ctr, uint32_t *__restrict__ err)
+{
+    constexpr int NW = kSortTB / 64;
+    __shared__ uint32_t wcnt[kSortItems][NW][256];  // digit counts per (round, wave), then their prefixes
+    __shared__ uint32_t base_s[256];
+    __shared__ uint32_t lds_w[NW + 1];
+    __shared__ int tile_s;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int shift = 8 * pass;
+    if (tid == 0) tile_s = (int)atomicAdd(&ctr[pass], 1u);
+    for (int r = 0; r < kSortItems; ++r)
+        for (int q = 0; q < NW; ++q) wcnt[r][q][tid] = 0;
+    __syncthreads();
+    const int tile = tile_s;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    uint64_t key[kSortItems];
+    uint32_t val[kSortItems], dig[kSortItems];
+    int rnk[kSortItems];
+    bool ok[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int i = tile * kSortTile + r * kSortTB + tid;
+        ok[r] = i < n;
+        key[r] = ok[r] ? kin[i] : 0ull;
+        val[r] = ok[r] ? vin[i] : 0u;
+        dig[r] = (uint32_t)(key[r] >> shift) & 255u;
+        unsigned long long peers = __ballot(ok[r]);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (dig[r] >> bit) & 1u;
+            const unsigned long long bb = __ballot(on);
+            peers &= on ? bb : ~bb;
+        }
+        rnk[r] = __popcll(peers & lt);
+        if (ok[r] && rnk[r] == 0) wcnt[r][w][dig[r]] = (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // thread d: exclusive prefix of digit d over (round, wave), tile total
+    uint32_t run = 0;
+    for (int r = 0; r < kSortItems; ++r)
+        for (int q = 0; q < NW; ++q) {
+            const uint32_t c = wcnt[r][q][tid];
+            wcnt[r][q][tid] = run;
+            run += c;
+        }
+    const uint32_t mine = run;
+    uint64_t *fl = flags + (size_t)pass * ntile * 256;
+    // the count travels inside the flag word, so relaxed device-scope atomics
+    // suffice (no other data is published)
+    __hip_atomic_store(&fl[(size_t)tile * 256 + tid], (tile == 0 ? kFlagIncl : kFlagAgg) | mine, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    // look back over the earlier tiles
+    uint64_t excl = 0;
+    for (int t = tile - 1; t >= 0; --t) {
+        uint64_t f = 0;
+        int spins = 0;
+        do {
+            f = __hip_atomic_load(&fl[(size_t)t * 256 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } while ((f >> 62) == 0 && ++spins < kSpinMax);
+        if ((f >> 62) == 0) {
+            atomicOr(err, 1u);
+            break;
+        }
+        excl += f & kFlagCount;
+        if ((f >> 62) == 2) break;
+    }
+    if (tile > 0)
+        __hip_atomic_store(&fl[(size_t)tile * 256 + tid], kFlagIncl | (excl + mine), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    // first slot of digit d for this tile: keys of smaller digits + earlier tiles
+    uint32_t tot;
+    const uint32_t gex = block_excl_scan(ghist[pass * 256 + tid], lds_w, tot);
+    base_s[tid] = gex + (uint32_t)excl;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+        if (ok[r]) {
+            const uint32_t pos = base_s[dig[r]] + wcnt[r][w][dig[r]] + rnk[r];
+            kout[pos] = key[r];
+            vout[pos] = val[r];
+        }
+}
+
 // Sorted positions: slot k takes the position of batch ion vals[k].
 __global__ void k_gather(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal,
                          const uint32_t *__restrict__ vals, int ntot, double *__restrict__ sp)
@@ -238,9 +371,10 @@ __global__ __launch_bounds__(256) void k_tree_levels(const CrystalDev *__restric
 }
 
 __global__ void k_tree_summary(const uint32_t *__restrict__ scanned, int nblk, const uint32_t *__restrict__ total,
-                               TreeSummary *__restrict__ sum)
+                               const uint32_t *__restrict__ sort_err, TreeSummary *__restrict__ sum)
 {
     if (threadIdx.x != 0) return;
+    sum->sort_error = sort_err ? (int32_t)*sort_err : 0;
     for (int l = 0; l <= kMaxLevel; ++l) sum->level_start[l] = (int32_t)scanned[l * nblk];
     sum->level_start[kMaxLevel + 1] = (int32_t)*total;
     sum->nbox = (int32_t)*total;
@@ -562,16 +696,34 @@ void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint3
     k_gather<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, vals, ntot, sp);
 }
 
+size_t radix_state_words(int n) { return (size_t)kMaxPasses * 256 + kMaxPasses + 1 + 1 +
+                                        2 * (size_t)kMaxPasses * sort_blocks(n) * 256; }
+
+int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int n, int passes, uint32_t *state,
+                      hipStream_t st)
+{
+    if (passes > kMaxPasses || n <= 0) return -1;
+    const int ntile = sort_blocks(n);
+    uint32_t *ghist = state, *ctr = state + kMaxPasses * 256, *err = ctr + kMaxPasses;
+    uint64_t *flags = (uint64_t *)(state + kMaxPasses * 256 + kMaxPasses + 2);  // 8-byte aligned
+    k_radix_prepare<<<ntile, kSortTB, 0, st>>>(k0, n, passes, ghist, flags, ntile);
+    for (int p = 0; p < passes; ++p) {
+        k_radix_pass<<<ntile, kSortTB, 0, st>>>(p % 2 ? k1 : k0, p % 2 ? v1 : v0, p % 2 ? k0 : k1, p % 2 ? v0 : v1, n,
+                                                p, ghist, flags, ntile, ctr, err);
+    }
+    return passes % 2;  // 1: the result is in (k1, v1)
+}
+
 int tree_blocks(int ntot) { return ceil_div(ntot, 256); }
 
 void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
-                       int32_t *box_end, uint32_t *blockcnt, uint32_t *partial, uint32_t *total, TreeSummary *sum,
-                       hipStream_t st)
+                       int32_t *box_end, uint32_t *blockcnt, uint32_t *partial, uint32_t *total,
+                       const uint32_t *sort_err, TreeSummary *sum, hipStream_t st)
 {
     const int nblk = tree_blocks(ntot);
     k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask, box_end, blockcnt, nblk);
     launch_scan(blockcnt, (kMaxLevel + 1) * nblk, partial, total, st);
-    k_tree_summary<<<1, 64, 0, st>>>(blockcnt, nblk, total, sum);
+    k_tree_summary<<<1, 64, 0, st>>>(blockcnt, nblk, total, sort_err, sum);
 }
 
 void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,

@@ -69,7 +69,8 @@ struct RootCube {
 struct TreeSummary {
     int32_t level_start[kMaxLevel + 2];  // boxes of level l: [level_start[l], level_start[l+1])
     int32_t nbox;
-    int32_t pad[3];
+    int32_t sort_error;  // non-zero: the sort's look-back gave up waiting (see k_radix_pass)
+    int32_t pad[2];
 };
 
 // ---------------------------------------------------------------- helpers

@@ -47,6 +47,16 @@ void launch_direct(const CrystalDev *cs, const int32_t *blk_crystal, const int32
 int scan_partials(int n);  // workspace entries launch_scan needs for n elements
 void launch_scan(uint32_t *a, int n, uint32_t *partial, uint32_t *total, hipStream_t st);
 int sort_blocks(int n);
+// Single-pass-per-digit radix sort of (k0, v0) by the low 8 x passes bits
+// (passes <= 8): state holds radix_state_words(n) uint32 whose first
+// radix_state_zero_words() must be zero on entry; the error word is
+// state + radix_state_err().  Returns 1 when the result is in (k1, v1), 0
+// when in (k0, v0), -1 when passes is out of range.
+size_t radix_state_words(int n);
+constexpr int radix_state_zero_words() { return 8 * 256 + 8 + 2; }
+constexpr int radix_state_err() { return 8 * 256 + 8; }
+int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int n, int passes, uint32_t *state,
+                      hipStream_t st);
 void launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, int n, int shift,
                        uint32_t *hist, uint32_t *partial, hipStream_t st);
 void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint32_t *vals, int ntot, double *sp,
@@ -55,8 +65,8 @@ int tree_blocks(int ntot);
 // box_end: ntot x (kMaxLevel + 1) ints, the end of every box at its first ion
 // (filled by launch_tree_count, read by launch_tree_build).
 void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
-                       int32_t *box_end, uint32_t *blockcnt, uint32_t *partial, uint32_t *total, TreeSummary *sum,
-                       hipStream_t st);
+                       int32_t *box_end, uint32_t *blockcnt, uint32_t *partial, uint32_t *total,
+                       const uint32_t *sort_err, TreeSummary *sum, hipStream_t st);
 void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
                        const uint32_t *rep_mask, const int32_t *box_end, const uint32_t *scanned, const BoxTable &bt,
                        const TreeSummary *sum, int nbox, hipStream_t st);

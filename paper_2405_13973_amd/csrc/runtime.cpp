@@ -444,16 +444,35 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     int cbits = 0;
     while ((1 << cbits) < nc) ++cbits;
     const int passes = (48 + cbits + 7) / 8;
-    for (int ps = 0; ps < passes; ++ps) {
-        launch_radix_pass(k0, v0, k1, v1, ntot, 8 * ps, hist, scan_part, st);
-        std::swap(k0, k1);
-        std::swap(v0, v1);
+    uint32_t *rstate;
+    PT_TRY(ws_get(ctx, "radix_state", sizeof(uint32_t) * radix_state_words(ntot), &rstate));
+    const uint32_t *sort_err = nullptr;
+    if (passes <= 8) {
+        ZeroRegions zr{};
+        zr.p[0] = (uint64_t *)rstate;
+        zr.n[0] = radix_state_zero_words() / 2;
+        launch_zero_regions(zr, st);
+        if (launch_radix_sort(k0, v0, k1, v1, ntot, passes, rstate, st) == 1) {
+            std::swap(k0, k1);
+            std::swap(v0, v1);
+        }
+        sort_err = rstate + radix_state_err();
+    } else {
+        for (int ps = 0; ps < passes; ++ps) {
+            launch_radix_pass(k0, v0, k1, v1, ntot, 8 * ps, hist, scan_part, st);
+            std::swap(k0, k1);
+            std::swap(v0, v1);
+        }
     }
     launch_gather(b.d_desc, b.ion_crystal, v0, ntot, sp, st);
-    launch_tree_count(b.d_desc, k0, ntot, s, rep, box_end, bcnt, scan_part, total, dsum, st);
+    launch_tree_count(b.d_desc, k0, ntot, s, rep, box_end, bcnt, scan_part, total, sort_err, dsum, st);
     PT_HIP(hipMemcpyAsync(ctx->h_sum, dsum, sizeof(TreeSummary), hipMemcpyDeviceToHost, st));
     PT_HIP(hipStreamSynchronize(st));
     const TreeSummary hs = *ctx->h_sum;
+    if (hs.sort_error) {
+        pt_set_error("radix sort: a workgroup gave up waiting for its predecessors' digit counts");
+        return PT_EDEVICE;
+    }
     const int nbox = hs.nbox;
     int nlev = 0;
     for (int l = 0; l <= kMaxLevel; ++l)
