@@ -35,7 +35,8 @@ PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "valu_fp32": 157.3, "valu_fp64": 
 # Arithmetic of one near-field pair as the P2P kernel performs it: 3 sub
 # (offset), 3 mul + 2 add (r^2), 1 rsqrt, 2 mul (r^-3), 3 mul + 3 add (field).
 P2P_FLOPS_PER_PAIR = 17
-PHASES = ["tree", "upward", "m2l_kernel", "m2l_reduce_l2l", "p2p_kernel", "l2p_partials", "total"]
+# phase 0 includes P2M, which runs on a second stream beside the list builders
+PHASES = ["tree_lists_p2m", "m2m", "m2l_kernel", "m2l_reduce_l2l", "p2p_kernel", "l2p_partials", "total"]
 LEAF_CANDIDATES = (32, 64, 128, 256)
 
 

@@ -101,7 +101,7 @@ struct pt_ctx {
     // the near field runs on its own stream, beside the far-field chain;
     // fork / join events order it after the lists and before the L2P kernel
     hipStream_t near_stream = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_tree = nullptr, ev_p2m = nullptr;
     hipEvent_t ev_near[2] = {};  // timing of the P2P kernel
     bool near_timed = false;
     int near_concurrent = -1;  // -1: by leaf size; 0 / 1: forced (PT_NEAR_CONCURRENT)
@@ -501,6 +501,16 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ensure_tables(ctx, p));
     const BoxTable bt = box_table(ctx);
     launch_tree_build(b.d_desc, roots, k0, ntot, s, rep, box_end, bcnt, bt, dsum, nbox, st);
+    // P2M needs only the boxes and the sorted positions: it runs on the
+    // second stream while the lists are built and the work-item count is read
+    // back; M2M waits for it
+    PT_HIP(hipEventRecord(ctx->ev_tree, st));
+    PT_HIP(hipStreamWaitEvent(ctx->near_stream, ctx->ev_tree, 0));
+    if (fp.precision == 1)
+        launch_p2m<float>(bt, sp, ntot, p, hs, ctx->tables.rec_f, (float *)M, s, ctx->near_stream);
+    else
+        launch_p2m<double>(bt, sp, ntot, p, hs, ctx->tables.rec_d, (double *)M, s, ctx->near_stream);
+    PT_HIP(hipEventRecord(ctx->ev_p2m, ctx->near_stream));
     int32_t *child_oct, *parent_oct, *src_items;
     uint32_t *item_off;
     PT_TRY(ws_get(ctx, "child_oct", sizeof(int32_t) * 8 * (size_t)nbox, &child_oct));
@@ -548,7 +558,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         const T *m2l = f ? (const T *)tb.m2l_f : (const T *)tb.m2l_d;
         const T *l2l = f ? (const T *)tb.l2l_f : (const T *)tb.l2l_d;
         const T *rec = f ? (const T *)tb.rec_f : (const T *)tb.rec_d;
-        launch_p2m<T>(bt, sp, ntot, p, hs, rec, (T *)M, s, st);
+        PT_HIP(hipStreamWaitEvent(st, ctx->ev_p2m, 0));  // P2M (second stream)
         launch_m2m<T>(bt, p, hs, m2m, tb.oct_slots, child_oct, (T *)M, (T *)m2l_part, st);
         launch_m2l_bucket(bt, nbox, m2l_cnt, m2l_list, st);
         // near field on its own stream, concurrently with M2L and L2L (vector
@@ -683,6 +693,8 @@ pt_status pt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, void *hip_str
     if (const char *e = getenv("PT_NEAR_CONCURRENT")) ctx->near_concurrent = atoi(e) ? 1 : 0;
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    PT_HIP(hipEventCreateWithFlags(&ctx->ev_tree, hipEventDisableTiming));
+    PT_HIP(hipEventCreateWithFlags(&ctx->ev_p2m, hipEventDisableTiming));
     for (auto &e : ctx->ev_near) PT_HIP(hipEventCreate(&e));
     *out = ctx.release();
     return PT_OK;
@@ -705,7 +717,7 @@ pt_status pt_ctx_destroy(pt_ctx *ctx)
     if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_near[0], ctx->ev_near[1]})
+    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_tree, ctx->ev_p2m, ctx->ev_near[0], ctx->ev_near[1]})
         if (e) (void)hipEventDestroy(e);
     if (ctx->near_stream) (void)hipStreamDestroy(ctx->near_stream);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);

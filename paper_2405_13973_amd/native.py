@@ -142,8 +142,9 @@ class Context:
         _check(load().pt_ctx_set_timing(self.h, 1 if on else 0))
 
     def phase_times(self, with_count=False):
-        """Mean per-evaluation phase times (ms) since set_timing(True): sort+tree+lists,
-        P2M+M2M, M2L kernel, M2L reduce+L2L, P2P kernel, L2P+partials, total."""
+        """Mean per-evaluation phase times (ms) since set_timing(True): sort+tree+lists
+        (with P2M beside them), M2M, M2L kernel, M2L reduce+L2L, P2P kernel, L2P+partials,
+        total."""
         ms = np.zeros(7)
         cnt = C.c_int64()
         _check(load().pt_ctx_phase_times(self.h, _ptr(ms), C.byref(cnt)))
