@@ -120,6 +120,47 @@ def cpu_baseline(cr, p, leaf, F_dir_gpu):
                       f"{el:.1f} s wall; direct sum checked on 48 sampled ions (max err/rms {dev:.1e})"}
 
 
+BATCH_LEAVES = (64, 128, 256)
+
+
+def tune_batch(ctx, cs, leaves, p_fixed, p0, precision, sync, time_it=True, target=1e-6, pmax=16):
+    """For each leaf size the smallest p whose RMS force error on the three
+    largest crystals is <= target (or p_fixed), then the fastest batch step.
+    Crystals are restored to their initial state afterwards by the caller."""
+    big = sorted(cs, key=lambda c: -c.n)[:3]
+    init = [c.read_state() for c in cs]
+    refs = []
+    for c in big:
+        c.set_force("direct")
+        refs.append(c.compute_forces())
+    best = None
+    for leaf in leaves:
+        for p in ([p_fixed] if p_fixed else range(p0, pmax + 1)):
+            errs = []
+            for c, R in zip(big, refs):
+                c.set_force("fmm", p, leaf, precision)
+                errs.append(rms_rel(c.compute_forces(), R))
+            log(f"  leaf {leaf} p={p}: max rms rel force err on the largest crystals {max(errs):.3e}")
+            if max(errs) <= target or p_fixed:
+                break
+        el = 0.0
+        if time_it:
+            for c in cs:
+                c.set_force("fmm", p, leaf, precision)
+            native.step_batch(cs, [2] * len(cs))
+            sync()
+            t0 = time.perf_counter()
+            native.step_batch(cs, [5] * len(cs))
+            sync()
+            el = time.perf_counter() - t0
+            for c, st in zip(cs, init):
+                c.set_state(st["pos"], st["vel"], st["step"])
+            log(f"  leaf {leaf} p={p}: {5 * sum(c.n for c in cs) / el:.4g} ion-steps/s")
+        if best is None or el < best[3]:
+            best = (leaf, p, errs, el)
+    return best[0], best[1], best[2]
+
+
 def bench_ensemble(a, ctx, sync):
     """Batched ensemble: independent crystals stepped together, one launch per
     phase per step for all of them."""
@@ -132,14 +173,12 @@ def bench_ensemble(a, ctx, sync):
         c.set_trap(B=cr.B, omega_z=cr.omega_z, dt=cr.dt)
         c.set_laser(cr.photon_mean)
         cs.append(c)
-    # accuracy of the chosen p on the largest crystals, against the FP64 direct sum
-    errs = []
-    for c in sorted(cs, key=lambda c: -c.n)[:3]:
-        c.set_force("direct")
-        F_dir = c.compute_forces()
-        c.set_force("fmm", a.p, a.leaf, a.precision)
-        errs.append(rms_rel(c.compute_forces(), F_dir))
-    for c in cs:
+    # the error bound is checked on the largest crystals against the FP64 direct
+    # sum; leaf size and p are tuned like config 3 unless given
+    leaves = (a.leaf,) if a.leaf else BATCH_LEAVES
+    a.leaf, a.p, errs = tune_batch(ctx, cs, leaves, a.p, a.p0, a.precision, sync, time_it=len(leaves) > 1)
+    for c, cr in zip(cs, crs):
+        c.set_state(cr.pos, cr.vel, 0)
         c.set_force("fmm", a.p, a.leaf, a.precision)
     native.step_batch(cs, [a.warmup] * len(cs))
     sync()
@@ -174,6 +213,12 @@ def bench_serving(a, ctx, sync):
     offered = sum(r.crystal.n * r.steps for r in reqs) / max(r.arrival_s for r in reqs)
     log(f"serving: {len(reqs)} requests over {max(r.arrival_s for r in reqs):.1f} s, offered "
         f"{offered:.3g} ion-steps/s")
+    # p from the error bound on the three largest requests (leaf 256 unless given)
+    big = sorted(reqs, key=lambda r: -r.crystal.n)[:3]
+    probe = [ctx.crystal(r.crystal.pos, r.crystal.vel, r.crystal.charge, r.crystal.mass, r.crystal.seed) for r in big]
+    a.leaf, a.p, errs = tune_batch(ctx, probe, (a.leaf or 256,), a.p, a.p0, a.precision, sync, time_it=False)
+    for c in probe:
+        c.destroy()
     srv = serving.Server(ctx, native, budget_bytes=a.budget_gb << 30, precision=a.precision, p=a.p, leaf=a.leaf,
                          chunk=a.chunk)
     rep = srv.run(reqs)
@@ -189,7 +234,8 @@ def bench_serving(a, ctx, sync):
         "config": {"workload": f"{len(reqs)} requests, Poisson arrivals 50/s, N log-uniform [200, 50000], "
                                f"K ~ U{{100..2000}}, photon mean 0.01, FMM p={a.p} leaf {a.leaf} ({a.precision}), "
                                f"tick {a.chunk} steps, budget {a.budget_gb} GiB",
-                   "requests": len(reqs)},
+                   "requests": len(reqs), "p": a.p, "leaf_size": a.leaf,
+                   "max_rms_rel_force_err_largest3": max(errs)},
         "latency_s": {"p50": p50, "p99": p99},
         "details": {"offered_ion_steps_per_s": offered, "achieved_ion_steps_per_s": rep.ion_steps_per_s,
                     "wall_s": rep.wall_s, "max_resident": rep.max_resident,
@@ -206,14 +252,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--leaf", type=int, default=0,
-                    help="leaf size (0: tune over %s for config3; 64 for ensemble / serving)" % (LEAF_CANDIDATES,))
+                    help="leaf size (0: tuned; serving: 256)")
     ap.add_argument("--p0", type=int, default=10, help="first p tried when choosing p")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--workload", choices=["config3", "ensemble", "serving"], default="config3",
                     help="config3: 1e5-ion crystal (default); ensemble: 256 crystals batched; serving: request stream")
-    ap.add_argument("--p", type=int, default=12, help="expansion degree for the ensemble / serving workloads")
+    ap.add_argument("--p", type=int, default=0,
+                    help="expansion degree for the ensemble / serving workloads (0: smallest meeting the bound)")
     ap.add_argument("--crystals", type=int, default=256)
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--chunk", type=int, default=50, help="serving: steps per tick")
@@ -244,7 +291,6 @@ def main():
         del src, dst
 
     if a.workload != "config3":
-        a.leaf = a.leaf or 64
         ctx = native.Context(0, hbm_budget=(a.budget_gb << 30) + (4 << 30), stream=stream.cuda_stream)
         out = bench_ensemble(a, ctx, sync) if a.workload == "ensemble" else bench_serving(a, ctx, sync)
         ctx.close()
