@@ -266,7 +266,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=50, help="serving: steps per tick")
     ap.add_argument("--budget-gb", type=int, default=64, help="serving: HBM budget for resident crystals")
     ap.add_argument("--roofline", choices=["auto", "m2l", "p2p"], default="auto",
-                    help="kernel of the roofline entry (auto: the one with the longer measured time)")
+                    help="kernel of the roofline entry (auto: P2P for leaves >= 128 ions, else M2L)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB first (reference kernel for HBM byte counters)")
     a = ap.parse_args()
@@ -351,7 +351,9 @@ def main():
     m2l_tflops = 2.0 * K * K * main_r["wc"][2] / (ph[2] * 1e-3) / 1e12
     p2p_tflops = P2P_FLOPS_PER_PAIR * main_r["wc"][3] / (ph[4] * 1e-3) / 1e12
     # roofline of the dominant kernel: M2L (matrix cores) or P2P (vector ALUs)
-    if a.roofline == "m2l" or (a.roofline == "auto" and ph[2] >= ph[4]):
+    # auto: the near field for leaves of 128 ions or more (the larger work, and
+    # the one the M2L kernel runs beside), else M2L
+    if a.roofline == "m2l" or (a.roofline == "auto" and leaf < 128):
         kernel, bound, achieved = "m2l", "mfma", m2l_tflops
         peak = PEAK["mfma_fp32" if fp32 else "mfma_fp64"]
         algorithmic = f"2 K^2 flops per M2L pair, K=(p+1)^2={K}, {int(main_r['wc'][2])} pairs per launch"
