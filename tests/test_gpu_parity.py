@@ -1,10 +1,14 @@
 """GPU path vs the CPU oracle, through the C ABI.
 
-Bars (written here, derived in the design doc):
+Bars:
   - Morton keys, permutation, boxes, interaction lists, photon counts: bit-exact.
   - direct-sum forces: max_i |F_gpu - F_oracle| / rms_j |F_oracle| <= 1e-12.
   - FP64 FMM forces vs the oracle FMM at the same p and leaf size: <= 1e-11 (same metric).
   - one step: positions / velocities within 1e-13 / 1e-11 relative to their rms.
+FP64 sums of 1e3-1e4 similar terms round at ~1e-15..1e-14 relative; the GPU and
+oracle FMM differ in basis and summation order only, so 1e-11 leaves three
+orders of margin while any formula error shows at the truncation level (~1e-6)
+or worse.
 """
 import math
 import sys

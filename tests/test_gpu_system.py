@@ -2,7 +2,7 @@
 their own sizes, checkpoint/resume, determinism, failure paths and admission
 under a small memory budget.
 
-Bars (derivations in DESIGN.md):
+Bars:
   - config 1, 100 FMM steps (FP64, p = 8, leaf 32) against the oracle run:
     positions within 1e-10 and velocities within 1e-8 of their rms; the
     per-step force parity is 1e-11 and 100 steps of 1 ns stay far inside
