@@ -666,20 +666,28 @@ extern "C" {
 
 const char *pt_last_error(void) { return g_err; }
 
-pt_status pt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, void *hip_stream, pt_ctx **out)
+// Releases everything a context holds (also a partly created one).
+static void release_ctx(pt_ctx *ctx)
 {
-    PT_REQUIRE(out, "out is NULL");
-    *out = nullptr;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
-        pt_set_error("no HIP device available");
-        return PT_EDEVICE;
-    }
-    PT_REQUIRE(hip_device >= 0 && hip_device < ndev, "device %d out of range [0, %d)", hip_device, ndev);
-    PT_HIP(hipSetDevice(hip_device));
-    std::unique_ptr<pt_ctx> ctx(new pt_ctx());
-    ctx->device = hip_device;
-    ctx->budget = hbm_budget_bytes;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->near_stream) (void)hipStreamSynchronize(ctx->near_stream);
+    for (auto &kv : ctx->allocs) (void)hipFree(kv.first);
+    ctx->allocs.clear();
+    if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
+    if (ctx->h_sum) (void)hipHostFree(ctx->h_sum);
+    if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_tree, ctx->ev_p2m, ctx->ev_near[0], ctx->ev_near[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->near_stream) (void)hipStreamDestroy(ctx->near_stream);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
+{
     if (hip_stream) {
         ctx->stream = (hipStream_t)hip_stream;
     } else {
@@ -696,7 +704,29 @@ pt_status pt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, void *hip_str
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_tree, hipEventDisableTiming));
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_p2m, hipEventDisableTiming));
     for (auto &e : ctx->ev_near) PT_HIP(hipEventCreate(&e));
-    *out = ctx.release();
+    return PT_OK;
+}
+
+pt_status pt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, void *hip_stream, pt_ctx **out)
+{
+    PT_REQUIRE(out, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        pt_set_error("no HIP device available");
+        return PT_EDEVICE;
+    }
+    PT_REQUIRE(hip_device >= 0 && hip_device < ndev, "device %d out of range [0, %d)", hip_device, ndev);
+    PT_HIP(hipSetDevice(hip_device));
+    pt_ctx *ctx = new pt_ctx();
+    ctx->device = hip_device;
+    ctx->budget = hbm_budget_bytes;
+    const pt_status st = init_ctx(ctx, hip_stream);
+    if (st != PT_OK) {
+        release_ctx(ctx);
+        return st;
+    }
+    *out = ctx;
     return PT_OK;
 }
 
@@ -707,21 +737,7 @@ pt_status pt_ctx_destroy(pt_ctx *ctx)
         pt_set_error("context still owns %d crystals", ctx->live);
         return PT_EBUSY;
     }
-    (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->near_stream) (void)hipStreamSynchronize(ctx->near_stream);
-    for (auto &kv : ctx->allocs) (void)hipFree(kv.first);
-    ctx->allocs.clear();
-    if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
-    if (ctx->h_sum) (void)hipHostFree(ctx->h_sum);
-    if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
-    for (auto &e : ctx->ev)
-        if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_tree, ctx->ev_p2m, ctx->ev_near[0], ctx->ev_near[1]})
-        if (e) (void)hipEventDestroy(e);
-    if (ctx->near_stream) (void)hipStreamDestroy(ctx->near_stream);
-    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
-    delete ctx;
+    release_ctx(ctx);
     return PT_OK;
 }
 
