@@ -447,8 +447,11 @@ constexpr int kP2PThreads = 256;  // four waves share one staged source tile
 // FP32 (1 ulp), the library routine for FP64.
 __device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double rsqrt_t(double x) { return rsqrt(x); }
-// Largest 1/r (1/m) of a near-field pair: separations below 1e-12 m are taken
-// as 1e-12 m (1/r^3 stays finite in FP32); only r = 0 reaches it in practice.
+// Added to every FP32 near-field r^2 (m^2): 1/r^3 <= 1e36 stays finite; at
+// 0.1 micrometre the relative change is 1e-10, far below FP32 rounding.
+constexpr double kSoft2 = 1e-24;
+// Largest FP64 near-field 1/r (1/m): separations below 1e-12 m are taken as
+// 1e-12 m; only r = 0 reaches it in practice.
 constexpr double kRinvMax = 1e12;
 
 template <typename T>
@@ -545,11 +548,16 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *
                 for (int q = q0; q < q1; ++q) {
                     const double4 v = src[q];
                     const T dx = (T)(xi - v.x), dy = (T)(yi - v.y), dz = (T)(zi - v.z);
-                    const T r2 = dx * dx + dy * dy + dz * dz;
-                    // r2 == 0 (the target itself: offsets are bit-identical, or a
-                    // coincident ion) gives rinv = inf, capped at kRinvMax, and
-                    // then a zero contribution since dx = dy = dz = 0
-                    const T rinv = min(rsqrt_t(r2), T(kRinvMax));
+                    // r = 0 (the target itself or a coincident ion) must give a
+                    // finite 1/r^3, whose contribution is then exactly zero since
+                    // dx = dy = dz = 0: FP32 adds kSoft2 to r^2 (folded into the
+                    // first FMA), FP64 caps 1/r at kRinvMax
+                    T rinv;
+                    if constexpr (sizeof(T) == 4) {
+                        rinv = rsqrt_t(dx * dx + dy * dy + (dz * dz + T(kSoft2)));
+                    } else {
+                        rinv = min(rsqrt_t(dx * dx + dy * dy + dz * dz), T(kRinvMax));
+                    }
                     const T ww = rinv * rinv * rinv;
                     px += dx * ww;
                     py += dy * ww;
