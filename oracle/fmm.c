@@ -580,8 +580,11 @@ static void or_box_center(const or_tree *t, int b, double c[3])
 
 /* Coulomb field sum_j (x_i - x_j)/|x_i - x_j|^3 (unit source weights) of the
  * targets listed in `targets` (ion ids; ns of them) through the FMM, written
- * to E (ns x 3).  need[b] marks the boxes whose local expansions are needed. */
-static void or_fmm_field(const or_tree *t, const double *pos, int p, int ns, const int32_t *targets, double *E)
+ * to E (ns x 3; may be NULL), and the potential sum_j 1/|x_i - x_j| to phi
+ * (ns; may be NULL): the local expansion's value (eq. FMM_local) plus the
+ * near field.  need[b] marks the boxes whose local expansions are needed. */
+static void or_fmm_field(const or_tree *t, const double *pos, int p, int ns, const int32_t *targets, double *E,
+                         double *phi)
 {
     int nb = t->nbox, K = (p + 1) * (p + 1);
     double complex *M = (double complex *)calloc((size_t)nb * (size_t)K, sizeof(double complex));
@@ -649,9 +652,9 @@ static void or_fmm_field(const or_tree *t, const double *pos, int p, int ns, con
     for (int a = 0; a < ns; ++a) {
         int id = targets[a];
         int leaf = leaf_of[slot_of[id]];
-        double c[3], g[3];
+        double c[3], g[3], v;
         or_box_center(t, leaf, c);
-        or_eval_le(p, L + (size_t)leaf * K, c, pos + 3 * id, NULL, g);
+        or_eval_le(p, L + (size_t)leaf * K, c, pos + 3 * id, &v, g);
         double ex = -g[0], ey = -g[1], ez = -g[2];
         for (int e = t->near_off[leaf]; e < t->near_off[leaf + 1]; ++e) {
             int s = t->near_src[e];
@@ -666,9 +669,11 @@ static void or_fmm_field(const or_tree *t, const double *pos, int p, int ns, con
                 double r = sqrt(r2);
                 double w = 1.0 / (r2 * r);
                 ex += dx * w; ey += dy * w; ez += dz * w;
+                v += 1.0 / r;
             }
         }
-        E[3 * a] = ex; E[3 * a + 1] = ey; E[3 * a + 2] = ez;
+        if (E) { E[3 * a] = ex; E[3 * a + 1] = ey; E[3 * a + 2] = ez; }
+        if (phi) phi[a] = v;
     }
     free(M); free(L); free(tmp); free(need); free(leaf_of); free(slot_of);
 }
@@ -681,7 +686,7 @@ int or_fmm_coulomb(int n, const double *pos, double q, int p, int leaf_size, dou
     if (!t) return -1;
     int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     for (int i = 0; i < n; ++i) ids[i] = i;
-    or_fmm_field(t, pos, p, n, ids, F);
+    or_fmm_field(t, pos, p, n, ids, F, NULL);
     double ke = 1.0 / (4.0 * OR_PI * OR_EPS0);
     for (int i = 0; i < 3 * n; ++i) F[i] *= ke * q * q;
     free(ids);
@@ -695,9 +700,31 @@ int or_fmm_coulomb_sampled(int n, const double *pos, double q, int p, int leaf_s
 {
     or_tree *t = or_tree_build(n, pos, leaf_size);
     if (!t) return -1;
-    or_fmm_field(t, pos, p, ns, idx, F);
+    or_fmm_field(t, pos, p, ns, idx, F, NULL);
     double ke = 1.0 / (4.0 * OR_PI * OR_EPS0);
     for (int i = 0; i < 3 * ns; ++i) F[i] *= ke * q * q;
+    or_tree_free(t);
+    return 0;
+}
+
+/* FMM Coulomb potential (volts) at the ions listed in idx (ns of them; all
+ * n ions in id order when idx is NULL): phi^fmm of eq. (rms_pot). */
+int or_fmm_potential(int n, const double *pos, double q, int p, int leaf_size, int ns, const int32_t *idx,
+                     double *phi)
+{
+    if (n == 0) return 0;
+    or_tree *t = or_tree_build(n, pos, leaf_size);
+    if (!t) return -1;
+    int32_t *ids = NULL;
+    if (!idx) {
+        ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        for (int i = 0; i < n; ++i) ids[i] = i;
+        ns = n;
+    }
+    or_fmm_field(t, pos, p, ns, idx ? idx : ids, NULL, phi);
+    double ke = 1.0 / (4.0 * OR_PI * OR_EPS0);
+    for (int i = 0; i < ns; ++i) phi[i] *= ke * q;
+    free(ids);
     or_tree_free(t);
     return 0;
 }

@@ -70,6 +70,10 @@ def lib():
             L.or_coulomb_direct.argtypes = [C.c_int, _d, C.c_double, _d]
             L.or_coulomb_direct_sampled.argtypes = [C.c_int, _d, C.c_double, C.c_int, _i32, _d]
             L.or_coulomb_energy.argtypes = [C.c_int, _d, C.c_double]
+            L.or_coulomb_potential_direct.argtypes = [C.c_int, _d, C.c_double, _d]
+            L.or_coulomb_potential_direct_sampled.argtypes = [C.c_int, _d, C.c_double, C.c_int, _i32, _d]
+            L.or_fmm_potential.argtypes = [C.c_int, _d, C.c_double, C.c_int, C.c_int, C.c_int, _nullable(np.int32), _d]
+            L.or_fmm_potential.restype = C.c_int
             L.or_coulomb_energy.restype = C.c_double
             L.or_energy.argtypes = [C.c_int, _d, _d, C.c_double, C.c_double, C.POINTER(Trap)]
             L.or_energy.restype = C.c_double
@@ -189,6 +193,38 @@ def fmm_coulomb_sampled(pos, q, p, leaf_size, idx):
     if rc:
         raise RuntimeError(f"or_fmm_coulomb_sampled failed ({rc})")
     return F
+
+
+def coulomb_potential_direct(pos, q, idx=None):
+    """phi_i = k_e q sum_{j != i} 1/r_ij (volts); at the ions in idx if given."""
+    pos = _pos(pos)
+    if idx is None:
+        phi = np.zeros(len(pos))
+        lib().or_coulomb_potential_direct(len(pos), pos, float(q), phi)
+        return phi
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    phi = np.zeros(len(idx))
+    lib().or_coulomb_potential_direct_sampled(len(pos), pos, float(q), len(idx), idx, phi)
+    return phi
+
+
+def fmm_potential(pos, q, p, leaf_size, idx=None):
+    """FMM potential (volts) at every ion, or at the ions in idx."""
+    pos = _pos(pos)
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+    ns = len(pos) if idx is None else len(idx)
+    phi = np.zeros(ns)
+    rc = lib().or_fmm_potential(len(pos), pos, float(q), int(p), int(leaf_size), ns, idx, phi)
+    if rc:
+        raise RuntimeError(f"or_fmm_potential failed ({rc})")
+    return phi
+
+
+def error_pot(phi, phi_dir):
+    """Relative RMS potential error of eq. (rms_pot)."""
+    phi, phi_dir = np.asarray(phi, np.float64), np.asarray(phi_dir, np.float64)
+    return float(np.sqrt(((phi - phi_dir) ** 2).sum() / (phi_dir ** 2).sum()))
 
 
 # --------------------------------------------------------------- integrator

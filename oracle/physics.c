@@ -183,6 +183,47 @@ void or_coulomb_direct_sampled(int n, const double *pos, double q, int ns, const
     }
 }
 
+/* Coulomb potential at each ion, phi_i = k_e q sum_{j != i} 1/r_ij (volts):
+ * the pair term of eq. (hamiltonian) per unit charge, the phi^dir of
+ * eq. (rms_pot).  Pairs at zero separation are left out. */
+void or_coulomb_potential_direct(int n, const double *pos, double q, double *phi)
+{
+    double ke = 1.0 / (4.0 * OR_PI * OR_EPS0);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = pos[3 * i] - pos[3 * j];
+            double dy = pos[3 * i + 1] - pos[3 * j + 1];
+            double dz = pos[3 * i + 2] - pos[3 * j + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r > 0.0) s += 1.0 / r;
+        }
+        phi[i] = ke * q * s;
+    }
+}
+
+/* The same for the ions listed in idx only (phi: ns values). */
+void or_coulomb_potential_direct_sampled(int n, const double *pos, double q, int ns, const int32_t *idx, double *phi)
+{
+    double ke = 1.0 / (4.0 * OR_PI * OR_EPS0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int a = 0; a < ns; ++a) {
+        int i = idx[a];
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = pos[3 * i] - pos[3 * j];
+            double dy = pos[3 * i + 1] - pos[3 * j + 1];
+            double dz = pos[3 * i + 2] - pos[3 * j + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r > 0.0) s += 1.0 / r;
+        }
+        phi[a] = ke * q * s;
+    }
+}
+
 /* Coulomb potential energy (1/2) sum_i q phi_coul(x_i) = k_e q^2 sum_{i<j} 1/r_ij. */
 double or_coulomb_energy(int n, const double *pos, double q)
 {

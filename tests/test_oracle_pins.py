@@ -311,6 +311,99 @@ def test_fmm_sampled_equals_full():
     np.testing.assert_array_equal(Fs, F[idx])
 
 
+# ------------------------------------------------------------- potential
+def test_potential_closed_forms():
+    """phi_i = k_e q sum_{j != i} 1/r_ij (pair term of eq. hamiltonian per unit charge):
+    two ions, and the 8 corners of a cube of side a (3 edges, 3 face and 1 body diagonal)."""
+    pos = np.array([[1e-5, -2e-5, 3e-5], [4e-5, 2e-5, -1e-5]])
+    r = np.linalg.norm(pos[0] - pos[1])
+    np.testing.assert_allclose(O.coulomb_potential_direct(pos, Q), [O.K_E * Q / r] * 2, rtol=1e-13)
+    a = 7e-6
+    c = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], float) * a + 1e-5
+    ref = O.K_E * Q / a * (3 + 3 / math.sqrt(2) + 1 / math.sqrt(3))
+    np.testing.assert_allclose(O.coulomb_potential_direct(c, Q), np.full(8, ref), rtol=1e-13)
+    # one ion alone, and a coincident pair (zero separation is left out)
+    assert O.coulomb_potential_direct(pos[:1], Q)[0] == 0.0
+    assert np.all(O.coulomb_potential_direct(np.stack([pos[0], pos[0]]), Q) == 0.0)
+
+
+def test_potential_matches_pairwise_distances():
+    """Brute force through scipy's pairwise distances, and the energy identity
+    U = (1/2) q sum_i phi_i = k_e q^2 sum_{i<j} 1/r_ij (no factor 1/2 dropped or doubled)."""
+    from scipy.spatial.distance import cdist, pdist
+    g = inputs.rng(21)
+    pos = inputs.uniform_ball(400, 1e-4, g)
+    D = cdist(pos, pos)
+    np.fill_diagonal(D, np.inf)
+    ref = O.K_E * Q * (1.0 / D).sum(1)
+    phi = O.coulomb_potential_direct(pos, Q)
+    np.testing.assert_allclose(phi, ref, rtol=1e-12)
+    U_pairs = O.K_E * Q * Q * (1.0 / pdist(pos)).sum()
+    assert abs(0.5 * Q * phi.sum() - U_pairs) <= 1e-12 * U_pairs
+    assert abs(O.coulomb_energy(pos, Q) - U_pairs) <= 1e-12 * U_pairs
+    idx = np.array([0, 3, 399], np.int32)
+    np.testing.assert_array_equal(O.coulomb_potential_direct(pos, Q, idx), phi[idx])
+
+
+def test_gauss_sphere_interior_potential():
+    """Uniformly charged ball: phi(r) = k_e Q (3 R^2 - r^2) / (2 R^3) inside, so phi falls
+    with r^2 at the rate k_e Q / (2 R^3); the lattice's own (Madelung) offset is a constant
+    that a straight-line fit in r^2 absorbs."""
+    a = 1e-6
+    R = 12 * a
+    g = np.arange(-13, 14) * a
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    pos = pos[np.linalg.norm(pos, axis=1) <= R]
+    Reff = (3 * len(pos) * a ** 3 / (4 * math.pi)) ** (1 / 3)
+    phi = O.coulomb_potential_direct(pos, Q)
+    r2 = (pos ** 2).sum(1)
+    inner = r2 < (0.6 * R) ** 2
+    slope = np.polyfit(r2[inner], phi[inner], 1)[0]
+    ref = -O.K_E * len(pos) * Q / (2 * Reff ** 3)
+    assert abs(slope / ref - 1) < 0.05, (slope, ref)
+
+
+def test_local_value_is_cluster_potential():
+    """eq. (FMM_local): the local expansion's value is the source cluster's potential to
+    truncation accuracy, and its finite differences give the expansion's own gradient."""
+    src, q = _cluster()
+    p = 12
+    cS = np.array([0.0, 3.0, 0.0])
+    L = O.m2l(O.p2m(src + cS, q, cS, p), cS, np.zeros(3), p)
+    for x in (np.array([0.2, -0.15, 0.1]), np.array([-0.3, 0.25, -0.2])):
+        v, g = O.eval_le(L, np.zeros(3), x, p)
+        exact = (q / np.linalg.norm(x[None] - (src + cS), axis=1)).sum()
+        assert abs(v - exact) < 1e-8 * abs(exact)
+        h = 1e-5
+        fd = [(O.eval_le(L, np.zeros(3), x + h * e, p)[0] - O.eval_le(L, np.zeros(3), x - h * e, p)[0]) / (2 * h)
+              for e in np.eye(3)]
+        np.testing.assert_allclose(g, fd, rtol=1e-7)
+
+
+def test_fmm_potential_error_decreases_geometrically_in_p():
+    """eq. (rms_pot) of the FMM potential against the direct one falls with the degree."""
+    g = inputs.rng(22)
+    pos = inputs.uniform_ball(300, 1e-4, g)
+    pd = O.coulomb_potential_direct(pos, Q)
+    errs = [O.error_pot(O.fmm_potential(pos, Q, p, 4), pd) for p in (2, 4, 6, 8, 10, 14, 18)]
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    rate = (errs[-1] / errs[0]) ** (1.0 / 16)
+    assert 0.2 < rate < 0.75, (rate, errs)
+    assert errs[-1] < 1e-7, errs
+
+
+def test_fmm_potential_single_leaf_is_direct_and_sampled_equals_full():
+    g = inputs.rng(23)
+    pos = inputs.uniform_ball(300, 1e-4, g)
+    pd = O.coulomb_potential_direct(pos, Q)
+    np.testing.assert_allclose(O.fmm_potential(pos, Q, 4, 300), pd, rtol=1e-13)
+    pos = inputs.uniform_ball(1500, 1e-4, g)
+    full = O.fmm_potential(pos, Q, 6, 16)
+    idx = np.array([0, 17, 400, 1499, 777], np.int32)
+    np.testing.assert_array_equal(O.fmm_potential(pos, Q, 6, 16, idx), full[idx])
+
+
 # ------------------------------------------------------------- tree
 def _interleave(k):
     """Bit interleave of three 16-bit ints, x highest of each triple (numpy, bit by bit)."""
