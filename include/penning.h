@@ -124,6 +124,23 @@ pt_status pt_compute_forces(pt_crystal *c, double *F_out);
  * host output.  All crystals must share the context and force parameters. */
 pt_status pt_compute_forces_batch(pt_crystal *const *cs, int n_crystals, double *const *F_out);
 
+/* Coulomb potential phi_i = k_e q sum_{j != i} 1/|x_i - x_j| (volts) at every
+ * ion at the current positions -- the pair term of eq. (hamiltonian) per unit
+ * charge, the quantity the paper's potential error (eq. rms_pot) compares --
+ * by the crystal's force method: the direct sum, or the FMM with the local
+ * expansion's value (eq. FMM_local) plus the near field.  Host output, n
+ * doubles, ion-id order; pairs at zero separation are left out.  Trap and
+ * wall potentials are not included.  Batch form as pt_compute_forces_batch.
+ * Errors: PT_EINVAL (NULL arguments, batch rules), PT_ENOMEM, PT_EDEVICE. */
+pt_status pt_compute_potential(pt_crystal *c, double *phi_out);
+pt_status pt_compute_potential_batch(pt_crystal *const *cs, int n_crystals, double *const *phi_out);
+/* Coulomb energy U = (1/2) q sum_i phi_i (joules) at the current positions
+ * (the pair part of eq. hamiltonian), with phi as pt_compute_potential; the
+ * sum over ions runs on the device in a fixed order (FP64), so only one
+ * double per crystal crosses to the host.  U_out: n_crystals doubles. */
+pt_status pt_coulomb_energy(pt_crystal *c, double *U_out);
+pt_status pt_coulomb_energy_batch(pt_crystal *const *cs, int n_crystals, double *U_out);
+
 /* Advance n_steps >= 0 steps (eq. time_ev2 with eq. velocity_kick). */
 pt_status pt_step(pt_crystal *c, int64_t n_steps);
 /* Advance crystal k by n_steps[k] steps; crystals still stepping are

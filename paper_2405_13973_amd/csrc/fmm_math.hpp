@@ -143,6 +143,73 @@ __host__ __device__ inline void l2p_field(int p, const T *L, const T *rec, T x, 
     ez = -g0;
 }
 
+// Field and value of a local expansion: l2p_field's field, plus the value
+//   phi h = sum_{n<=p} [Lh_n^0 Rh_n^0 + 2 sum_{m>0} Re(Lh_n^m conj(Rh_n^m))]
+// (orders m and -m of a real potential are complex conjugates); the columns
+// run to degree p for the value, the field terms stop at degree p - 1.
+template <typename T>
+__host__ __device__ inline void l2p_field_pot(int p, const T *L, const T *rec, T x, T y, T z, T &ex, T &ey, T &ez,
+                                              T &pot)
+{
+    const int Q = kq(p);
+    const T r2 = x * x + y * y + z * z;
+    T g0 = 0, g1r = 0, g1i = 0, v = 0;
+    T dre = 1, dim = 0;  // Rh_mu^mu
+    for (int mu = 0; mu <= p; ++mu) {
+        if (mu > 0) {
+            const T f = rec[mu * (mu + 1) / 2 + mu];
+            const T nre = f * (x * dre - y * dim);
+            const T nim = f * (x * dim + y * dre);
+            dre = nre;
+            dim = nim;
+        }
+        T r1re = 0, r1im = 0, r0re = 0, r0im = 0;
+        for (int np = mu; np <= p; ++np) {
+            const int q = np * (np + 1) / 2 + mu;
+            T cre, cim;  // Rh_np^mu
+            if (np == mu) {
+                cre = dre;
+                cim = dim;
+            } else {
+                const T a = rec[q] * z, b = rec[Q + q] * r2;
+                cre = a * r0re - b * r1re;
+                cim = a * r0im - b * r1im;
+            }
+            r1re = r0re;
+            r1im = r0im;
+            r0re = cre;
+            r0im = cim;
+            if (mu == 0) v += L[sidx_re(np, 0)] * cre;
+            else v += T(2) * (L[sidx_re(np, mu)] * cre + L[sidx_im(np, mu)] * cim);
+            if (np == p) continue;
+            const int n = np + 1;
+            {
+                const T lre = L[sidx_re(n, mu)];
+                const T lim = mu > 0 ? L[sidx_im(n, mu)] : T(0);
+                g0 += rec[2 * Q + q] * (lre * cre + lim * cim);
+            }
+            {
+                const T lre = L[sidx_re(n, mu + 1)];
+                const T lim = L[sidx_im(n, mu + 1)];
+                const T w = rec[3 * Q + q];
+                g1r += w * (lre * cre + lim * cim);
+                g1i += w * (lim * cre - lre * cim);
+            }
+            if (mu >= 1) {
+                const T lre = L[sidx_re(n, mu - 1)];
+                const T lim = mu - 1 > 0 ? L[sidx_im(n, mu - 1)] : T(0);
+                const T w = rec[4 * Q + q];
+                g1r -= w * (lre * cre + lim * cim);
+                g1i -= w * (lre * cim - lim * cre);
+            }
+        }
+    }
+    ex = g1r;
+    ey = g1i;
+    ez = -g0;
+    pot = v;
+}
+
 // conj(Rh_n^m(u)) of one point in real storage order into out[s * stride]
 // (s the storage index), from the recurrence table.
 template <typename T>

@@ -439,7 +439,8 @@ __global__ void k_m2l_reduce(BoxTable bt, int nbox, int Kp, int ngroup, const T 
 // phase's total with Kahan compensation.  The phases of a target are then
 // added in phase order.  Four waves share one staged tile, so that a compute
 // unit holds enough waves to hide the latency of the pair arithmetic.
-// Partial fields go to part[item][target][3].
+// Partial fields go to part[item][target][3]; with POT the potential sum
+// sum 1/r over the pairs with r > 0 comes along, in part[item][target][4].
 constexpr int kP2PStage = 512;
 constexpr int kP2PThreads = 256;  // four waves share one staged source tile
 
@@ -454,18 +455,19 @@ constexpr double kSoft2 = 1e-24;
 // 1e-12 m; only r = 0 reaches it in practice.
 constexpr double kRinvMax = 1e12;
 
-template <typename T>
+template <typename T, bool POT>
 __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *__restrict__ sp, int ntot,
                                                      const int2 *__restrict__ near, int stride,
                                                      const int4 *__restrict__ work, int n_items, T *__restrict__ part)
 {
     constexpr int NT = kP2PThreads;
+    constexpr int NC = POT ? 4 : 3;  // partial components per target
     constexpr int kU = kP2PStage / NT;
     __shared__ double4 src[kP2PStage];
     __shared__ int pre_s[kNearMax + 1];  // prefix of the item's range lengths
     __shared__ int beg_s[kNearMax];      // first ion of each range minus its prefix
     __shared__ int total_s;
-    __shared__ T hx[NT], hy[NT], hz[NT];
+    __shared__ T hx[NT], hy[NT], hz[NT], hp[POT ? NT : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int4 w = work[it];
@@ -504,7 +506,7 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *
         }
         __syncthreads();
         const int total = total_s;
-        T ax = 0, ay = 0, az = 0, cx = 0, cy = 0, cz = 0;
+        T ax = 0, ay = 0, az = 0, cx = 0, cy = 0, cz = 0, av = 0, cv = 0;
         for (int s0 = 0; s0 < total; s0 += kP2PStage) {
             const int n = min(kP2PStage, total - s0);
             // source index of each staged position: binary search for the
@@ -543,7 +545,7 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *
             __syncthreads();
             for (int q0 = ph < nph ? ph * blk : n; q0 < n; q0 += nph * blk) {
                 const int q1 = min(n, q0 + blk);
-                T px = 0, py = 0, pz = 0;
+                T px = 0, py = 0, pz = 0, pv = 0;
 #pragma unroll 4
                 for (int q = q0; q < q1; ++q) {
                     const double4 v = src[q];
@@ -551,9 +553,14 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *
                     // r = 0 (the target itself or a coincident ion) must give a
                     // finite 1/r^3, whose contribution is then exactly zero since
                     // dx = dy = dz = 0: FP32 adds kSoft2 to r^2 (folded into the
-                    // first FMA), FP64 caps 1/r at kRinvMax
-                    T rinv;
-                    if constexpr (sizeof(T) == 4) {
+                    // first FMA), FP64 caps 1/r at kRinvMax.  The potential has
+                    // no such factor: there, pairs with r = 0 are left out.
+                    T rinv, s2 = 0;
+                    if constexpr (POT) {
+                        s2 = dx * dx + dy * dy + dz * dz;
+                        if constexpr (sizeof(T) == 4) rinv = rsqrt_t(s2 + T(kSoft2));
+                        else rinv = min(rsqrt_t(s2), T(kRinvMax));
+                    } else if constexpr (sizeof(T) == 4) {
                         rinv = rsqrt_t(dx * dx + dy * dy + (dz * dz + T(kSoft2)));
                     } else {
                         rinv = min(rsqrt_t(dx * dx + dy * dy + dz * dz), T(kRinvMax));
@@ -562,6 +569,7 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *
                     px += dx * ww;
                     py += dy * ww;
                     pz += dz * ww;
+                    if constexpr (POT) pv += s2 > T(0) ? rinv : T(0);
                 }
                 T y_ = px - cx, t_ = ax + y_;
                 cx = (t_ - ax) - y_;
@@ -574,6 +582,12 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *
                 t_ = az + y_;
                 cz = (t_ - az) - y_;
                 az = t_;
+                if constexpr (POT) {
+                    y_ = pv - cv;
+                    t_ = av + y_;
+                    cv = (t_ - av) - y_;
+                    av = t_;
+                }
             }
             __syncthreads();  // all reads of src done before the next stage
         }
@@ -581,30 +595,36 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *
         hx[tid] = ax;
         hy[tid] = ay;
         hz[tid] = az;
+        if constexpr (POT) hp[tid] = av;
         __syncthreads();
         if (ph == 0) {
             for (int h = 1; h < nph; ++h) {
                 ax += hx[h * nt + ti];
                 ay += hy[h * nt + ti];
                 az += hz[h * nt + ti];
+                if constexpr (POT) av += hp[h * nt + ti];
             }
-            T *dst = part + ((size_t)it * 64 + ti) * 3;
+            T *dst = part + ((size_t)it * 64 + ti) * NC;
             dst[0] = ax;
             dst[1] = ay;
             dst[2] = az;
+            if constexpr (POT) dst[3] = av;
         }
     }
 }
 
 // Far field (L2P) of every ion of a leaf plus its near-field item partials,
-// added in item order.  Writes the field per unit charge in batch order.
-template <typename T>
+// added in item order.  Writes the field per unit charge in batch order; with
+// POT also the potential per unit charge (sum 1/r) into PHI.
+template <typename T, bool POT>
 __global__ __launch_bounds__(256) void k_far(BoxTable bt, const double *__restrict__ sp, int ntot, int p, int Kp,
                                             const T *__restrict__ L, const T *__restrict__ rec,
                                             const uint32_t *__restrict__ item_off,
                                             const int32_t *__restrict__ src_items, const T *__restrict__ part,
-                                            const uint32_t *__restrict__ vals, double *__restrict__ E)
+                                            const uint32_t *__restrict__ vals, double *__restrict__ E,
+                                            double *__restrict__ PHI)
 {
+    constexpr int NC = POT ? 4 : 3;
     __shared__ T rec_s[kRecFields * kq(kMaxP)];
     __shared__ T Lb[kMaxKp];
     const int b = blockIdx.x;
@@ -619,19 +639,23 @@ __global__ __launch_bounds__(256) void k_far(BoxTable bt, const double *__restri
     for (int k = bt.begin[b] + threadIdx.x; k < bt.end[b]; k += blockDim.x) {
         const int tl = k - bt.begin[b];
         const double xd = sp[k], yd = sp[ntot + k], zd = sp[2 * ntot + k];
-        T ex, ey, ez;
-        l2p_field<T>(p, Lb, rec_s, (T)((xd - g.x) * ih), (T)((yd - g.y) * ih), (T)((zd - g.z) * ih), ex, ey, ez);
-        double fx = (double)ex * ih * ih, fy = (double)ey * ih * ih, fz = (double)ez * ih * ih;
-        const T *pp = part + ((size_t)(base + (tl >> 6) * si) * 64 + (tl & 63)) * 3;
-        for (int j = 0; j < si; ++j, pp += 64 * 3) {
+        T ex, ey, ez, ev = 0;
+        const T ux = (T)((xd - g.x) * ih), uy = (T)((yd - g.y) * ih), uz = (T)((zd - g.z) * ih);
+        if constexpr (POT) l2p_field_pot<T>(p, Lb, rec_s, ux, uy, uz, ex, ey, ez, ev);
+        else l2p_field<T>(p, Lb, rec_s, ux, uy, uz, ex, ey, ez);
+        double fx = (double)ex * ih * ih, fy = (double)ey * ih * ih, fz = (double)ez * ih * ih, fv = (double)ev * ih;
+        const T *pp = part + ((size_t)(base + (tl >> 6) * si) * 64 + (tl & 63)) * NC;
+        for (int j = 0; j < si; ++j, pp += 64 * NC) {
             fx += (double)pp[0];
             fy += (double)pp[1];
             fz += (double)pp[2];
+            if constexpr (POT) fv += (double)pp[3];
         }
         const int gi = (int)vals[k];
         E[gi] = fx;
         E[ntot + gi] = fy;
         E[2 * ntot + gi] = fz;
+        if constexpr (POT) PHI[gi] = fv;
     }
 }
 
@@ -757,20 +781,27 @@ void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *
 
 template <typename T>
 void launch_near(const BoxTable &bt, const double *sp, int ntot, const int2 *near, int stride, const int4 *work,
-                 int n_items, T *part, hipStream_t st)
+                 int n_items, T *part, bool pot, hipStream_t st)
 {
-    if (n_items > 0)
-        k_p2p<T><<<std::min(n_items, 16384), kP2PThreads, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part);
+    if (n_items <= 0) return;
+    const int grid = std::min(n_items, 16384);
+    if (pot) k_p2p<T, true><<<grid, kP2PThreads, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part);
+    else k_p2p<T, false><<<grid, kP2PThreads, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part);
 }
 
 template <typename T>
 void launch_far(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
                 const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals, double *E,
-                int leaf_size, hipStream_t st)
+                double *phi, int leaf_size, hipStream_t st)
 {
     // one thread per ion of a leaf where the leaf size allows
     const int tb = std::min(256, std::max(64, (leaf_size + 63) / 64 * 64));
-    if (nbox > 0) k_far<T><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E);
+    if (nbox <= 0) return;
+    if (phi)
+        k_far<T, true><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E, phi);
+    else
+        k_far<T, false><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E,
+                                             nullptr);
 }
 
 template void launch_p2m<double>(const BoxTable &, const double *, int, int, const TreeSummary &, const double *,
@@ -794,14 +825,14 @@ template void launch_downward<double>(const BoxTable &, int, const TreeSummary &
 template void launch_downward<float>(const BoxTable &, int, const TreeSummary &, const float *, const int2 *,
                                      const int32_t *, float *, float *, hipStream_t);
 template void launch_near<double>(const BoxTable &, const double *, int, const int2 *, int, const int4 *, int,
-                                   double *, hipStream_t);
+                                   double *, bool, hipStream_t);
 template void launch_near<float>(const BoxTable &, const double *, int, const int2 *, int, const int4 *, int, float *,
-                                  hipStream_t);
+                                  bool, hipStream_t);
 template void launch_far<double>(const BoxTable &, const double *, int, int, int, const double *, const double *,
-                                  const uint32_t *, const int32_t *, const double *, const uint32_t *, double *, int,
-                                  hipStream_t);
+                                  const uint32_t *, const int32_t *, const double *, const uint32_t *, double *,
+                                  double *, int, hipStream_t);
 template void launch_far<float>(const BoxTable &, const double *, int, int, int, const float *, const float *,
-                                 const uint32_t *, const int32_t *, const float *, const uint32_t *, double *, int,
-                                 hipStream_t);
+                                 const uint32_t *, const int32_t *, const float *, const uint32_t *, double *,
+                                 double *, int, hipStream_t);
 
 }  // namespace pt

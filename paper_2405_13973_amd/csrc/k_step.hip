@@ -284,7 +284,9 @@ __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *_
     s[5 * n + i] = vz;
 }
 
-// Direct Coulomb field E_i = sum_{j != i} (x_i - x_j)/|x_i - x_j|^3 (FP64).
+// Direct Coulomb field E_i = sum_{j != i} (x_i - x_j)/|x_i - x_j|^3 (FP64);
+// with POT also the potential sum_{j != i} 1/|x_i - x_j| (both per unit
+// charge; the pair term of eq. hamiltonian).
 // A block takes kDirTB targets of one crystal (blk_crystal/blk_first) and
 // streams that crystal's ions through LDS in tiles; every thread owns two
 // targets.  Sources are summed in ascending index order, so the result does
@@ -292,17 +294,18 @@ __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *_
 constexpr int kDirTB = 256;
 constexpr int kDirT = 2;
 
+template <bool POT>
 __global__ __launch_bounds__(kDirTB) void k_direct(const CrystalDev *__restrict__ cs,
                                                    const int32_t *__restrict__ blk_crystal,
                                                    const int32_t *__restrict__ blk_first, int ntot,
-                                                   double *__restrict__ E)
+                                                   double *__restrict__ E, double *__restrict__ PHI)
 {
     __shared__ double sx[kDirTB], sy[kDirTB], sz[kDirTB];
     const int c = blk_crystal[blockIdx.x];
     const CrystalDev &cd = cs[c];
     const int n = cd.n;
     const double *s = cd.state;
-    double xi[kDirT], yi[kDirT], zi[kDirT], ax[kDirT], ay[kDirT], az[kDirT];
+    double xi[kDirT], yi[kDirT], zi[kDirT], ax[kDirT], ay[kDirT], az[kDirT], av[kDirT];
     int ti[kDirT];
 #pragma unroll
     for (int t = 0; t < kDirT; ++t) {
@@ -311,7 +314,7 @@ __global__ __launch_bounds__(kDirTB) void k_direct(const CrystalDev *__restrict_
         xi[t] = s[ii];
         yi[t] = s[n + ii];
         zi[t] = s[2 * n + ii];
-        ax[t] = ay[t] = az[t] = 0.0;
+        ax[t] = ay[t] = az[t] = av[t] = 0.0;
     }
     for (int base = 0; base < n; base += kDirTB) {
         const int j = base + threadIdx.x;
@@ -334,6 +337,7 @@ __global__ __launch_bounds__(kDirTB) void k_direct(const CrystalDev *__restrict_
                 ax[t] += dx * w;
                 ay[t] += dy * w;
                 az[t] += dz * w;
+                if constexpr (POT) av[t] += ri;
             }
         }
     }
@@ -344,6 +348,7 @@ __global__ __launch_bounds__(kDirTB) void k_direct(const CrystalDev *__restrict_
             E[g] = ax[t];
             E[ntot + g] = ay[t];
             E[2 * ntot + g] = az[t];
+            if constexpr (POT) PHI[g] = av[t];
         }
 }
 
@@ -406,9 +411,36 @@ void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int nto
 int direct_targets_per_block() { return kDirTB * kDirT; }
 
 void launch_direct(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int ntot,
-                   double *E, hipStream_t st)
+                   double *E, double *phi, hipStream_t st)
 {
-    if (nblk > 0) k_direct<<<nblk, kDirTB, 0, st>>>(cs, blk_crystal, blk_first, ntot, E);
+    if (nblk <= 0) return;
+    if (phi) k_direct<true><<<nblk, kDirTB, 0, st>>>(cs, blk_crystal, blk_first, ntot, E, phi);
+    else k_direct<false><<<nblk, kDirTB, 0, st>>>(cs, blk_crystal, blk_first, ntot, E, nullptr);
+}
+
+// One workgroup per crystal: each thread adds a strided subset of the
+// crystal's potentials in index order, then the 256 partial sums are added
+// pairwise in a fixed tree, so the result does not depend on the batch.
+constexpr int kSumTB = 256;
+__global__ __launch_bounds__(kSumTB) void k_phi_sum(const CrystalDev *__restrict__ cs, const double *__restrict__ phi,
+                                                    double *__restrict__ out)
+{
+    __shared__ double part[kSumTB];
+    const CrystalDev &cd = cs[blockIdx.x];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < cd.n; i += kSumTB) acc += phi[cd.ion_off + i];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kSumTB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+}
+
+void launch_phi_sum(const CrystalDev *cs, int nc, const double *phi, double *out, hipStream_t st)
+{
+    if (nc > 0) k_phi_sum<<<nc, kSumTB, 0, st>>>(cs, phi, out);
 }
 
 }  // namespace pt

@@ -40,8 +40,12 @@ void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCub
 void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
                        hipStream_t st);
 int direct_targets_per_block();
+// Direct field into E (3 x ntot); with phi non-null also the potential per
+// unit charge sum_{j != i} 1/r_ij into phi (ntot).
 void launch_direct(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int ntot,
-                   double *E, hipStream_t st);
+                   double *E, double *phi, hipStream_t st);
+// Per crystal c of the batch: out[c] = sum of phi over its ions (fixed order).
+void launch_phi_sum(const CrystalDev *cs, int nc, const double *phi, double *out, hipStream_t st);
 
 // k_tree.hip
 int scan_partials(int n);  // workspace entries launch_scan needs for n elements
@@ -112,14 +116,16 @@ int m2l_groups(int n2);  // slot groups of M2L (partial-sum buffer: groups x nbo
 template <typename T>
 void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_pad, const int2 *oct_slots,
                      const int32_t *parent_oct, T *L, T *part, hipStream_t st);
-// Near field over the work items into part (item x 64 x 3).
+// Near field over the work items into part (item x 64 x 3; with pot the
+// potential sum as a fourth component, item x 64 x 4).
 template <typename T>
 void launch_near(const BoxTable &bt, const double *sp, int ntot, const int2 *near, int stride, const int4 *work,
-                 int n_items, T *part, hipStream_t st);
-// Far field (L2P) + the item partials per ion into E (batch order).
+                 int n_items, T *part, bool pot, hipStream_t st);
+// Far field (L2P) + the item partials per ion into E (batch order); with phi
+// non-null also the potential per unit charge (part then holds 4 components).
 template <typename T>
 void launch_far(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
                 const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals, double *E,
-                int leaf_size, hipStream_t st);
+                double *phi, int leaf_size, hipStream_t st);
 
 }  // namespace pt

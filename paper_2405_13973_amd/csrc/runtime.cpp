@@ -397,8 +397,10 @@ static BoxTable box_table(pt_ctx *ctx)
 }
 
 // Coulomb field per unit charge of every ion of the batch into E (3 x ntot,
-// batch order).  Expects the bbox of the current positions accumulated.
-static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, double *E)
+// batch order); with phi non-null also the potential per unit charge
+// (sum_{j != i} 1/r_ij, ntot).  Expects the bbox of the current positions
+// accumulated.
+static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, double *E, double *phi = nullptr)
 {
     hipStream_t st = ctx->stream;
     const int ntot = b.ntot, nc = (int)b.cs.size();
@@ -412,7 +414,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     ctx->near_timed = false;
     mark(ctx, 0);
     if (fp.method == 0) {
-        launch_direct(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, ntot, E, st);
+        launch_direct(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, ntot, E, phi, st);
         for (int i = 1; i <= kPhases - 1; ++i) mark(ctx, i);
         ctx->timing_pending = ctx->timing;
         return PT_OK;
@@ -533,7 +535,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     int4 *work;
     void *ppart;
     PT_TRY(ws_get(ctx, "p2p_work", sizeof(int4) * (size_t)std::max(1, n_items), &work));
-    PT_TRY(ws_get(ctx, "p2p_part", esz * 64 * 3 * (size_t)std::max(1, n_items), (char **)&ppart));
+    const int ncomp = phi ? 4 : 3;  // near-field partial components per target
+    PT_TRY(ws_get(ctx, "p2p_part", esz * 64 * ncomp * (size_t)std::max(1, n_items), (char **)&ppart));
     launch_p2p_items(bt, dsum, nbox, near_cnt, stride, item_off, src_items, cuts, work, st);
     int32_t *m2l_cnt, *m2l_list;
     void *m2l_part;
@@ -575,7 +578,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         }
         auto near_field = [&]() -> pt_status {
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[0], ns));
-            launch_near<T>(bt, sp, ntot, near, stride, work, n_items, (T *)ppart, ns);
+            launch_near<T>(bt, sp, ntot, near, stride, work, n_items, (T *)ppart, phi != nullptr, ns);
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[1], ns));
             ctx->near_timed = ctx->timing;
             if (concurrent) PT_HIP(hipEventRecord(ctx->ev_join, ns));
@@ -591,7 +594,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         if (!concurrent) PT_TRY(near_field());
         mark(ctx, 5);
         if (concurrent) PT_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
-        launch_far<T>(bt, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E, s, st);
+        launch_far<T>(bt, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E, phi, s,
+                      st);
         return PT_OK;
     };
     PT_TRY(fp.precision == 1 ? run(float(0)) : run(double(0)));
@@ -906,33 +910,81 @@ static pt_status check_batch(pt_crystal *const *cs, int nc)
     return PT_OK;
 }
 
-pt_status pt_compute_forces_batch(pt_crystal *const *cs, int n_crystals, double *const *F_out)
+// One Coulomb evaluation of a batch at its current positions: forces (F_out),
+// potentials (phi_out) and / or Coulomb energies (U_out), each optional.
+static pt_status evaluate_batch(pt_crystal *const *cs, int n_crystals, double *const *F_out, double *const *phi_out,
+                                double *U_out)
 {
-    PT_TRY(check_batch(cs, n_crystals));
-    PT_REQUIRE(F_out, "F_out NULL");
-    for (int i = 0; i < n_crystals; ++i) PT_REQUIRE(F_out[i], "F_out[%d] NULL", i);
     pt_ctx *ctx = cs[0]->ctx;
     PT_HIP(hipSetDevice(ctx->device));
     Batch b;
     PT_TRY(form_batch(ctx, std::vector<pt_crystal *>(cs, cs + n_crystals), b));
     unsigned long long *bbox;
-    double *E;
+    double *E, *phi = nullptr, *usum = nullptr;
     PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * bbox_words(n_crystals), &bbox));
     PT_TRY(ws_get(ctx, "E", sizeof(double) * 3 * (size_t)b.ntot, &E));
+    if (phi_out || U_out) PT_TRY(ws_get(ctx, "phi", sizeof(double) * (size_t)std::max(1, b.ntot), &phi));
+    if (U_out) PT_TRY(ws_get(ctx, "phi_sum", sizeof(double) * (size_t)n_crystals, &usum));
     launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, n_crystals, 0, bbox, ctx->stream);
-    PT_TRY(eval_field(ctx, b, cs[0]->force, E));
-    std::vector<double> h(3 * (size_t)b.ntot);
-    PT_HIP(hipMemcpyAsync(h.data(), E, sizeof(double) * 3 * b.ntot, hipMemcpyDeviceToHost, ctx->stream));
+    PT_TRY(eval_field(ctx, b, cs[0]->force, E, phi));
+    std::vector<double> h, hp, hu;
+    if (F_out) {
+        h.resize(3 * (size_t)b.ntot);
+        PT_HIP(hipMemcpyAsync(h.data(), E, sizeof(double) * 3 * b.ntot, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    if (phi_out) {
+        hp.resize((size_t)b.ntot);
+        PT_HIP(hipMemcpyAsync(hp.data(), phi, sizeof(double) * b.ntot, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    if (U_out) {
+        launch_phi_sum(b.d_desc, n_crystals, phi, usum, ctx->stream);
+        hu.resize((size_t)n_crystals);
+        PT_HIP(hipMemcpyAsync(hu.data(), usum, sizeof(double) * n_crystals, hipMemcpyDeviceToHost, ctx->stream));
+    }
     PT_HIP(hipStreamSynchronize(ctx->stream));
     PT_TRY(finish_timing(ctx));
     for (int c = 0; c < n_crystals; ++c) {
-        const double coul = cs[c]->q * cs[c]->q / (4.0 * kPi * kEps0);
+        const double ke = 1.0 / (4.0 * kPi * kEps0), q = cs[c]->q;
         const int off = b.off[c];
-        for (int64_t i = 0; i < cs[c]->n; ++i)
-            for (int d = 0; d < 3; ++d) F_out[c][3 * i + d] = coul * h[(size_t)d * b.ntot + off + i];
+        if (F_out)
+            for (int64_t i = 0; i < cs[c]->n; ++i)
+                for (int d = 0; d < 3; ++d) F_out[c][3 * i + d] = ke * q * q * h[(size_t)d * b.ntot + off + i];
+        if (phi_out)
+            for (int64_t i = 0; i < cs[c]->n; ++i) phi_out[c][i] = ke * q * hp[(size_t)off + i];
+        if (U_out) U_out[c] = 0.5 * ke * q * q * hu[c];
     }
     return PT_OK;
 }
+
+pt_status pt_compute_forces_batch(pt_crystal *const *cs, int n_crystals, double *const *F_out)
+{
+    PT_TRY(check_batch(cs, n_crystals));
+    PT_REQUIRE(F_out, "F_out NULL");
+    for (int i = 0; i < n_crystals; ++i) PT_REQUIRE(F_out[i], "F_out[%d] NULL", i);
+    return evaluate_batch(cs, n_crystals, F_out, nullptr, nullptr);
+}
+
+pt_status pt_compute_potential_batch(pt_crystal *const *cs, int n_crystals, double *const *phi_out)
+{
+    PT_TRY(check_batch(cs, n_crystals));
+    PT_REQUIRE(phi_out, "phi_out NULL");
+    for (int i = 0; i < n_crystals; ++i) PT_REQUIRE(phi_out[i], "phi_out[%d] NULL", i);
+    return evaluate_batch(cs, n_crystals, nullptr, phi_out, nullptr);
+}
+
+pt_status pt_compute_potential(pt_crystal *c, double *phi_out)
+{
+    return pt_compute_potential_batch(&c, 1, &phi_out);
+}
+
+pt_status pt_coulomb_energy_batch(pt_crystal *const *cs, int n_crystals, double *U_out)
+{
+    PT_TRY(check_batch(cs, n_crystals));
+    PT_REQUIRE(U_out, "U_out NULL");
+    return evaluate_batch(cs, n_crystals, nullptr, nullptr, U_out);
+}
+
+pt_status pt_coulomb_energy(pt_crystal *c, double *U_out) { return pt_coulomb_energy_batch(&c, 1, U_out); }
 
 pt_status pt_compute_forces(pt_crystal *c, double *F_out)
 {

@@ -70,6 +70,10 @@ def load():
         "pt_set_state": [_vp, _dp, _dp, C.c_int64],
         "pt_compute_forces": [_vp, _dp],
         "pt_compute_forces_batch": [C.POINTER(_vp), C.c_int, C.POINTER(_dp)],
+        "pt_compute_potential": [_vp, _dp],
+        "pt_compute_potential_batch": [C.POINTER(_vp), C.c_int, C.POINTER(_dp)],
+        "pt_coulomb_energy": [_vp, _dp],
+        "pt_coulomb_energy_batch": [C.POINTER(_vp), C.c_int, _dp],
         "pt_step": [_vp, C.c_int64],
         "pt_step_batch": [C.POINTER(_vp), C.c_int, C.POINTER(C.c_int64)],
         "pt_synchronize": [_vp],
@@ -203,6 +207,16 @@ class Crystal:
         _check(load().pt_compute_forces(self.h, _ptr(F)))
         return F
 
+    def compute_potential(self):
+        phi = np.zeros(self.n)
+        _check(load().pt_compute_potential(self.h, _ptr(phi)))
+        return phi
+
+    def coulomb_energy(self):
+        U = C.c_double()
+        _check(load().pt_coulomb_energy(self.h, C.byref(U)))
+        return U.value
+
     def step(self, n_steps: int):
         _check(load().pt_step(self.h, int(n_steps)))
 
@@ -256,3 +270,20 @@ def compute_forces_batch(crystals):
     fo = (_dp * len(crystals))(*[_ptr(o) for o in outs])
     _check(L.pt_compute_forces_batch(arr, len(crystals), fo))
     return outs
+
+
+def compute_potential_batch(crystals):
+    L = load()
+    outs = [np.zeros(c.n) for c in crystals]
+    arr = (_vp * len(crystals))(*[c.h for c in crystals])
+    po = (_dp * len(crystals))(*[_ptr(o) for o in outs])
+    _check(L.pt_compute_potential_batch(arr, len(crystals), po))
+    return outs
+
+
+def coulomb_energy_batch(crystals):
+    L = load()
+    U = np.zeros(len(crystals))
+    arr = (_vp * len(crystals))(*[c.h for c in crystals])
+    _check(L.pt_coulomb_energy_batch(arr, len(crystals), _ptr(U)))
+    return U
