@@ -35,6 +35,8 @@ PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "valu_fp32": 157.3, "valu_fp64": 
 # Arithmetic of one near-field pair as the P2P kernel performs it: 3 sub
 # (offset), 3 mul + 2 add (r^2), 1 rsqrt, 2 mul (r^-3), 3 mul + 3 add (field).
 P2P_FLOPS_PER_PAIR = 17
+# with the potential: one add more (the 1/r sum)
+P2P_POT_FLOPS_PER_PAIR = 18
 # phase 0 includes P2M, which runs on a second stream beside the list builders
 PHASES = ["tree_lists_p2m", "m2m", "m2l_kernel", "m2l_reduce_l2l", "p2p_kernel", "l2p_partials", "total"]
 LEAF_CANDIDATES = (32, 64, 128, 256)
@@ -64,6 +66,7 @@ def log(*a):
 
 
 def rms_rel(F, ref):
+    """Relative RMS error: of the forces, and of the potential (eq. rms_pot)."""
     return math.sqrt(((F - ref) ** 2).sum() / (ref ** 2).sum())
 
 
@@ -115,9 +118,57 @@ def cpu_baseline(cr, p, leaf, F_dir_gpu):
         steps += more
     el = time.perf_counter() - t0
     log(f"  oracle: {steps} FMM steps of {cr.n} ions (p={p}, leaf={leaf}) in {el:.1f} s on {cores} threads")
+    # the oracle's FMM potential of all ions once (the potential measurement's baseline)
+    t0 = time.perf_counter()
+    O.fmm_potential(cr.pos, cr.charge, p, leaf)
+    pel = time.perf_counter() - t0
+    log(f"  oracle potential: {pel:.1f} s for {cr.n} ions")
     return {"value": cr.n * steps / el, "unit": "ion-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} full FP64 FMM steps (p={p}, leaf {leaf}) of the same {cr.n}-ion crystal, "
-                      f"{el:.1f} s wall; direct sum checked on 48 sampled ions (max err/rms {dev:.1e})"}
+                      f"{el:.1f} s wall; direct sum checked on 48 sampled ions (max err/rms {dev:.1e})",
+            "potential_ion_evals_per_s": cr.n / pel,
+            "potential_sample": f"one FP64 FMM potential evaluation of all {cr.n} ions, {pel:.1f} s wall"}
+
+
+def bench_potential(ctx, c, cr, p, leaf, prec, evals=10):
+    """Coulomb potential at every ion (the quantity of eq. rms_pot) with the
+    benchmark's force parameters: device time per evaluation (HIP events),
+    the near-field kernel's rate, Error_pot against the FP64 direct potential
+    and the energy."""
+    c.set_state(cr.pos, cr.vel, 0)
+    c.set_force("direct")
+    phi_dir = c.compute_potential()
+    c.set_force("fmm", p, leaf, prec)
+    for _ in range(2):
+        c.compute_forces()
+    ctx.set_timing(True)
+    for _ in range(evals):
+        c.compute_forces()
+    f_ph = ctx.phase_times()
+    ctx.set_timing(False)
+    phi = c.compute_potential()
+    ctx.set_timing(True)
+    for _ in range(evals):
+        c.compute_potential()
+    ph = ctx.phase_times()
+    wc = ctx.work_counts()
+    ctx.set_timing(False)
+    U = c.coulomb_energy()
+    err = rms_rel(phi, phi_dir)
+    tfl = P2P_POT_FLOPS_PER_PAIR * wc[3] / (ph[4] * 1e-3) / 1e12
+    peak = PEAK["valu_fp32" if prec == "mixed" else "valu_fp64"]
+    out = {
+        "ms_per_eval": float(ph[6]), "ion_evals_per_s": cr.n / (ph[6] * 1e-3),
+        "force_eval_ms": float(f_ph[6]), "potential_over_force_time": float(ph[6] / f_ph[6]),
+        "error_pot": err, "coulomb_energy_J": U, "p": p, "leaf_size": leaf, "precision": prec,
+        "p2p_kernel_ms": float(ph[4]),
+        "p2p_roofline": {"bound": "alu", "achieved": tfl, "peak": peak, "unit": "TFLOP/s", "frac": tfl / peak,
+                         "traffic": measured_traffic("p2p_pot", p, leaf, prec, cr.n),
+                         "algorithmic": f"{P2P_POT_FLOPS_PER_PAIR} flops per near-field pair, {int(wc[3])} "
+                                        f"ordered pairs per launch"},
+    }
+    log(f"  potential: {ph[6]:.3f} ms per evaluation (forces {f_ph[6]:.3f}), Error_pot {err:.2e}, U = {U:.6e} J")
+    return out
 
 
 BATCH_LEAVES = (64, 128, 256)
@@ -257,6 +308,7 @@ def main():
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-potential", action="store_true", help="skip the Coulomb-potential measurement")
     ap.add_argument("--workload", choices=["config3", "ensemble", "serving"], default="config3",
                     help="config3: 1e5-ion crystal (default); ensemble: 256 crystals batched; serving: request stream")
     ap.add_argument("--p", type=int, default=0,
@@ -406,6 +458,11 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cr, p, leaf, F_dir)
         out["details"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    if not a.no_potential:
+        out["potential"] = bench_potential(ctx, c, cr, p, leaf, a.precision)
+        if "cpu_baseline" in out:
+            out["potential"]["gpu_over_cpu"] = (out["potential"]["ion_evals_per_s"] /
+                                                out["cpu_baseline"]["potential_ion_evals_per_s"])
     ctx.close()
     print(json.dumps(out), flush=True)
 

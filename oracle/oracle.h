@@ -9,6 +9,7 @@
  * of 3D ion crystal dynamics in a Penning trap using the fast multipole
  * method" (arXiv 2405.13973), cited by section / equation label:
  *   forces ........ Sec. 2.1, eqs. (pot_trap), (pot_wall), (hamiltonian)
+ *   potential ..... eq. (hamiltonian) pair term per unit charge, eq. (rms_pot)
  *   integrator .... Sec. 2.2, eqs. (time_ev1), (time_ev2), (U0), (velocity_kick)
  *   photons ....... Sec. 2.2, eq. (laser_kick) and the Poisson-count passage
  *   FMM ........... Sec. 2.3, eqs. (FMM_coul), (multipole_error), (FMM_local),
