@@ -38,12 +38,35 @@ typedef struct {
     double omega_r;
 } or_trap;
 
-/* Fixed-mean isotropic photon-recoil model: per ion and per step a Poisson
- * number of photons with mean `mean_per_step`, each a recoil of h/(lambda m)
- * in a uniformly random direction. mean_per_step == 0 switches it off. */
+/* One laser beam of eq. (scattering_rate): propagation direction khat
+ * (normalised before use), detuning Delta (rad/s), peak saturation s0 and
+ * either a uniform profile (S = s0) or the 2D Gaussian of the cooling
+ * appendix, S = s0 exp(-(y - offset_y)^2 / waist_y^2 - z^2 / waist_z^2),
+ * in lab coordinates (m). */
+typedef struct {
+    double khat[3];
+    double detuning;
+    double s0;
+    double waist_y, waist_z;
+    double offset_y;
+    int uniform;
+} or_beam;
+
+#define OR_MAX_BEAMS 4
+
+/* Photon model.  mode 1 (or mode 0 with mean_per_step > 0): the fixed-mean
+ * isotropic model -- per ion and per step a Poisson number of photons with
+ * mean `mean_per_step`, each an emission recoil of h/(lambda m) in a
+ * uniformly random direction.  mode 2: the beams of eq. (scattering_rate)
+ * with natural linewidth gamma0 (rad/s), absorption and emission recoils of
+ * eq. (laser_kick).  Otherwise off. */
 typedef struct {
     double mean_per_step;
     double wavelength;
+    int mode;
+    double gamma0;
+    int n_beams;
+    or_beam beam[OR_MAX_BEAMS];
 } or_laser;
 
 /* Coulomb method: 0 = direct pairwise sum, 1 = fast multipole method. */

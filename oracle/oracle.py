@@ -29,8 +29,48 @@ class Trap(C.Structure):
     _fields_ = [("B", C.c_double), ("omega_z", C.c_double), ("delta", C.c_double), ("omega_r", C.c_double)]
 
 
+class Beam(C.Structure):
+    _fields_ = [("khat", C.c_double * 3), ("detuning", C.c_double), ("s0", C.c_double), ("waist_y", C.c_double),
+                ("waist_z", C.c_double), ("offset_y", C.c_double), ("uniform", C.c_int)]
+
+
 class Laser(C.Structure):
-    _fields_ = [("mean_per_step", C.c_double), ("wavelength", C.c_double)]
+    _fields_ = [("mean_per_step", C.c_double), ("wavelength", C.c_double), ("mode", C.c_int), ("gamma0", C.c_double),
+                ("n_beams", C.c_int), ("beam", Beam * 4)]
+
+
+def laser_struct(laser):
+    """Laser from a dict: {mean_per_step, wavelength} (fixed-mean mode) or
+    {mode: 2, wavelength, gamma0, beams: [{khat, detuning, s0, waist_y, waist_z,
+    offset_y, uniform}, ...]} (beam mode); None: off."""
+    la = Laser()
+    la.wavelength = 313e-9
+    if not laser:
+        return la
+    la.wavelength = laser["wavelength"]
+    if laser.get("mode", 1) == 2:
+        la.mode = 2
+        la.gamma0 = laser["gamma0"]
+        la.n_beams = len(laser["beams"])
+        for l, b in enumerate(laser["beams"]):
+            la.beam[l].khat[:] = [float(x) for x in b["khat"]]
+            la.beam[l].detuning = b["detuning"]
+            la.beam[l].s0 = b["s0"]
+            la.beam[l].waist_y = b.get("waist_y", 1.0)
+            la.beam[l].waist_z = b.get("waist_z", 1.0)
+            la.beam[l].offset_y = b.get("offset_y", 0.0)
+            la.beam[l].uniform = int(b.get("uniform", 0))
+    else:
+        la.mode = 1
+        la.mean_per_step = laser["mean_per_step"]
+    return la
+
+
+def scattering_rate(laser, l, x, v):
+    """gamma_L of beam l at position x with velocity v (eq. scattering_rate), 1/s."""
+    la = laser_struct(laser)
+    return lib().or_scattering_rate(C.byref(la), int(l), np.ascontiguousarray(x, np.float64),
+                                    np.ascontiguousarray(v, np.float64))
 
 
 class Force(C.Structure):
@@ -70,6 +110,8 @@ def lib():
             L.or_coulomb_direct.argtypes = [C.c_int, _d, C.c_double, _d]
             L.or_coulomb_direct_sampled.argtypes = [C.c_int, _d, C.c_double, C.c_int, _i32, _d]
             L.or_coulomb_energy.argtypes = [C.c_int, _d, C.c_double]
+            L.or_scattering_rate.argtypes = [C.POINTER(Laser), C.c_int, _d, _d]
+            L.or_scattering_rate.restype = C.c_double
             L.or_coulomb_potential_direct.argtypes = [C.c_int, _d, C.c_double, _d]
             L.or_coulomb_potential_direct_sampled.argtypes = [C.c_int, _d, C.c_double, C.c_int, _i32, _d]
             L.or_fmm_potential.argtypes = [C.c_int, _d, C.c_double, C.c_int, C.c_int, C.c_int, _nullable(np.int32), _d]
@@ -239,7 +281,7 @@ def run(pos, vel, q, m, trap: dict, dt, nsteps, *, t0=0.0, step0=0, seed=0, lase
     """nsteps oracle steps; returns (pos, vel[, photons of the last step])."""
     pos, vel = _pos(pos).copy(), _pos(vel).copy()
     tr = Trap(trap["B"], trap["omega_z"], trap.get("delta", 0.0), trap.get("omega_r", 0.0))
-    la = Laser(laser["mean_per_step"], laser["wavelength"]) if laser else Laser(0.0, 313e-9)
+    la = laser_struct(laser)
     fo = Force(0 if method == "direct" else 1, int(p), int(leaf_size))
     ph = np.zeros(len(pos), np.int32)
     rc = lib().or_run(len(pos), pos, vel, float(q), float(m), C.byref(tr), C.byref(la), C.byref(fo), float(t0),

@@ -280,6 +280,70 @@ void or_u0(int n, double *pos, double *vel, double wc, double tau)
     }
 }
 
+/* ---------------------------------------------------------------------
+ * Beam mode, eq. (scattering_rate): the photon absorption rate of an ion at
+ * x with velocity v from beam l,
+ *   gamma = S gamma0 (gamma0/2)^2 / ((gamma0/2)^2 (1 + 2 S) + (Delta - k.v)^2),
+ * with k = (2 pi / lambda) khat and the saturation S of the beam's profile.
+ * ------------------------------------------------------------------- */
+static void or_unit(const double a[3], double u[3])
+{
+    double r = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    u[0] = a[0] / r;
+    u[1] = a[1] / r;
+    u[2] = a[2] / r;
+}
+
+double or_scattering_rate(const or_laser *la, int l, const double x[3], const double v[3])
+{
+    const or_beam *b = &la->beam[l];
+    double kh[3];
+    or_unit(b->khat, kh);
+    double S = b->s0;
+    if (!b->uniform) {
+        double dy = x[1] - b->offset_y, z = x[2];
+        S = b->s0 * exp(-(dy * dy / (b->waist_y * b->waist_y) + z * z / (b->waist_z * b->waist_z)));
+    }
+    double k = 2.0 * OR_PI / la->wavelength;
+    double kv = k * (kh[0] * v[0] + kh[1] * v[1] + kh[2] * v[2]);
+    double dd = b->detuning - kv;
+    double g2 = 0.25 * la->gamma0 * la->gamma0;
+    return S * la->gamma0 * g2 / (g2 * (1.0 + 2.0 * S) + dd * dd);
+}
+
+/* Velocity change of eq. (laser_kick) for ion `ion` at `step` in beam mode:
+ * per beam a Poisson count n_l with mean gamma_l dt (slot l << 16), then
+ * n_l absorptions along khat_l and n_l isotropic emissions (slots
+ * (l << 16) | j), each of momentum h / lambda.  Returns the total count. */
+static int or_beam_kick(const or_laser *la, uint64_t seed, uint32_t ion, uint64_t step, double m, double dt,
+                        const double x[3], const double v[3], double dv[3])
+{
+    double rec = OR_H_PLANCK / (la->wavelength * m);
+    int total = 0;
+    dv[0] = dv[1] = dv[2] = 0.0;
+    for (int l = 0; l < la->n_beams; ++l) {
+        double F[17], kh[3];
+        or_poisson_cdf(or_scattering_rate(la, l, x, v) * dt, F);
+        uint32_t w[4];
+        or_draw(seed, ion, step, (uint32_t)l << 16, w);
+        int cnt = or_poisson_count(or_u53(w[0], w[1]), F);
+        double e[3] = {0.0, 0.0, 0.0};
+        for (int j = 1; j <= cnt; ++j) {
+            or_draw(seed, ion, step, ((uint32_t)l << 16) | (uint32_t)j, w);
+            double ct = 2.0 * or_u53(w[0], w[1]) - 1.0;
+            double ph = 2.0 * OR_PI * or_u53(w[2], w[3]);
+            double st = sqrt(1.0 - ct * ct);
+            e[0] += st * cos(ph);
+            e[1] += st * sin(ph);
+            e[2] += ct;
+        }
+        or_unit(la->beam[l].khat, kh);
+        for (int d = 0; d < 3; ++d) dv[d] += rec * ((double)cnt * kh[d] + e[d]);
+        total += cnt;
+    }
+    return total;
+}
+
 /* Coulomb force by the FMM (fmm.c). */
 int or_fmm_coulomb(int n, const double *pos, double q, int p, int leaf_size, double *F);
 
@@ -303,15 +367,22 @@ int or_step(int n, double *pos, double *vel, double q, double m, const or_trap *
         if (rc) { free(Fc); return rc; }
     }
     double F[17];
-    int laser_on = la && la->mean_per_step > 0.0;
+    int beams = la && la->mode == 2 && la->n_beams > 0;
+    int laser_on = la && !beams && la->mode != 2 && la->mean_per_step > 0.0;
     if (laser_on) or_poisson_cdf(la->mean_per_step, F);
     double recoil = laser_on ? OR_H_PLANCK / (la->wavelength * m) : 0.0;
     for (int i = 0; i < n; ++i) {
-        double fe[3];
+        double fe[3], vmid[3] = {vel[3 * i], vel[3 * i + 1], vel[3 * i + 2]};
         or_external_force(q, m, tr, tm, pos + 3 * i, fe);
         for (int d = 0; d < 3; ++d) vel[3 * i + d] += (fe[d] + Fc[3 * i + d]) * dt / m;
         int cnt = 0;
-        if (laser_on) {
+        if (beams) {
+            /* rates at the midpoint state: positions after the first half
+             * drift, velocities before the kick */
+            double dv[3];
+            cnt = or_beam_kick(la, seed, (uint32_t)i, step, m, dt, pos + 3 * i, vmid, dv);
+            for (int d = 0; d < 3; ++d) vel[3 * i + d] += dv[d];
+        } else if (laser_on) {
             uint32_t w[4];
             or_draw(seed, (uint32_t)i, step, 0u, w);
             cnt = or_poisson_count(or_u53(w[0], w[1]), F);

@@ -25,6 +25,23 @@ H_PLANCK = 6.62607015e-34
 ION_MASS = 9.0 * AMU          # 9Be+ (the paper's species)
 ION_CHARGE = E_CHARGE
 COOLING_WAVELENGTH = 313e-9   # photon recoil h/(lambda m) = 0.1417 m/s
+GAMMA0 = 2.0 * math.pi * 18e6  # natural linewidth of the cooling transition (rad/s)
+
+
+def cooling_beams(w_y: float = 2.48e-6, detuning_perp: float = 2.0 * math.pi * 13.6e6, offset: float = 5e-6,
+                  s_perp: float = 0.5, w_z: float = 1e-3, s_par: float = 5e-3) -> dict:
+    """The cooling set-up of the paper's Sec. 5 and its cooling-setup figure: two
+    counter-propagating axial beams of uniform intensity (detuning -gamma0/2,
+    peak saturation 5e-3) and a planar Gaussian beam along +x, centred at
+    y = offset, z = 0, with waists w_y and w_z (w_z large against the crystal),
+    peak saturation 0.5 and detuning detuning_perp (frequencies quoted in MHz
+    taken as cyclic, omega = 2 pi f)."""
+    return dict(mode=2, wavelength=COOLING_WAVELENGTH, gamma0=GAMMA0, beams=[
+        dict(khat=(0.0, 0.0, 1.0), detuning=-0.5 * GAMMA0, s0=s_par, uniform=1),
+        dict(khat=(0.0, 0.0, -1.0), detuning=-0.5 * GAMMA0, s0=s_par, uniform=1),
+        dict(khat=(1.0, 0.0, 0.0), detuning=detuning_perp, s0=s_perp, waist_y=w_y, waist_z=w_z, offset_y=offset,
+             uniform=0),
+    ])
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -76,6 +93,7 @@ class Crystal:
     omega_r: float = 0.0
     dt: float = 1e-9
     photon_mean: float = 0.0
+    beams: dict | None = None   # beam-mode laser (cooling_beams()); overrides photon_mean
     seed: int = 0
     charge: float = ION_CHARGE
     mass: float = ION_MASS
@@ -88,6 +106,8 @@ class Crystal:
         return dict(B=self.B, omega_z=self.omega_z, delta=self.delta, omega_r=self.omega_r)
 
     def laser(self):
+        if self.beams:
+            return self.beams
         if self.photon_mean <= 0:
             return None
         return dict(mean_per_step=self.photon_mean, wavelength=COOLING_WAVELENGTH)

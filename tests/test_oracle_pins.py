@@ -95,6 +95,84 @@ def test_recoil_direction_isotropic():
     assert np.abs((u ** 2).mean(axis=0) - 1 / 3).max() < 5 * math.sqrt(4 / 45 / m)
 
 
+# ---------------------------------------------------------- beam mode
+def _one_beam(s0, det, khat=(0.0, 0.0, 1.0), **kw):
+    b = dict(khat=khat, detuning=det, s0=s0, uniform=1)
+    b.update(kw)
+    return dict(mode=2, wavelength=inputs.COOLING_WAVELENGTH, gamma0=inputs.GAMMA0, beams=[b])
+
+
+def test_scattering_rate_closed_forms():
+    """eq. (scattering_rate): on resonance (Delta = k.v) the rate is S gamma0 / (1 + 2S);
+    it falls to half at a detuning offset of (gamma0/2) sqrt(1 + 2S) (power broadening);
+    it tends to gamma0/2 at large S; the Doppler term enters as Delta - k.v."""
+    G, k = inputs.GAMMA0, 2 * math.pi / inputs.COOLING_WAVELENGTH
+    x0 = np.zeros(3)
+    for S in (5e-3, 0.5, 3.0):
+        det = -0.5 * G
+        on = O.scattering_rate(_one_beam(S, det), 0, x0, [0.0, 0.0, det / k])
+        assert abs(on / (S * G / (1 + 2 * S)) - 1) < 1e-14
+        half = O.scattering_rate(_one_beam(S, det), 0, x0, [0.0, 0.0, (det - 0.5 * G * math.sqrt(1 + 2 * S)) / k])
+        assert abs(half / (0.5 * S * G / (1 + 2 * S)) - 1) < 1e-12
+    assert abs(O.scattering_rate(_one_beam(1e7, 0.0), 0, x0, x0) / (0.5 * G) - 1) < 1e-6
+    # red detuning: an ion moving against the beam (k.v < 0) scatters more (Doppler cooling)
+    b = _one_beam(0.5, -0.5 * G)
+    assert O.scattering_rate(b, 0, x0, [0.0, 0.0, -3.0]) > 1.5 * O.scattering_rate(b, 0, x0, [0.0, 0.0, 3.0])
+    # the direction is normalised before use
+    assert O.scattering_rate(_one_beam(0.5, -0.5 * G, khat=(0.0, 0.0, 7.0)), 0, x0, [0.0, 0.0, 1.0]) == \
+        O.scattering_rate(b, 0, x0, [0.0, 0.0, 1.0])
+
+
+def test_gaussian_beam_profile():
+    """The planar beam's saturation S = s0 exp(-(y - d)^2/w_y^2 - z^2/w_z^2), read back on
+    resonance from rate = S gamma0 / (1 + 2S), i.e. S = rate / (gamma0 - 2 rate)."""
+    G, k = inputs.GAMMA0, 2 * math.pi / inputs.COOLING_WAVELENGTH
+    las = inputs.cooling_beams()
+    b = las["beams"][2]
+    d, wy, wz, s0 = b["offset_y"], b["waist_y"], b["waist_z"], b["s0"]
+    v = [b["detuning"] / k, 0.0, 0.0]
+    for y, z, ref in [(d, 0.0, s0), (d + wy, 0.0, s0 / math.e), (d, -wz, s0 / math.e),
+                      (d - 2 * wy, 0.5 * wz, s0 * math.exp(-4.25))]:
+        r = O.scattering_rate(las, 2, [3e-6, y, z], v)
+        assert abs(r / (G - 2 * r) / ref - 1) < 1e-12, (y, z)
+    # the uniform axial beams do not depend on position
+    assert O.scattering_rate(las, 0, [1e-4, -2e-4, 3e-4], v) == O.scattering_rate(las, 0, [0.0, 0.0, 0.0], v)
+
+
+def test_beam_kick_statistics():
+    """eq. (laser_kick) in beam mode: per step the count is Poisson with mean gamma dt; each
+    photon adds h/(lambda m) along khat (absorption) and h/(lambda m) in an isotropic
+    direction (emission).  Ions 10 m apart, B = 0 and no trap: velocities change only by
+    the kick, and the laser-off run cancels the (negligible) Coulomb part exactly."""
+    n, dt = 20000, 20e-9
+    G = inputs.GAMMA0
+    pos = np.zeros((n, 3))
+    pos[:, 0] = np.arange(n) * 10.0
+    v0 = np.zeros((n, 3))
+    v0[:, 1] = 0.4  # transverse to the beam: no Doppler shift
+    las = _one_beam(0.5, -0.5 * G, khat=(1.0, 0.0, 0.0))
+    trap = dict(B=0.0, omega_z=0.0)
+    _, v1, ph = O.run(pos, v0, Q, M, trap, dt, 1, seed=9, laser=las, return_photons=True)
+    _, v_off = O.run(pos, v0, Q, M, trap, dt, 1, seed=9)
+    lam = O.scattering_rate(las, 0, pos[0], v0[0]) * dt
+    assert abs(lam - 0.5 * G / 3.0 * dt) < 1e-12 * lam
+    counts = np.bincount(ph, minlength=4)
+    expect = np.array([stats.poisson.pmf(0, lam), stats.poisson.pmf(1, lam), stats.poisson.pmf(2, lam),
+                       stats.poisson.sf(2, lam)]) * n
+    obs = np.array([counts[0], counts[1], counts[2], counts[3:].sum()])
+    assert stats.chisquare(obs, expect).pvalue > 1e-4, (obs, expect)
+    rec = O.H_PLANCK / (inputs.COOLING_WAVELENGTH * M)
+    dv = (v1 - v_off) / rec
+    tot = ph.sum()
+    # absorption along +x; emission averages out (variance 1/3 per photon and axis)
+    assert abs(dv[:, 0].sum() / tot - 1) < 5 / math.sqrt(3 * tot)
+    assert np.abs(dv[:, 1:].sum(0)).max() < 5 * math.sqrt(tot / 3)
+    # the emission part of each ion is a sum of ph unit vectors: E|e|^2 = ph
+    e = dv - ph[:, None] * np.array([1.0, 0.0, 0.0])
+    assert abs((e ** 2).sum() / tot - 1) < 5 * math.sqrt(2.0 / tot)
+    assert np.all(e[ph == 0] == 0) and np.allclose(np.linalg.norm(e[ph == 1], axis=1), 1.0, atol=1e-6)
+
+
 # ---------------------------------------------------------- forces
 def test_two_ion_force():
     """eq. (hamiltonian) pair term: F = k_e q^2 / r^2 along the separation."""
