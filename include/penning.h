@@ -10,8 +10,8 @@
  * the split operator U(t, dt) = U0(dt/2) Ukick(t + dt/2; dt) U0(dt/2) of
  * Sec. 2.2 (eqs. time_ev2, U0, velocity_kick), U0 being the exact gyration in
  * B.  Coulomb forces come from a direct O(N^2) sum or from a 3D Laplace fast
- * multipole method (Sec. 2.3); photon recoils are Poisson-distributed
- * isotropic kicks (eq. laser_kick).
+ * multipole method (Sec. 2.3); photon recoils are Poisson-distributed kicks
+ * (eq. laser_kick), at a fixed mean or from laser beams (eq. scattering_rate).
  *
  * Conventions
  *   - SI units.  Positions in m, velocities in m/s, forces in N, time in s.
@@ -62,16 +62,49 @@ typedef struct {
     double t0_s;
 } pt_trap_params;
 
-/* Photon-recoil model (Sec. 2.2, eq. laser_kick).  mode 0: off.  mode 1:
- * every ion scatters a Poisson number of photons per step with mean
- * mean_per_step (0 <= mean <= 2), each giving a recoil h/(wavelength m) in
- * a uniformly random direction.  Draws come from Philox4x32-10 keyed by the
- * crystal seed, counter (ion id, step, slot): slot 0 decides the count by
- * inversion of the Poisson CDF (capped at 16), slot j >= 1 the j-th direction. */
+/* One laser beam of eq. (scattering_rate).  khat: propagation direction
+ * (any non-zero length; normalised by the library).  detuning: Delta_l in
+ * rad/s.  s0 >= 0: peak saturation parameter.  uniform = 1: the saturation
+ * is s0 everywhere (a beam much wider than the crystal); uniform = 0: the 2D
+ * Gaussian profile of the paper's cooling appendix in lab coordinates,
+ * S = s0 exp(-(y - offset_y)^2 / waist_y^2 - z^2 / waist_z^2) (waists > 0, m),
+ * which describes beams propagating along +-x such as the planar beam. */
+typedef struct {
+    double khat[3];
+    double detuning;
+    double s0;
+    double waist_y, waist_z;
+    double offset_y;
+    int uniform;
+} pt_beam;
+
+#define PT_MAX_BEAMS 4
+
+/* Photon model (Sec. 2.2, eqs. scattering_rate and laser_kick).  Draws come
+ * from Philox4x32-10 keyed by the crystal seed, counter (ion id, step,
+ * slot); a count is the inversion of the Poisson CDF (capped at 16) at the
+ * uniform of its slot.
+ *   mode 0: off.
+ *   mode 1: every ion scatters a Poisson number of photons per step with
+ *     mean mean_per_step (0 <= mean <= 2), each an emission recoil
+ *     h/(wavelength m) in a uniformly random direction; slot 0 decides the
+ *     count, slot j >= 1 the j-th direction.
+ *   mode 2: n_beams (1..PT_MAX_BEAMS) beams with natural linewidth gamma0
+ *     (rad/s).  Per ion, beam l and step, the count has mean gamma_l dt with
+ *     the rate of eq. (scattering_rate) at the midpoint position and the
+ *     velocity before the kick, k_l = (2 pi / wavelength) khat_l; each photon
+ *     adds h/(wavelength m) along khat_l (absorption) and the same in a
+ *     uniformly random direction (emission).  Slot (l << 16) decides beam l's
+ *     count, slot (l << 16) | j its j-th emission.  Requires gamma0 dt <= 4, so
+ *     that no mean exceeds 2 (the largest rate is gamma0 / 2).
+ * PT_EINVAL for other modes or non-finite / out-of-range values. */
 typedef struct {
     int mode;
     double mean_per_step;
     double wavelength_m;
+    double gamma0;
+    int n_beams;
+    pt_beam beam[PT_MAX_BEAMS];
 } pt_laser_params;
 
 /* Coulomb solver.  method 0: direct pairwise sum (FP64).  method 1: FMM with

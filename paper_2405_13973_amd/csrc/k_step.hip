@@ -241,12 +241,67 @@ __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *_
     fx += cd.coul * E[g];
     fy += cd.coul * E[ntot + g];
     fz += cd.coul * E[2 * ntot + g];
+    const double vmx = vx, vmy = vy, vmz = vz;  // midpoint velocity, before the kick (beam rates)
     const double kdt = cd.dt * cd.inv_m;
     vx += fx * kdt;
     vy += fy * kdt;
     vz += fz * kdt;
     int32_t nph = 0;
-    if (cd.laser_on) {
+    if (cd.laser_on == 2) {
+        // beams, eq. (scattering_rate): per beam a Poisson count with mean
+        // rate * dt (slot l << 16), then per photon an absorption recoil
+        // along khat and an isotropic emission recoil (slots (l << 16) | j)
+        const uint32_t k0 = (uint32_t)cd.seed, k1 = (uint32_t)(cd.seed >> 32);
+        const double g2 = 0.25 * cd.gamma0 * cd.gamma0;
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int l = 0; l < cd.n_beams; ++l) {
+            const BeamDev &b = cd.beam[l];
+            double S = b.s0;
+            if (!b.uniform) {
+                const double dy = y - b.offset_y;
+                S = b.s0 * exp(-(dy * dy / (b.waist_y * b.waist_y) + z * z / (b.waist_z * b.waist_z)));
+            }
+            const double kv = cd.kwave * (b.khat[0] * vmx + b.khat[1] * vmy + b.khat[2] * vmz);
+            const double dd = b.detuning - kv;
+            const double lam = S * cd.gamma0 * g2 / (g2 * (1.0 + 2.0 * S) + dd * dd) * cd.dt;
+            uint32_t w[4] = {(uint32_t)i, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)l << 16};
+            philox4x32_10(w, k0, k1);
+            const double u = u53(w[0], w[1]);
+            // inversion of the Poisson CDF p_0 = e^-lam, p_k = p_{k-1} lam / k
+            double pk = exp(-lam), F = pk;
+            int cnt = 16;
+            for (int k = 0; k <= 16; ++k) {
+                if (k > 0) {
+                    pk = pk * lam / (double)k;
+                    F = F + pk;
+                }
+                if (u < F) {
+                    cnt = k;
+                    break;
+                }
+            }
+            double ex = 0.0, ey = 0.0, ez = 0.0;
+            for (int j = 1; j <= cnt; ++j) {
+                uint32_t d[4] = {(uint32_t)i, (uint32_t)step, (uint32_t)(step >> 32), ((uint32_t)l << 16) | (uint32_t)j};
+                philox4x32_10(d, k0, k1);
+                const double ct = 2.0 * u53(d[0], d[1]) - 1.0;
+                const double ph = 2.0 * kPi * u53(d[2], d[3]);
+                const double st = sqrt(1.0 - ct * ct);
+                double sp, cp;
+                sincos(ph, &sp, &cp);
+                ex += st * cp;
+                ey += st * sp;
+                ez += ct;
+            }
+            ax += cd.recoil * ((double)cnt * b.khat[0] + ex);
+            ay += cd.recoil * ((double)cnt * b.khat[1] + ey);
+            az += cd.recoil * ((double)cnt * b.khat[2] + ez);
+            nph += cnt;
+        }
+        vx += ax;
+        vy += ay;
+        vz += az;
+    } else if (cd.laser_on) {
         uint32_t w[4] = {(uint32_t)i, (uint32_t)step, (uint32_t)(step >> 32), 0u};
         const uint32_t k0 = (uint32_t)cd.seed, k1 = (uint32_t)(cd.seed >> 32);
         philox4x32_10(w, k0, k1);

@@ -36,6 +36,18 @@ constexpr double kEps0 = 8.8541878188e-12;
 
 // Everything a batched kernel needs to know about one crystal.  Built on
 // the host each time a batch is formed and copied to the device.
+// One laser beam (eq. scattering_rate): unit direction, detuning (rad/s),
+// peak saturation and profile (uniform, or Gaussian in y and z).
+constexpr int kMaxBeams = 4;
+struct BeamDev {
+    double khat[3];
+    double detuning;
+    double s0;
+    double waist_y, waist_z, offset_y;
+    int32_t uniform;
+    int32_t pad;
+};
+
 struct CrystalDev {
     double *state;        // 6 n doubles, see above
     int32_t *photons;     // n
@@ -51,8 +63,11 @@ struct CrystalDev {
     double coul;            // k_e q^2
     double recoil;          // h / (lambda m), 0 when the laser is off
     double poisson_F[17];   // cumulative Poisson table of the photon mean
-    int32_t laser_on;
-    int32_t pad;
+    int32_t laser_on;       // 1: fixed-mean photons, 2: beams
+    int32_t n_beams;
+    double gamma0;          // natural linewidth (rad/s), beams only
+    double kwave;           // 2 pi / wavelength (1/m)
+    BeamDev beam[kMaxBeams];
     uint64_t seed;
     uint64_t step0;         // step index of the first step of the current call
 };

@@ -315,6 +315,26 @@ static void fill_desc(const pt_crystal *c, int off, CrystalDev &d)
         acc = acc + pk;
         d.poisson_F[k] = acc;
     }
+    const bool beams = c->laser.mode == 2;
+    if (beams) {
+        d.laser_on = 2;
+        d.recoil = kPlanck / (c->laser.wavelength_m * c->m);
+        d.kwave = 2.0 * kPi / c->laser.wavelength_m;
+        d.gamma0 = c->laser.gamma0;
+        d.n_beams = c->laser.n_beams;
+        for (int l = 0; l < c->laser.n_beams; ++l) {
+            const pt_beam &b = c->laser.beam[l];
+            BeamDev &e = d.beam[l];
+            const double r = std::sqrt(b.khat[0] * b.khat[0] + b.khat[1] * b.khat[1] + b.khat[2] * b.khat[2]);
+            for (int k = 0; k < 3; ++k) e.khat[k] = b.khat[k] / r;
+            e.detuning = b.detuning;
+            e.s0 = b.s0;
+            e.waist_y = b.waist_y;
+            e.waist_z = b.waist_z;
+            e.offset_y = b.offset_y;
+            e.uniform = b.uniform ? 1 : 0;
+        }
+    }
     d.seed = c->seed;
     d.step0 = (uint64_t)c->step;
 }
@@ -851,10 +871,16 @@ pt_status pt_destroy_crystal(pt_crystal *c)
     return PT_OK;
 }
 
+// Beam mode: gamma0 dt <= 4 keeps every per-step photon mean <= 2 (the
+// largest rate of eq. scattering_rate is gamma0 / 2, reached at S -> inf).
+static bool beams_fit_step(const pt_laser_params &l, double dt) { return l.mode != 2 || l.gamma0 * dt <= 4.0; }
+
 pt_status pt_set_trap_params(pt_crystal *c, const pt_trap_params *p)
 {
     PT_REQUIRE(c, "crystal is NULL");
     PT_TRY(check_trap(c, p));
+    PT_REQUIRE(beams_fit_step(c->laser, p->dt_s), "gamma0 dt = %g exceeds 4 with the crystal's laser beams",
+               c->laser.gamma0 * p->dt_s);
     c->trap = *p;
     return PT_OK;
 }
@@ -862,11 +888,26 @@ pt_status pt_set_trap_params(pt_crystal *c, const pt_trap_params *p)
 pt_status pt_set_laser_params(pt_crystal *c, const pt_laser_params *p)
 {
     PT_REQUIRE(c && p, "NULL argument");
-    PT_REQUIRE(p->mode == 0 || p->mode == 1, "laser mode must be 0 or 1");
+    PT_REQUIRE(p->mode >= 0 && p->mode <= 2, "laser mode must be 0, 1 or 2");
     if (p->mode == 1) {
         PT_REQUIRE(std::isfinite(p->mean_per_step) && p->mean_per_step >= 0.0 && p->mean_per_step <= 2.0,
                    "photon mean must be in [0, 2]");
         PT_REQUIRE(std::isfinite(p->wavelength_m) && p->wavelength_m > 0.0, "wavelength must be > 0");
+    }
+    if (p->mode == 2) {
+        PT_REQUIRE(std::isfinite(p->wavelength_m) && p->wavelength_m > 0.0, "wavelength must be > 0");
+        PT_REQUIRE(std::isfinite(p->gamma0) && p->gamma0 > 0.0, "gamma0 must be > 0");
+        PT_REQUIRE(p->n_beams >= 1 && p->n_beams <= PT_MAX_BEAMS, "n_beams must be in [1, %d]", PT_MAX_BEAMS);
+        for (int l = 0; l < p->n_beams; ++l) {
+            const pt_beam &b = p->beam[l];
+            const double v[7] = {b.khat[0], b.khat[1], b.khat[2], b.detuning, b.s0, b.waist_y, b.offset_y};
+            PT_REQUIRE(finite_all(v, 7) && std::isfinite(b.waist_z), "beam %d: non-finite parameter", l);
+            PT_REQUIRE(b.khat[0] != 0.0 || b.khat[1] != 0.0 || b.khat[2] != 0.0, "beam %d: khat is zero", l);
+            PT_REQUIRE(b.s0 >= 0.0, "beam %d: s0 must be >= 0", l);
+            PT_REQUIRE(b.uniform || (b.waist_y > 0.0 && b.waist_z > 0.0), "beam %d: waists must be > 0", l);
+        }
+        PT_REQUIRE(beams_fit_step(*p, c->trap.dt_s), "gamma0 dt = %g exceeds 4 (photon means above 2 per step)",
+                   p->gamma0 * c->trap.dt_s);
     }
     c->laser = *p;
     return PT_OK;

@@ -31,8 +31,17 @@ class TrapParams(C.Structure):
                 ("dt_s", C.c_double), ("t0_s", C.c_double)]
 
 
+class Beam(C.Structure):
+    _fields_ = [("khat", C.c_double * 3), ("detuning", C.c_double), ("s0", C.c_double), ("waist_y", C.c_double),
+                ("waist_z", C.c_double), ("offset_y", C.c_double), ("uniform", C.c_int)]
+
+
+MAX_BEAMS = 4
+
+
 class LaserParams(C.Structure):
-    _fields_ = [("mode", C.c_int), ("mean_per_step", C.c_double), ("wavelength_m", C.c_double)]
+    _fields_ = [("mode", C.c_int), ("mean_per_step", C.c_double), ("wavelength_m", C.c_double),
+                ("gamma0", C.c_double), ("n_beams", C.c_int), ("beam", Beam * MAX_BEAMS)]
 
 
 class ForceParams(C.Structure):
@@ -188,6 +197,17 @@ class Crystal:
     def set_laser(self, mean_per_step=0.0, wavelength=313e-9, mode=None):
         mode = (1 if mean_per_step > 0 else 0) if mode is None else mode
         p = LaserParams(mode, mean_per_step, wavelength)
+        _check(load().pt_set_laser_params(self.h, C.byref(p)))
+        return self
+
+    def set_beams(self, laser: dict):
+        """Beam mode from {wavelength, gamma0, beams: [{khat, detuning, s0, waist_y,
+        waist_z, offset_y, uniform}, ...]}."""
+        p = LaserParams(2, 0.0, laser["wavelength"], laser["gamma0"], len(laser["beams"]))
+        for l, b in enumerate(laser["beams"]):
+            p.beam[l] = Beam((C.c_double * 3)(*[float(x) for x in b["khat"]]), b["detuning"], b["s0"],
+                             b.get("waist_y", 1.0), b.get("waist_z", 1.0), b.get("offset_y", 0.0),
+                             int(b.get("uniform", 0)))
         _check(load().pt_set_laser_params(self.h, C.byref(p)))
         return self
 
