@@ -171,6 +171,33 @@ def bench_potential(ctx, c, cr, p, leaf, prec, evals=10):
     return out
 
 
+# HBM bytes per ion of the kick + half-drift kernel: state read and written
+# (6 FP64 each), the field read (3 FP64), the photon count written (int32)
+KICK_BYTES_PER_ION = 48 + 48 + 24 + 4
+
+
+def bench_beams(ctx, c, cr, p, leaf, prec, steps, warmup, sync, ref_seconds):
+    """The same steps with the beam-mode laser of eq. (scattering_rate) on (the
+    cooling set-up of the paper's Sec. 5: two uniform axial beams and the offset
+    planar Gaussian beam), timed like the main steps."""
+    c.set_state(cr.pos, cr.vel, 0)
+    c.set_force("fmm", p, leaf, prec)
+    c.set_beams(inputs.cooling_beams())
+    # photons of the first step: the benchmark crystal starts far from equilibrium,
+    # and within a few steps the trap accelerates its outer ions to speeds whose
+    # Doppler shift detunes every beam
+    c.step(1)
+    photons = int(c.read_state()["photons"].sum())
+    el = timed_steps(ctx, c, steps, warmup, sync)[0]
+    c.set_laser(0.0)
+    log(f"  beams: {steps} steps in {el * 1e3:.2f} ms ({photons} photons in the first step)")
+    return {"ms_per_step": el * 1e3 / steps, "ion_steps_per_s": cr.n * steps / el,
+            "time_vs_no_laser": el / ref_seconds, "photons_first_step": photons,
+            "kick_bytes_per_ion": KICK_BYTES_PER_ION,
+            "setup": "two uniform axial beams (Delta=-gamma0/2, S0=5e-3) and a planar Gaussian beam along +x "
+                     "(d=5 um, w_y=2.48 um, w_z=1 mm, S0=0.5, Delta=2 pi 13.6 MHz), gamma0=2 pi 18 MHz"}
+
+
 BATCH_LEAVES = (64, 128, 256)
 
 
@@ -309,6 +336,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-potential", action="store_true", help="skip the Coulomb-potential measurement")
+    ap.add_argument("--no-beams", action="store_true", help="skip the beam-mode laser measurement")
     ap.add_argument("--workload", choices=["config3", "ensemble", "serving"], default="config3",
                     help="config3: 1e5-ion crystal (default); ensemble: 256 crystals batched; serving: request stream")
     ap.add_argument("--p", type=int, default=0,
@@ -458,6 +486,8 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cr, p, leaf, F_dir)
         out["details"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    if not a.no_beams:
+        out["beams"] = bench_beams(ctx, c, cr, p, leaf, a.precision, a.steps, a.warmup, sync, main_r["seconds"])
     if not a.no_potential:
         out["potential"] = bench_potential(ctx, c, cr, p, leaf, a.precision)
         if "cpu_baseline" in out:

@@ -214,7 +214,10 @@ __global__ void k_keys(const CrystalDev *__restrict__ cs, const int32_t *__restr
 }
 
 // Kick at the midpoint time and the second half drift.  E holds the Coulomb
-// field per unit charge (sum_j (x_i - x_j)/r^3) in batch order, SoA.
+// field per unit charge (sum_j (x_i - x_j)/r^3) in batch order, SoA.  BEAMS:
+// some crystal of the batch uses the beam-mode laser (the variant that holds
+// the per-beam rate and count code).
+template <bool BEAMS>
 __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
                              int kstep, const double *__restrict__ E)
 {
@@ -247,7 +250,7 @@ __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *_
     vy += fy * kdt;
     vz += fz * kdt;
     int32_t nph = 0;
-    if (cd.laser_on == 2) {
+    if (BEAMS && cd.laser_on == 2) {
         // beams, eq. (scattering_rate): per beam a Poisson count with mean
         // rate * dt (slot l << 16), then per photon an absorption recoil
         // along khat and an isotropic emission recoil (slots (l << 16) | j)
@@ -458,9 +461,11 @@ void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCub
 }
 
 void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
-                       hipStream_t st)
+                       bool beams, hipStream_t st)
 {
-    if (ntot > 0) k_kick_drift<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E);
+    if (ntot <= 0) return;
+    if (beams) k_kick_drift<true><<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E);
+    else k_kick_drift<false><<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E);
 }
 
 int direct_targets_per_block() { return kDirTB * kDirT; }

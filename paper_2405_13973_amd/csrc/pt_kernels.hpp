@@ -37,8 +37,9 @@ void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int nto
 void launch_root(unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st);
 void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCube *roots, int ntot, uint64_t *keys,
                  uint32_t *vals, hipStream_t st);
+// beams: some crystal of the batch uses the beam-mode laser
 void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
-                       hipStream_t st);
+                       bool beams, hipStream_t st);
 int direct_targets_per_block();
 // Direct field into E (3 x ntot); with phi non-null also the potential per
 // unit charge sum_{j != i} 1/r_ij into phi (ntot).

@@ -277,6 +277,7 @@ struct Batch {
     int32_t *ion_crystal = nullptr;
     int32_t *blk_crystal = nullptr, *blk_first = nullptr;
     int nblk_direct = 0;
+    bool beams = false;  // some crystal uses the beam-mode laser
 };
 
 static void fill_desc(const pt_crystal *c, int off, CrystalDev &d)
@@ -364,6 +365,8 @@ static pt_status form_batch(pt_ctx *ctx, const std::vector<pt_crystal *> &cs, Ba
         PT_HIP(hipStreamSynchronize(ctx->stream));  // staging buffer may still be read by a copy
     }
     for (int i = 0; i < nc; ++i) fill_desc(cs[i], b.off[i], ctx->h_desc[i]);
+    b.beams = false;
+    for (int i = 0; i < nc; ++i) b.beams = b.beams || cs[i]->laser.mode == 2;
     PT_HIP(hipMemcpyAsync(b.d_desc, ctx->h_desc, sizeof(CrystalDev) * nc, hipMemcpyHostToDevice, ctx->stream));
     launch_ion_crystal(b.d_desc, nc, b.ntot, b.ion_crystal, ctx->stream);
     // bounding boxes start empty; the root-cube kernel empties them again after each use
@@ -1070,7 +1073,7 @@ pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_
         launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, nc, 1, bbox, ctx->stream);
         PT_TRY(eval_field(ctx, b, cs[0]->force, E));
         // step index = descriptor step0 (set when the batch formed) + kstep
-        launch_kick_drift(b.d_desc, b.ion_crystal, b.ntot, (int)(k - group_start), E, ctx->stream);
+        launch_kick_drift(b.d_desc, b.ion_crystal, b.ntot, (int)(k - group_start), E, b.beams, ctx->stream);
     }
     for (int i = 0; i < n_crystals; ++i) cs[i]->step += n_steps[i];
     PT_HIP(hipGetLastError());
