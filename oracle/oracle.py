@@ -110,6 +110,8 @@ def lib():
             L.or_coulomb_direct.argtypes = [C.c_int, _d, C.c_double, _d]
             L.or_coulomb_direct_sampled.argtypes = [C.c_int, _d, C.c_double, C.c_int, _i32, _d]
             L.or_coulomb_energy.argtypes = [C.c_int, _d, C.c_double]
+            L.or_rotating_frame.argtypes = [C.c_int, _d, _d, C.c_double, C.c_double, _d, _d]
+            L.or_rotating_energy.argtypes = [C.c_int, _d, _d, C.c_double, C.c_double, C.POINTER(Trap), C.c_double, _d]
             L.or_scattering_rate.argtypes = [C.POINTER(Laser), C.c_int, _d, _d]
             L.or_scattering_rate.restype = C.c_double
             L.or_coulomb_potential_direct.argtypes = [C.c_int, _d, C.c_double, _d]
@@ -216,6 +218,23 @@ def energy(pos, vel, q, m, trap: dict):
     pos, vel = _pos(pos), _pos(vel)
     tr = Trap(trap["B"], trap["omega_z"], 0.0, 0.0)
     return lib().or_energy(len(pos), pos, vel, float(q), float(m), C.byref(tr))
+
+
+def rotating_frame(pos, vel, omega_r, t):
+    """Positions and velocities in the frame of eq. (rotation) at time t."""
+    pos, vel = _pos(pos), _pos(vel)
+    xr, vr = np.zeros_like(pos), np.zeros_like(vel)
+    lib().or_rotating_frame(len(pos), pos, vel, float(omega_r), float(t), xr, vr)
+    return xr, vr
+
+
+def rotating_energy(pos, vel, q, m, trap: dict, t):
+    """Rotating-frame energy terms (J): axial KE, planar KE, external, Coulomb, total."""
+    pos, vel = _pos(pos), _pos(vel)
+    tr = Trap(trap["B"], trap["omega_z"], trap.get("delta", 0.0), trap.get("omega_r", 0.0))
+    out = np.zeros(5)
+    lib().or_rotating_energy(len(pos), pos, vel, float(q), float(m), C.byref(tr), float(t), out)
+    return out
 
 
 def fmm_coulomb(pos, q, p, leaf_size):

@@ -255,6 +255,68 @@ double or_energy(int n, const double *pos, const double *vel, double q, double m
 }
 
 /* ---------------------------------------------------------------------
+ * Rotating frame, eq. (rotation): positions turned about z by the angle
+ * omega_r t, (x_r, y_r) = (x cos - y sin, x sin + y cos); velocities are the
+ * time derivatives of the rotated positions, v_r = R v + omega_r (-y_r, x_r, 0).
+ * A crystal turning clockwise (seen from +z) at omega_r -- the sense of the
+ * rotating wall cos(2(varphi + omega_r t)) -- is at rest in this frame.
+ * ------------------------------------------------------------------- */
+void or_rotating_frame(int n, const double *pos, const double *vel, double omega_r, double t, double *pos_r,
+                       double *vel_r)
+{
+    double c = cos(omega_r * t), s = sin(omega_r * t);
+    for (int i = 0; i < n; ++i) {
+        const double *x = pos + 3 * i, *v = vel + 3 * i;
+        double xr = c * x[0] - s * x[1], yr = s * x[0] + c * x[1];
+        pos_r[3 * i] = xr;
+        pos_r[3 * i + 1] = yr;
+        pos_r[3 * i + 2] = x[2];
+        vel_r[3 * i] = c * v[0] - s * v[1] - omega_r * yr;
+        vel_r[3 * i + 1] = s * v[0] + c * v[1] + omega_r * xr;
+        vel_r[3 * i + 2] = v[2];
+    }
+}
+
+/* Rotating-frame energy at time t, eq. (pe_rot) (its first line, which follows
+ * from eqs. pot_trap and pot_wall; see below) plus the kinetic energy of the
+ * rotating-frame velocities:
+ *   out[0] = sum m vz_r^2 / 2                                  axial kinetic
+ *   out[1] = sum m (vx_r^2 + vy_r^2) / 2                        planar kinetic
+ *   out[2] = sum [ m wz^2 z_r^2 / 2 - m (wr^2 - wc wr + wz^2/2)(x_r^2 + y_r^2) / 2
+ *                  + q k_z delta (x_r^2 - y_r^2) / 4 ]           external terms
+ *   out[3] = k_e q^2 sum_{i<j} 1/r_ij                           Coulomb
+ *   out[4] = the total.
+ * With k_z = m wz^2 / q and wc = q B / m.  The printed C_x, C_y form of the
+ * same equation carries the wall term as -m wz^2 delta (x_r^2 - y_r^2)/2, a
+ * factor -2 away; the rotating wall of eq. (pot_wall) seen in this frame is
+ * q k_z delta (x_r^2 - y_r^2) / 4, the term used here. */
+void or_rotating_energy(int n, const double *pos, const double *vel, double q, double m, const or_trap *tr, double t,
+                        double out[5])
+{
+    double wz = tr->omega_z, wr = tr->omega_r, wc = q * tr->B / m;
+    double kz = m * wz * wz / q;
+    double *xr = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double *vr = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    or_rotating_frame(n, pos, vel, wr, t, xr, vr);
+    double ka = 0.0, kp = 0.0, pe = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double *x = xr + 3 * i, *v = vr + 3 * i;
+        double rho2 = x[0] * x[0] + x[1] * x[1];
+        ka += 0.5 * m * v[2] * v[2];
+        kp += 0.5 * m * (v[0] * v[0] + v[1] * v[1]);
+        pe += 0.5 * m * wz * wz * x[2] * x[2] - 0.5 * m * (wr * wr - wc * wr + 0.5 * wz * wz) * rho2 +
+              0.25 * q * kz * tr->delta * (x[0] * x[0] - x[1] * x[1]);
+    }
+    out[0] = ka;
+    out[1] = kp;
+    out[2] = pe;
+    out[3] = or_coulomb_energy(n, xr, q);
+    out[4] = ka + kp + pe + out[3];
+    free(xr);
+    free(vr);
+}
+
+/* ---------------------------------------------------------------------
  * U0(tau), eq. (U0): exact motion of a charge in the uniform field B z-hat
  * with no electric field.  m dv/dt = q v x B gives dvx/dt = wc vy,
  * dvy/dt = -wc vx (wc = qB/m), i.e. clockwise gyration for q B > 0; the

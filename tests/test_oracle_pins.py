@@ -699,3 +699,99 @@ def test_energy_conservation_second_order():
         devs.append(d)
     assert devs[0] < 1e-3, devs
     assert 2.8 < devs[0] / devs[1] < 5.5, devs
+
+
+# ---------------------------------------------------------- rotating frame
+def _rigid(pos, wr):
+    """Velocity of a rigid clockwise rotation at wr about z (the sense of the wall)."""
+    return wr * np.stack([pos[:, 1], -pos[:, 0], np.zeros(len(pos))], 1)
+
+
+def test_rotating_frame_transform():
+    """eq. (rotation): a crystal turning clockwise at omega_r is at rest in the frame;
+    the turn is orthogonal and leaves z alone."""
+    g = inputs.rng(31)
+    x0 = inputs.uniform_ball(200, 1e-4, g)
+    wr, t = 2 * math.pi * 180e3, 3.7e-6
+    c, s_ = math.cos(wr * t), math.sin(wr * t)
+    # positions at time t of the clockwise rigid motion started at x0
+    x = np.stack([c * x0[:, 0] + s_ * x0[:, 1], -s_ * x0[:, 0] + c * x0[:, 1], x0[:, 2]], 1)
+    vz = g.normal(size=200)
+    v = _rigid(x, wr)
+    v[:, 2] = vz
+    xr, vr = O.rotating_frame(x, v, wr, t)
+    np.testing.assert_allclose(xr, x0, atol=1e-18)
+    assert np.abs(vr[:, :2]).max() < 1e-12 * wr * 1e-4
+    np.testing.assert_array_equal(vr[:, 2], vz)
+    np.testing.assert_allclose(np.linalg.norm(xr, axis=1), np.linalg.norm(x, axis=1), rtol=1e-15)
+
+
+def test_rotating_frame_temperatures():
+    """eqs. (temp_ax), (temp_pl): a thermal crystal at T that also turns rigidly at
+    omega_r has T_par = m sum vz^2 / (N kb) and T_perp = m sum (vx^2 + vy^2) / (2 N kb)
+    equal to T in the rotating frame (chi-square spreads sqrt(2/N), sqrt(1/N))."""
+    n, T = 20000, 10e-3
+    g = inputs.rng(32)
+    pos = inputs.uniform_ball(n, 1e-4, g)
+    wr = 2 * math.pi * 180e3
+    vel = inputs.thermal_velocities(n, T, M, g) + _rigid(pos, wr)
+    e = O.rotating_energy(pos, vel, Q, M, dict(B=4.5, omega_z=2 * math.pi * 1.5e6, omega_r=wr), 1.234e-6)
+    kb = inputs.K_BOLTZ
+    t_ax, t_pl = 2 * e[0] / (n * kb), e[1] / (n * kb)
+    assert abs(t_ax / T - 1) < 5 * math.sqrt(2 / n)
+    assert abs(t_pl / T - 1) < 5 * math.sqrt(1 / n)
+
+
+def test_rotating_energy_without_wall_is_the_beta_form():
+    """eq. (pe_rot) with delta = 0: the external terms equal (1/2) m wz^2 [beta (x_r^2 + y_r^2) + z_r^2]
+    with beta of eq. (beta), and the Coulomb term is the pair sum."""
+    g = inputs.rng(33)
+    pos = inputs.uniform_ball(300, 1e-4, g)
+    vel = g.normal(size=(300, 3))
+    B, wz, wr, t = 4.5, 2 * math.pi * 1.5e6, 2 * math.pi * 180e3, 2e-6
+    e = O.rotating_energy(pos, vel, Q, M, dict(B=B, omega_z=wz, omega_r=wr), t)
+    xr, vr = O.rotating_frame(pos, vel, wr, t)
+    wc = Q * B / M
+    beta = wr * (wc - wr) / wz ** 2 - 0.5
+    ext = 0.5 * M * wz ** 2 * (beta * (xr[:, 0] ** 2 + xr[:, 1] ** 2) + xr[:, 2] ** 2).sum()
+    assert abs(e[2] / ext - 1) < 1e-12
+    assert abs(e[3] / O.coulomb_energy(pos, Q) - 1) < 1e-12
+    assert abs(e[0] - 0.5 * M * (vr[:, 2] ** 2).sum()) <= 1e-12 * e[0]
+    assert abs(e[4] - e[:4].sum()) <= 1e-15 * abs(e[4])
+
+
+def test_rotating_energy_conserved_with_the_wall():
+    """With the rotating wall on, the lab-frame Hamiltonian depends on time but the
+    rotating-frame energy (the quantity of eq. rms_en) is conserved, its error
+    shrinking like dt^2.  This also fixes the wall term of eq. (pe_rot): the C_x, C_y
+    form's -m wz^2 delta (x_r^2 - y_r^2)/2 in place of q k_z delta (x_r^2 - y_r^2)/4 is
+    not conserved."""
+    B, wz, wr, delta = 4.5, 2 * math.pi * 1.0e6, 2 * math.pi * 180e3, 0.01
+    g = np.arange(-2, 2) * 8e-6
+    X, Y, Z = np.meshgrid(g, g, g[1:3], indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1) + 1e-7
+    vel = inputs.thermal_velocities(len(pos), 10e-3, M, inputs.rng(9)) + _rigid(pos, wr)
+    trap = dict(B=B, omega_z=wz, delta=delta, omega_r=wr)
+    kz = M * wz * wz / Q
+
+    def alt(x, v, t):  # the C_x, C_y form's wall term instead
+        xr, _ = O.rotating_frame(x, v, wr, t)
+        d2 = (xr[:, 0] ** 2 - xr[:, 1] ** 2).sum()
+        return O.rotating_energy(x, v, Q, M, trap, t)[4] - 0.25 * Q * kz * delta * d2 - 0.5 * M * wz ** 2 * delta * d2
+
+    devs, alts = [], []
+    for dt, nst in ((4e-9, 500), (2e-9, 1000)):
+        x, v = pos, vel
+        E0, A0 = O.rotating_energy(x, v, Q, M, trap, 0.0)[4], alt(x, v, 0.0)
+        d = da = 0.0
+        for k in range(10):
+            x, v = O.run(x, v, Q, M, trap, dt, nst // 10, step0=k * nst // 10)
+            t = (k + 1) * (nst // 10) * dt
+            d = max(d, abs(O.rotating_energy(x, v, Q, M, trap, t)[4] - E0) / abs(E0))
+            da = max(da, abs(alt(x, v, t) - A0) / abs(A0))
+        devs.append(d)
+        alts.append(da)
+    assert devs[0] < 3e-4, devs
+    assert 2.8 < devs[0] / devs[1] < 5.5, devs
+    assert alts[1] > 5 * devs[1], (alts, devs)
+
