@@ -174,6 +174,40 @@ pt_status pt_compute_potential_batch(pt_crystal *const *cs, int n_crystals, doub
 pt_status pt_coulomb_energy(pt_crystal *c, double *U_out);
 pt_status pt_coulomb_energy_batch(pt_crystal *const *cs, int n_crystals, double *U_out);
 
+/* Rotating-frame diagnostics (eqs. rotation, pe_rot, temp_ax, temp_pl) of the
+ * current state at its time t = t0 + step dt.  The frame turns about z by
+ * omega_r t (a crystal turning clockwise at omega_r, the sense of the rotating
+ * wall, is at rest in it); velocities are the time derivatives of the turned
+ * positions.  Energies in J, temperatures in K:
+ *   ke_axial = sum m vz_r^2 / 2, ke_planar = sum m (vx_r^2 + vy_r^2) / 2,
+ *   pe_external = sum [m wz^2 z_r^2 / 2 - m (wr^2 - wc wr + wz^2/2)(x_r^2 + y_r^2) / 2
+ *                      + q k_z delta (x_r^2 - y_r^2) / 4]   (wc = qB/m, k_z = m wz^2 / q),
+ *   pe_coulomb = (1/2) q sum phi_i by the crystal's force method (pt_coulomb_energy),
+ *   energy = the sum of the four: the rotating-frame energy that eq. (rms_en)
+ *     compares, conserved by the dynamics also with the rotating wall on,
+ *   temp_axial = m sum vz_r^2 / (N k_b), temp_planar = m sum (vx_r^2 + vy_r^2) / (2 N k_b):
+ *     the instantaneous terms of eqs. (temp_ax) and (temp_pl), whose time averages
+ *     those equations take; eq. (temp_pe) is (2/3)(pe_external + pe_coulomb - PE_0)/(N k_b)
+ *     for a reference configuration's energy PE_0 computed the same way.
+ * The sums over ions run on the device in a fixed order (FP64).  The wall
+ * term follows eq. (pot_wall) seen in the rotating frame (the printed C_x,
+ * C_y form of eq. pe_rot carries a different factor). */
+typedef struct {
+    double t;
+    double ke_axial;
+    double ke_planar;
+    double pe_external;
+    double pe_coulomb;
+    double energy;
+    double temp_axial;
+    double temp_planar;
+} pt_diagnostics;
+pt_status pt_rotating_diagnostics(pt_crystal *c, pt_diagnostics *out);
+pt_status pt_rotating_diagnostics_batch(pt_crystal *const *cs, int n_crystals, pt_diagnostics *out);
+/* Positions and velocities of the current state in the rotating frame (host,
+ * n x 3 each, ion-id order; either may be NULL). */
+pt_status pt_read_rotating_state(pt_crystal *c, double *pos_r, double *vel_r);
+
 /* Advance n_steps >= 0 steps (eq. time_ev2 with eq. velocity_kick). */
 pt_status pt_step(pt_crystal *c, int64_t n_steps);
 /* Advance crystal k by n_steps[k] steps; crystals still stepping are

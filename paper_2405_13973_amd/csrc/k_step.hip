@@ -503,4 +503,80 @@ void launch_phi_sum(const CrystalDev *cs, int nc, const double *phi, double *out
     if (nc > 0) k_phi_sum<<<nc, kSumTB, 0, st>>>(cs, phi, out);
 }
 
+// Rotating frame (eq. rotation) at the state's time t = t0 + step dt: the
+// position turned about z by omega_r t, the velocity the time derivative of
+// the turned position, v_r = R v + omega_r (-y_r, x_r, 0).
+__device__ inline void to_rotating(const CrystalDev &cd, int i, double xr[3], double vr[3])
+{
+    const int n = cd.n;
+    const double *s = cd.state;
+    const double t = cd.t0 + (double)cd.step0 * cd.dt;
+    double sn, cs_;
+    sincos(cd.omega_r * t, &sn, &cs_);
+    const double x = s[i], y = s[n + i], vx = s[3 * n + i], vy = s[4 * n + i];
+    xr[0] = cs_ * x - sn * y;
+    xr[1] = sn * x + cs_ * y;
+    xr[2] = s[2 * n + i];
+    vr[0] = cs_ * vx - sn * vy - cd.omega_r * xr[1];
+    vr[1] = sn * vx + cs_ * vy + cd.omega_r * xr[0];
+    vr[2] = s[5 * n + i];
+}
+
+// Per crystal (one workgroup each): the axial and planar kinetic energies of
+// the rotating-frame velocities and the external terms of eq. (pe_rot),
+//   m wz^2 z_r^2 / 2 - m (wr^2 - wc wr + wz^2 / 2)(x_r^2 + y_r^2) / 2 + q k_z delta (x_r^2 - y_r^2) / 4,
+// with m wz^2 = q k_z; strided per-thread sums in index order, then a fixed
+// pairwise tree (independent of the batch).
+__global__ __launch_bounds__(kSumTB) void k_rot_sums(const CrystalDev *__restrict__ cs, double *__restrict__ out)
+{
+    __shared__ double part[3][kSumTB];
+    const CrystalDev &cd = cs[blockIdx.x];
+    const double wr = cd.omega_r, wz2 = cd.qkz / cd.mass;
+    const double radial = 0.5 * cd.mass * (wr * wr - cd.wc * wr + 0.5 * wz2);
+    double ka = 0.0, kp = 0.0, pe = 0.0;
+    for (int i = threadIdx.x; i < cd.n; i += kSumTB) {
+        double xr[3], vr[3];
+        to_rotating(cd, i, xr, vr);
+        ka += 0.5 * cd.mass * vr[2] * vr[2];
+        kp += 0.5 * cd.mass * (vr[0] * vr[0] + vr[1] * vr[1]);
+        pe += 0.5 * cd.qkz * xr[2] * xr[2] - radial * (xr[0] * xr[0] + xr[1] * xr[1]) +
+              0.25 * cd.qkz * cd.delta * (xr[0] * xr[0] - xr[1] * xr[1]);
+    }
+    part[0][threadIdx.x] = ka;
+    part[1][threadIdx.x] = kp;
+    part[2][threadIdx.x] = pe;
+    __syncthreads();
+    for (int h = kSumTB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 3; ++k) part[k][threadIdx.x] += part[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[3 * blockIdx.x + threadIdx.x] = part[threadIdx.x][0];
+}
+
+// Rotating-frame positions and velocities of every ion, SoA (6 x ntot, batch order).
+__global__ void k_rot_state(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
+                            double *__restrict__ out)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ntot) return;
+    const CrystalDev &cd = cs[ion_crystal[g]];
+    double xr[3], vr[3];
+    to_rotating(cd, g - cd.ion_off, xr, vr);
+    for (int k = 0; k < 3; ++k) {
+        out[(size_t)k * ntot + g] = xr[k];
+        out[(size_t)(3 + k) * ntot + g] = vr[k];
+    }
+}
+
+void launch_rot_sums(const CrystalDev *cs, int nc, double *out, hipStream_t st)
+{
+    if (nc > 0) k_rot_sums<<<nc, kSumTB, 0, st>>>(cs, out);
+}
+
+void launch_rot_state(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, double *out, hipStream_t st)
+{
+    if (ntot > 0) k_rot_state<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, out);
+}
+
 }  // namespace pt

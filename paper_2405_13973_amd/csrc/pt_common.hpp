@@ -33,6 +33,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kECharge = 1.602176634e-19;
 constexpr double kPlanck = 6.62607015e-34;
 constexpr double kEps0 = 8.8541878188e-12;
+constexpr double kBoltzmann = 1.380649e-23;
 
 // Everything a batched kernel needs to know about one crystal.  Built on
 // the host each time a batch is formed and copied to the device.
@@ -60,6 +61,8 @@ struct CrystalDev {
     double qkz;             // q k_z = m omega_z^2
     double delta, omega_r;
     double inv_m;
+    double mass;            // m (rotating-frame diagnostics)
+    double wc;              // omega_c = q B / m
     double coul;            // k_e q^2
     double recoil;          // h / (lambda m), 0 when the laser is off
     double poisson_F[17];   // cumulative Poisson table of the photon mean

@@ -304,6 +304,8 @@ static void fill_desc(const pt_crystal *c, int off, CrystalDev &d)
     d.delta = c->trap.delta;
     d.omega_r = c->trap.omega_r;
     d.inv_m = 1.0 / c->m;
+    d.mass = c->m;
+    d.wc = wc;
     d.coul = c->q * c->q / (4.0 * kPi * kEps0);
     const bool on = c->laser.mode == 1 && c->laser.mean_per_step > 0.0;
     d.laser_on = on ? 1 : 0;
@@ -955,10 +957,16 @@ static pt_status check_batch(pt_crystal *const *cs, int nc)
 }
 
 // One Coulomb evaluation of a batch at its current positions: forces (F_out),
-// potentials (phi_out) and / or Coulomb energies (U_out), each optional.
+// potentials (phi_out), Coulomb energies (U_out) and / or rotating-frame
+// diagnostics (diag), each optional.
 static pt_status evaluate_batch(pt_crystal *const *cs, int n_crystals, double *const *F_out, double *const *phi_out,
-                                double *U_out)
+                                double *U_out, pt_diagnostics *diag = nullptr)
 {
+    std::vector<double> U_diag;
+    if (diag && !U_out) {
+        U_diag.resize((size_t)n_crystals);
+        U_out = U_diag.data();
+    }
     pt_ctx *ctx = cs[0]->ctx;
     PT_HIP(hipSetDevice(ctx->device));
     Batch b;
@@ -985,6 +993,14 @@ static pt_status evaluate_batch(pt_crystal *const *cs, int n_crystals, double *c
         hu.resize((size_t)n_crystals);
         PT_HIP(hipMemcpyAsync(hu.data(), usum, sizeof(double) * n_crystals, hipMemcpyDeviceToHost, ctx->stream));
     }
+    std::vector<double> hr;
+    if (diag) {
+        double *rsum;
+        PT_TRY(ws_get(ctx, "rot_sum", sizeof(double) * 3 * (size_t)n_crystals, &rsum));
+        launch_rot_sums(b.d_desc, n_crystals, rsum, ctx->stream);
+        hr.resize(3 * (size_t)n_crystals);
+        PT_HIP(hipMemcpyAsync(hr.data(), rsum, sizeof(double) * 3 * n_crystals, hipMemcpyDeviceToHost, ctx->stream));
+    }
     PT_HIP(hipStreamSynchronize(ctx->stream));
     PT_TRY(finish_timing(ctx));
     for (int c = 0; c < n_crystals; ++c) {
@@ -996,6 +1012,18 @@ static pt_status evaluate_batch(pt_crystal *const *cs, int n_crystals, double *c
         if (phi_out)
             for (int64_t i = 0; i < cs[c]->n; ++i) phi_out[c][i] = ke * q * hp[(size_t)off + i];
         if (U_out) U_out[c] = 0.5 * ke * q * q * hu[c];
+        if (diag) {
+            pt_diagnostics &d = diag[c];
+            const double nkb = (double)cs[c]->n * kBoltzmann;
+            d.t = cs[c]->trap.t0_s + (double)cs[c]->step * cs[c]->trap.dt_s;
+            d.ke_axial = hr[3 * c];
+            d.ke_planar = hr[3 * c + 1];
+            d.pe_external = hr[3 * c + 2];
+            d.pe_coulomb = U_out[c];
+            d.energy = d.ke_axial + d.ke_planar + d.pe_external + d.pe_coulomb;
+            d.temp_axial = 2.0 * d.ke_axial / nkb;
+            d.temp_planar = d.ke_planar / nkb;
+        }
     }
     return PT_OK;
 }
@@ -1029,6 +1057,39 @@ pt_status pt_coulomb_energy_batch(pt_crystal *const *cs, int n_crystals, double 
 }
 
 pt_status pt_coulomb_energy(pt_crystal *c, double *U_out) { return pt_coulomb_energy_batch(&c, 1, U_out); }
+
+pt_status pt_rotating_diagnostics_batch(pt_crystal *const *cs, int n_crystals, pt_diagnostics *out)
+{
+    PT_TRY(check_batch(cs, n_crystals));
+    PT_REQUIRE(out, "out NULL");
+    return evaluate_batch(cs, n_crystals, nullptr, nullptr, nullptr, out);
+}
+
+pt_status pt_rotating_diagnostics(pt_crystal *c, pt_diagnostics *out)
+{
+    return pt_rotating_diagnostics_batch(&c, 1, out);
+}
+
+pt_status pt_read_rotating_state(pt_crystal *c, double *pos_r, double *vel_r)
+{
+    PT_REQUIRE(c, "crystal is NULL");
+    pt_ctx *ctx = c->ctx;
+    PT_HIP(hipSetDevice(ctx->device));
+    Batch b;
+    PT_TRY(form_batch(ctx, std::vector<pt_crystal *>{c}, b));
+    double *rs;
+    PT_TRY(ws_get(ctx, "rot_state", sizeof(double) * 6 * (size_t)b.ntot, &rs));
+    launch_rot_state(b.d_desc, b.ion_crystal, b.ntot, rs, ctx->stream);
+    std::vector<double> h(6 * (size_t)b.ntot);
+    PT_HIP(hipMemcpyAsync(h.data(), rs, sizeof(double) * 6 * b.ntot, hipMemcpyDeviceToHost, ctx->stream));
+    PT_HIP(hipStreamSynchronize(ctx->stream));
+    for (int64_t i = 0; i < c->n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            if (pos_r) pos_r[3 * i + d] = h[(size_t)d * b.ntot + i];
+            if (vel_r) vel_r[3 * i + d] = h[(size_t)(3 + d) * b.ntot + i];
+        }
+    return PT_OK;
+}
 
 pt_status pt_compute_forces(pt_crystal *c, double *F_out)
 {

@@ -44,6 +44,14 @@ class LaserParams(C.Structure):
                 ("gamma0", C.c_double), ("n_beams", C.c_int), ("beam", Beam * MAX_BEAMS)]
 
 
+class Diagnostics(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("t", "ke_axial", "ke_planar", "pe_external", "pe_coulomb", "energy",
+                                          "temp_axial", "temp_planar")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ForceParams(C.Structure):
     _fields_ = [("method", C.c_int), ("p", C.c_int), ("leaf_size", C.c_int), ("precision", C.c_int)]
 
@@ -83,6 +91,9 @@ def load():
         "pt_compute_potential_batch": [C.POINTER(_vp), C.c_int, C.POINTER(_dp)],
         "pt_coulomb_energy": [_vp, _dp],
         "pt_coulomb_energy_batch": [C.POINTER(_vp), C.c_int, _dp],
+        "pt_rotating_diagnostics": [_vp, C.POINTER(Diagnostics)],
+        "pt_rotating_diagnostics_batch": [C.POINTER(_vp), C.c_int, C.POINTER(Diagnostics)],
+        "pt_read_rotating_state": [_vp, _dp, _dp],
         "pt_step": [_vp, C.c_int64],
         "pt_step_batch": [C.POINTER(_vp), C.c_int, C.POINTER(C.c_int64)],
         "pt_synchronize": [_vp],
@@ -237,6 +248,16 @@ class Crystal:
         _check(load().pt_coulomb_energy(self.h, C.byref(U)))
         return U.value
 
+    def rotating_diagnostics(self):
+        d = Diagnostics()
+        _check(load().pt_rotating_diagnostics(self.h, C.byref(d)))
+        return d.as_dict()
+
+    def read_rotating_state(self):
+        pos, vel = np.zeros((self.n, 3)), np.zeros((self.n, 3))
+        _check(load().pt_read_rotating_state(self.h, _ptr(pos), _ptr(vel)))
+        return pos, vel
+
     def step(self, n_steps: int):
         _check(load().pt_step(self.h, int(n_steps)))
 
@@ -299,6 +320,14 @@ def compute_potential_batch(crystals):
     po = (_dp * len(crystals))(*[_ptr(o) for o in outs])
     _check(L.pt_compute_potential_batch(arr, len(crystals), po))
     return outs
+
+
+def rotating_diagnostics_batch(crystals):
+    L = load()
+    out = (Diagnostics * len(crystals))()
+    arr = (_vp * len(crystals))(*[c.h for c in crystals])
+    _check(L.pt_rotating_diagnostics_batch(arr, len(crystals), out))
+    return [d.as_dict() for d in out]
 
 
 def coulomb_energy_batch(crystals):
