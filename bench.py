@@ -176,6 +176,25 @@ def bench_potential(ctx, c, cr, p, leaf, prec, evals=10):
 KICK_BYTES_PER_ION = 48 + 48 + 24 + 4
 
 
+def bench_diagnostics(ctx, c, cr, p, leaf, prec, sync, calls=10):
+    """Rotating-frame diagnostics (eqs. rotation, pe_rot, temp_ax, temp_pl) of the
+    benchmark crystal with its force parameters: wall time per call (one FMM
+    Coulomb-energy evaluation, the per-crystal sums on the device, a few doubles
+    back to the host)."""
+    c.set_state(cr.pos, cr.vel, 0)
+    c.set_force("fmm", p, leaf, prec)
+    c.set_trap(B=cr.B, omega_z=cr.omega_z, dt=cr.dt, omega_r=2 * math.pi * 180e3)
+    d = c.rotating_diagnostics()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        d = c.rotating_diagnostics()
+    el = (time.perf_counter() - t0) / calls
+    c.set_trap(B=cr.B, omega_z=cr.omega_z, dt=cr.dt)
+    log(f"  rotating-frame diagnostics: {el * 1e3:.3f} ms per call; E_r = {d['energy']:.6e} J")
+    return {"ms_per_call": el * 1e3, "omega_r": 2 * math.pi * 180e3, "values": d}
+
+
 def bench_beams(ctx, c, cr, p, leaf, prec, steps, warmup, sync, ref_seconds):
     """The same steps with the beam-mode laser of eq. (scattering_rate) on (the
     cooling set-up of the paper's Sec. 5: two uniform axial beams and the offset
@@ -319,7 +338,11 @@ def bench_serving(a, ctx, sync):
                     "wall_s": rep.wall_s, "max_resident": rep.max_resident,
                     "max_resident_bytes": rep.max_resident_bytes,
                     "note": "offered load above achieved: p99 is queue-dominated"
-                    if offered > rep.ion_steps_per_s else "offered load below achieved"},
+                    if offered > rep.ion_steps_per_s else "offered load below achieved",
+                    # rotating-frame temperatures of the finished crystals (eqs. temp_ax, temp_pl,
+                    # instantaneous), from the server's batched end-of-request diagnostics
+                    "final_temp_axial_K_median": float(np.median([d.diagnostics["temp_axial"] for d in rep.done])),
+                    "final_temp_planar_K_median": float(np.median([d.diagnostics["temp_planar"] for d in rep.done]))},
     }
 
 
@@ -337,6 +360,7 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-potential", action="store_true", help="skip the Coulomb-potential measurement")
     ap.add_argument("--no-beams", action="store_true", help="skip the beam-mode laser measurement")
+    ap.add_argument("--no-diagnostics", action="store_true", help="skip the rotating-frame diagnostics measurement")
     ap.add_argument("--workload", choices=["config3", "ensemble", "serving"], default="config3",
                     help="config3: 1e5-ion crystal (default); ensemble: 256 crystals batched; serving: request stream")
     ap.add_argument("--p", type=int, default=0,
@@ -490,6 +514,8 @@ def main():
         out["beams"] = bench_beams(ctx, c, cr, p, leaf, a.precision, a.steps, a.warmup, sync, main_r["seconds"])
     if not a.no_potential:
         out["potential"] = bench_potential(ctx, c, cr, p, leaf, a.precision)
+    if not a.no_diagnostics:
+        out["diagnostics"] = bench_diagnostics(ctx, c, cr, p, leaf, a.precision, sync)
         if "cpu_baseline" in out:
             out["potential"]["gpu_over_cpu"] = (out["potential"]["ion_evals_per_s"] /
                                                 out["cpu_baseline"]["potential_ion_evals_per_s"])

@@ -478,80 +478,140 @@ void launch_direct(const CrystalDev *cs, const int32_t *blk_crystal, const int32
     else k_direct<false><<<nblk, kDirTB, 0, st>>>(cs, blk_crystal, blk_first, ntot, E, nullptr);
 }
 
-// One workgroup per crystal: each thread adds a strided subset of the
-// crystal's potentials in index order, then the 256 partial sums are added
-// pairwise in a fixed tree, so the result does not depend on the batch.
-constexpr int kSumTB = 256;
-__global__ __launch_bounds__(kSumTB) void k_phi_sum(const CrystalDev *__restrict__ cs, const double *__restrict__ phi,
-                                                    double *__restrict__ out)
+// Potential sums, first level: each block of the direct-sum block table
+// (kDirT x kDirTB ions of one crystal) adds its ions' potentials in a fixed
+// tree into part[block]; blocks depend only on the crystal's own size, so the
+// sums do not depend on the batch.
+__global__ __launch_bounds__(kDirTB) void k_phi_partial(const CrystalDev *__restrict__ cs,
+                                                        const int32_t *__restrict__ blk_crystal,
+                                                        const int32_t *__restrict__ blk_first,
+                                                        const double *__restrict__ phi, double *__restrict__ part)
 {
-    __shared__ double part[kSumTB];
-    const CrystalDev &cd = cs[blockIdx.x];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < cd.n; i += kSumTB) acc += phi[cd.ion_off + i];
-    part[threadIdx.x] = acc;
+    __shared__ double acc[kDirTB];
+    const CrystalDev &cd = cs[blk_crystal[blockIdx.x]];
+    double a = 0.0;
+    for (int t = 0; t < kDirT; ++t) {
+        const int i = blk_first[blockIdx.x] + t * kDirTB + threadIdx.x;
+        if (i < cd.n) a += phi[cd.ion_off + i];
+    }
+    acc[threadIdx.x] = a;
     __syncthreads();
-    for (int h = kSumTB / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    for (int h = kDirTB / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) acc[threadIdx.x] += acc[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
 }
 
-void launch_phi_sum(const CrystalDev *cs, int nc, const double *phi, double *out, hipStream_t st)
+// Second level: one wave per crystal c adds the NC-component partial sums of
+// its blocks (the contiguous run of blk_crystal == c, found by binary
+// search): lane l takes blocks l, l + 64, ... in order, then the lanes'
+// sums are added in a fixed tree, so the result depends only on the
+// crystal's own blocks.
+__device__ inline int first_block(const int32_t *blk_crystal, int nblk, int c)
 {
-    if (nc > 0) k_phi_sum<<<nc, kSumTB, 0, st>>>(cs, phi, out);
+    int lo = 0, hi = nblk;
+    while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (blk_crystal[m] < c) lo = m + 1;
+        else hi = m;
+    }
+    return lo;
+}
+
+template <int NC>
+__global__ __launch_bounds__(64) void k_blocks_finish(const int32_t *__restrict__ blk_crystal, int nblk,
+                                                      const double *__restrict__ part, double *__restrict__ out)
+{
+    __shared__ double acc[NC][64];
+    const int c = blockIdx.x, lane = threadIdx.x;
+    const int b0 = first_block(blk_crystal, nblk, c), b1 = first_block(blk_crystal, nblk, c + 1);
+    double s[NC];
+    for (int k = 0; k < NC; ++k) s[k] = 0.0;
+    for (int b = b0 + lane; b < b1; b += 64)
+        for (int k = 0; k < NC; ++k) s[k] += part[NC * b + k];
+    for (int k = 0; k < NC; ++k) acc[k][lane] = s[k];
+    __syncthreads();
+    for (int h = 32; h > 0; h >>= 1) {
+        if (lane < h)
+            for (int k = 0; k < NC; ++k) acc[k][lane] += acc[k][lane + h];
+        __syncthreads();
+    }
+    if (lane < NC) out[NC * c + lane] = acc[lane][0];
+}
+
+void launch_phi_sum(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int nc,
+                    const double *phi, double *part, double *out, hipStream_t st)
+{
+    if (nc <= 0) return;
+    if (nblk > 0) k_phi_partial<<<nblk, kDirTB, 0, st>>>(cs, blk_crystal, blk_first, phi, part);
+    k_blocks_finish<1><<<nc, 64, 0, st>>>(blk_crystal, nblk, part, out);
 }
 
 // Rotating frame (eq. rotation) at the state's time t = t0 + step dt: the
 // position turned about z by omega_r t, the velocity the time derivative of
-// the turned position, v_r = R v + omega_r (-y_r, x_r, 0).
-__device__ inline void to_rotating(const CrystalDev &cd, int i, double xr[3], double vr[3])
+// the turned position, v_r = R v + omega_r (-y_r, x_r, 0).  (c, s) = cos and
+// sin of omega_r t, computed once per crystal by the caller.
+__device__ inline void frame_turn(const CrystalDev &cd, double *ts)
+{
+    const double t = cd.t0 + (double)cd.step0 * cd.dt;
+    sincos(cd.omega_r * t, &ts[1], &ts[0]);
+}
+
+__device__ inline void to_rotating(const CrystalDev &cd, int i, const double ts[2], double xr[3], double vr[3])
 {
     const int n = cd.n;
     const double *s = cd.state;
-    const double t = cd.t0 + (double)cd.step0 * cd.dt;
-    double sn, cs_;
-    sincos(cd.omega_r * t, &sn, &cs_);
+    const double c = ts[0], sn = ts[1];
     const double x = s[i], y = s[n + i], vx = s[3 * n + i], vy = s[4 * n + i];
-    xr[0] = cs_ * x - sn * y;
-    xr[1] = sn * x + cs_ * y;
+    xr[0] = c * x - sn * y;
+    xr[1] = sn * x + c * y;
     xr[2] = s[2 * n + i];
-    vr[0] = cs_ * vx - sn * vy - cd.omega_r * xr[1];
-    vr[1] = sn * vx + cs_ * vy + cd.omega_r * xr[0];
+    vr[0] = c * vx - sn * vy - cd.omega_r * xr[1];
+    vr[1] = sn * vx + c * vy + cd.omega_r * xr[0];
     vr[2] = s[5 * n + i];
 }
 
-// Per crystal (one workgroup each): the axial and planar kinetic energies of
-// the rotating-frame velocities and the external terms of eq. (pe_rot),
-//   m wz^2 z_r^2 / 2 - m (wr^2 - wc wr + wz^2 / 2)(x_r^2 + y_r^2) / 2 + q k_z delta (x_r^2 - y_r^2) / 4,
-// with m wz^2 = q k_z; strided per-thread sums in index order, then a fixed
-// pairwise tree (independent of the batch).
-__global__ __launch_bounds__(kSumTB) void k_rot_sums(const CrystalDev *__restrict__ cs, double *__restrict__ out)
+// Rotating-frame sums, first level: each block of the direct-sum block table
+// (kDirT x kDirTB ions of one crystal) adds the axial and planar kinetic
+// energies of the rotating-frame velocities and the external terms of eq.
+// (pe_rot),
+//   m wz^2 z_r^2 / 2 - m (wr^2 - wc wr + wz^2 / 2)(x_r^2 + y_r^2) / 2 + q k_z delta (x_r^2 - y_r^2) / 4
+// (m wz^2 = q k_z), in a fixed tree, into part[block][3].  Blocks depend only
+// on the crystal's own size, so the sums do not depend on the batch.
+__global__ __launch_bounds__(kDirTB) void k_rot_partial(const CrystalDev *__restrict__ cs,
+                                                        const int32_t *__restrict__ blk_crystal,
+                                                        const int32_t *__restrict__ blk_first,
+                                                        double *__restrict__ part)
 {
-    __shared__ double part[3][kSumTB];
-    const CrystalDev &cd = cs[blockIdx.x];
+    __shared__ double acc[3][kDirTB];
+    __shared__ double ts[2];
+    const CrystalDev &cd = cs[blk_crystal[blockIdx.x]];
+    if (threadIdx.x == 0) frame_turn(cd, ts);
+    __syncthreads();
     const double wr = cd.omega_r, wz2 = cd.qkz / cd.mass;
     const double radial = 0.5 * cd.mass * (wr * wr - cd.wc * wr + 0.5 * wz2);
     double ka = 0.0, kp = 0.0, pe = 0.0;
-    for (int i = threadIdx.x; i < cd.n; i += kSumTB) {
+    for (int t = 0; t < kDirT; ++t) {
+        const int i = blk_first[blockIdx.x] + t * kDirTB + threadIdx.x;
+        if (i >= cd.n) continue;
         double xr[3], vr[3];
-        to_rotating(cd, i, xr, vr);
+        to_rotating(cd, i, ts, xr, vr);
         ka += 0.5 * cd.mass * vr[2] * vr[2];
         kp += 0.5 * cd.mass * (vr[0] * vr[0] + vr[1] * vr[1]);
         pe += 0.5 * cd.qkz * xr[2] * xr[2] - radial * (xr[0] * xr[0] + xr[1] * xr[1]) +
               0.25 * cd.qkz * cd.delta * (xr[0] * xr[0] - xr[1] * xr[1]);
     }
-    part[0][threadIdx.x] = ka;
-    part[1][threadIdx.x] = kp;
-    part[2][threadIdx.x] = pe;
+    acc[0][threadIdx.x] = ka;
+    acc[1][threadIdx.x] = kp;
+    acc[2][threadIdx.x] = pe;
     __syncthreads();
-    for (int h = kSumTB / 2; h > 0; h >>= 1) {
+    for (int h = kDirTB / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h)
-            for (int k = 0; k < 3; ++k) part[k][threadIdx.x] += part[k][threadIdx.x + h];
+            for (int k = 0; k < 3; ++k) acc[k][threadIdx.x] += acc[k][threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x < 3) out[3 * blockIdx.x + threadIdx.x] = part[threadIdx.x][0];
+    if (threadIdx.x < 3) part[3 * blockIdx.x + threadIdx.x] = acc[threadIdx.x][0];
 }
 
 // Rotating-frame positions and velocities of every ion, SoA (6 x ntot, batch order).
@@ -561,17 +621,21 @@ __global__ void k_rot_state(const CrystalDev *__restrict__ cs, const int32_t *__
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ntot) return;
     const CrystalDev &cd = cs[ion_crystal[g]];
-    double xr[3], vr[3];
-    to_rotating(cd, g - cd.ion_off, xr, vr);
+    double ts[2], xr[3], vr[3];
+    frame_turn(cd, ts);
+    to_rotating(cd, g - cd.ion_off, ts, xr, vr);
     for (int k = 0; k < 3; ++k) {
         out[(size_t)k * ntot + g] = xr[k];
         out[(size_t)(3 + k) * ntot + g] = vr[k];
     }
 }
 
-void launch_rot_sums(const CrystalDev *cs, int nc, double *out, hipStream_t st)
+void launch_rot_sums(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int nc,
+                     double *part, double *out, hipStream_t st)
 {
-    if (nc > 0) k_rot_sums<<<nc, kSumTB, 0, st>>>(cs, out);
+    if (nc <= 0) return;
+    if (nblk > 0) k_rot_partial<<<nblk, kDirTB, 0, st>>>(cs, blk_crystal, blk_first, part);
+    k_blocks_finish<3><<<nc, 64, 0, st>>>(blk_crystal, nblk, part, out);
 }
 
 void launch_rot_state(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, double *out, hipStream_t st)

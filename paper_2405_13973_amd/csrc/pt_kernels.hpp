@@ -45,11 +45,15 @@ int direct_targets_per_block();
 // unit charge sum_{j != i} 1/r_ij into phi (ntot).
 void launch_direct(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int ntot,
                    double *E, double *phi, hipStream_t st);
-// Per crystal c of the batch: out[c] = sum of phi over its ions (fixed order).
-void launch_phi_sum(const CrystalDev *cs, int nc, const double *phi, double *out, hipStream_t st);
+// Per crystal c of the batch: out[c] = sum of phi over its ions (fixed order),
+// over the direct-sum block table; part: nblk doubles of workspace.
+void launch_phi_sum(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int nc,
+                    const double *phi, double *part, double *out, hipStream_t st);
 // Per crystal c: out[3c..3c+2] = rotating-frame axial KE, planar KE and the
-// external terms of eq. (pe_rot), at the state's time (fixed order).
-void launch_rot_sums(const CrystalDev *cs, int nc, double *out, hipStream_t st);
+// external terms of eq. (pe_rot), at the state's time (fixed order), over
+// the direct-sum block table; part: 3 x nblk doubles of workspace.
+void launch_rot_sums(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int nc,
+                     double *part, double *out, hipStream_t st);
 // Rotating-frame positions and velocities, SoA 6 x ntot in batch order.
 void launch_rot_state(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, double *out, hipStream_t st);
 

@@ -989,15 +989,18 @@ static pt_status evaluate_batch(pt_crystal *const *cs, int n_crystals, double *c
         PT_HIP(hipMemcpyAsync(hp.data(), phi, sizeof(double) * b.ntot, hipMemcpyDeviceToHost, ctx->stream));
     }
     if (U_out) {
-        launch_phi_sum(b.d_desc, n_crystals, phi, usum, ctx->stream);
+        double *ppart;
+        PT_TRY(ws_get(ctx, "phi_part", sizeof(double) * (size_t)std::max(1, b.nblk_direct), &ppart));
+        launch_phi_sum(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, n_crystals, phi, ppart, usum, ctx->stream);
         hu.resize((size_t)n_crystals);
         PT_HIP(hipMemcpyAsync(hu.data(), usum, sizeof(double) * n_crystals, hipMemcpyDeviceToHost, ctx->stream));
     }
     std::vector<double> hr;
     if (diag) {
-        double *rsum;
+        double *rsum, *rpart;
         PT_TRY(ws_get(ctx, "rot_sum", sizeof(double) * 3 * (size_t)n_crystals, &rsum));
-        launch_rot_sums(b.d_desc, n_crystals, rsum, ctx->stream);
+        PT_TRY(ws_get(ctx, "rot_part", sizeof(double) * 3 * (size_t)std::max(1, b.nblk_direct), &rpart));
+        launch_rot_sums(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, n_crystals, rpart, rsum, ctx->stream);
         hr.resize(3 * (size_t)n_crystals);
         PT_HIP(hipMemcpyAsync(hr.data(), rsum, sizeof(double) * 3 * n_crystals, hipMemcpyDeviceToHost, ctx->stream));
     }

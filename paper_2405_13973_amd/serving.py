@@ -42,6 +42,7 @@ class Done:
     pos: np.ndarray
     vel: np.ndarray
     photons: np.ndarray
+    diagnostics: dict | None = None  # rotating-frame energies and temperatures at the end
 
     @property
     def latency_s(self) -> float:
@@ -127,6 +128,11 @@ class Server:
                 a[2] -= k
                 ion_steps += k * a[1].n
             still = []
+            finished = [a for a in active if a[2] <= 0]
+            # rotating-frame energies and temperatures of the finished crystals,
+            # one batched evaluation (sums on the device; eqs. pe_rot, temp_ax, temp_pl)
+            diags = self.native.rotating_diagnostics_batch([a[1] for a in finished]) if finished else []
+            diag_of = {id(a): d for a, d in zip(finished, diags)}
             for a in active:
                 if a[2] > 0:
                     still.append(a)
@@ -135,7 +141,7 @@ class Server:
                 fin = self.clock() - t0
                 req = requests[a[0]]
                 done.append(Done(a[0], a[1].n, req.steps, req.arrival_s * time_scale, a[3], fin, st["pos"], st["vel"],
-                                 st["photons"]))
+                                 st["photons"], diag_of[id(a)]))
                 a[1].destroy()
                 used -= footprint(req.crystal.n)
             active = still

@@ -218,3 +218,4 @@ def test_serving_admission_under_a_small_budget():
     assert sorted(d.index for d in rep.done) == list(range(len(reqs)))
     assert rep.max_resident_bytes <= budget
     assert all(d.steps == reqs[d.index].steps for d in rep.done)
+    assert all(np.isfinite(d.diagnostics["energy"]) and d.diagnostics["temp_axial"] > 0 for d in rep.done)

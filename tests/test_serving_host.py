@@ -56,6 +56,10 @@ class FakeNative:
         # time advances with the work of the longest crystal in the batch
         self.clock.t += self.rate * sum(c.n * k for c, k in zip(cs, n))
 
+    def rotating_diagnostics_batch(self, cs):
+        self.diag_calls = getattr(self, "diag_calls", []) + [[c.n for c in cs]]
+        return [dict(energy=float(c.n), steps=c.steps) for c in cs]
+
 
 class FakeCtx:
     def __init__(self):
@@ -96,6 +100,11 @@ def test_all_requests_complete_with_their_steps():
     assert all(k <= 25 for call in nat.calls for _, k in call)
     # continuous batching: requests arriving while others run share calls
     assert any(len(call) > 1 for call in nat.calls)
+    # each request's end-of-run diagnostics come from one batched call per tick,
+    # taken after its last steps
+    assert sorted(n for call in nat.diag_calls for n in call) == sorted(d.n_ions for d in rep.done)
+    for d in rep.done:
+        assert d.diagnostics["energy"] == d.n_ions and d.diagnostics["steps"] == d.steps
 
 
 def test_admission_waits_for_memory():
