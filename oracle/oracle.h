@@ -30,12 +30,16 @@
 #define OR_PI 3.14159265358979323846
 
 /* Trap description: B along +z, axial frequency omega_z (rad/s), rotating
- * wall strength delta and rotation omega_r (rad/s). */
+ * wall strength delta and rotation omega_r (rad/s).  damping (1/s, 0 = off):
+ * the artificial damping of the paper's outlook -- once per step, after the
+ * kick, the velocity relative to the frame turning at omega_r (eq. rotation)
+ * is multiplied by exp(-damping dt). */
 typedef struct {
     double B;
     double omega_z;
     double delta;
     double omega_r;
+    double damping;
 } or_trap;
 
 /* One laser beam of eq. (scattering_rate): propagation direction khat

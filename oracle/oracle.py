@@ -26,7 +26,12 @@ _u64 = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 
 
 class Trap(C.Structure):
-    _fields_ = [("B", C.c_double), ("omega_z", C.c_double), ("delta", C.c_double), ("omega_r", C.c_double)]
+    _fields_ = [("B", C.c_double), ("omega_z", C.c_double), ("delta", C.c_double), ("omega_r", C.c_double),
+                ("damping", C.c_double)]
+
+
+def _trap(trap):
+    return Trap(trap["B"], trap["omega_z"], trap.get("delta", 0.0), trap.get("omega_r", 0.0), trap.get("damping", 0.0))
 
 
 class Beam(C.Structure):
@@ -189,7 +194,7 @@ def photon_counts(n, seed, step, mean):
 # ------------------------------------------------------------------ forces
 def external_force(q, m, trap: dict, t, x):
     F = np.zeros(3)
-    tr = Trap(trap["B"], trap["omega_z"], trap.get("delta", 0.0), trap.get("omega_r", 0.0))
+    tr = _trap(trap)
     lib().or_external_force(q, m, C.byref(tr), t, np.ascontiguousarray(x, dtype=np.float64), F)
     return F
 
@@ -216,7 +221,7 @@ def coulomb_energy(pos, q):
 
 def energy(pos, vel, q, m, trap: dict):
     pos, vel = _pos(pos), _pos(vel)
-    tr = Trap(trap["B"], trap["omega_z"], 0.0, 0.0)
+    tr = Trap(trap["B"], trap["omega_z"], 0.0, 0.0, 0.0)
     return lib().or_energy(len(pos), pos, vel, float(q), float(m), C.byref(tr))
 
 
@@ -231,7 +236,7 @@ def rotating_frame(pos, vel, omega_r, t):
 def rotating_energy(pos, vel, q, m, trap: dict, t):
     """Rotating-frame energy terms (J): axial KE, planar KE, external, Coulomb, total."""
     pos, vel = _pos(pos), _pos(vel)
-    tr = Trap(trap["B"], trap["omega_z"], trap.get("delta", 0.0), trap.get("omega_r", 0.0))
+    tr = _trap(trap)
     out = np.zeros(5)
     lib().or_rotating_energy(len(pos), pos, vel, float(q), float(m), C.byref(tr), float(t), out)
     return out
@@ -299,7 +304,7 @@ def run(pos, vel, q, m, trap: dict, dt, nsteps, *, t0=0.0, step0=0, seed=0, lase
         p=8, leaf_size=32, return_photons=False):
     """nsteps oracle steps; returns (pos, vel[, photons of the last step])."""
     pos, vel = _pos(pos).copy(), _pos(vel).copy()
-    tr = Trap(trap["B"], trap["omega_z"], trap.get("delta", 0.0), trap.get("omega_r", 0.0))
+    tr = _trap(trap)
     la = laser_struct(laser)
     fo = Force(0 if method == "direct" else 1, int(p), int(leaf_size))
     ph = np.zeros(len(pos), np.int32)

@@ -406,6 +406,20 @@ static int or_beam_kick(const or_laser *la, uint64_t seed, uint32_t ion, uint64_
     return total;
 }
 
+/* Artificial damping (the outlook of the paper's conclusion: momenta slowly
+ * decreased while the crystal evolves): the velocity relative to the frame of
+ * eq. (rotation) -- v minus the clockwise rigid rotation omega_r (y, -x, 0),
+ * the motion at rest in that frame -- is multiplied by exp(-damping dt / 2),
+ * once before and once after the kick, so that the split step stays
+ * symmetric and the damped fixed point sits within O(dt^2) of the rotating
+ * frame's equilibrium. */
+static void or_damp_half(const or_trap *tr, double dt, const double x[3], double v[3])
+{
+    double f = exp(-0.5 * tr->damping * dt);
+    double rig[3] = {tr->omega_r * x[1], -tr->omega_r * x[0], 0.0};
+    for (int d = 0; d < 3; ++d) v[d] = rig[d] + f * (v[d] - rig[d]);
+}
+
 /* Coulomb force by the FMM (fmm.c). */
 int or_fmm_coulomb(int n, const double *pos, double q, int p, int leaf_size, double *F);
 
@@ -434,6 +448,7 @@ int or_step(int n, double *pos, double *vel, double q, double m, const or_trap *
     if (laser_on) or_poisson_cdf(la->mean_per_step, F);
     double recoil = laser_on ? OR_H_PLANCK / (la->wavelength * m) : 0.0;
     for (int i = 0; i < n; ++i) {
+        if (tr->damping > 0.0) or_damp_half(tr, dt, pos + 3 * i, vel + 3 * i);
         double fe[3], vmid[3] = {vel[3 * i], vel[3 * i + 1], vel[3 * i + 2]};
         or_external_force(q, m, tr, tm, pos + 3 * i, fe);
         for (int d = 0; d < 3; ++d) vel[3 * i + d] += (fe[d] + Fc[3 * i + d]) * dt / m;
@@ -453,6 +468,7 @@ int or_step(int n, double *pos, double *vel, double q, double m, const or_trap *
             for (int d = 0; d < 3; ++d) vel[3 * i + d] += recoil * acc[d];
         }
         if (photons) photons[i] = cnt;
+        if (tr->damping > 0.0) or_damp_half(tr, dt, pos + 3 * i, vel + 3 * i);
     }
     or_u0(n, pos, vel, wc, 0.5 * dt);
     free(Fc);

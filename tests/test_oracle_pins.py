@@ -795,3 +795,60 @@ def test_rotating_energy_conserved_with_the_wall():
     assert 2.8 < devs[0] / devs[1] < 5.5, devs
     assert alts[1] > 5 * devs[1], (alts, devs)
 
+
+# ---------------------------------------------------------- artificial damping
+def _larmor_trap(beta=0.6, delta=0.05, damping=2e6):
+    """A trap whose rotating frame turns at omega_c / 2 (B_eff = B - 2 m omega_r / q = 0):
+    there every mode has kinetic energy and velocity damping relaxes all of them.
+    B is chosen so that beta (eq. beta) takes the given value."""
+    wz = 2 * math.pi * 1.5e6
+    wc = 2 * wz * math.sqrt(beta + 0.5)
+    return dict(B=wc * M / Q, omega_z=wz, delta=delta, omega_r=0.5 * wc, damping=damping)
+
+
+def test_damping_relaxes_two_ions_to_the_closed_form():
+    """Artificial damping (the paper's outlook): two ions settle along the softest axis of
+    the rotating-frame potential, here y (K_y = m wz^2 (beta - delta/2), the wall term of
+    R17), at the separation d^3 = 2 k_e q^2 / K_y where the Coulomb push balances it;
+    the damped split step's fixed point is within O(dt^2) of it."""
+    trap = _larmor_trap()
+    wz, wr = trap["omega_z"], trap["omega_r"]
+    beta = wr * (Q * trap["B"] / M - wr) / wz ** 2 - 0.5
+    d_ref = (2 * O.K_E * Q * Q / (M * wz ** 2 * (beta - trap["delta"] / 2))) ** (1 / 3)
+    pos = np.array([[3e-6, 2e-6, 1e-6], [-4e-6, -1e-6, -0.5e-6]])
+    vel = wr * np.stack([pos[:, 1], -pos[:, 0], np.zeros(2)], 1)  # at rest in the rotating frame
+    errs = []
+    for dt, nst in ((2e-9, 12000), (4e-9, 6000)):
+        x, v = O.run(pos, vel, Q, M, trap, dt, nst)
+        xr, vr = O.rotating_frame(x, v, wr, nst * dt)
+        sep = xr[0] - xr[1]
+        errs.append(abs(np.linalg.norm(sep) / d_ref - 1))
+        assert abs(abs(sep[1]) / np.linalg.norm(sep) - 1) < 1e-9  # along y
+        assert np.abs(vr).max() < 1e-6  # m/s: nanokelvin; lab speeds here are ~100 m/s
+    assert errs[0] < 5e-5, errs
+    assert 3.0 < errs[1] / errs[0] < 5.0, errs
+
+
+def test_damping_relaxes_to_a_rotating_equilibrium():
+    """After relaxation every ion moves on a circle at omega_r: trap, wall, Coulomb and the
+    magnetic force on the rigid-rotation velocity add up to the centripetal force
+    -m omega_r^2 (x, y, 0) (checked with the oracle's force routines), to the O(dt^2)
+    offset of the damped fixed point."""
+    trap = _larmor_trap()
+    wr, dt, nst = trap["omega_r"], 2e-9, 20000
+    pos = inputs.uniform_ball(30, 2e-5, inputs.rng(41))
+    vel = wr * np.stack([pos[:, 1], -pos[:, 0], np.zeros(30)], 1)
+    x, v = O.run(pos, vel, Q, M, trap, dt, nst)
+    t = nst * dt
+    _, vr = O.rotating_frame(x, v, wr, t)
+    # the softest modes (the crystal rocking in the weak wall potential) are
+    # overdamped and decay only at omega^2 / damping: a residual of 1e-2 m/s is
+    # ~50 nK, far below any temperature of interest
+    assert np.abs(vr).max() < 2e-2
+    F = O.coulomb_direct(x, Q) + np.array([O.external_force(Q, M, trap, t, xi) for xi in x])
+    vrig = wr * np.stack([x[:, 1], -x[:, 0], np.zeros(30)], 1)
+    F += Q * np.cross(vrig, [0.0, 0.0, trap["B"]])
+    centripetal = -M * wr ** 2 * np.stack([x[:, 0], x[:, 1], np.zeros(30)], 1)
+    scale = np.linalg.norm(O.coulomb_direct(x, Q), axis=1).mean()
+    assert np.abs(F - centripetal).max() < 2e-4 * scale
+
