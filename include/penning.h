@@ -52,7 +52,15 @@ typedef struct pt_crystal pt_crystal;
 /* Trap parameters (Sec. 2.1).  omega_z and omega_r in rad/s.  dt_s is the
  * step length and t0_s the time of step 0: step k runs from t0 + k dt to
  * t0 + (k+1) dt.  Requires dt > 0 and radial confinement of a single ion,
- * omega_c^2 > 2 omega_z^2 with omega_c = qB/m (else PT_EINVAL). */
+ * omega_c^2 > 2 omega_z^2 with omega_c = qB/m (else PT_EINVAL).
+ * damping_per_s >= 0 (0 = off): artificial damping, the paper's proposal for
+ * finding crystal equilibria -- each step multiplies the velocity relative to
+ * the frame turning at omega_r (eq. rotation), v - omega_r (y, -x, 0), by
+ * exp(-damping dt / 2) just before and again just after the kick, so the
+ * crystal relaxes to a minimum of the rotating-frame potential energy
+ * (eq. pe_rot); the split keeps the damped fixed point within O(dt^2) of it.
+ * Modes without kinetic energy relax slowly (E x B modes when omega_r is far
+ * from omega_c / 2, where B - 2 m omega_r / q vanishes). */
 typedef struct {
     double B_T;
     double omega_z;
@@ -60,6 +68,7 @@ typedef struct {
     double omega_r;
     double dt_s;
     double t0_s;
+    double damping_per_s;
 } pt_trap_params;
 
 /* One laser beam of eq. (scattering_rate).  khat: propagation direction

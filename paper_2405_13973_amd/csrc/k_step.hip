@@ -230,6 +230,16 @@ __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *_
     double *s = cd.state;
     double x = s[i], y = s[n + i], z = s[2 * n + i];
     double vx = s[3 * n + i], vy = s[4 * n + i], vz = s[5 * n + i];
+    // artificial damping, first half: the velocity relative to the rigid
+    // clockwise rotation omega_r (y, -x, 0) (at rest in the rotating frame)
+    // shrinks by exp(-damping dt / 2)
+    auto damp_half = [&]() {
+        const double rx = cd.omega_r * y, ry = -cd.omega_r * x;
+        vx = rx + cd.damp_f * (vx - rx);
+        vy = ry + cd.damp_f * (vy - ry);
+        vz = cd.damp_f * vz;
+    };
+    if (cd.damp_on) damp_half();
     const uint64_t step = cd.step0 + (uint64_t)kstep;
     const double t = cd.t0 + (double)step * cd.dt;
     const double tm = t + 0.5 * cd.dt;
@@ -333,6 +343,7 @@ __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *_
         vz += cd.recoil * az;
     }
     cd.photons[i] = nph;
+    if (cd.damp_on) damp_half();  // second half, after the kick
     u0_half(cd, x, y, z, vx, vy, vz);
     s[i] = x;
     s[n + i] = y;

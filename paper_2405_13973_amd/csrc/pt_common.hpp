@@ -61,6 +61,7 @@ struct CrystalDev {
     double qkz;             // q k_z = m omega_z^2
     double delta, omega_r;
     double inv_m;
+    double damp_f;          // exp(-damping dt / 2), applied before and after the kick
     double mass;            // m (rotating-frame diagnostics)
     double wc;              // omega_c = q B / m
     double coul;            // k_e q^2
@@ -68,6 +69,8 @@ struct CrystalDev {
     double poisson_F[17];   // cumulative Poisson table of the photon mean
     int32_t laser_on;       // 1: fixed-mean photons, 2: beams
     int32_t n_beams;
+    int32_t damp_on;        // artificial damping of the rotating-frame velocity
+    int32_t pad2;
     double gamma0;          // natural linewidth (rad/s), beams only
     double kwave;           // 2 pi / wavelength (1/m)
     BeamDev beam[kMaxBeams];

@@ -304,6 +304,8 @@ static void fill_desc(const pt_crystal *c, int off, CrystalDev &d)
     d.delta = c->trap.delta;
     d.omega_r = c->trap.omega_r;
     d.inv_m = 1.0 / c->m;
+    d.damp_f = c->trap.damping_per_s > 0.0 ? std::exp(-0.5 * c->trap.damping_per_s * c->trap.dt_s) : 1.0;
+    d.damp_on = c->trap.damping_per_s > 0.0 ? 1 : 0;
     d.mass = c->m;
     d.wc = wc;
     d.coul = c->q * c->q / (4.0 * kPi * kEps0);
@@ -666,8 +668,9 @@ static bool finite_all(const double *a, int64_t n)
 static pt_status check_trap(const pt_crystal *c, const pt_trap_params *p)
 {
     PT_REQUIRE(p, "trap params NULL");
-    const double v[6] = {p->B_T, p->omega_z, p->delta, p->omega_r, p->dt_s, p->t0_s};
-    PT_REQUIRE(finite_all(v, 6), "trap params must be finite");
+    const double v[7] = {p->B_T, p->omega_z, p->delta, p->omega_r, p->dt_s, p->t0_s, p->damping_per_s};
+    PT_REQUIRE(finite_all(v, 7), "trap params must be finite");
+    PT_REQUIRE(p->damping_per_s >= 0.0, "damping must be >= 0");
     PT_REQUIRE(p->dt_s > 0.0, "dt must be > 0");
     PT_REQUIRE(p->omega_z >= 0.0, "omega_z must be >= 0");
     const double wc = c->q * p->B_T / c->m;
@@ -791,7 +794,7 @@ static pt_status create_common(pt_ctx *ctx, int64_t n, double charge, double mas
     c->q = charge;
     c->m = mass;
     c->seed = seed;
-    c->trap = {4.5, 2.0 * kPi * 1.5e6, 0.0, 0.0, 1e-9, 0.0};
+    c->trap = {4.5, 2.0 * kPi * 1.5e6, 0.0, 0.0, 1e-9, 0.0, 0.0};
     if ((c->q * 4.5 / c->m) * (c->q * 4.5 / c->m) <= 2.0 * c->trap.omega_z * c->trap.omega_z) c->trap.omega_z = 0.0;
     c->laser = {0, 0.0, 313e-9};
     c->force = {0, 8, 32, 0};

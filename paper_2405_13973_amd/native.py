@@ -28,7 +28,7 @@ class PTError(RuntimeError):
 
 class TrapParams(C.Structure):
     _fields_ = [("B_T", C.c_double), ("omega_z", C.c_double), ("delta", C.c_double), ("omega_r", C.c_double),
-                ("dt_s", C.c_double), ("t0_s", C.c_double)]
+                ("dt_s", C.c_double), ("t0_s", C.c_double), ("damping_per_s", C.c_double)]
 
 
 class Beam(C.Structure):
@@ -200,8 +200,8 @@ class Crystal:
     def __init__(self, ctx: Context, h, n: int):
         self.ctx, self.h, self.n = ctx, h, n
 
-    def set_trap(self, B=4.5, omega_z=2 * np.pi * 1.5e6, delta=0.0, omega_r=0.0, dt=1e-9, t0=0.0):
-        p = TrapParams(B, omega_z, delta, omega_r, dt, t0)
+    def set_trap(self, B=4.5, omega_z=2 * np.pi * 1.5e6, delta=0.0, omega_r=0.0, dt=1e-9, t0=0.0, damping=0.0):
+        p = TrapParams(B, omega_z, delta, omega_r, dt, t0, damping)
         _check(load().pt_set_trap_params(self.h, C.byref(p)))
         return self
 
