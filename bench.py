@@ -195,6 +195,41 @@ def bench_diagnostics(ctx, c, cr, p, leaf, prec, sync, calls=10):
     return {"ms_per_call": el * 1e3, "omega_r": 2 * math.pi * 180e3, "values": d}
 
 
+def bench_relaxation(ctx, prec, sync, n=10000, steps=5000, dt=2e-9, damping=2e6):
+    """Artificial damping towards a crystal equilibrium (the paper's proposal in place
+    of a BFGS minimisation for large N): n ions uniform in a ball at the density of
+    the 1,000-ion configuration, at rest in a frame turning at omega_c / 2 (where
+    velocity damping reaches every mode; B set for beta = 0.6, delta = 0.05), FMM
+    forces (p = 8, leaf 64); rotating-frame temperatures and energy before and after
+    `steps` damped steps, and the wall time."""
+    wz = 2 * math.pi * 1.5e6
+    wc = 2 * wz * math.sqrt(1.1)
+    B, wr = wc * inputs.ION_MASS / inputs.ION_CHARGE, 0.5 * wc
+    pos = inputs.uniform_ball(n, 100e-6 * (n / 1000) ** (1 / 3), inputs.rng(7))
+    vel = wr * np.stack([pos[:, 1], -pos[:, 0], np.zeros(n)], 1)
+    c = ctx.crystal(pos, vel, inputs.ION_CHARGE, inputs.ION_MASS, 7)
+    c.set_trap(B=B, omega_z=wz, delta=0.05, omega_r=wr, dt=dt, damping=damping)
+    c.set_force("fmm", 8, 64, prec)
+    d0 = c.rotating_diagnostics()
+    c.step(200)  # the first, fastest part of the relaxation; also the warm-up
+    d1 = c.rotating_diagnostics()
+    sync()
+    t0 = time.perf_counter()
+    c.step(steps)
+    sync()
+    el = time.perf_counter() - t0
+    d2 = c.rotating_diagnostics()
+    c.destroy()
+    log(f"  relaxation: {n} ions, {steps} damped steps in {el:.2f} s; T_ax {d1['temp_axial']:.3g} -> "
+        f"{d2['temp_axial']:.3g} K, T_perp {d1['temp_planar']:.3g} -> {d2['temp_planar']:.3g} K")
+    return {"n_ions": n, "steps": steps, "dt_s": dt, "damping_per_s": damping, "ms_per_step": el * 1e3 / steps,
+            "ion_steps_per_s": n * steps / el, "simulated_s_per_wall_s": steps * dt / el,
+            "temp_axial_K": [d0["temp_axial"], d1["temp_axial"], d2["temp_axial"]],
+            "temp_planar_K": [d0["temp_planar"], d1["temp_planar"], d2["temp_planar"]],
+            "energy_J": [d0["energy"], d1["energy"], d2["energy"]],
+            "note": "temperatures and rotating-frame energy at the start, after 200 steps, and at the end"}
+
+
 def bench_beams(ctx, c, cr, p, leaf, prec, steps, warmup, sync, ref_seconds):
     """The same steps with the beam-mode laser of eq. (scattering_rate) on (the
     cooling set-up of the paper's Sec. 5: two uniform axial beams and the offset
@@ -361,6 +396,7 @@ def main():
     ap.add_argument("--no-potential", action="store_true", help="skip the Coulomb-potential measurement")
     ap.add_argument("--no-beams", action="store_true", help="skip the beam-mode laser measurement")
     ap.add_argument("--no-diagnostics", action="store_true", help="skip the rotating-frame diagnostics measurement")
+    ap.add_argument("--no-relaxation", action="store_true", help="skip the artificial-damping relaxation")
     ap.add_argument("--workload", choices=["config3", "ensemble", "serving"], default="config3",
                     help="config3: 1e5-ion crystal (default); ensemble: 256 crystals batched; serving: request stream")
     ap.add_argument("--p", type=int, default=0,
@@ -516,6 +552,8 @@ def main():
         out["potential"] = bench_potential(ctx, c, cr, p, leaf, a.precision)
     if not a.no_diagnostics:
         out["diagnostics"] = bench_diagnostics(ctx, c, cr, p, leaf, a.precision, sync)
+    if not a.no_relaxation:
+        out["relaxation"] = bench_relaxation(ctx, a.precision, sync)
         if "cpu_baseline" in out:
             out["potential"]["gpu_over_cpu"] = (out["potential"]["ion_evals_per_s"] /
                                                 out["cpu_baseline"]["potential_ion_evals_per_s"])
