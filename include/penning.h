@@ -243,7 +243,8 @@ pt_status pt_debug_export_tree(pt_crystal *c, int64_t sizes[4], uint64_t *keys, 
 
 /* Per-phase GPU time of force evaluations, measured with HIP events:
  * ms[0] sort+tree+lists (P2M runs on a second stream of the context
- * beside the lists), [1] M2M, [2] the M2L matrix-core kernel,
+ * beside the lists), [1] M2M with the M2L bucketing and the near-field work
+ * items, [2] the M2L matrix-core kernel,
  * [3] M2L reduction + L2L, [4] the P2P kernel (it runs on a second stream
  * of the context, concurrently with [1]-[3]), [5] waiting for the P2P
  * kernel plus L2P and the near-field partial sums, [6] total (the direct

@@ -188,6 +188,10 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
                                                          const T *__restrict__ X, T *__restrict__ out)
 {
     using MF = Mfma<T>;
+    // M2L runs beside the near field, whose waves would otherwise take most
+    // issue slots of the SIMDs it shares; a raised wave priority lets the
+    // M2L waves (the longer dependency chain) issue first when they are ready
+    if (ROLE == 0) __builtin_amdgcn_s_setprio(1);
     constexpr int ROWS = NRB * 16;
     constexpr int NT = 64 * kM2LWaves;
     constexpr int kXA = KC * ROWS / NT;  // operator values staged per thread (exact)
@@ -458,18 +462,36 @@ constexpr double kRinvMax = 1e12;
 template <typename T, bool POT>
 __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *__restrict__ sp, int ntot,
                                                      const int2 *__restrict__ near, int stride,
-                                                     const int4 *__restrict__ work, int n_items, T *__restrict__ part)
+                                                     const int4 *__restrict__ work, int n_items, T *__restrict__ part,
+                                                     int *__restrict__ queue)
 {
     constexpr int NT = kP2PThreads;
     constexpr int NC = POT ? 4 : 3;  // partial components per target
     constexpr int kU = kP2PStage / NT;
-    __shared__ double4 src[kP2PStage];
+    // staged sources as (x, y) pairs and z: 24 B per source, so that six of
+    // these workgroups and one translation-GEMM workgroup share a compute
+    // unit's LDS when the two kernels run side by side
+    __shared__ double2 sxy[kP2PStage];
+    __shared__ double szz[kP2PStage];
     __shared__ int pre_s[kNearMax + 1];  // prefix of the item's range lengths
     __shared__ int beg_s[kNearMax];      // first ion of each range minus its prefix
     __shared__ int total_s;
-    __shared__ T hx[NT], hy[NT], hz[NT], hp[POT ? NT : 1];
+    // the phases' hand-off arrays reuse the staging buffer once an item's
+    // sources are done (NC x NT values of T fit in it)
+    static_assert(sizeof(T) * 4 * NT <= sizeof(double2) * kP2PStage, "hand-off arrays must fit the stage");
+    T *const hx = reinterpret_cast<T *>(sxy), *const hy = hx + NT, *const hz = hy + NT, *const hp = hz + NT;
     const int tid = threadIdx.x, lane = tid & 63;
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    __shared__ int it_s;
+    for (int round = 0;; ++round) {
+        // the next item: with a queue (a grid capped below the item count),
+        // taken from it as workgroups free up, which balances items of very
+        // different sizes; without, the k-th of the grid stride.  Every item
+        // writes its own partials, so the order changes no result.
+        __syncthreads();  // the previous item is done with the shared arrays
+        if (tid == 0) it_s = queue ? atomicAdd(queue, 1) : (int)blockIdx.x + round * (int)gridDim.x;
+        __syncthreads();
+        const int it = it_s;
+        if (it >= n_items) break;
         const int4 w = work[it];
         const int b = w.x;
         const int2 *row = near + (size_t)b * stride;
@@ -480,8 +502,7 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *
         const int k = w.y + ti;
         const double xi = sp[k], yi = sp[ntot + k], zi = sp[2 * ntot + k];
         const int nr = min(w.w - w.z, kNearMax);
-        __syncthreads();  // the previous item is done with the shared arrays
-        if (tid < 64) {   // prefix of the range lengths, by the first wave
+        if (tid < 64) {  // prefix of the range lengths, by the first wave
             int total = 0;
             for (int r0 = 0; r0 < nr; r0 += 64) {
                 const int r = r0 + lane;
@@ -541,15 +562,18 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u)
-                if (js[u] >= 0) src[tid + NT * u] = make_double4(sx[u], sy[u], sz[u], 0.0);
+                if (js[u] >= 0) {
+                    sxy[tid + NT * u] = make_double2(sx[u], sy[u]);
+                    szz[tid + NT * u] = sz[u];
+                }
             __syncthreads();
             for (int q0 = ph < nph ? ph * blk : n; q0 < n; q0 += nph * blk) {
                 const int q1 = min(n, q0 + blk);
                 T px = 0, py = 0, pz = 0, pv = 0;
 #pragma unroll 4
                 for (int q = q0; q < q1; ++q) {
-                    const double4 v = src[q];
-                    const T dx = (T)(xi - v.x), dy = (T)(yi - v.y), dz = (T)(zi - v.z);
+                    const double2 v = sxy[q];
+                    const T dx = (T)(xi - v.x), dy = (T)(yi - v.y), dz = (T)(zi - szz[q]);
                     // r = 0 (the target itself or a coincident ion) must give a
                     // finite 1/r^3, whose contribution is then exactly zero since
                     // dx = dy = dz = 0: FP32 adds kSoft2 to r^2 (folded into the
@@ -589,7 +613,7 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *
                     av = t_;
                 }
             }
-            __syncthreads();  // all reads of src done before the next stage
+            __syncthreads();  // all reads of the stage done before the next one
         }
         // phases 1.. hand their sums to phase 0, added in phase order
         hx[tid] = ax;
@@ -781,12 +805,12 @@ void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *
 
 template <typename T>
 void launch_near(const BoxTable &bt, const double *sp, int ntot, const int2 *near, int stride, const int4 *work,
-                 int n_items, T *part, bool pot, hipStream_t st)
+                 int n_items, T *part, bool pot, int max_grid, int *queue, hipStream_t st)
 {
     if (n_items <= 0) return;
-    const int grid = std::min(n_items, 16384);
-    if (pot) k_p2p<T, true><<<grid, kP2PThreads, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part);
-    else k_p2p<T, false><<<grid, kP2PThreads, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part);
+    const int grid = std::min(n_items, max_grid);
+    if (pot) k_p2p<T, true><<<grid, kP2PThreads, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part, queue);
+    else k_p2p<T, false><<<grid, kP2PThreads, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part, queue);
 }
 
 template <typename T>
@@ -825,9 +849,9 @@ template void launch_downward<double>(const BoxTable &, int, const TreeSummary &
 template void launch_downward<float>(const BoxTable &, int, const TreeSummary &, const float *, const int2 *,
                                      const int32_t *, float *, float *, hipStream_t);
 template void launch_near<double>(const BoxTable &, const double *, int, const int2 *, int, const int4 *, int,
-                                   double *, bool, hipStream_t);
+                                   double *, bool, int, int *, hipStream_t);
 template void launch_near<float>(const BoxTable &, const double *, int, const int2 *, int, const int4 *, int, float *,
-                                  bool, hipStream_t);
+                                  bool, int, int *, hipStream_t);
 template void launch_far<double>(const BoxTable &, const double *, int, int, int, const double *, const double *,
                                   const uint32_t *, const int32_t *, const double *, const uint32_t *, double *,
                                   double *, int, hipStream_t);

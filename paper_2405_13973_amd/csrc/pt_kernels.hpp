@@ -127,10 +127,16 @@ template <typename T>
 void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_pad, const int2 *oct_slots,
                      const int32_t *parent_oct, T *L, T *part, hipStream_t st);
 // Near field over the work items into part (item x 64 x 3; with pot the
-// potential sum as a fourth component, item x 64 x 4).
+// potential sum as a fourth component, item x 64 x 4); at most max_grid
+// workgroups, which take the items from *queue (zero before the launch) or,
+// with queue NULL, stride over them.
 template <typename T>
 void launch_near(const BoxTable &bt, const double *sp, int ntot, const int2 *near, int stride, const int4 *work,
-                 int n_items, T *part, bool pot, hipStream_t st);
+                 int n_items, T *part, bool pot, int max_grid, int *queue, hipStream_t st);
+// Near-field workgroups per compute unit while the translation GEMM runs
+// beside the near field: with this many, one GEMM workgroup still fits in
+// every compute unit's LDS, whichever kernel reaches the unit first.
+constexpr int kNearPerCUConcurrent = 6;
 // Far field (L2P) + the item partials per ion into E (batch order); with phi
 // non-null also the potential per unit charge (part then holds 4 components).
 template <typename T>

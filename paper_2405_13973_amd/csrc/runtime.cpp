@@ -101,7 +101,8 @@ struct pt_ctx {
     // the near field runs on its own stream, beside the far-field chain;
     // fork / join events order it after the lists and before the L2P kernel
     hipStream_t near_stream = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_tree = nullptr, ev_p2m = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_tree = nullptr, ev_p2m = nullptr, ev_read = nullptr;
+    int num_cu = 1;  // compute units of the device
     hipEvent_t ev_near[2] = {};  // timing of the P2P kernel
     bool near_timed = false;
     int near_concurrent = -1;  // -1: by leaf size; 0 / 1: forced (PT_NEAR_CONCURRENT)
@@ -555,9 +556,41 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "scan_part", sizeof(uint32_t) * (scan_partials(std::max(scan_n, nbox)) + 1), &scan_part));
     launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, v_blk, near_pairs, child_oct, parent_oct, item_off,
                  src_items, cuts, scan_part, total + 1, st);
-    // near-field work items: their number sizes the item and partial buffers
+    // near-field work items: their number sizes the item and partial buffers.
+    // It is read back while the upward pass, which does not need it, runs: the
+    // host waits for an event right after the copy, not for the stream.
     PT_HIP(hipMemcpyAsync(ctx->h_counters, total + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    PT_HIP(hipStreamSynchronize(st));
+    PT_HIP(hipEventRecord(ctx->ev_read, st));
+    int32_t *m2l_cnt, *m2l_list, *p2p_queue;
+    void *m2l_part;
+    const int ngroup = m2l_groups(nbox - hs.level_start[2]);
+    PT_TRY(ws_get(ctx, "m2l_cnt", sizeof(int32_t) * 8, &m2l_cnt));
+    PT_TRY(ws_get(ctx, "p2p_queue", sizeof(uint64_t), &p2p_queue));
+    PT_TRY(ws_get(ctx, "m2l_list", sizeof(int32_t) * 8 * (size_t)nbox, &m2l_list));
+    PT_TRY(ws_get(ctx, "m2l_part", esz * Kp * (size_t)nbox * std::max(ngroup, 8), (char **)&m2l_part));
+    mark(ctx, 1);
+    const Tables &tb = ctx->tables;
+    // the zero rows of M and L, the M2L bucket counters and the near-field
+    // item queue, in one launch
+    ZeroRegions zr{};
+    zr.p[0] = (uint64_t *)((char *)M + esz * Kp * (size_t)nbox);
+    zr.p[1] = (uint64_t *)((char *)L + esz * Kp * (size_t)nbox);
+    zr.p[2] = (uint64_t *)m2l_cnt;
+    zr.p[3] = (uint64_t *)p2p_queue;
+    zr.n[0] = zr.n[1] = (int)(esz * Kp / 8);
+    zr.n[2] = 4;  // 8 int32 counters
+    zr.n[3] = 1;
+    launch_zero_regions(zr, st);
+    auto upward = [&](auto tag) -> pt_status {
+        using T = decltype(tag);
+        const T *m2m = sizeof(T) == sizeof(float) ? (const T *)tb.m2m_f : (const T *)tb.m2m_d;
+        PT_HIP(hipStreamWaitEvent(st, ctx->ev_p2m, 0));  // P2M (second stream)
+        launch_m2m<T>(bt, p, hs, m2m, tb.oct_slots, child_oct, (T *)M, (T *)m2l_part, st);
+        launch_m2l_bucket(bt, nbox, m2l_cnt, m2l_list, st);
+        return PT_OK;
+    };
+    PT_TRY(fp.precision == 1 ? upward(float(0)) : upward(double(0)));
+    PT_HIP(hipEventSynchronize(ctx->ev_read));
     const int n_items = (int)*(uint32_t *)ctx->h_counters;
     int4 *work;
     void *ppart;
@@ -565,32 +598,12 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     const int ncomp = phi ? 4 : 3;  // near-field partial components per target
     PT_TRY(ws_get(ctx, "p2p_part", esz * 64 * ncomp * (size_t)std::max(1, n_items), (char **)&ppart));
     launch_p2p_items(bt, dsum, nbox, near_cnt, stride, item_off, src_items, cuts, work, st);
-    int32_t *m2l_cnt, *m2l_list;
-    void *m2l_part;
-    const int ngroup = m2l_groups(nbox - hs.level_start[2]);
-    PT_TRY(ws_get(ctx, "m2l_cnt", sizeof(int32_t) * 8, &m2l_cnt));
-    PT_TRY(ws_get(ctx, "m2l_list", sizeof(int32_t) * 8 * (size_t)nbox, &m2l_list));
-    PT_TRY(ws_get(ctx, "m2l_part", esz * Kp * (size_t)nbox * std::max(ngroup, 8), (char **)&m2l_part));
-    mark(ctx, 1);
-    const Tables &tb = ctx->tables;
-    // the zero rows of M and L and the M2L bucket counters, in one launch
-    ZeroRegions zr{};
-    zr.p[0] = (uint64_t *)((char *)M + esz * Kp * (size_t)nbox);
-    zr.p[1] = (uint64_t *)((char *)L + esz * Kp * (size_t)nbox);
-    zr.p[2] = (uint64_t *)m2l_cnt;
-    zr.n[0] = zr.n[1] = (int)(esz * Kp / 8);
-    zr.n[2] = 4;  // 8 int32 counters
-    launch_zero_regions(zr, st);
     auto run = [&](auto tag) -> pt_status {
         using T = decltype(tag);
         const bool f = sizeof(T) == sizeof(float);
-        const T *m2m = f ? (const T *)tb.m2m_f : (const T *)tb.m2m_d;
         const T *m2l = f ? (const T *)tb.m2l_f : (const T *)tb.m2l_d;
         const T *l2l = f ? (const T *)tb.l2l_f : (const T *)tb.l2l_d;
         const T *rec = f ? (const T *)tb.rec_f : (const T *)tb.rec_d;
-        PT_HIP(hipStreamWaitEvent(st, ctx->ev_p2m, 0));  // P2M (second stream)
-        launch_m2m<T>(bt, p, hs, m2m, tb.oct_slots, child_oct, (T *)M, (T *)m2l_part, st);
-        launch_m2l_bucket(bt, nbox, m2l_cnt, m2l_list, st);
         // near field on its own stream, concurrently with M2L and L2L (vector
         // ALUs beside matrix cores) when leaves are large enough for the near
         // field to rival the far field; it starts once the upward pass is done
@@ -605,7 +618,12 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         }
         auto near_field = [&]() -> pt_status {
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[0], ns));
-            launch_near<T>(bt, sp, ntot, near, stride, work, n_items, (T *)ppart, phi != nullptr, ns);
+            const int max_grid = concurrent ? kNearPerCUConcurrent * ctx->num_cu : 16384;
+            // beside M2L the grid is capped and the workgroups take items from
+            // a queue; alone, one workgroup per item (no queue: its atomics
+            // would serialise over the many small items of small leaves)
+            launch_near<T>(bt, sp, ntot, near, stride, work, n_items, (T *)ppart, phi != nullptr, max_grid,
+                           concurrent ? p2p_queue : nullptr, ns);
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[1], ns));
             ctx->near_timed = ctx->timing;
             if (concurrent) PT_HIP(hipEventRecord(ctx->ev_join, ns));
@@ -711,7 +729,7 @@ static void release_ctx(pt_ctx *ctx)
     if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_tree, ctx->ev_p2m, ctx->ev_near[0], ctx->ev_near[1]})
+    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_tree, ctx->ev_p2m, ctx->ev_read, ctx->ev_near[0], ctx->ev_near[1]})
         if (e) (void)hipEventDestroy(e);
     if (ctx->near_stream) (void)hipStreamDestroy(ctx->near_stream);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -735,7 +753,10 @@ static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_tree, hipEventDisableTiming));
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_p2m, hipEventDisableTiming));
+    PT_HIP(hipEventCreateWithFlags(&ctx->ev_read, hipEventDisableTiming));
     for (auto &e : ctx->ev_near) PT_HIP(hipEventCreate(&e));
+    PT_HIP(hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    ctx->num_cu = std::max(1, ctx->num_cu);
     return PT_OK;
 }
 
