@@ -82,17 +82,28 @@ def choose_p(c, F_dir, precision, leaf, p0, target=1e-6, pmax=16):
     raise SystemExit(f"no p <= {pmax} reaches rms error {target} in {precision}")
 
 
-def timed_steps(ctx, c, steps, warmup, sync):
+def timed_steps(ctx, c, steps, warmup, sync, phases_too=True):
+    """Wall time of `steps` steps after `warmup` (uninstrumented: phase timing
+    waits for each evaluation's events before queueing the next, a host
+    synchronisation per step that plain stepping does not have), then the same
+    number of steps again with HIP-event phase timing for the per-phase and
+    per-kernel figures.  Both runs start from the state the warm-up left."""
     c.step(warmup)
+    st = c.read_state()
     sync()
-    ctx.set_timing(True)
     t0 = time.perf_counter()
     c.step(steps)
     sync()
     t1 = time.perf_counter()
-    phases, count = ctx.phase_times(with_count=True)
-    wc = ctx.work_counts()
-    ctx.set_timing(False)
+    phases, count, wc = None, 0, None
+    if phases_too:
+        c.set_state(st["pos"], st["vel"], st["step"])
+        ctx.set_timing(True)
+        c.step(steps)
+        sync()
+        phases, count = ctx.phase_times(with_count=True)
+        wc = ctx.work_counts()
+        ctx.set_timing(False)
     return t1 - t0, phases, count, wc
 
 
@@ -242,7 +253,7 @@ def bench_beams(ctx, c, cr, p, leaf, prec, steps, warmup, sync, ref_seconds):
     # Doppler shift detunes every beam
     c.step(1)
     photons = int(c.read_state()["photons"].sum())
-    el = timed_steps(ctx, c, steps, warmup, sync)[0]
+    el = timed_steps(ctx, c, steps, warmup, sync, phases_too=False)[0]
     c.set_laser(0.0)
     log(f"  beams: {steps} steps in {el * 1e3:.2f} ms ({photons} photons in the first step)")
     return {"ms_per_step": el * 1e3 / steps, "ion_steps_per_s": cr.n * steps / el,
@@ -314,11 +325,15 @@ def bench_ensemble(a, ctx, sync):
         c.set_force("fmm", a.p, a.leaf, a.precision)
     native.step_batch(cs, [a.warmup] * len(cs))
     sync()
-    ctx.set_timing(True)
     t0 = time.perf_counter()
     native.step_batch(cs, [a.steps] * len(cs))
     sync()
     el = time.perf_counter() - t0
+    # per-phase times from a few more, instrumented steps (phase timing waits
+    # for each evaluation's events, so it stays out of the timed region)
+    ctx.set_timing(True)
+    native.step_batch(cs, [3] * len(cs))
+    sync()
     phases = ctx.phase_times()
     ctx.set_timing(False)
     value = ntot * a.steps / el
@@ -454,7 +469,7 @@ def main():
             el = 0.0
             if len(leaves) > 1:
                 c.set_force("fmm", p, leaf, prec)
-                el = timed_steps(ctx, c, 10, 2, sync)[0]
+                el = timed_steps(ctx, c, 10, 2, sync, phases_too=False)[0]
                 log(f"  {prec} leaf {leaf}: p={p} {10 * cr.n / el:.4g} ion-steps/s")
             if best is None or el < best[3]:
                 best = (leaf, p, err, el)
