@@ -39,26 +39,32 @@ P2P_FLOPS_PER_PAIR = 17
 P2P_POT_FLOPS_PER_PAIR = 18
 # phase 0 includes P2M, which runs on a second stream beside the list builders
 PHASES = ["tree_lists_p2m", "m2m", "m2l_kernel", "m2l_reduce_l2l", "p2p_kernel", "l2p_partials", "total"]
-LEAF_CANDIDATES = (32, 64, 128, 256)
+# leaf sizes the tuner tries (for each the smallest p meeting the error bound,
+# then the fastest): step time depends on where a crystal's boxes are split,
+# not monotonically on the leaf size
+LEAF_CANDIDATES = (32, 64, 128, 192, 224, 256, 320, 384)
 
 
 def measured_traffic(kernel, p, leaf, precision, n):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    runs, or None when the kernel source or the workload differs from the
-    one profiled."""
+    runs (one record per profiled workload), or None when no record matches
+    the workload or the kernel source has changed since it was taken."""
     import hashlib
 
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        recs = json.load(open(os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")))["records"]
     except (OSError, ValueError, KeyError):
         return None
-    w = rec.get("workload", {})
-    if hashlib.sha256(src).hexdigest() != rec.get("sha256"):
-        return None
-    if (w.get("p"), w.get("leaf_size"), w.get("precision"), w.get("n_ions")) != (p, leaf, precision, n):
-        return None
-    return rec["hbm_bytes_per_launch"]
+    for rec in recs:
+        w = rec.get("workload", {})
+        if (w.get("p"), w.get("leaf_size"), w.get("precision"), w.get("n_ions")) != (p, leaf, precision, n):
+            continue
+        try:
+            src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        except (OSError, KeyError):
+            return None
+        return rec["hbm_bytes_per_launch"] if hashlib.sha256(src).hexdigest() == rec.get("sha256") else None
+    return None
 
 
 def log(*a):
