@@ -585,7 +585,8 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *
                         if constexpr (sizeof(T) == 4) rinv = rsqrt_t(s2 + T(kSoft2));
                         else rinv = min(rsqrt_t(s2), T(kRinvMax));
                     } else if constexpr (sizeof(T) == 4) {
-                        rinv = rsqrt_t(dx * dx + dy * dy + (dz * dz + T(kSoft2)));
+                        // nested so that r^2 is three fused multiply-adds
+                        rinv = rsqrt_t(fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, float(kSoft2)))));
                     } else {
                         rinv = min(rsqrt_t(dx * dx + dy * dy + dz * dz), T(kRinvMax));
                     }
