@@ -269,7 +269,10 @@ def bench_beams(ctx, c, cr, p, leaf, prec, steps, warmup, sync, ref_seconds):
                      "(d=5 um, w_y=2.48 um, w_z=1 mm, S0=0.5, Delta=2 pi 13.6 MHz), gamma0=2 pi 18 MHz"}
 
 
-BATCH_LEAVES = (64, 128, 256)
+BATCH_LEAVES = (64, 128, 256, 384, 512)
+# serving cannot tune while requests arrive: the leaf size the ensemble tuner
+# picks for the same range of crystal sizes (384 and 512 within 1% there)
+SERVING_LEAF = 384
 
 
 def tune_batch(ctx, cs, leaves, p_fixed, p0, precision, sync, time_it=True, target=1e-6, pmax=16):
@@ -369,7 +372,7 @@ def bench_serving(a, ctx, sync):
     # p from the error bound on the three largest requests (leaf 256 unless given)
     big = sorted(reqs, key=lambda r: -r.crystal.n)[:3]
     probe = [ctx.crystal(r.crystal.pos, r.crystal.vel, r.crystal.charge, r.crystal.mass, r.crystal.seed) for r in big]
-    a.leaf, a.p, errs = tune_batch(ctx, probe, (a.leaf or 256,), a.p, a.p0, a.precision, sync, time_it=False)
+    a.leaf, a.p, errs = tune_batch(ctx, probe, (a.leaf or SERVING_LEAF,), a.p, a.p0, a.precision, sync, time_it=False)
     for c in probe:
         c.destroy()
     srv = serving.Server(ctx, native, budget_bytes=a.budget_gb << 30, precision=a.precision, p=a.p, leaf=a.leaf,
