@@ -1,7 +1,7 @@
 """Coulomb potential and energy on the GPU vs the CPU oracle, through the C ABI.
 
 phi_i = k_e q sum_{j != i} 1/r_ij is the pair term of eq. (hamiltonian) per unit
-charge; the paper judges the FMM by the relative RMS error of eq. (rms_pot).
+charge; the paper measures the FMM by the relative RMS error of eq. (rms_pot).
 
 Bars (the same reasoning as the force tests):
   - direct potential: max_i |phi_gpu - phi_oracle| / rms_j phi_oracle <= 1e-12
