@@ -219,3 +219,24 @@ def test_serving_admission_under_a_small_budget():
     assert rep.max_resident_bytes <= budget
     assert all(d.steps == reqs[d.index].steps for d in rep.done)
     assert all(np.isfinite(d.diagnostics["energy"]) and d.diagnostics["temp_axial"] > 0 for d in rep.done)
+
+
+# ---------------------------------------------------------------- schedules
+@pytest.mark.parametrize("leaf", [32, 256])
+def test_near_field_schedules_are_bit_identical(leaf, monkeypatch):
+    """The near field runs beside M2L on a second stream (a capped grid taking work
+    items from a queue) or after it on the main stream (one workgroup per item);
+    every item writes its own partials, added in item order, so both schedules give
+    the same forces bit for bit, in both precisions."""
+    say(f"near-field schedules leaf {leaf}")
+    cr = inputs.config3(n=30000)
+    out = {}
+    for conc in ("0", "1"):
+        monkeypatch.setenv("PT_NEAR_CONCURRENT", conc)
+        with native.Context(0) as c:
+            for prec in ("mixed", "fp64"):
+                k = make(c, cr, "fmm", 11, leaf, prec)
+                out[(conc, prec)] = k.compute_forces()
+                k.destroy()
+    for prec in ("mixed", "fp64"):
+        assert np.array_equal(out[("0", prec)], out[("1", prec)]), prec
