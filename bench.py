@@ -361,6 +361,60 @@ def bench_ensemble(a, ctx, sync):
     }
 
 
+def bench_scaling(a, ctx, sync):
+    """Step time against N (the paper's scaling study, Sec. 3: ions uniform in a
+    sphere at one density for every N, initial velocities zero): FMM steps
+    (mixed, p and leaf as given, default 11 and 256) and direct-sum steps, with
+    the FMM's RMS force error against the FP64 direct sum."""
+    p, leaf = a.p or 11, a.leaf or 256
+    points = []
+    for k, n in enumerate((1000, 10000, 100000, 1000000)):
+        pos = inputs.uniform_ball(n, inputs.density_radius(n), inputs.rng(20 + k))
+        vel = np.zeros_like(pos)
+        c = ctx.crystal(pos, vel, inputs.ION_CHARGE, inputs.ION_MASS, 20 + k)
+        c.set_force("direct")
+        t0 = time.perf_counter()
+        F_dir = c.compute_forces()
+        dir_eval = time.perf_counter() - t0
+        dir_steps = 3 if n <= 100000 else 0
+        dir_ms = None
+        if dir_steps:
+            c.step(1)
+            sync()
+            t0 = time.perf_counter()
+            c.step(dir_steps)
+            sync()
+            dir_ms = (time.perf_counter() - t0) * 1e3 / dir_steps
+        c.set_state(pos, vel, 0)
+        c.set_force("fmm", p, leaf, a.precision)
+        err = rms_rel(c.compute_forces(), F_dir)
+        el = timed_steps(ctx, c, a.steps, a.warmup, sync, phases_too=False)[0]
+        c.destroy()
+        fmm_ms = el * 1e3 / a.steps
+        log(f"  N={n}: FMM {fmm_ms:.3f} ms/step (rms err {err:.2e}), direct "
+            f"{'%.3f ms/step' % dir_ms if dir_ms else '-'} (one direct force evaluation {dir_eval * 1e3:.1f} ms wall)")
+        points.append({"n_ions": n, "fmm_ms_per_step": fmm_ms, "fmm_ion_steps_per_s": n / (fmm_ms * 1e-3),
+                       "rms_rel_force_err": err, "direct_ms_per_step": dir_ms,
+                       "direct_eval_ms_wall": dir_eval * 1e3})
+    # growth over the top decade (1e5 -> 1e6); below ~1e5 ions neither path fills
+    # the GPU (the direct sum has N/512 workgroups; the FMM step's fixed launch
+    # and read-back costs, ~0.25 ms, dominate below 1e4), so smaller N understate it
+    hi, lo = points[-1], points[-2]
+    dec = math.log(hi["n_ions"] / lo["n_ions"])
+    slope = math.log(hi["fmm_ms_per_step"] / lo["fmm_ms_per_step"]) / dec
+    dslope = math.log(hi["direct_eval_ms_wall"] / lo["direct_eval_ms_wall"]) / dec
+    log(f"  growth exponent of the step time, 1e5 -> 1e6 ions: FMM {slope:.2f}, direct force evaluation {dslope:.2f}")
+    return {"metric": "scaling: step time vs N at fixed density (uniform sphere, zero initial velocity)",
+            "value": points[-1]["fmm_ion_steps_per_s"], "unit": "ion-steps/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": points[-1]["fmm_ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if a.precision == "mixed" else "f64",
+            "data": "synthetic",
+            "config": {"workload": f"uniform spheres at 1000 ions per (100 um)^3, N = 1e3..1e6, FMM p={p} leaf {leaf} "
+                                   f"({a.precision}), B=4.5 T, f_z=1.5 MHz, dt=1 ns", "p": p, "leaf_size": leaf},
+            "points": points, "fmm_exponent_1e5_1e6": slope, "direct_exponent_1e5_1e6": dslope,
+            "note": "exponents over the top decade; below ~1e5 ions neither path fills the GPU"}
+
+
 def bench_serving(a, ctx, sync):
     """Serving stream: Poisson arrivals, continuous batching, admission by HBM footprint."""
     from paper_2405_13973_amd import serving
@@ -421,8 +475,9 @@ def main():
     ap.add_argument("--no-beams", action="store_true", help="skip the beam-mode laser measurement")
     ap.add_argument("--no-diagnostics", action="store_true", help="skip the rotating-frame diagnostics measurement")
     ap.add_argument("--no-relaxation", action="store_true", help="skip the artificial-damping relaxation")
-    ap.add_argument("--workload", choices=["config3", "ensemble", "serving"], default="config3",
-                    help="config3: 1e5-ion crystal (default); ensemble: 256 crystals batched; serving: request stream")
+    ap.add_argument("--workload", choices=["config3", "ensemble", "serving", "scaling"], default="config3",
+                    help="config3: 1e5-ion crystal (default); ensemble: 256 crystals batched; serving: request stream; "
+                         "scaling: step time against N")
     ap.add_argument("--p", type=int, default=0,
                     help="expansion degree for the ensemble / serving workloads (0: smallest meeting the bound)")
     ap.add_argument("--crystals", type=int, default=256)
@@ -456,7 +511,7 @@ def main():
 
     if a.workload != "config3":
         ctx = native.Context(0, hbm_budget=(a.budget_gb << 30) + (4 << 30), stream=stream.cuda_stream)
-        out = bench_ensemble(a, ctx, sync) if a.workload == "ensemble" else bench_serving(a, ctx, sync)
+        out = {"ensemble": bench_ensemble, "serving": bench_serving, "scaling": bench_scaling}[a.workload](a, ctx, sync)
         ctx.close()
         print(json.dumps(out), flush=True)
         return
