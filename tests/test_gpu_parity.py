@@ -165,6 +165,35 @@ def test_tree_bit_exact_clumps(ctx):
     assert list(wc[:4]) == [len(R["level"]), int(R["is_leaf"].sum()), len(R["v_src"]), near_pairs]
 
 
+def test_tree_depth_limit_with_coincident_ions(ctx):
+    """Two stacks of 20 identical positions inside a ball: the tree cannot separate them, so
+    it runs to its depth limit (level 16) and keeps leaves above the leaf size there; the
+    zero-separation pairs contribute nothing (the oracle's pin of the same case)."""
+    say("tree depth limit, coincident ions")
+    pos = np.concatenate([np.full((20, 3), 1e-5), np.zeros((20, 3)), inputs.uniform_ball(200, 5e-5, inputs.rng(17))])
+    c = ctx.crystal(pos, np.zeros_like(pos), Q, M)
+    c.set_force("fmm", 6, 4, "fp64")
+    F = c.compute_forces()
+    T = c.export_tree()
+    c.set_force("fmm", 6, 4, "mixed")
+    Fm = c.compute_forces()
+    c.destroy()
+    R = O.tree(pos, 4)
+    assert R["level"].max() == 16
+    for k in ("key", "perm", "level", "parent", "ion_begin", "ion_end", "coords", "is_leaf", "v_off", "v_src",
+              "near_off", "near_src"):
+        assert np.array_equal(T[k], R[k]), k
+    ref = O.fmm_coulomb(pos, Q, 6, 4)
+    err = rel_max(F, ref)
+    say(f"   fp64 max err / rms = {err:.3e}")
+    assert err <= 1e-11
+    assert np.isfinite(Fm).all()
+    # against the oracle FMM of the same p and leaf, so only the FP32 rounding remains
+    rms = math.sqrt(((Fm - ref) ** 2).sum() / (ref ** 2).sum())
+    say(f"   mixed rms rel err vs oracle FMM = {rms:.3e}")
+    assert rms < 1e-5
+
+
 # ---------------------------------------------------------------- FMM
 @pytest.mark.parametrize("n,p,s", [(1000, 8, 32), (2000, 4, 16), (1500, 12, 64), (300, 6, 300)])
 def test_fmm_fp64_matches_oracle_fmm(ctx, n, p, s):
