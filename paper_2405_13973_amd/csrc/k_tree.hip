@@ -309,26 +309,75 @@ __global__ void k_gather(const CrystalDev *__restrict__ cs, const int32_t *__res
 
 // --------------------------------------------------------------- octree
 
-// Range [lo, hi) of the level-l box holding slot k, narrowed from the
-// range of its parent; keys are sorted so the box is the run of equal
-// (key >> shift) values around k.
-__device__ inline void narrow(const uint64_t *__restrict__ keys, int k, int shift, int &lo, int &hi)
+// First level (1..kMaxLevel) at which two 48-bit Morton keys of one crystal
+// differ, or kMaxLevel + 1 if they are equal.
+__host__ __device__ inline int first_diff_level(uint64_t a, uint64_t b)
 {
-    const uint64_t pre = keys[k] >> shift;
-    int a = lo, b = k;  // first index in [lo, k] with equal prefix
-    while (a < b) {
-        const int m = (a + b) >> 1;
-        if ((keys[m] >> shift) < pre) a = m + 1;
-        else b = m;
+    const uint64_t x = (a ^ b) & 0xFFFFFFFFFFFFull;
+    return x == 0 ? kMaxLevel + 1 : kMaxLevel - (63 - __builtin_clzll(x)) / 3;
+}
+
+// The levels at which sorted slot k is the first ion of a box (bit l), and the
+// end of each such box (end[l]), for the crystal occupying [lo_c, hi_c).
+//   - k starts a run of equal level-l prefixes for every l >= L, L the first
+//     level where keys[k - 1] and keys[k] differ (0 at the crystal's start);
+//   - that run is a box iff its parent run holds more than leaf ions (boxes
+//     split iff they exceed leaf), which for l = L is decided within leaf
+//     slots on either side of k, and for l > L (where the parent run starts
+//     at k) by whether slot k + leaf shares k's level-(l - 1) prefix;
+//   - a box's end is the first slot past k with a larger prefix.
+__host__ __device__ inline uint32_t slot_box_levels(const uint64_t *__restrict__ keys, int k, int lo_c, int hi_c,
+                                                    int leaf, int32_t *__restrict__ end)
+{
+    const uint64_t key = keys[k];
+    int L = 0;
+    if (k > lo_c) {
+        L = first_diff_level(keys[k - 1], key);
+        if (L > kMaxLevel) return 0u;
+        // the level-(L - 1) run around k: [a, c) within [k - leaf, k + leaf]
+        const int sh = 3 * (kMaxLevel - L + 1);
+        const uint64_t pre = key >> sh;
+        int a = k - leaf > lo_c ? k - leaf : lo_c, a1 = k - 1;  // first with prefix pre (k - 1 has it)
+        int c = k + 1, c1 = hi_c < k + leaf + 1 ? hi_c : k + leaf + 1;  // first with a larger prefix, or c1
+        while (a < a1 || c < c1) {
+            if (a < a1) {
+                const int m = (a + a1) >> 1;
+                if ((keys[m] >> sh) < pre) a = m + 1;
+                else a1 = m;
+            }
+            if (c < c1) {
+                const int m = (c + c1) >> 1;
+                if ((keys[m] >> sh) <= pre) c = m + 1;
+                else c1 = m;
+            }
+        }
+        if (c - a <= leaf) return 0u;  // the parent is a leaf (or k is inside one)
     }
-    int c = k + 1, d = hi;  // first index in [k+1, hi) with a larger prefix
-    while (c < d) {
-        const int m = (c + d) >> 1;
-        if ((keys[m] >> shift) <= pre) c = m + 1;
-        else d = m;
+    // deeper levels: boxes down to D, the first level where keys[k + leaf] differs
+    const int D = k + leaf < hi_c ? first_diff_level(key, keys[k + leaf]) : 0;
+    const int lmax = D > L ? (D < kMaxLevel ? D : kMaxLevel) : L;
+    uint32_t mask = 0u;
+    int bound = hi_c;
+    for (int l = L; l <= lmax; ++l) {
+        mask |= 1u << l;
+        if (l == 0) {
+            end[0] = hi_c;
+            continue;
+        }
+        // the run holds slot k + leaf for l < D, not for l >= D
+        const int sh = 3 * (kMaxLevel - l);
+        const uint64_t pre = key >> sh;
+        int c = l < D ? k + leaf + 1 : k + 1;
+        int c1 = l < D ? bound : (bound < k + leaf ? bound : k + leaf);
+        while (c < c1) {
+            const int m = (c + c1) >> 1;
+            if ((keys[m] >> sh) <= pre) c = m + 1;
+            else c1 = m;
+        }
+        end[l] = c;
+        bound = c;
     }
-    lo = a;
-    hi = c;
+    return mask;
 }
 
 // For every sorted slot: the levels at which it is the first ion of an
@@ -346,17 +395,8 @@ __global__ __launch_bounds__(256) void k_tree_levels(const CrystalDev *__restric
     uint32_t mask = 0u;
     if (k < ntot) {
         const int c = (int)(keys[k] >> 48);
-        int lo = cs[c].ion_off, hi = lo + cs[c].n;
-        int32_t *end = box_end + (size_t)k * (kMaxLevel + 1);
-        mask = (lo == k) ? 1u : 0u;
-        if (lo == k) end[0] = hi;
-        for (int l = 1; l <= kMaxLevel && hi - lo > leaf_size; ++l) {
-            narrow(keys, k, 3 * (kMaxLevel - l), lo, hi);
-            if (lo == k) {
-                mask |= 1u << l;
-                end[l] = hi;
-            }
-        }
+        const int lo = cs[c].ion_off;
+        mask = slot_box_levels(keys, k, lo, lo + cs[c].n, leaf_size, box_end + (size_t)k * (kMaxLevel + 1));
         rep_mask[k] = mask;
     }
     const int w = threadIdx.x >> 6;
