@@ -369,6 +369,20 @@ __host__ __device__ inline uint32_t slot_box_levels(const uint64_t *__restrict__
         const uint64_t pre = key >> sh;
         int c = l < D ? k + leaf + 1 : k + 1;
         int c1 = l < D ? bound : (bound < k + leaf ? bound : k + leaf);
+        // wide ranges (the large boxes' representatives, the kernel's longest
+        // chains): 8-way steps, 7 probes loaded at once; then bisection
+        while (c1 - c > 64) {
+            const int st = (c1 - c + 7) / 8;
+            uint64_t pk[7];
+#pragma unroll
+            for (int i = 0; i < 7; ++i) pk[i] = keys[c + (i + 1) * st - 1];  // all < c1
+            int nf = 0;
+#pragma unroll
+            for (int i = 0; i < 7; ++i) nf += (pk[i] >> sh) <= pre;
+            const int c0 = c;
+            c = c0 + nf * st;
+            if (nf < 7) c1 = c0 + (nf + 1) * st - 1;
+        }
         while (c < c1) {
             const int m = (c + c1) >> 1;
             if ((keys[m] >> sh) <= pre) c = m + 1;
