@@ -31,9 +31,10 @@
 
 /* Trap description: B along +z, axial frequency omega_z (rad/s), rotating
  * wall strength delta and rotation omega_r (rad/s).  damping (1/s, 0 = off):
- * the artificial damping of the paper's outlook -- once per step, after the
- * kick, the velocity relative to the frame turning at omega_r (eq. rotation)
- * is multiplied by exp(-damping dt). */
+ * the artificial damping of the paper's outlook -- the velocity relative to
+ * the frame turning at omega_r (eq. rotation) is multiplied by
+ * exp(-damping dt / 2) just before the kick and again just after it, so one
+ * step damps it by exp(-damping dt) in two symmetric halves. */
 typedef struct {
     double B;
     double omega_z;

@@ -192,6 +192,21 @@ def test_direct_newton_third_law():
     assert np.linalg.norm(F.sum(axis=0)) / np.linalg.norm(F, axis=1).sum() < 1e-13
 
 
+def test_direct_sampled_equals_full():
+    """The sampled direct sum (the reference of the full-size GPU checks) equals
+    the full sum at the sampled targets, bit for bit: unsorted and repeated
+    indices, the first and last ion, and a coincident pair (zero separation left
+    out, so both members still feel every other ion)."""
+    g = inputs.rng(31)
+    pos = inputs.uniform_ball(700, 1e-4, g)
+    pos[123] = pos[456]
+    F = O.coulomb_direct(pos, Q)
+    idx = np.array([699, 0, 456, 123, 17, 17, 350], dtype=np.int32)
+    Fs = O.coulomb_direct_sampled(pos, Q, idx)
+    np.testing.assert_array_equal(Fs, F[idx])
+    assert np.all(np.isfinite(Fs)) and np.linalg.norm(Fs[2] - Fs[3]) == 0.0
+
+
 def test_gauss_sphere_interior_field():
     """A uniformly charged ball: interior field k_e Q r / R^3, radial (Gauss's law).
     Lattice ions fill the ball; the discreteness error is a few (a/R)."""
