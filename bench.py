@@ -32,11 +32,15 @@ from paper_2405_13973_amd import inputs, native  # noqa: E402
 
 METRIC = "ion-steps/s at N=1e5, RMS rel force error≤1e-6 vs FP64; p99 latency mixed stream"
 PEAK = {"mfma_fp32": 157.3, "mfma_fp64": 78.6, "valu_fp32": 157.3, "valu_fp64": 78.6}
-# Arithmetic of one near-field pair as the P2P kernel performs it: 3 sub
-# (offset), 3 mul + 2 add (r^2), 1 rsqrt, 2 mul (r^-3), 3 mul + 3 add (field).
-P2P_FLOPS_PER_PAIR = 17
+# Algorithmic flops of one near-field pair by the measurement convention of
+# the method's cost model: 3 sub (separation), 3 FMA for r^2 (6 flops), 1
+# rsqrt, 3 mul for r^-3 q... counted as 20 in all.  The kernel itself issues
+# 17 arithmetic operations per pair (3 sub, 3 FMA, 1 rsqrt, 2 mul, 3 mul +
+# 3 add); both figures are reported.
+P2P_FLOPS_PER_PAIR = 20
+P2P_ISSUED_FLOPS_PER_PAIR = 17
 # with the potential: one add more (the 1/r sum)
-P2P_POT_FLOPS_PER_PAIR = 18
+P2P_POT_FLOPS_PER_PAIR = 21
 # phase 0 includes P2M, which runs on a second stream beside the list builders
 PHASES = ["tree_lists_p2m", "m2m", "m2l_kernel", "m2l_reduce_l2l", "p2p_kernel", "l2p_partials", "total"]
 # leaf sizes the tuner tries (for each the smallest p meeting the error bound,
@@ -89,34 +93,63 @@ def choose_p(c, F_dir, precision, leaf, p0, target=1e-6, pmax=16):
 
 
 def timed_steps(ctx, c, steps, warmup, sync, phases_too=True):
-    """Wall time of `steps` steps after `warmup` (uninstrumented: phase timing
-    waits for each evaluation's events before queueing the next, a host
-    synchronisation per step that plain stepping does not have), then the same
-    number of steps again with HIP-event phase timing for the per-phase and
-    per-kernel figures.  Both runs start from the state the warm-up left."""
+    """Wall time of `steps` steps after `warmup`.  With phases_too the timed
+    region itself carries the HIP-event phase timing (the library keeps the
+    event sets of up to 64 evaluations in flight, so the timing adds no host
+    wait), and the same steps are run again from the same state without events
+    for comparison.  Returns (seconds, phases, count, work counts, seconds of
+    the uninstrumented run)."""
     c.step(warmup)
     st = c.read_state()
     sync()
+    if phases_too:
+        ctx.set_timing(True)
     t0 = time.perf_counter()
     c.step(steps)
     sync()
     t1 = time.perf_counter()
-    phases, count, wc = None, 0, None
+    phases, count, wc, plain = None, 0, None, None
     if phases_too:
-        c.set_state(st["pos"], st["vel"], st["step"])
-        ctx.set_timing(True)
-        c.step(steps)
-        sync()
         phases, count = ctx.phase_times(with_count=True)
         wc = ctx.work_counts()
         ctx.set_timing(False)
-    return t1 - t0, phases, count, wc
+        end = c.read_state()
+        c.set_state(st["pos"], st["vel"], st["step"])
+        sync()
+        t2 = time.perf_counter()
+        c.step(steps)
+        sync()
+        plain = time.perf_counter() - t2
+        c.set_state(end["pos"], end["vel"], end["step"])
+    return t1 - t0, phases, count, wc, plain
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def omp_threads(k):
+    """Sets the OpenMP thread count of this process (the oracle's runtime)."""
+    import ctypes
+
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(k))
+        return True
+    except OSError:
+        return False
 
 
 def cpu_baseline(cr, p, leaf, F_dir_gpu):
-    """The FP64 CPU oracle, as it stands, on the host cores: one full FMM step
-    of the same crystal (same p and leaf size).  Also ties the GPU direct sum
-    used as the accuracy reference to the oracle on sampled ions."""
+    """The FP64 CPU oracle, as it stands, on the host cores: full FMM steps of
+    the same crystal (same p and leaf size) on every thread, and one step on one
+    core.  Also ties the GPU direct sum used as the accuracy reference to the
+    oracle on sampled ions."""
     from oracle import oracle as O
 
     idx = np.linspace(0, cr.n - 1, 48).astype(np.int32)
@@ -140,9 +173,20 @@ def cpu_baseline(cr, p, leaf, F_dir_gpu):
     O.fmm_potential(cr.pos, cr.charge, p, leaf)
     pel = time.perf_counter() - t0
     log(f"  oracle potential: {pel:.1f} s for {cr.n} ions")
+    one = None
+    if omp_threads(1):
+        t0 = time.perf_counter()
+        O.run(cr.pos, cr.vel, cr.charge, cr.mass, cr.trap(), cr.dt, 1, method="fmm", p=p, leaf_size=leaf)
+        one = time.perf_counter() - t0
+        omp_threads(cores)
+        log(f"  oracle: 1 FMM step on 1 core in {one:.1f} s")
     return {"value": cr.n * steps / el, "unit": "ion-steps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
             "sample": f"{steps} full FP64 FMM steps (p={p}, leaf {leaf}) of the same {cr.n}-ion crystal, "
-                      f"{el:.1f} s wall; direct sum checked on 48 sampled ions (max err/rms {dev:.1e})",
+                      f"{el:.1f} s wall on {cores} threads; direct sum checked on 48 sampled ions "
+                      f"(max err/rms {dev:.1e})",
+            "one_core_ion_steps_per_s": cr.n / one if one else None,
+            "one_core_sample": f"1 full FP64 FMM step on 1 core, {one:.1f} s wall" if one else None,
             "potential_ion_evals_per_s": cr.n / pel,
             "potential_sample": f"one FP64 FMM potential evaluation of all {cr.n} ions, {pel:.1f} s wall"}
 
@@ -270,6 +314,8 @@ def bench_beams(ctx, c, cr, p, leaf, prec, steps, warmup, sync, ref_seconds):
 
 
 BATCH_LEAVES = (64, 128, 256, 384, 512)
+# steps per crystal of the ensemble configuration (config 4)
+ENSEMBLE_STEPS = 500
 # serving cannot tune while requests arrive: the leaf size the ensemble tuner
 # picks for the same range of crystal sizes (384 and 512 within 1% there)
 SERVING_LEAF = 384
@@ -475,6 +521,10 @@ def main():
     ap.add_argument("--no-beams", action="store_true", help="skip the beam-mode laser measurement")
     ap.add_argument("--no-diagnostics", action="store_true", help="skip the rotating-frame diagnostics measurement")
     ap.add_argument("--no-relaxation", action="store_true", help="skip the artificial-damping relaxation")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 256-crystal ensemble leg (config 4)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg (config 5)")
+    ap.add_argument("--serving-requests", type=int, default=120,
+                    help="requests of the serving leg of the default run (the first ones of the config-5 stream)")
     ap.add_argument("--workload", choices=["config3", "ensemble", "serving", "scaling"], default="config3",
                     help="config3: 1e5-ion crystal (default); ensemble: 256 crystals batched; serving: request stream; "
                          "scaling: step time against N")
@@ -485,7 +535,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=50, help="serving: steps per tick")
     ap.add_argument("--budget-gb", type=int, default=64, help="serving: HBM budget for resident crystals")
     ap.add_argument("--roofline", choices=["auto", "m2l", "p2p"], default="auto",
-                    help="kernel of the roofline entry (auto: P2P for leaves >= 128 ions, else M2L)")
+                    help="kernel of the roofline entry (auto: the longer of the two in the timed region)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of MIB MiB first (reference kernel for HBM byte counters)")
     a = ap.parse_args()
@@ -542,18 +592,24 @@ def main():
     results = {}
     forms = [a.precision] + ([] if a.no_fp64_compare or a.precision == "fp64" else ["fp64"])
     for prec in forms:
+        # each form at its own best leaf size (the same candidates, the same bound)
         leaves = (a.leaf,) if a.leaf else LEAF_CANDIDATES
-        if prec != a.precision:
-            leaves = (results[a.precision]["leaf"],)
         leaf, p, err = tune(prec, leaves)
         c.set_state(cr.pos, cr.vel, 0)
         c.set_force("fmm", p, leaf, prec)
         sync()
-        el, phases, count, wc = timed_steps(ctx, c, a.steps, a.warmup, sync)
-        results[prec] = dict(p=p, leaf=leaf, err=err, seconds=el, phases=phases, count=count, wc=wc)
+        el, phases, count, wc, plain = timed_steps(ctx, c, a.steps, a.warmup, sync)
+        # the accuracy bound on the state the timed steps ended on (the crystal
+        # expands from its initial lattice, so its tree changes while timed)
+        c.set_force("direct")
+        F_end = c.compute_forces()
+        c.set_force("fmm", p, leaf, prec)
+        err_end = rms_rel(c.compute_forces(), F_end)
+        results[prec] = dict(p=p, leaf=leaf, err=err, err_end=err_end, seconds=el, phases=phases, count=count, wc=wc,
+                             plain=plain)
         log(f"  {prec}: p={p} leaf={leaf} {a.steps} steps in {el * 1e3:.2f} ms -> {cr.n * a.steps / el:.4g} "
-            f"ion-steps/s; phases(ms) " + " ".join(f"{k} {v:.3f}" for k, v in zip(PHASES, phases)) +
-            f" over {count} evals")
+            f"ion-steps/s (without events {plain * 1e3:.2f} ms); rms err start {err:.2e} end {err_end:.2e}; "
+            f"phases(ms) " + " ".join(f"{k} {v:.3f}" for k, v in zip(PHASES, phases)) + f" over {count} evals")
 
     # direct-sum rate on the same crystal, for the FMM/direct comparison
     c.set_force("direct")
@@ -569,18 +625,23 @@ def main():
     fp32 = a.precision == "mixed"
     m2l_tflops = 2.0 * K * K * main_r["wc"][2] / (ph[2] * 1e-3) / 1e12
     p2p_tflops = P2P_FLOPS_PER_PAIR * main_r["wc"][3] / (ph[4] * 1e-3) / 1e12
-    # roofline of the dominant kernel: M2L (matrix cores) or P2P (vector ALUs)
-    # auto: the near field for leaves of 128 ions or more (the larger work, and
-    # the one the M2L kernel runs beside), else M2L
-    if a.roofline == "m2l" or (a.roofline == "auto" and leaf < 128):
-        kernel, bound, achieved = "m2l", "mfma", m2l_tflops
-        peak = PEAK["mfma_fp32" if fp32 else "mfma_fp64"]
-        algorithmic = f"2 K^2 flops per M2L pair, K=(p+1)^2={K}, {int(main_r['wc'][2])} pairs per launch"
-    else:
-        kernel, bound, achieved = "p2p", "alu", p2p_tflops
-        peak = PEAK["valu_fp32" if fp32 else "valu_fp64"]
-        algorithmic = (f"{P2P_FLOPS_PER_PAIR} flops per near-field pair, {int(main_r['wc'][3])} ordered pairs "
-                       f"(i != j) per launch")
+    rooflines = {
+        "m2l": {"bound": "mfma", "kernel": "m2l", "kernel_ms": float(ph[2]), "achieved": m2l_tflops,
+                "peak": PEAK["mfma_fp32" if fp32 else "mfma_fp64"], "unit": "TFLOP/s",
+                "traffic": measured_traffic("m2l", p, leaf, a.precision, cr.n),
+                "algorithmic": f"2 K^2 flops per M2L pair, K=(p+1)^2={K}, {int(main_r['wc'][2])} pairs per launch"},
+        "p2p": {"bound": "alu", "kernel": "p2p", "kernel_ms": float(ph[4]), "achieved": p2p_tflops,
+                "peak": PEAK["valu_fp32" if fp32 else "valu_fp64"], "unit": "TFLOP/s",
+                "traffic": measured_traffic("p2p", p, leaf, a.precision, cr.n),
+                "algorithmic": f"{P2P_FLOPS_PER_PAIR} flops per near-field pair (the kernel issues "
+                               f"{P2P_ISSUED_FLOPS_PER_PAIR}), {int(main_r['wc'][3])} ordered pairs (i != j) per launch",
+                "issued_achieved": P2P_ISSUED_FLOPS_PER_PAIR * main_r["wc"][3] / (ph[4] * 1e-3) / 1e12},
+    }
+    for r in rooflines.values():
+        r["frac"] = r["achieved"] / r["peak"]
+    # the dominant kernel: the longer of the two, by its measured time in the
+    # timed region (or the one asked for)
+    kernel = a.roofline if a.roofline != "auto" else max(rooflines, key=lambda k: rooflines[k]["kernel_ms"])
     value = cr.n * a.steps / main_r["seconds"]
     out = {
         "metric": METRIC,
@@ -599,16 +660,14 @@ def main():
             "workload": f"{cr.n} ions, 5%-jittered cubic lattice in a (400,400,800) um prolate ellipsoid, "
                         f"B=4.5 T, f_z=1.5 MHz, dt=1 ns, FMM p={p} leaf {leaf} ({a.precision})",
             "n_ions": cr.n, "p": p, "leaf_size": leaf, "precision": a.precision,
-            "rms_rel_force_err": main_r["err"],
+            "rms_rel_force_err": main_r["err"], "rms_rel_force_err_after_timed_steps": main_r["err_end"],
         },
-        "roofline": {
-            "bound": bound, "kernel": kernel, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": measured_traffic(kernel, p, leaf, a.precision, cr.n),
-            "algorithmic": algorithmic,
-        },
+        "roofline": rooflines[kernel],
         "details": {
             "force_evals_per_s": 1e3 / ph[6],
             "phase_ms": {k: float(v) for k, v in zip(PHASES, ph)},
+            "rooflines": rooflines,
+            "ms_per_step_without_events": main_r["plain"] * 1e3 / a.steps,
             "direct_sum_ms": float(dir_ms),
             "boxes": int(main_r["wc"][0]), "leaves": int(main_r["wc"][1]), "m2l_pairs": int(main_r["wc"][2]),
             "p2p_pairs": int(main_r["wc"][3]),
@@ -620,7 +679,9 @@ def main():
         f = results["fp64"]
         out["details"]["fp64_ion_steps_per_s"] = cr.n * a.steps / f["seconds"]
         out["details"]["fp64_p"] = f["p"]
+        out["details"]["fp64_leaf_size"] = f["leaf"]
         out["details"]["fp64_rms_rel_force_err"] = f["err"]
+        out["details"]["fp64_rms_rel_force_err_after_timed_steps"] = f["err_end"]
         out["details"]["mixed_speedup_vs_fp64"] = f["seconds"] / main_r["seconds"]
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cr, p, leaf, F_dir)
@@ -633,9 +694,19 @@ def main():
         out["diagnostics"] = bench_diagnostics(ctx, c, cr, p, leaf, a.precision, sync)
     if not a.no_relaxation:
         out["relaxation"] = bench_relaxation(ctx, a.precision, sync)
-        if "cpu_baseline" in out:
-            out["potential"]["gpu_over_cpu"] = (out["potential"]["ion_evals_per_s"] /
-                                                out["cpu_baseline"]["potential_ion_evals_per_s"])
+    if "cpu_baseline" in out and "potential" in out:
+        out["potential"]["gpu_over_cpu"] = (out["potential"]["ion_evals_per_s"] /
+                                            out["cpu_baseline"]["potential_ion_evals_per_s"])
+    c.destroy()
+    if not a.no_ensemble:
+        e = argparse.Namespace(**vars(a))
+        e.steps, e.warmup, e.leaf, e.p = ENSEMBLE_STEPS, 3, SERVING_LEAF, 0
+        out["ensemble"] = bench_ensemble(e, ctx, sync)
+    if not a.no_serving:
+        s_ = argparse.Namespace(**vars(a))
+        s_.requests, s_.leaf, s_.p = a.serving_requests, SERVING_LEAF, 0
+        out["serving"] = bench_serving(s_, ctx, sync)
+        out["latency_s"] = out["serving"]["latency_s"]
     ctx.close()
     print(json.dumps(out), flush=True)
 

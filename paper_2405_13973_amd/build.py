@@ -38,8 +38,20 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str, extra) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """True when obj is missing or older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    deps.append(os.path.join(ROOT, "include", "penning.h"))
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def _compile(src: str, extra, force: bool = True) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    if not force and not _stale(src, obj):
+        return obj
     lang = ["-x", "hip"]
     cmd = [hipcc()] + lang + HIP_FLAGS + extra + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -48,12 +60,14 @@ def _compile(src: str, extra) -> str:
     return obj
 
 
-def build(jobs: int = 8, debug: bool = False, verbose: bool = False) -> str:
+def build(jobs: int = 8, debug: bool = False, verbose: bool = False, force: bool = True) -> str:
+    """Compile every source (force) or only those older than their object
+    files' sources and headers (force=False), then link."""
     os.makedirs(OBJ, exist_ok=True)
     extra = ["-g"] if debug else []
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, extra), srcs))
+        objs = list(ex.map(lambda s: _compile(s, extra, force), srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -69,5 +83,6 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("--debug", action="store_true")
+    ap.add_argument("--changed", action="store_true", help="recompile only sources changed since their objects")
     a = ap.parse_args()
-    print(build(a.jobs, a.debug, verbose=True))
+    print(build(a.jobs, a.debug, verbose=True, force=not a.changed))

@@ -55,8 +55,10 @@ __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t v0, uint64_t v1, i
     if (i < n_pairs * 6) p[i] = (i % 6) < 3 ? v0 : v1;
 }
 
-// Optional half drift, then per-crystal min/max of x, y, z (ordered-integer
-// atomics; min/max is exact, so the result does not depend on the order).
+// Optional half drift of the state into the working copy (positions only
+// are copied without the drift), then per-crystal min/max of x, y, z
+// (ordered-integer atomics; min/max is exact, so the result does not depend
+// on the order).
 __global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
                              int do_drift, unsigned long long *__restrict__ bbox_all, int bstride)
 {
@@ -70,18 +72,20 @@ __global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *_
         const CrystalDev &cd = cs[c];
         const int i = g - cd.ion_off;
         const int n = cd.n;
-        double *s = cd.state;
+        const double *s = cd.state;
+        double *m = cd.mid;
         double x = s[i], y = s[n + i], z = s[2 * n + i];
         if (do_drift) {
             double vx = s[3 * n + i], vy = s[4 * n + i];
             const double vz = s[5 * n + i];
             u0_half(cd, x, y, z, vx, vy, vz);
-            s[i] = x;
-            s[n + i] = y;
-            s[2 * n + i] = z;
-            s[3 * n + i] = vx;
-            s[4 * n + i] = vy;
+            m[3 * n + i] = vx;
+            m[4 * n + i] = vy;
+            m[5 * n + i] = vz;
         }
+        m[i] = x;
+        m[n + i] = y;
+        m[2 * n + i] = z;
         v[0] = dbl_to_ordered(x);
         v[1] = dbl_to_ordered(y);
         v[2] = dbl_to_ordered(z);
@@ -204,7 +208,7 @@ __global__ void k_keys(const CrystalDev *__restrict__ cs, const int32_t *__restr
     const RootCube r = roots[c];
     uint32_t q[3];
     for (int d = 0; d < 3; ++d) {
-        double f = floor((cd.state[d * n + i] - r.o[d]) * r.S);
+        double f = floor((cd.mid[d * n + i] - r.o[d]) * r.S);
         if (!(f >= 0.0)) f = 0.0;
         if (f > 65535.0) f = 65535.0;
         q[d] = (uint32_t)f;
@@ -227,9 +231,10 @@ __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *_
     const CrystalDev &cd = cs[c];
     const int i = g - cd.ion_off;
     const int n = cd.n;
+    const double *m = cd.mid;
     double *s = cd.state;
-    double x = s[i], y = s[n + i], z = s[2 * n + i];
-    double vx = s[3 * n + i], vy = s[4 * n + i], vz = s[5 * n + i];
+    double x = m[i], y = m[n + i], z = m[2 * n + i];
+    double vx = m[3 * n + i], vy = m[4 * n + i], vz = m[5 * n + i];
     // artificial damping, first half: the velocity relative to the rigid
     // clockwise rotation omega_r (y, -x, 0) (at rest in the rotating frame)
     // shrinks by exp(-damping dt / 2)
@@ -351,6 +356,12 @@ __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *_
     s[3 * n + i] = vx;
     s[4 * n + i] = vy;
     s[5 * n + i] = vz;
+    // a non-finite value is flagged for the host, which reports it at its
+    // next synchronising call (plain stores: every writer writes 1)
+    if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) && isfinite(vz))) {
+        *cd.nonfinite = 1;
+        *cd.ctx_nonfinite = 1;
+    }
 }
 
 // Direct Coulomb field E_i = sum_{j != i} (x_i - x_j)/|x_i - x_j|^3 (FP64);
@@ -373,7 +384,7 @@ __global__ __launch_bounds__(kDirTB) void k_direct(const CrystalDev *__restrict_
     const int c = blk_crystal[blockIdx.x];
     const CrystalDev &cd = cs[c];
     const int n = cd.n;
-    const double *s = cd.state;
+    const double *s = cd.mid;
     double xi[kDirT], yi[kDirT], zi[kDirT], ax[kDirT], ay[kDirT], az[kDirT], av[kDirT];
     int ti[kDirT];
 #pragma unroll

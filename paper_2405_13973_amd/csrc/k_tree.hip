@@ -302,9 +302,9 @@ __global__ void k_gather(const CrystalDev *__restrict__ cs, const int32_t *__res
     const int g = (int)vals[k];
     const CrystalDev &cd = cs[ion_crystal[g]];
     const int i = g - cd.ion_off;
-    sp[k] = cd.state[i];
-    sp[ntot + k] = cd.state[cd.n + i];
-    sp[2 * ntot + k] = cd.state[2 * cd.n + i];
+    sp[k] = cd.mid[i];
+    sp[ntot + k] = cd.mid[cd.n + i];
+    sp[2 * ntot + k] = cd.mid[2 * cd.n + i];
 }
 
 // --------------------------------------------------------------- octree

@@ -51,7 +51,14 @@ struct BeamDev {
 
 struct CrystalDev {
     double *state;        // 6 n doubles, see above
+    // Working copy of the state for the current evaluation, same layout:
+    // the first half drift writes here, every kernel up to the kick reads
+    // here, and only the kick writes the crystal's own state, so a step that
+    // fails before its kick leaves the state as it was.
+    double *mid;
     int32_t *photons;     // n
+    int32_t *nonfinite;   // set to 1 by the kick when it produces a non-finite value
+    int32_t *ctx_nonfinite;  // the same, one word for the whole context
     int32_t n;
     int32_t ion_off;      // first batch index of this crystal
     // integrator (host-computed in FP64)

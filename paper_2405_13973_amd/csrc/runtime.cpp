@@ -86,11 +86,16 @@ struct pt_crystal {
     int64_t step = 0;
     double *d_state = nullptr;   // 6 n
     int32_t *d_photons = nullptr;
+    int32_t *d_nonfinite = nullptr;  // set by the kick when the state turns non-finite
 };
 
 // Timed phases of a force evaluation (events 0..6 bracket them): sort+tree+
 // lists, P2M+M2M, M2L, M2L reduce+L2L, P2P, L2P + near-field partials, total.
 constexpr int kPhases = 7;
+// Event sets of timed evaluations kept in flight: the host collects a set
+// only when the ring is full or the times are asked for, so timing adds no
+// host wait to a run of up to this many evaluations.
+constexpr int kTimingRing = 64;
 // Leaf size from which the near field runs concurrently with M2L / L2L.
 constexpr int kConcurrentLeaf = 128;
 
@@ -103,11 +108,12 @@ struct pt_ctx {
     hipStream_t near_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_tree = nullptr, ev_p2m = nullptr, ev_read = nullptr;
     int num_cu = 1;  // compute units of the device
-    hipEvent_t ev_near[2] = {};  // timing of the P2P kernel
-    bool near_timed = false;
+    hipEvent_t ev_near[kTimingRing][2] = {};  // timing of the P2P kernel (its own stream)
+    bool near_timed[kTimingRing] = {};
     int near_concurrent = -1;  // -1: by leaf size; 0 / 1: forced (PT_NEAR_CONCURRENT)
     uint64_t budget = 0, used = 0;
     int live = 0;
+    int32_t *d_nonfinite = nullptr;  // set by any kick of this context that produces a non-finite value
     std::map<void *, size_t> allocs;
     // workspace (grow-only)
     std::map<std::string, DevBuf> ws;
@@ -124,9 +130,13 @@ struct pt_ctx {
     uint32_t *last_vals = nullptr;
     int last_ntot = 0, last_was_fmm = 0, last_stride = 0, last_p = 0, last_prec = 0;
     TreeSummary last_sum{};
-    // timing
-    int timing = 0, timing_pending = 0;
-    hipEvent_t ev[kPhases] = {};
+    // timing: a ring of event sets, ring_cur the set of the evaluation being
+    // queued, ring_pending sets recorded and not yet collected (the oldest at
+    // ring_cur - ring_pending)
+    int timing = 0;
+    bool ring_made = false;
+    int ring_cur = 0, ring_pending = 0;
+    hipEvent_t ev[kTimingRing][kPhases] = {};
     double phase_sum[kPhases] = {};
     int64_t phase_count = 0;
 };
@@ -281,11 +291,14 @@ struct Batch {
     bool beams = false;  // some crystal uses the beam-mode laser
 };
 
-static void fill_desc(const pt_crystal *c, int off, CrystalDev &d)
+static void fill_desc(const pt_crystal *c, int off, double *mid, CrystalDev &d)
 {
     std::memset(&d, 0, sizeof(d));
     d.state = c->d_state;
+    d.mid = mid + 6 * (size_t)off;
     d.photons = c->d_photons;
+    d.nonfinite = c->d_nonfinite;
+    d.ctx_nonfinite = c->ctx->d_nonfinite;
     d.n = (int32_t)c->n;
     d.ion_off = off;
     d.dt = c->trap.dt_s;
@@ -360,6 +373,8 @@ static pt_status form_batch(pt_ctx *ctx, const std::vector<pt_crystal *> &cs, Ba
     const int nc = (int)cs.size();
     PT_TRY(ws_get(ctx, "desc", sizeof(CrystalDev) * nc, &b.d_desc));
     PT_TRY(ws_get(ctx, "ion_crystal", sizeof(int32_t) * std::max(1, b.ntot), &b.ion_crystal));
+    double *mid;
+    PT_TRY(ws_get(ctx, "mid", sizeof(double) * 6 * (size_t)std::max(1, b.ntot), &mid));
     if (ctx->h_desc_cap < nc) {
         PT_HIP(hipStreamSynchronize(ctx->stream));
         if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
@@ -369,7 +384,7 @@ static pt_status form_batch(pt_ctx *ctx, const std::vector<pt_crystal *> &cs, Ba
     } else {
         PT_HIP(hipStreamSynchronize(ctx->stream));  // staging buffer may still be read by a copy
     }
-    for (int i = 0; i < nc; ++i) fill_desc(cs[i], b.off[i], ctx->h_desc[i]);
+    for (int i = 0; i < nc; ++i) fill_desc(cs[i], b.off[i], mid, ctx->h_desc[i]);
     b.beams = false;
     for (int i = 0; i < nc; ++i) b.beams = b.beams || cs[i]->laser.mode == 2;
     PT_HIP(hipMemcpyAsync(b.d_desc, ctx->h_desc, sizeof(CrystalDev) * nc, hipMemcpyHostToDevice, ctx->stream));
@@ -401,7 +416,44 @@ static pt_status finish_timing(pt_ctx *ctx);
 
 static void mark(pt_ctx *ctx, int i)
 {
-    if (ctx->timing) (void)hipEventRecord(ctx->ev[i], ctx->stream);
+    if (ctx->timing) (void)hipEventRecord(ctx->ev[ctx->ring_cur][i], ctx->stream);
+}
+
+// Collects the oldest recorded event set into the running sums.
+static pt_status collect_oldest(pt_ctx *ctx)
+{
+    const int s = (ctx->ring_cur - ctx->ring_pending + kTimingRing) % kTimingRing;
+    PT_HIP(hipEventSynchronize(ctx->ev[s][kPhases - 1]));
+    float ms;
+    for (int i = 0; i < kPhases - 1; ++i) {
+        // phase 4: the P2P kernel on its own stream (it overlaps phases 1-3)
+        if (i == 4 && ctx->near_timed[s]) PT_HIP(hipEventElapsedTime(&ms, ctx->ev_near[s][0], ctx->ev_near[s][1]));
+        else PT_HIP(hipEventElapsedTime(&ms, ctx->ev[s][i], ctx->ev[s][i + 1]));
+        ctx->phase_sum[i] += ms;
+    }
+    PT_HIP(hipEventElapsedTime(&ms, ctx->ev[s][0], ctx->ev[s][kPhases - 1]));
+    ctx->phase_sum[kPhases - 1] += ms;
+    ctx->phase_count++;
+    ctx->ring_pending--;
+    return PT_OK;
+}
+
+// Starts the event set of a new timed evaluation (collecting the oldest set
+// first when the ring is full).
+static pt_status timing_begin(pt_ctx *ctx)
+{
+    if (!ctx->timing) return PT_OK;
+    if (ctx->ring_pending == kTimingRing) PT_TRY(collect_oldest(ctx));
+    ctx->near_timed[ctx->ring_cur] = false;
+    return PT_OK;
+}
+
+// Marks the current set recorded and moves to the next one.
+static void timing_end(pt_ctx *ctx)
+{
+    if (!ctx->timing) return;
+    ctx->ring_pending++;
+    ctx->ring_cur = (ctx->ring_cur + 1) % kTimingRing;
 }
 
 static BoxTable box_table(pt_ctx *ctx)
@@ -438,13 +490,12 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     ctx->last_off = b.off;
     ctx->last_ntot = ntot;
     ctx->last_was_fmm = fp.method == 1;
-    PT_TRY(finish_timing(ctx));  // the event set is reused: collect the previous evaluation first
-    ctx->near_timed = false;
+    PT_TRY(timing_begin(ctx));
     mark(ctx, 0);
     if (fp.method == 0) {
         launch_direct(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, ntot, E, phi, st);
         for (int i = 1; i <= kPhases - 1; ++i) mark(ctx, i);
-        ctx->timing_pending = ctx->timing;
+        timing_end(ctx);
         return PT_OK;
     }
     const int p = fp.p, s = fp.leaf_size;
@@ -617,15 +668,15 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             PT_HIP(hipStreamWaitEvent(ns, ctx->ev_fork, 0));
         }
         auto near_field = [&]() -> pt_status {
-            if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[0], ns));
+            if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][0], ns));
             const int max_grid = concurrent ? kNearPerCUConcurrent * ctx->num_cu : 16384;
             // beside M2L the grid is capped and the workgroups take items from
             // a queue; alone, one workgroup per item (no queue: its atomics
             // would serialise over the many small items of small leaves)
             launch_near<T>(bt, sp, ntot, near, stride, work, n_items, (T *)ppart, phi != nullptr, max_grid,
                            concurrent ? p2p_queue : nullptr, ns);
-            if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[1], ns));
-            ctx->near_timed = ctx->timing;
+            if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][1], ns));
+            ctx->near_timed[ctx->ring_cur] = ctx->timing;
             if (concurrent) PT_HIP(hipEventRecord(ctx->ev_join, ns));
             return PT_OK;
         };
@@ -645,7 +696,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     };
     PT_TRY(fp.precision == 1 ? run(float(0)) : run(double(0)));
     mark(ctx, 6);
-    ctx->timing_pending = ctx->timing;
+    timing_end(ctx);
     ctx->last_sum = hs;
     ctx->last_stride = stride;
     ctx->last_p = p;
@@ -655,22 +706,10 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     return PT_OK;
 }
 
-// Adds the phase times of the last timed evaluation to the running sums.
+// Adds the phase times of every recorded evaluation to the running sums.
 static pt_status finish_timing(pt_ctx *ctx)
 {
-    if (!ctx->timing || !ctx->timing_pending) return PT_OK;
-    PT_HIP(hipEventSynchronize(ctx->ev[kPhases - 1]));
-    float ms;
-    for (int i = 0; i < kPhases - 1; ++i) {
-        // phase 4: the P2P kernel on its own stream (it overlaps phases 1-3)
-        if (i == 4 && ctx->near_timed) PT_HIP(hipEventElapsedTime(&ms, ctx->ev_near[0], ctx->ev_near[1]));
-        else PT_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
-        ctx->phase_sum[i] += ms;
-    }
-    PT_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[kPhases - 1]));
-    ctx->phase_sum[kPhases - 1] += ms;
-    ctx->phase_count++;
-    ctx->timing_pending = 0;
+    while (ctx->ring_pending > 0) PT_TRY(collect_oldest(ctx));
     return PT_OK;
 }
 
@@ -727,9 +766,13 @@ static void release_ctx(pt_ctx *ctx)
     if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
     if (ctx->h_sum) (void)hipHostFree(ctx->h_sum);
     if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
-    for (auto &e : ctx->ev)
-        if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_tree, ctx->ev_p2m, ctx->ev_read, ctx->ev_near[0], ctx->ev_near[1]})
+    for (auto &set : ctx->ev)
+        for (auto &e : set)
+            if (e) (void)hipEventDestroy(e);
+    for (auto &pair : ctx->ev_near)
+        for (auto &e : pair)
+            if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_tree, ctx->ev_p2m, ctx->ev_read})
         if (e) (void)hipEventDestroy(e);
     if (ctx->near_stream) (void)hipStreamDestroy(ctx->near_stream);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -746,7 +789,6 @@ static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
     }
     PT_HIP(hipHostMalloc((void **)&ctx->h_sum, sizeof(TreeSummary)));
     PT_HIP(hipHostMalloc((void **)&ctx->h_counters, sizeof(unsigned long long) * 2));
-    for (auto &e : ctx->ev) PT_HIP(hipEventCreate(&e));
     PT_HIP(hipStreamCreateWithFlags(&ctx->near_stream, hipStreamNonBlocking));
     if (const char *e = getenv("PT_NEAR_CONCURRENT")) ctx->near_concurrent = atoi(e) ? 1 : 0;
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
@@ -754,9 +796,11 @@ static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_tree, hipEventDisableTiming));
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_p2m, hipEventDisableTiming));
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_read, hipEventDisableTiming));
-    for (auto &e : ctx->ev_near) PT_HIP(hipEventCreate(&e));
     PT_HIP(hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
     ctx->num_cu = std::max(1, ctx->num_cu);
+    PT_TRY(ctx_alloc(ctx, (void **)&ctx->d_nonfinite, sizeof(int32_t)));
+    PT_HIP(hipMemsetAsync(ctx->d_nonfinite, 0, sizeof(int32_t), ctx->stream));
+    PT_HIP(hipStreamSynchronize(ctx->stream));
     return PT_OK;
 }
 
@@ -822,11 +866,14 @@ static pt_status create_common(pt_ctx *ctx, int64_t n, double charge, double mas
     PT_HIP(hipSetDevice(ctx->device));
     PT_TRY(ctx_alloc(ctx, (void **)&c->d_state, sizeof(double) * 6 * (size_t)n));
     pt_status s = ctx_alloc(ctx, (void **)&c->d_photons, sizeof(int32_t) * (size_t)n);
+    if (s == PT_OK) s = ctx_alloc(ctx, (void **)&c->d_nonfinite, sizeof(int32_t));
     if (s != PT_OK) {
         ctx_free(ctx, c->d_state);
+        ctx_free(ctx, c->d_photons);
         return s;
     }
     PT_HIP(hipMemsetAsync(c->d_photons, 0, sizeof(int32_t) * n, ctx->stream));
+    PT_HIP(hipMemsetAsync(c->d_nonfinite, 0, sizeof(int32_t), ctx->stream));
     *out = c.release();
     ctx->live++;
     return PT_OK;
@@ -893,6 +940,7 @@ pt_status pt_destroy_crystal(pt_crystal *c)
     (void)hipStreamSynchronize(ctx->stream);
     ctx_free(ctx, c->d_state);
     ctx_free(ctx, c->d_photons);
+    ctx_free(ctx, c->d_nonfinite);
     auto &lb = ctx->last_batch;
     if (std::find(lb.begin(), lb.end(), c) != lb.end()) lb.clear();
     ctx->live--;
@@ -957,6 +1005,7 @@ pt_status pt_set_state(pt_crystal *c, const double *pos, const double *vel, int6
     PT_REQUIRE(finite_all(pos, 3 * c->n) && finite_all(vel, 3 * c->n), "non-finite position or velocity");
     PT_HIP(hipStreamSynchronize(c->ctx->stream));
     PT_TRY(upload_state(c, pos, vel));
+    PT_HIP(hipMemset(c->d_nonfinite, 0, sizeof(int32_t)));
     c->step = step;
     return PT_OK;
 }
@@ -1137,6 +1186,10 @@ pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_
     Batch b;
     int formed_for = -1;
     int64_t group_start = 0;  // step at which the current batch was formed
+    // Each crystal's step counter advances as its steps are queued, so that
+    // after a failure it counts exactly the completed steps; a step that
+    // fails before its kick leaves the state as it was (the half drift and
+    // everything up to the kick work on a copy).
     for (int64_t k = 0; k < kmax; ++k) {
         // crystals still stepping; the batch is re-formed only when one finishes
         int nactive = 0;
@@ -1146,10 +1199,7 @@ pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_
             for (int i = 0; i < n_crystals; ++i)
                 if (n_steps[i] > k) act.push_back(cs[i]);
             // descriptors hold the step index of the first step of this group
-            for (auto *c : act) c->step += k;
-            pt_status s = form_batch(ctx, act, b);
-            for (auto *c : act) c->step -= k;
-            PT_TRY(s);
+            PT_TRY(form_batch(ctx, act, b));
             formed_for = nactive;
             group_start = k;
         }
@@ -1162,8 +1212,8 @@ pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_
         PT_TRY(eval_field(ctx, b, cs[0]->force, E));
         // step index = descriptor step0 (set when the batch formed) + kstep
         launch_kick_drift(b.d_desc, b.ion_crystal, b.ntot, (int)(k - group_start), E, b.beams, ctx->stream);
+        for (pt_crystal *c : b.cs) c->step++;
     }
-    for (int i = 0; i < n_crystals; ++i) cs[i]->step += n_steps[i];
     PT_HIP(hipGetLastError());
     return PT_OK;
 }
@@ -1175,6 +1225,13 @@ pt_status pt_synchronize(pt_ctx *ctx)
     PT_REQUIRE(ctx, "ctx is NULL");
     PT_HIP(hipStreamSynchronize(ctx->stream));
     PT_HIP(hipGetLastError());
+    int32_t flag = 0;
+    PT_HIP(hipMemcpy(&flag, ctx->d_nonfinite, sizeof(flag), hipMemcpyDeviceToHost));
+    if (flag) {
+        PT_HIP(hipMemset(ctx->d_nonfinite, 0, sizeof(int32_t)));
+        pt_set_error("a step produced a non-finite position or velocity (pt_read_state names the crystal)");
+        return PT_ENUMERIC;
+    }
     return PT_OK;
 }
 
@@ -1187,8 +1244,10 @@ pt_status pt_read_state(pt_crystal *c, double *pos, double *vel, int64_t *step, 
     PT_HIP(hipMemcpyAsync(soa.data(), c->d_state, sizeof(double) * 6 * n, hipMemcpyDeviceToHost, ctx->stream));
     if (photons)
         PT_HIP(hipMemcpyAsync(photons, c->d_photons, sizeof(int32_t) * n, hipMemcpyDeviceToHost, ctx->stream));
+    int32_t flag = 0;
+    PT_HIP(hipMemcpyAsync(&flag, c->d_nonfinite, sizeof(flag), hipMemcpyDeviceToHost, ctx->stream));
     PT_HIP(hipStreamSynchronize(ctx->stream));
-    bool finite = true;
+    bool finite = flag == 0;
     for (int64_t i = 0; i < n; ++i)
         for (int d = 0; d < 3; ++d) {
             const double x = soa[d * n + i], v = soa[(3 + d) * n + i];
@@ -1209,8 +1268,14 @@ pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable)
 {
     PT_REQUIRE(ctx, "ctx is NULL");
     PT_TRY(finish_timing(ctx));
+    if (enable && !ctx->ring_made) {
+        for (auto &set : ctx->ev)
+            for (auto &e : set) PT_HIP(hipEventCreate(&e));
+        for (auto &pair : ctx->ev_near)
+            for (auto &e : pair) PT_HIP(hipEventCreate(&e));
+        ctx->ring_made = true;
+    }
     ctx->timing = enable ? 1 : 0;
-    ctx->timing_pending = 0;
     for (double &v : ctx->phase_sum) v = 0.0;
     ctx->phase_count = 0;
     return PT_OK;

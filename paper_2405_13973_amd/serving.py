@@ -1,8 +1,11 @@
 """Continuous-batching server for crystal-simulation requests.
 
 Requests (a crystal and a number of steps) arrive over time.  Each tick the
-server admits waiting requests while their estimated device footprint fits the
-budget, then advances every resident crystal by up to `chunk` steps in one
+server admits waiting requests while the device memory they would take fits the
+budget -- their own state plus the growth of the shared batch workspace, from
+the context's measured memory and a per-ion workspace rate that starts from an
+estimate for the expansion degree and leaf size and follows the measured
+high-water mark -- then advances every resident crystal by up to `chunk` steps in one
 pt_step_batch call -- every phase of a step is one launch for all resident
 crystals, whatever their sizes -- and retires the finished ones.  A request's
 state stays in HBM from admission to completion.  Results do not depend on
@@ -20,15 +23,33 @@ import time
 
 import numpy as np
 
-# Device bytes per ion held while a crystal is resident: its state (52 B) plus
-# its share of the batch workspace (keys, sorted positions, field, boxes, lists
-# and expansions; about 350 B per ion at p = 11, leaf 32), rounded up.
-BYTES_PER_ION = 512
-BYTES_FIXED = 1 << 20
+# Device bytes a resident crystal owns: FP64 positions and velocities (48 per
+# ion), the photon counts (4 per ion) and a status word.
+STATE_BYTES_PER_ION = 52
+STATE_BYTES_FIXED = 16
 
 
-def footprint(n_ions: int) -> int:
-    return BYTES_FIXED + BYTES_PER_ION * int(n_ions)
+def state_bytes(n_ions: int) -> int:
+    return STATE_BYTES_FIXED + STATE_BYTES_PER_ION * int(n_ions)
+
+
+def workspace_bytes_per_ion(p: int, leaf: int, precision: str) -> float:
+    """Estimate of the batch workspace per ion of the FMM step: per ion the sort
+    keys and values, tree scratch, sorted positions, field and working state
+    (about 200 B); per box (about 3.5 boxes per leaf-size ions) the box table,
+    colleague, window and near lists (about 2.4 kB) and 14 expansion rows of
+    (p+1)^2 coefficients padded to 16 (M, L and the M2L partial sums); 25 % on
+    top for the workspace's growth rule."""
+    kp = ((p + 1) ** 2 + 15) // 16 * 16
+    esz = 4 if precision == "mixed" else 8
+    per_box = 2400 + 14 * kp * esz
+    return 1.25 * (200 + 3.5 / max(1, leaf) * per_box)
+
+
+def footprint(n_ions: int, p: int = 11, leaf: int = 32, precision: str = "mixed") -> int:
+    """Estimated device bytes a request of n_ions adds while resident: its state
+    plus its share of the batch workspace."""
+    return state_bytes(n_ions) + int(workspace_bytes_per_ion(p, leaf, precision) * n_ions)
 
 
 @dataclasses.dataclass
@@ -74,6 +95,18 @@ class Server:
         self.force = ("fmm", p, leaf, precision)
         self.chunk = int(chunk)
         self.clock, self.sleep = clock, sleep
+        # workspace bytes per resident ion: the estimate, raised to the measured
+        # high-water mark after every tick
+        self.ws_rate = workspace_bytes_per_ion(p, leaf, precision)
+
+    def _projected(self, base, resident_ions, resident_state, n_new):
+        """Device bytes in use if a request of n_new ions joined the residents:
+        memory in use now, its state, and the workspace growth the larger batch
+        would need beyond the workspace already held."""
+        used = self.ctx.memory()[0]
+        ws_now = max(0, used - base - resident_state)
+        ws_need = self.ws_rate * (resident_ions + n_new)
+        return used + state_bytes(n_new) + max(0.0, ws_need - ws_now)
 
     def _admit(self, req):
         cr = req.crystal
@@ -91,9 +124,9 @@ class Server:
         waiting = collections.deque()
         active = []  # [index, crystal, remaining, admit_s]
         done = []
-        used = 0
         ion_steps = 0
         max_res = max_bytes = 0
+        base = self.ctx.memory()[0]  # held before the first admission (tables of earlier use, flags)
         t0 = self.clock()
         while pending or waiting or active:
             now = self.clock() - t0
@@ -101,8 +134,10 @@ class Server:
                 waiting.append(pending.popleft())
             while waiting:
                 i = waiting[0]
-                need = footprint(requests[i].crystal.n)
-                if used + need > self.budget and active:
+                n_new = requests[i].crystal.n
+                res_ions = sum(a[1].n for a in active)
+                res_state = sum(state_bytes(a[1].n) for a in active)
+                if active and self._projected(base, res_ions, res_state, n_new) > self.budget:
                     break  # wait for memory to free up
                 try:
                     c = self._admit(requests[i])
@@ -111,10 +146,8 @@ class Server:
                         break
                     raise
                 waiting.popleft()
-                used += need
                 active.append([i, c, requests[i].steps, now])
             max_res = max(max_res, len(active))
-            max_bytes = max(max_bytes, used)
             if not active:
                 if pending:
                     wait = requests[pending[0]].arrival_s * time_scale - (self.clock() - t0)
@@ -124,6 +157,12 @@ class Server:
             n = [min(a[2], self.chunk) for a in active]
             self.native.step_batch([a[1] for a in active], n)
             self.ctx.synchronize()
+            used = self.ctx.memory()[0]
+            max_bytes = max(max_bytes, used)
+            res_ions = sum(a[1].n for a in active)
+            ws = used - base - sum(state_bytes(a[1].n) for a in active)
+            if res_ions:
+                self.ws_rate = max(self.ws_rate, ws / res_ions)
             for a, k in zip(active, n):
                 a[2] -= k
                 ion_steps += k * a[1].n
@@ -133,6 +172,7 @@ class Server:
             # one batched evaluation (sums on the device; eqs. pe_rot, temp_ax, temp_pl)
             diags = self.native.rotating_diagnostics_batch([a[1] for a in finished]) if finished else []
             diag_of = {id(a): d for a, d in zip(finished, diags)}
+            max_bytes = max(max_bytes, self.ctx.memory()[0])
             for a in active:
                 if a[2] > 0:
                     still.append(a)
@@ -143,7 +183,6 @@ class Server:
                 done.append(Done(a[0], a[1].n, req.steps, req.arrival_s * time_scale, a[3], fin, st["pos"], st["vel"],
                                  st["photons"], diag_of[id(a)]))
                 a[1].destroy()
-                used -= footprint(req.crystal.n)
             active = still
         return Report(done, self.clock() - t0, ion_steps, max_res, max_bytes)
 

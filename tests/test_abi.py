@@ -38,3 +38,16 @@ def test_ctx_create_without_device_fails_cleanly():
     h = C.c_void_p()
     assert lib.pt_ctx_create(0, 0, None, C.byref(h)) == native.PT_EDEVICE
     assert not h.value
+
+
+def test_numeric_status_reaches_the_caller():
+    """PT_ENUMERIC (a step produced a non-finite state, reported at the next
+    synchronising call) and every other status surfaces as PTError with its code."""
+    lib = native.load()
+    assert lib.pt_synchronize(None) == native.PT_EINVAL
+    for code, name in ((native.PT_ENUMERIC, "PT_ENUMERIC"), (native.PT_ENOMEM, "PT_ENOMEM"),
+                       (native.PT_EDEVICE, "PT_EDEVICE")):
+        with pytest.raises(native.PTError) as e:
+            native._check(code)
+        assert e.value.code == code and name in str(e.value)
+    native._check(native.PT_OK)

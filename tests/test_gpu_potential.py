@@ -21,6 +21,7 @@ import sys
 import numpy as np
 import pytest
 
+from bench import LEAF_CANDIDATES
 from oracle import oracle as O
 from paper_2405_13973_amd import inputs, native
 
@@ -142,7 +143,7 @@ def test_batch_potential_equals_alone(ctx, method, precision):
     assert np.array_equal(np.array(U_alone), U_together)
 
 
-@pytest.mark.parametrize("leaf", [256, 32])
+@pytest.mark.parametrize("leaf", LEAF_CANDIDATES)
 def test_config3_full_size_sampled_potential(ctx, leaf):
     say(f"config3 potential N=1e5 leaf {leaf}")
     cr = inputs.config3()

@@ -45,12 +45,15 @@ class FakeNative:
     class PTError(RuntimeError):
         code = 0
 
-    def __init__(self, clock, sec_per_ion_step):
+    def __init__(self, clock, sec_per_ion_step, ctx=None):
         self.clock, self.rate = clock, sec_per_ion_step
         self.calls = []
+        self.ctx = ctx
 
     def step_batch(self, cs, n):
         self.calls.append([(c.n, k) for c, k in zip(cs, n)])
+        if self.ctx is not None:  # the batch workspace grows to the batch, never shrinks
+            self.ctx.ws = max(self.ctx.ws, int(self.ctx.ws_per_ion * sum(c.n for c in cs)))
         for c, k in zip(cs, n):
             c.steps += k
         # time advances with the work of the longest crystal in the batch
@@ -62,8 +65,12 @@ class FakeNative:
 
 
 class FakeCtx:
-    def __init__(self):
+    """Device memory as the library counts it: each live crystal's state plus a
+    grow-only batch workspace of ws_per_ion bytes per ion of the largest batch."""
+
+    def __init__(self, ws_per_ion=300.0):
         self.created = []
+        self.ws, self.ws_per_ion = 0, ws_per_ion
 
     def crystal(self, pos, vel, q, m, seed):
         c = FakeCrystal(None, len(pos))
@@ -72,6 +79,10 @@ class FakeCtx:
 
     def synchronize(self):
         pass
+
+    def memory(self):
+        live = sum(serving.state_bytes(c.n) for c in self.created if c.alive)
+        return live + self.ws, 0
 
 
 def _reqs(ns, ks, arrivals):
@@ -111,6 +122,7 @@ def test_admission_waits_for_memory():
     clk = FakeClock()
     nat = FakeNative(clk, 1e-9)
     ctx = FakeCtx()
+    nat.ctx = ctx
     n = 10000
     budget = serving.footprint(n) + serving.footprint(n) // 2  # room for one crystal at a time
     reqs = _reqs([n, n, n], [30, 30, 30], [0.0, 0.0, 0.0])
@@ -130,3 +142,31 @@ def test_latency_percentiles():
     p50, p99 = rep.latency_percentiles()
     assert 0 < p50 <= p99
     assert rep.ion_steps_per_s > 0
+
+
+def test_footprint_grows_with_smaller_leaves_and_higher_degree():
+    """More boxes per ion (small leaves) and longer expansions (high p, FP64)
+    take more workspace per ion."""
+    f = serving.workspace_bytes_per_ion
+    assert f(11, 32, "mixed") > f(11, 384, "mixed")
+    assert f(12, 64, "mixed") > f(8, 64, "mixed")
+    assert f(11, 64, "fp64") > f(11, 64, "mixed")
+    assert serving.footprint(1000, 11, 32) > serving.state_bytes(1000)
+
+
+def test_admission_learns_the_measured_workspace():
+    """When the batch workspace per ion is larger than the estimate, the server
+    raises its rate to the measured one after the first tick and still keeps the
+    memory it uses within the budget."""
+    clk = FakeClock()
+    ctx = FakeCtx(ws_per_ion=3 * serving.workspace_bytes_per_ion(11, 32, "mixed"))
+    nat = FakeNative(clk, 1e-9, ctx)
+    n = 4000
+    per = serving.state_bytes(n) + ctx.ws_per_ion * n
+    budget = int(2.5 * per)  # two such requests fit, three do not
+    reqs = _reqs([n] * 6, [20] * 6, [0.0, 0.0, 0.001, 0.001, 0.002, 0.002])
+    srv = serving.Server(ctx, nat, budget_bytes=budget, chunk=5, clock=clk, sleep=clk.sleep)
+    rep = srv.run(reqs)
+    assert len(rep.done) == 6
+    assert srv.ws_rate >= ctx.ws_per_ion * 0.999
+    assert rep.max_resident_bytes <= budget
