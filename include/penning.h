@@ -166,6 +166,22 @@ pt_status pt_compute_forces(pt_crystal *c, double *F_out);
  * host output.  All crystals must share the context and force parameters. */
 pt_status pt_compute_forces_batch(pt_crystal *const *cs, int n_crystals, double *const *F_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the Coulomb
+ * force of pt_compute_forces by the direct sum, written to a DEVICE buffer
+ * F_dev (n x 3 doubles, ion-id order, owned by the caller), queued on the
+ * context's stream and not waited for (pt_synchronize waits).  The result is
+ * bit-identical to pt_compute_forces with the direct method.  Its work
+ * buffers live in one fixed per-GPU device array of 7 MiB, set up when the
+ * context is created; the call itself allocates nothing.  Limits: the
+ * crystal's force method must be the direct sum and n <= PT_NOALLOC_MAX_IONS
+ * (else PT_EINVAL).  Every such call on one GPU shares that array, and the
+ * array keeps the last call's contents: calls that overlap on one GPU (e.g.
+ * from two contexts on different streams) race and must be serialised by the
+ * caller.  Errors: PT_EINVAL, PT_EDEVICE. */
+#define PT_NOALLOC_MAX_IONS 131072
+pt_status pt_compute_forces_noalloc(pt_crystal *c, double *F_dev);
+
 /* Coulomb potential phi_i = k_e q sum_{j != i} 1/|x_i - x_j| (volts) at every
  * ion at the current positions -- the pair term of eq. (hamiltonian) per unit
  * charge, the quantity the paper's potential error (eq. rms_pot) compares --

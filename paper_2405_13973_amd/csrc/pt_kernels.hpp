@@ -144,4 +144,21 @@ void launch_far(const BoxTable &bt, const double *sp, int ntot, int p, int nbox,
                 const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals, double *E,
                 double *phi, int leaf_size, hipStream_t st);
 
+// noalloc.hip: the fixed scratch of pt_compute_forces_noalloc (direct sum of
+// one crystal of at most kNoAllocMaxIons ions).
+constexpr int kNoAllocMaxIons = PT_NOALLOC_MAX_IONS;
+constexpr size_t kNoAllocScratchBytes = (size_t)7 << 20;
+// Byte offsets of its regions for n ions.
+struct NoAllocLayout {
+    size_t desc, bbox, ion_crystal, blk_crystal, blk_first, mid, E, total;
+    int nblk;
+};
+NoAllocLayout noalloc_layout(int n);
+// The device address of this device's scratch (looked up once per device,
+// with the device current).
+pt_status noalloc_scratch(int device, void **out);
+void launch_noalloc_setup(const CrystalDev &d, CrystalDev *desc, int32_t *ion_crystal, int n, int32_t *blk_crystal,
+                          int32_t *blk_first, int nblk, hipStream_t st);
+void launch_scale_field(const double *E, int n, double s, double *F, hipStream_t st);
+
 }  // namespace pt

@@ -114,6 +114,7 @@ struct pt_ctx {
     uint64_t budget = 0, used = 0;
     int live = 0;
     int32_t *d_nonfinite = nullptr;  // set by any kick of this context that produces a non-finite value
+    char *noalloc = nullptr;         // this device's fixed scratch (pt_compute_forces_noalloc)
     std::map<void *, size_t> allocs;
     // workspace (grow-only)
     std::map<std::string, DevBuf> ws;
@@ -799,6 +800,7 @@ static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
     PT_HIP(hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
     ctx->num_cu = std::max(1, ctx->num_cu);
     PT_TRY(ctx_alloc(ctx, (void **)&ctx->d_nonfinite, sizeof(int32_t)));
+    PT_TRY(noalloc_scratch(ctx->device, (void **)&ctx->noalloc));
     PT_HIP(hipMemsetAsync(ctx->d_nonfinite, 0, sizeof(int32_t), ctx->stream));
     PT_HIP(hipStreamSynchronize(ctx->stream));
     return PT_OK;
@@ -1170,6 +1172,40 @@ pt_status pt_read_rotating_state(pt_crystal *c, double *pos_r, double *vel_r)
 pt_status pt_compute_forces(pt_crystal *c, double *F_out)
 {
     return pt_compute_forces_batch(&c, 1, &F_out);
+}
+
+// The direct-sum path of pt_compute_forces on the device's fixed scratch:
+// every work buffer is a region of that array, the descriptor and block table
+// are written by a kernel, and the forces go to the caller's device buffer.
+pt_status pt_compute_forces_noalloc(pt_crystal *c, double *F_dev)
+{
+    PT_REQUIRE(c && F_dev, "NULL argument");
+    PT_REQUIRE(c->force.method == 0, "pt_compute_forces_noalloc supports the direct method only");
+    PT_REQUIRE(c->n <= kNoAllocMaxIons, "n = %lld exceeds the no-allocation limit of %d ions", (long long)c->n,
+               kNoAllocMaxIons);
+    pt_ctx *ctx = c->ctx;
+    const int n = (int)c->n;
+    const NoAllocLayout l = noalloc_layout(n);
+    PT_REQUIRE(l.total <= kNoAllocScratchBytes, "scratch layout of %zu bytes exceeds %zu", l.total,
+               kNoAllocScratchBytes);
+    PT_HIP(hipSetDevice(ctx->device));
+    char *base = ctx->noalloc;
+    CrystalDev d;
+    fill_desc(c, 0, (double *)(base + l.mid), d);
+    CrystalDev *desc = (CrystalDev *)(base + l.desc);
+    int32_t *ion_crystal = (int32_t *)(base + l.ion_crystal);
+    int32_t *blk_crystal = (int32_t *)(base + l.blk_crystal), *blk_first = (int32_t *)(base + l.blk_first);
+    unsigned long long *bbox = (unsigned long long *)(base + l.bbox);
+    double *E = (double *)(base + l.E);
+    hipStream_t st = ctx->stream;
+    launch_noalloc_setup(d, desc, ion_crystal, n, blk_crystal, blk_first, l.nblk, st);
+    launch_bbox_reset(bbox, 1, st);
+    launch_drift_bbox(desc, ion_crystal, n, 1, 0, bbox, st);
+    launch_direct(desc, blk_crystal, blk_first, l.nblk, n, E, nullptr, st);
+    const double ke = 1.0 / (4.0 * kPi * kEps0), q = c->q;
+    launch_scale_field(E, n, ke * q * q, F_dev, st);
+    PT_HIP(hipGetLastError());
+    return PT_OK;
 }
 
 pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_steps)

@@ -87,6 +87,7 @@ def load():
         "pt_set_state": [_vp, _dp, _dp, C.c_int64],
         "pt_compute_forces": [_vp, _dp],
         "pt_compute_forces_batch": [C.POINTER(_vp), C.c_int, C.POINTER(_dp)],
+        "pt_compute_forces_noalloc": [_vp, _vp],
         "pt_compute_potential": [_vp, _dp],
         "pt_compute_potential_batch": [C.POINTER(_vp), C.c_int, C.POINTER(_dp)],
         "pt_coulomb_energy": [_vp, _dp],
@@ -237,6 +238,12 @@ class Crystal:
         F = np.zeros((self.n, 3))
         _check(load().pt_compute_forces(self.h, _ptr(F)))
         return F
+
+    def compute_forces_noalloc(self, F_dev_ptr: int):
+        """Direct-sum forces into a caller's device buffer (n x 3 doubles at the
+        integer address F_dev_ptr), queued on the context's stream without any
+        allocation; call ctx.synchronize() before reading it."""
+        _check(load().pt_compute_forces_noalloc(self.h, _vp(F_dev_ptr)))
 
     def compute_potential(self):
         phi = np.zeros(self.n)
