@@ -223,6 +223,8 @@ def bench_potential(ctx, c, cr, p, leaf, prec, evals=10):
         "force_eval_ms": float(f_ph[6]), "potential_over_force_time": float(ph[6] / f_ph[6]),
         "error_pot": err, "coulomb_energy_J": U, "p": p, "leaf_size": leaf, "precision": prec,
         "p2p_kernel_ms": float(ph[4]),
+        "phase_ms": {k: float(v) for k, v in zip(PHASES, ph)},
+        "force_phase_ms": {k: float(v) for k, v in zip(PHASES, f_ph)},
         "p2p_roofline": {"bound": "alu", "achieved": tfl, "peak": peak, "unit": "TFLOP/s", "frac": tfl / peak,
                          "traffic": measured_traffic("p2p_pot", p, leaf, prec, cr.n),
                          "algorithmic": f"{P2P_POT_FLOPS_PER_PAIR} flops per near-field pair, {int(wc[3])} "

@@ -87,25 +87,22 @@ __global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const double *__restric
     }
 }
 
-// ---------------------------------------------------------------- M2L
+// ---------------------------------------------------------------- M2M / L2L
 //
-// M2L is a dense contraction on the matrix cores.  Targets that share the
-// octant parity c = (ix, iy, iz) & 1 see a given slot w of the 6x6x6 source
-// window at the same offset d = w - 2 - c, hence through the same operator
-// T_d; the scaled operators do not depend on level or crystal, so one
-// parity's targets from every level >= 2 and every crystal form the columns
-// of one GEMM
-//     L[:, targets] = sum_w T_{d(w)} (Kp x Kp) * M[src(w, targets)] (Kp x n)
-// over the 189 non-touching slots.  A workgroup of 4 waves takes 64 targets
-// (16 per wave) and a group of slots; per slot it stages Kp x 16 chunks of
-// T_d (column-major, zero padded) and the matching 16 x 64 chunk of source
-// expansions in LDS, and every wave runs v_mfma 16x16x4 over all row blocks
-// of its 16 columns -- each operator chunk is read from L2 once per 64
-// targets.  Slot groups write separate partial sums that a second kernel adds
-// in group order, so every target's sum has a fixed order whatever tile it
-// landed in (batch-invariant, deterministic).  Workgroup ids are laid out
-// with id mod 8 = parity: under round-robin dispatch over the 8 XCDs, each
-// XCD's L2 serves a single parity's operators.
+// The translations between levels are dense contractions on the matrix cores:
+// with scaled coefficients the 8 child-to-parent (M2M) and the 8
+// parent-to-child (L2L) operators do not depend on level or crystal, so one
+// level's boxes of every crystal form the columns of one GEMM per octant
+// slot,
+//     out[:, boxes] (+)= sum_slots A_slot (Kp x Kp) * X[src(slot, boxes)] (Kp x n).
+// A workgroup of 4 waves takes 64 boxes (16 per wave) and one slot group; per
+// slot it stages k-chunks of the operator (column-major, zero padded) and of
+// the 64 source expansions in LDS, and every wave runs v_mfma 16x16x4 over
+// all row blocks of its 16 columns.  Slot groups (one octant each) write
+// separate partial sums that a second kernel adds in group order, so every
+// box's sum has a fixed order whatever tile it landed in (batch-invariant,
+// deterministic).  (M2L, the conversion over the V lists, is organised by
+// operator instead: k_m2l.hip.)
 
 template <typename T>
 struct Mfma;
@@ -122,34 +119,15 @@ struct Mfma<float> {
     __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// Buckets the boxes of level >= 2 by octant parity.
-__global__ void k_m2l_bucket(BoxTable bt, int nbox, int32_t *__restrict__ cnt, int32_t *__restrict__ list)
-{
-    // one atomic per parity and wave; the order inside a bucket does not
-    // change any result (a target's sum runs over its own slots in slot order)
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const int o = (b < nbox && bt.level[b] >= 2) ? octant_of(bt.ix[b], bt.iy[b], bt.iz[b]) : -1;
-    const uint64_t below = (1ull << lane) - 1ull;
-    for (int q = 0; q < 8; ++q) {
-        const uint64_t m = __ballot(o == q);
-        if (!m) continue;
-        const int leader = __ffsll((long long)m) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&cnt[q], __popcll(m));
-        base = __shfl(base, leader);
-        if (o == q) list[(size_t)q * nbox + base + __popcll(m & below)] = b;
-    }
-}
-
 constexpr int kM2LWaves = 4;           // 16 target columns per wave
 constexpr int kM2LCols = 16 * kM2LWaves;
 constexpr int kM2LRB = 12;             // row blocks (of 16) per workgroup: Kp <= 192 in one pass
 
-// One translation GEMM serves M2L, M2M and L2L:
+// One translation GEMM serves M2M and L2L:
 //   out[t] (op) sum over slots s of  A[op(s)] * X[src(t, s)]
-// targets t: either bucket lists (M2L: one bucket per parity) or the box range
-// [b0, b0 + n); src(t, s) = srctab[t * src_stride + col(s)] (-1: no source).
+// targets t: either bucket lists (cnt non-null) or the box range [b0, b0 + n);
+// src(t, s) = srctab[t * src_stride + col(s)] (-1: no source); an operator
+// index above 255 carries reflection signs (mask = index >> 8).
 // Output modes: 0 partial sums per slot group, 1 overwrite (skipping targets
 // flagged in `skip`), 2 accumulate.
 struct XlateArgs {
@@ -181,17 +159,13 @@ constexpr int kXSlots = 32;  // slots per workgroup, at most
 // rows past Kp (PARTIAL row groups only) read an in-bounds address and are
 // replaced by zero, and a missing source reads X[zrow], an expansion row
 // kept at zero.
-// ROLE only names the kernel symbol (0 M2L, 1 M2M, 2 L2L) so that profiles
-// tell the three uses apart.
+// ROLE only names the kernel symbol (1 M2M, 2 L2L) so that profiles tell
+// the uses apart.
 template <typename T, int NRB, bool PARTIAL, int ROLE, int KC>
 __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *__restrict__ At,
                                                          const T *__restrict__ X, T *__restrict__ out)
 {
     using MF = Mfma<T>;
-    // M2L runs beside the near field, whose waves would otherwise take most
-    // issue slots of the SIMDs it shares; a raised wave priority lets the
-    // M2L waves (the longer dependency chain) issue first when they are ready
-    if (ROLE == 0) __builtin_amdgcn_s_setprio(1);
     constexpr int ROWS = NRB * 16;
     constexpr int NT = 64 * kM2LWaves;
     constexpr int kXA = KC * ROWS / NT;  // operator values staged per thread (exact)
@@ -412,20 +386,6 @@ __global__ void k_xlate_reduce(int b0, int n, int Kp, int nbox, int ngroup, int 
     T acc = 0;
     for (int g = 0; g < ngroup; ++g) acc += part[(size_t)g * nbox * Kp + off];
     out[off] = mode == 2 ? out[off] + acc : acc;
-}
-
-// L = sum of the slot-group partials, in group order; zero above level 2.
-template <typename T>
-__global__ void k_m2l_reduce(BoxTable bt, int nbox, int Kp, int ngroup, const T *__restrict__ part,
-                             T *__restrict__ L)
-{
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)nbox * Kp) return;
-    const int b = (int)(e / Kp);
-    T acc = 0;
-    if (bt.level[b] >= 2)
-        for (int g = 0; g < ngroup; ++g) acc += part[(size_t)g * nbox * Kp + e];
-    L[e] = acc;
 }
 
 // Near field (P2P) of one work item per 256-thread workgroup (grid-stride
@@ -745,49 +705,11 @@ void launch_m2m(const BoxTable &bt, int p, const TreeSummary &hs, const T *m2m_p
     }
 }
 
-void launch_m2l_bucket(const BoxTable &bt, int nbox, int32_t *cnt, int32_t *list, hipStream_t st)
-{
-    if (nbox <= 0) return;
-    k_m2l_bucket<<<ceil_div(nbox, 256), 256, 0, st>>>(bt, nbox, cnt, list);
-}
-
-template <typename T>
-void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t *vtab, const int2 *slots,
-                const T *m2l_pad, const T *M, const int32_t *cnt, const int32_t *list, T *part, int ngroup,
-                hipStream_t st)
-{
-    const int Kp = kpad(p), nbox = hs.nbox;
-    const int n2 = nbox - hs.level_start[2];  // targets: boxes of level >= 2
-    if (nbox <= 0 || n2 <= 0) return;
-    XlateArgs a = xlate_base(Kp, nbox);
-    a.cnt = cnt;
-    a.list = list;
-    a.list_stride = nbox;
-    a.nbucket = 8;  // workgroup id mod 8 = parity = XCD under round-robin dispatch
-    a.ngroup = ngroup;
-    a.tile_stride = std::max(1, ceil_div(n2, 8 * kM2LCols));
-    a.slots = slots;
-    a.nslot = 189;
-    a.srctab = vtab;
-    a.src_stride = kWin;
-    a.mode = 0;
-    xlate_rows(a, 8L * a.tile_stride * ngroup);
-    launch_xlate<T, 0>(a, 8 * a.tile_stride * ngroup * a.nrowgrp, m2l_pad, M, part, st);
-}
-
-template <typename T>
-void launch_m2l_reduce(const BoxTable &bt, int p, int nbox, const T *part, int ngroup, T *L, hipStream_t st)
-{
-    const int Kp = kpad(p);
-    const size_t tot = (size_t)nbox * Kp;
-    if (tot) k_m2l_reduce<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(bt, nbox, Kp, ngroup, part, L);
-}
-
 int m2l_groups(int)
 {
-    // A constant: the grouping fixes the order in which a target's slots are
-    // summed, so it must not depend on the batch (12 groups of <= 16 slots).
-    return 12;
+    // M2M and L2L: one group per octant slot (8), a constant, so that the
+    // summation order does not depend on the batch
+    return 8;
 }
 
 template <typename T>
@@ -814,6 +736,11 @@ void launch_near(const BoxTable &bt, const double *sp, int ntot, const int2 *nea
     else k_p2p<T, false><<<grid, kP2PThreads, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part, queue);
 }
 
+size_t near_lds_bytes()
+{
+    return sizeof(double2) * kP2PStage + sizeof(double) * kP2PStage + sizeof(int) * (2 * kNearMax + 3);
+}
+
 template <typename T>
 void launch_far(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
                 const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals, double *E,
@@ -837,14 +764,6 @@ template void launch_m2m<double>(const BoxTable &, int, const TreeSummary &, con
                                  const int32_t *, double *, double *, hipStream_t);
 template void launch_m2m<float>(const BoxTable &, int, const TreeSummary &, const float *, const int2 *,
                                 const int32_t *, float *, float *, hipStream_t);
-template void launch_m2l<double>(const BoxTable &, int, const TreeSummary &, const int32_t *, const int2 *,
-                                 const double *, const double *, const int32_t *, const int32_t *, double *, int,
-                                 hipStream_t);
-template void launch_m2l<float>(const BoxTable &, int, const TreeSummary &, const int32_t *, const int2 *,
-                                const float *, const float *, const int32_t *, const int32_t *, float *, int,
-                                hipStream_t);
-template void launch_m2l_reduce<double>(const BoxTable &, int, int, const double *, int, double *, hipStream_t);
-template void launch_m2l_reduce<float>(const BoxTable &, int, int, const float *, int, float *, hipStream_t);
 template void launch_downward<double>(const BoxTable &, int, const TreeSummary &, const double *, const int2 *,
                                       const int32_t *, double *, double *, hipStream_t);
 template void launch_downward<float>(const BoxTable &, int, const TreeSummary &, const float *, const int2 *,

@@ -1,0 +1,436 @@
+// M2L, the multipole-to-local conversion over the V lists (Zaris et al.,
+// Sec. 2.3, eq. FMM_local; downward pass), as a dense contraction on the
+// matrix cores, organised by operator.
+//
+// With coefficients scaled by the box side, the conversion from a source box
+// S to a target box T of the same level depends only on their offset d (one
+// of the 316 offsets in [-3,3]^3 outside [-1,1]^3):  L_T += T_d M_S.  T_d is
+// S T_|d| S for the 56 stored base operators of offsets with non-negative
+// components, S the diagonal sign matrix of the reflections of d's negative
+// components.  So every V pair (T, S) is a matrix-vector product with one of
+// 56 base matrices plus sign flips, and the pairs that share a base matrix
+// form one GEMM:
+//   1. pairs are counted per target and per base operator, and two scans give
+//      each pair a row in a result buffer R (targets in box order, a target's
+//      pairs in the order of its parity's slot table) and a place in its
+//      operator's bucket (operators in order, then boxes, then slots);
+//   2. a persistent workgroup takes a contiguous run of work units -- 64
+//      pairs of one operator bucket times one group of output rows -- keeps
+//      that row group of the base operator in LDS while it stays on the same
+//      operator, and computes the 64 products on the matrix cores
+//      (16 columns per wave), the column signs applied to the loaded source
+//      coefficients and the row signs to the results, each product written to
+//      its own row of R;
+//   3. L_T is the sum of its rows of R in order.
+// Every product is computed by the same instructions whichever workgroup,
+// batch or column it lands in, and each target's sum runs in its fixed slot
+// order, so results are deterministic and do not depend on the batch.  No
+// work is spent on absent sources: a unit multiplies only existing pairs
+// (the last unit of a bucket is padded with the zero expansion row).
+#include <algorithm>
+
+#include "fmm_math.hpp"
+#include "pt_common.hpp"
+#include "pt_kernels.hpp"
+
+namespace pt {
+
+namespace {
+
+constexpr int kOps = 64;       // base operator slots (56 used)
+constexpr int kSlots = 189;    // non-touching window slots per parity
+constexpr int kCols = 64;      // pairs per work unit (16 per wave)
+constexpr int kGemmThreads = 256;
+
+__device__ inline int parity_of(const BoxTable &bt, int b)
+{
+    return ((bt.ix[b] & 1) << 2) | ((bt.iy[b] & 1) << 1) | (bt.iz[b] & 1);
+}
+
+template <typename T>
+struct MfmaOp;
+template <>
+struct MfmaOp<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 op(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int r) { return 4 * r + (lane >> 4); }  // output row of element r
+};
+template <>
+struct MfmaOp<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// 16 bytes of T: the unit of every operand load (VEC values).
+template <typename T>
+struct Vec16 {
+    static constexpr int N = 16 / sizeof(T);
+    T v[N];
+};
+
+}  // namespace
+
+// Pass 1, one workgroup per box: the V pairs of a target box of level >= 2
+// (its parity's 189 slots with a source), counted in total (pcnt[b]) and per
+// base operator (cnt_ob[o * nbox + b]).
+__global__ __launch_bounds__(256) void k_m2l_count(BoxTable bt, const TreeSummary *__restrict__ sum,
+                                                   const int32_t *__restrict__ vtab, const int2 *__restrict__ slots,
+                                                   uint32_t *__restrict__ pcnt, uint32_t *__restrict__ cnt_ob)
+{
+    __shared__ uint32_t per_op[kOps];
+    __shared__ uint32_t total;
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int nbox = sum->nbox;
+    if (b >= nbox) return;
+    if (tid < kOps) per_op[tid] = 0;
+    if (tid == 0) total = 0;
+    __syncthreads();
+    if (bt.level[b] >= 2 && tid < kSlots) {
+        const int2 s = slots[parity_of(bt, b) * kSlots + tid];
+        if (vtab[(size_t)b * kWin + s.x] >= 0) {
+            atomicAdd(&per_op[s.y & 255], 1u);
+            atomicAdd(&total, 1u);
+        }
+    }
+    __syncthreads();
+    if (tid < kOps) cnt_ob[(size_t)tid * nbox + b] = per_op[tid];
+    if (tid == 0) pcnt[b] = total;
+}
+
+// Pass 2, one workgroup per box, after the exclusive scans of pcnt (-> the
+// box's first row of R) and cnt_ob (-> the box's first place in each operator
+// bucket): each pair's bucket entry {source box, row of R, reflection mask}.
+// Ranks follow the slot order, so the layout is deterministic.
+__global__ __launch_bounds__(256) void k_m2l_emit(BoxTable bt, const TreeSummary *__restrict__ sum,
+                                                  const int32_t *__restrict__ vtab, const int2 *__restrict__ slots,
+                                                  const uint32_t *__restrict__ pair_off,
+                                                  const uint32_t *__restrict__ ob_off, int4 *__restrict__ bucket)
+{
+    __shared__ int src_s[kSlots];
+    __shared__ int op_s[kSlots];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int nbox = sum->nbox;
+    if (b >= nbox || bt.level[b] < 2) return;
+    const int par = parity_of(bt, b);
+    if (tid < kSlots) {
+        const int2 s = slots[par * kSlots + tid];
+        src_s[tid] = vtab[(size_t)b * kWin + s.x];
+        op_s[tid] = s.y;
+    }
+    __syncthreads();
+    if (tid >= kSlots || src_s[tid] < 0) return;
+    const int op = op_s[tid] & 255;
+    int rank = 0, rank_op = 0;
+    for (int k = 0; k < tid; ++k)
+        if (src_s[k] >= 0) {
+            ++rank;
+            rank_op += (op_s[k] & 255) == op;
+        }
+    const uint32_t pos = ob_off[(size_t)op * nbox + b] + (uint32_t)rank_op;
+    bucket[pos] = make_int4(src_s[tid], (int)(pair_off[b] + (uint32_t)rank), op_s[tid] >> 8, 0);
+}
+
+// Pass 3, one wave: per operator its bucket's first entry (op_beg[o], with
+// op_beg[64] = all pairs) and the prefix of its unit counts (chunk_off).
+__global__ __launch_bounds__(64) void k_m2l_chunks(const TreeSummary *__restrict__ sum,
+                                                   const uint32_t *__restrict__ ob_off,
+                                                   const uint32_t *__restrict__ npairs, int32_t *__restrict__ op_beg,
+                                                   int32_t *__restrict__ chunk_off)
+{
+    const int o = threadIdx.x;
+    const int nbox = sum->nbox;
+    const int beg = nbox > 0 ? (int)ob_off[(size_t)o * nbox] : 0;
+    const int end = o + 1 < kOps ? (nbox > 0 ? (int)ob_off[(size_t)(o + 1) * nbox] : 0) : (int)*npairs;
+    int c = (end - beg + kCols - 1) / kCols;
+    // inclusive wave scan of the unit counts
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(c, off);
+        if (o >= off) c += y;
+    }
+    op_beg[o] = beg;
+    chunk_off[o + 1] = c;
+    if (o == 0) chunk_off[0] = 0;
+    if (o == kOps - 1) op_beg[kOps] = (int)*npairs;
+}
+
+// Pass 4: the products.  Work unit u (of nrg * U, U = chunk_off[64]) is row
+// group rg = u / U of chunk u % U; each workgroup takes a contiguous run of
+// units, so it mostly stays on one operator and one row group.
+//
+// Operand layout: a step covers 4 VEC values of k.  Lane l (column j = l % 16,
+// quarter q = l / 16) loads the 16 bytes of source coefficients k = 4 VEC s +
+// VEC q + e (e < VEC) and reads the same k of row (l % 16) of each row block
+// from LDS with one 16-byte read; the e-th matrix-core instruction of the
+// step takes element e of both, i.e. the contraction runs over a fixed
+// permutation of k, the same for every product.
+template <typename T, int NRB>
+__global__ __launch_bounds__(kGemmThreads) void k_m2l_gemm(int Kp, int nrg, int zrow,
+                                                           const int32_t *__restrict__ chunk_off_g,
+                                                           const int32_t *__restrict__ op_beg_g,
+                                                           const int4 *__restrict__ bucket, const T *__restrict__ A,
+                                                           const T *__restrict__ M, T *__restrict__ R)
+{
+    using MF = MfmaOp<T>;
+    using V = Vec16<T>;
+    constexpr int VEC = V::N;
+    constexpr int ROWS = NRB * 16;
+    // runs beside the near field: a raised wave priority lets these waves
+    // (long dependency chains on the matrix cores) issue first when ready
+    __builtin_amdgcn_s_setprio(1);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int strideE = Kp + VEC;  // row stride of the LDS operator rows (16-byte reads without bank conflicts)
+    T *As = reinterpret_cast<T *>(smem_raw);                               // [ROWS][strideE]
+    uint8_t *cbits = reinterpret_cast<uint8_t *>(As + (size_t)ROWS * strideE);  // [Kp]
+    __shared__ int32_t chunk_off[kOps + 1], op_beg[kOps + 1];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int i = tid; i <= kOps; i += kGemmThreads) {
+        chunk_off[i] = chunk_off_g[i];
+        op_beg[i] = op_beg_g[i];
+    }
+    for (int i = tid; i < Kp; i += kGemmThreads) cbits[i] = (uint8_t)refl_bits(i);
+    __syncthreads();
+    const int U = chunk_off[kOps];
+    const long units = (long)U * nrg;
+    const int u0 = (int)(units * blockIdx.x / gridDim.x), u1 = (int)(units * (blockIdx.x + 1) / gridDim.x);
+    const int steps = Kp / (4 * VEC);
+    const int j = lane & 15, q = lane >> 4;
+    // a unit's operator, row group and pair range, and this lane's pair
+    struct Unit {
+        int op, rg, beg, end;
+        int4 pe;  // {source box, row of R (-1: none), reflection mask, 0}
+    };
+    auto unit_of = [&](int u) {
+        Unit t;
+        t.rg = u / U;
+        const int ch = u - t.rg * U;
+        t.op = 0;  // the bucket holding chunk ch: last o with chunk_off[o] <= ch
+        for (int step = 32; step > 0; step >>= 1)
+            if (t.op + step <= kOps && chunk_off[t.op + step] <= ch) t.op += step;
+        t.beg = op_beg[t.op] + (ch - chunk_off[t.op]) * kCols;
+        t.end = min(t.beg + kCols, op_beg[t.op + 1]);
+        const int col = t.beg + wave * 16 + j;
+        t.pe = col < t.end ? bucket[col] : make_int4(zrow, -1, 0, 0);
+        return t;
+    };
+    // 16 bytes of a pair's source coefficients for step s, with its column signs
+    auto load_b = [&](const int4 &pe, int s) {
+        V v = *reinterpret_cast<const V *>(M + (size_t)pe.x * Kp + q * VEC + (size_t)s * 4 * VEC);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const int k = s * 4 * VEC + q * VEC + e;
+            if (__popc(pe.z & cbits[k]) & 1) v.v[e] = -v.v[e];
+        }
+        return v;
+    };
+    // operator rows of a step from LDS
+    const T *arow = As + (size_t)j * strideE + q * VEC;
+    auto load_a = [&](int s, V *a) {
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) a[r] = *reinterpret_cast<const V *>(arow + (size_t)r * 16 * strideE + s * 4 * VEC);
+    };
+    if (u0 >= u1) return;
+    int cur_op = -1, cur_rg = -1;
+    Unit cu = unit_of(u0);
+    V b0, b1;
+    bool pre = false;  // b0, b1 already hold the current unit's first two steps
+    for (int u = u0; u < u1; ++u) {
+        // the next unit's pair entry is fetched now and its first source loads
+        // are issued during this unit's last two steps, so the matrix work runs
+        // on without a gap between units
+        const bool has_next = u + 1 < u1;
+        Unit nx = cu;
+        if (has_next) nx = unit_of(u + 1);
+        if (cu.op != cur_op || cu.rg != cur_rg) {
+            __syncthreads();  // every wave is done with the previous rows
+            const T *src = A + (size_t)cu.op * Kp * Kp;
+            const int row0 = cu.rg * ROWS;
+            const int vecs = ROWS * (Kp / VEC);
+            for (int e = tid; e < vecs; e += kGemmThreads) {
+                const int r = e / (Kp / VEC), c = (e - r * (Kp / VEC)) * VEC;
+                V v;
+                if (row0 + r < Kp) v = *reinterpret_cast<const V *>(src + (size_t)(row0 + r) * Kp + c);
+                else
+                    for (int k = 0; k < VEC; ++k) v.v[k] = T(0);
+                *reinterpret_cast<V *>(As + (size_t)r * strideE + c) = v;
+            }
+            __syncthreads();
+            cur_op = cu.op;
+            cur_rg = cu.rg;
+        }
+        if (!pre) {
+            b0 = load_b(cu.pe, 0);
+            b1 = steps > 1 ? load_b(cu.pe, 1) : b0;
+        }
+        typename MF::v4 acc[NRB];
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) acc[r] = typename MF::v4{0, 0, 0, 0};
+        V a0[NRB], a1[NRB];
+        load_a(0, a0);
+        const bool cross = has_next && steps >= 2;
+        for (int s = 0; s < steps; ++s) {
+            V b2 = b1;
+            if (s + 2 < steps) b2 = load_b(cu.pe, s + 2);
+            else if (cross) b2 = load_b(nx.pe, s + 2 - steps);
+            if (s + 1 < steps) load_a(s + 1, a1);
+            // consecutive instructions update different accumulators, so
+            // none waits for the previous one's result
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+#pragma unroll
+                for (int r = 0; r < NRB; ++r) acc[r] = MF::op(a0[r].v[e], b0.v[e], acc[r]);
+#pragma unroll
+            for (int r = 0; r < NRB; ++r) a0[r] = a1[r];
+            b0 = b1;
+            b1 = b2;
+        }
+        pre = cross;
+        if (cu.pe.y >= 0) {
+            const int row0 = cu.rg * ROWS;
+            T *dst = R + (size_t)cu.pe.y * Kp + row0;
+#pragma unroll
+            for (int r = 0; r < NRB; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = r * 16 + MF::row(lane, e);
+                    if (row0 + row < Kp) {
+                        const T v = acc[r][e];
+                        dst[row] = (__popc(cu.pe.z & cbits[row0 + row]) & 1) ? -v : v;
+                    }
+                }
+        }
+        cu = nx;
+    }
+}
+
+// Pass 5: L_T = sum of T's rows of R in order (zero for boxes above level 2
+// or without V pairs); a box's rows run from pair_off[b] to the next box's
+// first row (npairs after the last box).  One thread per 16 bytes of
+// coefficients; the row loads are issued in groups of 8 ahead of their
+// additions, which stay in row order.
+template <typename T>
+__global__ void k_m2l_sum(const TreeSummary *__restrict__ sum, int Kp, const uint32_t *__restrict__ pair_off,
+                          const uint32_t *__restrict__ npairs, const T *__restrict__ R, T *__restrict__ L)
+{
+    using V = Vec16<T>;
+    constexpr int VEC = V::N;
+    const int nbox = sum->nbox;
+    const int per_box = Kp / VEC;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)nbox * per_box;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int b = (int)(e / per_box), c = (int)(e - (size_t)b * per_box) * VEC;
+        const int n = (int)((b + 1 < nbox ? pair_off[b + 1] : *npairs) - pair_off[b]);
+        const T *r = R + (size_t)pair_off[b] * Kp + c;
+        V acc;
+        for (int i = 0; i < VEC; ++i) acc.v[i] = T(0);
+        int k = 0;
+        for (; k + 8 <= n; k += 8) {
+            V v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const V *>(r + (size_t)(k + u) * Kp);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) acc.v[i] += v[u].v[i];
+        }
+        for (; k < n; ++k) {
+            const V v = *reinterpret_cast<const V *>(r + (size_t)k * Kp);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc.v[i] += v.v[i];
+        }
+        *reinterpret_cast<V *>(L + (size_t)b * Kp + c) = acc;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+void launch_m2l_count(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
+                      uint32_t *pcnt, uint32_t *cnt_ob, uint32_t *scan_part, uint32_t *npairs, hipStream_t st)
+{
+    if (nbox <= 0) return;
+    k_m2l_count<<<nbox, 256, 0, st>>>(bt, sum, vtab, slots, pcnt, cnt_ob);
+    // pcnt -> first row of R per box (CSR); cnt_ob -> first bucket place per (operator, box)
+    launch_scan(pcnt, nbox, scan_part, npairs, st);
+    launch_scan(cnt_ob, kOps * nbox, scan_part, nullptr, st);
+}
+
+int m2l_ops() { return kOps; }
+
+void launch_m2l_emit(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
+                     const uint32_t *pair_off, const uint32_t *ob_off, const uint32_t *npairs, int4 *bucket,
+                     int32_t *op_beg, int32_t *chunk_off, hipStream_t st)
+{
+    if (nbox <= 0) return;
+    k_m2l_emit<<<nbox, 256, 0, st>>>(bt, sum, vtab, slots, pair_off, ob_off, bucket);
+    k_m2l_chunks<<<1, 64, 0, st>>>(sum, ob_off, npairs, op_beg, chunk_off);
+}
+
+// Row blocks of 16 per workgroup: as many as fit the LDS share of one
+// workgroup (two per compute unit beside the near field), balanced over the
+// row groups.
+template <typename T>
+static int m2l_row_blocks(int Kp, int &nrg)
+{
+    const int blocks = Kp / 16;
+    const size_t per_block = (size_t)16 * (Kp + 16 / sizeof(T)) * sizeof(T);
+    const int fit = std::max(1, (int)(kM2LLdsBudget / per_block));
+    nrg = ceil_div(blocks, std::min(fit, kM2LMaxRowBlocks));
+    return ceil_div(blocks, nrg);
+}
+
+template <typename T>
+size_t m2l_gemm_lds(int Kp)
+{
+    int nrg;
+    const int nrb = m2l_row_blocks<T>(Kp, nrg);
+    return (size_t)nrb * 16 * (Kp + 16 / sizeof(T)) * sizeof(T) + (size_t)Kp;
+}
+
+template <typename T>
+int m2l_per_cu(int Kp, size_t lds_beside)
+{
+    const size_t lds = m2l_gemm_lds<T>(Kp) + 2 * (kOps + 1) * sizeof(int32_t);
+    const size_t room = kLdsPerCU > lds_beside ? kLdsPerCU - lds_beside : 0;
+    return std::max(1, std::min(kM2LMaxPerCU, (int)(room / lds)));
+}
+
+template <typename T>
+void launch_m2l_gemm(int Kp, int nbox, int grid, const int32_t *chunk_off, const int32_t *op_beg, const int4 *bucket,
+                     const T *A, const T *M, T *R, hipStream_t st)
+{
+    int nrg;
+    const int nrb = m2l_row_blocks<T>(Kp, nrg);
+    const size_t lds = m2l_gemm_lds<T>(Kp);
+    switch (nrb) {
+#define PT_G(NB) \
+    case NB: k_m2l_gemm<T, NB><<<grid, kGemmThreads, lds, st>>>(Kp, nrg, nbox, chunk_off, op_beg, bucket, A, M, R); break;
+        PT_G(1) PT_G(2) PT_G(3) PT_G(4) PT_G(5) PT_G(6)
+#undef PT_G
+    default: break;
+    }
+}
+
+template <typename T>
+void launch_m2l_sum(const TreeSummary *sum, int nbox, int Kp, const uint32_t *pair_off, const uint32_t *npairs,
+                    const T *R, T *L, hipStream_t st)
+{
+    const size_t tot = (size_t)nbox * (Kp / (16 / sizeof(T)));
+    if (tot)
+        k_m2l_sum<T><<<(unsigned)std::min<size_t>((tot + 63) / 64, 65535), 64, 0, st>>>(sum, Kp, pair_off, npairs, R,
+                                                                                      L);
+}
+
+template int m2l_per_cu<float>(int, size_t);
+template int m2l_per_cu<double>(int, size_t);
+template size_t m2l_gemm_lds<float>(int);
+template size_t m2l_gemm_lds<double>(int);
+template void launch_m2l_gemm<float>(int, int, int, const int32_t *, const int32_t *, const int4 *, const float *,
+                                     const float *, float *, hipStream_t);
+template void launch_m2l_gemm<double>(int, int, int, const int32_t *, const int32_t *, const int4 *, const double *,
+                                      const double *, double *, hipStream_t);
+template void launch_m2l_sum<float>(const TreeSummary *, int, int, const uint32_t *, const uint32_t *,
+                                    const float *, float *, hipStream_t);
+template void launch_m2l_sum<double>(const TreeSummary *, int, int, const uint32_t *, const uint32_t *,
+                                     const double *, double *, hipStream_t);
+
+}  // namespace pt

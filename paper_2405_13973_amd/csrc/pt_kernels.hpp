@@ -109,20 +109,7 @@ void launch_p2m(const BoxTable &bt, const double *sp, int ntot, int p, const Tre
 template <typename T>
 void launch_m2m(const BoxTable &bt, int p, const TreeSummary &hs, const T *m2m_pad, const int2 *oct_slots,
                 const int32_t *child_oct, T *M, T *part, hipStream_t st);
-// m2l_pad: 64 base operators (offsets with non-negative components, index
-// m2l_base), each Kp x Kp column-major (A[j][i] = T[i][j]), zero-padded;
-// slots: per parity the 189 non-touching window slots {slot, base operator +
-// 256 x reflection mask (bit 0: dx < 0, bit 1: dy < 0, bit 2: dz < 0)};
-// cnt: 8 ints (zero on entry to launch_m2l_bucket), list: 8 x nbox ints,
-// part: ngroup x nbox x Kp of workspace.
-void launch_m2l_bucket(const BoxTable &bt, int nbox, int32_t *cnt, int32_t *list, hipStream_t st);
-template <typename T>
-void launch_m2l(const BoxTable &bt, int p, const TreeSummary &hs, const int32_t *vtab, const int2 *slots,
-                const T *m2l_pad, const T *M, const int32_t *cnt, const int32_t *list, T *part, int ngroup,
-                hipStream_t st);
-template <typename T>
-void launch_m2l_reduce(const BoxTable &bt, int p, int nbox, const T *part, int ngroup, T *L, hipStream_t st);
-int m2l_groups(int n2);  // slot groups of M2L (partial-sum buffer: groups x nbox x Kp; M2M/L2L use <= 8)
+int m2l_groups(int n2);  // slot groups of M2M / L2L partial sums (partial-sum buffer: groups x nbox x Kp)
 template <typename T>
 void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_pad, const int2 *oct_slots,
                      const int32_t *parent_oct, T *L, T *part, hipStream_t st);
@@ -137,12 +124,53 @@ void launch_near(const BoxTable &bt, const double *sp, int ntot, const int2 *nea
 // beside the near field: with this many, one GEMM workgroup still fits in
 // every compute unit's LDS, whichever kernel reaches the unit first.
 constexpr int kNearPerCUConcurrent = 6;
+// LDS of one near-field workgroup (its staged sources and range tables).
+size_t near_lds_bytes();
 // Far field (L2P) + the item partials per ion into E (batch order); with phi
 // non-null also the potential per unit charge (part then holds 4 components).
 template <typename T>
 void launch_far(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
                 const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals, double *E,
                 double *phi, int leaf_size, hipStream_t st);
+
+// k_m2l.hip: M2L organised by base operator.
+// slots: per parity the 189 non-touching window slots {slot, base operator +
+// 256 x reflection mask (bit 0: dx < 0, bit 1: dy < 0, bit 2: dz < 0)}.
+// launch_m2l_count: pcnt (nbox) and cnt_ob (m2l_ops() x nbox) are scanned in
+// place (pcnt -> first row of R per box, cnt_ob -> first bucket place per
+// (operator, box)); npairs <- the number of V pairs.  scan_part needs
+// scan_partials(m2l_ops() * nbox) + 1 words.
+int m2l_ops();
+void launch_m2l_count(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
+                      uint32_t *pcnt, uint32_t *cnt_ob, uint32_t *scan_part, uint32_t *npairs, hipStream_t st);
+// bucket: npairs int4 {source box, row of R, reflection mask, 0}; op_beg and
+// chunk_off: m2l_ops() + 1 ints each.
+void launch_m2l_emit(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
+                     const uint32_t *pair_off, const uint32_t *ob_off, const uint32_t *npairs, int4 *bucket,
+                     int32_t *op_beg, int32_t *chunk_off, hipStream_t st);
+// LDS of one GEMM workgroup: at most this much for the operator rows, and at
+// most this many row blocks of 16 (compiled variants).
+constexpr size_t kM2LLdsBudget = 48 << 10;
+constexpr int kM2LMaxRowBlocks = 6;
+template <typename T>
+size_t m2l_gemm_lds(int Kp);
+// A: the 64 base operators, row-major Kp x Kp each (row = output coefficient),
+// zero padded; M: nbox + 1 expansion rows (row nbox zero); R: npairs x Kp.
+template <typename T>
+void launch_m2l_gemm(int Kp, int nbox, int grid, const int32_t *chunk_off, const int32_t *op_beg, const int4 *bucket,
+                     const T *A, const T *M, T *R, hipStream_t st);
+// L = per box the sum of its rows of R in order (pair_off: the scanned pcnt).
+template <typename T>
+void launch_m2l_sum(const TreeSummary *sum, int nbox, int Kp, const uint32_t *pair_off, const uint32_t *npairs,
+                    const T *R, T *L, hipStream_t st);
+// Persistent M2L workgroups per compute unit: as many as the LDS holds (at
+// most kM2LMaxPerCU) next to lds_beside bytes taken by a kernel running
+// beside it; the grid is sized to what can be resident, since the static
+// split of the work would leave late-starting workgroups as a tail.
+constexpr size_t kLdsPerCU = 160 << 10;
+constexpr int kM2LMaxPerCU = 4;
+template <typename T>
+int m2l_per_cu(int Kp, size_t lds_beside);
 
 // noalloc.hip: the fixed scratch of pt_compute_forces_noalloc (direct sum of
 // one crystal of at most kNoAllocMaxIons ions).

@@ -234,7 +234,14 @@ static pt_status ensure_tables(pt_ctx *ctx, int p)
     m2l.swap(base);
     pad_cm(m2m, 8);
     pad_cm(l2l, 8);
-    pad_cm(m2l, 64);
+    // M2L operators row-major (row = output coefficient), zero-padded to Kp x Kp
+    {
+        std::vector<double> pad((size_t)64 * Kp * Kp, 0.0);
+        for (int c = 0; c < 64; ++c)
+            for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j) pad[(size_t)c * Kp * Kp + (size_t)i * Kp + j] = m2l[c * KK + (size_t)i * K + j];
+        m2l.swap(pad);
+    }
     auto upload = [&](const std::vector<double> &v, double **dd, float **df) -> pt_status {
         PT_TRY(ctx_alloc(ctx, (void **)dd, v.size() * sizeof(double)));
         PT_HIP(hipMemcpy(*dd, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -605,55 +612,67 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "near_pairs", sizeof(int64_t) * (size_t)nbox, &near_pairs));
     int32_t *cuts;
     PT_TRY(ws_get(ctx, "p2p_cuts", sizeof(int32_t) * (size_t)stride * nbox, &cuts));
-    PT_TRY(ws_get(ctx, "scan_part", sizeof(uint32_t) * (scan_partials(std::max(scan_n, nbox)) + 1), &scan_part));
+    PT_TRY(ws_get(ctx, "scan_part",
+                  sizeof(uint32_t) * (scan_partials(std::max(std::max(scan_n, nbox), m2l_ops() * nbox)) + 1),
+                  &scan_part));
+    uint32_t *m2l_pcnt, *m2l_cnt_ob;
+    PT_TRY(ws_get(ctx, "m2l_pcnt", sizeof(uint32_t) * (size_t)nbox, &m2l_pcnt));
+    PT_TRY(ws_get(ctx, "m2l_cnt_ob", sizeof(uint32_t) * (size_t)m2l_ops() * nbox, &m2l_cnt_ob));
     launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, v_blk, near_pairs, child_oct, parent_oct, item_off,
                  src_items, cuts, scan_part, total + 1, st);
-    // near-field work items: their number sizes the item and partial buffers.
-    // It is read back while the upward pass, which does not need it, runs: the
-    // host waits for an event right after the copy, not for the stream.
-    PT_HIP(hipMemcpyAsync(ctx->h_counters, total + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    // M2L pairs: counted and scanned here, so that their number comes back
+    // with the near-field item count
+    launch_m2l_count(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, scan_part, total + 2, st);
+    // near-field work items and M2L pairs: their numbers size the item,
+    // partial and pair buffers.  They are read back while the upward pass,
+    // which does not need them, runs: the host waits for an event right after
+    // the copy, not for the stream.
+    PT_HIP(hipMemcpyAsync(ctx->h_counters, total + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     PT_HIP(hipEventRecord(ctx->ev_read, st));
-    int32_t *m2l_cnt, *m2l_list, *p2p_queue;
-    void *m2l_part;
+    int32_t *p2p_queue;
+    void *xl_part;
     const int ngroup = m2l_groups(nbox - hs.level_start[2]);
-    PT_TRY(ws_get(ctx, "m2l_cnt", sizeof(int32_t) * 8, &m2l_cnt));
     PT_TRY(ws_get(ctx, "p2p_queue", sizeof(uint64_t), &p2p_queue));
-    PT_TRY(ws_get(ctx, "m2l_list", sizeof(int32_t) * 8 * (size_t)nbox, &m2l_list));
-    PT_TRY(ws_get(ctx, "m2l_part", esz * Kp * (size_t)nbox * std::max(ngroup, 8), (char **)&m2l_part));
+    PT_TRY(ws_get(ctx, "xl_part", esz * Kp * (size_t)nbox * ngroup, (char **)&xl_part));
     mark(ctx, 1);
     const Tables &tb = ctx->tables;
-    // the zero rows of M and L, the M2L bucket counters and the near-field
-    // item queue, in one launch
+    // the zero rows of M and L and the near-field item queue, in one launch
     ZeroRegions zr{};
     zr.p[0] = (uint64_t *)((char *)M + esz * Kp * (size_t)nbox);
     zr.p[1] = (uint64_t *)((char *)L + esz * Kp * (size_t)nbox);
-    zr.p[2] = (uint64_t *)m2l_cnt;
-    zr.p[3] = (uint64_t *)p2p_queue;
+    zr.p[2] = (uint64_t *)p2p_queue;
     zr.n[0] = zr.n[1] = (int)(esz * Kp / 8);
-    zr.n[2] = 4;  // 8 int32 counters
-    zr.n[3] = 1;
+    zr.n[2] = 1;
     launch_zero_regions(zr, st);
     auto upward = [&](auto tag) -> pt_status {
         using T = decltype(tag);
         const T *m2m = sizeof(T) == sizeof(float) ? (const T *)tb.m2m_f : (const T *)tb.m2m_d;
         PT_HIP(hipStreamWaitEvent(st, ctx->ev_p2m, 0));  // P2M (second stream)
-        launch_m2m<T>(bt, p, hs, m2m, tb.oct_slots, child_oct, (T *)M, (T *)m2l_part, st);
-        launch_m2l_bucket(bt, nbox, m2l_cnt, m2l_list, st);
+        launch_m2m<T>(bt, p, hs, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, st);
         return PT_OK;
     };
     PT_TRY(fp.precision == 1 ? upward(float(0)) : upward(double(0)));
     PT_HIP(hipEventSynchronize(ctx->ev_read));
-    const int n_items = (int)*(uint32_t *)ctx->h_counters;
-    int4 *work;
+    const int n_items = (int)((uint32_t *)ctx->h_counters)[0];
+    const int n_pairs = (int)((uint32_t *)ctx->h_counters)[1];
+    int4 *work, *m2l_bucket;
+    int32_t *m2l_ops_tab;
+    void *m2l_R;
+    PT_TRY(ws_get(ctx, "m2l_bucket", sizeof(int4) * (size_t)std::max(1, n_pairs), &m2l_bucket));
+    PT_TRY(ws_get(ctx, "m2l_ops_tab", sizeof(int32_t) * 2 * (m2l_ops() + 1), &m2l_ops_tab));
+    PT_TRY(ws_get(ctx, "m2l_R", esz * Kp * (size_t)std::max(1, n_pairs), (char **)&m2l_R));
+    int32_t *m2l_op_beg = m2l_ops_tab, *m2l_chunk_off = m2l_ops_tab + m2l_ops() + 1;
     void *ppart;
     PT_TRY(ws_get(ctx, "p2p_work", sizeof(int4) * (size_t)std::max(1, n_items), &work));
     const int ncomp = phi ? 4 : 3;  // near-field partial components per target
     PT_TRY(ws_get(ctx, "p2p_part", esz * 64 * ncomp * (size_t)std::max(1, n_items), (char **)&ppart));
     launch_p2p_items(bt, dsum, nbox, near_cnt, stride, item_off, src_items, cuts, work, st);
+    launch_m2l_emit(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, total + 2, m2l_bucket, m2l_op_beg,
+                    m2l_chunk_off, st);
     auto run = [&](auto tag) -> pt_status {
         using T = decltype(tag);
         const bool f = sizeof(T) == sizeof(float);
-        const T *m2l = f ? (const T *)tb.m2l_f : (const T *)tb.m2l_d;
+        const T *m2l = f ? (const T *)tb.m2l_f : (const T *)tb.m2l_d;  // row-major base operators
         const T *l2l = f ? (const T *)tb.l2l_f : (const T *)tb.l2l_d;
         const T *rec = f ? (const T *)tb.rec_f : (const T *)tb.rec_d;
         // near field on its own stream, concurrently with M2L and L2L (vector
@@ -683,10 +702,13 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         };
         if (concurrent) PT_TRY(near_field());
         mark(ctx, 2);
-        launch_m2l<T>(bt, p, hs, vtab, tb.slots, m2l, (const T *)M, m2l_cnt, m2l_list, (T *)m2l_part, ngroup, st);
+        const int m2l_grid =
+            ctx->num_cu * m2l_per_cu<T>(Kp, concurrent ? kNearPerCUConcurrent * near_lds_bytes() : 0);
+        launch_m2l_gemm<T>(Kp, nbox, m2l_grid, m2l_chunk_off, m2l_op_beg, m2l_bucket, m2l, (const T *)M,
+                           (T *)m2l_R, st);
         mark(ctx, 3);
-        launch_m2l_reduce<T>(bt, p, nbox, (const T *)m2l_part, ngroup, (T *)L, st);
-        launch_downward<T>(bt, p, hs, l2l, tb.oct_slots, parent_oct, (T *)L, (T *)m2l_part, st);
+        launch_m2l_sum<T>(dsum, nbox, Kp, m2l_pcnt, total + 2, (const T *)m2l_R, (T *)L, st);
+        launch_downward<T>(bt, p, hs, l2l, tb.oct_slots, parent_oct, (T *)L, (T *)xl_part, st);
         mark(ctx, 4);
         if (!concurrent) PT_TRY(near_field());
         mark(ctx, 5);

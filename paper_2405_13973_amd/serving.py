@@ -5,7 +5,11 @@ server admits waiting requests while the device memory they would take fits the
 budget -- their own state plus the growth of the shared batch workspace, from
 the context's measured memory and a per-ion workspace rate that starts from an
 estimate for the expansion degree and leaf size and follows the measured
-high-water mark -- then advances every resident crystal by up to `chunk` steps in one
+high-water mark.  The estimate can fall short; the context's own HBM budget is
+the hard limit: a tick that runs out of it (PT_ENOMEM, which leaves every
+crystal at its last completed step) sends the newest request that has not
+stepped yet back to the head of the queue, raises the rate and runs again.
+Then it advances every resident crystal by up to `chunk` steps in one
 pt_step_batch call -- every phase of a step is one launch for all resident
 crystals, whatever their sizes -- and retires the finished ones.  A request's
 state stays in HBM from admission to completion.  Results do not depend on
@@ -37,12 +41,13 @@ def workspace_bytes_per_ion(p: int, leaf: int, precision: str) -> float:
     """Estimate of the batch workspace per ion of the FMM step: per ion the sort
     keys and values, tree scratch, sorted positions, field and working state
     (about 200 B); per box (about 3.5 boxes per leaf-size ions) the box table,
-    colleague, window and near lists (about 2.4 kB) and 14 expansion rows of
-    (p+1)^2 coefficients padded to 16 (M, L and the M2L partial sums); 25 % on
-    top for the workspace's growth rule."""
+    colleague, window and near lists (about 2.4 kB), 10 expansion rows of
+    (p+1)^2 coefficients padded to 16 (M, L and the translation partial sums)
+    and one row per M2L pair (about 150 pairs per box); 25 % on top for the
+    workspace's growth rule."""
     kp = ((p + 1) ** 2 + 15) // 16 * 16
     esz = 4 if precision == "mixed" else 8
-    per_box = 2400 + 14 * kp * esz
+    per_box = 2400 + (10 + 150) * kp * esz
     return 1.25 * (200 + 3.5 / max(1, leaf) * per_box)
 
 
@@ -98,6 +103,7 @@ class Server:
         # workspace bytes per resident ion: the estimate, raised to the measured
         # high-water mark after every tick
         self.ws_rate = workspace_bytes_per_ion(p, leaf, precision)
+        self.requeued = 0  # admissions undone after the context ran out of memory
 
     def _projected(self, base, resident_ions, resident_state, n_new):
         """Device bytes in use if a request of n_new ions joined the residents:
@@ -122,7 +128,7 @@ class Server:
         order = sorted(range(len(requests)), key=lambda i: requests[i].arrival_s)
         pending = collections.deque(order)
         waiting = collections.deque()
-        active = []  # [index, crystal, remaining, admit_s]
+        active = []  # [index, crystal, remaining, admit_s, step at admission]
         done = []
         ion_steps = 0
         max_res = max_bytes = 0
@@ -146,7 +152,7 @@ class Server:
                         break
                     raise
                 waiting.popleft()
-                active.append([i, c, requests[i].steps, now])
+                active.append([i, c, requests[i].steps, now, 0])  # index, crystal, remaining, admit time, step0
             max_res = max(max_res, len(active))
             if not active:
                 if pending:
@@ -155,7 +161,26 @@ class Server:
                         self.sleep(min(wait, 0.05))
                 continue
             n = [min(a[2], self.chunk) for a in active]
-            self.native.step_batch([a[1] for a in active], n)
+            try:
+                self.native.step_batch([a[1] for a in active], n)
+            except self.native.PTError as e:
+                if e.code != self.native.PT_ENOMEM:
+                    raise
+                # every crystal stands at its last completed step: count them
+                for a in active:
+                    done_now = a[1].read_state()["step"] - a[4]
+                    ion_steps += (done_now - (requests[a[0]].steps - a[2])) * a[1].n
+                    a[2] = requests[a[0]].steps - done_now
+                fresh = [a for a in active if a[2] == requests[a[0]].steps]
+                if len(active) == 1 or not fresh:
+                    raise
+                back = fresh[-1]
+                active.remove(back)
+                back[1].destroy()
+                waiting.appendleft(back[0])
+                self.ws_rate *= 1.25
+                self.requeued += 1
+                continue
             self.ctx.synchronize()
             used = self.ctx.memory()[0]
             max_bytes = max(max_bytes, used)

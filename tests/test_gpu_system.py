@@ -249,14 +249,17 @@ def test_budget_exhaustion_and_busy_context():
 def test_serving_admission_under_a_small_budget():
     say("serving admission")
     reqs = inputs.serving_stream(count=12, rate_hz=1e4, seed=15, n_lo=500, n_hi=3000, k_lo=5, k_hi=20)
-    with native.Context(0) as c:
-        # the operator tables (p = 8) and three of the largest requests
-        k = make(c, reqs[0].crystal, "fmm", 8, 32, "mixed")
+    with native.Context(0) as probe:
+        # the operator tables (p = 8) and the workspace of one request
+        k = make(probe, reqs[0].crystal, "fmm", 8, 32, "mixed")
         k.compute_forces()
         k.destroy()
-        budget = c.memory()[0] + 3 * serving.footprint(3000, 8, 32, "mixed")
+        budget = probe.memory()[0] + 3 * serving.footprint(3000, 8, 32, "mixed")
+    # the server plans with its estimate; the context's budget is the hard limit
+    with native.Context(0, hbm_budget=budget) as c:
         srv = serving.Server(c, native, budget_bytes=budget, precision="mixed", p=8, leaf=32, chunk=5)
         rep = srv.run(reqs)
+    say(f"   max resident {rep.max_resident}, {rep.max_resident_bytes} of {budget} bytes, requeued {srv.requeued}")
     assert sorted(d.index for d in rep.done) == list(range(len(reqs)))
     assert rep.max_resident_bytes <= budget
     assert all(d.steps == reqs[d.index].steps for d in rep.done)

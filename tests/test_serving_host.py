@@ -43,7 +43,9 @@ class FakeNative:
     PT_ENOMEM = -2
 
     class PTError(RuntimeError):
-        code = 0
+        def __init__(self, code):
+            super().__init__(code)
+            self.code = code
 
     def __init__(self, clock, sec_per_ion_step, ctx=None):
         self.clock, self.rate = clock, sec_per_ion_step
@@ -51,9 +53,13 @@ class FakeNative:
         self.ctx = ctx
 
     def step_batch(self, cs, n):
-        self.calls.append([(c.n, k) for c, k in zip(cs, n)])
         if self.ctx is not None:  # the batch workspace grows to the batch, never shrinks
-            self.ctx.ws = max(self.ctx.ws, int(self.ctx.ws_per_ion * sum(c.n for c in cs)))
+            need = max(self.ctx.ws, int(self.ctx.ws_per_ion * sum(c.n for c in cs)))
+            live = self.ctx.memory()[0] - self.ctx.ws
+            if self.ctx.hard_budget and live + need > self.ctx.hard_budget:
+                raise self.PTError(self.PT_ENOMEM)  # nothing stepped, as in the library
+            self.ctx.ws = need
+        self.calls.append([(c.n, k) for c, k in zip(cs, n)])
         for c, k in zip(cs, n):
             c.steps += k
         # time advances with the work of the longest crystal in the batch
@@ -68,9 +74,10 @@ class FakeCtx:
     """Device memory as the library counts it: each live crystal's state plus a
     grow-only batch workspace of ws_per_ion bytes per ion of the largest batch."""
 
-    def __init__(self, ws_per_ion=300.0):
+    def __init__(self, ws_per_ion=300.0, hard_budget=0):
         self.created = []
         self.ws, self.ws_per_ion = 0, ws_per_ion
+        self.hard_budget = hard_budget
 
     def crystal(self, pos, vel, q, m, seed):
         c = FakeCrystal(None, len(pos))
@@ -170,3 +177,24 @@ def test_admission_learns_the_measured_workspace():
     assert len(rep.done) == 6
     assert srv.ws_rate >= ctx.ws_per_ion * 0.999
     assert rep.max_resident_bytes <= budget
+
+
+def test_out_of_memory_tick_requeues_the_newest_request():
+    """The context's own budget is the hard limit: when the workspace outgrows the
+    estimate so that a tick fails with PT_ENOMEM, the newest request that has not
+    stepped goes back to the head of the queue and every request still completes,
+    without the memory in use ever passing the budget."""
+    clk = FakeClock()
+    n = 4000
+    true_rate = 4 * serving.workspace_bytes_per_ion(11, 32, "mixed")
+    budget = int(2.5 * (serving.state_bytes(n) + true_rate * n))
+    ctx = FakeCtx(ws_per_ion=true_rate, hard_budget=budget)
+    nat = FakeNative(clk, 1e-9, ctx)
+    reqs = _reqs([n] * 5, [20] * 5, [0.0] * 5)
+    srv = serving.Server(ctx, nat, budget_bytes=budget, chunk=5, clock=clk, sleep=clk.sleep)
+    rep = srv.run(reqs)
+    assert sorted(d.index for d in rep.done) == list(range(5))
+    assert all(d.steps == 20 for d in rep.done)
+    assert srv.requeued >= 1
+    assert rep.max_resident_bytes <= budget
+    assert rep.ion_steps == 5 * 20 * n
