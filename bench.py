@@ -106,6 +106,7 @@ def timed_steps(ctx, c, steps, warmup, sync, phases_too=True):
         ctx.set_timing(True)
     t0 = time.perf_counter()
     c.step(steps)
+    ctx.synchronize()  # also reads back the queued steps' outcome (and re-runs any that overflowed)
     sync()
     t1 = time.perf_counter()
     phases, count, wc, plain = None, 0, None, None
@@ -118,6 +119,7 @@ def timed_steps(ctx, c, steps, warmup, sync, phases_too=True):
         sync()
         t2 = time.perf_counter()
         c.step(steps)
+        ctx.synchronize()
         sync()
         plain = time.perf_counter() - t2
         c.set_state(end["pos"], end["vel"], end["step"])
@@ -381,9 +383,11 @@ def bench_ensemble(a, ctx, sync):
         c.set_state(cr.pos, cr.vel, 0)
         c.set_force("fmm", a.p, a.leaf, a.precision)
     native.step_batch(cs, [a.warmup] * len(cs))
+    ctx.synchronize()
     sync()
     t0 = time.perf_counter()
     native.step_batch(cs, [a.steps] * len(cs))
+    ctx.synchronize()
     sync()
     el = time.perf_counter() - t0
     # per-phase times from a few more, instrumented steps (phase timing waits
@@ -394,7 +398,9 @@ def bench_ensemble(a, ctx, sync):
     phases = ctx.phase_times()
     ctx.set_timing(False)
     value = ntot * a.steps / el
-    log(f"  {a.steps} batched steps in {el * 1e3:.1f} ms -> {value:.4g} ion-steps/s; max rms err {max(errs):.2e}")
+    stats = ctx.step_stats()
+    log(f"  {a.steps} batched steps in {el * 1e3:.1f} ms -> {value:.4g} ion-steps/s; max rms err {max(errs):.2e}; "
+        f"step evaluations so far {stats}")
     return {
         "metric": "ensemble ion-steps/s (256 crystals, N log-uniform 100..20000, one launch per phase per step)",
         "value": value, "unit": "ion-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -404,8 +410,7 @@ def bench_ensemble(a, ctx, sync):
                                f"f_z~U[1,2] MHz, photon mean~U[0,0.05], FMM p={a.p} leaf {a.leaf} ({a.precision})",
                    "crystals": len(crs), "ions": ntot, "p": a.p, "leaf_size": a.leaf,
                    "max_rms_rel_force_err_largest3": max(errs)},
-        "details": {"phase_ms": {k: float(v) for k, v in zip(
-            PHASES, phases)}},
+        "details": {"phase_ms": {k: float(v) for k, v in zip(PHASES, phases)}, "step_evaluations": stats},
     }
 
 

@@ -24,9 +24,10 @@
  *     No call throws across the ABI.  Calls on one context are not
  *     thread-safe: serialise them.
  *   - Work is queued on the context's HIP stream.  pt_step and
- *     pt_step_batch return once their work is queued (a force evaluation
- *     with the FMM waits once per step for the tree's size); pt_read_state,
- *     pt_compute_forces and pt_synchronize wait for completion.
+ *     pt_step_batch return once their work is queued (with the FMM, only the
+ *     first step of a new batch waits, twice, to measure its tree);
+ *     pt_read_state, pt_compute_forces and pt_synchronize wait for
+ *     completion.
  */
 #ifndef PENNING_H
 #define PENNING_H
@@ -237,7 +238,18 @@ pt_status pt_read_rotating_state(pt_crystal *c, double *pos_r, double *vel_r);
 pt_status pt_step(pt_crystal *c, int64_t n_steps);
 /* Advance crystal k by n_steps[k] steps; crystals still stepping are
  * batched together so that each phase of a step is one launch for all of
- * them.  Results are identical to stepping each crystal alone. */
+ * them.  Results are identical to stepping each crystal alone.
+ * With the FMM, the first step of a batch measures its tree and lists (two
+ * host waits) and sizes the work buffers for them with room to grow; the
+ * following steps are queued with no host wait, the kernels reading every
+ * count on the device.  If a step's tree or lists outgrow that room, the
+ * device stops the run before that step's kick (state and photon counts stay
+ * at the last completed step), and the context's next call (any call, e.g.
+ * pt_synchronize or pt_read_state) reads this back and runs the remaining
+ * steps again from there, measuring first: results do not depend on it.
+ * Errors: PT_EINVAL (NULL, negative counts, batch rules), PT_ENOMEM and
+ * PT_EDEVICE (the crystals then stand at their last completed step, which
+ * pt_read_state reports). */
 pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_steps);
 pt_status pt_synchronize(pt_ctx *ctx);
 
@@ -275,6 +287,13 @@ pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[7], int64_t *count);
 /* Work counts of the last FMM evaluation: [0] boxes, [1] leaves, [2] M2L
  * pairs, [3] P2P pairs (ordered, i != j counted), [4] levels, [5] ions. */
 pt_status pt_ctx_work_counts(pt_ctx *ctx, int64_t counts[6]);
+
+/* Step statistics since the context was created (each pointer nullable):
+ * FMM evaluations of steps queued on capacities, FMM evaluations that
+ * measured their batch's counts (with host waits), and runs of queued steps
+ * that a capacity overflow sent back (see pt_step_batch).  Waits for pending
+ * steps. */
+pt_status pt_ctx_step_stats(pt_ctx *ctx, int64_t *queued, int64_t *measured, int64_t *reruns);
 
 const char *pt_last_error(void);
 

@@ -33,14 +33,15 @@ static int p2m_chunk(int Kp, int leaf_size)
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const double *__restrict__ sp, int ntot, int p, int Kp,
-                                            int chunk, const T *__restrict__ rec, T *__restrict__ M)
+__global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const TreeSummary *__restrict__ sum,
+                                            const double *__restrict__ sp, int ntot, int p, int Kp, int chunk,
+                                            const T *__restrict__ rec, T *__restrict__ M)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *C = reinterpret_cast<T *>(smem_raw);  // [Kp][chunk + 1]
     __shared__ T rec_s[2 * kq(kMaxP)];      // the recurrence fields the expansion needs
     const int b = blockIdx.x;
-    if (!bt.leaf[b]) return;
+    if (sum->halt || b >= sum->nbox || !bt.leaf[b]) return;
     const double4 g = bt.geo[b];
     const double ih = 1.0 / g.w;
     const int K = kcoef(p);
@@ -135,7 +136,13 @@ struct XlateArgs {
     const int32_t *list;  // bucket lists, list_stride apart
     int list_stride;
     int nbucket;          // 8 (by parity) or 1
-    int b0, nrange;       // target range when cnt == nullptr
+    // target range when cnt == nullptr: [b0, b0 + nrange), or with lvl non-null
+    // the boxes of tree level `level`, [lvl[level], lvl[level + 1]) read on
+    // the device (lvl = the summary's level_start)
+    int b0, nrange;
+    const int32_t *lvl;
+    int level;
+    const TreeSummary *sum;  // the run state: nothing is done once it halts
     int tile_stride, ngroup, nrowgrp, Kp;
     const int2 *slots;    // per bucket nslot entries {source column, operator index}
     int nslot;
@@ -187,7 +194,9 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
     rest /= a.nrowgrp;
     const int g = rest % a.ngroup;
     const int tile0 = rest / a.ngroup;
-    const int n = a.cnt ? a.cnt[o] : a.nrange;
+    if (a.sum->halt) return;
+    const int b0 = a.lvl ? a.lvl[a.level] : a.b0;
+    const int n = a.cnt ? a.cnt[o] : (a.lvl ? a.lvl[a.level + 1] - b0 : a.nrange);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int row0 = rg * ROWS;
     const int s0 = (a.nslot * g) / a.ngroup, s1 = (a.nslot * (g + 1)) / a.ngroup;
@@ -227,7 +236,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
         __syncthreads();  // previous tile finished with the shared arrays
         if (tid < kM2LCols) {
             const int t = tile * kM2LCols + tid;
-            tgt_s[tid] = t < n ? (a.cnt ? a.list[(size_t)o * a.list_stride + t] : a.b0 + t) : -1;
+            tgt_s[tid] = t < n ? (a.cnt ? a.list[(size_t)o * a.list_stride + t] : b0 + t) : -1;
         }
         if (tid < ns) op_s[tid] = a.slots[o * a.nslot + s0 + tid].y;
         __syncthreads();
@@ -372,20 +381,24 @@ static void launch_xlate(const XlateArgs &a, int grid, const T *At, const T *X, 
     }
 }
 
-// Box range [b0, b0 + n): out = (mode 2: out +) sum of the slot-group partials,
-// in group order; mode 1 leaves the boxes flagged in skip untouched.
+// The boxes of tree level `level` ([lvl[level], lvl[level + 1]), read on the
+// device): out = (mode 2: out +) sum of the slot-group partials, in group
+// order; mode 1 leaves the boxes flagged in skip untouched.  Grid-stride.
 template <typename T>
-__global__ void k_xlate_reduce(int b0, int n, int Kp, int nbox, int ngroup, int mode, const uint8_t *__restrict__ skip,
-                               const T *__restrict__ part, T *__restrict__ out)
+__global__ void k_xlate_reduce(const TreeSummary *__restrict__ sum, int level, int Kp, int nbox, int ngroup, int mode,
+                               const uint8_t *__restrict__ skip, const T *__restrict__ part, T *__restrict__ out)
 {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)n * Kp) return;
-    const int b = b0 + (int)(e / Kp);
-    const size_t off = (size_t)b * Kp + e % Kp;
-    if (mode == 1 && skip[b]) return;
-    T acc = 0;
-    for (int g = 0; g < ngroup; ++g) acc += part[(size_t)g * nbox * Kp + off];
-    out[off] = mode == 2 ? out[off] + acc : acc;
+    if (sum->halt) return;
+    const int b0 = sum->level_start[level], n = sum->level_start[level + 1] - b0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)n * Kp;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int b = b0 + (int)(e / Kp);
+        const size_t off = (size_t)b * Kp + e % Kp;
+        if (mode == 1 && skip[b]) continue;
+        T acc = 0;
+        for (int g = 0; g < ngroup; ++g) acc += part[(size_t)g * nbox * Kp + off];
+        out[off] = mode == 2 ? out[off] + acc : acc;
+    }
 }
 
 // Near field (P2P) of one work item per 256-thread workgroup (grid-stride
@@ -420,11 +433,14 @@ constexpr double kSoft2 = 1e-24;
 constexpr double kRinvMax = 1e12;
 
 template <typename T, bool POT>
-__global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const double *__restrict__ sp, int ntot,
+__global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSummary *__restrict__ sum,
+                                                     const double *__restrict__ sp, int ntot,
                                                      const int2 *__restrict__ near, int stride,
-                                                     const int4 *__restrict__ work, int n_items, T *__restrict__ part,
-                                                     int *__restrict__ queue)
+                                                     const int4 *__restrict__ work, const uint32_t *__restrict__ n_items_p,
+                                                     T *__restrict__ part, int *__restrict__ queue)
 {
+    if (sum->halt) return;
+    const int n_items = (int)*n_items_p;
     constexpr int NT = kP2PThreads;
     constexpr int NC = POT ? 4 : 3;  // partial components per target
     constexpr int kU = kP2PStage / NT;
@@ -607,13 +623,13 @@ __global__ __launch_bounds__(256) void k_far(BoxTable bt, const double *__restri
                                             const uint32_t *__restrict__ item_off,
                                             const int32_t *__restrict__ src_items, const T *__restrict__ part,
                                             const uint32_t *__restrict__ vals, double *__restrict__ E,
-                                            double *__restrict__ PHI)
+                                            double *__restrict__ PHI, const TreeSummary *__restrict__ sum)
 {
     constexpr int NC = POT ? 4 : 3;
     __shared__ T rec_s[kRecFields * kq(kMaxP)];
     __shared__ T Lb[kMaxKp];
     const int b = blockIdx.x;
-    if (!bt.leaf[b]) return;
+    if (sum->halt || b >= sum->nbox || !bt.leaf[b]) return;
     const double4 g = bt.geo[b];
     const double ih = 1.0 / g.w;
     for (int i = threadIdx.x; i < kRecFields * kq(p); i += blockDim.x) rec_s[i] = rec[i];
@@ -658,15 +674,19 @@ static XlateArgs xlate_base(int Kp, int nbox)
 }
 
 // A level of M2M (mode 1) or L2L (mode 2): 8 octant slots, split into
-// groups whose partial sums a second kernel adds in group order.
+// groups whose partial sums a second kernel adds in group order.  The
+// level's boxes are read on the device; grids cover cap boxes (more boxes
+// are still covered, by striding).
 template <typename T>
-static void launch_level_xlate(const BoxTable &bt, int Kp, int nbox, int b0, int n, int mode, const T *ops,
-                               const int2 *oct_slots, const int32_t *srctab, T *X, T *part, hipStream_t st)
+static void launch_level_xlate(const BoxTable &bt, const TreeSummary *sum, int Kp, int nbox, int level, int cap,
+                               int mode, const T *ops, const int2 *oct_slots, const int32_t *srctab, T *X, T *part,
+                               hipStream_t st)
 {
-    const int tiles = ceil_div(n, kM2LCols);
+    const int tiles = std::max(1, ceil_div(cap, kM2LCols));
     XlateArgs a = xlate_base(Kp, nbox);
-    a.b0 = b0;
-    a.nrange = n;
+    a.lvl = sum->level_start;
+    a.level = level;
+    a.sum = sum;
     a.ngroup = 8;  // one octant slot per group: summation order independent of the batch
     a.tile_stride = tiles;
     a.slots = oct_slots;
@@ -677,31 +697,30 @@ static void launch_level_xlate(const BoxTable &bt, int Kp, int nbox, int b0, int
     xlate_rows(a, (long)tiles * a.ngroup);
     if (mode == 1) launch_xlate<T, 1>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, st);
     else launch_xlate<T, 2>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, st);
-    const size_t tot = (size_t)n * Kp;
-    k_xlate_reduce<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(b0, n, Kp, nbox, a.ngroup, mode, bt.leaf, part,
-                                                                        X);
+    const size_t tot = (size_t)std::max(1, cap) * Kp;
+    k_xlate_reduce<T><<<(unsigned)std::min<size_t>((tot + 255) / 256, 8192), 256, 0, st>>>(
+        sum, level, Kp, nbox, a.ngroup, mode, bt.leaf, part, X);
 }
 
 template <typename T>
-void launch_p2m(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *rec, T *M,
-                int leaf_size, hipStream_t st)
+void launch_p2m(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, int p, int nbox, const T *rec,
+                T *M, int leaf_size, hipStream_t st)
 {
     const int Kp = kpad(p);
     const int chunk = p2m_chunk<T>(Kp, leaf_size);
     const size_t smem = (size_t)Kp * (chunk + 1) * sizeof(T);
-    if (hs.nbox > 0) k_p2m<T><<<hs.nbox, 64, smem, st>>>(bt, sp, ntot, p, Kp, chunk, rec, M);
+    if (nbox > 0) k_p2m<T><<<nbox, 64, smem, st>>>(bt, sum, sp, ntot, p, Kp, chunk, rec, M);
 }
 
 template <typename T>
-void launch_m2m(const BoxTable &bt, int p, const TreeSummary &hs, const T *m2m_pad, const int2 *oct_slots,
-                const int32_t *child_oct, T *M, T *part, hipStream_t st)
+void launch_m2m(const BoxTable &bt, const TreeSummary *sum, int p, const Caps &cap, const T *m2m_pad,
+                const int2 *oct_slots, const int32_t *child_oct, T *M, T *part, hipStream_t st)
 {
     // level by level: parents of level l gather their children by octant
     const int Kp = kpad(p);
-    for (int l = kMaxLevel - 1; l >= 2; --l) {
-        const int b0 = hs.level_start[l], b1 = hs.level_start[l + 1];
-        if (b1 <= b0 || hs.level_start[l + 2] <= b1) continue;  // no children below
-        launch_level_xlate<T>(bt, Kp, hs.nbox, b0, b1 - b0, 1, m2m_pad, oct_slots, child_oct, M, part, st);
+    for (int l = std::min(cap.nlev, kMaxLevel + 1) - 2; l >= 2; --l) {
+        if (cap.lvl[l] <= 0 || cap.lvl[l + 1] <= 0) continue;  // no boxes, or no children below
+        launch_level_xlate<T>(bt, sum, Kp, cap.nbox, l, cap.lvl[l], 1, m2m_pad, oct_slots, child_oct, M, part, st);
     }
 }
 
@@ -713,27 +732,29 @@ int m2l_groups(int)
 }
 
 template <typename T>
-void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_pad, const int2 *oct_slots,
-                     const int32_t *parent_oct, T *L, T *part, hipStream_t st)
+void launch_downward(const BoxTable &bt, const TreeSummary *sum, int p, const Caps &cap, const T *l2l_pad,
+                     const int2 *oct_slots, const int32_t *parent_oct, T *L, T *part, hipStream_t st)
 {
     const int Kp = kpad(p);
     // L2L level by level (3 and deeper): each box adds its parent's expansion
     // shifted by the operator of its own octant (slot = octant)
-    for (int l = 3; l <= kMaxLevel; ++l) {
-        const int b0 = hs.level_start[l], b1 = hs.level_start[l + 1];
-        if (b1 <= b0) continue;
-        launch_level_xlate<T>(bt, Kp, hs.nbox, b0, b1 - b0, 2, l2l_pad, oct_slots, parent_oct, L, part, st);
+    for (int l = 3; l < std::min(cap.nlev, kMaxLevel + 1); ++l) {
+        if (cap.lvl[l] <= 0) continue;
+        launch_level_xlate<T>(bt, sum, Kp, cap.nbox, l, cap.lvl[l], 2, l2l_pad, oct_slots, parent_oct, L, part, st);
     }
 }
 
 template <typename T>
-void launch_near(const BoxTable &bt, const double *sp, int ntot, const int2 *near, int stride, const int4 *work,
-                 int n_items, T *part, bool pot, int max_grid, int *queue, hipStream_t st)
+void launch_near(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, const int2 *near, int stride,
+                 const int4 *work, const uint32_t *n_items, int cap_items, T *part, bool pot, int max_grid, int *queue,
+                 hipStream_t st)
 {
-    if (n_items <= 0) return;
-    const int grid = std::min(n_items, max_grid);
-    if (pot) k_p2p<T, true><<<grid, kP2PThreads, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part, queue);
-    else k_p2p<T, false><<<grid, kP2PThreads, 0, st>>>(bt, sp, ntot, near, stride, work, n_items, part, queue);
+    if (cap_items <= 0) return;
+    const int grid = std::min(cap_items, max_grid);
+    if (pot)
+        k_p2p<T, true><<<grid, kP2PThreads, 0, st>>>(bt, sum, sp, ntot, near, stride, work, n_items, part, queue);
+    else
+        k_p2p<T, false><<<grid, kP2PThreads, 0, st>>>(bt, sum, sp, ntot, near, stride, work, n_items, part, queue);
 }
 
 size_t near_lds_bytes()
@@ -742,41 +763,35 @@ size_t near_lds_bytes()
 }
 
 template <typename T>
-void launch_far(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
-                const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals, double *E,
-                double *phi, int leaf_size, hipStream_t st)
+void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, int p, int nbox, const T *L,
+                const T *rec, const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals,
+                double *E, double *phi, int leaf_size, hipStream_t st)
 {
     // one thread per ion of a leaf where the leaf size allows
     const int tb = std::min(256, std::max(64, (leaf_size + 63) / 64 * 64));
     if (nbox <= 0) return;
     if (phi)
-        k_far<T, true><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E, phi);
+        k_far<T, true><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E, phi,
+                                            sum);
     else
         k_far<T, false><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E,
-                                             nullptr);
+                                             nullptr, sum);
 }
 
-template void launch_p2m<double>(const BoxTable &, const double *, int, int, const TreeSummary &, const double *,
-                                 double *, int, hipStream_t);
-template void launch_p2m<float>(const BoxTable &, const double *, int, int, const TreeSummary &, const float *,
-                                float *, int, hipStream_t);
-template void launch_m2m<double>(const BoxTable &, int, const TreeSummary &, const double *, const int2 *,
-                                 const int32_t *, double *, double *, hipStream_t);
-template void launch_m2m<float>(const BoxTable &, int, const TreeSummary &, const float *, const int2 *,
-                                const int32_t *, float *, float *, hipStream_t);
-template void launch_downward<double>(const BoxTable &, int, const TreeSummary &, const double *, const int2 *,
-                                      const int32_t *, double *, double *, hipStream_t);
-template void launch_downward<float>(const BoxTable &, int, const TreeSummary &, const float *, const int2 *,
-                                     const int32_t *, float *, float *, hipStream_t);
-template void launch_near<double>(const BoxTable &, const double *, int, const int2 *, int, const int4 *, int,
-                                   double *, bool, int, int *, hipStream_t);
-template void launch_near<float>(const BoxTable &, const double *, int, const int2 *, int, const int4 *, int, float *,
-                                  bool, int, int *, hipStream_t);
-template void launch_far<double>(const BoxTable &, const double *, int, int, int, const double *, const double *,
-                                  const uint32_t *, const int32_t *, const double *, const uint32_t *, double *,
-                                  double *, int, hipStream_t);
-template void launch_far<float>(const BoxTable &, const double *, int, int, int, const float *, const float *,
-                                 const uint32_t *, const int32_t *, const float *, const uint32_t *, double *,
-                                 double *, int, hipStream_t);
+#define PT_INST(T)                                                                                                  \
+    template void launch_p2m<T>(const BoxTable &, const TreeSummary *, const double *, int, int, int, const T *,     \
+                                T *, int, hipStream_t);                                                            \
+    template void launch_m2m<T>(const BoxTable &, const TreeSummary *, int, const Caps &, const T *, const int2 *,   \
+                                const int32_t *, T *, T *, hipStream_t);                                           \
+    template void launch_downward<T>(const BoxTable &, const TreeSummary *, int, const Caps &, const T *,            \
+                                     const int2 *, const int32_t *, T *, T *, hipStream_t);                        \
+    template void launch_near<T>(const BoxTable &, const TreeSummary *, const double *, int, const int2 *, int,      \
+                                 const int4 *, const uint32_t *, int, T *, bool, int, int *, hipStream_t);         \
+    template void launch_far<T>(const BoxTable &, const TreeSummary *, const double *, int, int, int, const T *,     \
+                                const T *, const uint32_t *, const int32_t *, const T *, const uint32_t *, double *, \
+                                double *, int, hipStream_t);
+PT_INST(float)
+PT_INST(double)
+#undef PT_INST
 
 }  // namespace pt

@@ -82,7 +82,11 @@ __global__ __launch_bounds__(256) void k_m2l_count(BoxTable bt, const TreeSummar
     __shared__ uint32_t total;
     const int b = blockIdx.x, tid = threadIdx.x;
     const int nbox = sum->nbox;
-    if (b >= nbox) return;
+    if (sum->halt) return;
+    if (b >= nbox) {  // the grid may cover a capacity past the tree: no pairs
+        if (tid == 0) pcnt[b] = 0;
+        return;
+    }
     if (tid < kOps) per_op[tid] = 0;
     if (tid == 0) total = 0;
     __syncthreads();
@@ -111,7 +115,7 @@ __global__ __launch_bounds__(256) void k_m2l_emit(BoxTable bt, const TreeSummary
     __shared__ int op_s[kSlots];
     const int b = blockIdx.x, tid = threadIdx.x;
     const int nbox = sum->nbox;
-    if (b >= nbox || bt.level[b] < 2) return;
+    if (sum->halt || b >= nbox || bt.level[b] < 2) return;
     const int par = parity_of(bt, b);
     if (tid < kSlots) {
         const int2 s = slots[par * kSlots + tid];
@@ -139,6 +143,7 @@ __global__ __launch_bounds__(64) void k_m2l_chunks(const TreeSummary *__restrict
                                                    int32_t *__restrict__ chunk_off)
 {
     const int o = threadIdx.x;
+    if (sum->halt) return;
     const int nbox = sum->nbox;
     const int beg = nbox > 0 ? (int)ob_off[(size_t)o * nbox] : 0;
     const int end = o + 1 < kOps ? (nbox > 0 ? (int)ob_off[(size_t)(o + 1) * nbox] : 0) : (int)*npairs;
@@ -165,7 +170,7 @@ __global__ __launch_bounds__(64) void k_m2l_chunks(const TreeSummary *__restrict
 // step takes element e of both, i.e. the contraction runs over a fixed
 // permutation of k, the same for every product.
 template <typename T, int NRB>
-__global__ __launch_bounds__(kGemmThreads) void k_m2l_gemm(int Kp, int nrg, int zrow,
+__global__ __launch_bounds__(kGemmThreads) void k_m2l_gemm(const TreeSummary *__restrict__ sum, int Kp, int nrg, int zrow,
                                                            const int32_t *__restrict__ chunk_off_g,
                                                            const int32_t *__restrict__ op_beg_g,
                                                            const int4 *__restrict__ bucket, const T *__restrict__ A,
@@ -178,6 +183,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_m2l_gemm(int Kp, int nrg, int 
     // runs beside the near field: a raised wave priority lets these waves
     // (long dependency chains on the matrix cores) issue first when ready
     __builtin_amdgcn_s_setprio(1);
+    if (sum->halt) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int strideE = Kp + VEC;  // row stride of the LDS operator rows (16-byte reads without bank conflicts)
     T *As = reinterpret_cast<T *>(smem_raw);                               // [ROWS][strideE]
@@ -314,6 +320,7 @@ __global__ void k_m2l_sum(const TreeSummary *__restrict__ sum, int Kp, const uin
 {
     using V = Vec16<T>;
     constexpr int VEC = V::N;
+    if (sum->halt) return;
     const int nbox = sum->nbox;
     const int per_box = Kp / VEC;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)nbox * per_box;
@@ -395,15 +402,17 @@ int m2l_per_cu(int Kp, size_t lds_beside)
 }
 
 template <typename T>
-void launch_m2l_gemm(int Kp, int nbox, int grid, const int32_t *chunk_off, const int32_t *op_beg, const int4 *bucket,
-                     const T *A, const T *M, T *R, hipStream_t st)
+void launch_m2l_gemm(const TreeSummary *sum, int Kp, int nbox, int grid, const int32_t *chunk_off,
+                     const int32_t *op_beg, const int4 *bucket, const T *A, const T *M, T *R, hipStream_t st)
 {
     int nrg;
     const int nrb = m2l_row_blocks<T>(Kp, nrg);
     const size_t lds = m2l_gemm_lds<T>(Kp);
     switch (nrb) {
 #define PT_G(NB) \
-    case NB: k_m2l_gemm<T, NB><<<grid, kGemmThreads, lds, st>>>(Kp, nrg, nbox, chunk_off, op_beg, bucket, A, M, R); break;
+    case NB:                                                                                                    \
+        k_m2l_gemm<T, NB><<<grid, kGemmThreads, lds, st>>>(sum, Kp, nrg, nbox, chunk_off, op_beg, bucket, A, M, R); \
+        break;
         PT_G(1) PT_G(2) PT_G(3) PT_G(4) PT_G(5) PT_G(6)
 #undef PT_G
     default: break;
@@ -424,10 +433,10 @@ template int m2l_per_cu<float>(int, size_t);
 template int m2l_per_cu<double>(int, size_t);
 template size_t m2l_gemm_lds<float>(int);
 template size_t m2l_gemm_lds<double>(int);
-template void launch_m2l_gemm<float>(int, int, int, const int32_t *, const int32_t *, const int4 *, const float *,
-                                     const float *, float *, hipStream_t);
-template void launch_m2l_gemm<double>(int, int, int, const int32_t *, const int32_t *, const int4 *, const double *,
-                                      const double *, double *, hipStream_t);
+template void launch_m2l_gemm<float>(const TreeSummary *, int, int, int, const int32_t *, const int32_t *,
+                                     const int4 *, const float *, const float *, float *, hipStream_t);
+template void launch_m2l_gemm<double>(const TreeSummary *, int, int, int, const int32_t *, const int32_t *,
+                                      const int4 *, const double *, const double *, double *, hipStream_t);
 template void launch_m2l_sum<float>(const TreeSummary *, int, int, const uint32_t *, const uint32_t *,
                                     const float *, float *, hipStream_t);
 template void launch_m2l_sum<double>(const TreeSummary *, int, int, const uint32_t *, const uint32_t *,

@@ -60,8 +60,10 @@ __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t v0, uint64_t v1, i
 // (ordered-integer atomics; min/max is exact, so the result does not depend
 // on the order).
 __global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
-                             int do_drift, unsigned long long *__restrict__ bbox_all, int bstride)
+                             int do_drift, unsigned long long *__restrict__ bbox_all, int bstride,
+                             const int32_t *__restrict__ halt)
 {
+    if (halt && *halt) return;  // a halted run: the same word for every workgroup
     unsigned long long *bbox = bbox_all + (size_t)(blockIdx.x % kBBoxCopies) * bstride;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = g < ntot;
@@ -196,11 +198,11 @@ __global__ void k_root(unsigned long long *__restrict__ bbox, int nc, int bstrid
 // to [0, 2^16 - 1]; subtract then multiply, never fused).
 __global__ void k_keys(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal,
                        const RootCube *__restrict__ roots, int ntot, uint64_t *__restrict__ keys,
-                       uint32_t *__restrict__ vals)
+                       uint32_t *__restrict__ vals, const int32_t *__restrict__ halt)
 {
 #pragma clang fp contract(off)
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ntot) return;
+    if (g >= ntot || (halt && *halt)) return;
     const int c = ion_crystal[g];
     const CrystalDev &cd = cs[c];
     const int i = g - cd.ion_off;
@@ -223,9 +225,15 @@ __global__ void k_keys(const CrystalDev *__restrict__ cs, const int32_t *__restr
 // the per-beam rate and count code).
 template <bool BEAMS>
 __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
-                             int kstep, const double *__restrict__ E)
+                             int kstep, const double *__restrict__ E, TreeSummary *__restrict__ sum, int call_k)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sum && sum->halt) {
+        // the step's tree or lists did not fit their buffers: the state stays
+        // at the last completed step, which the host reads from fail_step
+        if (g == 0 && sum->fail_step < 0) sum->fail_step = call_k;
+        return;
+    }
     if (g >= ntot) return;
     const int c = ion_crystal[g];
     const CrystalDev &cd = cs[c];
@@ -465,10 +473,11 @@ void launch_zero_u64(uint64_t *p, int n, hipStream_t st)
 }
 
 void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int nc, int do_drift,
-                       unsigned long long *bbox, hipStream_t st)
+                       unsigned long long *bbox, const int32_t *halt, hipStream_t st)
 {
     if (ntot > 0)
-        k_drift_bbox<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, do_drift, bbox, bbox_stride(nc));
+        k_drift_bbox<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, do_drift, bbox, bbox_stride(nc),
+                                                          halt);
 }
 
 void launch_root(unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st)
@@ -477,18 +486,51 @@ void launch_root(unsigned long long *bbox, int nc, RootCube *roots, hipStream_t 
 }
 
 void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCube *roots, int ntot, uint64_t *keys,
-                 uint32_t *vals, hipStream_t st)
+                 uint32_t *vals, const int32_t *halt, hipStream_t st)
 {
-    if (ntot > 0) k_keys<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, roots, ntot, keys, vals);
+    if (ntot > 0) k_keys<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, roots, ntot, keys, vals, halt);
 }
 
 void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
-                       bool beams, hipStream_t st)
+                       bool beams, TreeSummary *sum, int call_k, hipStream_t st)
 {
     if (ntot <= 0) return;
-    if (beams) k_kick_drift<true><<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E);
-    else k_kick_drift<false><<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E);
+    if (beams) k_kick_drift<true><<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k);
+    else k_kick_drift<false><<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k);
 }
+
+// Capacity checks and the run reset (one thread each).
+__global__ void k_cap_check_tree(TreeSummary *__restrict__ sum, Caps cap)
+{
+    if (sum->halt) return;
+    int nlev = 0;
+    for (int l = 0; l <= kMaxLevel; ++l)
+        if (sum->level_start[l + 1] > sum->level_start[l]) nlev = l + 1;
+    // (a level holding more boxes than its grid covers is still covered, by
+    // striding; only the buffers sized by these counts can overflow)
+    if (sum->nbox > cap.nbox || nlev > cap.nlev || sum->sort_error != 0) sum->halt = 1;
+}
+
+__global__ void k_cap_check_lists(TreeSummary *__restrict__ sum, const uint32_t *__restrict__ total, Caps cap)
+{
+    if (sum->halt) return;
+    if (total[1] > (uint32_t)cap.items || total[2] > (uint32_t)cap.pairs) sum->halt = 1;
+}
+
+__global__ void k_run_reset(TreeSummary *__restrict__ sum)
+{
+    sum->halt = 0;
+    sum->fail_step = -1;
+}
+
+void launch_cap_check_tree(TreeSummary *sum, const Caps &cap, hipStream_t st) { k_cap_check_tree<<<1, 1, 0, st>>>(sum, cap); }
+
+void launch_cap_check_lists(TreeSummary *sum, const uint32_t *total, const Caps &cap, hipStream_t st)
+{
+    k_cap_check_lists<<<1, 1, 0, st>>>(sum, total, cap);
+}
+
+void launch_run_reset(TreeSummary *sum, hipStream_t st) { k_run_reset<<<1, 1, 0, st>>>(sum); }
 
 int direct_targets_per_block() { return kDirTB * kDirT; }
 

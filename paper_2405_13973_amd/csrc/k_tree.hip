@@ -184,8 +184,9 @@ constexpr int kSpinMax = 1 << 20;
 
 __global__ __launch_bounds__(kSortTB) void k_radix_prepare(const uint64_t *__restrict__ keys, int n, int passes,
                                                            uint32_t *__restrict__ ghist, uint64_t *__restrict__ flags,
-                                                           int ntile)
+                                                           int ntile, const int32_t *__restrict__ halt)
 {
+    if (halt && *halt) return;  // a halted run (every workgroup sees the same word)
     __shared__ uint32_t cnt[kMaxPasses][256];
     const int tid = threadIdx.x;
     for (int p = 0; p < passes; ++p) {
@@ -210,8 +211,10 @@ __global__ __launch_bounds__(kSortTB) void k_radix_pass(const uint64_t *__restri
                                                         uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                         int n, int pass, const uint32_t *__restrict__ ghist,
                                                         uint64_t *__restrict__ flags, int ntile,
-                                                        uint32_t *__restrict__ ctr, uint32_t *__restrict__ err)
+                                                        uint32_t *__restrict__ ctr, uint32_t *__restrict__ err,
+                                                        const int32_t *__restrict__ halt)
 {
+    if (halt && *halt) return;  // set before the sort starts: every workgroup returns, none waits
     constexpr int NW = kSortTB / 64;
     __shared__ uint32_t wcnt[kSortItems][NW][256];  // digit counts per (round, wave), then their prefixes
     __shared__ uint32_t base_s[256];
@@ -295,10 +298,11 @@ __global__ __launch_bounds__(kSortTB) void k_radix_pass(const uint64_t *__restri
 
 // Sorted positions: slot k takes the position of batch ion vals[k].
 __global__ void k_gather(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal,
-                         const uint32_t *__restrict__ vals, int ntot, double *__restrict__ sp)
+                         const uint32_t *__restrict__ vals, int ntot, double *__restrict__ sp,
+                         const int32_t *__restrict__ halt)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ntot) return;
+    if (k >= ntot || (halt && *halt)) return;
     const int g = (int)vals[k];
     const CrystalDev &cd = cs[ion_crystal[g]];
     const int i = g - cd.ion_off;
@@ -399,8 +403,10 @@ __host__ __device__ inline uint32_t slot_box_levels(const uint64_t *__restrict__
 __global__ __launch_bounds__(256) void k_tree_levels(const CrystalDev *__restrict__ cs,
                                                      const uint64_t *__restrict__ keys, int ntot, int leaf_size,
                                                      uint32_t *__restrict__ rep_mask, int32_t *__restrict__ box_end,
-                                                     uint32_t *__restrict__ blockcnt, int nblk)
+                                                     uint32_t *__restrict__ blockcnt, int nblk,
+                                                     const int32_t *__restrict__ halt)
 {
+    if (halt && *halt) return;
     // rep_mask[k]: the levels at which slot k is the first ion of a box;
     // box_end[k][l]: the end of that level-l box (written for those levels only);
     // blockcnt[l][block]: how many such slots of this block start a level-l box
@@ -427,7 +433,7 @@ __global__ __launch_bounds__(256) void k_tree_levels(const CrystalDev *__restric
 __global__ void k_tree_summary(const uint32_t *__restrict__ scanned, int nblk, const uint32_t *__restrict__ total,
                                const uint32_t *__restrict__ sort_err, TreeSummary *__restrict__ sum)
 {
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x != 0 || sum->halt) return;
     sum->sort_error = sort_err ? (int32_t)*sort_err : 0;
     for (int l = 0; l <= kMaxLevel; ++l) sum->level_start[l] = (int32_t)scanned[l * nblk];
     sum->level_start[kMaxLevel + 1] = (int32_t)*total;
@@ -440,9 +446,11 @@ __global__ __launch_bounds__(256) void k_tree_emit(const CrystalDev *__restrict_
                                                    const uint64_t *__restrict__ keys, int ntot, int leaf_size,
                                                    const uint32_t *__restrict__ rep_mask,
                                                    const int32_t *__restrict__ box_end,
-                                                   const uint32_t *__restrict__ scanned, int nblk, BoxTable bt)
+                                                   const uint32_t *__restrict__ scanned, int nblk, BoxTable bt,
+                                                   const TreeSummary *__restrict__ sum)
 {
     __shared__ uint32_t wc[4][kMaxLevel + 1];
+    if (sum->halt) return;
     const int k = blockIdx.x * 256 + threadIdx.x;
     const uint32_t mask = k < ntot ? rep_mask[k] : 0u;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -487,7 +495,7 @@ __global__ __launch_bounds__(256) void k_tree_emit(const CrystalDev *__restrict_
 __global__ void k_tree_links(BoxTable bt, const TreeSummary *__restrict__ sum)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= sum->nbox) return;
+    if (sum->halt || b >= sum->nbox) return;
     const int l = bt.level[b];
     const int beg = bt.begin[b];
     int parent = -1;
@@ -531,7 +539,7 @@ __global__ void k_oct_tables(BoxTable bt, const TreeSummary *__restrict__ sum, i
                              int32_t *__restrict__ parent_oct)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= sum->nbox) return;
+    if (sum->halt || b >= sum->nbox) return;
     int32_t ch[8], pa[8];
     for (int o = 0; o < 8; ++o) ch[o] = pa[o] = -1;
     for (int c = bt.child[b], e = c + bt.nchild[b]; c < e; ++c)
@@ -549,7 +557,7 @@ __global__ void k_colleagues(BoxTable bt, const TreeSummary *__restrict__ sum, i
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int nbox = sum->nbox;
-    if (i >= nbox * kNeigh) return;
+    if (sum->halt || i >= nbox * kNeigh) return;
     const int b = i / kNeigh, s = i - b * kNeigh;
     const int l = bt.level[b];
     const int lim = 1 << l;
@@ -585,7 +593,7 @@ __global__ void k_vlist(BoxTable bt, const TreeSummary *__restrict__ sum, const 
     __shared__ int cnt_s;
     if (threadIdx.x == 0) cnt_s = 0;
     __syncthreads();
-    const int nbox = sum->nbox;
+    const int nbox = sum->halt ? 0 : sum->nbox;
     int cnt = 0;
     for (int e = threadIdx.x; e < kVBoxes * kWin; e += blockDim.x) {
         const int b = blockIdx.x * kVBoxes + e / kWin, w = e % kWin;
@@ -640,8 +648,10 @@ __global__ __launch_bounds__(64) void k_nearlist(BoxTable bt, const TreeSummary 
     __shared__ int anc_s[kMaxLevel + 1];
     __shared__ int nanc_s;
     const int b = blockIdx.x, lane = threadIdx.x;
-    if (b >= sum->nbox) return;
-    if (!bt.leaf[b]) {
+    if (sum->halt) return;
+    // the grid may cover more boxes than the tree has (a capacity): those
+    // count zero items, so that the scan of the item counts stays exact
+    if (b >= sum->nbox || !bt.leaf[b]) {
         if (lane == 0) {
             near_cnt[b] = 0;
             items[b] = 0;
@@ -707,7 +717,7 @@ __global__ __launch_bounds__(64) void k_p2p_items(BoxTable bt, const TreeSummary
                                                   const int32_t *__restrict__ cuts, int4 *__restrict__ work)
 {
     const int b = blockIdx.x;
-    if (b >= sum->nbox || !bt.leaf[b]) return;
+    if (sum->halt || b >= sum->nbox || !bt.leaf[b]) return;
     const int32_t *cut = cuts + (size_t)b * stride;
     const int cnt = near_cnt[b], si = src_items[b];
     const int nt = bt.end[b] - bt.begin[b];
@@ -745,25 +755,25 @@ void launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
 }
 
 void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint32_t *vals, int ntot, double *sp,
-                   hipStream_t st)
+                   const int32_t *halt, hipStream_t st)
 {
-    k_gather<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, vals, ntot, sp);
+    k_gather<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, vals, ntot, sp, halt);
 }
 
 size_t radix_state_words(int n) { return (size_t)kMaxPasses * 256 + kMaxPasses + 1 + 1 +
                                         2 * (size_t)kMaxPasses * sort_blocks(n) * 256; }
 
 int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int n, int passes, uint32_t *state,
-                      hipStream_t st)
+                      const int32_t *halt, hipStream_t st)
 {
     if (passes > kMaxPasses || n <= 0) return -1;
     const int ntile = sort_blocks(n);
     uint32_t *ghist = state, *ctr = state + kMaxPasses * 256, *err = ctr + kMaxPasses;
     uint64_t *flags = (uint64_t *)(state + kMaxPasses * 256 + kMaxPasses + 2);  // 8-byte aligned
-    k_radix_prepare<<<ntile, kSortTB, 0, st>>>(k0, n, passes, ghist, flags, ntile);
+    k_radix_prepare<<<ntile, kSortTB, 0, st>>>(k0, n, passes, ghist, flags, ntile, halt);
     for (int p = 0; p < passes; ++p) {
         k_radix_pass<<<ntile, kSortTB, 0, st>>>(p % 2 ? k1 : k0, p % 2 ? v1 : v0, p % 2 ? k0 : k1, p % 2 ? v0 : v1, n,
-                                                p, ghist, flags, ntile, ctr, err);
+                                                p, ghist, flags, ntile, ctr, err, halt);
     }
     return passes % 2;  // 1: the result is in (k1, v1)
 }
@@ -775,7 +785,7 @@ void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int
                        const uint32_t *sort_err, TreeSummary *sum, hipStream_t st)
 {
     const int nblk = tree_blocks(ntot);
-    k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask, box_end, blockcnt, nblk);
+    k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask, box_end, blockcnt, nblk, &sum->halt);
     launch_scan(blockcnt, (kMaxLevel + 1) * nblk, partial, total, st);
     k_tree_summary<<<1, 64, 0, st>>>(blockcnt, nblk, total, sort_err, sum);
 }
@@ -785,7 +795,7 @@ void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64
                        const TreeSummary *sum, int nbox, hipStream_t st)
 {
     const int nblk = tree_blocks(ntot);
-    k_tree_emit<<<nblk, 256, 0, st>>>(cs, roots, keys, ntot, leaf_size, rep_mask, box_end, scanned, nblk, bt);
+    k_tree_emit<<<nblk, 256, 0, st>>>(cs, roots, keys, ntot, leaf_size, rep_mask, box_end, scanned, nblk, bt, sum);
     k_tree_links<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum);
 }
 

@@ -93,12 +93,25 @@ struct RootCube {
     double pad[3];
 };
 
-// Device copy of the size summary read back after the tree count.
+// Device size summary of the current tree (read back by the measuring
+// evaluation), with the run state of a queued sequence of steps: halt is set
+// (and stays set) when a step's tree or lists exceed the capacities its
+// buffers were sized for, after which every kernel of the sequence does
+// nothing and each kick leaves the state as it was; fail_step is the
+// sequence's first step that was not completed (-1: none).
 struct TreeSummary {
     int32_t level_start[kMaxLevel + 2];  // boxes of level l: [level_start[l], level_start[l+1])
     int32_t nbox;
     int32_t sort_error;  // non-zero: the sort's look-back gave up waiting (see k_radix_pass)
-    int32_t pad[2];
+    int32_t halt;
+    int32_t fail_step;
+};
+
+// Capacities of a queued force evaluation's buffers and grids: boxes, tree
+// levels, near-field work items, M2L pairs, and boxes per level.
+struct Caps {
+    int32_t nbox, nlev, items, pairs;
+    int32_t lvl[kMaxLevel + 1];
 };
 
 // ---------------------------------------------------------------- helpers

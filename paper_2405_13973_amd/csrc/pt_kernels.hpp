@@ -32,14 +32,18 @@ struct ZeroRegions {
     int n[kZeroRegions];
 };
 void launch_zero_regions(const ZeroRegions &z, hipStream_t st);
+// halt (nullable, here and below): a run-state word; once set, nothing is done.
 void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int nc, int do_drift,
-                       unsigned long long *bbox, hipStream_t st);
+                       unsigned long long *bbox, const int32_t *halt, hipStream_t st);
 void launch_root(unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st);
 void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCube *roots, int ntot, uint64_t *keys,
-                 uint32_t *vals, hipStream_t st);
+                 uint32_t *vals, const int32_t *halt, hipStream_t st);
 // beams: some crystal of the batch uses the beam-mode laser
+// With sum non-null (the FMM), a halted run leaves the state as it was and
+// records its first such step in sum->fail_step.
+// call_k: the step's index within its pt_step_batch call (what fail_step records).
 void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
-                       bool beams, hipStream_t st);
+                       bool beams, TreeSummary *sum, int call_k, hipStream_t st);
 int direct_targets_per_block();
 // Direct field into E (3 x ntot); with phi non-null also the potential per
 // unit charge sum_{j != i} 1/r_ij into phi (ntot).
@@ -69,12 +73,13 @@ int sort_blocks(int n);
 size_t radix_state_words(int n);
 constexpr int radix_state_zero_words() { return 8 * 256 + 8 + 2; }
 constexpr int radix_state_err() { return 8 * 256 + 8; }
+// halt (nullable): a run-state word; when it is set the passes do nothing.
 int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int n, int passes, uint32_t *state,
-                      hipStream_t st);
+                      const int32_t *halt, hipStream_t st);
 void launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, int n, int shift,
                        uint32_t *hist, uint32_t *partial, hipStream_t st);
 void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint32_t *vals, int ntot, double *sp,
-                   hipStream_t st);
+                   const int32_t *halt, hipStream_t st);
 int tree_blocks(int ntot);
 // box_end: ntot x (kMaxLevel + 1) ints, the end of every box at its first ion
 // (filled by launch_tree_count, read by launch_tree_build).
@@ -103,23 +108,29 @@ void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, cons
 // rec: recurrence table (fmm_math.hpp), kRecFields x kq(p) entries.
 // m2m_pad / l2l_pad: 8 operators, Kp x Kp column-major, zero padded;
 // oct_slots: the 8 slots {octant, octant}; child_oct / parent_oct: 8 x nbox.
+// Every launcher below takes the device summary `sum`; its kernels do nothing
+// once sum->halt is set.  Grids cover nbox = the box capacity (boxes past the
+// tree's own count do nothing); level ranges and item counts are read on the
+// device.
 template <typename T>
-void launch_p2m(const BoxTable &bt, const double *sp, int ntot, int p, const TreeSummary &hs, const T *rec, T *M,
-                int leaf_size, hipStream_t st);
+void launch_p2m(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, int p, int nbox, const T *rec,
+                T *M, int leaf_size, hipStream_t st);
 template <typename T>
-void launch_m2m(const BoxTable &bt, int p, const TreeSummary &hs, const T *m2m_pad, const int2 *oct_slots,
-                const int32_t *child_oct, T *M, T *part, hipStream_t st);
+void launch_m2m(const BoxTable &bt, const TreeSummary *sum, int p, const Caps &cap, const T *m2m_pad,
+                const int2 *oct_slots, const int32_t *child_oct, T *M, T *part, hipStream_t st);
 int m2l_groups(int n2);  // slot groups of M2M / L2L partial sums (partial-sum buffer: groups x nbox x Kp)
 template <typename T>
-void launch_downward(const BoxTable &bt, int p, const TreeSummary &hs, const T *l2l_pad, const int2 *oct_slots,
-                     const int32_t *parent_oct, T *L, T *part, hipStream_t st);
+void launch_downward(const BoxTable &bt, const TreeSummary *sum, int p, const Caps &cap, const T *l2l_pad,
+                     const int2 *oct_slots, const int32_t *parent_oct, T *L, T *part, hipStream_t st);
 // Near field over the work items into part (item x 64 x 3; with pot the
-// potential sum as a fourth component, item x 64 x 4); at most max_grid
-// workgroups, which take the items from *queue (zero before the launch) or,
-// with queue NULL, stride over them.
+// potential sum as a fourth component, item x 64 x 4); *n_items items (on the
+// device, at most cap_items), at most max_grid workgroups, which take the
+// items from *queue (zero before the launch) or, with queue NULL, stride over
+// them.
 template <typename T>
-void launch_near(const BoxTable &bt, const double *sp, int ntot, const int2 *near, int stride, const int4 *work,
-                 int n_items, T *part, bool pot, int max_grid, int *queue, hipStream_t st);
+void launch_near(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, const int2 *near, int stride,
+                 const int4 *work, const uint32_t *n_items, int cap_items, T *part, bool pot, int max_grid, int *queue,
+                 hipStream_t st);
 // Near-field workgroups per compute unit while the translation GEMM runs
 // beside the near field: with this many, one GEMM workgroup still fits in
 // every compute unit's LDS, whichever kernel reaches the unit first.
@@ -129,9 +140,17 @@ size_t near_lds_bytes();
 // Far field (L2P) + the item partials per ion into E (batch order); with phi
 // non-null also the potential per unit charge (part then holds 4 components).
 template <typename T>
-void launch_far(const BoxTable &bt, const double *sp, int ntot, int p, int nbox, const T *L, const T *rec,
-                const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals, double *E,
-                double *phi, int leaf_size, hipStream_t st);
+void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, int p, int nbox, const T *L,
+                const T *rec, const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals,
+                double *E, double *phi, int leaf_size, hipStream_t st);
+// Capacity checks of a queued evaluation: after the tree count (boxes,
+// levels; a sort failure also halts), and after the lists (near-field items
+// in total[1], M2L pairs in total[2]).  Each sets sum->halt when a count
+// exceeds its capacity.
+void launch_cap_check_tree(TreeSummary *sum, const Caps &cap, hipStream_t st);
+void launch_cap_check_lists(TreeSummary *sum, const uint32_t *total, const Caps &cap, hipStream_t st);
+// Starts a run: halt = 0, fail_step = -1.
+void launch_run_reset(TreeSummary *sum, hipStream_t st);
 
 // k_m2l.hip: M2L organised by base operator.
 // slots: per parity the 189 non-touching window slots {slot, base operator +
@@ -157,8 +176,8 @@ size_t m2l_gemm_lds(int Kp);
 // A: the 64 base operators, row-major Kp x Kp each (row = output coefficient),
 // zero padded; M: nbox + 1 expansion rows (row nbox zero); R: npairs x Kp.
 template <typename T>
-void launch_m2l_gemm(int Kp, int nbox, int grid, const int32_t *chunk_off, const int32_t *op_beg, const int4 *bucket,
-                     const T *A, const T *M, T *R, hipStream_t st);
+void launch_m2l_gemm(const TreeSummary *sum, int Kp, int nbox, int grid, const int32_t *chunk_off,
+                     const int32_t *op_beg, const int4 *bucket, const T *A, const T *M, T *R, hipStream_t st);
 // L = per box the sum of its rows of R in order (pair_off: the scanned pcnt).
 template <typename T>
 void launch_m2l_sum(const TreeSummary *sum, int nbox, int Kp, const uint32_t *pair_off, const uint32_t *npairs,

@@ -96,6 +96,15 @@ constexpr int kPhases = 7;
 // only when the ring is full or the times are asked for, so timing adds no
 // host wait to a run of up to this many evaluations.
 constexpr int kTimingRing = 64;
+// Queued steps between two looks at the run state: every kCheckEvery steps
+// the run's fail_step is copied to the host behind the work, and a look at a
+// copy stops the queueing once a step halted; the host waits for a copy only
+// when it is more than kCheckAhead copies ahead, so a halted run wastes at
+// most about (kCheckAhead + 1) kCheckEvery steps while the device always has
+// work queued.
+constexpr int kCheckEvery = 8;
+constexpr int kCheckSlots = 8;
+constexpr int kCheckAhead = 2;
 // Leaf size from which the near field runs concurrently with M2L / L2L.
 constexpr int kConcurrentLeaf = 128;
 
@@ -114,6 +123,11 @@ struct pt_ctx {
     uint64_t budget = 0, used = 0;
     int live = 0;
     int32_t *d_nonfinite = nullptr;  // set by any kick of this context that produces a non-finite value
+    bool no_queue = false;           // every evaluation measures (PT_QUEUED_STEPS=0)
+    bool tight_caps = false;         // capacities one box short of the measured tree (PT_CAPS_TIGHT=1: tests)
+    bool eval_halted = false;        // the last measuring evaluation found its run halted
+    int64_t reruns = 0;              // queued runs re-run after a capacity overflow
+    int64_t n_queued = 0, n_measured = 0;  // FMM evaluations of steps, by kind
     char *noalloc = nullptr;         // this device's fixed scratch (pt_compute_forces_noalloc)
     std::map<void *, size_t> allocs;
     // workspace (grow-only)
@@ -123,6 +137,8 @@ struct pt_ctx {
     CrystalDev *h_desc = nullptr;
     int h_desc_cap = 0;
     TreeSummary *h_sum = nullptr;
+    int32_t *h_fail = nullptr;                 // pinned: kCheckSlots copies of fail_step
+    hipEvent_t ev_check[kCheckSlots] = {};
     unsigned long long *h_counters = nullptr;
     // last force evaluation (for the debug export and statistics)
     std::vector<pt_crystal *> last_batch;
@@ -130,7 +146,23 @@ struct pt_ctx {
     uint64_t *last_keys = nullptr;
     uint32_t *last_vals = nullptr;
     int last_ntot = 0, last_was_fmm = 0, last_stride = 0, last_p = 0, last_prec = 0;
-    TreeSummary last_sum{};
+    Caps last_cap{};   // capacities (measuring: exact counts) of the last FMM evaluation
+    Caps measured{};   // counts of the last measuring evaluation
+    // capacities for queued steps, valid for one batch (its crystals, size
+    // and force parameters)
+    bool caps_ok = false;
+    Caps caps{};
+    double caps_slack = 1.5;  // raised by half after each overflow, up to 4
+    std::vector<pt_crystal *> caps_batch;
+    int caps_ntot = 0;
+    pt_force_params caps_force{};
+    // the last pt_step_batch call, until its outcome has been read back: a
+    // step that halted (see TreeSummary) is re-run from there on
+    struct Pending {
+        bool active = false;
+        std::vector<pt_crystal *> cs;
+        std::vector<int64_t> n_steps, step_start;
+    } pending;
     // timing: a ring of event sets, ring_cur the set of the evaluation being
     // queued, ring_pending sets recorded and not yet collected (the oldest at
     // ring_cur - ring_pending)
@@ -421,6 +453,7 @@ static pt_status form_batch(pt_ctx *ctx, const std::vector<pt_crystal *> &cs, Ba
 }
 
 static pt_status finish_timing(pt_ctx *ctx);
+static pt_status settle(pt_ctx *ctx);
 
 static void mark(pt_ctx *ctx, int i)
 {
@@ -484,11 +517,34 @@ static BoxTable box_table(pt_ctx *ctx)
     return t;
 }
 
+// Capacities for queued evaluations of a batch whose measured counts are m:
+// room for a tree that grows from step to step (slack times as many boxes,
+// items and pairs, a quarter more boxes per level, as many levels).
+static Caps grow_caps(const Caps &m, double slack)
+{
+    Caps c = m;
+    c.nbox = (int)(m.nbox * slack) + 16;
+    c.items = (int)(m.items * slack) + 64;
+    c.pairs = (int)(m.pairs * slack) + 256;
+    for (int l = 0; l <= kMaxLevel; ++l) c.lvl[l] = l < m.nlev ? m.lvl[l] + m.lvl[l] / 4 + 8 : 0;
+    return c;
+}
+
+
 // Coulomb field per unit charge of every ion of the batch into E (3 x ntot,
 // batch order); with phi non-null also the potential per unit charge
 // (sum_{j != i} 1/r_ij, ntot).  Expects the bbox of the current positions
 // accumulated.
-static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, double *E, double *phi = nullptr)
+//
+// With the FMM, two ways: measuring (queued == nullptr), where the host
+// reads back the tree's size and then the numbers of near-field items and
+// M2L pairs and sizes everything exactly (two host waits), the counts going
+// to ctx->measured; or queued, where buffers and grids are sized from the
+// capacities *queued, kernels read the counts on the device, nothing is read
+// back, and a count above its capacity halts the run on the device (the
+// step's kick then leaves the state as it was, see TreeSummary).
+static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, double *E, double *phi = nullptr,
+                            const Caps *queued = nullptr)
 {
     hipStream_t st = ctx->stream;
     const int ntot = b.ntot, nc = (int)b.cs.size();
@@ -529,7 +585,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "sp", sizeof(double) * 3 * ntot, &sp));
     PT_TRY(ws_get(ctx, "sum", sizeof(TreeSummary), &dsum));
     launch_root(bbox, nc, roots, st);
-    launch_keys(b.d_desc, b.ion_crystal, roots, ntot, k0, v0, st);
+    launch_keys(b.d_desc, b.ion_crystal, roots, ntot, k0, v0, &dsum->halt, st);
     int cbits = 0;
     while ((1 << cbits) < nc) ++cbits;
     const int passes = (48 + cbits + 7) / 8;
@@ -541,7 +597,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         zr.p[0] = (uint64_t *)rstate;
         zr.n[0] = radix_state_zero_words() / 2;
         launch_zero_regions(zr, st);
-        if (launch_radix_sort(k0, v0, k1, v1, ntot, passes, rstate, st) == 1) {
+        if (launch_radix_sort(k0, v0, k1, v1, ntot, passes, rstate, &dsum->halt, st) == 1) {
             std::swap(k0, k1);
             std::swap(v0, v1);
         }
@@ -553,20 +609,36 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             std::swap(v0, v1);
         }
     }
-    launch_gather(b.d_desc, b.ion_crystal, v0, ntot, sp, st);
+    launch_gather(b.d_desc, b.ion_crystal, v0, ntot, sp, &dsum->halt, st);
     launch_tree_count(b.d_desc, k0, ntot, s, rep, box_end, bcnt, scan_part, total, sort_err, dsum, st);
-    PT_HIP(hipMemcpyAsync(ctx->h_sum, dsum, sizeof(TreeSummary), hipMemcpyDeviceToHost, st));
-    PT_HIP(hipStreamSynchronize(st));
-    const TreeSummary hs = *ctx->h_sum;
-    if (hs.sort_error) {
-        pt_set_error("radix sort: a workgroup gave up waiting for its predecessors' digit counts");
-        return PT_EDEVICE;
+    Caps cap{};
+    if (queued) {
+        cap = *queued;
+        launch_cap_check_tree(dsum, cap, st);
+    } else {
+        PT_HIP(hipMemcpyAsync(ctx->h_sum, dsum, sizeof(TreeSummary), hipMemcpyDeviceToHost, st));
+        PT_HIP(hipStreamSynchronize(st));
+        const TreeSummary hs = *ctx->h_sum;
+        ctx->eval_halted = hs.halt != 0;
+        if (hs.halt) {
+            // an earlier step of this run halted: nothing more is done (every
+            // kernel would skip, and the counts read back are stale)
+            for (int i = 1; i <= kPhases - 1; ++i) mark(ctx, i);
+            timing_end(ctx);
+            return PT_OK;
+        }
+        if (hs.sort_error) {
+            pt_set_error("radix sort: a workgroup gave up waiting for its predecessors' digit counts");
+            return PT_EDEVICE;
+        }
+        cap.nbox = hs.nbox;
+        for (int l = 0; l <= kMaxLevel; ++l) {
+            cap.lvl[l] = hs.level_start[l + 1] - hs.level_start[l];
+            if (cap.lvl[l] > 0) cap.nlev = l + 1;
+        }
     }
-    const int nbox = hs.nbox;
-    int nlev = 0;
-    for (int l = 0; l <= kMaxLevel; ++l)
-        if (hs.level_start[l + 1] > hs.level_start[l]) nlev = l + 1;
-    const int stride = kNeigh + 26 * std::max(0, nlev - 1);
+    const int nbox = cap.nbox;
+    const int stride = kNeigh + 26 * std::max(0, cap.nlev - 1);
     const int Kp = kpad(p);
     const size_t esz = fp.precision == 1 ? sizeof(float) : sizeof(double);
     void *scratch;
@@ -596,9 +668,9 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_HIP(hipEventRecord(ctx->ev_tree, st));
     PT_HIP(hipStreamWaitEvent(ctx->near_stream, ctx->ev_tree, 0));
     if (fp.precision == 1)
-        launch_p2m<float>(bt, sp, ntot, p, hs, ctx->tables.rec_f, (float *)M, s, ctx->near_stream);
+        launch_p2m<float>(bt, dsum, sp, ntot, p, nbox, ctx->tables.rec_f, (float *)M, s, ctx->near_stream);
     else
-        launch_p2m<double>(bt, sp, ntot, p, hs, ctx->tables.rec_d, (double *)M, s, ctx->near_stream);
+        launch_p2m<double>(bt, dsum, sp, ntot, p, nbox, ctx->tables.rec_d, (double *)M, s, ctx->near_stream);
     PT_HIP(hipEventRecord(ctx->ev_p2m, ctx->near_stream));
     int32_t *child_oct, *parent_oct, *src_items;
     uint32_t *item_off;
@@ -624,14 +696,18 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     // with the near-field item count
     launch_m2l_count(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, scan_part, total + 2, st);
     // near-field work items and M2L pairs: their numbers size the item,
-    // partial and pair buffers.  They are read back while the upward pass,
-    // which does not need them, runs: the host waits for an event right after
-    // the copy, not for the stream.
-    PT_HIP(hipMemcpyAsync(ctx->h_counters, total + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    PT_HIP(hipEventRecord(ctx->ev_read, st));
+    // partial and pair buffers.  Measuring, they are read back while the
+    // upward pass, which does not need them, runs: the host waits for an
+    // event right after the copy, not for the stream.
+    if (queued) {
+        launch_cap_check_lists(dsum, total, cap, st);
+    } else {
+        PT_HIP(hipMemcpyAsync(ctx->h_counters, total + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        PT_HIP(hipEventRecord(ctx->ev_read, st));
+    }
     int32_t *p2p_queue;
     void *xl_part;
-    const int ngroup = m2l_groups(nbox - hs.level_start[2]);
+    const int ngroup = m2l_groups(0);
     PT_TRY(ws_get(ctx, "p2p_queue", sizeof(uint64_t), &p2p_queue));
     PT_TRY(ws_get(ctx, "xl_part", esz * Kp * (size_t)nbox * ngroup, (char **)&xl_part));
     mark(ctx, 1);
@@ -648,13 +724,16 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         using T = decltype(tag);
         const T *m2m = sizeof(T) == sizeof(float) ? (const T *)tb.m2m_f : (const T *)tb.m2m_d;
         PT_HIP(hipStreamWaitEvent(st, ctx->ev_p2m, 0));  // P2M (second stream)
-        launch_m2m<T>(bt, p, hs, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, st);
+        launch_m2m<T>(bt, dsum, p, cap, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, st);
         return PT_OK;
     };
     PT_TRY(fp.precision == 1 ? upward(float(0)) : upward(double(0)));
-    PT_HIP(hipEventSynchronize(ctx->ev_read));
-    const int n_items = (int)((uint32_t *)ctx->h_counters)[0];
-    const int n_pairs = (int)((uint32_t *)ctx->h_counters)[1];
+    if (!queued) {
+        PT_HIP(hipEventSynchronize(ctx->ev_read));
+        cap.items = (int)((uint32_t *)ctx->h_counters)[0];
+        cap.pairs = (int)((uint32_t *)ctx->h_counters)[1];
+    }
+    const int n_items = cap.items, n_pairs = cap.pairs;
     int4 *work, *m2l_bucket;
     int32_t *m2l_ops_tab;
     void *m2l_R;
@@ -693,8 +772,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             // beside M2L the grid is capped and the workgroups take items from
             // a queue; alone, one workgroup per item (no queue: its atomics
             // would serialise over the many small items of small leaves)
-            launch_near<T>(bt, sp, ntot, near, stride, work, n_items, (T *)ppart, phi != nullptr, max_grid,
-                           concurrent ? p2p_queue : nullptr, ns);
+            launch_near<T>(bt, dsum, sp, ntot, near, stride, work, total + 1, n_items, (T *)ppart, phi != nullptr,
+                           max_grid, concurrent ? p2p_queue : nullptr, ns);
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][1], ns));
             ctx->near_timed[ctx->ring_cur] = ctx->timing;
             if (concurrent) PT_HIP(hipEventRecord(ctx->ev_join, ns));
@@ -704,28 +783,37 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         mark(ctx, 2);
         const int m2l_grid =
             ctx->num_cu * m2l_per_cu<T>(Kp, concurrent ? kNearPerCUConcurrent * near_lds_bytes() : 0);
-        launch_m2l_gemm<T>(Kp, nbox, m2l_grid, m2l_chunk_off, m2l_op_beg, m2l_bucket, m2l, (const T *)M,
+        launch_m2l_gemm<T>(dsum, Kp, nbox, m2l_grid, m2l_chunk_off, m2l_op_beg, m2l_bucket, m2l, (const T *)M,
                            (T *)m2l_R, st);
         mark(ctx, 3);
         launch_m2l_sum<T>(dsum, nbox, Kp, m2l_pcnt, total + 2, (const T *)m2l_R, (T *)L, st);
-        launch_downward<T>(bt, p, hs, l2l, tb.oct_slots, parent_oct, (T *)L, (T *)xl_part, st);
+        launch_downward<T>(bt, dsum, p, cap, l2l, tb.oct_slots, parent_oct, (T *)L, (T *)xl_part, st);
         mark(ctx, 4);
         if (!concurrent) PT_TRY(near_field());
         mark(ctx, 5);
         if (concurrent) PT_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
-        launch_far<T>(bt, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E, phi, s,
-                      st);
+        launch_far<T>(bt, dsum, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E,
+                      phi, s, st);
         return PT_OK;
     };
     PT_TRY(fp.precision == 1 ? run(float(0)) : run(double(0)));
     mark(ctx, 6);
     timing_end(ctx);
-    ctx->last_sum = hs;
+    if (!queued) ctx->measured = cap;
+    ctx->last_cap = cap;
     ctx->last_stride = stride;
     ctx->last_p = p;
     ctx->last_prec = fp.precision;
     ctx->last_keys = k0;  // the ping-pong buffer holding the sorted result
     ctx->last_vals = v0;
+    return PT_OK;
+}
+
+// The device summary of the last FMM evaluation (waits for the stream).
+static pt_status read_summary(pt_ctx *ctx, TreeSummary &out)
+{
+    PT_HIP(hipStreamSynchronize(ctx->stream));
+    PT_HIP(hipMemcpy(&out, ctx->ws["sum"].ptr, sizeof(TreeSummary), hipMemcpyDeviceToHost));
     return PT_OK;
 }
 
@@ -788,6 +876,9 @@ static void release_ctx(pt_ctx *ctx)
     ctx->allocs.clear();
     if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
     if (ctx->h_sum) (void)hipHostFree(ctx->h_sum);
+    if (ctx->h_fail) (void)hipHostFree(ctx->h_fail);
+    for (hipEvent_t e : ctx->ev_check)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
     for (auto &set : ctx->ev)
         for (auto &e : set)
@@ -811,9 +902,13 @@ static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
         ctx->own_stream = true;
     }
     PT_HIP(hipHostMalloc((void **)&ctx->h_sum, sizeof(TreeSummary)));
+    PT_HIP(hipHostMalloc((void **)&ctx->h_fail, sizeof(int32_t) * kCheckSlots));
+    for (auto &e : ctx->ev_check) PT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     PT_HIP(hipHostMalloc((void **)&ctx->h_counters, sizeof(unsigned long long) * 2));
     PT_HIP(hipStreamCreateWithFlags(&ctx->near_stream, hipStreamNonBlocking));
     if (const char *e = getenv("PT_NEAR_CONCURRENT")) ctx->near_concurrent = atoi(e) ? 1 : 0;
+    if (const char *e = getenv("PT_QUEUED_STEPS")) ctx->no_queue = atoi(e) == 0;
+    if (const char *e = getenv("PT_CAPS_TIGHT")) ctx->tight_caps = atoi(e) != 0;
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_tree, hipEventDisableTiming));
@@ -854,6 +949,7 @@ pt_status pt_ctx_create(int hip_device, uint64_t hbm_budget_bytes, void *hip_str
 pt_status pt_ctx_destroy(pt_ctx *ctx)
 {
     PT_REQUIRE(ctx, "ctx is NULL");
+    (void)settle(ctx);
     if (ctx->live > 0) {
         pt_set_error("context still owns %d crystals", ctx->live);
         return PT_EBUSY;
@@ -961,7 +1057,9 @@ pt_status pt_destroy_crystal(pt_crystal *c)
 {
     PT_REQUIRE(c, "crystal is NULL");
     pt_ctx *ctx = c->ctx;
+    (void)settle(ctx);
     (void)hipStreamSynchronize(ctx->stream);
+    if (std::find(ctx->caps_batch.begin(), ctx->caps_batch.end(), c) != ctx->caps_batch.end()) ctx->caps_ok = false;
     ctx_free(ctx, c->d_state);
     ctx_free(ctx, c->d_photons);
     ctx_free(ctx, c->d_nonfinite);
@@ -979,6 +1077,7 @@ static bool beams_fit_step(const pt_laser_params &l, double dt) { return l.mode 
 pt_status pt_set_trap_params(pt_crystal *c, const pt_trap_params *p)
 {
     PT_REQUIRE(c, "crystal is NULL");
+    PT_TRY(settle(c->ctx));
     PT_TRY(check_trap(c, p));
     PT_REQUIRE(beams_fit_step(c->laser, p->dt_s), "gamma0 dt = %g exceeds 4 with the crystal's laser beams",
                c->laser.gamma0 * p->dt_s);
@@ -989,6 +1088,7 @@ pt_status pt_set_trap_params(pt_crystal *c, const pt_trap_params *p)
 pt_status pt_set_laser_params(pt_crystal *c, const pt_laser_params *p)
 {
     PT_REQUIRE(c && p, "NULL argument");
+    PT_TRY(settle(c->ctx));
     PT_REQUIRE(p->mode >= 0 && p->mode <= 2, "laser mode must be 0, 1 or 2");
     if (p->mode == 1) {
         PT_REQUIRE(std::isfinite(p->mean_per_step) && p->mean_per_step >= 0.0 && p->mean_per_step <= 2.0,
@@ -1017,6 +1117,7 @@ pt_status pt_set_laser_params(pt_crystal *c, const pt_laser_params *p)
 pt_status pt_set_force_params(pt_crystal *c, const pt_force_params *p)
 {
     PT_REQUIRE(c, "crystal is NULL");
+    PT_TRY(settle(c->ctx));
     PT_TRY(check_force(p));
     c->force = *p;
     return PT_OK;
@@ -1027,6 +1128,7 @@ pt_status pt_set_state(pt_crystal *c, const double *pos, const double *vel, int6
     PT_REQUIRE(c && pos && vel, "NULL argument");
     PT_REQUIRE(step >= 0, "step must be >= 0");
     PT_REQUIRE(finite_all(pos, 3 * c->n) && finite_all(vel, 3 * c->n), "non-finite position or velocity");
+    PT_TRY(settle(c->ctx));
     PT_HIP(hipStreamSynchronize(c->ctx->stream));
     PT_TRY(upload_state(c, pos, vel));
     PT_HIP(hipMemset(c->d_nonfinite, 0, sizeof(int32_t)));
@@ -1065,7 +1167,13 @@ static pt_status evaluate_batch(pt_crystal *const *cs, int n_crystals, double *c
         U_out = U_diag.data();
     }
     pt_ctx *ctx = cs[0]->ctx;
+    PT_TRY(settle(ctx));
     PT_HIP(hipSetDevice(ctx->device));
+    if (cs[0]->force.method == 1) {  // a fresh run state for the measuring evaluation
+        TreeSummary *dsum;
+        PT_TRY(ws_get(ctx, "sum", sizeof(TreeSummary), &dsum));
+        launch_run_reset(dsum, ctx->stream);
+    }
     Batch b;
     PT_TRY(form_batch(ctx, std::vector<pt_crystal *>(cs, cs + n_crystals), b));
     unsigned long long *bbox;
@@ -1074,7 +1182,7 @@ static pt_status evaluate_batch(pt_crystal *const *cs, int n_crystals, double *c
     PT_TRY(ws_get(ctx, "E", sizeof(double) * 3 * (size_t)b.ntot, &E));
     if (phi_out || U_out) PT_TRY(ws_get(ctx, "phi", sizeof(double) * (size_t)std::max(1, b.ntot), &phi));
     if (U_out) PT_TRY(ws_get(ctx, "phi_sum", sizeof(double) * (size_t)n_crystals, &usum));
-    launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, n_crystals, 0, bbox, ctx->stream);
+    launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, n_crystals, 0, bbox, nullptr, ctx->stream);
     PT_TRY(eval_field(ctx, b, cs[0]->force, E, phi));
     std::vector<double> h, hp, hu;
     if (F_out) {
@@ -1174,6 +1282,7 @@ pt_status pt_read_rotating_state(pt_crystal *c, double *pos_r, double *vel_r)
 {
     PT_REQUIRE(c, "crystal is NULL");
     pt_ctx *ctx = c->ctx;
+    PT_TRY(settle(ctx));
     PT_HIP(hipSetDevice(ctx->device));
     Batch b;
     PT_TRY(form_batch(ctx, std::vector<pt_crystal *>{c}, b));
@@ -1206,6 +1315,7 @@ pt_status pt_compute_forces_noalloc(pt_crystal *c, double *F_dev)
     PT_REQUIRE(c->n <= kNoAllocMaxIons, "n = %lld exceeds the no-allocation limit of %d ions", (long long)c->n,
                kNoAllocMaxIons);
     pt_ctx *ctx = c->ctx;
+    PT_TRY(settle(ctx));  // steps still pending are completed first
     const int n = (int)c->n;
     const NoAllocLayout l = noalloc_layout(n);
     PT_REQUIRE(l.total <= kNoAllocScratchBytes, "scratch layout of %zu bytes exceeds %zu", l.total,
@@ -1222,7 +1332,7 @@ pt_status pt_compute_forces_noalloc(pt_crystal *c, double *F_dev)
     hipStream_t st = ctx->stream;
     launch_noalloc_setup(d, desc, ion_crystal, n, blk_crystal, blk_first, l.nblk, st);
     launch_bbox_reset(bbox, 1, st);
-    launch_drift_bbox(desc, ion_crystal, n, 1, 0, bbox, st);
+    launch_drift_bbox(desc, ion_crystal, n, 1, 0, bbox, nullptr, st);
     launch_direct(desc, blk_crystal, blk_first, l.nblk, n, E, nullptr, st);
     const double ke = 1.0 / (4.0 * kPi * kEps0), q = c->q;
     launch_scale_field(E, n, ke * q * q, F_dev, st);
@@ -1230,25 +1340,64 @@ pt_status pt_compute_forces_noalloc(pt_crystal *c, double *F_dev)
     return PT_OK;
 }
 
-pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_steps)
+// Queues n_steps[i] steps of crystal i (all of one context and force
+// parameters).  With the FMM, the first evaluation of a batch that has no
+// valid capacities measures its counts (two host waits); the following steps
+// are queued on capacities grown from them, with no host wait.  The outcome
+// is read back by settle() at the context's next call.
+static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, const int64_t *n_steps)
 {
-    PT_TRY(check_batch(cs, n_crystals));
-    PT_REQUIRE(n_steps, "n_steps NULL");
     int64_t kmax = 0;
-    for (int i = 0; i < n_crystals; ++i) {
-        PT_REQUIRE(n_steps[i] >= 0, "n_steps must be >= 0");
-        kmax = std::max(kmax, n_steps[i]);
-    }
-    pt_ctx *ctx = cs[0]->ctx;
+    for (int i = 0; i < n_crystals; ++i) kmax = std::max(kmax, n_steps[i]);
     PT_HIP(hipSetDevice(ctx->device));
+    const pt_force_params fp = cs[0]->force;
+    const bool fmm = fp.method == 1;
+    TreeSummary *dsum = nullptr;
+    if (fmm) {
+        PT_TRY(ws_get(ctx, "sum", sizeof(TreeSummary), &dsum));
+        launch_run_reset(dsum, ctx->stream);
+    }
+    ctx->pending.active = true;
+    ctx->pending.cs.assign(cs, cs + n_crystals);
+    ctx->pending.n_steps.assign(n_steps, n_steps + n_crystals);
+    ctx->pending.step_start.resize(n_crystals);
+    for (int i = 0; i < n_crystals; ++i) ctx->pending.step_start[i] = cs[i]->step;
     Batch b;
     int formed_for = -1;
     int64_t group_start = 0;  // step at which the current batch was formed
+    int checks = 0, looked = 0;  // run-state copies issued, and looked at
     // Each crystal's step counter advances as its steps are queued, so that
     // after a failure it counts exactly the completed steps; a step that
     // fails before its kick leaves the state as it was (the half drift and
     // everything up to the kick work on a copy).
     for (int64_t k = 0; k < kmax; ++k) {
+        if (fmm && k > 0 && k % kCheckEvery == 0) {
+            // look at the copies that have landed, waiting only for those more
+            // than kCheckAhead checks back (the host stays at most that many
+            // segments ahead of the device, which keeps as many queued), then
+            // issue one
+            bool halted = false;
+            while (looked < checks && !halted) {
+                const int sl = looked % kCheckSlots;
+                if (checks - looked > kCheckAhead) {
+                    PT_HIP(hipEventSynchronize(ctx->ev_check[sl]));
+                } else {
+                    const hipError_t q = hipEventQuery(ctx->ev_check[sl]);
+                    if (q == hipErrorNotReady) break;
+                    PT_HIP(q);
+                }
+                halted = ctx->h_fail[sl] >= 0;
+                ++looked;
+            }
+            if (halted) break;  // the next call re-runs from the halted step (settle)
+            if (checks - looked < kCheckSlots) {
+                const int sl = checks % kCheckSlots;
+                PT_HIP(hipMemcpyAsync(ctx->h_fail + sl, &dsum->fail_step, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      ctx->stream));
+                PT_HIP(hipEventRecord(ctx->ev_check[sl], ctx->stream));
+                ++checks;
+            }
+        }
         // crystals still stepping; the batch is re-formed only when one finishes
         int nactive = 0;
         for (int i = 0; i < n_crystals; ++i) nactive += n_steps[i] > k;
@@ -1266,14 +1415,72 @@ pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_
         double *E;
         PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * bbox_words(nc), &bbox));
         PT_TRY(ws_get(ctx, "E", sizeof(double) * 3 * (size_t)b.ntot, &E));
-        launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, nc, 1, bbox, ctx->stream);
-        PT_TRY(eval_field(ctx, b, cs[0]->force, E));
+        launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, nc, 1, bbox, fmm ? &dsum->halt : nullptr, ctx->stream);
+        const bool queued = fmm && ctx->caps_ok && ctx->caps_batch == b.cs && ctx->caps_ntot == b.ntot &&
+                            same_force(ctx->caps_force, fp);
+        ctx->eval_halted = false;
+        PT_TRY(eval_field(ctx, b, fp, E, nullptr, queued ? &ctx->caps : nullptr));
+        if (fmm) (queued ? ctx->n_queued : ctx->n_measured)++;
+        if (fmm && !queued && !ctx->eval_halted) {
+            ctx->caps = grow_caps(ctx->measured, ctx->caps_slack);
+            if (ctx->tight_caps) ctx->caps.nbox = std::max(1, ctx->measured.nbox - 1);
+            ctx->caps_batch = b.cs;
+            ctx->caps_ntot = b.ntot;
+            ctx->caps_force = fp;
+            ctx->caps_ok = !ctx->no_queue;
+        }
         // step index = descriptor step0 (set when the batch formed) + kstep
-        launch_kick_drift(b.d_desc, b.ion_crystal, b.ntot, (int)(k - group_start), E, b.beams, ctx->stream);
+        launch_kick_drift(b.d_desc, b.ion_crystal, b.ntot, (int)(k - group_start), E, b.beams, dsum, (int)k,
+                          ctx->stream);
         for (pt_crystal *c : b.cs) c->step++;
     }
     PT_HIP(hipGetLastError());
     return PT_OK;
+}
+
+// Reads back the outcome of the last queued steps: if a step halted on the
+// device (its tree or lists outgrew the capacities), every crystal stands at
+// the last completed step; the step counters are set to it and the rest is
+// run again from there, starting with a measuring evaluation (so each pass
+// completes at least one step).
+static pt_status settle(pt_ctx *ctx)
+{
+    while (ctx->pending.active) {
+        ctx->pending.active = false;
+        auto it = ctx->ws.find("sum");
+        if (it == ctx->ws.end() || ctx->pending.cs.empty() || ctx->pending.cs[0]->force.method != 1) return PT_OK;
+        TreeSummary ts;
+        PT_HIP(hipStreamSynchronize(ctx->stream));
+        PT_HIP(hipMemcpy(&ts, it->second.ptr, sizeof(TreeSummary), hipMemcpyDeviceToHost));
+        if (ts.fail_step < 0) return PT_OK;
+        auto &pd = ctx->pending;
+        const int n = (int)pd.cs.size();
+        std::vector<int64_t> rest(n);
+        for (int i = 0; i < n; ++i) {
+            const int64_t done = std::min<int64_t>(pd.n_steps[i], ts.fail_step);
+            pd.cs[i]->step = pd.step_start[i] + done;
+            rest[i] = pd.n_steps[i] - done;
+        }
+        ctx->caps_ok = false;
+        ctx->caps_slack = std::min(4.0, ctx->caps_slack * 1.5);
+        ctx->reruns++;
+        if (ts.sort_error) {
+            pt_set_error("radix sort: a workgroup gave up waiting for its predecessors' digit counts");
+            return PT_EDEVICE;
+        }
+        std::vector<pt_crystal *> cs = pd.cs;
+        PT_TRY(step_run(ctx, cs.data(), n, rest.data()));
+    }
+    return PT_OK;
+}
+
+pt_status pt_step_batch(pt_crystal *const *cs, int n_crystals, const int64_t *n_steps)
+{
+    PT_TRY(check_batch(cs, n_crystals));
+    PT_REQUIRE(n_steps, "n_steps NULL");
+    for (int i = 0; i < n_crystals; ++i) PT_REQUIRE(n_steps[i] >= 0, "n_steps must be >= 0");
+    PT_TRY(settle(cs[0]->ctx));
+    return step_run(cs[0]->ctx, cs, n_crystals, n_steps);
 }
 
 pt_status pt_step(pt_crystal *c, int64_t n_steps) { return pt_step_batch(&c, 1, &n_steps); }
@@ -1281,6 +1488,7 @@ pt_status pt_step(pt_crystal *c, int64_t n_steps) { return pt_step_batch(&c, 1, 
 pt_status pt_synchronize(pt_ctx *ctx)
 {
     PT_REQUIRE(ctx, "ctx is NULL");
+    PT_TRY(settle(ctx));
     PT_HIP(hipStreamSynchronize(ctx->stream));
     PT_HIP(hipGetLastError());
     int32_t flag = 0;
@@ -1297,6 +1505,7 @@ pt_status pt_read_state(pt_crystal *c, double *pos, double *vel, int64_t *step, 
 {
     PT_REQUIRE(c, "crystal is NULL");
     pt_ctx *ctx = c->ctx;
+    PT_TRY(settle(ctx));
     const int64_t n = c->n;
     std::vector<double> soa(6 * (size_t)n);
     PT_HIP(hipMemcpyAsync(soa.data(), c->d_state, sizeof(double) * 6 * n, hipMemcpyDeviceToHost, ctx->stream));
@@ -1325,6 +1534,7 @@ pt_status pt_read_state(pt_crystal *c, double *pos, double *vel, int64_t *step, 
 pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable)
 {
     PT_REQUIRE(ctx, "ctx is NULL");
+    PT_TRY(settle(ctx));
     PT_TRY(finish_timing(ctx));
     if (enable && !ctx->ring_made) {
         for (auto &set : ctx->ev)
@@ -1342,21 +1552,34 @@ pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable)
 pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[7], int64_t *count)
 {
     PT_REQUIRE(ctx && ms, "NULL argument");
+    PT_TRY(settle(ctx));
     PT_TRY(finish_timing(ctx));
     for (int i = 0; i < kPhases; ++i) ms[i] = ctx->phase_count ? ctx->phase_sum[i] / (double)ctx->phase_count : 0.0;
     if (count) *count = ctx->phase_count;
     return PT_OK;
 }
 
+pt_status pt_ctx_step_stats(pt_ctx *ctx, int64_t *queued, int64_t *measured, int64_t *reruns)
+{
+    PT_REQUIRE(ctx, "ctx is NULL");
+    PT_TRY(settle(ctx));
+    if (queued) *queued = ctx->n_queued;
+    if (measured) *measured = ctx->n_measured;
+    if (reruns) *reruns = ctx->reruns;
+    return PT_OK;
+}
+
 pt_status pt_ctx_work_counts(pt_ctx *ctx, int64_t counts[6])
 {
     PT_REQUIRE(ctx && counts, "NULL argument");
+    PT_TRY(settle(ctx));
     for (int i = 0; i < 6; ++i) counts[i] = 0;
     counts[5] = ctx->last_ntot;
     if (!ctx->last_was_fmm) return PT_OK;
-    PT_HIP(hipStreamSynchronize(ctx->stream));
-    const int nbox = ctx->last_sum.nbox;
-    std::vector<int32_t> vb(vlist_blocks(nbox));
+    TreeSummary ls;
+    PT_TRY(read_summary(ctx, ls));
+    const int nbox = ls.nbox;
+    std::vector<int32_t> vb(vlist_blocks(ctx->last_cap.nbox));
     std::vector<int64_t> np(nbox);
     PT_HIP(hipMemcpy(vb.data(), ctx->ws["v_blk"].ptr, vb.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     PT_HIP(hipMemcpy(np.data(), ctx->ws["near_pairs"].ptr, np.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -1369,7 +1592,7 @@ pt_status pt_ctx_work_counts(pt_ctx *ctx, int64_t counts[6])
     for (uint8_t x : leaf) nl += x;
     int nlev = 0;
     for (int l = 0; l <= kMaxLevel; ++l)
-        if (ctx->last_sum.level_start[l + 1] > ctx->last_sum.level_start[l]) nlev = l + 1;
+        if (ls.level_start[l + 1] > ls.level_start[l]) nlev = l + 1;
     counts[0] = nbox;
     counts[1] = nl;
     counts[2] = nv;
@@ -1385,14 +1608,16 @@ pt_status pt_debug_export_tree(pt_crystal *c, int64_t sizes[4], uint64_t *keys, 
 {
     PT_REQUIRE(c && sizes, "NULL argument");
     pt_ctx *ctx = c->ctx;
+    PT_TRY(settle(ctx));
     auto &lb = ctx->last_batch;
     auto it = std::find(lb.begin(), lb.end(), c);
     PT_REQUIRE(ctx->last_was_fmm && it != lb.end(), "no FMM evaluation of this crystal to export");
     const int ci = (int)(it - lb.begin());
     const int off = ctx->last_off[ci];
     const int n = (int)c->n;
-    const int nbox = ctx->last_sum.nbox, ntot = ctx->last_ntot, stride = ctx->last_stride;
-    PT_HIP(hipStreamSynchronize(ctx->stream));
+    TreeSummary ls;
+    PT_TRY(read_summary(ctx, ls));
+    const int nbox = ls.nbox, ntot = ctx->last_ntot, stride = ctx->last_stride;
     auto dl = [&](const char *nm, void *dst, size_t bytes) -> pt_status {
         PT_HIP(hipMemcpy(dst, ctx->ws[nm].ptr, bytes, hipMemcpyDeviceToHost));
         return PT_OK;

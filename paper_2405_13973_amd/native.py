@@ -103,6 +103,7 @@ def load():
         "pt_ctx_set_timing": [_vp, C.c_int],
         "pt_ctx_phase_times": [_vp, _dp, C.POINTER(C.c_int64)],
         "pt_ctx_work_counts": [_vp, C.POINTER(C.c_int64)],
+        "pt_ctx_step_stats": [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -179,6 +180,12 @@ class Context:
         c = np.zeros(6, np.int64)
         _check(load().pt_ctx_work_counts(self.h, _ptr(c, C.c_int64)))
         return c
+
+    def step_stats(self):
+        """FMM step evaluations queued on capacities, measured, and queued runs re-run."""
+        q, m, r = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(load().pt_ctx_step_stats(self.h, C.byref(q), C.byref(m), C.byref(r)))
+        return dict(queued=q.value, measured=m.value, reruns=r.value)
 
     def synchronize(self):
         _check(load().pt_synchronize(self.h))
