@@ -131,10 +131,10 @@ template <typename T>
 void launch_near(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, const int2 *near, int stride,
                  const int4 *work, const uint32_t *n_items, int cap_items, T *part, bool pot, int max_grid, int *queue,
                  hipStream_t st);
-// Near-field workgroups per compute unit while the translation GEMM runs
-// beside the near field: with this many, one GEMM workgroup still fits in
-// every compute unit's LDS, whichever kernel reaches the unit first.
-constexpr int kNearPerCUConcurrent = 6;
+// Near-field workgroups per compute unit while the M2L GEMM runs beside the
+// near field: with this many, two GEMM workgroups still fit in every compute
+// unit's LDS, whichever kernel reaches the unit first.
+constexpr int kNearPerCUConcurrent = 4;
 // LDS of one near-field workgroup (its staged sources and range tables).
 size_t near_lds_bytes();
 // Far field (L2P) + the item partials per ion into E (batch order); with phi

@@ -120,6 +120,7 @@ struct pt_ctx {
     hipEvent_t ev_near[kTimingRing][2] = {};  // timing of the P2P kernel (its own stream)
     bool near_timed[kTimingRing] = {};
     int near_concurrent = -1;  // -1: by leaf size; 0 / 1: forced (PT_NEAR_CONCURRENT)
+    int near_per_cu = kNearPerCUConcurrent;  // near-field workgroups per CU beside M2L (PT_NEAR_PER_CU)
     uint64_t budget = 0, used = 0;
     int live = 0;
     int32_t *d_nonfinite = nullptr;  // set by any kick of this context that produces a non-finite value
@@ -768,7 +769,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         }
         auto near_field = [&]() -> pt_status {
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][0], ns));
-            const int max_grid = concurrent ? kNearPerCUConcurrent * ctx->num_cu : 16384;
+            const int max_grid = concurrent ? ctx->near_per_cu * ctx->num_cu : 16384;
             // beside M2L the grid is capped and the workgroups take items from
             // a queue; alone, one workgroup per item (no queue: its atomics
             // would serialise over the many small items of small leaves)
@@ -782,7 +783,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         if (concurrent) PT_TRY(near_field());
         mark(ctx, 2);
         const int m2l_grid =
-            ctx->num_cu * m2l_per_cu<T>(Kp, concurrent ? kNearPerCUConcurrent * near_lds_bytes() : 0);
+            ctx->num_cu * m2l_per_cu<T>(Kp, concurrent ? ctx->near_per_cu * near_lds_bytes() : 0);
         launch_m2l_gemm<T>(dsum, Kp, nbox, m2l_grid, m2l_chunk_off, m2l_op_beg, m2l_bucket, m2l, (const T *)M,
                            (T *)m2l_R, st);
         mark(ctx, 3);
@@ -907,6 +908,7 @@ static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
     PT_HIP(hipHostMalloc((void **)&ctx->h_counters, sizeof(unsigned long long) * 2));
     PT_HIP(hipStreamCreateWithFlags(&ctx->near_stream, hipStreamNonBlocking));
     if (const char *e = getenv("PT_NEAR_CONCURRENT")) ctx->near_concurrent = atoi(e) ? 1 : 0;
+    if (const char *e = getenv("PT_NEAR_PER_CU")) ctx->near_per_cu = std::max(1, std::min(8, atoi(e)));
     if (const char *e = getenv("PT_QUEUED_STEPS")) ctx->no_queue = atoi(e) == 0;
     if (const char *e = getenv("PT_CAPS_TIGHT")) ctx->tight_caps = atoi(e) != 0;
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
