@@ -618,11 +618,15 @@ def main():
             f"ion-steps/s (without events {plain * 1e3:.2f} ms); rms err start {err:.2e} end {err_end:.2e}; "
             f"phases(ms) " + " ".join(f"{k} {v:.3f}" for k, v in zip(PHASES, phases)) + f" over {count} evals")
 
-    # direct-sum rate on the same crystal, for the FMM/direct comparison
+    # direct-sum rate on the same crystal, for the FMM/direct comparison and
+    # the direct kernel's own roofline (mean of three evaluations)
     c.set_force("direct")
     ctx.set_timing(True)
-    c.compute_forces()
-    dir_ms = ctx.phase_times()[6]
+    dir_runs = []
+    for _ in range(3):
+        c.compute_forces()
+        dir_runs.append(ctx.phase_times()[6])
+    dir_ms = float(np.mean(dir_runs))
     ctx.set_timing(False)
 
     main_r = results[a.precision]
@@ -649,6 +653,17 @@ def main():
     # the dominant kernel: the longer of the two, by its measured time in the
     # timed region (or the one asked for)
     kernel = a.roofline if a.roofline != "auto" else max(rooflines, key=lambda k: rooflines[k]["kernel_ms"])
+    # the exact direct sum (not part of the FMM step): both of its kernels
+    dir_pairs = float(cr.n) * (cr.n - 1)
+    rooflines["direct"] = {
+        "bound": "alu", "kernel": "direct", "kernel_ms": dir_ms,
+        "achieved": P2P_FLOPS_PER_PAIR * dir_pairs / (dir_ms * 1e-3) / 1e12, "peak": PEAK["valu_fp64"],
+        "unit": "TFLOP/s", "traffic": None,
+        "algorithmic": f"{P2P_FLOPS_PER_PAIR} flops per ordered pair (i != j), {int(dir_pairs)} pairs per evaluation "
+                       f"(FP64, the chunk sums and their reduction)"}
+    rooflines["direct"]["frac"] = rooflines["direct"]["achieved"] / rooflines["direct"]["peak"]
+    log(f"  direct sum: {dir_ms:.3f} ms per evaluation, {rooflines['direct']['achieved']:.1f} TFLOP/s "
+        f"({100 * rooflines['direct']['frac']:.1f}% of the FP64 vector peak)")
     value = cr.n * a.steps / main_r["seconds"]
     out = {
         "metric": METRIC,

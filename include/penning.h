@@ -173,7 +173,7 @@ pt_status pt_compute_forces_batch(pt_crystal *const *cs, int n_crystals, double 
  * F_dev (n x 3 doubles, ion-id order, owned by the caller), queued on the
  * context's stream and not waited for (pt_synchronize waits).  The result is
  * bit-identical to pt_compute_forces with the direct method.  Its work
- * buffers live in one fixed per-GPU device array of 7 MiB, set up when the
+ * buffers live in one fixed per-GPU device array of 24 MiB, set up when the
  * context is created; the call itself allocates nothing.  Limits: the
  * crystal's force method must be the direct sum and n <= PT_NOALLOC_MAX_IONS
  * (else PT_EINVAL).  Every such call on one GPU shares that array, and the

@@ -374,70 +374,135 @@ __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *_
 
 // Direct Coulomb field E_i = sum_{j != i} (x_i - x_j)/|x_i - x_j|^3 (FP64);
 // with POT also the potential sum_{j != i} 1/|x_i - x_j| (both per unit
-// charge; the pair term of eq. hamiltonian).
-// A block takes kDirTB targets of one crystal (blk_crystal/blk_first) and
-// streams that crystal's ions through LDS in tiles; every thread owns two
-// targets.  Sources are summed in ascending index order, so the result does
-// not depend on the batch.
-constexpr int kDirTB = 256;
-constexpr int kDirT = 2;
+// charge; the pair term of eq. hamiltonian).  Work split: direct_chunks.
+//
+// First level: block (c, first, chunk) takes targets first + lane + 64 t of
+// crystal c and chunk `chunk` of its sources.  Each wave walks its own piece
+// of the chunk in ascending order, kDirUnroll sources at a time; the source index
+// is the same for the whole wave, so the sources arrive by scalar loads and
+// enter the arithmetic as scalar operands, with no LDS staging or barrier in
+// the loop.  The block's waves then add their sums in wave order through LDS
+// and store the chunk's partials.
+//
+// Pair arithmetic.  r2 carries an offset of 2^-680, below the rounding of
+// any r2 above 2^-626 (separations above 1e-94 m), so that r2 > 0 also for
+// coincident ions.  r^-3 comes from the hardware reciprocal square root y0,
+// whose relative error is about 5e-8, by the second-order correction
+//   r^-3 = y0^3 (1 - e)^(-3/2) = y0^3 (1 + 3/2 e + 15/8 e^2 + O(e^3)),  e = 1 - r2 y0^2,
+// which is within an ulp or two of the correctly rounded value (the e^3 term is
+// below 1e-22).  A pair at zero separation contributes nothing: its
+// dx = dy = dz = 0 multiply a finite weight (about 2^1020), and for the
+// potential it is masked.  That includes j = i, so the loop has no index
+// test and no branch.
+constexpr double kDirR2Offset = 0x1p-680;
+constexpr int kDirUnroll = 4;  // sources per scalar load of each coordinate
 
 template <bool POT>
-__global__ __launch_bounds__(kDirTB) void k_direct(const CrystalDev *__restrict__ cs,
-                                                   const int32_t *__restrict__ blk_crystal,
-                                                   const int32_t *__restrict__ blk_first, int ntot,
-                                                   double *__restrict__ E, double *__restrict__ PHI)
+__global__ __launch_bounds__(64 * kDirWaves) __attribute__((amdgpu_waves_per_eu(8))) void k_direct(const CrystalDev *__restrict__ cs,
+                                                           const DirBlock *__restrict__ tab,
+                                                           double *__restrict__ part)
 {
-    __shared__ double sx[kDirTB], sy[kDirTB], sz[kDirTB];
-    const int c = blk_crystal[blockIdx.x];
-    const CrystalDev &cd = cs[c];
-    const int n = cd.n;
-    const double *s = cd.mid;
-    double xi[kDirT], yi[kDirT], zi[kDirT], ax[kDirT], ay[kDirT], az[kDirT], av[kDirT];
-    int ti[kDirT];
+    constexpr int NC = POT ? 4 : 3;
+    __shared__ double red[kDirWaves - 1][NC][kDirTile];
+    const DirBlock blk = tab[blockIdx.x];
+    const CrystalDev &cd = cs[blk.c];
+    const int n = cd.n, chunks = direct_chunks(n), len = direct_piece(n);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int j0 = min(n, (blk.chunk * kDirWaves + wave) * len), j1 = min(n, j0 + len);
+    // the positions, as global memory: with the wave-uniform index below the
+    // compiler then reads them with scalar loads
+    using gdouble = const __attribute__((address_space(1))) double;
+    gdouble *__restrict__ x = (gdouble *)cd.mid;
+    gdouble *__restrict__ y = x + n;
+    gdouble *__restrict__ z = y + n;
+    double xi[kDirT], yi[kDirT], zi[kDirT], acc[kDirT][NC];
 #pragma unroll
     for (int t = 0; t < kDirT; ++t) {
-        ti[t] = blk_first[blockIdx.x] + t * kDirTB + threadIdx.x;
-        const int ii = ti[t] < n ? ti[t] : 0;
-        xi[t] = s[ii];
-        yi[t] = s[n + ii];
-        zi[t] = s[2 * n + ii];
-        ax[t] = ay[t] = az[t] = av[t] = 0.0;
-    }
-    for (int base = 0; base < n; base += kDirTB) {
-        const int j = base + threadIdx.x;
-        __syncthreads();
-        if (j < n) {
-            sx[threadIdx.x] = s[j];
-            sy[threadIdx.x] = s[n + j];
-            sz[threadIdx.x] = s[2 * n + j];
-        }
-        __syncthreads();
-        const int cnt = min(kDirTB, n - base);
-        for (int k = 0; k < cnt; ++k) {
-            const double x = sx[k], y = sy[k], z = sz[k];
+        const int i = blk.first + 64 * t + lane;
+        const int ii = i < n ? i : 0;
+        xi[t] = x[ii];
+        yi[t] = y[ii];
+        zi[t] = z[ii];
 #pragma unroll
-            for (int t = 0; t < kDirT; ++t) {
-                const double dx = xi[t] - x, dy = yi[t] - y, dz = zi[t] - z;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const double ri = (r2 > 0.0 && base + k != ti[t]) ? rsqrt(r2) : 0.0;
-                const double w = ri * ri * ri;
-                ax[t] += dx * w;
-                ay[t] += dy * w;
-                az[t] += dz * w;
-                if constexpr (POT) av[t] += ri;
+        for (int k = 0; k < NC; ++k) acc[t][k] = 0.0;
+    }
+    // the correction's constants, held in registers (a VGPR and an SGPR) so
+    // that the compiler neither rematerialises them per pair nor needs two
+    // scalar operands in one instruction
+    double c15 = 1.5, c1875 = 1.875, c05 = 0.5, c0375 = 0.375;
+    __asm__("" : "+v"(c15));
+    __asm__("" : "+s"(c1875));
+    if constexpr (POT) {
+        __asm__("" : "+v"(c05));
+        __asm__("" : "+s"(c0375));
+    }
+    auto add_source = [&](double xj, double yj, double zj) {
+#pragma unroll
+        for (int t = 0; t < kDirT; ++t) {
+            const double dx = xi[t] - xj, dy = yi[t] - yj, dz = zi[t] - zj;
+            const double r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, kDirR2Offset)));
+            const double y0 = __builtin_amdgcn_rsq(r2);
+            const double y2 = y0 * y0;
+            const double y3 = y2 * y0;
+            const double e = fma(-r2, y2, 1.0);
+            const double w = fma(y3, e * fma(e, c1875, c15), y3);
+            acc[t][0] = fma(dx, w, acc[t][0]);
+            acc[t][1] = fma(dy, w, acc[t][1]);
+            acc[t][2] = fma(dz, w, acc[t][2]);
+            if constexpr (POT) {
+                // r^-1 = y0 (1 + e/2 + 3/8 e^2 + O(e^3))
+                const double ri = fma(y0 * e, fma(e, c0375, c05), y0);
+                acc[t][NC - 1] += r2 > kDirR2Offset ? ri : 0.0;
+            }
+        }
+    };
+    int j = j0;
+    for (; j + kDirUnroll <= j1; j += kDirUnroll) {
+#pragma unroll
+        for (int u = 0; u < kDirUnroll; ++u) add_source(x[j + u], y[j + u], z[j + u]);
+    }
+    for (; j < j1; ++j) add_source(x[j], y[j], z[j]);
+    if (wave > 0) {
+#pragma unroll
+        for (int t = 0; t < kDirT; ++t)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) red[wave - 1][k][64 * t + lane] = acc[t][k];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double *__restrict__ out = part + cd.dpart + (size_t)blk.chunk * n;
+#pragma unroll
+        for (int t = 0; t < kDirT; ++t) {
+            const int i = blk.first + 64 * t + lane;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                double a = acc[t][k];
+                for (int w = 0; w < kDirWaves - 1; ++w) a += red[w][k][64 * t + lane];
+                if (i < n) out[(size_t)k * chunks * n + i] = a;
             }
         }
     }
+}
+
+// Second level: ion g adds its crystal's chunk partials in chunk order.
+template <bool POT>
+__global__ void k_direct_finish(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
+                                const double *__restrict__ part, double *__restrict__ E, double *__restrict__ PHI)
+{
+    constexpr int NC = POT ? 4 : 3;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ntot) return;
+    const CrystalDev &cd = cs[ion_crystal[g]];
+    const int n = cd.n, chunks = direct_chunks(n);
+    const double *__restrict__ p = part + cd.dpart + (g - cd.ion_off);
 #pragma unroll
-    for (int t = 0; t < kDirT; ++t)
-        if (ti[t] < n) {
-            const int g = cd.ion_off + ti[t];
-            E[g] = ax[t];
-            E[ntot + g] = ay[t];
-            E[2 * ntot + g] = az[t];
-            if constexpr (POT) PHI[g] = av[t];
-        }
+    for (int k = 0; k < NC; ++k) {
+        double a = p[(size_t)k * chunks * n];
+        for (int s = 1; s < chunks; ++s) a += p[((size_t)k * chunks + s) * n];
+        if (k < 3) E[(size_t)k * ntot + g] = a;
+        else PHI[g] = a;
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -532,35 +597,46 @@ void launch_cap_check_lists(TreeSummary *sum, const uint32_t *total, const Caps 
 
 void launch_run_reset(TreeSummary *sum, hipStream_t st) { k_run_reset<<<1, 1, 0, st>>>(sum); }
 
-int direct_targets_per_block() { return kDirTB * kDirT; }
-
-void launch_direct(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int ntot,
-                   double *E, double *phi, hipStream_t st)
+void launch_direct(const CrystalDev *cs, const DirBlock *tab, int nblk, const int32_t *ion_crystal, int ntot,
+                   double *part, double *E, double *phi, hipStream_t st)
 {
-    if (nblk <= 0) return;
-    if (phi) k_direct<true><<<nblk, kDirTB, 0, st>>>(cs, blk_crystal, blk_first, ntot, E, phi);
-    else k_direct<false><<<nblk, kDirTB, 0, st>>>(cs, blk_crystal, blk_first, ntot, E, nullptr);
+    if (nblk <= 0 || ntot <= 0) return;
+    if (phi) {
+        k_direct<true><<<nblk, 64 * kDirWaves, 0, st>>>(cs, tab, part);
+        k_direct_finish<true><<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, part, E, phi);
+    } else {
+        k_direct<false><<<nblk, 64 * kDirWaves, 0, st>>>(cs, tab, part);
+        k_direct_finish<false><<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, part, E, nullptr);
+    }
 }
 
-// Potential sums, first level: each block of the direct-sum block table
-// (kDirT x kDirTB ions of one crystal) adds its ions' potentials in a fixed
+// The ion sums below (potential and rotating-frame energies) go over the
+// sum block table: block k takes ions blk_first[k] + t kSumTB + thread
+// (t < kSumT) of crystal blk_crystal[k].
+constexpr int kSumTB = 256;
+constexpr int kSumT = 2;
+
+int sum_ions_per_block() { return kSumTB * kSumT; }
+
+// Potential sums, first level: each block of the sum block table
+// (kSumT x kSumTB ions of one crystal) adds its ions' potentials in a fixed
 // tree into part[block]; blocks depend only on the crystal's own size, so the
 // sums do not depend on the batch.
-__global__ __launch_bounds__(kDirTB) void k_phi_partial(const CrystalDev *__restrict__ cs,
+__global__ __launch_bounds__(kSumTB) void k_phi_partial(const CrystalDev *__restrict__ cs,
                                                         const int32_t *__restrict__ blk_crystal,
                                                         const int32_t *__restrict__ blk_first,
                                                         const double *__restrict__ phi, double *__restrict__ part)
 {
-    __shared__ double acc[kDirTB];
+    __shared__ double acc[kSumTB];
     const CrystalDev &cd = cs[blk_crystal[blockIdx.x]];
     double a = 0.0;
-    for (int t = 0; t < kDirT; ++t) {
-        const int i = blk_first[blockIdx.x] + t * kDirTB + threadIdx.x;
+    for (int t = 0; t < kSumT; ++t) {
+        const int i = blk_first[blockIdx.x] + t * kSumTB + threadIdx.x;
         if (i < cd.n) a += phi[cd.ion_off + i];
     }
     acc[threadIdx.x] = a;
     __syncthreads();
-    for (int h = kDirTB / 2; h > 0; h >>= 1) {
+    for (int h = kSumTB / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) acc[threadIdx.x] += acc[threadIdx.x + h];
         __syncthreads();
     }
@@ -608,7 +684,7 @@ void launch_phi_sum(const CrystalDev *cs, const int32_t *blk_crystal, const int3
                     const double *phi, double *part, double *out, hipStream_t st)
 {
     if (nc <= 0) return;
-    if (nblk > 0) k_phi_partial<<<nblk, kDirTB, 0, st>>>(cs, blk_crystal, blk_first, phi, part);
+    if (nblk > 0) k_phi_partial<<<nblk, kSumTB, 0, st>>>(cs, blk_crystal, blk_first, phi, part);
     k_blocks_finish<1><<<nc, 64, 0, st>>>(blk_crystal, nblk, part, out);
 }
 
@@ -636,19 +712,19 @@ __device__ inline void to_rotating(const CrystalDev &cd, int i, const double ts[
     vr[2] = s[5 * n + i];
 }
 
-// Rotating-frame sums, first level: each block of the direct-sum block table
-// (kDirT x kDirTB ions of one crystal) adds the axial and planar kinetic
+// Rotating-frame sums, first level: each block of the sum block table
+// (kSumT x kSumTB ions of one crystal) adds the axial and planar kinetic
 // energies of the rotating-frame velocities and the external terms of eq.
 // (pe_rot),
 //   m wz^2 z_r^2 / 2 - m (wr^2 - wc wr + wz^2 / 2)(x_r^2 + y_r^2) / 2 + q k_z delta (x_r^2 - y_r^2) / 4
 // (m wz^2 = q k_z), in a fixed tree, into part[block][3].  Blocks depend only
 // on the crystal's own size, so the sums do not depend on the batch.
-__global__ __launch_bounds__(kDirTB) void k_rot_partial(const CrystalDev *__restrict__ cs,
+__global__ __launch_bounds__(kSumTB) void k_rot_partial(const CrystalDev *__restrict__ cs,
                                                         const int32_t *__restrict__ blk_crystal,
                                                         const int32_t *__restrict__ blk_first,
                                                         double *__restrict__ part)
 {
-    __shared__ double acc[3][kDirTB];
+    __shared__ double acc[3][kSumTB];
     __shared__ double ts[2];
     const CrystalDev &cd = cs[blk_crystal[blockIdx.x]];
     if (threadIdx.x == 0) frame_turn(cd, ts);
@@ -656,8 +732,8 @@ __global__ __launch_bounds__(kDirTB) void k_rot_partial(const CrystalDev *__rest
     const double wr = cd.omega_r, wz2 = cd.qkz / cd.mass;
     const double radial = 0.5 * cd.mass * (wr * wr - cd.wc * wr + 0.5 * wz2);
     double ka = 0.0, kp = 0.0, pe = 0.0;
-    for (int t = 0; t < kDirT; ++t) {
-        const int i = blk_first[blockIdx.x] + t * kDirTB + threadIdx.x;
+    for (int t = 0; t < kSumT; ++t) {
+        const int i = blk_first[blockIdx.x] + t * kSumTB + threadIdx.x;
         if (i >= cd.n) continue;
         double xr[3], vr[3];
         to_rotating(cd, i, ts, xr, vr);
@@ -670,7 +746,7 @@ __global__ __launch_bounds__(kDirTB) void k_rot_partial(const CrystalDev *__rest
     acc[1][threadIdx.x] = kp;
     acc[2][threadIdx.x] = pe;
     __syncthreads();
-    for (int h = kDirTB / 2; h > 0; h >>= 1) {
+    for (int h = kSumTB / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h)
             for (int k = 0; k < 3; ++k) acc[k][threadIdx.x] += acc[k][threadIdx.x + h];
         __syncthreads();
@@ -698,7 +774,7 @@ void launch_rot_sums(const CrystalDev *cs, const int32_t *blk_crystal, const int
                      double *part, double *out, hipStream_t st)
 {
     if (nc <= 0) return;
-    if (nblk > 0) k_rot_partial<<<nblk, kDirTB, 0, st>>>(cs, blk_crystal, blk_first, part);
+    if (nblk > 0) k_rot_partial<<<nblk, kSumTB, 0, st>>>(cs, blk_crystal, blk_first, part);
     k_blocks_finish<3><<<nc, 64, 0, st>>>(blk_crystal, nblk, part, out);
 }
 

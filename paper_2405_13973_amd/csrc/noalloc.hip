@@ -44,43 +44,66 @@ pt_status noalloc_scratch(int device, void **out)
     return PT_OK;
 }
 
+// Bytes of the regions for n ions, 256-aligned each.
+constexpr size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+constexpr size_t noalloc_bytes(int n)
+{
+    const size_t nblk = (size_t)direct_chunks(n) * ((n + kDirTile - 1) / kDirTile);
+    return up256(sizeof(CrystalDev)) + up256(sizeof(unsigned long long) * bbox_words(1)) + up256(4 * (size_t)n) +
+           up256(sizeof(DirBlock) * nblk) + up256(sizeof(double) * 3 * (size_t)n) +
+           up256(sizeof(double) * 3 * (size_t)direct_chunks(n) * n) + up256(sizeof(double) * 3 * (size_t)n);
+}
+
+// The largest layout up to kNoAllocMaxIons ions: the partials grow with
+// chunks x n, which peaks where a tile count is full, so those sizes (and the
+// limit itself) are the ones to check.
+constexpr bool noalloc_fits()
+{
+    for (int tiles = 1; (long long)(tiles - 1) * kDirTile < kNoAllocMaxIons; ++tiles) {
+        const int n = tiles * kDirTile < kNoAllocMaxIons ? tiles * kDirTile : kNoAllocMaxIons;
+        if (noalloc_bytes(n) > kNoAllocScratchBytes) return false;
+    }
+    return true;
+}
+static_assert(noalloc_fits(), "the no-allocation scratch must hold the layout of every size up to its limit");
+
 NoAllocLayout noalloc_layout(int n)
 {
-    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-    const int nblk = ceil_div(n, direct_targets_per_block());
+    const int nblk = direct_chunks(n) * ceil_div(n, kDirTile);
     NoAllocLayout l{};
     size_t o = 0;
     l.desc = o;
-    o += up(sizeof(CrystalDev));
+    o += up256(sizeof(CrystalDev));
     l.bbox = o;
-    o += up(sizeof(unsigned long long) * bbox_words(1));
+    o += up256(sizeof(unsigned long long) * bbox_words(1));
     l.ion_crystal = o;
-    o += up(sizeof(int32_t) * (size_t)n);
-    l.blk_crystal = o;
-    o += up(sizeof(int32_t) * (size_t)nblk);
-    l.blk_first = o;
-    o += up(sizeof(int32_t) * (size_t)nblk);
+    o += up256(sizeof(int32_t) * (size_t)n);
+    l.tab = o;
+    o += up256(sizeof(DirBlock) * (size_t)nblk);
     l.mid = o;  // positions only: x[n] y[n] z[n]
-    o += up(sizeof(double) * 3 * (size_t)n);
+    o += up256(sizeof(double) * 3 * (size_t)n);
+    l.part = o;  // the direct sum's chunk partials, 3 x chunks x n
+    o += up256(sizeof(double) * 3 * (size_t)direct_chunks(n) * n);
     l.E = o;
-    o += up(sizeof(double) * 3 * (size_t)n);
+    o += up256(sizeof(double) * 3 * (size_t)n);
     l.total = o;
     l.nblk = nblk;
     return l;
 }
 
 // One crystal's descriptor, its ion -> crystal map (all zero) and the
-// direct-sum block table (block k: targets from k * tpb), written by kernels
-// rather than copied from the host.
+// direct-sum block table (block k: target tile k mod tiles, source chunk
+// k / tiles), written by kernels rather than copied from the host.
 __global__ void k_noalloc_setup(CrystalDev d, CrystalDev *__restrict__ desc, int32_t *__restrict__ ion_crystal, int n,
-                                int32_t *__restrict__ blk_crystal, int32_t *__restrict__ blk_first, int nblk, int tpb)
+                                DirBlock *__restrict__ tab, int nblk)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g == 0) *desc = d;
     if (g < n) ion_crystal[g] = 0;
     if (g < nblk) {
-        blk_crystal[g] = 0;
-        blk_first[g] = g * tpb;
+        const int tiles = (n + kDirTile - 1) / kDirTile;
+        tab[g] = DirBlock{0, (g % tiles) * kDirTile, g / tiles, 0};
     }
 }
 
@@ -94,12 +117,11 @@ __global__ void k_scale_field(const double *__restrict__ E, int n, double s, dou
     F[e] = s * E[(size_t)d * n + i];
 }
 
-void launch_noalloc_setup(const CrystalDev &d, CrystalDev *desc, int32_t *ion_crystal, int n, int32_t *blk_crystal,
-                          int32_t *blk_first, int nblk, hipStream_t st)
+void launch_noalloc_setup(const CrystalDev &d, CrystalDev *desc, int32_t *ion_crystal, int n, DirBlock *tab, int nblk,
+                          hipStream_t st)
 {
     const int m = std::max(1, std::max(n, nblk));
-    k_noalloc_setup<<<ceil_div(m, 256), 256, 0, st>>>(d, desc, ion_crystal, n, blk_crystal, blk_first, nblk,
-                                                      direct_targets_per_block());
+    k_noalloc_setup<<<ceil_div(m, 256), 256, 0, st>>>(d, desc, ion_crystal, n, tab, nblk);
 }
 
 void launch_scale_field(const double *E, int n, double s, double *F, hipStream_t st)

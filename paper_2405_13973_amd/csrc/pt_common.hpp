@@ -83,6 +83,7 @@ struct CrystalDev {
     BeamDev beam[kMaxBeams];
     uint64_t seed;
     uint64_t step0;         // step index of the first step of the current call
+    int64_t dpart;          // first double of this crystal's direct-sum partials (see direct_chunks)
 };
 
 // Root cube of a crystal: lower corner o, side W, quantisation scale 2^16/W.
@@ -184,6 +185,46 @@ __host__ __device__ inline double u53(uint32_t a, uint32_t b)
 }
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Work split of the direct sum over a crystal of n ions.  A block takes
+// kDirTile targets (kDirT per lane of one wave) and one of direct_chunks(n)
+// contiguous chunks of the sources; each of its kDirWaves waves takes its own
+// piece of direct_piece(n) sources of that chunk (the last pieces shorter or
+// empty).  The block writes the chunk's partial sums, NC x chunks x n
+// doubles per crystal from CrystalDev::dpart (component k, chunk s, ion i at
+// (k chunks + s) n + i), and each ion then adds its chunks in order.  Both
+// numbers depend on n alone, so a crystal's sums are formed in the same
+// order whatever batch it is in.  Chunks are chosen to give about
+// kDirBlocksWanted blocks for one crystal, with pieces of at least
+// kDirMinPiece sources.
+constexpr int kDirT = 2;
+constexpr int kDirTile = 64 * kDirT;
+constexpr int kDirWaves = 8;
+constexpr int kDirBlocksWanted = 4096;
+constexpr int kDirMaxChunks = 16;
+constexpr int kDirMinPiece = 64;
+
+__host__ __device__ constexpr int direct_chunks(int n)
+{
+    const int tiles = (n + kDirTile - 1) / kDirTile;
+    int s = tiles > 0 ? (kDirBlocksWanted + tiles - 1) / tiles : 1;
+    const int by_piece = n / (kDirWaves * kDirMinPiece);
+    if (s > by_piece) s = by_piece;
+    if (s > kDirMaxChunks) s = kDirMaxChunks;
+    return s < 1 ? 1 : s;
+}
+
+__host__ __device__ constexpr int direct_piece(int n)
+{
+    const int pieces = direct_chunks(n) * kDirWaves;
+    return ((n + pieces - 1) / pieces + 7) / 8 * 8;
+}
+
+// One block of the direct sum: crystal c, its targets first..first+kDirTile-1,
+// source chunk `chunk`.
+struct DirBlock {
+    int32_t c, first, chunk, pad;
+};
 
 }  // namespace pt
 

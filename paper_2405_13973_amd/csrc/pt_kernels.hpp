@@ -21,8 +21,8 @@ void launch_ion_crystal(const CrystalDev *cs, int nc, int ntot, int32_t *ion_cry
 // atomics of different workgroups spread over separate cache lines; the
 // root-cube kernel reduces the copies.  The buffer holds bbox_words(nc) words.
 constexpr int kBBoxCopies = 16;
-inline int bbox_stride(int nc) { return (6 * nc + 47) / 48 * 48; }
-inline size_t bbox_words(int nc) { return (size_t)kBBoxCopies * bbox_stride(nc); }
+constexpr int bbox_stride(int nc) { return (6 * nc + 47) / 48 * 48; }
+constexpr size_t bbox_words(int nc) { return (size_t)kBBoxCopies * bbox_stride(nc); }
 void launch_bbox_reset(unsigned long long *bbox, int nc, hipStream_t st);
 void launch_zero_u64(uint64_t *p, int n, hipStream_t st);
 // Several small regions of 64-bit words (n[r] = 0: unused slot) zeroed in one launch.
@@ -44,18 +44,22 @@ void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCub
 // call_k: the step's index within its pt_step_batch call (what fail_step records).
 void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
                        bool beams, TreeSummary *sum, int call_k, hipStream_t st);
-int direct_targets_per_block();
 // Direct field into E (3 x ntot); with phi non-null also the potential per
-// unit charge sum_{j != i} 1/r_ij into phi (ntot).
-void launch_direct(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int ntot,
-                   double *E, double *phi, hipStream_t st);
+// unit charge sum_{j != i} 1/r_ij into phi (ntot).  tab: the nblk blocks of
+// the batch (direct_chunks); part: the crystals' partials, 4 x chunks x n
+// doubles per crystal from its dpart (3 x when phi is null).
+void launch_direct(const CrystalDev *cs, const DirBlock *tab, int nblk, const int32_t *ion_crystal, int ntot,
+                   double *part, double *E, double *phi, hipStream_t st);
+// Ions per block of the sum block table (blk_crystal / blk_first) that the
+// two per-crystal sums below go over.
+int sum_ions_per_block();
 // Per crystal c of the batch: out[c] = sum of phi over its ions (fixed order),
-// over the direct-sum block table; part: nblk doubles of workspace.
+// over the sum block table; part: nblk doubles of workspace.
 void launch_phi_sum(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int nc,
                     const double *phi, double *part, double *out, hipStream_t st);
 // Per crystal c: out[3c..3c+2] = rotating-frame axial KE, planar KE and the
 // external terms of eq. (pe_rot), at the state's time (fixed order), over
-// the direct-sum block table; part: 3 x nblk doubles of workspace.
+// the sum block table; part: 3 x nblk doubles of workspace.
 void launch_rot_sums(const CrystalDev *cs, const int32_t *blk_crystal, const int32_t *blk_first, int nblk, int nc,
                      double *part, double *out, hipStream_t st);
 // Rotating-frame positions and velocities, SoA 6 x ntot in batch order.
@@ -194,18 +198,18 @@ int m2l_per_cu(int Kp, size_t lds_beside);
 // noalloc.hip: the fixed scratch of pt_compute_forces_noalloc (direct sum of
 // one crystal of at most kNoAllocMaxIons ions).
 constexpr int kNoAllocMaxIons = PT_NOALLOC_MAX_IONS;
-constexpr size_t kNoAllocScratchBytes = (size_t)7 << 20;
+constexpr size_t kNoAllocScratchBytes = (size_t)24 << 20;
 // Byte offsets of its regions for n ions.
 struct NoAllocLayout {
-    size_t desc, bbox, ion_crystal, blk_crystal, blk_first, mid, E, total;
+    size_t desc, bbox, ion_crystal, tab, mid, part, E, total;
     int nblk;
 };
 NoAllocLayout noalloc_layout(int n);
 // The device address of this device's scratch (looked up once per device,
 // with the device current).
 pt_status noalloc_scratch(int device, void **out);
-void launch_noalloc_setup(const CrystalDev &d, CrystalDev *desc, int32_t *ion_crystal, int n, int32_t *blk_crystal,
-                          int32_t *blk_first, int nblk, hipStream_t st);
+void launch_noalloc_setup(const CrystalDev &d, CrystalDev *desc, int32_t *ion_crystal, int n, DirBlock *tab, int nblk,
+                          hipStream_t st);
 void launch_scale_field(const double *E, int n, double s, double *F, hipStream_t st);
 
 }  // namespace pt

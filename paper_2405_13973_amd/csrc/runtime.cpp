@@ -327,9 +327,12 @@ struct Batch {
     int ntot = 0;
     CrystalDev *d_desc = nullptr;
     int32_t *ion_crystal = nullptr;
-    int32_t *blk_crystal = nullptr, *blk_first = nullptr;
-    int nblk_direct = 0;
-    bool beams = false;  // some crystal uses the beam-mode laser
+    int32_t *blk_crystal = nullptr, *blk_first = nullptr;  // sum block table (per-crystal ion sums)
+    int nblk_sum = 0;
+    DirBlock *dir_tab = nullptr;  // direct-sum block table (direct method only)
+    int nblk_dir = 0;
+    int64_t dir_part = 0;  // doubles of the direct sum's chunk partials
+    bool beams = false;    // some crystal uses the beam-mode laser
 };
 
 static void fill_desc(const pt_crystal *c, int off, double *mid, CrystalDev &d)
@@ -426,6 +429,19 @@ static pt_status form_batch(pt_ctx *ctx, const std::vector<pt_crystal *> &cs, Ba
         PT_HIP(hipStreamSynchronize(ctx->stream));  // staging buffer may still be read by a copy
     }
     for (int i = 0; i < nc; ++i) fill_desc(cs[i], b.off[i], mid, ctx->h_desc[i]);
+    // direct method: chunk partials of each crystal (4 x chunks x n doubles)
+    // and the block table over (crystal, source chunk, target tile)
+    const bool direct = nc > 0 && cs[0]->force.method == 0;
+    std::vector<DirBlock> dtab;
+    b.dir_part = 0;
+    if (direct)
+        for (int i = 0; i < nc; ++i) {
+            const int n = (int)cs[i]->n, chunks = direct_chunks(n), tiles = ceil_div(n, kDirTile);
+            ctx->h_desc[i].dpart = b.dir_part;
+            b.dir_part += 4 * (int64_t)chunks * n;
+            for (int s = 0; s < chunks; ++s)
+                for (int t = 0; t < tiles; ++t) dtab.push_back(DirBlock{i, t * kDirTile, s, 0});
+        }
     b.beams = false;
     for (int i = 0; i < nc; ++i) b.beams = b.beams || cs[i]->laser.mode == 2;
     PT_HIP(hipMemcpyAsync(b.d_desc, ctx->h_desc, sizeof(CrystalDev) * nc, hipMemcpyHostToDevice, ctx->stream));
@@ -434,22 +450,27 @@ static pt_status form_batch(pt_ctx *ctx, const std::vector<pt_crystal *> &cs, Ba
     unsigned long long *bbox;
     PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * bbox_words(nc), &bbox));
     launch_bbox_reset(bbox, nc, ctx->stream);
-    // direct-method block table: each block serves targets of one crystal
-    const int tpb = direct_targets_per_block();
+    // sum block table: each block serves ions of one crystal
+    const int tpb = sum_ions_per_block();
     std::vector<int32_t> bc, bf;
     for (int i = 0; i < nc; ++i)
         for (int64_t f = 0; f < cs[i]->n; f += tpb) {
             bc.push_back(i);
             bf.push_back((int32_t)f);
         }
-    b.nblk_direct = (int)bc.size();
+    b.nblk_sum = (int)bc.size();
     PT_TRY(ws_get(ctx, "blk_crystal", sizeof(int32_t) * std::max<size_t>(1, bc.size()), &b.blk_crystal));
     PT_TRY(ws_get(ctx, "blk_first", sizeof(int32_t) * std::max<size_t>(1, bf.size()), &b.blk_first));
+    b.nblk_dir = (int)dtab.size();
+    if (direct) PT_TRY(ws_get(ctx, "dir_tab", sizeof(DirBlock) * std::max<size_t>(1, dtab.size()), &b.dir_tab));
     if (!bc.empty()) {
         PT_HIP(hipMemcpyAsync(b.blk_crystal, bc.data(), bc.size() * 4, hipMemcpyHostToDevice, ctx->stream));
         PT_HIP(hipMemcpyAsync(b.blk_first, bf.data(), bf.size() * 4, hipMemcpyHostToDevice, ctx->stream));
-        PT_HIP(hipStreamSynchronize(ctx->stream));  // pageable sources
     }
+    if (!dtab.empty())
+        PT_HIP(hipMemcpyAsync(b.dir_tab, dtab.data(), dtab.size() * sizeof(DirBlock), hipMemcpyHostToDevice,
+                              ctx->stream));
+    if (!bc.empty() || !dtab.empty()) PT_HIP(hipStreamSynchronize(ctx->stream));  // pageable sources
     return PT_OK;
 }
 
@@ -558,7 +579,10 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(timing_begin(ctx));
     mark(ctx, 0);
     if (fp.method == 0) {
-        launch_direct(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, ntot, E, phi, st);
+        PT_REQUIRE(b.nblk_dir > 0 || ntot == 0, "batch formed without the direct-sum block table");
+        double *part;
+        PT_TRY(ws_get(ctx, "dir_part", sizeof(double) * (size_t)std::max<int64_t>(1, b.dir_part), &part));
+        launch_direct(b.d_desc, b.dir_tab, b.nblk_dir, b.ion_crystal, ntot, part, E, phi, st);
         for (int i = 1; i <= kPhases - 1; ++i) mark(ctx, i);
         timing_end(ctx);
         return PT_OK;
@@ -1197,8 +1221,8 @@ static pt_status evaluate_batch(pt_crystal *const *cs, int n_crystals, double *c
     }
     if (U_out) {
         double *ppart;
-        PT_TRY(ws_get(ctx, "phi_part", sizeof(double) * (size_t)std::max(1, b.nblk_direct), &ppart));
-        launch_phi_sum(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, n_crystals, phi, ppart, usum, ctx->stream);
+        PT_TRY(ws_get(ctx, "phi_part", sizeof(double) * (size_t)std::max(1, b.nblk_sum), &ppart));
+        launch_phi_sum(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_sum, n_crystals, phi, ppart, usum, ctx->stream);
         hu.resize((size_t)n_crystals);
         PT_HIP(hipMemcpyAsync(hu.data(), usum, sizeof(double) * n_crystals, hipMemcpyDeviceToHost, ctx->stream));
     }
@@ -1206,8 +1230,8 @@ static pt_status evaluate_batch(pt_crystal *const *cs, int n_crystals, double *c
     if (diag) {
         double *rsum, *rpart;
         PT_TRY(ws_get(ctx, "rot_sum", sizeof(double) * 3 * (size_t)n_crystals, &rsum));
-        PT_TRY(ws_get(ctx, "rot_part", sizeof(double) * 3 * (size_t)std::max(1, b.nblk_direct), &rpart));
-        launch_rot_sums(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_direct, n_crystals, rpart, rsum, ctx->stream);
+        PT_TRY(ws_get(ctx, "rot_part", sizeof(double) * 3 * (size_t)std::max(1, b.nblk_sum), &rpart));
+        launch_rot_sums(b.d_desc, b.blk_crystal, b.blk_first, b.nblk_sum, n_crystals, rpart, rsum, ctx->stream);
         hr.resize(3 * (size_t)n_crystals);
         PT_HIP(hipMemcpyAsync(hr.data(), rsum, sizeof(double) * 3 * n_crystals, hipMemcpyDeviceToHost, ctx->stream));
     }
@@ -1328,14 +1352,15 @@ pt_status pt_compute_forces_noalloc(pt_crystal *c, double *F_dev)
     fill_desc(c, 0, (double *)(base + l.mid), d);
     CrystalDev *desc = (CrystalDev *)(base + l.desc);
     int32_t *ion_crystal = (int32_t *)(base + l.ion_crystal);
-    int32_t *blk_crystal = (int32_t *)(base + l.blk_crystal), *blk_first = (int32_t *)(base + l.blk_first);
+    DirBlock *tab = (DirBlock *)(base + l.tab);
     unsigned long long *bbox = (unsigned long long *)(base + l.bbox);
-    double *E = (double *)(base + l.E);
+    double *part = (double *)(base + l.part), *E = (double *)(base + l.E);
     hipStream_t st = ctx->stream;
-    launch_noalloc_setup(d, desc, ion_crystal, n, blk_crystal, blk_first, l.nblk, st);
+    d.dpart = 0;
+    launch_noalloc_setup(d, desc, ion_crystal, n, tab, l.nblk, st);
     launch_bbox_reset(bbox, 1, st);
     launch_drift_bbox(desc, ion_crystal, n, 1, 0, bbox, nullptr, st);
-    launch_direct(desc, blk_crystal, blk_first, l.nblk, n, E, nullptr, st);
+    launch_direct(desc, tab, l.nblk, ion_crystal, n, part, E, nullptr, st);
     const double ke = 1.0 / (4.0 * kPi * kEps0), q = c->q;
     launch_scale_field(E, n, ke * q * q, F_dev, st);
     PT_HIP(hipGetLastError());

@@ -56,7 +56,9 @@ def ball(n, seed, R=1e-4):
 
 
 # ---------------------------------------------------------------- direct
-@pytest.mark.parametrize("n", [1, 2, 3, 511, 1000, 1025])
+# sizes across the direct sum's work split: one source chunk (n < 1024), two
+# (1025), eight with a ragged last tile and piece (4100), sixteen (9001)
+@pytest.mark.parametrize("n", [1, 2, 3, 511, 1000, 1025, 4100, 9001])
 def test_direct_forces_match_oracle(ctx, n):
     say(f"direct forces n={n}")
     cr = ball(n, 100 + n)
@@ -68,6 +70,24 @@ def test_direct_forces_match_oracle(ctx, n):
         assert np.all(F == 0)
     else:
         assert rel_max(F, ref) <= 1e-12
+
+
+def test_direct_batch_equals_alone(ctx):
+    """Crystals with different chunk counts in one batch: each crystal's sums
+    keep their order, so the batch result equals the single-crystal one bit for bit."""
+    say("direct batch invariance")
+    crs = [ball(n, 900 + n) for n in (1025, 3, 9001, 600)]
+    alone = []
+    for cr in crs:
+        c = make(ctx, cr)
+        alone.append(c.compute_forces())
+        c.destroy()
+    cs = [make(ctx, cr) for cr in crs]
+    together = native.compute_forces_batch(cs)
+    for c in cs:
+        c.destroy()
+    for a, b in zip(alone, together):
+        assert np.array_equal(a, b)
 
 
 def test_direct_coincident_pair_contributes_nothing(ctx):

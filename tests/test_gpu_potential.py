@@ -56,7 +56,7 @@ def ball(n, seed, R=1e-4):
     return inputs.uniform_ball(n, R, inputs.rng(seed))
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 511, 1025])
+@pytest.mark.parametrize("n", [1, 2, 3, 511, 1025, 4100])
 def test_direct_potential_matches_oracle(ctx, n):
     say(f"direct potential n={n}")
     pos = ball(n, 400 + n)
