@@ -7,7 +7,7 @@
 // T is the expansion / near-field type: double for the FP64 form, float for
 // the mixed form.  Box centres, ion-to-centre offsets and the integrator stay
 // FP64 in both; in the mixed form the offsets are rounded to FP32 only after
-// the FP64 subtraction, and near-field sums are compensated (Kahan).
+// the FP64 subtraction, and FP32 near-field sums are compensated (Kahan).
 #include <algorithm>
 
 #include "fmm_math.hpp"
@@ -410,27 +410,26 @@ __global__ void k_xlate_reduce(const TreeSummary *__restrict__ sum, int level, i
 // pairs keep full relative precision (offsets rounded to FP32 first would
 // carry an absolute error of order 1e-7 of the box size into every
 // separation, and the rare very close pairs of random crystals dominate an
-// RMS force error).  An item with nt targets gives each target
-// floor(256 / nt) threads (phases), which take source blocks round robin;
-// within a block sources are summed plainly and each block is added to the
-// phase's total with Kahan compensation.  The phases of a target are then
-// added in phase order.  Four waves share one staged tile, so that a compute
-// unit holds enough waves to hide the latency of the pair arithmetic.
+// RMS force error).  r^-3 is the FP32 hardware reciprocal square root (1
+// ulp) cubed in the mixed form, and the hardware FP64 estimate refined as in
+// the direct sum in the FP64 form.  An item with nt targets gives each
+// target floor(256 / nt) threads (phases), which take source blocks round
+// robin; within a block sources are summed plainly and each block is added
+// to the phase's total, with Kahan compensation in FP32 (plainly in FP64).
+// The phases of a target are then added in phase order.  Four waves share
+// one staged tile, so that a compute unit holds enough waves to hide the
+// latency of the pair arithmetic.
 // Partial fields go to part[item][target][3]; with POT the potential sum
 // sum 1/r over the pairs with r > 0 comes along, in part[item][target][4].
 constexpr int kP2PStage = 512;
 constexpr int kP2PThreads = 256;  // four waves share one staged source tile
 
-// 1/sqrt(x) in the arithmetic type: the hardware reciprocal square root for
-// FP32 (1 ulp), the library routine for FP64.
-__device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ inline double rsqrt_t(double x) { return rsqrt(x); }
 // Added to every FP32 near-field r^2 (m^2): 1/r^3 <= 1e36 stays finite; at
 // 0.1 micrometre the relative change is 1e-10, far below FP32 rounding.
 constexpr double kSoft2 = 1e-24;
-// Largest FP64 near-field 1/r (1/m): separations below 1e-12 m are taken as
-// 1e-12 m; only r = 0 reaches it in practice.
-constexpr double kRinvMax = 1e12;
+// Added to every FP64 near-field r^2 (m^2): below the rounding of any r^2
+// above 2^-626, and the weight at r = 0 (about 2^1020) stays finite.
+constexpr double kSoft2F64 = 0x1p-680;
 
 template <typename T, bool POT>
 __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSummary *__restrict__ sum,
@@ -552,42 +551,58 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
                     const T dx = (T)(xi - v.x), dy = (T)(yi - v.y), dz = (T)(zi - szz[q]);
                     // r = 0 (the target itself or a coincident ion) must give a
                     // finite 1/r^3, whose contribution is then exactly zero since
-                    // dx = dy = dz = 0: FP32 adds kSoft2 to r^2 (folded into the
-                    // first FMA), FP64 caps 1/r at kRinvMax.  The potential has
-                    // no such factor: there, pairs with r = 0 are left out.
-                    T rinv, s2 = 0;
-                    if constexpr (POT) {
-                        s2 = dx * dx + dy * dy + dz * dz;
-                        if constexpr (sizeof(T) == 4) rinv = rsqrt_t(s2 + T(kSoft2));
-                        else rinv = min(rsqrt_t(s2), T(kRinvMax));
-                    } else if constexpr (sizeof(T) == 4) {
-                        // nested so that r^2 is three fused multiply-adds
-                        rinv = rsqrt_t(fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, float(kSoft2)))));
+                    // dx = dy = dz = 0: r^2 carries a tiny offset (folded into
+                    // the first FMA).  The potential has no such factor: there,
+                    // pairs with r = 0 are left out.
+                    T rinv = T(0), ww;
+                    bool apart = true;
+                    if constexpr (sizeof(T) == 4) {
+                        const T r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, float(kSoft2))));
+                        rinv = __builtin_amdgcn_rsqf(r2);  // 1 ulp
+                        ww = rinv * rinv * rinv;
+                        if constexpr (POT) apart = r2 > float(kSoft2);
                     } else {
-                        rinv = min(rsqrt_t(dx * dx + dy * dy + dz * dz), T(kRinvMax));
+                        // r^-3 = y0^3 (1 + 3/2 e + 15/8 e^2), r^-1 = y0 (1 + e/2 + 3/8 e^2),
+                        // e = 1 - r2 y0^2, from the hardware estimate y0 (relative
+                        // error about 5e-8), as in the direct sum
+                        const T r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, kSoft2F64)));
+                        const T y0 = __builtin_amdgcn_rsq(r2);
+                        const T y2 = y0 * y0, y3 = y2 * y0;
+                        const T e = fma(-r2, y2, 1.0);
+                        ww = fma(y3, e * fma(e, 1.875, 1.5), y3);
+                        if constexpr (POT) {
+                            rinv = fma(y0 * e, fma(e, 0.375, 0.5), y0);
+                            apart = r2 > kSoft2F64;
+                        }
                     }
-                    const T ww = rinv * rinv * rinv;
                     px += dx * ww;
                     py += dy * ww;
                     pz += dz * ww;
-                    if constexpr (POT) pv += s2 > T(0) ? rinv : T(0);
+                    if constexpr (POT) pv += apart ? rinv : T(0);
                 }
-                T y_ = px - cx, t_ = ax + y_;
-                cx = (t_ - ax) - y_;
-                ax = t_;
-                y_ = py - cy;
-                t_ = ay + y_;
-                cy = (t_ - ay) - y_;
-                ay = t_;
-                y_ = pz - cz;
-                t_ = az + y_;
-                cz = (t_ - az) - y_;
-                az = t_;
-                if constexpr (POT) {
-                    y_ = pv - cv;
-                    t_ = av + y_;
-                    cv = (t_ - av) - y_;
-                    av = t_;
+                if constexpr (sizeof(T) == 4) {
+                    T y_ = px - cx, t_ = ax + y_;
+                    cx = (t_ - ax) - y_;
+                    ax = t_;
+                    y_ = py - cy;
+                    t_ = ay + y_;
+                    cy = (t_ - ay) - y_;
+                    ay = t_;
+                    y_ = pz - cz;
+                    t_ = az + y_;
+                    cz = (t_ - az) - y_;
+                    az = t_;
+                    if constexpr (POT) {
+                        y_ = pv - cv;
+                        t_ = av + y_;
+                        cv = (t_ - av) - y_;
+                        av = t_;
+                    }
+                } else {
+                    ax += px;
+                    ay += py;
+                    az += pz;
+                    if constexpr (POT) av += pv;
                 }
             }
             __syncthreads();  // all reads of the stage done before the next one
