@@ -658,7 +658,7 @@ def main():
     rooflines["direct"] = {
         "bound": "alu", "kernel": "direct", "kernel_ms": dir_ms,
         "achieved": P2P_FLOPS_PER_PAIR * dir_pairs / (dir_ms * 1e-3) / 1e12, "peak": PEAK["valu_fp64"],
-        "unit": "TFLOP/s", "traffic": None,
+        "unit": "TFLOP/s", "traffic": measured_traffic("direct", p, leaf, a.precision, cr.n),
         "algorithmic": f"{P2P_FLOPS_PER_PAIR} flops per ordered pair (i != j), {int(dir_pairs)} pairs per evaluation "
                        f"(FP64, the chunk sums and their reduction)"}
     rooflines["direct"]["frac"] = rooflines["direct"]["achieved"] / rooflines["direct"]["peak"]
