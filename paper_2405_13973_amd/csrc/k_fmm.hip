@@ -126,7 +126,9 @@ constexpr int kM2LRB = 12;             // row blocks (of 16) per workgroup: Kp <
 
 // One translation GEMM serves M2M and L2L:
 //   out[t] (op) sum over slots s of  A[op(s)] * X[src(t, s)]
-// targets t: either bucket lists (cnt non-null) or the box range [b0, b0 + n);
+// targets t: either bucket lists (cnt non-null; with lvl non-null each
+// bucket's list starts at the level's first box index) or the box range
+// [b0, b0 + n);
 // src(t, s) = srctab[t * src_stride + col(s)] (-1: no source); an operator
 // index above 255 carries reflection signs (mask = index >> 8).
 // Output modes: 0 partial sums per slot group, 1 overwrite (skipping targets
@@ -172,6 +174,9 @@ template <typename T, int NRB, bool PARTIAL, int ROLE, int KC>
 __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *__restrict__ At,
                                                          const T *__restrict__ X, T *__restrict__ out)
 {
+    // the upward and downward passes run beside the near field: a raised wave
+    // priority keeps their short per-level launches from waiting behind its waves
+    __builtin_amdgcn_s_setprio(1);
     using MF = Mfma<T>;
     constexpr int ROWS = NRB * 16;
     constexpr int NT = 64 * kM2LWaves;
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
         __syncthreads();  // previous tile finished with the shared arrays
         if (tid < kM2LCols) {
             const int t = tile * kM2LCols + tid;
-            tgt_s[tid] = t < n ? (a.cnt ? a.list[(size_t)o * a.list_stride + t] : b0 + t) : -1;
+            tgt_s[tid] = t < n ? (a.cnt ? a.list[(size_t)o * a.list_stride + (a.lvl ? b0 : 0) + t] : b0 + t) : -1;
         }
         if (tid < ns) op_s[tid] = a.slots[o * a.nslot + s0 + tid].y;
         __syncthreads();
@@ -388,6 +393,7 @@ template <typename T>
 __global__ void k_xlate_reduce(const TreeSummary *__restrict__ sum, int level, int Kp, int nbox, int ngroup, int mode,
                                const uint8_t *__restrict__ skip, const T *__restrict__ part, T *__restrict__ out)
 {
+    __builtin_amdgcn_s_setprio(1);  // beside the near field, as k_xlate
     if (sum->halt) return;
     const int b0 = sum->level_start[level], n = sum->level_start[level + 1] - b0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)n * Kp;
@@ -748,14 +754,36 @@ int m2l_groups(int)
 
 template <typename T>
 void launch_downward(const BoxTable &bt, const TreeSummary *sum, int p, const Caps &cap, const T *l2l_pad,
-                     const int2 *oct_slots, const int32_t *parent_oct, T *L, T *part, hipStream_t st)
+                     const int2 *oct_slots, const int32_t *parent_oct, const uint32_t *l2l_cnt,
+                     const int32_t *l2l_list, T *L, hipStream_t st)
 {
     const int Kp = kpad(p);
-    // L2L level by level (3 and deeper): each box adds its parent's expansion
-    // shifted by the operator of its own octant (slot = octant)
+    // L2L level by level (3 and deeper): the level's boxes in 8 octant
+    // buckets, so that every column of a tile shares its operator; each box
+    // has exactly one source (its parent), so the product is added to L
+    // directly.  A box's column is computed by the same instructions as with
+    // 8 octant slot groups (where the 7 other groups read the zero row and add
+    // exact zeros), so the result is the same.
     for (int l = 3; l < std::min(cap.nlev, kMaxLevel + 1); ++l) {
         if (cap.lvl[l] <= 0) continue;
-        launch_level_xlate<T>(bt, sum, Kp, cap.nbox, l, cap.lvl[l], 2, l2l_pad, oct_slots, parent_oct, L, part, st);
+        const int tiles = std::max(1, ceil_div(cap.lvl[l], kM2LCols));
+        XlateArgs a = xlate_base(Kp, cap.nbox);
+        a.cnt = (const int32_t *)l2l_cnt + 8 * l;
+        a.list = l2l_list;
+        a.list_stride = cap.nbox;
+        a.nbucket = 8;
+        a.lvl = sum->level_start;
+        a.level = l;
+        a.sum = sum;
+        a.ngroup = 1;
+        a.tile_stride = tiles;
+        a.slots = oct_slots;  // bucket o: slot {octant o, operator o}
+        a.nslot = 1;
+        a.srctab = parent_oct;
+        a.src_stride = 8;
+        a.mode = 2;
+        xlate_rows(a, (long)tiles * a.nbucket);
+        launch_xlate<T, 2>(a, tiles * a.nbucket * a.nrowgrp, l2l_pad, L, L, st);
     }
 }
 
@@ -799,7 +827,8 @@ void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, in
     template void launch_m2m<T>(const BoxTable &, const TreeSummary *, int, const Caps &, const T *, const int2 *,   \
                                 const int32_t *, T *, T *, hipStream_t);                                           \
     template void launch_downward<T>(const BoxTable &, const TreeSummary *, int, const Caps &, const T *,            \
-                                     const int2 *, const int32_t *, T *, T *, hipStream_t);                        \
+                                     const int2 *, const int32_t *, const uint32_t *, const int32_t *, T *,          \
+                                     hipStream_t);                                                                 \
     template void launch_near<T>(const BoxTable &, const TreeSummary *, const double *, int, const int2 *, int,      \
                                  const int4 *, const uint32_t *, int, T *, bool, int, int *, hipStream_t);         \
     template void launch_far<T>(const BoxTable &, const TreeSummary *, const double *, int, int, int, const T *,     \

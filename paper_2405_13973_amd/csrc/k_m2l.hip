@@ -111,6 +111,7 @@ __global__ __launch_bounds__(256) void k_m2l_emit(BoxTable bt, const TreeSummary
                                                   const uint32_t *__restrict__ pair_off,
                                                   const uint32_t *__restrict__ ob_off, int4 *__restrict__ bucket)
 {
+    __builtin_amdgcn_s_setprio(1);  // may run beside the near field, as the GEMM
     __shared__ int src_s[kSlots];
     __shared__ int op_s[kSlots];
     const int b = blockIdx.x, tid = threadIdx.x;
@@ -142,6 +143,7 @@ __global__ __launch_bounds__(64) void k_m2l_chunks(const TreeSummary *__restrict
                                                    const uint32_t *__restrict__ npairs, int32_t *__restrict__ op_beg,
                                                    int32_t *__restrict__ chunk_off)
 {
+    __builtin_amdgcn_s_setprio(1);  // may run beside the near field, as the GEMM
     const int o = threadIdx.x;
     if (sum->halt) return;
     const int nbox = sum->nbox;
@@ -318,6 +320,7 @@ template <typename T>
 __global__ void k_m2l_sum(const TreeSummary *__restrict__ sum, int Kp, const uint32_t *__restrict__ pair_off,
                           const uint32_t *__restrict__ npairs, const T *__restrict__ R, T *__restrict__ L)
 {
+    __builtin_amdgcn_s_setprio(1);  // runs beside the near field, as the GEMM
     using V = Vec16<T>;
     constexpr int VEC = V::N;
     if (sum->halt) return;

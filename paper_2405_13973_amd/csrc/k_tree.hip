@@ -534,9 +534,11 @@ __global__ void k_tree_links(BoxTable bt, const TreeSummary *__restrict__ sum)
 
 // Source maps of the M2M / L2L translation GEMMs, 8 slots per box indexed by
 // octant: child_oct[b][o] = child of b in octant o, parent_oct[b][o] = parent
-// of b in b's own octant slot (-1 elsewhere).
+// of b in b's own octant slot (-1 elsewhere); and the L2L buckets (boxes of
+// levels >= 3 by level and octant, l2l_cnt zeroed beforehand).
 __global__ void k_oct_tables(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ child_oct,
-                             int32_t *__restrict__ parent_oct)
+                             int32_t *__restrict__ parent_oct, uint32_t *__restrict__ l2l_cnt,
+                             int32_t *__restrict__ l2l_list, int list_stride)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (sum->halt || b >= sum->nbox) return;
@@ -544,10 +546,16 @@ __global__ void k_oct_tables(BoxTable bt, const TreeSummary *__restrict__ sum, i
     for (int o = 0; o < 8; ++o) ch[o] = pa[o] = -1;
     for (int c = bt.child[b], e = c + bt.nchild[b]; c < e; ++c)
         ch[((bt.ix[c] & 1) << 2) | ((bt.iy[c] & 1) << 1) | (bt.iz[c] & 1)] = c;
-    pa[((bt.ix[b] & 1) << 2) | ((bt.iy[b] & 1) << 1) | (bt.iz[b] & 1)] = bt.parent[b];
+    const int oct = ((bt.ix[b] & 1) << 2) | ((bt.iy[b] & 1) << 1) | (bt.iz[b] & 1);
+    pa[oct] = bt.parent[b];
     for (int o = 0; o < 8; ++o) {
         child_oct[(size_t)b * 8 + o] = ch[o];
         parent_oct[(size_t)b * 8 + o] = pa[o];
+    }
+    const int l = bt.level[b];
+    if (l >= 3) {
+        const uint32_t i = atomicAdd(&l2l_cnt[8 * l + oct], 1u);
+        l2l_list[(size_t)oct * list_stride + sum->level_start[l] + i] = b;
     }
 }
 
@@ -803,10 +811,10 @@ int vlist_blocks(int nbox) { return ceil_div(nbox, kVBoxes); }
 
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
                   int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
-                  int32_t *parent_oct, uint32_t *item_off, int32_t *src_items, int32_t *cuts, uint32_t *scan_part,
-                  uint32_t *n_items, hipStream_t st)
+                  int32_t *parent_oct, uint32_t *l2l_cnt, int32_t *l2l_list, uint32_t *item_off, int32_t *src_items,
+                  int32_t *cuts, uint32_t *scan_part, uint32_t *n_items, hipStream_t st)
 {
-    k_oct_tables<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, child_oct, parent_oct);
+    k_oct_tables<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, child_oct, parent_oct, l2l_cnt, l2l_list, nbox);
     k_colleagues<<<ceil_div(nbox * kNeigh, 256), 256, 0, st>>>(bt, sum, coll);
     k_vlist<<<vlist_blocks(nbox), 256, 0, st>>>(bt, sum, coll, child_oct, vtab, v_blk);
     k_nearlist<<<nbox, 64, 0, st>>>(bt, sum, coll, stride, near, near_cnt, item_off, src_items, cuts, near_pairs);

@@ -99,10 +99,16 @@ void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64
 // Work counts: v_blk (vlist_blocks(nbox) ints) = V pairs per group of boxes,
 // near_pairs (nbox) = near-field pairs per leaf.
 int vlist_blocks(int nbox);
+// L2L buckets: the boxes of levels >= 3 by tree level and octant,
+// l2l_list[o * nbox + level_start[l] + i] for i < l2l_cnt[8 l + o] (order
+// within a bucket unspecified: every box's result is computed alone);
+// l2l_cnt must be zero beforehand.
+constexpr int kL2LCounts = 8 * (kMaxLevel + 1);
+static_assert(kL2LCounts % 2 == 0, "L2L counts are cleared as 64-bit words");
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
                   int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
-                  int32_t *parent_oct, uint32_t *item_off, int32_t *src_items, int32_t *cuts, uint32_t *scan_part,
-                  uint32_t *n_items, hipStream_t st);
+                  int32_t *parent_oct, uint32_t *l2l_cnt, int32_t *l2l_list, uint32_t *item_off, int32_t *src_items,
+                  int32_t *cuts, uint32_t *scan_part, uint32_t *n_items, hipStream_t st);
 // cuts (stride per box): first near range of each source item of a leaf.
 void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *near_cnt, int stride,
                       const uint32_t *item_off, const int32_t *src_items, const int32_t *cuts, int4 *work,
@@ -123,9 +129,12 @@ template <typename T>
 void launch_m2m(const BoxTable &bt, const TreeSummary *sum, int p, const Caps &cap, const T *m2m_pad,
                 const int2 *oct_slots, const int32_t *child_oct, T *M, T *part, hipStream_t st);
 int m2l_groups(int n2);  // slot groups of M2M / L2L partial sums (partial-sum buffer: groups x nbox x Kp)
+// L2L, level by level: each box of an octant bucket adds its parent's local
+// expansion shifted by its octant's operator (l2l_cnt / l2l_list as above).
 template <typename T>
 void launch_downward(const BoxTable &bt, const TreeSummary *sum, int p, const Caps &cap, const T *l2l_pad,
-                     const int2 *oct_slots, const int32_t *parent_oct, T *L, T *part, hipStream_t st);
+                     const int2 *oct_slots, const int32_t *parent_oct, const uint32_t *l2l_cnt,
+                     const int32_t *l2l_list, T *L, hipStream_t st);
 // Near field over the work items into part (item x 64 x 3; with pot the
 // potential sum as a fourth component, item x 64 x 4); *n_items items (on the
 // device, at most cap_items), at most max_grid workgroups, which take the
@@ -135,10 +144,13 @@ template <typename T>
 void launch_near(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, const int2 *near, int stride,
                  const int4 *work, const uint32_t *n_items, int cap_items, T *part, bool pot, int max_grid, int *queue,
                  hipStream_t st);
-// Near-field workgroups per compute unit while the M2L GEMM runs beside the
-// near field: with this many, two GEMM workgroups still fit in every compute
-// unit's LDS, whichever kernel reaches the unit first.
+// Near-field workgroups per compute unit while the far field runs beside the
+// near field: with four, two M2L GEMM workgroups still fit in every compute
+// unit's LDS, whichever kernel reaches the unit first.  When the near field
+// forks before the upward pass (mixed form), three: the translation
+// workgroups of the upward pass then also find registers beside it.
 constexpr int kNearPerCUConcurrent = 4;
+constexpr int kNearPerCUEarly = 3;
 // LDS of one near-field workgroup (its staged sources and range tables).
 size_t near_lds_bytes();
 // Far field (L2P) + the item partials per ion into E (batch order); with phi

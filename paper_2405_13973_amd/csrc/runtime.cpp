@@ -120,7 +120,8 @@ struct pt_ctx {
     hipEvent_t ev_near[kTimingRing][2] = {};  // timing of the P2P kernel (its own stream)
     bool near_timed[kTimingRing] = {};
     int near_concurrent = -1;  // -1: by leaf size; 0 / 1: forced (PT_NEAR_CONCURRENT)
-    int near_per_cu = kNearPerCUConcurrent;  // near-field workgroups per CU beside M2L (PT_NEAR_PER_CU)
+    int near_per_cu = 0;  // near-field workgroups per CU beside the far field (PT_NEAR_PER_CU; 0: by schedule)
+    int near_early = -1;  // -1: by precision; 0 / 1: forced (PT_NEAR_EARLY): near field forks before the upward pass
     uint64_t budget = 0, used = 0;
     int live = 0;
     int32_t *d_nonfinite = nullptr;  // set by any kick of this context that produces a non-finite value
@@ -617,11 +618,18 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     uint32_t *rstate;
     PT_TRY(ws_get(ctx, "radix_state", sizeof(uint32_t) * radix_state_words(ntot), &rstate));
     const uint32_t *sort_err = nullptr;
-    if (passes <= 8) {
+    // the sort's counters and the L2L bucket counts start at zero
+    uint32_t *l2l_cnt;
+    PT_TRY(ws_get(ctx, "l2l_cnt", sizeof(uint32_t) * kL2LCounts, &l2l_cnt));
+    {
         ZeroRegions zr{};
         zr.p[0] = (uint64_t *)rstate;
-        zr.n[0] = radix_state_zero_words() / 2;
+        zr.n[0] = passes <= 8 ? radix_state_zero_words() / 2 : 0;
+        zr.p[1] = (uint64_t *)l2l_cnt;
+        zr.n[1] = kL2LCounts / 2;
         launch_zero_regions(zr, st);
+    }
+    if (passes <= 8) {
         if (launch_radix_sort(k0, v0, k1, v1, ntot, passes, rstate, &dsum->halt, st) == 1) {
             std::swap(k0, k1);
             std::swap(v0, v1);
@@ -701,6 +709,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     uint32_t *item_off;
     PT_TRY(ws_get(ctx, "child_oct", sizeof(int32_t) * 8 * (size_t)nbox, &child_oct));
     PT_TRY(ws_get(ctx, "parent_oct", sizeof(int32_t) * 8 * (size_t)nbox, &parent_oct));
+    int32_t *l2l_list;
+    PT_TRY(ws_get(ctx, "l2l_list", sizeof(int32_t) * 8 * (size_t)nbox, &l2l_list));
     PT_TRY(ws_get(ctx, "item_off", sizeof(uint32_t) * (size_t)nbox, &item_off));
     PT_TRY(ws_get(ctx, "src_items", sizeof(int32_t) * (size_t)nbox, &src_items));
     int32_t *v_blk;
@@ -715,15 +725,15 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     uint32_t *m2l_pcnt, *m2l_cnt_ob;
     PT_TRY(ws_get(ctx, "m2l_pcnt", sizeof(uint32_t) * (size_t)nbox, &m2l_pcnt));
     PT_TRY(ws_get(ctx, "m2l_cnt_ob", sizeof(uint32_t) * (size_t)m2l_ops() * nbox, &m2l_cnt_ob));
-    launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, v_blk, near_pairs, child_oct, parent_oct, item_off,
-                 src_items, cuts, scan_part, total + 1, st);
+    launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, v_blk, near_pairs, child_oct, parent_oct, l2l_cnt,
+                 l2l_list, item_off, src_items, cuts, scan_part, total + 1, st);
     // M2L pairs: counted and scanned here, so that their number comes back
     // with the near-field item count
     launch_m2l_count(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, scan_part, total + 2, st);
     // near-field work items and M2L pairs: their numbers size the item,
-    // partial and pair buffers.  Measuring, they are read back while the
-    // upward pass, which does not need them, runs: the host waits for an
-    // event right after the copy, not for the stream.
+    // partial and pair buffers.  Measuring, they are read back (the host waits
+    // for an event right after the copy, not for the stream); queued, a
+    // check against the capacities halts the run on overflow.
     if (queued) {
         launch_cap_check_lists(dsum, total, cap, st);
     } else {
@@ -745,14 +755,6 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     zr.n[0] = zr.n[1] = (int)(esz * Kp / 8);
     zr.n[2] = 1;
     launch_zero_regions(zr, st);
-    auto upward = [&](auto tag) -> pt_status {
-        using T = decltype(tag);
-        const T *m2m = sizeof(T) == sizeof(float) ? (const T *)tb.m2m_f : (const T *)tb.m2m_d;
-        PT_HIP(hipStreamWaitEvent(st, ctx->ev_p2m, 0));  // P2M (second stream)
-        launch_m2m<T>(bt, dsum, p, cap, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, st);
-        return PT_OK;
-    };
-    PT_TRY(fp.precision == 1 ? upward(float(0)) : upward(double(0)));
     if (!queued) {
         PT_HIP(hipEventSynchronize(ctx->ev_read));
         cap.items = (int)((uint32_t *)ctx->h_counters)[0];
@@ -771,32 +773,34 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     const int ncomp = phi ? 4 : 3;  // near-field partial components per target
     PT_TRY(ws_get(ctx, "p2p_part", esz * 64 * ncomp * (size_t)std::max(1, n_items), (char **)&ppart));
     launch_p2p_items(bt, dsum, nbox, near_cnt, stride, item_off, src_items, cuts, work, st);
-    launch_m2l_emit(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, total + 2, m2l_bucket, m2l_op_beg,
-                    m2l_chunk_off, st);
     auto run = [&](auto tag) -> pt_status {
         using T = decltype(tag);
         const bool f = sizeof(T) == sizeof(float);
+        const T *m2m = f ? (const T *)tb.m2m_f : (const T *)tb.m2m_d;
         const T *m2l = f ? (const T *)tb.m2l_f : (const T *)tb.m2l_d;  // row-major base operators
         const T *l2l = f ? (const T *)tb.l2l_f : (const T *)tb.l2l_d;
         const T *rec = f ? (const T *)tb.rec_f : (const T *)tb.rec_d;
         // near field on its own stream, concurrently with M2L and L2L (vector
         // ALUs beside matrix cores) when leaves are large enough for the near
-        // field to rival the far field; it starts once the upward pass is done
-        // (P2M and M2M would starve beside it) and joins before L2P.  With
-        // small leaves M2L dominates and sharing the chip only slows it: the
-        // near field then runs after L2L on the main stream.
+        // field to rival the far field, joining before L2P; the far-field
+        // kernels beside it raise their wave priority.  It needs only the
+        // sorted positions and its work items: in the mixed form it forks as
+        // soon as those exist (after P2M on its stream), beside the upward
+        // pass too; the FP64 near field's registers leave no room for the
+        // upward pass's workgroups, so there it forks after the upward pass
+        // (measured, both).  With small leaves M2L dominates and sharing the
+        // chip only slows it: the near field then runs after L2L on the main
+        // stream.
         const bool concurrent = ctx->near_concurrent > 0 || (ctx->near_concurrent < 0 && s >= kConcurrentLeaf);
+        const bool early = concurrent && (ctx->near_early >= 0 ? ctx->near_early > 0 : f);
+        const int near_cap = ctx->near_per_cu > 0 ? ctx->near_per_cu : early ? kNearPerCUEarly : kNearPerCUConcurrent;
         hipStream_t ns = concurrent ? ctx->near_stream : st;
-        if (concurrent) {
-            PT_HIP(hipEventRecord(ctx->ev_fork, st));
-            PT_HIP(hipStreamWaitEvent(ns, ctx->ev_fork, 0));
-        }
         auto near_field = [&]() -> pt_status {
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][0], ns));
-            const int max_grid = concurrent ? ctx->near_per_cu * ctx->num_cu : 16384;
-            // beside M2L the grid is capped and the workgroups take items from
-            // a queue; alone, one workgroup per item (no queue: its atomics
-            // would serialise over the many small items of small leaves)
+            const int max_grid = concurrent ? near_cap * ctx->num_cu : 16384;
+            // beside the far field the grid is capped and the workgroups take
+            // items from a queue; alone, one workgroup per item (no queue: its
+            // atomics would serialise over the many small items of small leaves)
             launch_near<T>(bt, dsum, sp, ntot, near, stride, work, total + 1, n_items, (T *)ppart, phi != nullptr,
                            max_grid, concurrent ? p2p_queue : nullptr, ns);
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][1], ns));
@@ -804,15 +808,26 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             if (concurrent) PT_HIP(hipEventRecord(ctx->ev_join, ns));
             return PT_OK;
         };
-        if (concurrent) PT_TRY(near_field());
+        auto fork = [&]() -> pt_status {
+            PT_HIP(hipEventRecord(ctx->ev_fork, st));
+            PT_HIP(hipStreamWaitEvent(ns, ctx->ev_fork, 0));
+            return near_field();
+        };
+        if (early) PT_TRY(fork());
+        // upward pass (after P2M on the second stream), then the M2L buckets
+        PT_HIP(hipStreamWaitEvent(st, ctx->ev_p2m, 0));
+        launch_m2m<T>(bt, dsum, p, cap, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, st);
+        launch_m2l_emit(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, total + 2, m2l_bucket,
+                        m2l_op_beg, m2l_chunk_off, st);
+        if (concurrent && !early) PT_TRY(fork());
         mark(ctx, 2);
         const int m2l_grid =
-            ctx->num_cu * m2l_per_cu<T>(Kp, concurrent ? ctx->near_per_cu * near_lds_bytes() : 0);
+            ctx->num_cu * m2l_per_cu<T>(Kp, concurrent ? near_cap * near_lds_bytes() : 0);
         launch_m2l_gemm<T>(dsum, Kp, nbox, m2l_grid, m2l_chunk_off, m2l_op_beg, m2l_bucket, m2l, (const T *)M,
                            (T *)m2l_R, st);
         mark(ctx, 3);
         launch_m2l_sum<T>(dsum, nbox, Kp, m2l_pcnt, total + 2, (const T *)m2l_R, (T *)L, st);
-        launch_downward<T>(bt, dsum, p, cap, l2l, tb.oct_slots, parent_oct, (T *)L, (T *)xl_part, st);
+        launch_downward<T>(bt, dsum, p, cap, l2l, tb.oct_slots, parent_oct, l2l_cnt, l2l_list, (T *)L, st);
         mark(ctx, 4);
         if (!concurrent) PT_TRY(near_field());
         mark(ctx, 5);
@@ -933,6 +948,7 @@ static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
     PT_HIP(hipStreamCreateWithFlags(&ctx->near_stream, hipStreamNonBlocking));
     if (const char *e = getenv("PT_NEAR_CONCURRENT")) ctx->near_concurrent = atoi(e) ? 1 : 0;
     if (const char *e = getenv("PT_NEAR_PER_CU")) ctx->near_per_cu = std::max(1, std::min(8, atoi(e)));
+    if (const char *e = getenv("PT_NEAR_EARLY")) ctx->near_early = atoi(e) ? 1 : 0;
     if (const char *e = getenv("PT_QUEUED_STEPS")) ctx->no_queue = atoi(e) == 0;
     if (const char *e = getenv("PT_CAPS_TIGHT")) ctx->tight_caps = atoi(e) != 0;
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
