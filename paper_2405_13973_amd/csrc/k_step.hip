@@ -586,6 +586,7 @@ __global__ void k_run_reset(TreeSummary *__restrict__ sum)
 {
     sum->halt = 0;
     sum->fail_step = -1;
+    sum->refine_overflow = 0;
 }
 
 void launch_cap_check_tree(TreeSummary *sum, const Caps &cap, hipStream_t st) { k_cap_check_tree<<<1, 1, 0, st>>>(sum, cap); }

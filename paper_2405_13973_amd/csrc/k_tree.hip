@@ -183,13 +183,14 @@ constexpr uint64_t kFlagAgg = 1ull << 62, kFlagIncl = 2ull << 62, kFlagCount = (
 constexpr int kSpinMax = 1 << 20;
 
 __global__ __launch_bounds__(kSortTB) void k_radix_prepare(const uint64_t *__restrict__ keys, int n, int passes,
-                                                           uint32_t *__restrict__ ghist, uint64_t *__restrict__ flags,
-                                                           int ntile, const int32_t *__restrict__ halt)
+                                                           int first, uint32_t *__restrict__ ghist,
+                                                           uint64_t *__restrict__ flags, int ntile,
+                                                           const int32_t *__restrict__ halt)
 {
     if (halt && *halt) return;  // a halted run (every workgroup sees the same word)
     __shared__ uint32_t cnt[kMaxPasses][256];
     const int tid = threadIdx.x;
-    for (int p = 0; p < passes; ++p) {
+    for (int p = first; p < passes; ++p) {
         cnt[p][tid] = 0;
         flags[((size_t)p * ntile + blockIdx.x) * 256 + tid] = 0ull;
     }
@@ -198,12 +199,46 @@ __global__ __launch_bounds__(kSortTB) void k_radix_prepare(const uint64_t *__res
         const int i = blockIdx.x * kSortTile + r * kSortTB + tid;
         if (i < n) {
             const uint64_t key = keys[i];
-            for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][(key >> (8 * p)) & 255u], 1u);
+            for (int p = first; p < passes; ++p) atomicAdd(&cnt[p][(key >> (8 * p)) & 255u], 1u);
         }
     }
     __syncthreads();
-    for (int p = 0; p < passes; ++p)
+    for (int p = first; p < passes; ++p)
         if (cnt[p][tid]) atomicAdd(&ghist[p * 256 + tid], cnt[p][tid]);
+}
+
+// Completes a stable sort by key >> shift: each run of equal key >> shift is
+// ordered by (key, value) by the thread at its first slot (insertion sort;
+// runs hold one or two slots at the sizes of interest).  The order a full
+// sort gives -- by key, equal keys by value, values ascending on entry -- is
+// what this produces, since the stable sort kept each run in value order.
+__global__ void k_sort_refine(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, int n, int shift,
+                              TreeSummary *__restrict__ sum)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || sum->halt) return;
+    const uint64_t run = keys[k] >> shift;
+    if (k > 0 && (keys[k - 1] >> shift) == run) return;  // not the first slot of its run
+    int e = k + 1;
+    while (e < n && e - k <= kRefineMax && (keys[e] >> shift) == run) ++e;
+    if (e - k > kRefineMax) {
+        // plain stores: every writer writes 1
+        sum->refine_overflow = 1;
+        sum->halt = 1;
+        return;
+    }
+    for (int i = k + 1; i < e; ++i) {
+        const uint64_t kk = keys[i];
+        const uint32_t vv = vals[i];
+        int j = i - 1;
+        while (j >= k && (keys[j] > kk || (keys[j] == kk && vals[j] > vv))) {
+            keys[j + 1] = keys[j];
+            vals[j + 1] = vals[j];
+            --j;
+        }
+        keys[j + 1] = kk;
+        vals[j + 1] = vv;
+    }
 }
 
 __global__ __launch_bounds__(kSortTB) void k_radix_pass(const uint64_t *__restrict__ kin,
@@ -771,19 +806,25 @@ void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint3
 size_t radix_state_words(int n) { return (size_t)kMaxPasses * 256 + kMaxPasses + 1 + 1 +
                                         2 * (size_t)kMaxPasses * sort_blocks(n) * 256; }
 
-int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int n, int passes, uint32_t *state,
-                      const int32_t *halt, hipStream_t st)
+int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int n, int passes, int first,
+                      uint32_t *state, const int32_t *halt, hipStream_t st)
 {
-    if (passes > kMaxPasses || n <= 0) return -1;
+    if (passes > kMaxPasses || first < 0 || first > passes || n <= 0) return -1;
     const int ntile = sort_blocks(n);
     uint32_t *ghist = state, *ctr = state + kMaxPasses * 256, *err = ctr + kMaxPasses;
     uint64_t *flags = (uint64_t *)(state + kMaxPasses * 256 + kMaxPasses + 2);  // 8-byte aligned
-    k_radix_prepare<<<ntile, kSortTB, 0, st>>>(k0, n, passes, ghist, flags, ntile, halt);
-    for (int p = 0; p < passes; ++p) {
-        k_radix_pass<<<ntile, kSortTB, 0, st>>>(p % 2 ? k1 : k0, p % 2 ? v1 : v0, p % 2 ? k0 : k1, p % 2 ? v0 : v1, n,
-                                                p, ghist, flags, ntile, ctr, err, halt);
+    k_radix_prepare<<<ntile, kSortTB, 0, st>>>(k0, n, passes, first, ghist, flags, ntile, halt);
+    for (int p = first; p < passes; ++p) {
+        const bool odd = (p - first) % 2;
+        k_radix_pass<<<ntile, kSortTB, 0, st>>>(odd ? k1 : k0, odd ? v1 : v0, odd ? k0 : k1, odd ? v0 : v1, n, p, ghist,
+                                                flags, ntile, ctr, err, halt);
     }
-    return passes % 2;  // 1: the result is in (k1, v1)
+    return (passes - first) % 2;  // 1: the result is in (k1, v1)
+}
+
+void launch_sort_refine(uint64_t *keys, uint32_t *vals, int n, int shift, TreeSummary *sum, hipStream_t st)
+{
+    if (n > 0) k_sort_refine<<<ceil_div(n, 256), 256, 0, st>>>(keys, vals, n, shift, sum);
 }
 
 int tree_blocks(int ntot) { return ceil_div(ntot, 256); }

@@ -106,6 +106,7 @@ struct TreeSummary {
     int32_t sort_error;  // non-zero: the sort's look-back gave up waiting (see k_radix_pass)
     int32_t halt;
     int32_t fail_step;
+    int32_t refine_overflow;  // non-zero: a queued step's sort by the top digits left a run too long to finish
 };
 
 // Capacities of a queued force evaluation's buffers and grids: boxes, tree

@@ -69,17 +69,28 @@ void launch_rot_state(const CrystalDev *cs, const int32_t *ion_crystal, int ntot
 int scan_partials(int n);  // workspace entries launch_scan needs for n elements
 void launch_scan(uint32_t *a, int n, uint32_t *partial, uint32_t *total, hipStream_t st);
 int sort_blocks(int n);
-// Single-pass-per-digit radix sort of (k0, v0) by the low 8 x passes bits
-// (passes <= 8): state holds radix_state_words(n) uint32 whose first
-// radix_state_zero_words() must be zero on entry; the error word is
-// state + radix_state_err().  Returns 1 when the result is in (k1, v1), 0
-// when in (k0, v0), -1 when passes is out of range.
+// Single-pass-per-digit radix sort of (k0, v0) by the 8-bit digits
+// first..passes-1 (bits 8 first to 8 passes; passes <= 8), stable: with
+// first = 0 and keys below 2^(8 passes) a full sort.  state holds
+// radix_state_words(n) uint32 whose first radix_state_zero_words() must be
+// zero on entry; the error word is state + radix_state_err().  Returns 1
+// when the result is in (k1, v1), 0 when in (k0, v0), -1 when passes is out
+// of range.
 size_t radix_state_words(int n);
 constexpr int radix_state_zero_words() { return 8 * 256 + 8 + 2; }
 constexpr int radix_state_err() { return 8 * 256 + 8; }
 // halt (nullable): a run-state word; when it is set the passes do nothing.
-int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int n, int passes, uint32_t *state,
-                      const int32_t *halt, hipStream_t st);
+int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int n, int passes, int first,
+                      uint32_t *state, const int32_t *halt, hipStream_t st);
+// After a stable sort by key >> shift: orders every run of equal key >> shift
+// by (key, value), which completes the full sort.  A run longer than
+// kRefineMax sets sum->refine_overflow and halts the run instead.
+constexpr int kRefineMax = 32;
+// Morton levels (3 bits each) by which the sort of a queued step orders
+// before the runs are refined: whole 8-bit digits.
+constexpr int kSortTopLevels = 8;
+static_assert((3 * kSortTopLevels) % 8 == 0, "the top levels must fill whole digits");
+void launch_sort_refine(uint64_t *keys, uint32_t *vals, int n, int shift, TreeSummary *sum, hipStream_t st);
 void launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, int n, int shift,
                        uint32_t *hist, uint32_t *partial, hipStream_t st);
 void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint32_t *vals, int ntot, double *sp,

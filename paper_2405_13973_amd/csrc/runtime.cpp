@@ -122,6 +122,9 @@ struct pt_ctx {
     int near_concurrent = -1;  // -1: by leaf size; 0 / 1: forced (PT_NEAR_CONCURRENT)
     int near_per_cu = 0;  // near-field workgroups per CU beside the far field (PT_NEAR_PER_CU; 0: by schedule)
     int near_early = -1;  // -1: by precision; 0 / 1: forced (PT_NEAR_EARLY): near field forks before the upward pass
+    bool partial_sort = true;  // queued steps sort by the top digits and refine (PT_PARTIAL_SORT=0: all digits)
+    std::vector<pt_crystal *> psort_off_batch;  // batch whose queued steps sort by all digits (a run overflowed)
+    int64_t psort_off_ntot = -1;
     uint64_t budget = 0, used = 0;
     int live = 0;
     int32_t *d_nonfinite = nullptr;  // set by any kick of this context that produces a non-finite value
@@ -629,11 +632,20 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         zr.n[1] = kL2LCounts / 2;
         launch_zero_regions(zr, st);
     }
+    // A queued step sorts by the top digits only (the Morton levels down to
+    // kSortTopLevels and the crystal) and orders each run of equal top digits
+    // by (key, value): the same order as the full sort while every run is
+    // short, which holds unless very many ions share a cell of that level; a
+    // longer run halts the step, and it is run again with the full sort.
+    const bool partial = queued && ctx->partial_sort &&
+                         !(ctx->psort_off_batch == b.cs && ctx->psort_off_ntot == (int64_t)ntot);
+    const int first = partial ? (48 - 3 * kSortTopLevels) / 8 : 0;
     if (passes <= 8) {
-        if (launch_radix_sort(k0, v0, k1, v1, ntot, passes, rstate, &dsum->halt, st) == 1) {
+        if (launch_radix_sort(k0, v0, k1, v1, ntot, passes, first, rstate, &dsum->halt, st) == 1) {
             std::swap(k0, k1);
             std::swap(v0, v1);
         }
+        if (partial) launch_sort_refine(k0, v0, ntot, 8 * first, dsum, st);
         sort_err = rstate + radix_state_err();
     } else {
         for (int ps = 0; ps < passes; ++ps) {
@@ -949,6 +961,7 @@ static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
     if (const char *e = getenv("PT_NEAR_CONCURRENT")) ctx->near_concurrent = atoi(e) ? 1 : 0;
     if (const char *e = getenv("PT_NEAR_PER_CU")) ctx->near_per_cu = std::max(1, std::min(8, atoi(e)));
     if (const char *e = getenv("PT_NEAR_EARLY")) ctx->near_early = atoi(e) ? 1 : 0;
+    if (const char *e = getenv("PT_PARTIAL_SORT")) ctx->partial_sort = atoi(e) != 0;
     if (const char *e = getenv("PT_QUEUED_STEPS")) ctx->no_queue = atoi(e) == 0;
     if (const char *e = getenv("PT_CAPS_TIGHT")) ctx->tight_caps = atoi(e) != 0;
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
@@ -1505,7 +1518,14 @@ static pt_status settle(pt_ctx *ctx)
             rest[i] = pd.n_steps[i] - done;
         }
         ctx->caps_ok = false;
-        ctx->caps_slack = std::min(4.0, ctx->caps_slack * 1.5);
+        if (ts.refine_overflow) {
+            // the batch's queued steps sort by all digits from now on
+            ctx->psort_off_batch = pd.cs;
+            ctx->psort_off_ntot = 0;
+            for (pt_crystal *c : pd.cs) ctx->psort_off_ntot += c->n;
+        } else {
+            ctx->caps_slack = std::min(4.0, ctx->caps_slack * 1.5);
+        }
         ctx->reruns++;
         if (ts.sort_error) {
             pt_set_error("radix sort: a workgroup gave up waiting for its predecessors' digit counts");

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _run(monkeypatch, env, crs, steps, precision, leaf):
-    for k in ("PT_QUEUED_STEPS", "PT_CAPS_TIGHT"):
+    for k in ("PT_QUEUED_STEPS", "PT_CAPS_TIGHT", "PT_PARTIAL_SORT"):
         monkeypatch.delenv(k, raising=False)
     for k, v in env.items():
         monkeypatch.setenv(k, v)
@@ -71,3 +71,33 @@ def test_queued_steps_at_full_size(monkeypatch):
     (a, sa), (b, sb) = res
     assert sa["queued"] == 0 and sb["queued"] == 11
     assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+
+
+def test_sort_refine_overflow_reruns_with_the_full_sort(monkeypatch):
+    """Queued steps sort by the top Morton levels and order each run of equal
+    top digits by (key, index).  A far outlier stretches the root cube so that
+    the whole cluster shares a few cells at that level: the runs are too long,
+    the first queued step halts and is run again with the full sort, and the
+    states equal those of measured steps and of the full sort throughout."""
+    g = inputs.rng(81)
+    pos = inputs.uniform_ball(3000, 1e-4, g)
+    pos[0] = (5e-2, 0.0, 0.0)
+    vel = inputs.thermal_velocities(3000, 10e-3, inputs.ION_MASS, g)
+    cr = inputs.Crystal(pos, vel, seed=81)
+    print("sort refine overflow", flush=True)
+    runs = {}
+    for name, env in (("measured", {"PT_QUEUED_STEPS": "0"}), ("full", {"PT_PARTIAL_SORT": "0"}), ("partial", {})):
+        for k in ("PT_QUEUED_STEPS", "PT_CAPS_TIGHT", "PT_PARTIAL_SORT"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        with native.Context(0) as ctx:
+            c = ctx.crystal(cr.pos, cr.vel, cr.charge, cr.mass, cr.seed)
+            c.set_trap(B=cr.B, omega_z=cr.omega_z, dt=cr.dt)
+            c.set_force("fmm", 8, 48, "fp64")
+            c.step(6)
+            runs[name] = (c.read_state(), ctx.step_stats())
+    (m, sm), (f, sf), (p, sp) = runs["measured"], runs["full"], runs["partial"]
+    assert sm["queued"] == 0 and sp["reruns"] > sf["reruns"]
+    for key in ("pos", "vel"):
+        assert np.array_equal(m[key], f[key]) and np.array_equal(m[key], p[key]), key
