@@ -154,10 +154,14 @@ __global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *_
 // Root cube per crystal, in the exact operation order of the tree contract:
 // W = max extent (1e-9 m if zero), o = (lo + hi)/2 - W/2, S = 2^16 / W.
 // Resets the bounding box for its next use.
-__global__ void k_root(unsigned long long *__restrict__ bbox, int nc, int bstride, RootCube *__restrict__ roots)
+__global__ void k_root(unsigned long long *__restrict__ bbox, int nc, int bstride, RootCube *__restrict__ roots,
+                       ZeroRegions zr)
 {
 #pragma clang fp contract(off)
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    // the counters of the steps that follow start at zero (grid-stride)
+    for (int r = 0; r < kZeroRegions; ++r)
+        for (int i = c; i < zr.n[r]; i += gridDim.x * blockDim.x) zr.p[r][i] = 0ull;
     if (c >= nc) return;
     unsigned long long w[6];
     for (int k = 0; k < 6; ++k) w[k] = bbox[6 * c + k];
@@ -545,9 +549,9 @@ void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int nto
                                                           halt);
 }
 
-void launch_root(unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st)
+void launch_root(unsigned long long *bbox, int nc, RootCube *roots, const ZeroRegions &zr, hipStream_t st)
 {
-    k_root<<<ceil_div(nc, 64), 64, 0, st>>>(bbox, nc, bbox_stride(nc), roots);
+    k_root<<<ceil_div(nc, 64), 64, 0, st>>>(bbox, nc, bbox_stride(nc), roots, zr);
 }
 
 void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCube *roots, int ntot, uint64_t *keys,
@@ -565,17 +569,6 @@ void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int nto
 }
 
 // Capacity checks and the run reset (one thread each).
-__global__ void k_cap_check_tree(TreeSummary *__restrict__ sum, Caps cap)
-{
-    if (sum->halt) return;
-    int nlev = 0;
-    for (int l = 0; l <= kMaxLevel; ++l)
-        if (sum->level_start[l + 1] > sum->level_start[l]) nlev = l + 1;
-    // (a level holding more boxes than its grid covers is still covered, by
-    // striding; only the buffers sized by these counts can overflow)
-    if (sum->nbox > cap.nbox || nlev > cap.nlev || sum->sort_error != 0) sum->halt = 1;
-}
-
 __global__ void k_cap_check_lists(TreeSummary *__restrict__ sum, const uint32_t *__restrict__ total, Caps cap)
 {
     if (sum->halt) return;
@@ -589,7 +582,6 @@ __global__ void k_run_reset(TreeSummary *__restrict__ sum)
     sum->refine_overflow = 0;
 }
 
-void launch_cap_check_tree(TreeSummary *sum, const Caps &cap, hipStream_t st) { k_cap_check_tree<<<1, 1, 0, st>>>(sum, cap); }
 
 void launch_cap_check_lists(TreeSummary *sum, const uint32_t *total, const Caps &cap, hipStream_t st)
 {

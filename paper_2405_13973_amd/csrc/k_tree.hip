@@ -22,12 +22,14 @@ namespace pt {
 
 // --------------------------------------------------------------- scan
 
-// Exclusive prefix sum of n uint32 in place, in two launches: block sums of
-// 4096-element chunks, then each chunk scanned with its offset, which each
-// block adds up itself from the sums of the chunks before it (a few dozen
-// at the sizes here).  *total (optional) gets the sum.
+// Exclusive prefix sum of n uint32 in place: block sums of 8192-element
+// chunks, then each chunk scanned with its offset, which each block adds up
+// itself from the sums of the chunks before it (a few dozen at the sizes
+// here); one chunk needs only the second launch.  *total (optional) gets the
+// sum.
 constexpr int kScanTB = 1024;
-constexpr int kScanChunk = 4 * kScanTB;
+constexpr int kScanPer = 8;
+constexpr int kScanChunk = kScanPer * kScanTB;
 
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *lds_w, uint32_t &block_total)
 {
@@ -61,10 +63,10 @@ __global__ __launch_bounds__(kScanTB) void k_scan_reduce(const uint32_t *__restr
                                                          uint32_t *__restrict__ partial)
 {
     __shared__ uint32_t w[kScanTB / 64 + 1];
-    const int base = blockIdx.x * kScanChunk + 4 * threadIdx.x;
+    const int base = blockIdx.x * kScanChunk + kScanPer * threadIdx.x;
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) s += base + k < n ? a[base + k] : 0u;
+    for (int k = 0; k < kScanPer; ++k) s += base + k < n ? a[base + k] : 0u;
     uint32_t tot;
     block_excl_scan(s, w, tot);
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
@@ -81,15 +83,18 @@ __global__ __launch_bounds__(kScanTB) void k_scan_down(uint32_t *__restrict__ a,
     uint32_t off;
     block_excl_scan(pre, w, off);
     __syncthreads();  // w is reused below
-    const int base = blockIdx.x * kScanChunk + 4 * threadIdx.x;
-    uint32_t v[4];
+    const int base = blockIdx.x * kScanChunk + kScanPer * threadIdx.x;
+    uint32_t v[kScanPer], s = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = base + k < n ? a[base + k] : 0u;
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = base + k < n ? a[base + k] : 0u;
+        s += v[k];
+    }
     uint32_t tot;
-    uint32_t run = off + block_excl_scan(v[0] + v[1] + v[2] + v[3], w, tot);
+    uint32_t run = off + block_excl_scan(s, w, tot);
     if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kScanPer; ++k) {
         if (base + k < n) a[base + k] = run;
         run += v[k];
     }
@@ -466,13 +471,26 @@ __global__ __launch_bounds__(256) void k_tree_levels(const CrystalDev *__restric
 }
 
 __global__ void k_tree_summary(const uint32_t *__restrict__ scanned, int nblk, const uint32_t *__restrict__ total,
-                               const uint32_t *__restrict__ sort_err, TreeSummary *__restrict__ sum)
+                               const uint32_t *__restrict__ sort_err, TreeSummary *__restrict__ sum, Caps cap,
+                               int check)
 {
     if (threadIdx.x != 0 || sum->halt) return;
-    sum->sort_error = sort_err ? (int32_t)*sort_err : 0;
-    for (int l = 0; l <= kMaxLevel; ++l) sum->level_start[l] = (int32_t)scanned[l * nblk];
-    sum->level_start[kMaxLevel + 1] = (int32_t)*total;
-    sum->nbox = (int32_t)*total;
+    const int32_t err = sort_err ? (int32_t)*sort_err : 0;
+    sum->sort_error = err;
+    int nlev = 0;
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        sum->level_start[l] = (int32_t)scanned[l * nblk];
+        if (l > 0 && sum->level_start[l] > sum->level_start[l - 1]) nlev = l;
+    }
+    const int32_t nbox = (int32_t)*total;
+    sum->level_start[kMaxLevel + 1] = nbox;
+    sum->nbox = nbox;
+    if (nbox > sum->level_start[kMaxLevel]) nlev = kMaxLevel + 1;
+    // a queued step: boxes and levels must fit the capacities (a level
+    // holding more boxes than its grid covers is still covered, by striding;
+    // only the buffers sized by these counts can overflow), and the sort
+    // must have finished
+    if (check && (nbox > cap.nbox || nlev > cap.nlev || err != 0)) sum->halt = 1;
 }
 
 // Writes one box record per (slot, level) representative.
@@ -573,9 +591,11 @@ __global__ void k_tree_links(BoxTable bt, const TreeSummary *__restrict__ sum)
 // levels >= 3 by level and octant, l2l_cnt zeroed beforehand).
 __global__ void k_oct_tables(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ child_oct,
                              int32_t *__restrict__ parent_oct, uint32_t *__restrict__ l2l_cnt,
-                             int32_t *__restrict__ l2l_list, int list_stride)
+                             int32_t *__restrict__ l2l_list, int list_stride, ZeroRegions zr)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int r = 0; r < kZeroRegions; ++r)  // words the later kernels need zeroed (grid-stride)
+        for (int i = b; i < zr.n[r]; i += gridDim.x * blockDim.x) zr.p[r][i] = 0ull;
     if (sum->halt || b >= sum->nbox) return;
     int32_t ch[8], pa[8];
     for (int o = 0; o < 8; ++o) ch[o] = pa[o] = -1;
@@ -782,7 +802,7 @@ void launch_scan(uint32_t *a, int n, uint32_t *partial, uint32_t *total, hipStre
         return;
     }
     const int nb = scan_partials(n);
-    k_scan_reduce<<<nb, kScanTB, 0, st>>>(a, n, partial);
+    if (nb > 1) k_scan_reduce<<<nb, kScanTB, 0, st>>>(a, n, partial);  // one chunk reads no partials
     k_scan_down<<<nb, kScanTB, 0, st>>>(a, n, partial, total);
 }
 
@@ -831,12 +851,12 @@ int tree_blocks(int ntot) { return ceil_div(ntot, 256); }
 
 void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
                        int32_t *box_end, uint32_t *blockcnt, uint32_t *partial, uint32_t *total,
-                       const uint32_t *sort_err, TreeSummary *sum, hipStream_t st)
+                       const uint32_t *sort_err, TreeSummary *sum, const Caps *check, hipStream_t st)
 {
     const int nblk = tree_blocks(ntot);
     k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask, box_end, blockcnt, nblk, &sum->halt);
     launch_scan(blockcnt, (kMaxLevel + 1) * nblk, partial, total, st);
-    k_tree_summary<<<1, 64, 0, st>>>(blockcnt, nblk, total, sort_err, sum);
+    k_tree_summary<<<1, 64, 0, st>>>(blockcnt, nblk, total, sort_err, sum, check ? *check : Caps{}, check ? 1 : 0);
 }
 
 void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
@@ -852,10 +872,11 @@ int vlist_blocks(int nbox) { return ceil_div(nbox, kVBoxes); }
 
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
                   int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
-                  int32_t *parent_oct, uint32_t *l2l_cnt, int32_t *l2l_list, uint32_t *item_off, int32_t *src_items,
-                  int32_t *cuts, uint32_t *scan_part, uint32_t *n_items, hipStream_t st)
+                  int32_t *parent_oct, uint32_t *l2l_cnt, int32_t *l2l_list, const ZeroRegions &zr,
+                  uint32_t *item_off, int32_t *src_items, int32_t *cuts, uint32_t *scan_part, uint32_t *n_items,
+                  hipStream_t st)
 {
-    k_oct_tables<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, child_oct, parent_oct, l2l_cnt, l2l_list, nbox);
+    k_oct_tables<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, child_oct, parent_oct, l2l_cnt, l2l_list, nbox, zr);
     k_colleagues<<<ceil_div(nbox * kNeigh, 256), 256, 0, st>>>(bt, sum, coll);
     k_vlist<<<vlist_blocks(nbox), 256, 0, st>>>(bt, sum, coll, child_oct, vtab, v_blk);
     k_nearlist<<<nbox, 64, 0, st>>>(bt, sum, coll, stride, near, near_cnt, item_off, src_items, cuts, near_pairs);

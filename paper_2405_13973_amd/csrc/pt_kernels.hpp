@@ -35,7 +35,9 @@ void launch_zero_regions(const ZeroRegions &z, hipStream_t st);
 // halt (nullable, here and below): a run-state word; once set, nothing is done.
 void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int nc, int do_drift,
                        unsigned long long *bbox, const int32_t *halt, hipStream_t st);
-void launch_root(unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st);
+// Root cubes from the bounding boxes (which it empties again); it also
+// zeroes the regions of zr (64-bit words).
+void launch_root(unsigned long long *bbox, int nc, RootCube *roots, const ZeroRegions &zr, hipStream_t st);
 void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCube *roots, int ntot, uint64_t *keys,
                  uint32_t *vals, const int32_t *halt, hipStream_t st);
 // beams: some crystal of the batch uses the beam-mode laser
@@ -98,9 +100,11 @@ void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint3
 int tree_blocks(int ntot);
 // box_end: ntot x (kMaxLevel + 1) ints, the end of every box at its first ion
 // (filled by launch_tree_count, read by launch_tree_build).
+// check (nullable): capacities the tree must fit, else the run halts (a
+// queued step: the summary then halts the run).
 void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
                        int32_t *box_end, uint32_t *blockcnt, uint32_t *partial, uint32_t *total,
-                       const uint32_t *sort_err, TreeSummary *sum, hipStream_t st);
+                       const uint32_t *sort_err, TreeSummary *sum, const Caps *check, hipStream_t st);
 void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
                        const uint32_t *rep_mask, const int32_t *box_end, const uint32_t *scanned, const BoxTable &bt,
                        const TreeSummary *sum, int nbox, hipStream_t st);
@@ -116,10 +120,12 @@ int vlist_blocks(int nbox);
 // l2l_cnt must be zero beforehand.
 constexpr int kL2LCounts = 8 * (kMaxLevel + 1);
 static_assert(kL2LCounts % 2 == 0, "L2L counts are cleared as 64-bit words");
+// zr: 64-bit words to zero on the way (the first kernel clears them).
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
                   int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
-                  int32_t *parent_oct, uint32_t *l2l_cnt, int32_t *l2l_list, uint32_t *item_off, int32_t *src_items,
-                  int32_t *cuts, uint32_t *scan_part, uint32_t *n_items, hipStream_t st);
+                  int32_t *parent_oct, uint32_t *l2l_cnt, int32_t *l2l_list, const ZeroRegions &zr,
+                  uint32_t *item_off, int32_t *src_items, int32_t *cuts, uint32_t *scan_part, uint32_t *n_items,
+                  hipStream_t st);
 // cuts (stride per box): first near range of each source item of a leaf.
 void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *near_cnt, int stride,
                       const uint32_t *item_off, const int32_t *src_items, const int32_t *cuts, int4 *work,
@@ -170,11 +176,10 @@ template <typename T>
 void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, int p, int nbox, const T *L,
                 const T *rec, const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals,
                 double *E, double *phi, int leaf_size, hipStream_t st);
-// Capacity checks of a queued evaluation: after the tree count (boxes,
-// levels; a sort failure also halts), and after the lists (near-field items
-// in total[1], M2L pairs in total[2]).  Each sets sum->halt when a count
-// exceeds its capacity.
-void launch_cap_check_tree(TreeSummary *sum, const Caps &cap, hipStream_t st);
+// Capacity check of a queued evaluation after the lists (near-field items
+// in total[1], M2L pairs in total[2]): sets sum->halt when a count exceeds
+// its capacity.  (Boxes and levels are checked by the tree summary, see
+// launch_tree_count; a sort failure also halts there.)
 void launch_cap_check_lists(TreeSummary *sum, const uint32_t *total, const Caps &cap, hipStream_t st);
 // Starts a run: halt = 0, fail_step = -1.
 void launch_run_reset(TreeSummary *sum, hipStream_t st);

@@ -613,25 +613,25 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "scan_part", sizeof(uint32_t) * (scan_partials(scan_n) + 1), &scan_part));
     PT_TRY(ws_get(ctx, "sp", sizeof(double) * 3 * ntot, &sp));
     PT_TRY(ws_get(ctx, "sum", sizeof(TreeSummary), &dsum));
-    launch_root(bbox, nc, roots, st);
-    launch_keys(b.d_desc, b.ion_crystal, roots, ntot, k0, v0, &dsum->halt, st);
     int cbits = 0;
     while ((1 << cbits) < nc) ++cbits;
     const int passes = (48 + cbits + 7) / 8;
     uint32_t *rstate;
     PT_TRY(ws_get(ctx, "radix_state", sizeof(uint32_t) * radix_state_words(ntot), &rstate));
     const uint32_t *sort_err = nullptr;
-    // the sort's counters and the L2L bucket counts start at zero
     uint32_t *l2l_cnt;
     PT_TRY(ws_get(ctx, "l2l_cnt", sizeof(uint32_t) * kL2LCounts, &l2l_cnt));
     {
+        // the root-cube kernel also zeroes the sort's counters and the L2L
+        // bucket counts
         ZeroRegions zr{};
         zr.p[0] = (uint64_t *)rstate;
         zr.n[0] = passes <= 8 ? radix_state_zero_words() / 2 : 0;
         zr.p[1] = (uint64_t *)l2l_cnt;
         zr.n[1] = kL2LCounts / 2;
-        launch_zero_regions(zr, st);
+        launch_root(bbox, nc, roots, zr, st);
     }
+    launch_keys(b.d_desc, b.ion_crystal, roots, ntot, k0, v0, &dsum->halt, st);
     // A queued step sorts by the top digits only (the Morton levels down to
     // kSortTopLevels and the crystal) and orders each run of equal top digits
     // by (key, value): the same order as the full sort while every run is
@@ -655,11 +655,10 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         }
     }
     launch_gather(b.d_desc, b.ion_crystal, v0, ntot, sp, &dsum->halt, st);
-    launch_tree_count(b.d_desc, k0, ntot, s, rep, box_end, bcnt, scan_part, total, sort_err, dsum, st);
+    launch_tree_count(b.d_desc, k0, ntot, s, rep, box_end, bcnt, scan_part, total, sort_err, dsum, queued, st);
     Caps cap{};
     if (queued) {
-        cap = *queued;
-        launch_cap_check_tree(dsum, cap, st);
+        cap = *queued;  // the tree summary has checked the tree against it
     } else {
         PT_HIP(hipMemcpyAsync(ctx->h_sum, dsum, sizeof(TreeSummary), hipMemcpyDeviceToHost, st));
         PT_HIP(hipStreamSynchronize(st));
@@ -737,8 +736,20 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     uint32_t *m2l_pcnt, *m2l_cnt_ob;
     PT_TRY(ws_get(ctx, "m2l_pcnt", sizeof(uint32_t) * (size_t)nbox, &m2l_pcnt));
     PT_TRY(ws_get(ctx, "m2l_cnt_ob", sizeof(uint32_t) * (size_t)m2l_ops() * nbox, &m2l_cnt_ob));
-    launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, v_blk, near_pairs, child_oct, parent_oct, l2l_cnt,
-                 l2l_list, item_off, src_items, cuts, scan_part, total + 1, st);
+    int32_t *p2p_queue;
+    PT_TRY(ws_get(ctx, "p2p_queue", sizeof(uint64_t), &p2p_queue));
+    {
+        // zeroed by the list builders: the zero rows of M and L (read for
+        // absent sources) and the near-field item queue
+        ZeroRegions zr{};
+        zr.p[0] = (uint64_t *)((char *)M + esz * Kp * (size_t)nbox);
+        zr.p[1] = (uint64_t *)((char *)L + esz * Kp * (size_t)nbox);
+        zr.p[2] = (uint64_t *)p2p_queue;
+        zr.n[0] = zr.n[1] = (int)(esz * Kp / 8);
+        zr.n[2] = 1;
+        launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, v_blk, near_pairs, child_oct, parent_oct,
+                     l2l_cnt, l2l_list, zr, item_off, src_items, cuts, scan_part, total + 1, st);
+    }
     // M2L pairs: counted and scanned here, so that their number comes back
     // with the near-field item count
     launch_m2l_count(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, scan_part, total + 2, st);
@@ -752,21 +763,11 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         PT_HIP(hipMemcpyAsync(ctx->h_counters, total + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         PT_HIP(hipEventRecord(ctx->ev_read, st));
     }
-    int32_t *p2p_queue;
     void *xl_part;
     const int ngroup = m2l_groups(0);
-    PT_TRY(ws_get(ctx, "p2p_queue", sizeof(uint64_t), &p2p_queue));
     PT_TRY(ws_get(ctx, "xl_part", esz * Kp * (size_t)nbox * ngroup, (char **)&xl_part));
     mark(ctx, 1);
     const Tables &tb = ctx->tables;
-    // the zero rows of M and L and the near-field item queue, in one launch
-    ZeroRegions zr{};
-    zr.p[0] = (uint64_t *)((char *)M + esz * Kp * (size_t)nbox);
-    zr.p[1] = (uint64_t *)((char *)L + esz * Kp * (size_t)nbox);
-    zr.p[2] = (uint64_t *)p2p_queue;
-    zr.n[0] = zr.n[1] = (int)(esz * Kp / 8);
-    zr.n[2] = 1;
-    launch_zero_regions(zr, st);
     if (!queued) {
         PT_HIP(hipEventSynchronize(ctx->ev_read));
         cap.items = (int)((uint32_t *)ctx->h_counters)[0];
