@@ -637,8 +637,12 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
 
 // Far field (L2P) of every ion of a leaf plus its near-field item partials,
 // added in item order.  Writes the field per unit charge in batch order; with
-// POT also the potential per unit charge (sum 1/r) into PHI.
-template <typename T, bool POT>
+// POT also the potential per unit charge (sum 1/r) into PHI.  MODE 0 does
+// both; MODE 1 only the far field (stored in E / PHI), so that it can run
+// before the near field has finished; MODE 2 then adds the partials to the
+// stored values.  The FP64 values and the order of the additions are the
+// same in both ways.
+template <typename T, bool POT, int MODE>
 __global__ __launch_bounds__(256) void k_far(BoxTable bt, const double *__restrict__ sp, int ntot, int p, int Kp,
                                             const T *__restrict__ L, const T *__restrict__ rec,
                                             const uint32_t *__restrict__ item_off,
@@ -653,27 +657,42 @@ __global__ __launch_bounds__(256) void k_far(BoxTable bt, const double *__restri
     if (sum->halt || b >= sum->nbox || !bt.leaf[b]) return;
     const double4 g = bt.geo[b];
     const double ih = 1.0 / g.w;
-    for (int i = threadIdx.x; i < kRecFields * kq(p); i += blockDim.x) rec_s[i] = rec[i];
-    for (int i = threadIdx.x; i < Kp; i += blockDim.x) Lb[i] = L[(size_t)b * Kp + i];
-    __syncthreads();
+    if constexpr (MODE != 2) {
+        for (int i = threadIdx.x; i < kRecFields * kq(p); i += blockDim.x) rec_s[i] = rec[i];
+        for (int i = threadIdx.x; i < Kp; i += blockDim.x) Lb[i] = L[(size_t)b * Kp + i];
+        __syncthreads();
+    }
     const int si = src_items[b];
     const uint32_t base = item_off[b];
     for (int k = bt.begin[b] + threadIdx.x; k < bt.end[b]; k += blockDim.x) {
         const int tl = k - bt.begin[b];
-        const double xd = sp[k], yd = sp[ntot + k], zd = sp[2 * ntot + k];
-        T ex, ey, ez, ev = 0;
-        const T ux = (T)((xd - g.x) * ih), uy = (T)((yd - g.y) * ih), uz = (T)((zd - g.z) * ih);
-        if constexpr (POT) l2p_field_pot<T>(p, Lb, rec_s, ux, uy, uz, ex, ey, ez, ev);
-        else l2p_field<T>(p, Lb, rec_s, ux, uy, uz, ex, ey, ez);
-        double fx = (double)ex * ih * ih, fy = (double)ey * ih * ih, fz = (double)ez * ih * ih, fv = (double)ev * ih;
-        const T *pp = part + ((size_t)(base + (tl >> 6) * si) * 64 + (tl & 63)) * NC;
-        for (int j = 0; j < si; ++j, pp += 64 * NC) {
-            fx += (double)pp[0];
-            fy += (double)pp[1];
-            fz += (double)pp[2];
-            if constexpr (POT) fv += (double)pp[3];
-        }
         const int gi = (int)vals[k];
+        double fx, fy, fz, fv = 0.0;
+        if constexpr (MODE == 2) {
+            fx = E[gi];
+            fy = E[ntot + gi];
+            fz = E[2 * ntot + gi];
+            if constexpr (POT) fv = PHI[gi];
+        } else {
+            const double xd = sp[k], yd = sp[ntot + k], zd = sp[2 * ntot + k];
+            T ex, ey, ez, ev = 0;
+            const T ux = (T)((xd - g.x) * ih), uy = (T)((yd - g.y) * ih), uz = (T)((zd - g.z) * ih);
+            if constexpr (POT) l2p_field_pot<T>(p, Lb, rec_s, ux, uy, uz, ex, ey, ez, ev);
+            else l2p_field<T>(p, Lb, rec_s, ux, uy, uz, ex, ey, ez);
+            fx = (double)ex * ih * ih;
+            fy = (double)ey * ih * ih;
+            fz = (double)ez * ih * ih;
+            fv = (double)ev * ih;
+        }
+        if constexpr (MODE != 1) {
+            const T *pp = part + ((size_t)(base + (tl >> 6) * si) * 64 + (tl & 63)) * NC;
+            for (int j = 0; j < si; ++j, pp += 64 * NC) {
+                fx += (double)pp[0];
+                fy += (double)pp[1];
+                fz += (double)pp[2];
+                if constexpr (POT) fv += (double)pp[3];
+            }
+        }
         E[gi] = fx;
         E[ntot + gi] = fy;
         E[2 * ntot + gi] = fz;
@@ -808,17 +827,26 @@ size_t near_lds_bytes()
 template <typename T>
 void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, int p, int nbox, const T *L,
                 const T *rec, const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals,
-                double *E, double *phi, int leaf_size, hipStream_t st)
+                double *E, double *phi, int leaf_size, int mode, hipStream_t st)
 {
     // one thread per ion of a leaf where the leaf size allows
     const int tb = std::min(256, std::max(64, (leaf_size + 63) / 64 * 64));
     if (nbox <= 0) return;
-    if (phi)
-        k_far<T, true><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E, phi,
-                                            sum);
-    else
-        k_far<T, false><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E,
-                                             nullptr, sum);
+#define PT_FAR(M)                                                                                                   \
+    if (phi)                                                                                                        \
+        k_far<T, true, M><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E, \
+                                               phi, sum);                                                           \
+    else                                                                                                            \
+        k_far<T, false, M><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals,  \
+                                                E, nullptr, sum);
+    if (mode == 1) {
+        PT_FAR(1)
+    } else if (mode == 2) {
+        PT_FAR(2)
+    } else {
+        PT_FAR(0)
+    }
+#undef PT_FAR
 }
 
 #define PT_INST(T)                                                                                                  \
@@ -833,7 +861,7 @@ void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, in
                                  const int4 *, const uint32_t *, int, T *, bool, int, int *, hipStream_t);         \
     template void launch_far<T>(const BoxTable &, const TreeSummary *, const double *, int, int, int, const T *,     \
                                 const T *, const uint32_t *, const int32_t *, const T *, const uint32_t *, double *, \
-                                double *, int, hipStream_t);
+                                double *, int, int, hipStream_t);
 PT_INST(float)
 PT_INST(double)
 #undef PT_INST

@@ -172,10 +172,12 @@ constexpr int kNearPerCUEarly = 3;
 size_t near_lds_bytes();
 // Far field (L2P) + the item partials per ion into E (batch order); with phi
 // non-null also the potential per unit charge (part then holds 4 components).
+// mode 0: both; 1: the far field only (into E / phi); 2: adds the partials to
+// what mode 1 stored (the same values as mode 0).
 template <typename T>
 void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, int p, int nbox, const T *L,
                 const T *rec, const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals,
-                double *E, double *phi, int leaf_size, hipStream_t st);
+                double *E, double *phi, int leaf_size, int mode, hipStream_t st);
 // Capacity check of a queued evaluation after the lists (near-field items
 // in total[1], M2L pairs in total[2]): sets sum->halt when a count exceeds
 // its capacity.  (Boxes and levels are checked by the tree summary, see

@@ -842,11 +842,18 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         launch_m2l_sum<T>(dsum, nbox, Kp, m2l_pcnt, total + 2, (const T *)m2l_R, (T *)L, st);
         launch_downward<T>(bt, dsum, p, cap, l2l, tb.oct_slots, parent_oct, l2l_cnt, l2l_list, (T *)L, st);
         mark(ctx, 4);
-        if (!concurrent) PT_TRY(near_field());
+        if (!concurrent) {
+            PT_TRY(near_field());
+        } else {
+            // beside the near field, the far field of every ion is evaluated
+            // before the join and the near-field partials added after it
+            launch_far<T>(bt, dsum, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0,
+                          E, phi, s, 1, st);
+        }
         mark(ctx, 5);
         if (concurrent) PT_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
         launch_far<T>(bt, dsum, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E,
-                      phi, s, st);
+                      phi, s, concurrent ? 2 : 0, st);
         return PT_OK;
     };
     PT_TRY(fp.precision == 1 ? run(float(0)) : run(double(0)));
