@@ -122,9 +122,11 @@ struct pt_ctx {
     int near_concurrent = -1;  // -1: by leaf size; 0 / 1: forced (PT_NEAR_CONCURRENT)
     int near_per_cu = 0;  // near-field workgroups per CU beside the far field (PT_NEAR_PER_CU; 0: by schedule)
     int near_early = -1;  // -1: by precision; 0 / 1: forced (PT_NEAR_EARLY): near field forks before the upward pass
-    bool partial_sort = true;  // queued steps sort by the top digits and refine (PT_PARTIAL_SORT=0: all digits)
-    std::vector<pt_crystal *> psort_off_batch;  // batch whose queued steps sort by all digits (a run overflowed)
-    int64_t psort_off_ntot = -1;
+    // first Morton digit the sort of a queued step orders by (the runs of
+    // equal higher digits are then refined): starts at the top kSortTopLevels
+    // levels, one digit lower after every run that is too long to refine, 0 =
+    // the full sort (PT_PARTIAL_SORT=0 starts there)
+    int psort_first = (48 - 3 * kSortTopLevels) / 8;
     uint64_t budget = 0, used = 0;
     int live = 0;
     int32_t *d_nonfinite = nullptr;  // set by any kick of this context that produces a non-finite value
@@ -636,10 +638,10 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     // kSortTopLevels and the crystal) and orders each run of equal top digits
     // by (key, value): the same order as the full sort while every run is
     // short, which holds unless very many ions share a cell of that level; a
-    // longer run halts the step, and it is run again with the full sort.
-    const bool partial = queued && ctx->partial_sort &&
-                         !(ctx->psort_off_batch == b.cs && ctx->psort_off_ntot == (int64_t)ntot);
-    const int first = partial ? (48 - 3 * kSortTopLevels) / 8 : 0;
+    // longer run halts the step, which is run again, and the context's later
+    // queued steps sort by one digit more.
+    const int first = queued ? ctx->psort_first : 0;
+    const bool partial = first > 0;
     if (passes <= 8) {
         if (launch_radix_sort(k0, v0, k1, v1, ntot, passes, first, rstate, &dsum->halt, st) == 1) {
             std::swap(k0, k1);
@@ -969,7 +971,8 @@ static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
     if (const char *e = getenv("PT_NEAR_CONCURRENT")) ctx->near_concurrent = atoi(e) ? 1 : 0;
     if (const char *e = getenv("PT_NEAR_PER_CU")) ctx->near_per_cu = std::max(1, std::min(8, atoi(e)));
     if (const char *e = getenv("PT_NEAR_EARLY")) ctx->near_early = atoi(e) ? 1 : 0;
-    if (const char *e = getenv("PT_PARTIAL_SORT")) ctx->partial_sort = atoi(e) != 0;
+    if (const char *e = getenv("PT_PARTIAL_SORT"))
+        if (!atoi(e)) ctx->psort_first = 0;
     if (const char *e = getenv("PT_QUEUED_STEPS")) ctx->no_queue = atoi(e) == 0;
     if (const char *e = getenv("PT_CAPS_TIGHT")) ctx->tight_caps = atoi(e) != 0;
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
@@ -1409,6 +1412,18 @@ pt_status pt_compute_forces_noalloc(pt_crystal *c, double *F_dev)
 // valid capacities measures its counts (two host waits); the following steps
 // are queued on capacities grown from them, with no host wait.  The outcome
 // is read back by settle() at the context's next call.
+// Whether `sub` is `all` with some crystals left out (order kept).
+static bool ordered_subset(const std::vector<pt_crystal *> &sub, const std::vector<pt_crystal *> &all)
+{
+    size_t j = 0;
+    for (pt_crystal *c : sub) {
+        while (j < all.size() && all[j] != c) ++j;
+        if (j == all.size()) return false;
+        ++j;
+    }
+    return true;
+}
+
 static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, const int64_t *n_steps)
 {
     int64_t kmax = 0;
@@ -1480,8 +1495,11 @@ static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, co
         PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * bbox_words(nc), &bbox));
         PT_TRY(ws_get(ctx, "E", sizeof(double) * 3 * (size_t)b.ntot, &E));
         launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, nc, 1, bbox, fmm ? &dsum->halt : nullptr, ctx->stream);
-        const bool queued = fmm && ctx->caps_ok && ctx->caps_batch == b.cs && ctx->caps_ntot == b.ntot &&
-                            same_force(ctx->caps_force, fp);
+        // queued on the capacities measured for this batch or for one it is
+        // part of (crystals that finished their steps drop out: every count a
+        // capacity bounds is a sum or maximum over the crystals)
+        const bool queued = fmm && ctx->caps_ok && b.ntot <= ctx->caps_ntot && same_force(ctx->caps_force, fp) &&
+                            ordered_subset(b.cs, ctx->caps_batch);
         ctx->eval_halted = false;
         PT_TRY(eval_field(ctx, b, fp, E, nullptr, queued ? &ctx->caps : nullptr));
         if (fmm) (queued ? ctx->n_queued : ctx->n_measured)++;
@@ -1527,10 +1545,7 @@ static pt_status settle(pt_ctx *ctx)
         }
         ctx->caps_ok = false;
         if (ts.refine_overflow) {
-            // the batch's queued steps sort by all digits from now on
-            ctx->psort_off_batch = pd.cs;
-            ctx->psort_off_ntot = 0;
-            for (pt_crystal *c : pd.cs) ctx->psort_off_ntot += c->n;
+            ctx->psort_first = std::max(0, ctx->psort_first - 1);  // sort by one more digit from now on
         } else {
             ctx->caps_slack = std::min(4.0, ctx->caps_slack * 1.5);
         }

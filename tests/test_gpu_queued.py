@@ -77,8 +77,9 @@ def test_sort_refine_overflow_reruns_with_the_full_sort(monkeypatch):
     """Queued steps sort by the top Morton levels and order each run of equal
     top digits by (key, index).  A far outlier stretches the root cube so that
     the whole cluster shares a few cells at that level: the runs are too long,
-    the first queued step halts and is run again with the full sort, and the
-    states equal those of measured steps and of the full sort throughout."""
+    the queued step halts and is run again, later queued steps sort by more
+    digits, and the states equal those of measured steps and of the full sort
+    throughout."""
     g = inputs.rng(81)
     pos = inputs.uniform_ball(3000, 1e-4, g)
     pos[0] = (5e-2, 0.0, 0.0)
