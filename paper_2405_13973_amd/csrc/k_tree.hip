@@ -212,13 +212,26 @@ __global__ __launch_bounds__(kSortTB) void k_radix_prepare(const uint64_t *__res
         if (cnt[p][tid]) atomicAdd(&ghist[p * 256 + tid], cnt[p][tid]);
 }
 
+// Sorted position of slot k: that of batch ion g = vals[k].
+__device__ inline void gather_slot(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal,
+                                   int ntot, double *__restrict__ sp, int k, uint32_t g)
+{
+    const CrystalDev &cd = cs[ion_crystal[g]];
+    const int i = (int)g - cd.ion_off;
+    sp[k] = cd.mid[i];
+    sp[ntot + k] = cd.mid[cd.n + i];
+    sp[2 * ntot + k] = cd.mid[2 * cd.n + i];
+}
+
 // Completes a stable sort by key >> shift: each run of equal key >> shift is
 // ordered by (key, value) by the thread at its first slot (insertion sort;
 // runs hold one or two slots at the sizes of interest).  The order a full
 // sort gives -- by key, equal keys by value, values ascending on entry -- is
 // what this produces, since the stable sort kept each run in value order.
+// The same thread then gathers the sorted positions of its run's slots.
 __global__ void k_sort_refine(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, int n, int shift,
-                              TreeSummary *__restrict__ sum)
+                              TreeSummary *__restrict__ sum, const CrystalDev *__restrict__ cs,
+                              const int32_t *__restrict__ ion_crystal, double *__restrict__ sp)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n || sum->halt) return;
@@ -244,6 +257,7 @@ __global__ void k_sort_refine(uint64_t *__restrict__ keys, uint32_t *__restrict_
         keys[j + 1] = kk;
         vals[j + 1] = vv;
     }
+    for (int i = k; i < e; ++i) gather_slot(cs, ion_crystal, n, sp, i, vals[i]);
 }
 
 __global__ __launch_bounds__(kSortTB) void k_radix_pass(const uint64_t *__restrict__ kin,
@@ -343,12 +357,7 @@ __global__ void k_gather(const CrystalDev *__restrict__ cs, const int32_t *__res
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ntot || (halt && *halt)) return;
-    const int g = (int)vals[k];
-    const CrystalDev &cd = cs[ion_crystal[g]];
-    const int i = g - cd.ion_off;
-    sp[k] = cd.mid[i];
-    sp[ntot + k] = cd.mid[cd.n + i];
-    sp[2 * ntot + k] = cd.mid[2 * cd.n + i];
+    gather_slot(cs, ion_crystal, ntot, sp, k, vals[k]);
 }
 
 // --------------------------------------------------------------- octree
@@ -842,9 +851,10 @@ int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, in
     return (passes - first) % 2;  // 1: the result is in (k1, v1)
 }
 
-void launch_sort_refine(uint64_t *keys, uint32_t *vals, int n, int shift, TreeSummary *sum, hipStream_t st)
+void launch_sort_refine(uint64_t *keys, uint32_t *vals, int n, int shift, TreeSummary *sum, const CrystalDev *cs,
+                        const int32_t *ion_crystal, double *sp, hipStream_t st)
 {
-    if (n > 0) k_sort_refine<<<ceil_div(n, 256), 256, 0, st>>>(keys, vals, n, shift, sum);
+    if (n > 0) k_sort_refine<<<ceil_div(n, 256), 256, 0, st>>>(keys, vals, n, shift, sum, cs, ion_crystal, sp);
 }
 
 int tree_blocks(int ntot) { return ceil_div(ntot, 256); }

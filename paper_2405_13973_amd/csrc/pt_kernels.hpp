@@ -85,14 +85,16 @@ constexpr int radix_state_err() { return 8 * 256 + 8; }
 int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int n, int passes, int first,
                       uint32_t *state, const int32_t *halt, hipStream_t st);
 // After a stable sort by key >> shift: orders every run of equal key >> shift
-// by (key, value), which completes the full sort.  A run longer than
-// kRefineMax sets sum->refine_overflow and halts the run instead.
+// by (key, value), which completes the full sort, and gathers the sorted
+// positions as launch_gather does.  A run longer than kRefineMax sets
+// sum->refine_overflow and halts the run instead.
 constexpr int kRefineMax = 32;
 // Morton levels (3 bits each) by which the sort of a queued step orders
 // before the runs are refined: whole 8-bit digits.
 constexpr int kSortTopLevels = 8;
 static_assert((3 * kSortTopLevels) % 8 == 0, "the top levels must fill whole digits");
-void launch_sort_refine(uint64_t *keys, uint32_t *vals, int n, int shift, TreeSummary *sum, hipStream_t st);
+void launch_sort_refine(uint64_t *keys, uint32_t *vals, int n, int shift, TreeSummary *sum, const CrystalDev *cs,
+                        const int32_t *ion_crystal, double *sp, hipStream_t st);
 void launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, int n, int shift,
                        uint32_t *hist, uint32_t *partial, hipStream_t st);
 void launch_gather(const CrystalDev *cs, const int32_t *ion_crystal, const uint32_t *vals, int ntot, double *sp,

@@ -640,14 +640,14 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     // short, which holds unless very many ions share a cell of that level; a
     // longer run halts the step, which is run again, and the context's later
     // queued steps sort by one digit more.
-    const int first = queued ? ctx->psort_first : 0;
+    const int first = queued && passes <= 8 ? ctx->psort_first : 0;
     const bool partial = first > 0;
     if (passes <= 8) {
         if (launch_radix_sort(k0, v0, k1, v1, ntot, passes, first, rstate, &dsum->halt, st) == 1) {
             std::swap(k0, k1);
             std::swap(v0, v1);
         }
-        if (partial) launch_sort_refine(k0, v0, ntot, 8 * first, dsum, st);
+        if (partial) launch_sort_refine(k0, v0, ntot, 8 * first, dsum, b.d_desc, b.ion_crystal, sp, st);
         sort_err = rstate + radix_state_err();
     } else {
         for (int ps = 0; ps < passes; ++ps) {
@@ -656,7 +656,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             std::swap(v0, v1);
         }
     }
-    launch_gather(b.d_desc, b.ion_crystal, v0, ntot, sp, &dsum->halt, st);
+    if (!partial) launch_gather(b.d_desc, b.ion_crystal, v0, ntot, sp, &dsum->halt, st);  // else done by the refine
     launch_tree_count(b.d_desc, k0, ntot, s, rep, box_end, bcnt, scan_part, total, sort_err, dsum, queued, st);
     Caps cap{};
     if (queued) {

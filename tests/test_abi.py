@@ -51,3 +51,18 @@ def test_numeric_status_reaches_the_caller():
             native._check(code)
         assert e.value.code == code and name in str(e.value)
     native._check(native.PT_OK)
+
+
+def test_library_resolves_its_own_symbols():
+    """Every function of the library's own namespace is defined in it (a
+    declaration that drifted from its definition would leave an undefined
+    symbol that only fails when the library is loaded and called)."""
+    import shutil
+    import subprocess
+
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm is not available")
+    out = subprocess.run([nm, "-D", "--undefined-only", native.LIB_PATH], capture_output=True, text=True, check=True)
+    own = [line for line in out.stdout.splitlines() if "_ZN2pt" in line]
+    assert not own, own
