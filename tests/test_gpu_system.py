@@ -315,19 +315,33 @@ def test_non_finite_state_is_reported_after_the_step():
 # ---------------------------------------------------------------- schedules
 @pytest.mark.parametrize("leaf", [32, 256])
 def test_near_field_schedules_are_bit_identical(leaf, monkeypatch):
-    """The near field runs beside M2L on a second stream (a capped grid taking work
-    items from a queue) or after it on the main stream (one workgroup per item);
-    every item writes its own partials, added in item order, so both schedules give
-    the same forces bit for bit, in both precisions."""
+    """The near field runs beside the far field on a second stream (a capped grid
+    taking work items from a queue; forked before or after the upward pass, the
+    far-field L2P then split around the join) or after it on the main stream (one
+    workgroup per item); every item writes its own partials, added in item order,
+    so every schedule gives the same forces, and the same states after queued
+    steps, bit for bit, in both precisions."""
     say(f"near-field schedules leaf {leaf}")
     cr = inputs.config3(n=30000)
+    settings = {"after": {"PT_NEAR_CONCURRENT": "0"},
+                "beside, early fork": {"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1"},
+                "beside, late fork": {"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "0"}}
     out = {}
-    for conc in ("0", "1"):
-        monkeypatch.setenv("PT_NEAR_CONCURRENT", conc)
+    for name, env in settings.items():
+        for k in ("PT_NEAR_CONCURRENT", "PT_NEAR_EARLY"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
         with native.Context(0) as c:
             for prec in ("mixed", "fp64"):
                 k = make(c, cr, "fmm", 11, leaf, prec)
-                out[(conc, prec)] = k.compute_forces()
+                F = k.compute_forces()
+                k.step(3)
+                out[(name, prec)] = (F, k.read_state())
                 k.destroy()
     for prec in ("mixed", "fp64"):
-        assert np.array_equal(out[("0", prec)], out[("1", prec)]), prec
+        F0, s0 = out[("after", prec)]
+        for name in settings:
+            F, st = out[(name, prec)]
+            assert np.array_equal(F0, F), (name, prec)
+            assert np.array_equal(s0["pos"], st["pos"]) and np.array_equal(s0["vel"], st["vel"]), (name, prec)
