@@ -58,12 +58,15 @@ __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t v0, uint64_t v1, i
 // Optional half drift of the state into the working copy (positions only
 // are copied without the drift), then per-crystal min/max of x, y, z
 // (ordered-integer atomics; min/max is exact, so the result does not depend
-// on the order).
+// on the order).  The regions of zr are zeroed on the way (grid-stride).
 __global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
                              int do_drift, unsigned long long *__restrict__ bbox_all, int bstride,
-                             const int32_t *__restrict__ halt)
+                             const int32_t *__restrict__ halt, ZeroRegions zr)
 {
     if (halt && *halt) return;  // a halted run: the same word for every workgroup
+    for (int r = 0; r < kZeroRegions; ++r)  // counters of the steps that follow start at zero
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < zr.n[r]; i += gridDim.x * blockDim.x)
+            zr.p[r][i] = 0ull;
     unsigned long long *bbox = bbox_all + (size_t)(blockIdx.x % kBBoxCopies) * bstride;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = g < ntot;
@@ -151,75 +154,21 @@ __global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *_
     }
 }
 
-// Root cube per crystal, in the exact operation order of the tree contract:
-// W = max extent (1e-9 m if zero), o = (lo + hi)/2 - W/2, S = 2^16 / W.
-// Resets the bounding box for its next use.
-__global__ void k_root(unsigned long long *__restrict__ bbox, int nc, int bstride, RootCube *__restrict__ roots,
-                       ZeroRegions zr)
+// Root cube of every crystal (one thread each).
+__global__ void k_roots(const unsigned long long *__restrict__ bbox, int nc, int bstride, RootCube *__restrict__ roots)
 {
-#pragma clang fp contract(off)
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    // the counters of the steps that follow start at zero (grid-stride)
-    for (int r = 0; r < kZeroRegions; ++r)
-        for (int i = c; i < zr.n[r]; i += gridDim.x * blockDim.x) zr.p[r][i] = 0ull;
-    if (c >= nc) return;
-    unsigned long long w[6];
-    for (int k = 0; k < 6; ++k) w[k] = bbox[6 * c + k];
-    for (int cp = 1; cp < kBBoxCopies; ++cp)
-        for (int k = 0; k < 6; ++k) {
-            const unsigned long long o = bbox[(size_t)cp * bstride + 6 * c + k];
-            w[k] = k < 3 ? (o < w[k] ? o : w[k]) : (o > w[k] ? o : w[k]);
-        }
-    double lo[3], hi[3];
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = ordered_to_dbl(w[d]);
-        hi[d] = ordered_to_dbl(w[3 + d]);
-    }
-    double W = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        const double e = hi[d] - lo[d];
-        if (e > W) W = e;
-    }
-    if (W == 0.0) W = 1e-9;
-    RootCube r;
-    for (int d = 0; d < 3; ++d) {
-        const double ctr = 0.5 * (lo[d] + hi[d]);
-        r.o[d] = ctr - 0.5 * W;
-    }
-    r.W = W;
-    r.S = 65536.0 / W;
-    r.pad[0] = r.pad[1] = r.pad[2] = 0.0;
-    roots[c] = r;
-    for (int cp = 0; cp < kBBoxCopies; ++cp)
-        for (int d = 0; d < 3; ++d) {
-            bbox[(size_t)cp * bstride + 6 * c + d] = ~0ull;
-            bbox[(size_t)cp * bstride + 6 * c + 3 + d] = 0ull;
-        }
+    if (c < nc) roots[c] = root_of(bbox, bstride, c);
 }
 
-// 64-bit sort key per ion: crystal index above a 48-bit Morton key of the
-// position quantised to the crystal's root cube (floor((x - o) S), clamped
-// to [0, 2^16 - 1]; subtract then multiply, never fused).
+// Sort keys and values of every ion (ion_sort_key).
 __global__ void k_keys(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal,
                        const RootCube *__restrict__ roots, int ntot, uint64_t *__restrict__ keys,
                        uint32_t *__restrict__ vals, const int32_t *__restrict__ halt)
 {
-#pragma clang fp contract(off)
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ntot || (halt && *halt)) return;
-    const int c = ion_crystal[g];
-    const CrystalDev &cd = cs[c];
-    const int i = g - cd.ion_off;
-    const int n = cd.n;
-    const RootCube r = roots[c];
-    uint32_t q[3];
-    for (int d = 0; d < 3; ++d) {
-        double f = floor((cd.mid[d * n + i] - r.o[d]) * r.S);
-        if (!(f >= 0.0)) f = 0.0;
-        if (f > 65535.0) f = 65535.0;
-        q[d] = (uint32_t)f;
-    }
-    keys[g] = ((uint64_t)c << 48) | morton3(q[0], q[1], q[2]);
+    keys[g] = ion_sort_key(cs, ion_crystal, roots, g);
     vals[g] = (uint32_t)g;
 }
 
@@ -542,16 +491,16 @@ void launch_zero_u64(uint64_t *p, int n, hipStream_t st)
 }
 
 void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int nc, int do_drift,
-                       unsigned long long *bbox, const int32_t *halt, hipStream_t st)
+                       unsigned long long *bbox, const int32_t *halt, const ZeroRegions &zr, hipStream_t st)
 {
     if (ntot > 0)
-        k_drift_bbox<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, do_drift, bbox, bbox_stride(nc),
-                                                          halt);
+        k_drift_bbox<<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, do_drift, bbox, bbox_stride(nc), halt,
+                                                          zr);
 }
 
-void launch_root(unsigned long long *bbox, int nc, RootCube *roots, const ZeroRegions &zr, hipStream_t st)
+void launch_roots(const unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st)
 {
-    k_root<<<ceil_div(nc, 64), 64, 0, st>>>(bbox, nc, bbox_stride(nc), roots, zr);
+    k_roots<<<ceil_div(nc, 64), 64, 0, st>>>(bbox, nc, bbox_stride(nc), roots);
 }
 
 void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCube *roots, int ntot, uint64_t *keys,
@@ -568,13 +517,7 @@ void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int nto
     else k_kick_drift<false><<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k);
 }
 
-// Capacity checks and the run reset (one thread each).
-__global__ void k_cap_check_lists(TreeSummary *__restrict__ sum, const uint32_t *__restrict__ total, Caps cap)
-{
-    if (sum->halt) return;
-    if (total[1] > (uint32_t)cap.items || total[2] > (uint32_t)cap.pairs) sum->halt = 1;
-}
-
+// The run reset (one thread).
 __global__ void k_run_reset(TreeSummary *__restrict__ sum)
 {
     sum->halt = 0;
@@ -582,11 +525,6 @@ __global__ void k_run_reset(TreeSummary *__restrict__ sum)
     sum->refine_overflow = 0;
 }
 
-
-void launch_cap_check_lists(TreeSummary *sum, const uint32_t *total, const Caps &cap, hipStream_t st)
-{
-    k_cap_check_lists<<<1, 1, 0, st>>>(sum, total, cap);
-}
 
 void launch_run_reset(TreeSummary *sum, hipStream_t st) { k_run_reset<<<1, 1, 0, st>>>(sum); }
 

@@ -72,9 +72,18 @@ __global__ __launch_bounds__(kScanTB) void k_scan_reduce(const uint32_t *__restr
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
+__device__ void scan_down_chunk(uint32_t *__restrict__ a, int n, const uint32_t *__restrict__ partial,
+                                uint32_t *__restrict__ total);
+
 __global__ __launch_bounds__(kScanTB) void k_scan_down(uint32_t *__restrict__ a, int n,
                                                        const uint32_t *__restrict__ partial,
                                                        uint32_t *__restrict__ total)
+{
+    scan_down_chunk(a, n, partial, total);
+}
+
+__device__ void scan_down_chunk(uint32_t *__restrict__ a, int n, const uint32_t *__restrict__ partial,
+                                uint32_t *__restrict__ total)
 {
     __shared__ uint32_t w[kScanTB / 64 + 1];
     // offset of this chunk: the sum of the chunk sums before it
@@ -187,8 +196,12 @@ constexpr int kMaxPasses = 8;
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagIncl = 2ull << 62, kFlagCount = (1ull << 62) - 1;
 constexpr int kSpinMax = 1 << 20;
 
-__global__ __launch_bounds__(kSortTB) void k_radix_prepare(const uint64_t *__restrict__ keys, int n, int passes,
-                                                           int first, uint32_t *__restrict__ ghist,
+// KEYS: the keys (and values) are computed here from the root cubes and
+// written out, rather than read.
+template <bool KEYS>
+__global__ __launch_bounds__(kSortTB) void k_radix_prepare(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                           KeySource src, int n, int passes, int first,
+                                                           uint32_t *__restrict__ ghist,
                                                            uint64_t *__restrict__ flags, int ntile,
                                                            const int32_t *__restrict__ halt)
 {
@@ -199,11 +212,25 @@ __global__ __launch_bounds__(kSortTB) void k_radix_prepare(const uint64_t *__res
         cnt[p][tid] = 0;
         flags[((size_t)p * ntile + blockIdx.x) * 256 + tid] = 0ull;
     }
+    if constexpr (KEYS) {
+        // the root cubes of the crystals of this tile (batch ions are in
+        // crystal order), before any key of the tile needs them
+        const int i0 = blockIdx.x * kSortTile, i1 = min(n, i0 + kSortTile) - 1;
+        const int c0 = src.ion_crystal[i0], c1 = src.ion_crystal[i1];
+        for (int c = c0 + tid; c <= c1; c += kSortTB) src.roots[c] = root_of(src.bbox, bbox_stride(src.nc), c);
+    }
     __syncthreads();
     for (int r = 0; r < kSortItems; ++r) {
         const int i = blockIdx.x * kSortTile + r * kSortTB + tid;
         if (i < n) {
-            const uint64_t key = keys[i];
+            uint64_t key;
+            if constexpr (KEYS) {
+                key = ion_sort_key(src.cs, src.ion_crystal, src.roots, i);
+                keys[i] = key;
+                vals[i] = (uint32_t)i;
+            } else {
+                key = keys[i];
+            }
             for (int p = first; p < passes; ++p) atomicAdd(&cnt[p][(key >> (8 * p)) & 255u], 1u);
         }
     }
@@ -447,15 +474,44 @@ __host__ __device__ inline uint32_t slot_box_levels(const uint64_t *__restrict__
     return mask;
 }
 
+// The tree summary from the scanned per-level counts (one thread): level
+// starts, box count, sort error; a queued step also checks the tree against
+// its capacities.
+__device__ void tree_summary(const uint32_t *__restrict__ scanned, int nblk, uint32_t nbox_total,
+                             const uint32_t *__restrict__ sort_err, TreeSummary *__restrict__ sum, const Caps &cap,
+                             int check)
+{
+    if (sum->halt) return;
+    const int32_t err = sort_err ? (int32_t)*sort_err : 0;
+    sum->sort_error = err;
+    int nlev = 0;
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        sum->level_start[l] = (int32_t)scanned[l * nblk];
+        if (l > 0 && sum->level_start[l] > sum->level_start[l - 1]) nlev = l;
+    }
+    const int32_t nbox = (int32_t)nbox_total;
+    sum->level_start[kMaxLevel + 1] = nbox;
+    sum->nbox = nbox;
+    if (nbox > sum->level_start[kMaxLevel]) nlev = kMaxLevel + 1;
+    // a queued step: boxes and levels must fit the capacities (a level
+    // holding more boxes than its grid covers is still covered, by striding;
+    // only the buffers sized by these counts can overflow), and the sort
+    // must have finished
+    if (check && (nbox > cap.nbox || nlev > cap.nlev || err != 0)) sum->halt = 1;
+}
+
 // For every sorted slot: the levels at which it is the first ion of an
 // existing box (bit l of rep_mask).
 __global__ __launch_bounds__(256) void k_tree_levels(const CrystalDev *__restrict__ cs,
                                                      const uint64_t *__restrict__ keys, int ntot, int leaf_size,
                                                      uint32_t *__restrict__ rep_mask, int32_t *__restrict__ box_end,
                                                      uint32_t *__restrict__ blockcnt, int nblk,
-                                                     const int32_t *__restrict__ halt)
+                                                     const int32_t *__restrict__ halt,
+                                                     unsigned long long *__restrict__ bbox, int bbox_n)
 {
     if (halt && *halt) return;
+    // the bounding boxes are read: emptied for the next drift (grid-stride)
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < bbox_n; i += gridDim.x * 256) bbox[i] = (i % 6) < 3 ? ~0ull : 0ull;
     // rep_mask[k]: the levels at which slot k is the first ion of a box;
     // box_end[k][l]: the end of that level-l box (written for those levels only);
     // blockcnt[l][block]: how many such slots of this block start a level-l box
@@ -483,23 +539,20 @@ __global__ void k_tree_summary(const uint32_t *__restrict__ scanned, int nblk, c
                                const uint32_t *__restrict__ sort_err, TreeSummary *__restrict__ sum, Caps cap,
                                int check)
 {
-    if (threadIdx.x != 0 || sum->halt) return;
-    const int32_t err = sort_err ? (int32_t)*sort_err : 0;
-    sum->sort_error = err;
-    int nlev = 0;
-    for (int l = 0; l <= kMaxLevel; ++l) {
-        sum->level_start[l] = (int32_t)scanned[l * nblk];
-        if (l > 0 && sum->level_start[l] > sum->level_start[l - 1]) nlev = l;
-    }
-    const int32_t nbox = (int32_t)*total;
-    sum->level_start[kMaxLevel + 1] = nbox;
-    sum->nbox = nbox;
-    if (nbox > sum->level_start[kMaxLevel]) nlev = kMaxLevel + 1;
-    // a queued step: boxes and levels must fit the capacities (a level
-    // holding more boxes than its grid covers is still covered, by striding;
-    // only the buffers sized by these counts can overflow), and the sort
-    // must have finished
-    if (check && (nbox > cap.nbox || nlev > cap.nlev || err != 0)) sum->halt = 1;
+    if (threadIdx.x == 0) tree_summary(scanned, nblk, *total, sort_err, sum, cap, check);
+}
+
+// The per-level counts in one scan chunk: scanned in place by one
+// workgroup, whose first thread then writes the summary (the scanned counts
+// and the total are this workgroup's own writes).
+__global__ __launch_bounds__(kScanTB) void k_scan_tree_summary(uint32_t *__restrict__ a, int nblk,
+                                                               uint32_t *__restrict__ total,
+                                                               const uint32_t *__restrict__ sort_err,
+                                                               TreeSummary *__restrict__ sum, Caps cap, int check)
+{
+    scan_down_chunk(a, (kMaxLevel + 1) * nblk, nullptr, total);
+    __syncthreads();
+    if (threadIdx.x == 0) tree_summary(a, nblk, *total, sort_err, sum, cap, check);
 }
 
 // Writes one box record per (slot, level) representative.
@@ -782,14 +835,23 @@ __global__ __launch_bounds__(64) void k_nearlist(BoxTable bt, const TreeSummary 
 // Work items {leaf, first target, first range, end range} at the scanned
 // offsets, one wave per leaf: item tc * si + j pairs target chunk tc with
 // source item j (ranges cut[j] .. cut[j + 1]).
-__global__ __launch_bounds__(64) void k_p2p_items(BoxTable bt, const TreeSummary *__restrict__ sum,
+__global__ __launch_bounds__(64) void k_p2p_items(BoxTable bt, TreeSummary *__restrict__ sum,
                                                   const int32_t *__restrict__ near_cnt, int stride,
                                                   const uint32_t *__restrict__ item_off,
                                                   const int32_t *__restrict__ src_items,
-                                                  const int32_t *__restrict__ cuts, int4 *__restrict__ work)
+                                                  const int32_t *__restrict__ cuts, int4 *__restrict__ work,
+                                                  const uint32_t *__restrict__ total, Caps cap, int check)
 {
     const int b = blockIdx.x;
-    if (sum->halt || b >= sum->nbox || !bt.leaf[b]) return;
+    if (sum->halt) return;
+    // a queued step: items and M2L pairs must fit their capacities; every
+    // workgroup reads the same counts, so none writes past the buffers (plain
+    // stores: every writer writes 1)
+    if (check && (total[1] > (uint32_t)cap.items || total[2] > (uint32_t)cap.pairs)) {
+        if (threadIdx.x == 0) sum->halt = 1;
+        return;
+    }
+    if (b >= sum->nbox || !bt.leaf[b]) return;
     const int32_t *cut = cuts + (size_t)b * stride;
     const int cnt = near_cnt[b], si = src_items[b];
     const int nt = bt.end[b] - bt.begin[b];
@@ -836,13 +898,17 @@ size_t radix_state_words(int n) { return (size_t)kMaxPasses * 256 + kMaxPasses +
                                         2 * (size_t)kMaxPasses * sort_blocks(n) * 256; }
 
 int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int n, int passes, int first,
-                      uint32_t *state, const int32_t *halt, hipStream_t st)
+                      uint32_t *state, const int32_t *halt, const KeySource *keys, hipStream_t st)
 {
     if (passes > kMaxPasses || first < 0 || first > passes || n <= 0) return -1;
     const int ntile = sort_blocks(n);
     uint32_t *ghist = state, *ctr = state + kMaxPasses * 256, *err = ctr + kMaxPasses;
     uint64_t *flags = (uint64_t *)(state + kMaxPasses * 256 + kMaxPasses + 2);  // 8-byte aligned
-    k_radix_prepare<<<ntile, kSortTB, 0, st>>>(k0, n, passes, first, ghist, flags, ntile, halt);
+    if (keys)
+        k_radix_prepare<true><<<ntile, kSortTB, 0, st>>>(k0, v0, *keys, n, passes, first, ghist, flags, ntile, halt);
+    else
+        k_radix_prepare<false><<<ntile, kSortTB, 0, st>>>(k0, v0, KeySource{}, n, passes, first, ghist, flags, ntile,
+                                                          halt);
     for (int p = first; p < passes; ++p) {
         const bool odd = (p - first) % 2;
         k_radix_pass<<<ntile, kSortTB, 0, st>>>(odd ? k1 : k0, odd ? v1 : v0, odd ? k0 : k1, odd ? v0 : v1, n, p, ghist,
@@ -861,12 +927,20 @@ int tree_blocks(int ntot) { return ceil_div(ntot, 256); }
 
 void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
                        int32_t *box_end, uint32_t *blockcnt, uint32_t *partial, uint32_t *total,
-                       const uint32_t *sort_err, TreeSummary *sum, const Caps *check, hipStream_t st)
+                       const uint32_t *sort_err, TreeSummary *sum, const Caps *check, unsigned long long *bbox,
+                       int nc, hipStream_t st)
 {
     const int nblk = tree_blocks(ntot);
-    k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask, box_end, blockcnt, nblk, &sum->halt);
-    launch_scan(blockcnt, (kMaxLevel + 1) * nblk, partial, total, st);
-    k_tree_summary<<<1, 64, 0, st>>>(blockcnt, nblk, total, sort_err, sum, check ? *check : Caps{}, check ? 1 : 0);
+    const int n = (kMaxLevel + 1) * nblk;
+    const Caps cap = check ? *check : Caps{};
+    k_tree_levels<<<nblk, 256, 0, st>>>(cs, keys, ntot, leaf_size, rep_mask, box_end, blockcnt, nblk, &sum->halt,
+                                        bbox, (int)bbox_words(nc));
+    if (scan_partials(n) == 1) {  // one chunk: the summary comes with the scan
+        k_scan_tree_summary<<<1, kScanTB, 0, st>>>(blockcnt, nblk, total, sort_err, sum, cap, check ? 1 : 0);
+        return;
+    }
+    launch_scan(blockcnt, n, partial, total, st);
+    k_tree_summary<<<1, 64, 0, st>>>(blockcnt, nblk, total, sort_err, sum, cap, check ? 1 : 0);
 }
 
 void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
@@ -893,11 +967,12 @@ void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t 
     launch_scan(item_off, nbox, scan_part, n_items, st);
 }
 
-void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *near_cnt, int stride,
+void launch_p2p_items(const BoxTable &bt, TreeSummary *sum, int nbox, const int32_t *near_cnt, int stride,
                       const uint32_t *item_off, const int32_t *src_items, const int32_t *cuts, int4 *work,
-                      hipStream_t st)
+                      const uint32_t *total, const Caps *check, hipStream_t st)
 {
-    k_p2p_items<<<nbox, 64, 0, st>>>(bt, sum, near_cnt, stride, item_off, src_items, cuts, work);
+    k_p2p_items<<<nbox, 64, 0, st>>>(bt, sum, near_cnt, stride, item_off, src_items, cuts, work, total,
+                                     check ? *check : Caps{}, check ? 1 : 0);
 }
 
 }  // namespace pt

@@ -19,11 +19,48 @@ void launch_ion_crystal(const CrystalDev *cs, int nc, int ntot, int32_t *ion_cry
 // Bounding boxes: kBBoxCopies copies of [crystal][6] ordered-integer words,
 // bbox_stride(nc) words apart (a multiple of 6 and of 128 bytes), so that the
 // atomics of different workgroups spread over separate cache lines; the
-// root-cube kernel reduces the copies.  The buffer holds bbox_words(nc) words.
+// root cubes reduce the copies.  The buffer holds bbox_words(nc) words.
+// launch_bbox_reset empties them; after an FMM evaluation's drift has filled
+// them, its tree-level kernel empties them again (once every reader is done).
 constexpr int kBBoxCopies = 16;
 constexpr int bbox_stride(int nc) { return (6 * nc + 47) / 48 * 48; }
 constexpr size_t bbox_words(int nc) { return (size_t)kBBoxCopies * bbox_stride(nc); }
 void launch_bbox_reset(unsigned long long *bbox, int nc, hipStream_t st);
+
+// Root cube of crystal c from its bounding-box copies, in the exact
+// operation order of the tree contract: W = max extent (1e-9 m if zero),
+// o = (lo + hi)/2 - W/2, S = 2^16 / W.
+__device__ inline RootCube root_of(const unsigned long long *__restrict__ bbox, int bstride, int c)
+{
+#pragma clang fp contract(off)
+    unsigned long long w[6];
+    for (int k = 0; k < 6; ++k) w[k] = bbox[6 * c + k];
+    for (int cp = 1; cp < kBBoxCopies; ++cp)
+        for (int k = 0; k < 6; ++k) {
+            const unsigned long long o = bbox[(size_t)cp * bstride + 6 * c + k];
+            w[k] = k < 3 ? (o < w[k] ? o : w[k]) : (o > w[k] ? o : w[k]);
+        }
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = ordered_to_dbl(w[d]);
+        hi[d] = ordered_to_dbl(w[3 + d]);
+    }
+    double W = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double e = hi[d] - lo[d];
+        if (e > W) W = e;
+    }
+    if (W == 0.0) W = 1e-9;
+    RootCube r;
+    for (int d = 0; d < 3; ++d) {
+        const double ctr = 0.5 * (lo[d] + hi[d]);
+        r.o[d] = ctr - 0.5 * W;
+    }
+    r.W = W;
+    r.S = 65536.0 / W;
+    r.pad[0] = r.pad[1] = r.pad[2] = 0.0;
+    return r;
+}
 void launch_zero_u64(uint64_t *p, int n, hipStream_t st);
 // Several small regions of 64-bit words (n[r] = 0: unused slot) zeroed in one launch.
 constexpr int kZeroRegions = 4;
@@ -32,12 +69,34 @@ struct ZeroRegions {
     int n[kZeroRegions];
 };
 void launch_zero_regions(const ZeroRegions &z, hipStream_t st);
-// halt (nullable, here and below): a run-state word; once set, nothing is done.
+// halt (nullable, here and below): a run-state word; once set, nothing is
+// done.  zr: 64-bit words zeroed on the way (for the kernels that follow).
 void launch_drift_bbox(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int nc, int do_drift,
-                       unsigned long long *bbox, const int32_t *halt, hipStream_t st);
-// Root cubes from the bounding boxes (which it empties again); it also
-// zeroes the regions of zr (64-bit words).
-void launch_root(unsigned long long *bbox, int nc, RootCube *roots, const ZeroRegions &zr, hipStream_t st);
+                       unsigned long long *bbox, const int32_t *halt, const ZeroRegions &zr, hipStream_t st);
+// Root cubes of the nc crystals from the bounding boxes (which are left as
+// they are).
+void launch_roots(const unsigned long long *bbox, int nc, RootCube *roots, hipStream_t st);
+// 64-bit sort key of batch ion g: its crystal index above a 48-bit Morton
+// key of its position quantised to the crystal's root cube (floor((x - o) S),
+// clamped to [0, 2^16 - 1]; subtract then multiply, never fused).
+__device__ inline uint64_t ion_sort_key(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal,
+                                        const RootCube *__restrict__ roots, int g)
+{
+#pragma clang fp contract(off)
+    const int c = ion_crystal[g];
+    const CrystalDev &cd = cs[c];
+    const int i = g - cd.ion_off;
+    const int n = cd.n;
+    const RootCube r = roots[c];
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        double f = floor((cd.mid[d * n + i] - r.o[d]) * r.S);
+        if (!(f >= 0.0)) f = 0.0;
+        if (f > 65535.0) f = 65535.0;
+        q[d] = (uint32_t)f;
+    }
+    return ((uint64_t)c << 48) | morton3(q[0], q[1], q[2]);
+}
 void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCube *roots, int ntot, uint64_t *keys,
                  uint32_t *vals, const int32_t *halt, hipStream_t st);
 // beams: some crystal of the batch uses the beam-mode laser
@@ -82,8 +141,20 @@ size_t radix_state_words(int n);
 constexpr int radix_state_zero_words() { return 8 * 256 + 8 + 2; }
 constexpr int radix_state_err() { return 8 * 256 + 8; }
 // halt (nullable): a run-state word; when it is set the passes do nothing.
+// keys (nullable): the sort keys are computed on the way (ion_sort_key of
+// batch ion i into k0[i], v0[i] = i), in place of launch_roots and
+// launch_keys: every workgroup makes the root cubes of the crystals of its
+// tile out of the bounding boxes (bbox, nc) and writes them to roots (the
+// same values, whichever workgroup writes).
+struct KeySource {
+    const CrystalDev *cs;
+    const int32_t *ion_crystal;
+    const unsigned long long *bbox;
+    int nc;
+    RootCube *roots;
+};
 int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int n, int passes, int first,
-                      uint32_t *state, const int32_t *halt, hipStream_t st);
+                      uint32_t *state, const int32_t *halt, const KeySource *keys, hipStream_t st);
 // After a stable sort by key >> shift: orders every run of equal key >> shift
 // by (key, value), which completes the full sort, and gathers the sorted
 // positions as launch_gather does.  A run longer than kRefineMax sets
@@ -104,9 +175,11 @@ int tree_blocks(int ntot);
 // (filled by launch_tree_count, read by launch_tree_build).
 // check (nullable): capacities the tree must fit, else the run halts (a
 // queued step: the summary then halts the run).
+// bbox (nc crystals): emptied on the way (the sort has read it).
 void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int leaf_size, uint32_t *rep_mask,
                        int32_t *box_end, uint32_t *blockcnt, uint32_t *partial, uint32_t *total,
-                       const uint32_t *sort_err, TreeSummary *sum, const Caps *check, hipStream_t st);
+                       const uint32_t *sort_err, TreeSummary *sum, const Caps *check, unsigned long long *bbox,
+                       int nc, hipStream_t st);
 void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
                        const uint32_t *rep_mask, const int32_t *box_end, const uint32_t *scanned, const BoxTable &bt,
                        const TreeSummary *sum, int nbox, hipStream_t st);
@@ -129,9 +202,12 @@ void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t 
                   uint32_t *item_off, int32_t *src_items, int32_t *cuts, uint32_t *scan_part, uint32_t *n_items,
                   hipStream_t st);
 // cuts (stride per box): first near range of each source item of a leaf.
-void launch_p2p_items(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *near_cnt, int stride,
+// check (nullable, a queued evaluation): near-field items (total[1]) and M2L
+// pairs (total[2]) must fit their capacities, else the run halts here and no
+// item is written.
+void launch_p2p_items(const BoxTable &bt, TreeSummary *sum, int nbox, const int32_t *near_cnt, int stride,
                       const uint32_t *item_off, const int32_t *src_items, const int32_t *cuts, int4 *work,
-                      hipStream_t st);
+                      const uint32_t *total, const Caps *check, hipStream_t st);
 
 // k_fmm.hip
 // rec: recurrence table (fmm_math.hpp), kRecFields x kq(p) entries.
@@ -180,11 +256,6 @@ template <typename T>
 void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, int p, int nbox, const T *L,
                 const T *rec, const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals,
                 double *E, double *phi, int leaf_size, int mode, hipStream_t st);
-// Capacity check of a queued evaluation after the lists (near-field items
-// in total[1], M2L pairs in total[2]): sets sum->halt when a count exceeds
-// its capacity.  (Boxes and levels are checked by the tree summary, see
-// launch_tree_count; a sort failure also halts there.)
-void launch_cap_check_lists(TreeSummary *sum, const uint32_t *total, const Caps &cap, hipStream_t st);
 // Starts a run: halt = 0, fail_step = -1.
 void launch_run_reset(TreeSummary *sum, hipStream_t st);
 

@@ -3,8 +3,9 @@
 //
 // Per force evaluation of a batch (all crystals of one pt_step_batch /
 // pt_compute_forces_batch call that are still active):
-//   bbox (fused with the first half drift when stepping) -> root cubes ->
-//   keys -> LSD radix sort (8-bit digits over crystal + 48 key bits) ->
+//   bbox (fused with the first half drift when stepping) -> root cubes and
+//   keys with the digit counts -> LSD radix sort (8-bit digits over
+//   crystal + 48 key bits) ->
 //   gather sorted positions -> per-level box counts -> [one host read-back of
 //   the box count per level] -> box table + links -> colleagues, V windows,
 //   near lists -> P2M, M2M per level -> M2L -> L2L per level -> L2P + P2P.
@@ -561,8 +562,9 @@ static Caps grow_caps(const Caps &m, double slack)
 
 // Coulomb field per unit charge of every ion of the batch into E (3 x ntot,
 // batch order); with phi non-null also the potential per unit charge
-// (sum_{j != i} 1/r_ij, ntot).  Expects the bbox of the current positions
-// accumulated.
+// (sum_{j != i} 1/r_ij, ntot).  Starts with the bounding boxes of the
+// positions, after the first half drift when drift is set (halt_aware: the
+// drift is skipped once the run has halted).
 //
 // With the FMM, two ways: measuring (queued == nullptr), where the host
 // reads back the tree's size and then the numbers of near-field items and
@@ -571,8 +573,8 @@ static Caps grow_caps(const Caps &m, double slack)
 // capacities *queued, kernels read the counts on the device, nothing is read
 // back, and a count above its capacity halts the run on the device (the
 // step's kick then leaves the state as it was, see TreeSummary).
-static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, double *E, double *phi = nullptr,
-                            const Caps *queued = nullptr)
+static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, double *E, double *phi,
+                            const Caps *queued, int drift, bool halt_aware)
 {
     hipStream_t st = ctx->stream;
     const int ntot = b.ntot, nc = (int)b.cs.size();
@@ -582,12 +584,13 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     ctx->last_off = b.off;
     ctx->last_ntot = ntot;
     ctx->last_was_fmm = fp.method == 1;
-    PT_TRY(timing_begin(ctx));
-    mark(ctx, 0);
     if (fp.method == 0) {
         PT_REQUIRE(b.nblk_dir > 0 || ntot == 0, "batch formed without the direct-sum block table");
         double *part;
         PT_TRY(ws_get(ctx, "dir_part", sizeof(double) * (size_t)std::max<int64_t>(1, b.dir_part), &part));
+        launch_drift_bbox(b.d_desc, b.ion_crystal, ntot, nc, drift, bbox, nullptr, ZeroRegions{}, st);
+        PT_TRY(timing_begin(ctx));
+        mark(ctx, 0);
         launch_direct(b.d_desc, b.dir_tab, b.nblk_dir, b.ion_crystal, ntot, part, E, phi, st);
         for (int i = 1; i <= kPhases - 1; ++i) mark(ctx, i);
         timing_end(ctx);
@@ -624,16 +627,22 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     uint32_t *l2l_cnt;
     PT_TRY(ws_get(ctx, "l2l_cnt", sizeof(uint32_t) * kL2LCounts, &l2l_cnt));
     {
-        // the root-cube kernel also zeroes the sort's counters and the L2L
-        // bucket counts
+        // the drift also zeroes the sort's counters and the L2L bucket counts
         ZeroRegions zr{};
         zr.p[0] = (uint64_t *)rstate;
         zr.n[0] = passes <= 8 ? radix_state_zero_words() / 2 : 0;
         zr.p[1] = (uint64_t *)l2l_cnt;
         zr.n[1] = kL2LCounts / 2;
-        launch_root(bbox, nc, roots, zr, st);
+        launch_drift_bbox(b.d_desc, b.ion_crystal, ntot, nc, drift, bbox, halt_aware ? &dsum->halt : nullptr, zr, st);
     }
-    launch_keys(b.d_desc, b.ion_crystal, roots, ntot, k0, v0, &dsum->halt, st);
+    PT_TRY(timing_begin(ctx));
+    mark(ctx, 0);
+    // root cubes and keys: made by the sort's first kernel (else by two launches)
+    const KeySource key_src{b.d_desc, b.ion_crystal, bbox, nc, roots};
+    if (passes > 8) {
+        launch_roots(bbox, nc, roots, st);
+        launch_keys(b.d_desc, b.ion_crystal, roots, ntot, k0, v0, &dsum->halt, st);
+    }
     // A queued step sorts by the top digits only (the Morton levels down to
     // kSortTopLevels and the crystal) and orders each run of equal top digits
     // by (key, value): the same order as the full sort while every run is
@@ -643,7 +652,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     const int first = queued && passes <= 8 ? ctx->psort_first : 0;
     const bool partial = first > 0;
     if (passes <= 8) {
-        if (launch_radix_sort(k0, v0, k1, v1, ntot, passes, first, rstate, &dsum->halt, st) == 1) {
+        if (launch_radix_sort(k0, v0, k1, v1, ntot, passes, first, rstate, &dsum->halt, &key_src, st) == 1) {
             std::swap(k0, k1);
             std::swap(v0, v1);
         }
@@ -657,7 +666,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         }
     }
     if (!partial) launch_gather(b.d_desc, b.ion_crystal, v0, ntot, sp, &dsum->halt, st);  // else done by the refine
-    launch_tree_count(b.d_desc, k0, ntot, s, rep, box_end, bcnt, scan_part, total, sort_err, dsum, queued, st);
+    launch_tree_count(b.d_desc, k0, ntot, s, rep, box_end, bcnt, scan_part, total, sort_err, dsum, queued, bbox, nc,
+                      st);
     Caps cap{};
     if (queued) {
         cap = *queued;  // the tree summary has checked the tree against it
@@ -757,11 +767,10 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     launch_m2l_count(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, scan_part, total + 2, st);
     // near-field work items and M2L pairs: their numbers size the item,
     // partial and pair buffers.  Measuring, they are read back (the host waits
-    // for an event right after the copy, not for the stream); queued, a
-    // check against the capacities halts the run on overflow.
-    if (queued) {
-        launch_cap_check_lists(dsum, total, cap, st);
-    } else {
+    // for an event right after the copy, not for the stream); queued, the
+    // item writer checks them against the capacities and halts the run on
+    // overflow.
+    if (!queued) {
         PT_HIP(hipMemcpyAsync(ctx->h_counters, total + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         PT_HIP(hipEventRecord(ctx->ev_read, st));
     }
@@ -787,7 +796,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "p2p_work", sizeof(int4) * (size_t)std::max(1, n_items), &work));
     const int ncomp = phi ? 4 : 3;  // near-field partial components per target
     PT_TRY(ws_get(ctx, "p2p_part", esz * 64 * ncomp * (size_t)std::max(1, n_items), (char **)&ppart));
-    launch_p2p_items(bt, dsum, nbox, near_cnt, stride, item_off, src_items, cuts, work, st);
+    launch_p2p_items(bt, dsum, nbox, near_cnt, stride, item_off, src_items, cuts, work, total, queued, st);
     auto run = [&](auto tag) -> pt_status {
         using T = decltype(tag);
         const bool f = sizeof(T) == sizeof(float);
@@ -1242,14 +1251,11 @@ static pt_status evaluate_batch(pt_crystal *const *cs, int n_crystals, double *c
     }
     Batch b;
     PT_TRY(form_batch(ctx, std::vector<pt_crystal *>(cs, cs + n_crystals), b));
-    unsigned long long *bbox;
     double *E, *phi = nullptr, *usum = nullptr;
-    PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * bbox_words(n_crystals), &bbox));
     PT_TRY(ws_get(ctx, "E", sizeof(double) * 3 * (size_t)b.ntot, &E));
     if (phi_out || U_out) PT_TRY(ws_get(ctx, "phi", sizeof(double) * (size_t)std::max(1, b.ntot), &phi));
     if (U_out) PT_TRY(ws_get(ctx, "phi_sum", sizeof(double) * (size_t)n_crystals, &usum));
-    launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, n_crystals, 0, bbox, nullptr, ctx->stream);
-    PT_TRY(eval_field(ctx, b, cs[0]->force, E, phi));
+    PT_TRY(eval_field(ctx, b, cs[0]->force, E, phi, nullptr, 0, false));
     std::vector<double> h, hp, hu;
     if (F_out) {
         h.resize(3 * (size_t)b.ntot);
@@ -1399,7 +1405,7 @@ pt_status pt_compute_forces_noalloc(pt_crystal *c, double *F_dev)
     d.dpart = 0;
     launch_noalloc_setup(d, desc, ion_crystal, n, tab, l.nblk, st);
     launch_bbox_reset(bbox, 1, st);
-    launch_drift_bbox(desc, ion_crystal, n, 1, 0, bbox, nullptr, st);
+    launch_drift_bbox(desc, ion_crystal, n, 1, 0, bbox, nullptr, ZeroRegions{}, st);
     launch_direct(desc, tab, l.nblk, ion_crystal, n, part, E, nullptr, st);
     const double ke = 1.0 / (4.0 * kPi * kEps0), q = c->q;
     launch_scale_field(E, n, ke * q * q, F_dev, st);
@@ -1489,19 +1495,15 @@ static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, co
             formed_for = nactive;
             group_start = k;
         }
-        const int nc = (int)b.cs.size();
-        unsigned long long *bbox;
         double *E;
-        PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * bbox_words(nc), &bbox));
         PT_TRY(ws_get(ctx, "E", sizeof(double) * 3 * (size_t)b.ntot, &E));
-        launch_drift_bbox(b.d_desc, b.ion_crystal, b.ntot, nc, 1, bbox, fmm ? &dsum->halt : nullptr, ctx->stream);
         // queued on the capacities measured for this batch or for one it is
         // part of (crystals that finished their steps drop out: every count a
         // capacity bounds is a sum or maximum over the crystals)
         const bool queued = fmm && ctx->caps_ok && b.ntot <= ctx->caps_ntot && same_force(ctx->caps_force, fp) &&
                             ordered_subset(b.cs, ctx->caps_batch);
         ctx->eval_halted = false;
-        PT_TRY(eval_field(ctx, b, fp, E, nullptr, queued ? &ctx->caps : nullptr));
+        PT_TRY(eval_field(ctx, b, fp, E, nullptr, queued ? &ctx->caps : nullptr, 1, fmm));
         if (fmm) (queued ? ctx->n_queued : ctx->n_measured)++;
         if (fmm && !queued && !ctx->eval_halted) {
             ctx->caps = grow_caps(ctx->measured, ctx->caps_slack);
