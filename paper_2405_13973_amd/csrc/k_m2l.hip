@@ -10,7 +10,7 @@
 // components.  So every V pair (T, S) is a matrix-vector product with one of
 // 56 base matrices plus sign flips, and the pairs that share a base matrix
 // form one GEMM:
-//   1. pairs are counted per target and per base operator, and two scans give
+//   1. pairs are counted per target and per base operator, and scans give
 //      each pair a row in a result buffer R (targets in box order, a target's
 //      pairs in the order of its parity's slot table) and a place in its
 //      operator's bucket (operators in order, then boxes, then slots);
@@ -41,6 +41,7 @@ constexpr int kOps = 64;       // base operator slots (56 used)
 constexpr int kSlots = 189;    // non-touching window slots per parity
 constexpr int kCols = 64;      // pairs per work unit (16 per wave)
 constexpr int kGemmThreads = 256;
+constexpr int kOpSlices = 16;  // copies of the operator totals: the counting workgroups' atomics spread over them
 
 __device__ inline int parity_of(const BoxTable &bt, int b)
 {
@@ -76,7 +77,8 @@ struct Vec16 {
 // base operator (cnt_ob[o * nbox + b]).
 __global__ __launch_bounds__(256) void k_m2l_count(BoxTable bt, const TreeSummary *__restrict__ sum,
                                                    const int32_t *__restrict__ vtab, const int2 *__restrict__ slots,
-                                                   uint32_t *__restrict__ pcnt, uint32_t *__restrict__ cnt_ob)
+                                                   uint32_t *__restrict__ pcnt, uint32_t *__restrict__ cnt_ob,
+                                                   uint32_t *__restrict__ op_total)
 {
     __shared__ uint32_t per_op[kOps];
     __shared__ uint32_t total;
@@ -98,67 +100,117 @@ __global__ __launch_bounds__(256) void k_m2l_count(BoxTable bt, const TreeSummar
         }
     }
     __syncthreads();
-    if (tid < kOps) cnt_ob[(size_t)tid * nbox + b] = per_op[tid];
+    if (tid < kOps) {
+        cnt_ob[(size_t)tid * nbox + b] = per_op[tid];
+        if (per_op[tid]) atomicAdd(&op_total[(b % kOpSlices) * kOps + tid], per_op[tid]);  // integer sums: any order
+    }
     if (tid == 0) pcnt[b] = total;
 }
 
-// Pass 2, one workgroup per box, after the exclusive scans of pcnt (-> the
-// box's first row of R) and cnt_ob (-> the box's first place in each operator
+// Pass 1b, one launch of kOps + 3 workgroups (kScanThreads each) after the
+// counts: workgroup o < kOps scans its operator's row of cnt_ob from the
+// operator's first bucket place (the totals of the operators before it), so
+// the places are those of one scan of cnt_ob in (operator, box) order;
+// workgroup kOps scans pcnt, kOps + 1 the near-field item counts, and
+// kOps + 2 writes the operator table from the totals.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_list_scans(const TreeSummary *__restrict__ sum, int nbox_cap,
+                                                             uint32_t *__restrict__ pcnt, uint32_t *__restrict__ cnt_ob,
+                                                             const uint32_t *__restrict__ op_total,
+                                                             uint32_t *__restrict__ npairs,
+                                                             uint32_t *__restrict__ item_off,
+                                                             uint32_t *__restrict__ n_items,
+                                                             int32_t *__restrict__ op_beg,
+                                                             int32_t *__restrict__ chunk_off)
+{
+    __shared__ uint32_t lds_w[kScanThreads / 64 + 1];
+    __shared__ uint32_t tot_s[kOps];
+    if (sum->halt) return;
+    const int g = blockIdx.x, tid = threadIdx.x;
+    const int nbox = sum->nbox;
+    if (tid < kOps) {  // the operator totals: sums over the slices
+        uint32_t t = 0;
+        for (int sl = 0; sl < kOpSlices; ++sl) t += op_total[sl * kOps + tid];
+        tot_s[tid] = t;
+    }
+    __syncthreads();
+    if (g < kOps) {
+        uint32_t base = 0;
+        for (int o = 0; o < g; ++o) base += tot_s[o];
+        block_scan_inplace(cnt_ob + (size_t)g * nbox, nbox, base, lds_w);
+    } else if (g == kOps) {
+        const uint32_t tot = block_scan_inplace(pcnt, nbox_cap, 0u, lds_w);
+        if (tid == 0) *npairs = tot;
+    } else if (g == kOps + 1) {
+        const uint32_t tot = block_scan_inplace(item_off, nbox_cap, 0u, lds_w);
+        if (tid == 0) *n_items = tot;
+    } else if (tid < 64) {
+        // per operator its bucket's first entry (op_beg[o], op_beg[kOps] = all
+        // pairs) and the prefix of its work-unit counts (chunk_off)
+        const int o = tid;
+        const uint32_t t = tot_s[o];
+        uint32_t c = (t + kCols - 1) / kCols;  // inclusive wave scan of the unit counts
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t z = __shfl_up(c, off);
+            if (o >= off) c += z;
+        }
+        uint32_t first = 0;  // exclusive prefix of the totals
+        for (int k = 0; k < o; ++k) first += tot_s[k];
+        op_beg[o] = (int32_t)first;
+        chunk_off[o + 1] = (int32_t)c;
+        if (o == 0) chunk_off[0] = 0;
+        if (o == kOps - 1) op_beg[kOps] = (int32_t)(first + t);
+    }
+}
+
+// Pass 2, one workgroup per box, after the scans of pcnt (-> the box's
+// first row of R) and cnt_ob (-> the box's first place in each operator
 // bucket): each pair's bucket entry {source box, row of R, reflection mask}.
-// Ranks follow the slot order, so the layout is deterministic.
+// Ranks follow the slot order, so the layout is deterministic: a slot's rank
+// among the box's pairs and among those of its operator come from ballots
+// within each wave plus the counts of the waves before it.
 __global__ __launch_bounds__(256) void k_m2l_emit(BoxTable bt, const TreeSummary *__restrict__ sum,
                                                   const int32_t *__restrict__ vtab, const int2 *__restrict__ slots,
                                                   const uint32_t *__restrict__ pair_off,
                                                   const uint32_t *__restrict__ ob_off, int4 *__restrict__ bucket)
 {
     __builtin_amdgcn_s_setprio(1);  // may run beside the near field, as the GEMM
-    __shared__ int src_s[kSlots];
-    __shared__ int op_s[kSlots];
-    const int b = blockIdx.x, tid = threadIdx.x;
+    constexpr int NW = 256 / 64;
+    __shared__ uint32_t wave_cnt[NW];
+    __shared__ uint32_t wave_op_cnt[NW][kOps];
+    const int b = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int nbox = sum->nbox;
     if (sum->halt || b >= nbox || bt.level[b] < 2) return;
-    const int par = parity_of(bt, b);
+    wave_op_cnt[w][lane] = 0;
+    int src = -1, opw = 0;
     if (tid < kSlots) {
-        const int2 s = slots[par * kSlots + tid];
-        src_s[tid] = vtab[(size_t)b * kWin + s.x];
-        op_s[tid] = s.y;
+        const int2 s = slots[parity_of(bt, b) * kSlots + tid];
+        src = vtab[(size_t)b * kWin + s.x];
+        opw = s.y;
     }
+    const bool valid = src >= 0;
+    const int op = opw & 255;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const unsigned long long vb = __ballot(valid);
+    unsigned long long peers = vb;  // valid lanes of this wave with the same operator
+#pragma unroll
+    for (int bit = 0; bit < 6; ++bit) {
+        const bool on = (op >> bit) & 1;
+        const unsigned long long m = __ballot(on);
+        peers &= on ? m : ~m;
+    }
+    __syncthreads();  // wave_op_cnt cleared
+    if (lane == 0) wave_cnt[w] = (uint32_t)__popcll(vb);
+    if (valid && __popcll(peers & lt) == 0) wave_op_cnt[w][op] = (uint32_t)__popcll(peers);
     __syncthreads();
-    if (tid >= kSlots || src_s[tid] < 0) return;
-    const int op = op_s[tid] & 255;
-    int rank = 0, rank_op = 0;
-    for (int k = 0; k < tid; ++k)
-        if (src_s[k] >= 0) {
-            ++rank;
-            rank_op += (op_s[k] & 255) == op;
-        }
-    const uint32_t pos = ob_off[(size_t)op * nbox + b] + (uint32_t)rank_op;
-    bucket[pos] = make_int4(src_s[tid], (int)(pair_off[b] + (uint32_t)rank), op_s[tid] >> 8, 0);
-}
-
-// Pass 3, one wave: per operator its bucket's first entry (op_beg[o], with
-// op_beg[64] = all pairs) and the prefix of its unit counts (chunk_off).
-__global__ __launch_bounds__(64) void k_m2l_chunks(const TreeSummary *__restrict__ sum,
-                                                   const uint32_t *__restrict__ ob_off,
-                                                   const uint32_t *__restrict__ npairs, int32_t *__restrict__ op_beg,
-                                                   int32_t *__restrict__ chunk_off)
-{
-    __builtin_amdgcn_s_setprio(1);  // may run beside the near field, as the GEMM
-    const int o = threadIdx.x;
-    if (sum->halt) return;
-    const int nbox = sum->nbox;
-    const int beg = nbox > 0 ? (int)ob_off[(size_t)o * nbox] : 0;
-    const int end = o + 1 < kOps ? (nbox > 0 ? (int)ob_off[(size_t)(o + 1) * nbox] : 0) : (int)*npairs;
-    int c = (end - beg + kCols - 1) / kCols;
-    // inclusive wave scan of the unit counts
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(c, off);
-        if (o >= off) c += y;
+    if (!valid) return;
+    uint32_t rank = (uint32_t)__popcll(vb & lt), rank_op = (uint32_t)__popcll(peers & lt);
+    for (int k = 0; k < w; ++k) {
+        rank += wave_cnt[k];
+        rank_op += wave_op_cnt[k][op];
     }
-    op_beg[o] = beg;
-    chunk_off[o + 1] = c;
-    if (o == 0) chunk_off[0] = 0;
-    if (o == kOps - 1) op_beg[kOps] = (int)*npairs;
+    const uint32_t pos = ob_off[(size_t)op * nbox + b] + rank_op;
+    bucket[pos] = make_int4(src, (int)(pair_off[b] + rank), opw >> 8, 0);
 }
 
 // Pass 4: the products.  Work unit u (of nrg * U, U = chunk_off[64]) is row
@@ -355,24 +407,23 @@ __global__ void k_m2l_sum(const TreeSummary *__restrict__ sum, int Kp, const uin
 // ---------------------------------------------------------------- launchers
 
 void launch_m2l_count(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
-                      uint32_t *pcnt, uint32_t *cnt_ob, uint32_t *scan_part, uint32_t *npairs, hipStream_t st)
+                      uint32_t *pcnt, uint32_t *cnt_ob, uint32_t *op_total, uint32_t *npairs, uint32_t *item_off,
+                      uint32_t *n_items, int32_t *op_beg, int32_t *chunk_off, hipStream_t st)
 {
     if (nbox <= 0) return;
-    k_m2l_count<<<nbox, 256, 0, st>>>(bt, sum, vtab, slots, pcnt, cnt_ob);
-    // pcnt -> first row of R per box (CSR); cnt_ob -> first bucket place per (operator, box)
-    launch_scan(pcnt, nbox, scan_part, npairs, st);
-    launch_scan(cnt_ob, kOps * nbox, scan_part, nullptr, st);
+    k_m2l_count<<<nbox, 256, 0, st>>>(bt, sum, vtab, slots, pcnt, cnt_ob, op_total);
+    k_list_scans<<<kOps + 3, kScanThreads, 0, st>>>(sum, nbox, pcnt, cnt_ob, op_total, npairs, item_off, n_items,
+                                                    op_beg, chunk_off);
 }
 
 int m2l_ops() { return kOps; }
+int m2l_op_total_words() { return kOps * kOpSlices; }
 
 void launch_m2l_emit(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
-                     const uint32_t *pair_off, const uint32_t *ob_off, const uint32_t *npairs, int4 *bucket,
-                     int32_t *op_beg, int32_t *chunk_off, hipStream_t st)
+                     const uint32_t *pair_off, const uint32_t *ob_off, int4 *bucket, hipStream_t st)
 {
     if (nbox <= 0) return;
     k_m2l_emit<<<nbox, 256, 0, st>>>(bt, sum, vtab, slots, pair_off, ob_off, bucket);
-    k_m2l_chunks<<<1, 64, 0, st>>>(sum, ob_off, npairs, op_beg, chunk_off);
 }
 
 // Row blocks of 16 per workgroup: as many as fit the LDS share of one

@@ -26,36 +26,10 @@ namespace pt {
 // chunks, then each chunk scanned with its offset, which each block adds up
 // itself from the sums of the chunks before it (a few dozen at the sizes
 // here); one chunk needs only the second launch.  *total (optional) gets the
-// sum.
+// sum.  (block_excl_scan: pt_kernels.hpp.)
 constexpr int kScanTB = 1024;
 constexpr int kScanPer = 8;
 constexpr int kScanChunk = kScanPer * kScanTB;
-
-__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *lds_w, uint32_t &block_total)
-{
-    // inclusive wave scan, then wave totals through LDS
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) lds_w[w] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int k = 0; k < nw; ++k) {
-            const uint32_t t = lds_w[k];
-            lds_w[k] = run;
-            run += t;
-        }
-        lds_w[nw] = run;
-    }
-    __syncthreads();
-    block_total = lds_w[nw];
-    return lds_w[w] + x - v;
-}
 
 __global__ void k_set_u32(uint32_t *__restrict__ p, uint32_t v) { *p = v; }
 
@@ -651,13 +625,14 @@ __global__ void k_tree_links(BoxTable bt, const TreeSummary *__restrict__ sum)
 // octant: child_oct[b][o] = child of b in octant o, parent_oct[b][o] = parent
 // of b in b's own octant slot (-1 elsewhere); and the L2L buckets (boxes of
 // levels >= 3 by level and octant, l2l_cnt zeroed beforehand).
-__global__ void k_oct_tables(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ child_oct,
-                             int32_t *__restrict__ parent_oct, uint32_t *__restrict__ l2l_cnt,
-                             int32_t *__restrict__ l2l_list, int list_stride, ZeroRegions zr)
+// Thread b of nthreads (b: the box); the regions of zr are zeroed on the
+// way (grid-stride over the nthreads).
+__device__ void oct_tables(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ child_oct,
+                           int32_t *__restrict__ parent_oct, uint32_t *__restrict__ l2l_cnt,
+                           int32_t *__restrict__ l2l_list, int list_stride, const ZeroRegions &zr, int b, int nthreads)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int r = 0; r < kZeroRegions; ++r)  // words the later kernels need zeroed (grid-stride)
-        for (int i = b; i < zr.n[r]; i += gridDim.x * blockDim.x) zr.p[r][i] = 0ull;
+    for (int r = 0; r < kZeroRegions; ++r)  // words the later kernels need zeroed
+        for (int i = b; i < zr.n[r]; i += nthreads) zr.p[r][i] = 0ull;
     if (sum->halt || b >= sum->nbox) return;
     int32_t ch[8], pa[8];
     for (int o = 0; o < 8; ++o) ch[o] = pa[o] = -1;
@@ -678,9 +653,8 @@ __global__ void k_oct_tables(BoxTable bt, const TreeSummary *__restrict__ sum, i
 
 // Same-level neighbours (offsets in [-1,1]^3, slot (dx+1)*9 + (dy+1)*3 + (dz+1)),
 // one thread per (box, slot): a binary search of the level's sorted keys.
-__global__ void k_colleagues(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ coll)
+__device__ void colleagues(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ coll, int i)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int nbox = sum->nbox;
     if (sum->halt || i >= nbox * kNeigh) return;
     const int b = i / kNeigh, s = i - b * kNeigh;
@@ -702,6 +676,24 @@ __global__ void k_colleagues(BoxTable bt, const TreeSummary *__restrict__ sum, i
         if (a < l1 && bt.key[a] == want) found = a;
     }
     coll[i] = found;
+}
+
+// Colleagues (the first ncb workgroups, one thread per (box, slot)) and the
+// octant tables (the rest, one thread per box) in one launch: both read only
+// the box table.
+__global__ __launch_bounds__(256) void k_oct_colleagues(BoxTable bt, const TreeSummary *__restrict__ sum,
+                                                        int32_t *__restrict__ coll, int ncb,
+                                                        int32_t *__restrict__ child_oct,
+                                                        int32_t *__restrict__ parent_oct,
+                                                        uint32_t *__restrict__ l2l_cnt,
+                                                        int32_t *__restrict__ l2l_list, int list_stride, ZeroRegions zr)
+{
+    if ((int)blockIdx.x < ncb) {
+        colleagues(bt, sum, coll, blockIdx.x * 256 + threadIdx.x);
+        return;
+    }
+    oct_tables(bt, sum, child_oct, parent_oct, l2l_cnt, l2l_list, list_stride, zr,
+               ((int)blockIdx.x - ncb) * 256 + threadIdx.x, ((int)gridDim.x - ncb) * 256);
 }
 
 // V lists into the dense window table (-1 = no source), one thread per
@@ -957,14 +949,13 @@ int vlist_blocks(int nbox) { return ceil_div(nbox, kVBoxes); }
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
                   int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
                   int32_t *parent_oct, uint32_t *l2l_cnt, int32_t *l2l_list, const ZeroRegions &zr,
-                  uint32_t *item_off, int32_t *src_items, int32_t *cuts, uint32_t *scan_part, uint32_t *n_items,
-                  hipStream_t st)
+                  uint32_t *item_off, int32_t *src_items, int32_t *cuts, hipStream_t st)
 {
-    k_oct_tables<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum, child_oct, parent_oct, l2l_cnt, l2l_list, nbox, zr);
-    k_colleagues<<<ceil_div(nbox * kNeigh, 256), 256, 0, st>>>(bt, sum, coll);
+    const int ncb = ceil_div(nbox * kNeigh, 256);
+    k_oct_colleagues<<<ncb + ceil_div(nbox, 256), 256, 0, st>>>(bt, sum, coll, ncb, child_oct, parent_oct, l2l_cnt,
+                                                                l2l_list, nbox, zr);
     k_vlist<<<vlist_blocks(nbox), 256, 0, st>>>(bt, sum, coll, child_oct, vtab, v_blk);
     k_nearlist<<<nbox, 64, 0, st>>>(bt, sum, coll, stride, near, near_cnt, item_off, src_items, cuts, near_pairs);
-    launch_scan(item_off, nbox, scan_part, n_items, st);
 }
 
 void launch_p2p_items(const BoxTable &bt, TreeSummary *sum, int nbox, const int32_t *near_cnt, int stride,

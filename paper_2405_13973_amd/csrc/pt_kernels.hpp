@@ -14,6 +14,63 @@ struct BoxTable {
     double4 *geo;     // centre xyz, side h
 };
 
+// Workgroup scans (blockDim.x a multiple of 64).
+// Exclusive scan of one value per thread; block_total gets the sum.  lds_w:
+// blockDim.x / 64 + 1 words.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *lds_w, uint32_t &block_total)
+{
+    // inclusive wave scan, then wave totals through LDS
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds_w[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < nw; ++k) {
+            const uint32_t t = lds_w[k];
+            lds_w[k] = run;
+            run += t;
+        }
+        lds_w[nw] = run;
+    }
+    __syncthreads();
+    block_total = lds_w[nw];
+    return lds_w[w] + x - v;
+}
+
+// a[i] <- base + a[0] + ... + a[i-1] for i < n, in place, by one workgroup
+// (rounds of kScanRound consecutive values per thread); returns the sum of
+// the n values.  lds_w as above.
+constexpr int kScanRound = 8;
+__device__ inline uint32_t block_scan_inplace(uint32_t *__restrict__ a, int n, uint32_t base, uint32_t *lds_w)
+{
+    uint32_t carry = 0;
+    for (int r0 = 0; r0 < n; r0 += (int)blockDim.x * kScanRound) {
+        const int i0 = r0 + (int)threadIdx.x * kScanRound;
+        uint32_t v[kScanRound], s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanRound; ++k) {
+            v[k] = i0 + k < n ? a[i0 + k] : 0u;
+            s += v[k];
+        }
+        uint32_t tot;
+        uint32_t run = base + carry + block_excl_scan(s, lds_w, tot);
+#pragma unroll
+        for (int k = 0; k < kScanRound; ++k) {
+            if (i0 + k < n) a[i0 + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+        __syncthreads();  // lds_w is reused by the next round
+    }
+    return carry;
+}
+
 // k_step.hip
 void launch_ion_crystal(const CrystalDev *cs, int nc, int ntot, int32_t *ion_crystal, hipStream_t st);
 // Bounding boxes: kBBoxCopies copies of [crystal][6] ordered-integer words,
@@ -196,11 +253,11 @@ int vlist_blocks(int nbox);
 constexpr int kL2LCounts = 8 * (kMaxLevel + 1);
 static_assert(kL2LCounts % 2 == 0, "L2L counts are cleared as 64-bit words");
 // zr: 64-bit words to zero on the way (the first kernel clears them).
+// item_off gets the item counts per leaf; launch_m2l_count scans them.
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
                   int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
                   int32_t *parent_oct, uint32_t *l2l_cnt, int32_t *l2l_list, const ZeroRegions &zr,
-                  uint32_t *item_off, int32_t *src_items, int32_t *cuts, uint32_t *scan_part, uint32_t *n_items,
-                  hipStream_t st);
+                  uint32_t *item_off, int32_t *src_items, int32_t *cuts, hipStream_t st);
 // cuts (stride per box): first near range of each source item of a leaf.
 // check (nullable, a queued evaluation): near-field items (total[1]) and M2L
 // pairs (total[2]) must fit their capacities, else the run halts here and no
@@ -262,18 +319,24 @@ void launch_run_reset(TreeSummary *sum, hipStream_t st);
 // k_m2l.hip: M2L organised by base operator.
 // slots: per parity the 189 non-touching window slots {slot, base operator +
 // 256 x reflection mask (bit 0: dx < 0, bit 1: dy < 0, bit 2: dz < 0)}.
-// launch_m2l_count: pcnt (nbox) and cnt_ob (m2l_ops() x nbox) are scanned in
-// place (pcnt -> first row of R per box, cnt_ob -> first bucket place per
-// (operator, box)); npairs <- the number of V pairs.  scan_part needs
-// scan_partials(m2l_ops() * nbox) + 1 words.
+// launch_m2l_count: the V pairs counted per box (pcnt, nbox) and per
+// (operator, box) (cnt_ob, m2l_ops() rows of the tree's box count), with the
+// operator totals added into op_total (m2l_op_total_words() words, slices of
+// m2l_ops(), zero beforehand);
+// then one launch scans them all in place: pcnt -> first row of R per box
+// (*npairs <- the number of V pairs), cnt_ob -> first bucket place per
+// (operator, box), item_off (nbox item counts of the near field) -> first
+// item per leaf (*n_items <- their number), and writes the operator table
+// op_beg / chunk_off (m2l_ops() + 1 ints each: each operator's first bucket
+// place and the prefix of its work-unit counts).
 int m2l_ops();
+int m2l_op_total_words();
 void launch_m2l_count(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
-                      uint32_t *pcnt, uint32_t *cnt_ob, uint32_t *scan_part, uint32_t *npairs, hipStream_t st);
-// bucket: npairs int4 {source box, row of R, reflection mask, 0}; op_beg and
-// chunk_off: m2l_ops() + 1 ints each.
+                      uint32_t *pcnt, uint32_t *cnt_ob, uint32_t *op_total, uint32_t *npairs, uint32_t *item_off,
+                      uint32_t *n_items, int32_t *op_beg, int32_t *chunk_off, hipStream_t st);
+// bucket: npairs int4 {source box, row of R, reflection mask, 0}.
 void launch_m2l_emit(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
-                     const uint32_t *pair_off, const uint32_t *ob_off, const uint32_t *npairs, int4 *bucket,
-                     int32_t *op_beg, int32_t *chunk_off, hipStream_t st);
+                     const uint32_t *pair_off, const uint32_t *ob_off, int4 *bucket, hipStream_t st);
 // LDS of one GEMM workgroup: at most this much for the operator rows, and at
 // most this many row blocks of 16 (compiled variants).
 constexpr size_t kM2LLdsBudget = 48 << 10;

@@ -742,29 +742,34 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "near_pairs", sizeof(int64_t) * (size_t)nbox, &near_pairs));
     int32_t *cuts;
     PT_TRY(ws_get(ctx, "p2p_cuts", sizeof(int32_t) * (size_t)stride * nbox, &cuts));
-    PT_TRY(ws_get(ctx, "scan_part",
-                  sizeof(uint32_t) * (scan_partials(std::max(std::max(scan_n, nbox), m2l_ops() * nbox)) + 1),
-                  &scan_part));
-    uint32_t *m2l_pcnt, *m2l_cnt_ob;
+    uint32_t *m2l_pcnt, *m2l_cnt_ob, *m2l_op_total;
     PT_TRY(ws_get(ctx, "m2l_pcnt", sizeof(uint32_t) * (size_t)nbox, &m2l_pcnt));
     PT_TRY(ws_get(ctx, "m2l_cnt_ob", sizeof(uint32_t) * (size_t)m2l_ops() * nbox, &m2l_cnt_ob));
+    PT_TRY(ws_get(ctx, "m2l_op_total", sizeof(uint32_t) * (size_t)m2l_op_total_words(), &m2l_op_total));
+    int32_t *m2l_ops_tab;
+    PT_TRY(ws_get(ctx, "m2l_ops_tab", sizeof(int32_t) * 2 * (m2l_ops() + 1), &m2l_ops_tab));
+    int32_t *m2l_op_beg = m2l_ops_tab, *m2l_chunk_off = m2l_ops_tab + m2l_ops() + 1;
     int32_t *p2p_queue;
     PT_TRY(ws_get(ctx, "p2p_queue", sizeof(uint64_t), &p2p_queue));
     {
         // zeroed by the list builders: the zero rows of M and L (read for
-        // absent sources) and the near-field item queue
+        // absent sources), the near-field item queue and the M2L operator
+        // totals
         ZeroRegions zr{};
         zr.p[0] = (uint64_t *)((char *)M + esz * Kp * (size_t)nbox);
         zr.p[1] = (uint64_t *)((char *)L + esz * Kp * (size_t)nbox);
         zr.p[2] = (uint64_t *)p2p_queue;
+        zr.p[3] = (uint64_t *)m2l_op_total;
         zr.n[0] = zr.n[1] = (int)(esz * Kp / 8);
         zr.n[2] = 1;
+        zr.n[3] = m2l_op_total_words() / 2;
         launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, v_blk, near_pairs, child_oct, parent_oct,
-                     l2l_cnt, l2l_list, zr, item_off, src_items, cuts, scan_part, total + 1, st);
+                     l2l_cnt, l2l_list, zr, item_off, src_items, cuts, st);
     }
     // M2L pairs: counted and scanned here, so that their number comes back
     // with the near-field item count
-    launch_m2l_count(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, scan_part, total + 2, st);
+    launch_m2l_count(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, m2l_op_total, total + 2,
+                     item_off, total + 1, m2l_op_beg, m2l_chunk_off, st);
     // near-field work items and M2L pairs: their numbers size the item,
     // partial and pair buffers.  Measuring, they are read back (the host waits
     // for an event right after the copy, not for the stream); queued, the
@@ -786,12 +791,9 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     }
     const int n_items = cap.items, n_pairs = cap.pairs;
     int4 *work, *m2l_bucket;
-    int32_t *m2l_ops_tab;
     void *m2l_R;
     PT_TRY(ws_get(ctx, "m2l_bucket", sizeof(int4) * (size_t)std::max(1, n_pairs), &m2l_bucket));
-    PT_TRY(ws_get(ctx, "m2l_ops_tab", sizeof(int32_t) * 2 * (m2l_ops() + 1), &m2l_ops_tab));
     PT_TRY(ws_get(ctx, "m2l_R", esz * Kp * (size_t)std::max(1, n_pairs), (char **)&m2l_R));
-    int32_t *m2l_op_beg = m2l_ops_tab, *m2l_chunk_off = m2l_ops_tab + m2l_ops() + 1;
     void *ppart;
     PT_TRY(ws_get(ctx, "p2p_work", sizeof(int4) * (size_t)std::max(1, n_items), &work));
     const int ncomp = phi ? 4 : 3;  // near-field partial components per target
@@ -841,8 +843,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         // upward pass (after P2M on the second stream), then the M2L buckets
         PT_HIP(hipStreamWaitEvent(st, ctx->ev_p2m, 0));
         launch_m2m<T>(bt, dsum, p, cap, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, st);
-        launch_m2l_emit(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, total + 2, m2l_bucket,
-                        m2l_op_beg, m2l_chunk_off, st);
+        launch_m2l_emit(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, m2l_bucket, st);
         if (concurrent && !early) PT_TRY(fork());
         mark(ctx, 2);
         const int m2l_grid =
