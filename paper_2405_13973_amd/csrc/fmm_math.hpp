@@ -211,14 +211,16 @@ __host__ __device__ inline void l2p_field_pot(int p, const T *L, const T *rec, T
 }
 
 // conj(Rh_n^m(u)) of one point in real storage order into out[s * stride]
-// (s the storage index), from the recurrence table.
+// (s the storage index), from the recurrence table; only the orders m in
+// [m_lo, m_hi) are written (each by the same operations as in a full pass).
 template <typename T>
-__host__ __device__ inline void p2m_terms(int p, const T *rec, T x, T y, T z, T *out, int stride)
+__host__ __device__ inline void p2m_terms(int p, const T *rec, T x, T y, T z, T *out, int stride, int m_lo = 0,
+                                          int m_hi = 1 << 30)
 {
     const int Q = kq(p);
     const T r2 = x * x + y * y + z * z;
     T dre = 1, dim = 0;
-    for (int m = 0; m <= p; ++m) {
+    for (int m = 0; m <= p && m < m_hi; ++m) {
         if (m > 0) {
             const T f = rec[m * (m + 1) / 2 + m];
             const T nre = f * (x * dre - y * dim);
@@ -226,6 +228,7 @@ __host__ __device__ inline void p2m_terms(int p, const T *rec, T x, T y, T z, T 
             dre = nre;
             dim = nim;
         }
+        if (m < m_lo) continue;
         T r1re = 0, r1im = 0, r0re = 0, r0im = 0;
         for (int n = m; n <= p; ++n) {
             const int q = n * (n + 1) / 2 + m;

@@ -18,13 +18,19 @@ namespace pt {
 
 __device__ inline int octant_of(int ix, int iy, int iz) { return ((ix & 1) << 2) | ((iy & 1) << 1) | (iz & 1); }
 
-// P2M: one 64-thread block per leaf.  Ions are taken `chunk` (64, or 32 when
-// the tile would exceed 64 KiB) at a time: each thread evaluates conj(Rh_n^m) of its ion for all (n, m) by one pass of the
-// recurrences into an LDS tile [coefficient][ion]; then each thread sums its
-// coefficients over the tile's ions, in four interleaved partial sums (ions
-// j = 0, 1, 2, 3 mod 4) added in a fixed order, which keeps the LDS reads
-// independent of one another.
-constexpr int kP2MMaxPer = 8;  // coefficients per thread: Kp <= 512
+// P2M: one 256-thread block per leaf.  Ions are taken `chunk` (64, or 32 when
+// the tile would exceed 64 KiB) at a time into an LDS tile
+// [coefficient][ion] of conj(Rh_n^m): lane j of every wave takes ion j, and
+// the four waves split the orders m (kP2MWaves ranges of about equal term
+// counts; each wave runs the m recurrence from m = 0 to reach its first
+// order), so each term is computed by the same operations as in one pass
+// over all m.  Then each thread sums one coefficient (two when Kp > 256)
+// over the tile's ions, in four interleaved partial sums (ions j = 0, 1, 2,
+// 3 mod 4) added in a fixed order, which keeps the LDS reads independent of
+// one another.
+constexpr int kP2MWaves = 4;
+constexpr int kP2MThreads = 64 * kP2MWaves;
+constexpr int kP2MMaxPer = 2;  // coefficients per thread: Kp <= 512
 
 template <typename T>
 static int p2m_chunk(int Kp, int leaf_size)
@@ -32,10 +38,20 @@ static int p2m_chunk(int Kp, int leaf_size)
     return leaf_size > 32 && (size_t)Kp * 65 * sizeof(T) <= 65536 ? 64 : 32;
 }
 
+// First order m of wave w's range: the orders are cut where the running
+// count of terms (p - m + 1 per order) reaches w / kP2MWaves of the total.
+__device__ inline int p2m_first_order(int p, int w)
+{
+    const int total = (p + 1) * (p + 2) / 2;
+    int m = 0, run = 0;
+    while (m <= p && run * kP2MWaves < w * total) run += p - m++ + 1;
+    return m;
+}
+
 template <typename T>
-__global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const TreeSummary *__restrict__ sum,
-                                            const double *__restrict__ sp, int ntot, int p, int Kp, int chunk,
-                                            const T *__restrict__ rec, T *__restrict__ M)
+__global__ __launch_bounds__(kP2MThreads) void k_p2m(BoxTable bt, const TreeSummary *__restrict__ sum,
+                                                     const double *__restrict__ sp, int ntot, int p, int Kp,
+                                                     int chunk, const T *__restrict__ rec, T *__restrict__ M)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *C = reinterpret_cast<T *>(smem_raw);  // [Kp][chunk + 1]
@@ -45,8 +61,10 @@ __global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const TreeSummary *__re
     const double4 g = bt.geo[b];
     const double ih = 1.0 / g.w;
     const int K = kcoef(p);
-    for (int i = threadIdx.x; i < 2 * kq(p); i += 64) rec_s[i] = rec[i];
+    for (int i = threadIdx.x; i < 2 * kq(p); i += kP2MThreads) rec_s[i] = rec[i];
     __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m_lo = p2m_first_order(p, w), m_hi = w + 1 < kP2MWaves ? p2m_first_order(p, w + 1) : p + 1;
     const int i0 = bt.begin[b], i1 = bt.end[b];
     const int ld = chunk + 1;  // odd: the rows of a column fall in distinct banks
     T acc[kP2MMaxPer];
@@ -54,15 +72,15 @@ __global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const TreeSummary *__re
     for (int r = 0; r < kP2MMaxPer; ++r) acc[r] = T(0);
     for (int c0 = i0; c0 < i1; c0 += chunk) {
         const int cnt = min(chunk, i1 - c0);
-        if ((int)threadIdx.x < cnt) {
-            const int i = c0 + threadIdx.x;
+        if (lane < cnt && m_lo < m_hi) {
+            const int i = c0 + lane;
             p2m_terms<T>(p, rec_s, (T)((sp[i] - g.x) * ih), (T)((sp[ntot + i] - g.y) * ih),
-                         (T)((sp[2 * ntot + i] - g.z) * ih), C + threadIdx.x, ld);
+                         (T)((sp[2 * ntot + i] - g.z) * ih), C + lane, ld, m_lo, m_hi);
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kP2MMaxPer; ++r) {
-            const int s = threadIdx.x + 64 * r;
+            const int s = threadIdx.x + kP2MThreads * r;
             if (s < K) {
                 const T *row = C + s * ld;
                 T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -83,7 +101,7 @@ __global__ __launch_bounds__(64) void k_p2m(BoxTable bt, const TreeSummary *__re
     }
 #pragma unroll
     for (int r = 0; r < kP2MMaxPer; ++r) {
-        const int s = threadIdx.x + 64 * r;
+        const int s = threadIdx.x + kP2MThreads * r;
         if (s < Kp) M[(size_t)b * Kp + s] = s < K ? acc[r] : T(0);
     }
 }
@@ -749,7 +767,7 @@ void launch_p2m(const BoxTable &bt, const TreeSummary *sum, const double *sp, in
     const int Kp = kpad(p);
     const int chunk = p2m_chunk<T>(Kp, leaf_size);
     const size_t smem = (size_t)Kp * (chunk + 1) * sizeof(T);
-    if (nbox > 0) k_p2m<T><<<nbox, 64, smem, st>>>(bt, sum, sp, ntot, p, Kp, chunk, rec, M);
+    if (nbox > 0) k_p2m<T><<<nbox, kP2MThreads, smem, st>>>(bt, sum, sp, ntot, p, Kp, chunk, rec, M);
 }
 
 template <typename T>
