@@ -47,6 +47,7 @@ PHASES = ["tree_lists_p2m", "m2m", "m2l_kernel", "m2l_reduce_l2l", "p2p_kernel",
 # then the fastest): step time depends on where a crystal's boxes are split,
 # not monotonically on the leaf size
 LEAF_CANDIDATES = (32, 64, 128, 192, 224, 256, 320, 384)
+NEAR_SHARE_CANDIDATES = (0, 4, 5)  # 0: the library's default (3 beside the upward pass, 4 after it)
 
 
 def measured_traffic(kernel, p, leaf, precision, n):
@@ -521,6 +522,8 @@ def main():
     ap.add_argument("--leaf", type=int, default=0,
                     help="leaf size (0: tuned; serving: 256)")
     ap.add_argument("--p0", type=int, default=10, help="first p tried when choosing p")
+    ap.add_argument("--near-share", type=int, default=-1,
+                    help="near-field workgroups per compute unit beside the far field (-1: tuned; 0: default)")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
@@ -596,12 +599,32 @@ def main():
                 best = (leaf, p, err, el)
         return best[:3]
 
+    def tune_share(prec, leaf, p):
+        """Near-field workgroups per compute unit beside the far field (a
+        schedule parameter, no effect on the results): the fastest of the
+        candidates over two runs of 20 steps each, unless given."""
+        if a.near_share >= 0:
+            ctx.set_near_share(a.near_share)
+            return a.near_share
+        best = None
+        for share in NEAR_SHARE_CANDIDATES:
+            ctx.set_near_share(share)
+            c.set_state(cr.pos, cr.vel, 0)
+            c.set_force("fmm", p, leaf, prec)
+            el = min(timed_steps(ctx, c, 20, 2, sync, phases_too=False)[0] for _ in range(2))
+            log(f"  {prec} leaf {leaf} near share {share}: {20 * cr.n / el:.4g} ion-steps/s")
+            if best is None or el < best[1]:
+                best = (share, el)
+        ctx.set_near_share(best[0])
+        return best[0]
+
     results = {}
     forms = [a.precision] + ([] if a.no_fp64_compare or a.precision == "fp64" else ["fp64"])
     for prec in forms:
         # each form at its own best leaf size (the same candidates, the same bound)
         leaves = (a.leaf,) if a.leaf else LEAF_CANDIDATES
         leaf, p, err = tune(prec, leaves)
+        share = tune_share(prec, leaf, p)
         c.set_state(cr.pos, cr.vel, 0)
         c.set_force("fmm", p, leaf, prec)
         sync()
@@ -612,8 +635,8 @@ def main():
         F_end = c.compute_forces()
         c.set_force("fmm", p, leaf, prec)
         err_end = rms_rel(c.compute_forces(), F_end)
-        results[prec] = dict(p=p, leaf=leaf, err=err, err_end=err_end, seconds=el, phases=phases, count=count, wc=wc,
-                             plain=plain)
+        results[prec] = dict(p=p, leaf=leaf, share=share, err=err, err_end=err_end, seconds=el, phases=phases,
+                             count=count, wc=wc, plain=plain)
         log(f"  {prec}: p={p} leaf={leaf} {a.steps} steps in {el * 1e3:.2f} ms -> {cr.n * a.steps / el:.4g} "
             f"ion-steps/s (without events {plain * 1e3:.2f} ms); rms err start {err:.2e} end {err_end:.2e}; "
             f"phases(ms) " + " ".join(f"{k} {v:.3f}" for k, v in zip(PHASES, phases)) + f" over {count} evals")
@@ -631,6 +654,7 @@ def main():
 
     main_r = results[a.precision]
     p, leaf = main_r["p"], main_r["leaf"]
+    ctx.set_near_share(main_r["share"])  # the legs on the same crystal below
     K = (p + 1) ** 2
     ph = main_r["phases"]
     fp32 = a.precision == "mixed"
@@ -681,7 +705,7 @@ def main():
         "config": {
             "workload": f"{cr.n} ions, 5%-jittered cubic lattice in a (400,400,800) um prolate ellipsoid, "
                         f"B=4.5 T, f_z=1.5 MHz, dt=1 ns, FMM p={p} leaf {leaf} ({a.precision})",
-            "n_ions": cr.n, "p": p, "leaf_size": leaf, "precision": a.precision,
+            "n_ions": cr.n, "p": p, "leaf_size": leaf, "precision": a.precision, "near_share": main_r["share"],
             "rms_rel_force_err": main_r["err"], "rms_rel_force_err_after_timed_steps": main_r["err_end"],
         },
         "roofline": rooflines[kernel],
@@ -702,6 +726,7 @@ def main():
         out["details"]["fp64_ion_steps_per_s"] = cr.n * a.steps / f["seconds"]
         out["details"]["fp64_p"] = f["p"]
         out["details"]["fp64_leaf_size"] = f["leaf"]
+        out["details"]["fp64_near_share"] = f["share"]
         out["details"]["fp64_rms_rel_force_err"] = f["err"]
         out["details"]["fp64_rms_rel_force_err_after_timed_steps"] = f["err_end"]
         out["details"]["mixed_speedup_vs_fp64"] = f["seconds"] / main_r["seconds"]
@@ -720,6 +745,7 @@ def main():
         out["potential"]["gpu_over_cpu"] = (out["potential"]["ion_evals_per_s"] /
                                             out["cpu_baseline"]["potential_ion_evals_per_s"])
     c.destroy()
+    ctx.set_near_share(0)  # the batched workloads run on the library's default schedule
     if not a.no_ensemble:
         e = argparse.Namespace(**vars(a))
         e.steps, e.warmup, e.leaf, e.p = ENSEMBLE_STEPS, 3, SERVING_LEAF, 0

@@ -284,6 +284,15 @@ pt_status pt_debug_export_tree(pt_crystal *c, int64_t sizes[4], uint64_t *keys, 
 pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable);
 pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[7], int64_t *count);
 
+/* Share of the chip the near field takes while the far field runs beside
+ * it (a schedule parameter of the FMM evaluation, which changes no result):
+ * per_cu near-field workgroups per compute unit, 1..8, or 0 for the default
+ * (3 when the near field forks before the upward pass, the mixed form; 4
+ * when it forks after it, the FP64 form).  The environment variable
+ * PT_NEAR_PER_CU sets it at context creation.  PT_EINVAL for another value;
+ * waits for pending steps. */
+pt_status pt_ctx_set_near_share(pt_ctx *ctx, int per_cu);
+
 /* Work counts of the last FMM evaluation: [0] boxes, [1] leaves, [2] M2L
  * pairs, [3] P2P pairs (ordered, i != j counted), [4] levels, [5] ions. */
 pt_status pt_ctx_work_counts(pt_ctx *ctx, int64_t counts[6]);

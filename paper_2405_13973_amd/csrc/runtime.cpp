@@ -1620,6 +1620,15 @@ pt_status pt_read_state(pt_crystal *c, double *pos, double *vel, int64_t *step, 
     return PT_OK;
 }
 
+pt_status pt_ctx_set_near_share(pt_ctx *ctx, int per_cu)
+{
+    PT_REQUIRE(ctx, "ctx is NULL");
+    PT_REQUIRE(per_cu >= 0 && per_cu <= 8, "near-field workgroups per compute unit must be 0 (default) .. 8");
+    PT_TRY(settle(ctx));
+    ctx->near_per_cu = per_cu;
+    return PT_OK;
+}
+
 pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable)
 {
     PT_REQUIRE(ctx, "ctx is NULL");

@@ -101,6 +101,7 @@ def load():
         "pt_read_state": [_vp, _dp, _dp, C.POINTER(C.c_int64), _dp, C.POINTER(C.c_int32)],
         "pt_debug_export_tree": [_vp, C.POINTER(C.c_int64)] + [_vp] * 13,
         "pt_ctx_set_timing": [_vp, C.c_int],
+        "pt_ctx_set_near_share": [_vp, C.c_int],
         "pt_ctx_phase_times": [_vp, _dp, C.POINTER(C.c_int64)],
         "pt_ctx_work_counts": [_vp, C.POINTER(C.c_int64)],
         "pt_ctx_step_stats": [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
@@ -175,6 +176,10 @@ class Context:
         cnt = C.c_int64()
         _check(load().pt_ctx_phase_times(self.h, _ptr(ms), C.byref(cnt)))
         return (ms, cnt.value) if with_count else ms
+
+    def set_near_share(self, per_cu):
+        """Near-field workgroups per compute unit beside the far field (0: default)."""
+        _check(load().pt_ctx_set_near_share(self.h, int(per_cu)))
 
     def work_counts(self):
         c = np.zeros(6, np.int64)

@@ -224,6 +224,8 @@ def test_invalid_inputs_return_status_codes(ctx):
     expect(native.PT_EINVAL, native.step_batch, [c, d], [1, 1])  # different force parameters
     expect(native.PT_EINVAL, native.step_batch, [c, c], [1, 1])  # the same crystal twice
     expect(native.PT_EINVAL, native.step_batch, [c], [-1])
+    expect(native.PT_EINVAL, ctx.set_near_share, -1)
+    expect(native.PT_EINVAL, ctx.set_near_share, 9)
     # the parameters in force before the rejected calls still work
     c.step(2)
     assert c.read_state()["step"] == 2
@@ -317,22 +319,26 @@ def test_non_finite_state_is_reported_after_the_step():
 def test_near_field_schedules_are_bit_identical(leaf, monkeypatch):
     """The near field runs beside the far field on a second stream (a capped grid
     taking work items from a queue; forked before or after the upward pass, the
-    far-field L2P then split around the join) or after it on the main stream (one
-    workgroup per item); every item writes its own partials, added in item order,
+    far-field L2P then split around the join; with any share of the chip) or after
+    it on the main stream (one workgroup per item); every item writes its own
+    partials, added in item order,
     so every schedule gives the same forces, and the same states after queued
     steps, bit for bit, in both precisions."""
     say(f"near-field schedules leaf {leaf}")
     cr = inputs.config3(n=30000)
-    settings = {"after": {"PT_NEAR_CONCURRENT": "0"},
-                "beside, early fork": {"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1"},
-                "beside, late fork": {"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "0"}}
+    settings = {"after": ({"PT_NEAR_CONCURRENT": "0"}, 0),
+                "beside, early fork": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1"}, 0),
+                "beside, early fork, 5 per CU": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1"}, 5),
+                "beside, late fork": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "0"}, 0),
+                "beside, late fork, 2 per CU": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "0"}, 2)}
     out = {}
-    for name, env in settings.items():
-        for k in ("PT_NEAR_CONCURRENT", "PT_NEAR_EARLY"):
+    for name, (env, share) in settings.items():
+        for k in ("PT_NEAR_CONCURRENT", "PT_NEAR_EARLY", "PT_NEAR_PER_CU"):
             monkeypatch.delenv(k, raising=False)
         for k, v in env.items():
             monkeypatch.setenv(k, v)
         with native.Context(0) as c:
+            c.set_near_share(share)
             for prec in ("mixed", "fp64"):
                 k = make(c, cr, "fmm", 11, leaf, prec)
                 F = k.compute_forces()
