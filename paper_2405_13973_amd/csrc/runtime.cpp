@@ -123,6 +123,7 @@ struct pt_ctx {
     int near_concurrent = -1;  // -1: by leaf size; 0 / 1: forced (PT_NEAR_CONCURRENT)
     int near_per_cu = 0;  // near-field workgroups per CU beside the far field (PT_NEAR_PER_CU; 0: by schedule)
     int near_early = -1;  // -1: by precision; 0 / 1: forced (PT_NEAR_EARLY): near field forks before the upward pass
+    int near_main = 1;    // forking before the upward pass: 1 = the far field forks, the near field stays (PT_NEAR_MAIN)
     // first Morton digit the sort of a queued step orders by (the runs of
     // equal higher digits are then refined): starts at the top kSortTopLevels
     // levels, one digit lower after every run that is too long to refine, 0 =
@@ -484,9 +485,9 @@ static pt_status form_batch(pt_ctx *ctx, const std::vector<pt_crystal *> &cs, Ba
 static pt_status finish_timing(pt_ctx *ctx);
 static pt_status settle(pt_ctx *ctx);
 
-static void mark(pt_ctx *ctx, int i)
+static void mark(pt_ctx *ctx, int i, hipStream_t on = nullptr)
 {
-    if (ctx->timing) (void)hipEventRecord(ctx->ev[ctx->ring_cur][i], ctx->stream);
+    if (ctx->timing) (void)hipEventRecord(ctx->ev[ctx->ring_cur][i], on ? on : ctx->stream);
 }
 
 // Collects the oldest recorded event set into the running sums.
@@ -821,23 +822,53 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         const bool early = concurrent && (ctx->near_early >= 0 ? ctx->near_early > 0 : f);
         const int near_cap = ctx->near_per_cu > 0 ? ctx->near_per_cu : early ? kNearPerCUEarly : kNearPerCUConcurrent;
         hipStream_t ns = concurrent ? ctx->near_stream : st;
-        auto near_field = [&]() -> pt_status {
-            if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][0], ns));
+        auto near_field = [&](hipStream_t on) -> pt_status {
+            if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][0], on));
             const int max_grid = concurrent ? near_cap * ctx->num_cu : 16384;
             // beside the far field the grid is capped and the workgroups take
             // items from a queue; alone, one workgroup per item (no queue: its
             // atomics would serialise over the many small items of small leaves)
             launch_near<T>(bt, dsum, sp, ntot, near, stride, work, total + 1, n_items, (T *)ppart, phi != nullptr,
-                           max_grid, concurrent ? p2p_queue : nullptr, ns);
-            if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][1], ns));
+                           max_grid, concurrent ? p2p_queue : nullptr, on);
+            if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][1], on));
             ctx->near_timed[ctx->ring_cur] = ctx->timing;
-            if (concurrent) PT_HIP(hipEventRecord(ctx->ev_join, ns));
             return PT_OK;
         };
+        if (early && ctx->near_main) {
+            // forking before the upward pass: the far field goes to the second
+            // stream (after P2M there) and the near field stays on the main
+            // stream, right after its work items, so the branch that decides
+            // the step starts without waiting for a fork (measured: a few per
+            // cent; forking after the upward pass, the FP64 form, keeps the
+            // near field on the second stream, which is faster there)
+            PT_HIP(hipEventRecord(ctx->ev_fork, st));
+            PT_HIP(hipStreamWaitEvent(ns, ctx->ev_fork, 0));
+            launch_m2m<T>(bt, dsum, p, cap, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, ns);
+            launch_m2l_emit(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, m2l_bucket, ns);
+            mark(ctx, 2, ns);
+            const int m2l_grid = ctx->num_cu * m2l_per_cu<T>(Kp, near_cap * near_lds_bytes());
+            launch_m2l_gemm<T>(dsum, Kp, nbox, m2l_grid, m2l_chunk_off, m2l_op_beg, m2l_bucket, m2l, (const T *)M,
+                               (T *)m2l_R, ns);
+            mark(ctx, 3, ns);
+            launch_m2l_sum<T>(dsum, nbox, Kp, m2l_pcnt, total + 2, (const T *)m2l_R, (T *)L, ns);
+            launch_downward<T>(bt, dsum, p, cap, l2l, tb.oct_slots, parent_oct, l2l_cnt, l2l_list, (T *)L, ns);
+            mark(ctx, 4, ns);
+            launch_far<T>(bt, dsum, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E,
+                          phi, s, 1, ns);
+            mark(ctx, 5, ns);
+            PT_HIP(hipEventRecord(ctx->ev_join, ns));
+            PT_TRY(near_field(st));
+            PT_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+            launch_far<T>(bt, dsum, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E,
+                          phi, s, 2, st);
+            return PT_OK;
+        }
         auto fork = [&]() -> pt_status {
             PT_HIP(hipEventRecord(ctx->ev_fork, st));
             PT_HIP(hipStreamWaitEvent(ns, ctx->ev_fork, 0));
-            return near_field();
+            PT_TRY(near_field(ns));
+            PT_HIP(hipEventRecord(ctx->ev_join, ns));
+            return PT_OK;
         };
         if (early) PT_TRY(fork());
         // upward pass (after P2M on the second stream), then the M2L buckets
@@ -855,7 +886,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         launch_downward<T>(bt, dsum, p, cap, l2l, tb.oct_slots, parent_oct, l2l_cnt, l2l_list, (T *)L, st);
         mark(ctx, 4);
         if (!concurrent) {
-            PT_TRY(near_field());
+            PT_TRY(near_field(st));
         } else {
             // beside the near field, the far field of every ion is evaluated
             // before the join and the near-field partials added after it
@@ -981,6 +1012,7 @@ static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
     if (const char *e = getenv("PT_NEAR_CONCURRENT")) ctx->near_concurrent = atoi(e) ? 1 : 0;
     if (const char *e = getenv("PT_NEAR_PER_CU")) ctx->near_per_cu = std::max(1, std::min(8, atoi(e)));
     if (const char *e = getenv("PT_NEAR_EARLY")) ctx->near_early = atoi(e) ? 1 : 0;
+    if (const char *e = getenv("PT_NEAR_MAIN")) ctx->near_main = atoi(e) ? 1 : 0;
     if (const char *e = getenv("PT_PARTIAL_SORT"))
         if (!atoi(e)) ctx->psort_first = 0;
     if (const char *e = getenv("PT_QUEUED_STEPS")) ctx->no_queue = atoi(e) == 0;

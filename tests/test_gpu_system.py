@@ -317,23 +317,25 @@ def test_non_finite_state_is_reported_after_the_step():
 # ---------------------------------------------------------------- schedules
 @pytest.mark.parametrize("leaf", [32, 256])
 def test_near_field_schedules_are_bit_identical(leaf, monkeypatch):
-    """The near field runs beside the far field on a second stream (a capped grid
-    taking work items from a queue; forked before or after the upward pass, the
-    far-field L2P then split around the join; with any share of the chip) or after
-    it on the main stream (one workgroup per item); every item writes its own
-    partials, added in item order,
-    so every schedule gives the same forces, and the same states after queued
-    steps, bit for bit, in both precisions."""
+    """The near field runs beside the far field (a capped grid taking work items
+    from a queue; before or after the upward pass, the far field or the near field
+    on the second stream, the far-field L2P then split around the join; with any
+    share of the chip) or after it on the main stream (one workgroup per item);
+    every item writes its own partials, added in item order, so every schedule
+    gives the same forces, and the same states after queued steps, bit for bit,
+    in both precisions."""
     say(f"near-field schedules leaf {leaf}")
     cr = inputs.config3(n=30000)
     settings = {"after": ({"PT_NEAR_CONCURRENT": "0"}, 0),
                 "beside, early fork": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1"}, 0),
                 "beside, early fork, 5 per CU": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1"}, 5),
+                "beside, early fork, near field forked": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1",
+                                                           "PT_NEAR_MAIN": "0"}, 0),
                 "beside, late fork": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "0"}, 0),
                 "beside, late fork, 2 per CU": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "0"}, 2)}
     out = {}
     for name, (env, share) in settings.items():
-        for k in ("PT_NEAR_CONCURRENT", "PT_NEAR_EARLY", "PT_NEAR_PER_CU"):
+        for k in ("PT_NEAR_CONCURRENT", "PT_NEAR_EARLY", "PT_NEAR_PER_CU", "PT_NEAR_MAIN"):
             monkeypatch.delenv(k, raising=False)
         for k, v in env.items():
             monkeypatch.setenv(k, v)
