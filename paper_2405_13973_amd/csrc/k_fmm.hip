@@ -366,10 +366,16 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_xlate(XlateArgs a, const T *
 // change any summation order.
 constexpr long kXMinGrid = 128;
 constexpr long kXWideGrid = 768;
-static void xlate_rows(XlateArgs &a, long base_grid)
+// Beside a near field of four or five workgroups per compute unit (72 VGPRs
+// per wave), a SIMD keeps 224 or 152 VGPRs free: the translations then use
+// 16-value k-chunks and at most this many row blocks per workgroup (the
+// compiled variants need at most 144 VGPRs), so their waves find room
+// instead of waiting for near-field workgroups to finish.
+constexpr int kXNarrowRB = 7;
+static void xlate_rows(XlateArgs &a, long base_grid, bool narrow)
 {
     const int blocks = a.Kp / 16;
-    int nrg = ceil_div(blocks, kM2LRB);
+    int nrg = ceil_div(blocks, narrow ? kXNarrowRB : kM2LRB);
     while (nrg < blocks && base_grid * nrg < kXMinGrid) {
         // next row-group count that shrinks the per-workgroup block count
         const int nrb = ceil_div(blocks, nrg);
@@ -379,14 +385,14 @@ static void xlate_rows(XlateArgs &a, long base_grid)
 }
 
 template <typename T, int ROLE>
-static void launch_xlate(const XlateArgs &a, int grid, const T *At, const T *X, T *out, hipStream_t st)
+static void launch_xlate(const XlateArgs &a, int grid, const T *At, const T *X, T *out, bool narrow, hipStream_t st)
 {
     const int blocks = a.Kp / 16;
     const int nrb = ceil_div(blocks, a.nrowgrp);
     const bool partial = nrb * a.nrowgrp != blocks;
     // k-chunks of 48 when the grid is too small to hide a step's load
     // latency behind other workgroups' matrix-core work
-    const bool wide = a.Kp % 48 == 0 && (long)grid < kXWideGrid;
+    const bool wide = !narrow && a.Kp % 48 == 0 && (long)grid < kXWideGrid;
     switch ((nrb * 2 + (partial ? 1 : 0)) * 2 + (wide ? 1 : 0)) {
 #define PT_XL(NB)                                                                                       \
     case 4 * NB: k_xlate<T, NB, false, ROLE, 16><<<grid, 64 * kM2LWaves, 0, st>>>(a, At, X, out); break; \
@@ -738,7 +744,7 @@ static XlateArgs xlate_base(int Kp, int nbox)
 template <typename T>
 static void launch_level_xlate(const BoxTable &bt, const TreeSummary *sum, int Kp, int nbox, int level, int cap,
                                int mode, const T *ops, const int2 *oct_slots, const int32_t *srctab, T *X, T *part,
-                               hipStream_t st)
+                               bool narrow, hipStream_t st)
 {
     const int tiles = std::max(1, ceil_div(cap, kM2LCols));
     XlateArgs a = xlate_base(Kp, nbox);
@@ -752,9 +758,9 @@ static void launch_level_xlate(const BoxTable &bt, const TreeSummary *sum, int K
     a.srctab = srctab;
     a.src_stride = 8;
     a.mode = 0;
-    xlate_rows(a, (long)tiles * a.ngroup);
-    if (mode == 1) launch_xlate<T, 1>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, st);
-    else launch_xlate<T, 2>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, st);
+    xlate_rows(a, (long)tiles * a.ngroup, narrow);
+    if (mode == 1) launch_xlate<T, 1>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, narrow, st);
+    else launch_xlate<T, 2>(a, tiles * a.ngroup * a.nrowgrp, ops, X, part, narrow, st);
     const size_t tot = (size_t)std::max(1, cap) * Kp;
     k_xlate_reduce<T><<<(unsigned)std::min<size_t>((tot + 255) / 256, 8192), 256, 0, st>>>(
         sum, level, Kp, nbox, a.ngroup, mode, bt.leaf, part, X);
@@ -772,13 +778,14 @@ void launch_p2m(const BoxTable &bt, const TreeSummary *sum, const double *sp, in
 
 template <typename T>
 void launch_m2m(const BoxTable &bt, const TreeSummary *sum, int p, const Caps &cap, const T *m2m_pad,
-                const int2 *oct_slots, const int32_t *child_oct, T *M, T *part, hipStream_t st)
+                const int2 *oct_slots, const int32_t *child_oct, T *M, T *part, bool narrow, hipStream_t st)
 {
     // level by level: parents of level l gather their children by octant
     const int Kp = kpad(p);
     for (int l = std::min(cap.nlev, kMaxLevel + 1) - 2; l >= 2; --l) {
         if (cap.lvl[l] <= 0 || cap.lvl[l + 1] <= 0) continue;  // no boxes, or no children below
-        launch_level_xlate<T>(bt, sum, Kp, cap.nbox, l, cap.lvl[l], 1, m2m_pad, oct_slots, child_oct, M, part, st);
+        launch_level_xlate<T>(bt, sum, Kp, cap.nbox, l, cap.lvl[l], 1, m2m_pad, oct_slots, child_oct, M, part, narrow,
+                              st);
     }
 }
 
@@ -792,7 +799,7 @@ int m2l_groups(int)
 template <typename T>
 void launch_downward(const BoxTable &bt, const TreeSummary *sum, int p, const Caps &cap, const T *l2l_pad,
                      const int2 *oct_slots, const int32_t *parent_oct, const uint32_t *l2l_cnt,
-                     const int32_t *l2l_list, T *L, hipStream_t st)
+                     const int32_t *l2l_list, T *L, bool narrow, hipStream_t st)
 {
     const int Kp = kpad(p);
     // L2L level by level (3 and deeper): the level's boxes in 8 octant
@@ -819,8 +826,8 @@ void launch_downward(const BoxTable &bt, const TreeSummary *sum, int p, const Ca
         a.srctab = parent_oct;
         a.src_stride = 8;
         a.mode = 2;
-        xlate_rows(a, (long)tiles * a.nbucket);
-        launch_xlate<T, 2>(a, tiles * a.nbucket * a.nrowgrp, l2l_pad, L, L, st);
+        xlate_rows(a, (long)tiles * a.nbucket, narrow);
+        launch_xlate<T, 2>(a, tiles * a.nbucket * a.nrowgrp, l2l_pad, L, L, narrow, st);
     }
 }
 
@@ -871,9 +878,9 @@ void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, in
     template void launch_p2m<T>(const BoxTable &, const TreeSummary *, const double *, int, int, int, const T *,     \
                                 T *, int, hipStream_t);                                                            \
     template void launch_m2m<T>(const BoxTable &, const TreeSummary *, int, const Caps &, const T *, const int2 *,   \
-                                const int32_t *, T *, T *, hipStream_t);                                           \
+                                const int32_t *, T *, T *, bool, hipStream_t);                                     \
     template void launch_downward<T>(const BoxTable &, const TreeSummary *, int, const Caps &, const T *,            \
-                                     const int2 *, const int32_t *, const uint32_t *, const int32_t *, T *,          \
+                                     const int2 *, const int32_t *, const uint32_t *, const int32_t *, T *, bool,    \
                                      hipStream_t);                                                                 \
     template void launch_near<T>(const BoxTable &, const TreeSummary *, const double *, int, const int2 *, int,      \
                                  const int4 *, const uint32_t *, int, T *, bool, int, int *, hipStream_t);         \

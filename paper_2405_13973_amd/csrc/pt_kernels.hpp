@@ -277,16 +277,18 @@ void launch_p2p_items(const BoxTable &bt, TreeSummary *sum, int nbox, const int3
 template <typename T>
 void launch_p2m(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, int p, int nbox, const T *rec,
                 T *M, int leaf_size, hipStream_t st);
+// narrow: beside a near field of four or more workgroups per compute unit
+// (mixed form), translation variants that need fewer registers (M2M and L2L).
 template <typename T>
 void launch_m2m(const BoxTable &bt, const TreeSummary *sum, int p, const Caps &cap, const T *m2m_pad,
-                const int2 *oct_slots, const int32_t *child_oct, T *M, T *part, hipStream_t st);
+                const int2 *oct_slots, const int32_t *child_oct, T *M, T *part, bool narrow, hipStream_t st);
 int m2l_groups(int n2);  // slot groups of M2M / L2L partial sums (partial-sum buffer: groups x nbox x Kp)
 // L2L, level by level: each box of an octant bucket adds its parent's local
 // expansion shifted by its octant's operator (l2l_cnt / l2l_list as above).
 template <typename T>
 void launch_downward(const BoxTable &bt, const TreeSummary *sum, int p, const Caps &cap, const T *l2l_pad,
                      const int2 *oct_slots, const int32_t *parent_oct, const uint32_t *l2l_cnt,
-                     const int32_t *l2l_list, T *L, hipStream_t st);
+                     const int32_t *l2l_list, T *L, bool narrow, hipStream_t st);
 // Near field over the work items into part (item x 64 x 3; with pot the
 // potential sum as a fourth component, item x 64 x 4); *n_items items (on the
 // device, at most cap_items), at most max_grid workgroups, which take the

@@ -822,6 +822,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         const bool early = concurrent && (ctx->near_early >= 0 ? ctx->near_early > 0 : f);
         const int near_cap = ctx->near_per_cu > 0 ? ctx->near_per_cu : early ? kNearPerCUEarly : kNearPerCUConcurrent;
         hipStream_t ns = concurrent ? ctx->near_stream : st;
+        // translations that leave room for their waves beside a large near field
+        const bool narrow = f && concurrent && near_cap >= 4;
         auto near_field = [&](hipStream_t on) -> pt_status {
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][0], on));
             const int max_grid = concurrent ? near_cap * ctx->num_cu : 16384;
@@ -843,7 +845,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             // near field on the second stream, which is faster there)
             PT_HIP(hipEventRecord(ctx->ev_fork, st));
             PT_HIP(hipStreamWaitEvent(ns, ctx->ev_fork, 0));
-            launch_m2m<T>(bt, dsum, p, cap, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, ns);
+            launch_m2m<T>(bt, dsum, p, cap, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, narrow, ns);
             launch_m2l_emit(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, m2l_bucket, ns);
             mark(ctx, 2, ns);
             const int m2l_grid = ctx->num_cu * m2l_per_cu<T>(Kp, near_cap * near_lds_bytes());
@@ -851,7 +853,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
                                (T *)m2l_R, ns);
             mark(ctx, 3, ns);
             launch_m2l_sum<T>(dsum, nbox, Kp, m2l_pcnt, total + 2, (const T *)m2l_R, (T *)L, ns);
-            launch_downward<T>(bt, dsum, p, cap, l2l, tb.oct_slots, parent_oct, l2l_cnt, l2l_list, (T *)L, ns);
+            launch_downward<T>(bt, dsum, p, cap, l2l, tb.oct_slots, parent_oct, l2l_cnt, l2l_list, (T *)L, narrow, ns);
             mark(ctx, 4, ns);
             launch_far<T>(bt, dsum, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E,
                           phi, s, 1, ns);
@@ -873,7 +875,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         if (early) PT_TRY(fork());
         // upward pass (after P2M on the second stream), then the M2L buckets
         PT_HIP(hipStreamWaitEvent(st, ctx->ev_p2m, 0));
-        launch_m2m<T>(bt, dsum, p, cap, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, st);
+        launch_m2m<T>(bt, dsum, p, cap, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, narrow, st);
         launch_m2l_emit(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, m2l_bucket, st);
         if (concurrent && !early) PT_TRY(fork());
         mark(ctx, 2);
@@ -883,7 +885,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
                            (T *)m2l_R, st);
         mark(ctx, 3);
         launch_m2l_sum<T>(dsum, nbox, Kp, m2l_pcnt, total + 2, (const T *)m2l_R, (T *)L, st);
-        launch_downward<T>(bt, dsum, p, cap, l2l, tb.oct_slots, parent_oct, l2l_cnt, l2l_list, (T *)L, st);
+        launch_downward<T>(bt, dsum, p, cap, l2l, tb.oct_slots, parent_oct, l2l_cnt, l2l_list, (T *)L, narrow, st);
         mark(ctx, 4);
         if (!concurrent) {
             PT_TRY(near_field(st));
