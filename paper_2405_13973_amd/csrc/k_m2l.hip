@@ -107,12 +107,13 @@ __global__ __launch_bounds__(256) void k_m2l_count(BoxTable bt, const TreeSummar
     if (tid == 0) pcnt[b] = total;
 }
 
-// Pass 1b, one launch of kOps + 3 workgroups (kScanThreads each) after the
+// Pass 1b, one launch of kOps + 4 workgroups (kScanThreads each) after the
 // counts: workgroup o < kOps scans its operator's row of cnt_ob from the
 // operator's first bucket place (the totals of the operators before it), so
 // the places are those of one scan of cnt_ob in (operator, box) order;
-// workgroup kOps scans pcnt, kOps + 1 the near-field item counts, and
-// kOps + 2 writes the operator table from the totals.
+// workgroup kOps scans pcnt, kOps + 1 the near-field item counts, kOps + 2
+// writes the operator table from the totals and kOps + 3 adds up the
+// near-field pairs.
 constexpr int kScanThreads = 1024;
 __global__ __launch_bounds__(kScanThreads) void k_list_scans(const TreeSummary *__restrict__ sum, int nbox_cap,
                                                              uint32_t *__restrict__ pcnt, uint32_t *__restrict__ cnt_ob,
@@ -121,7 +122,9 @@ __global__ __launch_bounds__(kScanThreads) void k_list_scans(const TreeSummary *
                                                              uint32_t *__restrict__ item_off,
                                                              uint32_t *__restrict__ n_items,
                                                              int32_t *__restrict__ op_beg,
-                                                             int32_t *__restrict__ chunk_off)
+                                                             int32_t *__restrict__ chunk_off,
+                                                             const int64_t *__restrict__ near_pairs,
+                                                             unsigned long long *__restrict__ near_total)
 {
     __shared__ uint32_t lds_w[kScanThreads / 64 + 1];
     __shared__ uint32_t tot_s[kOps];
@@ -144,6 +147,19 @@ __global__ __launch_bounds__(kScanThreads) void k_list_scans(const TreeSummary *
     } else if (g == kOps + 1) {
         const uint32_t tot = block_scan_inplace(item_off, nbox_cap, 0u, lds_w);
         if (tid == 0) *n_items = tot;
+    } else if (g == kOps + 3) {
+        // the near-field pairs of all leaves (integer sum: any order)
+        __shared__ unsigned long long ws[kScanThreads / 64];
+        unsigned long long acc = 0;
+        for (int b = tid; b < nbox_cap; b += kScanThreads) acc += (unsigned long long)near_pairs[b];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if ((tid & 63) == 0) ws[tid >> 6] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long t = 0;
+            for (int w = 0; w < kScanThreads / 64; ++w) t += ws[w];
+            *near_total = t;
+        }
     } else if (tid < 64) {
         // per operator its bucket's first entry (op_beg[o], op_beg[kOps] = all
         // pairs) and the prefix of its work-unit counts (chunk_off)
@@ -408,12 +424,13 @@ __global__ void k_m2l_sum(const TreeSummary *__restrict__ sum, int Kp, const uin
 
 void launch_m2l_count(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
                       uint32_t *pcnt, uint32_t *cnt_ob, uint32_t *op_total, uint32_t *npairs, uint32_t *item_off,
-                      uint32_t *n_items, int32_t *op_beg, int32_t *chunk_off, hipStream_t st)
+                      uint32_t *n_items, int32_t *op_beg, int32_t *chunk_off, const int64_t *near_pairs,
+                      unsigned long long *near_total, hipStream_t st)
 {
     if (nbox <= 0) return;
     k_m2l_count<<<nbox, 256, 0, st>>>(bt, sum, vtab, slots, pcnt, cnt_ob, op_total);
-    k_list_scans<<<kOps + 3, kScanThreads, 0, st>>>(sum, nbox, pcnt, cnt_ob, op_total, npairs, item_off, n_items,
-                                                    op_beg, chunk_off);
+    k_list_scans<<<kOps + 4, kScanThreads, 0, st>>>(sum, nbox, pcnt, cnt_ob, op_total, npairs, item_off, n_items,
+                                                    op_beg, chunk_off, near_pairs, near_total);
 }
 
 int m2l_ops() { return kOps; }

@@ -330,12 +330,14 @@ void launch_run_reset(TreeSummary *sum, hipStream_t st);
 // (operator, box), item_off (nbox item counts of the near field) -> first
 // item per leaf (*n_items <- their number), and writes the operator table
 // op_beg / chunk_off (m2l_ops() + 1 ints each: each operator's first bucket
-// place and the prefix of its work-unit counts).
+// place and the prefix of its work-unit counts); *near_total <- the sum of
+// the near-field pairs per leaf (near_pairs, nbox).
 int m2l_ops();
 int m2l_op_total_words();
 void launch_m2l_count(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
                       uint32_t *pcnt, uint32_t *cnt_ob, uint32_t *op_total, uint32_t *npairs, uint32_t *item_off,
-                      uint32_t *n_items, int32_t *op_beg, int32_t *chunk_off, hipStream_t st);
+                      uint32_t *n_items, int32_t *op_beg, int32_t *chunk_off, const int64_t *near_pairs,
+                      unsigned long long *near_total, hipStream_t st);
 // bucket: npairs int4 {source box, row of R, reflection mask, 0}.
 void launch_m2l_emit(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
                      const uint32_t *pair_off, const uint32_t *ob_off, int4 *bucket, hipStream_t st);

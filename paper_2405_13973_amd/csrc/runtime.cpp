@@ -29,6 +29,16 @@
 
 using namespace pt;
 
+// Capacities of queued steps: the measured counts times this slack (raised
+// after an overflow, see settle()).
+constexpr double kCapsSlack = 1.5;
+// Near-field pairs per M2L pair above which the near field alone outlasts the
+// M2L GEMM alone (~2e12 near pairs/s against ~1.1e9 V pairs/s at p = 11,
+// measured): it then keeps the main stream when the two branches split
+// before the upward pass.  Below it (M2L-heavy trees, e.g. 1e6 ions at leaf
+// 256: ~740) the far field keeps the main stream.
+constexpr double kNearFirstRatio = 2000.0;
+
 // ---------------------------------------------------------------- errors
 
 static thread_local char g_err[512] = "";
@@ -123,7 +133,9 @@ struct pt_ctx {
     int near_concurrent = -1;  // -1: by leaf size; 0 / 1: forced (PT_NEAR_CONCURRENT)
     int near_per_cu = 0;  // near-field workgroups per CU beside the far field (PT_NEAR_PER_CU; 0: by schedule)
     int near_early = -1;  // -1: by precision; 0 / 1: forced (PT_NEAR_EARLY): near field forks before the upward pass
-    int near_main = 1;    // forking before the upward pass: 1 = the far field forks, the near field stays (PT_NEAR_MAIN)
+    int near_main = -1;   // forking before the upward pass: 1 = the far field forks, the near field stays,
+                          // 0 = the near field forks, -1 = by the measured balance (PT_NEAR_MAIN)
+    bool near_first = false;  // the last measured batch's near field outweighs its M2L
     // first Morton digit the sort of a queued step orders by (the runs of
     // equal higher digits are then refined): starts at the top kSortTopLevels
     // levels, one digit lower after every run that is too long to refine, 0 =
@@ -161,7 +173,7 @@ struct pt_ctx {
     // and force parameters)
     bool caps_ok = false;
     Caps caps{};
-    double caps_slack = 1.5;  // raised by half after each overflow, up to 4
+    double caps_slack = kCapsSlack;  // raised by half after each overflow of a batch, up to 4
     std::vector<pt_crystal *> caps_batch;
     int caps_ntot = 0;
     pt_force_params caps_force{};
@@ -769,8 +781,10 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     }
     // M2L pairs: counted and scanned here, so that their number comes back
     // with the near-field item count
+    unsigned long long *near_total;
+    PT_TRY(ws_get(ctx, "near_total", sizeof(unsigned long long), &near_total));
     launch_m2l_count(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, m2l_op_total, total + 2,
-                     item_off, total + 1, m2l_op_beg, m2l_chunk_off, st);
+                     item_off, total + 1, m2l_op_beg, m2l_chunk_off, near_pairs, near_total, st);
     // near-field work items and M2L pairs: their numbers size the item,
     // partial and pair buffers.  Measuring, they are read back (the host waits
     // for an event right after the copy, not for the stream); queued, the
@@ -778,6 +792,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     // overflow.
     if (!queued) {
         PT_HIP(hipMemcpyAsync(ctx->h_counters, total + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        PT_HIP(hipMemcpyAsync(ctx->h_counters + 1, near_total, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         PT_HIP(hipEventRecord(ctx->ev_read, st));
     }
     void *xl_part;
@@ -789,6 +804,9 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         PT_HIP(hipEventSynchronize(ctx->ev_read));
         cap.items = (int)((uint32_t *)ctx->h_counters)[0];
         cap.pairs = (int)((uint32_t *)ctx->h_counters)[1];
+        // which branch of an early split stays on the main stream, for this
+        // evaluation and the batch's queued steps
+        ctx->near_first = (double)ctx->h_counters[1] > kNearFirstRatio * (double)cap.pairs;
     }
     const int n_items = cap.items, n_pairs = cap.pairs;
     int4 *work, *m2l_bucket;
@@ -836,7 +854,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             ctx->near_timed[ctx->ring_cur] = ctx->timing;
             return PT_OK;
         };
-        if (early && ctx->near_main) {
+        if (early && (ctx->near_main > 0 || (ctx->near_main < 0 && ctx->near_first))) {
             // forking before the upward pass: the far field goes to the second
             // stream (after P2M there) and the near field stays on the main
             // stream, right after its work items, so the branch that decides
@@ -1541,6 +1559,10 @@ static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, co
         PT_TRY(eval_field(ctx, b, fp, E, nullptr, queued ? &ctx->caps : nullptr, 1, fmm));
         if (fmm) (queued ? ctx->n_queued : ctx->n_measured)++;
         if (fmm && !queued && !ctx->eval_halted) {
+            // the slack grown by overflows belongs to the batch that overflowed:
+            // a batch of other crystals (or other force parameters) starts anew
+            if (!ordered_subset(b.cs, ctx->caps_batch) || !same_force(ctx->caps_force, fp))
+                ctx->caps_slack = kCapsSlack;
             ctx->caps = grow_caps(ctx->measured, ctx->caps_slack);
             if (ctx->tight_caps) ctx->caps.nbox = std::max(1, ctx->measured.nbox - 1);
             ctx->caps_batch = b.cs;

@@ -327,7 +327,7 @@ def test_near_field_schedules_are_bit_identical(leaf, monkeypatch):
     say(f"near-field schedules leaf {leaf}")
     cr = inputs.config3(n=30000)
     settings = {"after": ({"PT_NEAR_CONCURRENT": "0"}, 0),
-                "beside, early fork": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1"}, 0),
+                "beside, early fork": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1", "PT_NEAR_MAIN": "1"}, 0),
                 "beside, early fork, 5 per CU": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1"}, 5),
                 "beside, early fork, near field forked": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1",
                                                            "PT_NEAR_MAIN": "0"}, 0),
