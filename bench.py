@@ -745,7 +745,10 @@ def main():
         out["potential"]["gpu_over_cpu"] = (out["potential"]["ion_evals_per_s"] /
                                             out["cpu_baseline"]["potential_ion_evals_per_s"])
     c.destroy()
-    ctx.set_near_share(0)  # the batched workloads run on the library's default schedule
+    # the batched workloads run in a context of their own (as with --workload),
+    # on the library's default schedule
+    ctx.close()
+    ctx = native.Context(0, hbm_budget=(a.budget_gb << 30) + (4 << 30), stream=stream.cuda_stream)
     if not a.no_ensemble:
         e = argparse.Namespace(**vars(a))
         e.steps, e.warmup, e.leaf, e.p = ENSEMBLE_STEPS, 3, SERVING_LEAF, 0

@@ -32,12 +32,19 @@ using namespace pt;
 // Capacities of queued steps: the measured counts times this slack (raised
 // after an overflow, see settle()).
 constexpr double kCapsSlack = 1.5;
-// Near-field pairs per M2L pair above which the near field alone outlasts the
-// M2L GEMM alone (~2e12 near pairs/s against ~1.1e9 V pairs/s at p = 11,
-// measured): it then keeps the main stream when the two branches split
-// before the upward pass.  Below it (M2L-heavy trees, e.g. 1e6 ions at leaf
-// 256: ~740) the far field keeps the main stream.
+// When the two branches split before the upward pass, the near field keeps
+// the main stream (and starts without waiting for the fork) if it outweighs
+// M2L -- more than kNearFirstRatio near-field pairs per V pair, where the near
+// field alone outlasts the M2L GEMM alone (~2e12 near pairs/s against ~1.1e9
+// V pairs/s at p = 11) -- or if M2L is small, fewer than kNearFirstPairs V
+// pairs (measured: 1e5-ion spheres at 270k V pairs gain 20%, 3e5 with 345k are
+// even); otherwise the far field keeps it (1e6-ion spheres, ~3M V pairs: the
+// far branch is the longer one, and starting it second costs 30%).
 constexpr double kNearFirstRatio = 2000.0;
+constexpr double kNearFirstPairs = 1.0e6;
+// First digit the sort of a queued step orders by (the top kSortTopLevels
+// levels; lowered after a run too long to refine, see settle()).
+constexpr int kPsortFirst = (48 - 3 * kSortTopLevels) / 8;
 
 // ---------------------------------------------------------------- errors
 
@@ -140,7 +147,8 @@ struct pt_ctx {
     // equal higher digits are then refined): starts at the top kSortTopLevels
     // levels, one digit lower after every run that is too long to refine, 0 =
     // the full sort (PT_PARTIAL_SORT=0 starts there)
-    int psort_first = (48 - 3 * kSortTopLevels) / 8;
+    int psort_first = kPsortFirst;
+    bool psort_off = false;  // PT_PARTIAL_SORT=0: every queued step sorts all digits
     uint64_t budget = 0, used = 0;
     int live = 0;
     int32_t *d_nonfinite = nullptr;  // set by any kick of this context that produces a non-finite value
@@ -806,7 +814,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         cap.pairs = (int)((uint32_t *)ctx->h_counters)[1];
         // which branch of an early split stays on the main stream, for this
         // evaluation and the batch's queued steps
-        ctx->near_first = (double)ctx->h_counters[1] > kNearFirstRatio * (double)cap.pairs;
+        ctx->near_first = (double)ctx->h_counters[1] > kNearFirstRatio * (double)cap.pairs ||
+                          (double)cap.pairs < kNearFirstPairs;
     }
     const int n_items = cap.items, n_pairs = cap.pairs;
     int4 *work, *m2l_bucket;
@@ -1034,7 +1043,10 @@ static pt_status init_ctx(pt_ctx *ctx, void *hip_stream)
     if (const char *e = getenv("PT_NEAR_EARLY")) ctx->near_early = atoi(e) ? 1 : 0;
     if (const char *e = getenv("PT_NEAR_MAIN")) ctx->near_main = atoi(e) ? 1 : 0;
     if (const char *e = getenv("PT_PARTIAL_SORT"))
-        if (!atoi(e)) ctx->psort_first = 0;
+        if (!atoi(e)) {
+            ctx->psort_first = 0;
+            ctx->psort_off = true;
+        }
     if (const char *e = getenv("PT_QUEUED_STEPS")) ctx->no_queue = atoi(e) == 0;
     if (const char *e = getenv("PT_CAPS_TIGHT")) ctx->tight_caps = atoi(e) != 0;
     PT_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
@@ -1561,8 +1573,10 @@ static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, co
         if (fmm && !queued && !ctx->eval_halted) {
             // the slack grown by overflows belongs to the batch that overflowed:
             // a batch of other crystals (or other force parameters) starts anew
-            if (!ordered_subset(b.cs, ctx->caps_batch) || !same_force(ctx->caps_force, fp))
+            if (!ordered_subset(b.cs, ctx->caps_batch) || !same_force(ctx->caps_force, fp)) {
                 ctx->caps_slack = kCapsSlack;
+                if (!ctx->psort_off) ctx->psort_first = kPsortFirst;  // and the sort's depth
+            }
             ctx->caps = grow_caps(ctx->measured, ctx->caps_slack);
             if (ctx->tight_caps) ctx->caps.nbox = std::max(1, ctx->measured.nbox - 1);
             ctx->caps_batch = b.cs;
