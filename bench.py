@@ -47,7 +47,11 @@ PHASES = ["tree_lists_p2m", "m2m", "m2l_kernel", "m2l_reduce_l2l", "p2p_kernel",
 # then the fastest): step time depends on where a crystal's boxes are split,
 # not monotonically on the leaf size
 LEAF_CANDIDATES = (32, 64, 128, 192, 224, 256, 320, 384)
-NEAR_SHARE_CANDIDATES = (0, 4, 5)  # 0: the library's default (3 beside the upward pass, 4 after it)
+NEAR_SHARE_CANDIDATES = (0, 4, 5)
+# the timed steps record the phase events of every TIMING_EVERY-th evaluation
+# (each recorded event is a packet in the stream; recording all of them slowed
+# the step by 12-35%)
+TIMING_EVERY = 4  # 0: the library's default (3 beside the upward pass, 4 after it)
 
 
 def measured_traffic(kernel, p, leaf, precision, n):
@@ -95,16 +99,16 @@ def choose_p(c, F_dir, precision, leaf, p0, target=1e-6, pmax=16):
 
 def timed_steps(ctx, c, steps, warmup, sync, phases_too=True):
     """Wall time of `steps` steps after `warmup`.  With phases_too the timed
-    region itself carries the HIP-event phase timing (the library keeps the
-    event sets of up to 64 evaluations in flight, so the timing adds no host
-    wait), and the same steps are run again from the same state without events
-    for comparison.  Returns (seconds, phases, count, work counts, seconds of
+    region itself carries the HIP-event phase timing of every TIMING_EVERY-th
+    evaluation (the library keeps the event sets of up to 64 evaluations in
+    flight, so the timing adds no host wait), and the same steps are run again
+    from the same state without events for comparison.  Returns (seconds, phases, count, work counts, seconds of
     the uninstrumented run)."""
     c.step(warmup)
     st = c.read_state()
     sync()
     if phases_too:
-        ctx.set_timing(True)
+        ctx.set_timing(True, every=TIMING_EVERY)
     t0 = time.perf_counter()
     c.step(steps)
     ctx.synchronize()  # also reads back the queued steps' outcome (and re-runs any that overflowed)

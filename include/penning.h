@@ -279,8 +279,11 @@ pt_status pt_debug_export_tree(pt_crystal *c, int64_t sizes[4], uint64_t *keys, 
  * method has all its time in [0]) -- each the mean over the evaluations
  * since timing was last switched on (count receives their number; may be
  * NULL).
- * pt_ctx_set_timing(ctx, 1) starts a new measurement; with timing on, each
- * evaluation waits for the previous one's events before it is queued. */
+ * pt_ctx_set_timing(ctx, n) with n >= 1 starts a new measurement that
+ * records the events of every n-th evaluation (each recorded event is a
+ * packet in the stream, so a sparse n perturbs the timed steps less); 0 stops
+ * it; PT_EINVAL for n < 0.  The event sets of up to 64 evaluations stay in
+ * flight, so recording adds no host wait. */
 pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable);
 pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[7], int64_t *count);
 

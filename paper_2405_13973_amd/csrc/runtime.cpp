@@ -195,7 +195,9 @@ struct pt_ctx {
     // timing: a ring of event sets, ring_cur the set of the evaluation being
     // queued, ring_pending sets recorded and not yet collected (the oldest at
     // ring_cur - ring_pending)
-    int timing = 0;
+    int timing = 0;         // the evaluation being queued records its events
+    int timing_every = 0;   // set by pt_ctx_set_timing: record every timing_every-th evaluation (0: none)
+    int64_t timing_evals = 0;
     bool ring_made = false;
     int ring_cur = 0, ring_pending = 0;
     hipEvent_t ev[kTimingRing][kPhases] = {};
@@ -533,6 +535,7 @@ static pt_status collect_oldest(pt_ctx *ctx)
 // first when the ring is full).
 static pt_status timing_begin(pt_ctx *ctx)
 {
+    ctx->timing = ctx->timing_every > 0 && ctx->timing_evals++ % ctx->timing_every == 0 ? 1 : 0;
     if (!ctx->timing) return PT_OK;
     if (ctx->ring_pending == kTimingRing) PT_TRY(collect_oldest(ctx));
     ctx->near_timed[ctx->ring_cur] = false;
@@ -1702,6 +1705,7 @@ pt_status pt_ctx_set_near_share(pt_ctx *ctx, int per_cu)
 pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable)
 {
     PT_REQUIRE(ctx, "ctx is NULL");
+    PT_REQUIRE(enable >= 0, "timing: 0 (off) or n >= 1 (every n-th evaluation)");
     PT_TRY(settle(ctx));
     PT_TRY(finish_timing(ctx));
     if (enable && !ctx->ring_made) {
@@ -1711,7 +1715,9 @@ pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable)
             for (auto &e : pair) PT_HIP(hipEventCreate(&e));
         ctx->ring_made = true;
     }
-    ctx->timing = enable ? 1 : 0;
+    ctx->timing = 0;
+    ctx->timing_every = enable > 0 ? enable : 0;
+    ctx->timing_evals = 0;
     for (double &v : ctx->phase_sum) v = 0.0;
     ctx->phase_count = 0;
     return PT_OK;

@@ -165,8 +165,9 @@ class Context:
         _check(load().pt_ctx_memory(self.h, C.byref(used), C.byref(budget)))
         return used.value, budget.value
 
-    def set_timing(self, on: bool):
-        _check(load().pt_ctx_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, on, every: int = 1):
+        """Phase timing on (the events of every `every`-th evaluation) or off."""
+        _check(load().pt_ctx_set_timing(self.h, int(every) if on else 0))
 
     def phase_times(self, with_count=False):
         """Mean per-evaluation phase times (ms) since set_timing(True): sort+tree+lists

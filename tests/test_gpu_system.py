@@ -353,3 +353,28 @@ def test_near_field_schedules_are_bit_identical(leaf, monkeypatch):
             F, st = out[(name, prec)]
             assert np.array_equal(F0, F), (name, prec)
             assert np.array_equal(s0["pos"], st["pos"]) and np.array_equal(s0["vel"], st["vel"]), (name, prec)
+
+
+def test_phase_timing_records_every_nth_evaluation(ctx):
+    """Phase timing of every n-th evaluation: the count is the number of recorded
+    evaluations, every phase is a non-negative time, the tree phase and the near
+    field fit within the total; the steps' results do not depend on it."""
+    say("phase timing")
+    cr = inputs.config3(n=20000)
+    k = make(ctx, cr, "fmm", 11, 224)
+    k.step(2)
+    s0 = k.read_state()
+    k.step(8)
+    ref = k.read_state()
+    k.set_state(s0["pos"], s0["vel"], s0["step"])
+    ctx.set_timing(True, every=4)
+    k.step(8)
+    ph, count = ctx.phase_times(with_count=True)
+    ctx.set_timing(False)
+    assert count == 2
+    assert np.all(ph >= 0.0) and ph[6] > 0.0
+    assert ph[0] + ph[4] <= ph[6] * 1.05  # the near field starts after the tree phase, ends before the total
+    got = k.read_state()
+    assert np.array_equal(got["pos"], ref["pos"]) and np.array_equal(got["vel"], ref["vel"])
+    expect(native.PT_EINVAL, ctx.set_timing, True, -1)
+    k.destroy()
