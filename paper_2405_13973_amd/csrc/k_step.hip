@@ -15,16 +15,19 @@
 namespace pt {
 
 // Exact U0(dt/2): v rotates by -omega_c dt/2 about z; x moves along the arc.
+// Every multiply-add is an explicit fma, so that each kernel that makes the
+// half drift (the bounding-box kernel, the kick that also makes the next
+// step's drift) computes the same bits.
 __device__ inline void u0_half(const CrystalDev &c, double &x, double &y, double &z, double &vx, double &vy,
                                double vz)
 {
-    const double nx = x + vx * c.a_half + vy * c.b_half;
-    const double ny = y - vx * c.b_half + vy * c.a_half;
-    const double nvx = vx * c.c_half + vy * c.s_half;
-    const double nvy = -vx * c.s_half + vy * c.c_half;
+    const double nx = fma(vy, c.b_half, fma(vx, c.a_half, x));
+    const double ny = fma(vy, c.a_half, fma(-vx, c.b_half, y));
+    const double nvx = fma(vy, c.s_half, vx * c.c_half);
+    const double nvy = fma(vy, c.c_half, -vx * c.s_half);
     x = nx;
     y = ny;
-    z = z + vz * (0.5 * c.dt);
+    z = fma(vz, 0.5 * c.dt, z);
     vx = nvx;
     vy = nvy;
 }
@@ -55,42 +58,17 @@ __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t v0, uint64_t v1, i
     if (i < n_pairs * 6) p[i] = (i % 6) < 3 ? v0 : v1;
 }
 
-// Optional half drift of the state into the working copy (positions only
-// are copied without the drift), then per-crystal min/max of x, y, z
-// (ordered-integer atomics; min/max is exact, so the result does not depend
-// on the order).  The regions of zr are zeroed on the way (grid-stride).
-__global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
-                             int do_drift, unsigned long long *__restrict__ bbox_all, int bstride,
-                             const int32_t *__restrict__ halt, ZeroRegions zr)
+// Per-crystal min/max of the positions of the block's active threads into the
+// bounding-box copy of this workgroup (ordered-integer atomics): a wave
+// reduction when the wave is uniform in crystal, then a block reduction
+// through LDS when all its waves agree; else per-wave atomics.  Called by every
+// thread of the workgroup.
+__device__ void bbox_add(bool active, int c, double x, double y, double z, unsigned long long *__restrict__ bbox_all,
+                         int bstride)
 {
-    if (halt && *halt) return;  // a halted run: the same word for every workgroup
-    for (int r = 0; r < kZeroRegions; ++r)  // counters of the steps that follow start at zero
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < zr.n[r]; i += gridDim.x * blockDim.x)
-            zr.p[r][i] = 0ull;
     unsigned long long *bbox = bbox_all + (size_t)(blockIdx.x % kBBoxCopies) * bstride;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = g < ntot;
-    int c = 0;
     unsigned long long v[6] = {~0ull, ~0ull, ~0ull, 0ull, 0ull, 0ull};
     if (active) {
-        c = ion_crystal[g];
-        const CrystalDev &cd = cs[c];
-        const int i = g - cd.ion_off;
-        const int n = cd.n;
-        const double *s = cd.state;
-        double *m = cd.mid;
-        double x = s[i], y = s[n + i], z = s[2 * n + i];
-        if (do_drift) {
-            double vx = s[3 * n + i], vy = s[4 * n + i];
-            const double vz = s[5 * n + i];
-            u0_half(cd, x, y, z, vx, vy, vz);
-            m[3 * n + i] = vx;
-            m[4 * n + i] = vy;
-            m[5 * n + i] = vz;
-        }
-        m[i] = x;
-        m[n + i] = y;
-        m[2 * n + i] = z;
         v[0] = dbl_to_ordered(x);
         v[1] = dbl_to_ordered(y);
         v[2] = dbl_to_ordered(z);
@@ -98,8 +76,6 @@ __global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *_
         v[4] = v[1];
         v[5] = v[2];
     }
-    // wave reduction when the wave is uniform in crystal, then a block
-    // reduction through LDS when all its waves agree; else per-wave atomics
     __shared__ unsigned long long wv[4][6];
     __shared__ int wc[4];
     const unsigned long long act = __ballot(active);
@@ -154,6 +130,47 @@ __global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *_
     }
 }
 
+// Optional half drift of the state into the working copy (positions only
+// are copied without the drift), then per-crystal min/max of x, y, z
+// (ordered-integer atomics; min/max is exact, so the result does not depend
+// on the order).  The regions of zr are zeroed on the way (grid-stride).
+__global__ void k_drift_bbox(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
+                             int do_drift, unsigned long long *__restrict__ bbox_all, int bstride,
+                             const int32_t *__restrict__ halt, ZeroRegions zr)
+{
+    if (halt && *halt) return;  // a halted run: the same word for every workgroup
+    for (int r = 0; r < kZeroRegions; ++r)  // counters of the steps that follow start at zero
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < zr.n[r]; i += gridDim.x * blockDim.x)
+            zr.p[r][i] = 0ull;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = g < ntot;
+    int c = 0;
+    double x = 0.0, y = 0.0, z = 0.0;
+    if (active) {
+        c = ion_crystal[g];
+        const CrystalDev &cd = cs[c];
+        const int i = g - cd.ion_off;
+        const int n = cd.n;
+        const double *s = cd.state;
+        double *m = cd.mid;
+        x = s[i];
+        y = s[n + i];
+        z = s[2 * n + i];
+        if (do_drift) {
+            double vx = s[3 * n + i], vy = s[4 * n + i];
+            const double vz = s[5 * n + i];
+            u0_half(cd, x, y, z, vx, vy, vz);
+            m[3 * n + i] = vx;
+            m[4 * n + i] = vy;
+            m[5 * n + i] = vz;
+        }
+        m[i] = x;
+        m[n + i] = y;
+        m[2 * n + i] = z;
+    }
+    bbox_add(active, c, x, y, z, bbox_all, bstride);
+}
+
 // Root cube of every crystal (one thread each).
 __global__ void k_roots(const unsigned long long *__restrict__ bbox, int nc, int bstride, RootCube *__restrict__ roots)
 {
@@ -175,24 +192,32 @@ __global__ void k_keys(const CrystalDev *__restrict__ cs, const int32_t *__restr
 // Kick at the midpoint time and the second half drift.  E holds the Coulomb
 // field per unit charge (sum_j (x_i - x_j)/r^3) in batch order, SoA.  BEAMS:
 // some crystal of the batch uses the beam-mode laser (the variant that holds
-// the per-beam rate and count code).
-template <bool BEAMS>
+// the per-beam rate and count code).  NEXT: the next step of the same batch
+// follows, and its first half drift is done here as well, from the state
+// just computed (as k_drift_bbox would read it back): the working copy, the
+// bounding boxes, and the regions of zr zeroed.
+template <bool BEAMS, bool NEXT>
 __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
-                             int kstep, const double *__restrict__ E, TreeSummary *__restrict__ sum, int call_k)
+                             int kstep, const double *__restrict__ E, TreeSummary *__restrict__ sum, int call_k,
+                             ZeroRegions zr, unsigned long long *__restrict__ bbox_all, int bstride)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (sum && sum->halt) {
         // the step's tree or lists did not fit their buffers: the state stays
         // at the last completed step, which the host reads from fail_step
+        // (the whole grid returns: the word is the same for every workgroup)
         if (g == 0 && sum->fail_step < 0) sum->fail_step = call_k;
         return;
     }
-    if (g >= ntot) return;
-    const int c = ion_crystal[g];
+    const bool active = g < ntot;
+    int c = 0;
+    double bx = 0.0, by = 0.0, bz = 0.0;  // the next step's drifted position (NEXT)
+    if (active) {
+    c = ion_crystal[g];
     const CrystalDev &cd = cs[c];
     const int i = g - cd.ion_off;
     const int n = cd.n;
-    const double *m = cd.mid;
+    double *m = cd.mid;
     double *s = cd.state;
     double x = m[i], y = m[n + i], z = m[2 * n + i];
     double vx = m[3 * n + i], vy = m[4 * n + i], vz = m[5 * n + i];
@@ -322,6 +347,24 @@ __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *_
     if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) && isfinite(vz))) {
         *cd.nonfinite = 1;
         *cd.ctx_nonfinite = 1;
+    }
+    if constexpr (NEXT) {
+        u0_half(cd, x, y, z, vx, vy, vz);
+        m[i] = x;
+        m[n + i] = y;
+        m[2 * n + i] = z;
+        m[3 * n + i] = vx;
+        m[4 * n + i] = vy;
+        m[5 * n + i] = vz;
+        bx = x;
+        by = y;
+        bz = z;
+    }
+    }
+    if constexpr (NEXT) {
+        for (int r = 0; r < kZeroRegions; ++r)  // counters of the next evaluation start at zero
+            for (int j = g; j < zr.n[r]; j += gridDim.x * blockDim.x) zr.p[r][j] = 0ull;
+        bbox_add(active, c, bx, by, bz, bbox_all, bstride);
     }
 }
 
@@ -510,11 +553,26 @@ void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCub
 }
 
 void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
-                       bool beams, TreeSummary *sum, int call_k, hipStream_t st)
+                       bool beams, TreeSummary *sum, int call_k, const NextDrift *next, hipStream_t st)
 {
     if (ntot <= 0) return;
-    if (beams) k_kick_drift<true><<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k);
-    else k_kick_drift<false><<<ceil_div(ntot, 256), 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k);
+    const int grid = ceil_div(ntot, 256);
+    if (next) {
+        const int bs = bbox_stride(next->nc);
+        if (beams)
+            k_kick_drift<true, true><<<grid, 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k, next->zr,
+                                                           next->bbox, bs);
+        else
+            k_kick_drift<false, true><<<grid, 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k, next->zr,
+                                                            next->bbox, bs);
+    } else {
+        if (beams)
+            k_kick_drift<true, false><<<grid, 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k,
+                                                            ZeroRegions{}, nullptr, 0);
+        else
+            k_kick_drift<false, false><<<grid, 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k,
+                                                             ZeroRegions{}, nullptr, 0);
+    }
 }
 
 // The run reset (one thread).

@@ -160,8 +160,17 @@ void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCub
 // With sum non-null (the FMM), a halted run leaves the state as it was and
 // records its first such step in sum->fail_step.
 // call_k: the step's index within its pt_step_batch call (what fail_step records).
+// next (nullable): the next step of the same batch follows; its first half
+// drift is done by the same launch (as launch_drift_bbox with do_drift = 1:
+// the working copy, the bounding boxes bbox of nc crystals, zr zeroed), and
+// its evaluation then skips launch_drift_bbox.
+struct NextDrift {
+    unsigned long long *bbox;
+    int nc;
+    ZeroRegions zr;
+};
 void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
-                       bool beams, TreeSummary *sum, int call_k, hipStream_t st);
+                       bool beams, TreeSummary *sum, int call_k, const NextDrift *next, hipStream_t st);
 // Direct field into E (3 x ntot); with phi non-null also the potential per
 // unit charge sum_{j != i} 1/r_ij into phi (ntot).  tab: the nblk blocks of
 // the batch (direct_chunks); part: the crystals' partials, 4 x chunks x n

@@ -143,6 +143,7 @@ struct pt_ctx {
     int near_main = -1;   // forking before the upward pass: 1 = the far field forks, the near field stays,
                           // 0 = the near field forks, -1 = by the measured balance (PT_NEAR_MAIN)
     bool near_first = false;  // the last measured batch's near field outweighs its M2L
+    ZeroRegions last_zr{};    // words the last evaluation's drift zeroed (for a kick that makes the next drift)
     // first Morton digit the sort of a queued step orders by (the runs of
     // equal higher digits are then refined): starts at the top kSortTopLevels
     // levels, one digit lower after every run that is too long to refine, 0 =
@@ -587,8 +588,9 @@ static Caps grow_caps(const Caps &m, double slack)
 // Coulomb field per unit charge of every ion of the batch into E (3 x ntot,
 // batch order); with phi non-null also the potential per unit charge
 // (sum_{j != i} 1/r_ij, ntot).  Starts with the bounding boxes of the
-// positions, after the first half drift when drift is set (halt_aware: the
-// drift is skipped once the run has halted).
+// positions, after the first half drift when drift is 1 (halt_aware: the
+// drift is skipped once the run has halted); drift 2: the previous step's
+// kick has made the drift and the boxes already.
 //
 // With the FMM, two ways: measuring (queued == nullptr), where the host
 // reads back the tree's size and then the numbers of near-field items and
@@ -612,7 +614,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         PT_REQUIRE(b.nblk_dir > 0 || ntot == 0, "batch formed without the direct-sum block table");
         double *part;
         PT_TRY(ws_get(ctx, "dir_part", sizeof(double) * (size_t)std::max<int64_t>(1, b.dir_part), &part));
-        launch_drift_bbox(b.d_desc, b.ion_crystal, ntot, nc, drift, bbox, nullptr, ZeroRegions{}, st);
+        ctx->last_zr = ZeroRegions{};
+        if (drift != 2) launch_drift_bbox(b.d_desc, b.ion_crystal, ntot, nc, drift, bbox, nullptr, ZeroRegions{}, st);
         PT_TRY(timing_begin(ctx));
         mark(ctx, 0);
         launch_direct(b.d_desc, b.dir_tab, b.nblk_dir, b.ion_crystal, ntot, part, E, phi, st);
@@ -657,7 +660,10 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         zr.n[0] = passes <= 8 ? radix_state_zero_words() / 2 : 0;
         zr.p[1] = (uint64_t *)l2l_cnt;
         zr.n[1] = kL2LCounts / 2;
-        launch_drift_bbox(b.d_desc, b.ion_crystal, ntot, nc, drift, bbox, halt_aware ? &dsum->halt : nullptr, zr, st);
+        ctx->last_zr = zr;  // a kick that also makes the next step's drift zeroes the same words
+        if (drift != 2)
+            launch_drift_bbox(b.d_desc, b.ion_crystal, ntot, nc, drift, bbox, halt_aware ? &dsum->halt : nullptr, zr,
+                              st);
     }
     PT_TRY(timing_begin(ctx));
     mark(ctx, 0);
@@ -1518,6 +1524,7 @@ static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, co
     Batch b;
     int formed_for = -1;
     int64_t group_start = 0;  // step at which the current batch was formed
+    int drift = 1;            // 2: the previous kick made this step's first half drift
     int checks = 0, looked = 0;  // run-state copies issued, and looked at
     // Each crystal's step counter advances as its steps are queued, so that
     // after a failure it counts exactly the completed steps; a step that
@@ -1562,6 +1569,7 @@ static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, co
             PT_TRY(form_batch(ctx, act, b));
             formed_for = nactive;
             group_start = k;
+            drift = 1;
         }
         double *E;
         PT_TRY(ws_get(ctx, "E", sizeof(double) * 3 * (size_t)b.ntot, &E));
@@ -1571,7 +1579,7 @@ static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, co
         const bool queued = fmm && ctx->caps_ok && b.ntot <= ctx->caps_ntot && same_force(ctx->caps_force, fp) &&
                             ordered_subset(b.cs, ctx->caps_batch);
         ctx->eval_halted = false;
-        PT_TRY(eval_field(ctx, b, fp, E, nullptr, queued ? &ctx->caps : nullptr, 1, fmm));
+        PT_TRY(eval_field(ctx, b, fp, E, nullptr, queued ? &ctx->caps : nullptr, drift, fmm));
         if (fmm) (queued ? ctx->n_queued : ctx->n_measured)++;
         if (fmm && !queued && !ctx->eval_halted) {
             // the slack grown by overflows belongs to the batch that overflowed:
@@ -1587,9 +1595,21 @@ static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, co
             ctx->caps_force = fp;
             ctx->caps_ok = !ctx->no_queue;
         }
-        // step index = descriptor step0 (set when the batch formed) + kstep
+        // step index = descriptor step0 (set when the batch formed) + kstep;
+        // when the next step keeps this batch, the kick also makes its first
+        // half drift and bounding boxes (one launch fewer per step)
+        int next_active = 0;
+        for (int i = 0; i < n_crystals; ++i) next_active += n_steps[i] > k + 1;
+        const bool fuse = k + 1 < kmax && next_active == nactive;
+        NextDrift nd{};
+        if (fuse) {
+            nd.bbox = (unsigned long long *)ctx->ws["bbox"].ptr;
+            nd.nc = (int)b.cs.size();
+            nd.zr = ctx->last_zr;
+        }
         launch_kick_drift(b.d_desc, b.ion_crystal, b.ntot, (int)(k - group_start), E, b.beams, dsum, (int)k,
-                          ctx->stream);
+                          fuse ? &nd : nullptr, ctx->stream);
+        drift = fuse ? 2 : 1;
         for (pt_crystal *c : b.cs) c->step++;
     }
     PT_HIP(hipGetLastError());
