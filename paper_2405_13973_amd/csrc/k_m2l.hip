@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_m2l_emit(BoxTable bt, const TreeSummary
 // from LDS with one 16-byte read; the e-th matrix-core instruction of the
 // step takes element e of both, i.e. the contraction runs over a fixed
 // permutation of k, the same for every product.
-template <typename T, int NRB>
+template <typename T, int NRB, int STEPS>
 __global__ __launch_bounds__(kGemmThreads) void k_m2l_gemm(const TreeSummary *__restrict__ sum, int Kp, int nrg, int zrow,
                                                            const int32_t *__restrict__ chunk_off_g,
                                                            const int32_t *__restrict__ op_beg_g,
@@ -257,19 +257,22 @@ __global__ __launch_bounds__(kGemmThreads) void k_m2l_gemm(const TreeSummary *__
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int strideE = Kp + VEC;  // row stride of the LDS operator rows (16-byte reads without bank conflicts)
     T *As = reinterpret_cast<T *>(smem_raw);                               // [ROWS][strideE]
-    uint8_t *cbits = reinterpret_cast<uint8_t *>(As + (size_t)ROWS * strideE);  // [Kp]
+    // sign of coefficient k under reflection mask m: sgn[m * Kp + k] (0 or 1)
+    uint8_t *sgn = reinterpret_cast<uint8_t *>(As + (size_t)ROWS * strideE);  // [8][Kp]
     __shared__ int32_t chunk_off[kOps + 1], op_beg[kOps + 1];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int i = tid; i <= kOps; i += kGemmThreads) {
         chunk_off[i] = chunk_off_g[i];
         op_beg[i] = op_beg_g[i];
     }
-    for (int i = tid; i < Kp; i += kGemmThreads) cbits[i] = (uint8_t)refl_bits(i);
+    for (int i = tid; i < 8 * Kp; i += kGemmThreads) sgn[i] = (uint8_t)(__popc((i / Kp) & refl_bits(i % Kp)) & 1);
     __syncthreads();
     const int U = chunk_off[kOps];
     const long units = (long)U * nrg;
     const int u0 = (int)(units * blockIdx.x / gridDim.x), u1 = (int)(units * (blockIdx.x + 1) / gridDim.x);
-    const int steps = Kp / (4 * VEC);
+    // STEPS > 0: the step count, fixed at compile time (a multiple of three)
+    constexpr bool TRIPLE = STEPS > 0;
+    const int steps = TRIPLE ? STEPS : Kp / (4 * VEC);
     const int j = lane & 15, q = lane >> 4;
     // a unit's operator, row group and pair range, and this lane's pair
     struct Unit {
@@ -289,14 +292,16 @@ __global__ __launch_bounds__(kGemmThreads) void k_m2l_gemm(const TreeSummary *__
         t.pe = col < t.end ? bucket[col] : make_int4(zrow, -1, 0, 0);
         return t;
     };
-    // 16 bytes of a pair's source coefficients for step s, with its column signs
-    auto load_b = [&](const int4 &pe, int s) {
-        V v = *reinterpret_cast<const V *>(M + (size_t)pe.x * Kp + q * VEC + (size_t)s * 4 * VEC);
+    // 16 bytes of source coefficients of box `box` for step s
+    auto load_b = [&](int box, int s) {
+        return *reinterpret_cast<const V *>(M + (size_t)box * Kp + q * VEC + (size_t)s * 4 * VEC);
+    };
+    // their column signs, applied when step s uses them
+    auto signed_b = [&](V v, int m, int s) {
+        const uint8_t *g = sgn + m * Kp + s * 4 * VEC + q * VEC;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            const int k = s * 4 * VEC + q * VEC + e;
-            if (__popc(pe.z & cbits[k]) & 1) v.v[e] = -v.v[e];
-        }
+        for (int e = 0; e < VEC; ++e)
+            if (g[e]) v.v[e] = -v.v[e];
         return v;
     };
     // operator rows of a step from LDS
@@ -308,12 +313,21 @@ __global__ __launch_bounds__(kGemmThreads) void k_m2l_gemm(const TreeSummary *__
     if (u0 >= u1) return;
     int cur_op = -1, cur_rg = -1;
     Unit cu = unit_of(u0);
-    V b0, b1;
-    bool pre = false;  // b0, b1 already hold the current unit's first two steps
+    // Source coefficients sit in three register slots, step s in slot s % 3,
+    // loaded two steps ahead of their use, so each load's wait comes right
+    // before its use and no register copy waits for it.  With a step count
+    // fixed at compile time (a multiple of three) the steps are straight-
+    // line code and every step issues its load: the last two steps of a unit
+    // load the next unit's first two (slots 0 and 1), or repeat this unit's
+    // when it is the last, so the compiler can count each load's wait.
+    // Otherwise the unit's first two steps are loaded at its start and the
+    // tail is guarded.
+    V bq0, bq1, bq2;
+    if (TRIPLE) {
+        bq0 = load_b(cu.pe.x, 0);
+        bq1 = load_b(cu.pe.x, 1);
+    }
     for (int u = u0; u < u1; ++u) {
-        // the next unit's pair entry is fetched now and its first source loads
-        // are issued during this unit's last two steps, so the matrix work runs
-        // on without a gap between units
         const bool has_next = u + 1 < u1;
         Unit nx = cu;
         if (has_next) nx = unit_of(u + 1);
@@ -334,33 +348,50 @@ __global__ __launch_bounds__(kGemmThreads) void k_m2l_gemm(const TreeSummary *__
             cur_op = cu.op;
             cur_rg = cu.rg;
         }
-        if (!pre) {
-            b0 = load_b(cu.pe, 0);
-            b1 = steps > 1 ? load_b(cu.pe, 1) : b0;
+        if (!TRIPLE) {
+            bq0 = load_b(cu.pe.x, 0);
+            if (steps > 1) bq1 = load_b(cu.pe.x, 1);
         }
         typename MF::v4 acc[NRB];
 #pragma unroll
         for (int r = 0; r < NRB; ++r) acc[r] = typename MF::v4{0, 0, 0, 0};
         V a0[NRB], a1[NRB];
         load_a(0, a0);
-        const bool cross = has_next && steps >= 2;
-        for (int s = 0; s < steps; ++s) {
-            V b2 = b1;
-            if (s + 2 < steps) b2 = load_b(cu.pe, s + 2);
-            else if (cross) b2 = load_b(nx.pe, s + 2 - steps);
-            if (s + 1 < steps) load_a(s + 1, a1);
+        // one step: load step s + 2 into slot `to` (past the end: the next
+        // unit's step s + 2 - steps), then multiply with slot `use`
+        auto step = [&](int s, const V &use, V &to) {
+            const int ns = s + 2;
+            if (TRIPLE) {
+                const bool in = ns < steps;
+                to = load_b(in ? cu.pe.x : nx.pe.x, in ? ns : ns - steps);
+            } else if (ns < steps) {
+                to = load_b(cu.pe.x, ns);
+            }
+            // keep the load here: the scheduler would otherwise sink it to
+            // its use two steps on and wait for it there
+            __builtin_amdgcn_sched_barrier(0);
+            load_a(min(s + 1, steps - 1), a1);
+            const V bs = signed_b(use, cu.pe.z, s);
             // consecutive instructions update different accumulators, so
             // none waits for the previous one's result
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
 #pragma unroll
-                for (int r = 0; r < NRB; ++r) acc[r] = MF::op(a0[r].v[e], b0.v[e], acc[r]);
+                for (int r = 0; r < NRB; ++r) acc[r] = MF::op(a0[r].v[e], bs.v[e], acc[r]);
 #pragma unroll
             for (int r = 0; r < NRB; ++r) a0[r] = a1[r];
-            b0 = b1;
-            b1 = b2;
+        };
+        auto three = [&](int s) {
+            step(s, bq0, bq2);
+            if (TRIPLE || s + 1 < steps) step(s + 1, bq1, bq0);
+            if (TRIPLE || s + 2 < steps) step(s + 2, bq2, bq1);
+        };
+        if constexpr (TRIPLE) {
+#pragma unroll
+            for (int s = 0; s < STEPS; s += 3) three(s);
+        } else {
+            for (int s = 0; s < steps; s += 3) three(s);
         }
-        pre = cross;
         if (cu.pe.y >= 0) {
             const int row0 = cu.rg * ROWS;
             T *dst = R + (size_t)cu.pe.y * Kp + row0;
@@ -371,7 +402,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_m2l_gemm(const TreeSummary *__
                     const int row = r * 16 + MF::row(lane, e);
                     if (row0 + row < Kp) {
                         const T v = acc[r][e];
-                        dst[row] = (__popc(cu.pe.z & cbits[row0 + row]) & 1) ? -v : v;
+                        dst[row] = sgn[cu.pe.z * Kp + row0 + row] ? -v : v;
                     }
                 }
         }
@@ -461,7 +492,7 @@ size_t m2l_gemm_lds(int Kp)
 {
     int nrg;
     const int nrb = m2l_row_blocks<T>(Kp, nrg);
-    return (size_t)nrb * 16 * (Kp + 16 / sizeof(T)) * sizeof(T) + (size_t)Kp;
+    return (size_t)nrb * 16 * (Kp + 16 / sizeof(T)) * sizeof(T) + (size_t)8 * Kp;
 }
 
 template <typename T>
@@ -479,10 +510,18 @@ void launch_m2l_gemm(const TreeSummary *sum, int Kp, int nbox, int grid, const i
     int nrg;
     const int nrb = m2l_row_blocks<T>(Kp, nrg);
     const size_t lds = m2l_gemm_lds<T>(Kp);
+    const int steps = Kp / (4 * (16 / (int)sizeof(T)));
+    // order 11 (144 coefficients) runs with its step count fixed at compile time
+    constexpr int kFixed = 144 / (4 * (16 / (int)sizeof(T)));
     switch (nrb) {
-#define PT_G(NB) \
-    case NB:                                                                                                    \
-        k_m2l_gemm<T, NB><<<grid, kGemmThreads, lds, st>>>(sum, Kp, nrg, nbox, chunk_off, op_beg, bucket, A, M, R); \
+#define PT_G(NB)                                                                                          \
+    case NB:                                                                                              \
+        if (steps == kFixed)                                                                              \
+            k_m2l_gemm<T, NB, kFixed>                                                                     \
+                <<<grid, kGemmThreads, lds, st>>>(sum, Kp, nrg, nbox, chunk_off, op_beg, bucket, A, M, R); \
+        else                                                                                              \
+            k_m2l_gemm<T, NB, 0>                                                                          \
+                <<<grid, kGemmThreads, lds, st>>>(sum, Kp, nrg, nbox, chunk_off, op_beg, bucket, A, M, R); \
         break;
         PT_G(1) PT_G(2) PT_G(3) PT_G(4) PT_G(5) PT_G(6)
 #undef PT_G
