@@ -10,7 +10,8 @@
 // components.  So every V pair (T, S) is a matrix-vector product with one of
 // 56 base matrices plus sign flips, and the pairs that share a base matrix
 // form one GEMM:
-//   1. pairs are counted per target and per base operator, and scans give
+//   1. pairs are counted per target and per base operator (with the V
+//      lists, in the box-list kernel of the tree code), and scans give
 //      each pair a row in a result buffer R (targets in box order, a target's
 //      pairs in the order of its parity's slot table) and a place in its
 //      operator's bucket (operators in order, then boxes, then slots);
@@ -37,16 +38,11 @@ namespace pt {
 
 namespace {
 
-constexpr int kOps = 64;       // base operator slots (56 used)
-constexpr int kSlots = 189;    // non-touching window slots per parity
-constexpr int kCols = 64;      // pairs per work unit (16 per wave)
+constexpr int kOps = kM2LOps;
+constexpr int kSlots = kM2LSlots;
+constexpr int kCols = 64;  // pairs per work unit (16 per wave)
 constexpr int kGemmThreads = 256;
-constexpr int kOpSlices = 16;  // copies of the operator totals: the counting workgroups' atomics spread over them
-
-__device__ inline int parity_of(const BoxTable &bt, int b)
-{
-    return ((bt.ix[b] & 1) << 2) | ((bt.iy[b] & 1) << 1) | (bt.iz[b] & 1);
-}
+constexpr int kOpSlices = kM2LOpSlices;
 
 template <typename T>
 struct MfmaOp;
@@ -72,43 +68,8 @@ struct Vec16 {
 
 }  // namespace
 
-// Pass 1, one workgroup per box: the V pairs of a target box of level >= 2
-// (its parity's 189 slots with a source), counted in total (pcnt[b]) and per
-// base operator (cnt_ob[o * nbox + b]).
-__global__ __launch_bounds__(256) void k_m2l_count(BoxTable bt, const TreeSummary *__restrict__ sum,
-                                                   const int32_t *__restrict__ vtab, const int2 *__restrict__ slots,
-                                                   uint32_t *__restrict__ pcnt, uint32_t *__restrict__ cnt_ob,
-                                                   uint32_t *__restrict__ op_total)
-{
-    __shared__ uint32_t per_op[kOps];
-    __shared__ uint32_t total;
-    const int b = blockIdx.x, tid = threadIdx.x;
-    const int nbox = sum->nbox;
-    if (sum->halt) return;
-    if (b >= nbox) {  // the grid may cover a capacity past the tree: no pairs
-        if (tid == 0) pcnt[b] = 0;
-        return;
-    }
-    if (tid < kOps) per_op[tid] = 0;
-    if (tid == 0) total = 0;
-    __syncthreads();
-    if (bt.level[b] >= 2 && tid < kSlots) {
-        const int2 s = slots[parity_of(bt, b) * kSlots + tid];
-        if (vtab[(size_t)b * kWin + s.x] >= 0) {
-            atomicAdd(&per_op[s.y & 255], 1u);
-            atomicAdd(&total, 1u);
-        }
-    }
-    __syncthreads();
-    if (tid < kOps) {
-        cnt_ob[(size_t)tid * nbox + b] = per_op[tid];
-        if (per_op[tid]) atomicAdd(&op_total[(b % kOpSlices) * kOps + tid], per_op[tid]);  // integer sums: any order
-    }
-    if (tid == 0) pcnt[b] = total;
-}
-
-// Pass 1b, one launch of kOps + 4 workgroups (kScanThreads each) after the
-// counts: workgroup o < kOps scans its operator's row of cnt_ob from the
+// Pass 1, one launch of kOps + 4 workgroups (kScanThreads each) after the
+// counts of the box lists: workgroup o < kOps scans its operator's row of cnt_ob from the
 // operator's first bucket place (the totals of the operators before it), so
 // the places are those of one scan of cnt_ob in (operator, box) order;
 // workgroup kOps scans pcnt, kOps + 1 the near-field item counts, kOps + 2
@@ -200,7 +161,7 @@ __global__ __launch_bounds__(256) void k_m2l_emit(BoxTable bt, const TreeSummary
     wave_op_cnt[w][lane] = 0;
     int src = -1, opw = 0;
     if (tid < kSlots) {
-        const int2 s = slots[parity_of(bt, b) * kSlots + tid];
+        const int2 s = slots[box_parity(bt, b) * kSlots + tid];
         src = vtab[(size_t)b * kWin + s.x];
         opw = s.y;
     }
@@ -453,13 +414,11 @@ __global__ void k_m2l_sum(const TreeSummary *__restrict__ sum, int Kp, const uin
 
 // ---------------------------------------------------------------- launchers
 
-void launch_m2l_count(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
-                      uint32_t *pcnt, uint32_t *cnt_ob, uint32_t *op_total, uint32_t *npairs, uint32_t *item_off,
-                      uint32_t *n_items, int32_t *op_beg, int32_t *chunk_off, const int64_t *near_pairs,
-                      unsigned long long *near_total, hipStream_t st)
+void launch_list_scans(const TreeSummary *sum, int nbox, uint32_t *pcnt, uint32_t *cnt_ob, const uint32_t *op_total,
+                       uint32_t *npairs, uint32_t *item_off, uint32_t *n_items, int32_t *op_beg, int32_t *chunk_off,
+                       const int64_t *near_pairs, unsigned long long *near_total, hipStream_t st)
 {
     if (nbox <= 0) return;
-    k_m2l_count<<<nbox, 256, 0, st>>>(bt, sum, vtab, slots, pcnt, cnt_ob, op_total);
     k_list_scans<<<kOps + 4, kScanThreads, 0, st>>>(sum, nbox, pcnt, cnt_ob, op_total, npairs, item_off, n_items,
                                                     op_beg, chunk_off, near_pairs, near_total);
 }

@@ -696,42 +696,6 @@ __global__ __launch_bounds__(256) void k_oct_colleagues(BoxTable bt, const TreeS
                ((int)blockIdx.x - ncb) * 256 + threadIdx.x, ((int)gridDim.x - ncb) * 256);
 }
 
-// V lists into the dense window table (-1 = no source), one thread per
-// (box, window cell).  Window cell (wx, wy, wz) of a box with parity
-// (cx, cy, cz) is the same-level box at offset (wx-2-cx, wy-2-cy, wz-2-cz);
-// its parent is the colleague of the box's parent in slot
-// (wx>>1, wy>>1, wz>>1) and it sits in that parent's octant
-// (wx&1, wy&1, wz&1).  Cells touching the box are not in the list.
-constexpr int kVBoxes = 8;  // boxes per workgroup
-__global__ void k_vlist(BoxTable bt, const TreeSummary *__restrict__ sum, const int32_t *__restrict__ coll,
-                        const int32_t *__restrict__ child_oct, int32_t *__restrict__ vtab,
-                        int32_t *__restrict__ v_blk)
-{
-    __shared__ int cnt_s;
-    if (threadIdx.x == 0) cnt_s = 0;
-    __syncthreads();
-    const int nbox = sum->halt ? 0 : sum->nbox;
-    int cnt = 0;
-    for (int e = threadIdx.x; e < kVBoxes * kWin; e += blockDim.x) {
-        const int b = blockIdx.x * kVBoxes + e / kWin, w = e % kWin;
-        if (b >= nbox) break;
-        int src = -1;
-        if (bt.level[b] >= 2) {
-            const int wx = w / 36, wy = (w / 6) % 6, wz = w % 6;
-            const int dx = wx - 2 - (bt.ix[b] & 1), dy = wy - 2 - (bt.iy[b] & 1), dz = wz - 2 - (bt.iz[b] & 1);
-            if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) {
-                const int Q = coll[(size_t)bt.parent[b] * kNeigh + (wx >> 1) * 9 + (wy >> 1) * 3 + (wz >> 1)];
-                if (Q >= 0) src = child_oct[(size_t)Q * 8 + (((wx & 1) << 2) | ((wy & 1) << 1) | (wz & 1))];
-            }
-        }
-        vtab[(size_t)b * kWin + w] = src;
-        cnt += src >= 0;
-    }
-    if (cnt) atomicAdd(&cnt_s, cnt);
-    __syncthreads();
-    if (threadIdx.x == 0) v_blk[blockIdx.x] = cnt_s;  // V pairs of the workgroup's boxes
-}
-
 // Near lists of the leaves: ion ranges, stride entries per box.  The near
 // field of a leaf is then cut into work items of at most kP2PChunk sources
 // (cut at range boundaries) times chunks of 64 targets, so that no single
@@ -751,25 +715,45 @@ __device__ inline int p2p_src_items(const int2 *row, int cnt, int32_t *cut)
     return items + (acc > 0 ? 1 : 0);
 }
 
-// One wave per box.  Ranges are appended in a fixed order -- the leaf's own
-// colleagues (slot order, itself included), then the leaf colleagues of each
-// ancestor from the parent up (slot order, the ancestor itself excluded) --
-// compacted with ballots, staged in LDS and written out coalesced.
-__global__ __launch_bounds__(64) void k_nearlist(BoxTable bt, const TreeSummary *__restrict__ sum,
-                                                 const int32_t *__restrict__ coll, int stride,
-                                                 int2 *__restrict__ near, int32_t *__restrict__ near_cnt,
-                                                 uint32_t *__restrict__ items, int32_t *__restrict__ src_items,
-                                                 int32_t *__restrict__ cuts, int64_t *__restrict__ pairs)
+// The lists of one box, one workgroup of 256 threads per box.
+//
+// V list into the dense window table (-1 = no source), one thread per window
+// cell.  Window cell (wx, wy, wz) of a box with parity (cx, cy, cz) is the
+// same-level box at offset (wx-2-cx, wy-2-cy, wz-2-cz); its parent is the
+// colleague of the box's parent in slot (wx>>1, wy>>1, wz>>1) and it sits in
+// that parent's octant (wx&1, wy&1, wz&1).  Cells touching the box are not in
+// the list.  Its V pairs are then counted in total (pcnt) and per base
+// operator (cnt_ob, a row per operator), the operator totals added into one
+// of the kM2LOpSlices slices of op_total.
+//
+// Near list of a leaf (the first wave): ion ranges, stride entries per box,
+// appended in a fixed order -- the leaf's own colleagues (slot order, itself
+// included), then the leaf colleagues of each ancestor from the parent up
+// (slot order, the ancestor itself excluded) -- compacted with ballots,
+// staged in LDS and written out coalesced; then its near-field work items
+// are counted.
+__global__ __launch_bounds__(256) void k_box_lists(BoxTable bt, const TreeSummary *__restrict__ sum,
+                                                   const int32_t *__restrict__ coll,
+                                                   const int32_t *__restrict__ child_oct, int32_t *__restrict__ vtab,
+                                                   const int2 *__restrict__ slots, uint32_t *__restrict__ pcnt,
+                                                   uint32_t *__restrict__ cnt_ob, uint32_t *__restrict__ op_total,
+                                                   int stride, int2 *__restrict__ near, int32_t *__restrict__ near_cnt,
+                                                   uint32_t *__restrict__ items, int32_t *__restrict__ src_items,
+                                                   int32_t *__restrict__ cuts, int64_t *__restrict__ pairs)
 {
+    __shared__ int32_t win_s[kWin];
+    __shared__ uint32_t per_op[kM2LOps];
+    __shared__ uint32_t vtot_s;
     __shared__ int2 row_s[kNearMax];
     __shared__ int anc_s[kMaxLevel + 1];
     __shared__ int nanc_s;
-    const int b = blockIdx.x, lane = threadIdx.x;
+    const int b = blockIdx.x, tid = threadIdx.x;
     if (sum->halt) return;
     // the grid may cover more boxes than the tree has (a capacity): those
-    // count zero items, so that the scan of the item counts stays exact
-    if (b >= sum->nbox || !bt.leaf[b]) {
-        if (lane == 0) {
+    // count no V pairs and no items, so that the scans of the counts stay exact
+    if (b >= sum->nbox) {
+        if (tid == 0) {
+            pcnt[b] = 0;
             near_cnt[b] = 0;
             items[b] = 0;
             src_items[b] = 0;
@@ -777,50 +761,95 @@ __global__ __launch_bounds__(64) void k_nearlist(BoxTable bt, const TreeSummary 
         }
         return;
     }
-    if (lane == 0) {
+    const bool v_box = bt.level[b] >= 2, leaf = bt.leaf[b];
+    if (tid < kWin) {
+        const int w = tid;
+        int src = -1;
+        if (v_box) {
+            const int wx = w / 36, wy = (w / 6) % 6, wz = w % 6;
+            const int dx = wx - 2 - (bt.ix[b] & 1), dy = wy - 2 - (bt.iy[b] & 1), dz = wz - 2 - (bt.iz[b] & 1);
+            if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) {
+                const int Q = coll[(size_t)bt.parent[b] * kNeigh + (wx >> 1) * 9 + (wy >> 1) * 3 + (wz >> 1)];
+                if (Q >= 0) src = child_oct[(size_t)Q * 8 + (((wx & 1) << 2) | ((wy & 1) << 1) | (wz & 1))];
+            }
+        }
+        vtab[(size_t)b * kWin + w] = src;
+        win_s[w] = src;
+    }
+    if (tid < kM2LOps) per_op[tid] = 0;
+    if (tid == 0) {
+        vtot_s = 0;
         int n = 0;
-        for (int A = bt.parent[b]; A >= 0 && n <= kMaxLevel; A = bt.parent[A]) anc_s[n++] = A;
+        if (leaf)
+            for (int A = bt.parent[b]; A >= 0 && n <= kMaxLevel; A = bt.parent[A]) anc_s[n++] = A;
         nanc_s = n;
     }
     __syncthreads();
-    const int nanc = nanc_s;
-    const uint64_t below = (1ull << lane) - 1ull;
+    if (v_box && tid < kM2LSlots) {
+        const int2 sl = slots[box_parity(bt, b) * kM2LSlots + tid];
+        if (win_s[sl.x] >= 0) {
+            atomicAdd(&per_op[sl.y & 255], 1u);
+            atomicAdd(&vtot_s, 1u);
+        }
+    }
+    // the near list, in the first wave (its ballots are the wave's)
+    const int lane = tid & 63;
     int cnt = 0;
     long long srcs = 0;
-    auto append = [&](int Q) {
-        const bool v = Q >= 0;
-        const uint64_t m = __ballot(v);
-        const int at = cnt + __popcll(m & below);
-        if (v && at < kNearMax) {
-            const int2 rg = make_int2(bt.begin[Q], bt.end[Q]);
-            row_s[at] = rg;
-            srcs += rg.y - rg.x;
+    if (leaf && tid < 64) {
+        const int nanc = nanc_s;
+        const uint64_t below = (1ull << lane) - 1ull;
+        auto append = [&](int Q) {
+            const bool v = Q >= 0;
+            const uint64_t m = __ballot(v);
+            const int at = cnt + __popcll(m & below);
+            if (v && at < kNearMax) {
+                const int2 rg = make_int2(bt.begin[Q], bt.end[Q]);
+                row_s[at] = rg;
+                srcs += rg.y - rg.x;
+            }
+            cnt += __popcll(m);
+        };
+        append(lane < kNeigh ? coll[(size_t)b * kNeigh + lane] : -1);
+        for (int a0 = 0; a0 < nanc; a0 += 2) {
+            const int a = a0 + (lane >> 5), s = lane & 31;
+            int Q = -1;
+            if (a < nanc && s < kNeigh && s != 13) {
+                Q = coll[(size_t)anc_s[a] * kNeigh + s];
+                if (Q >= 0 && !bt.leaf[Q]) Q = -1;
+            }
+            append(Q);
         }
-        cnt += __popcll(m);
-    };
-    append(lane < kNeigh ? coll[(size_t)b * kNeigh + lane] : -1);
-    for (int a0 = 0; a0 < nanc; a0 += 2) {
-        const int a = a0 + (lane >> 5), s = lane & 31;
-        int Q = -1;
-        if (a < nanc && s < kNeigh && s != 13) {
-            Q = coll[(size_t)anc_s[a] * kNeigh + s];
-            if (Q >= 0 && !bt.leaf[Q]) Q = -1;
-        }
-        append(Q);
-    }
-    cnt = min(cnt, min(stride, kNearMax));  // stride = 27 + 26 x (levels - 1) bounds cnt
+        cnt = min(cnt, min(stride, kNearMax));  // stride = 27 + 26 x (levels - 1) bounds cnt
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) srcs += __shfl_xor(srcs, off);
+        for (int off = 32; off > 0; off >>= 1) srcs += __shfl_xor(srcs, off);
+    }
     __syncthreads();
-    int2 *row = near + (size_t)b * stride;
-    for (int r = lane; r < cnt; r += 64) row[r] = row_s[r];
-    if (lane == 0) {
-        near_cnt[b] = cnt;
-        const long long nt = bt.end[b] - bt.begin[b];
-        const int si = p2p_src_items(row_s, cnt, cuts + (size_t)b * stride);
-        src_items[b] = si;
-        items[b] = (uint32_t)(si * ((nt + 63) / 64));
-        pairs[b] = nt * srcs - nt;  // near-field pairs of the leaf (self excluded)
+    if (tid < kM2LOps) {
+        cnt_ob[(size_t)tid * sum->nbox + b] = per_op[tid];
+        if (per_op[tid]) atomicAdd(&op_total[(b % kM2LOpSlices) * kM2LOps + tid], per_op[tid]);  // integer sums
+    }
+    if (tid == 0) pcnt[b] = vtot_s;
+    if (tid < 64) {
+        if (!leaf) {
+            if (tid == 0) {
+                near_cnt[b] = 0;
+                items[b] = 0;
+                src_items[b] = 0;
+                pairs[b] = 0;
+            }
+            return;
+        }
+        int2 *row = near + (size_t)b * stride;
+        for (int r = lane; r < cnt; r += 64) row[r] = row_s[r];
+        if (lane == 0) {
+            near_cnt[b] = cnt;
+            const long long nt = bt.end[b] - bt.begin[b];
+            const int si = p2p_src_items(row_s, cnt, cuts + (size_t)b * stride);
+            src_items[b] = si;
+            items[b] = (uint32_t)(si * ((nt + 63) / 64));
+            pairs[b] = nt * srcs - nt;  // near-field pairs of the leaf (self excluded)
+        }
     }
 }
 
@@ -944,18 +973,17 @@ void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64
     k_tree_links<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum);
 }
 
-int vlist_blocks(int nbox) { return ceil_div(nbox, kVBoxes); }
-
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
-                  int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
-                  int32_t *parent_oct, uint32_t *l2l_cnt, int32_t *l2l_list, const ZeroRegions &zr,
-                  uint32_t *item_off, int32_t *src_items, int32_t *cuts, hipStream_t st)
+                  int2 *near, int32_t *near_cnt, int64_t *near_pairs, int32_t *child_oct, int32_t *parent_oct,
+                  uint32_t *l2l_cnt, int32_t *l2l_list, const ZeroRegions &zr, uint32_t *item_off,
+                  int32_t *src_items, int32_t *cuts, const int2 *slots, uint32_t *pcnt, uint32_t *cnt_ob,
+                  uint32_t *op_total, hipStream_t st)
 {
     const int ncb = ceil_div(nbox * kNeigh, 256);
     k_oct_colleagues<<<ncb + ceil_div(nbox, 256), 256, 0, st>>>(bt, sum, coll, ncb, child_oct, parent_oct, l2l_cnt,
                                                                 l2l_list, nbox, zr);
-    k_vlist<<<vlist_blocks(nbox), 256, 0, st>>>(bt, sum, coll, child_oct, vtab, v_blk);
-    k_nearlist<<<nbox, 64, 0, st>>>(bt, sum, coll, stride, near, near_cnt, item_off, src_items, cuts, near_pairs);
+    k_box_lists<<<nbox, 256, 0, st>>>(bt, sum, coll, child_oct, vtab, slots, pcnt, cnt_ob, op_total, stride, near,
+                                      near_cnt, item_off, src_items, cuts, near_pairs);
 }
 
 void launch_p2p_items(const BoxTable &bt, TreeSummary *sum, int nbox, const int32_t *near_cnt, int stride,

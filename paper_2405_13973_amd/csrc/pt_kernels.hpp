@@ -14,6 +14,19 @@ struct BoxTable {
     double4 *geo;     // centre xyz, side h
 };
 
+// M2L by base operator: operator slots (56 used), non-touching window slots
+// per parity, and the slices of the operator totals (the counting
+// workgroups' atomics spread over them)
+constexpr int kM2LOps = 64;
+constexpr int kM2LSlots = 189;
+constexpr int kM2LOpSlices = 16;
+
+// parity (ix & 1, iy & 1, iz & 1) of box b as a 3-bit number
+__device__ inline int box_parity(const BoxTable &bt, int b)
+{
+    return ((bt.ix[b] & 1) << 2) | ((bt.iy[b] & 1) << 1) | (bt.iz[b] & 1);
+}
+
 // Workgroup scans (blockDim.x a multiple of 64).
 // Exclusive scan of one value per thread; block_total gets the sum.  lds_w:
 // blockDim.x / 64 + 1 words.
@@ -252,9 +265,7 @@ void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64
 // Also counts the near-field work items {leaf, first target, range begin,
 // range end}: item_off (nbox, scanned in place to offsets), src_items (nbox),
 // n_items (device total).  launch_p2p_items then writes them into work.
-// Work counts: v_blk (vlist_blocks(nbox) ints) = V pairs per group of boxes,
-// near_pairs (nbox) = near-field pairs per leaf.
-int vlist_blocks(int nbox);
+// Work counts: near_pairs (nbox) = near-field pairs per leaf.
 // L2L buckets: the boxes of levels >= 3 by tree level and octant,
 // l2l_list[o * nbox + level_start[l] + i] for i < l2l_cnt[8 l + o] (order
 // within a bucket unspecified: every box's result is computed alone);
@@ -262,11 +273,18 @@ int vlist_blocks(int nbox);
 constexpr int kL2LCounts = 8 * (kMaxLevel + 1);
 static_assert(kL2LCounts % 2 == 0, "L2L counts are cleared as 64-bit words");
 // zr: 64-bit words to zero on the way (the first kernel clears them).
-// item_off gets the item counts per leaf; launch_m2l_count scans them.
+// item_off gets the item counts per leaf; launch_list_scans scans them.
+// The V pairs are counted on the way: per box (pcnt, nbox) and per
+// (operator, box) (cnt_ob, kM2LOps rows of the tree's box count), with the
+// operator totals added into op_total (m2l_op_total_words() words, slices of
+// kM2LOps, zero beforehand: one of the zr regions).  slots: per parity the
+// kM2LSlots non-touching window slots {slot, base operator + 256 x
+// reflection mask}.
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,
-                  int2 *near, int32_t *near_cnt, int32_t *v_blk, int64_t *near_pairs, int32_t *child_oct,
-                  int32_t *parent_oct, uint32_t *l2l_cnt, int32_t *l2l_list, const ZeroRegions &zr,
-                  uint32_t *item_off, int32_t *src_items, int32_t *cuts, hipStream_t st);
+                  int2 *near, int32_t *near_cnt, int64_t *near_pairs, int32_t *child_oct, int32_t *parent_oct,
+                  uint32_t *l2l_cnt, int32_t *l2l_list, const ZeroRegions &zr, uint32_t *item_off,
+                  int32_t *src_items, int32_t *cuts, const int2 *slots, uint32_t *pcnt, uint32_t *cnt_ob,
+                  uint32_t *op_total, hipStream_t st);
 // cuts (stride per box): first near range of each source item of a leaf.
 // check (nullable, a queued evaluation): near-field items (total[1]) and M2L
 // pairs (total[2]) must fit their capacities, else the run halts here and no
@@ -330,11 +348,7 @@ void launch_run_reset(TreeSummary *sum, hipStream_t st);
 // k_m2l.hip: M2L organised by base operator.
 // slots: per parity the 189 non-touching window slots {slot, base operator +
 // 256 x reflection mask (bit 0: dx < 0, bit 1: dy < 0, bit 2: dz < 0)}.
-// launch_m2l_count: the V pairs counted per box (pcnt, nbox) and per
-// (operator, box) (cnt_ob, m2l_ops() rows of the tree's box count), with the
-// operator totals added into op_total (m2l_op_total_words() words, slices of
-// m2l_ops(), zero beforehand);
-// then one launch scans them all in place: pcnt -> first row of R per box
+// launch_list_scans: one launch scans the list counts in place: pcnt -> first row of R per box
 // (*npairs <- the number of V pairs), cnt_ob -> first bucket place per
 // (operator, box), item_off (nbox item counts of the near field) -> first
 // item per leaf (*n_items <- their number), and writes the operator table
@@ -343,10 +357,9 @@ void launch_run_reset(TreeSummary *sum, hipStream_t st);
 // the near-field pairs per leaf (near_pairs, nbox).
 int m2l_ops();
 int m2l_op_total_words();
-void launch_m2l_count(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
-                      uint32_t *pcnt, uint32_t *cnt_ob, uint32_t *op_total, uint32_t *npairs, uint32_t *item_off,
-                      uint32_t *n_items, int32_t *op_beg, int32_t *chunk_off, const int64_t *near_pairs,
-                      unsigned long long *near_total, hipStream_t st);
+void launch_list_scans(const TreeSummary *sum, int nbox, uint32_t *pcnt, uint32_t *cnt_ob, const uint32_t *op_total,
+                       uint32_t *npairs, uint32_t *item_off, uint32_t *n_items, int32_t *op_beg, int32_t *chunk_off,
+                       const int64_t *near_pairs, unsigned long long *near_total, hipStream_t st);
 // bucket: npairs int4 {source box, row of R, reflection mask, 0}.
 void launch_m2l_emit(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
                      const uint32_t *pair_off, const uint32_t *ob_off, int4 *bucket, hipStream_t st);

@@ -766,9 +766,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "l2l_list", sizeof(int32_t) * 8 * (size_t)nbox, &l2l_list));
     PT_TRY(ws_get(ctx, "item_off", sizeof(uint32_t) * (size_t)nbox, &item_off));
     PT_TRY(ws_get(ctx, "src_items", sizeof(int32_t) * (size_t)nbox, &src_items));
-    int32_t *v_blk;
     int64_t *near_pairs;
-    PT_TRY(ws_get(ctx, "v_blk", sizeof(int32_t) * (size_t)vlist_blocks(nbox), &v_blk));
     PT_TRY(ws_get(ctx, "near_pairs", sizeof(int64_t) * (size_t)nbox, &near_pairs));
     int32_t *cuts;
     PT_TRY(ws_get(ctx, "p2p_cuts", sizeof(int32_t) * (size_t)stride * nbox, &cuts));
@@ -793,15 +791,16 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         zr.n[0] = zr.n[1] = (int)(esz * Kp / 8);
         zr.n[2] = 1;
         zr.n[3] = m2l_op_total_words() / 2;
-        launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, v_blk, near_pairs, child_oct, parent_oct,
-                     l2l_cnt, l2l_list, zr, item_off, src_items, cuts, st);
+        launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, near_pairs, child_oct, parent_oct, l2l_cnt,
+                     l2l_list, zr, item_off, src_items, cuts, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, m2l_op_total,
+                     st);
     }
-    // M2L pairs: counted and scanned here, so that their number comes back
-    // with the near-field item count
+    // M2L pairs: counted with the lists and scanned here, so that their
+    // number comes back with the near-field item count
     unsigned long long *near_total;
     PT_TRY(ws_get(ctx, "near_total", sizeof(unsigned long long), &near_total));
-    launch_m2l_count(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, m2l_op_total, total + 2,
-                     item_off, total + 1, m2l_op_beg, m2l_chunk_off, near_pairs, near_total, st);
+    launch_list_scans(dsum, nbox, m2l_pcnt, m2l_cnt_ob, m2l_op_total, total + 2, item_off, total + 1, m2l_op_beg,
+                      m2l_chunk_off, near_pairs, near_total, st);
     // near-field work items and M2L pairs: their numbers size the item,
     // partial and pair buffers.  Measuring, they are read back (the host waits
     // for an event right after the copy, not for the stream); queued, the
@@ -1773,12 +1772,12 @@ pt_status pt_ctx_work_counts(pt_ctx *ctx, int64_t counts[6])
     TreeSummary ls;
     PT_TRY(read_summary(ctx, ls));
     const int nbox = ls.nbox;
-    std::vector<int32_t> vb(vlist_blocks(ctx->last_cap.nbox));
     std::vector<int64_t> np(nbox);
-    PT_HIP(hipMemcpy(vb.data(), ctx->ws["v_blk"].ptr, vb.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    uint32_t tot[4];
+    PT_HIP(hipMemcpy(tot, ctx->ws["total"].ptr, sizeof(tot), hipMemcpyDeviceToHost));
     PT_HIP(hipMemcpy(np.data(), ctx->ws["near_pairs"].ptr, np.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
-    int64_t nv = 0, nn = 0;
-    for (int32_t x : vb) nv += x;
+    const int64_t nv = tot[2];  // V pairs: the scan total of the last evaluation's per-box counts
+    int64_t nn = 0;
     for (int64_t x : np) nn += x;
     std::vector<uint8_t> leaf(nbox);
     PT_HIP(hipMemcpy(leaf.data(), ctx->ws["b_leaf"].ptr, nbox, hipMemcpyDeviceToHost));
