@@ -672,7 +672,8 @@ __global__ __launch_bounds__(256) void k_far(BoxTable bt, const double *__restri
                                             const uint32_t *__restrict__ item_off,
                                             const int32_t *__restrict__ src_items, const T *__restrict__ part,
                                             const uint32_t *__restrict__ vals, double *__restrict__ E,
-                                            double *__restrict__ PHI, const TreeSummary *__restrict__ sum)
+                                            double *__restrict__ PHI, const TreeSummary *__restrict__ sum,
+                                            int2 *__restrict__ poff)
 {
     constexpr int NC = POT ? 4 : 3;
     __shared__ T rec_s[kRecFields * kq(kMaxP)];
@@ -708,6 +709,8 @@ __global__ __launch_bounds__(256) void k_far(BoxTable bt, const double *__restri
             fz = (double)ez * ih * ih;
             fv = (double)ev * ih;
         }
+        if constexpr (MODE == 1)
+            if (poff) poff[gi] = make_int2((int)((base + (tl >> 6) * si) * 64 + (tl & 63)), si);
         if constexpr (MODE != 1) {
             const T *pp = part + ((size_t)(base + (tl >> 6) * si) * 64 + (tl & 63)) * NC;
             for (int j = 0; j < si; ++j, pp += 64 * NC) {
@@ -852,7 +855,7 @@ size_t near_lds_bytes()
 template <typename T>
 void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, int p, int nbox, const T *L,
                 const T *rec, const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals,
-                double *E, double *phi, int leaf_size, int mode, hipStream_t st)
+                double *E, double *phi, int leaf_size, int mode, hipStream_t st, int2 *poff)
 {
     // one thread per ion of a leaf where the leaf size allows
     const int tb = std::min(256, std::max(64, (leaf_size + 63) / 64 * 64));
@@ -860,10 +863,10 @@ void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, in
 #define PT_FAR(M)                                                                                                   \
     if (phi)                                                                                                        \
         k_far<T, true, M><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals, E, \
-                                               phi, sum);                                                           \
+                                               phi, sum, nullptr);                                                  \
     else                                                                                                            \
         k_far<T, false, M><<<nbox, tb, 0, st>>>(bt, sp, ntot, p, kpad(p), L, rec, item_off, src_items, part, vals,  \
-                                                E, nullptr, sum);
+                                                E, nullptr, sum, poff);
     if (mode == 1) {
         PT_FAR(1)
     } else if (mode == 2) {
@@ -886,7 +889,7 @@ void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, in
                                  const int4 *, const uint32_t *, int, T *, bool, int, int *, hipStream_t);         \
     template void launch_far<T>(const BoxTable &, const TreeSummary *, const double *, int, int, int, const T *,     \
                                 const T *, const uint32_t *, const int32_t *, const T *, const uint32_t *, double *, \
-                                double *, int, int, hipStream_t);
+                                double *, int, int, hipStream_t, int2 *);
 PT_INST(float)
 PT_INST(double)
 #undef PT_INST

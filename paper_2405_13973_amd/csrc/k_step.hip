@@ -190,7 +190,10 @@ __global__ void k_keys(const CrystalDev *__restrict__ cs, const int32_t *__restr
 }
 
 // Kick at the midpoint time and the second half drift.  E holds the Coulomb
-// field per unit charge (sum_j (x_i - x_j)/r^3) in batch order, SoA.  BEAMS:
+// field per unit charge (sum_j (x_i - x_j)/r^3) in batch order, SoA, or,
+// with kp.part set, its far field, to which the ion's near-field item
+// partials are added here in item order (as the far-field kernel would add
+// them, the same FP64 values).  BEAMS:
 // some crystal of the batch uses the beam-mode laser (the variant that holds
 // the per-beam rate and count code).  NEXT: the next step of the same batch
 // follows, and its first half drift is done here as well, from the state
@@ -199,7 +202,7 @@ __global__ void k_keys(const CrystalDev *__restrict__ cs, const int32_t *__restr
 template <bool BEAMS, bool NEXT>
 __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *__restrict__ ion_crystal, int ntot,
                              int kstep, const double *__restrict__ E, TreeSummary *__restrict__ sum, int call_k,
-                             ZeroRegions zr, unsigned long long *__restrict__ bbox_all, int bstride)
+                             ZeroRegions zr, unsigned long long *__restrict__ bbox_all, int bstride, KickPartials kp)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (sum && sum->halt) {
@@ -242,9 +245,28 @@ __global__ void k_kick_drift(const CrystalDev *__restrict__ cs, const int32_t *_
         fx -= w * (x * C - y * S);
         fy += w * (y * C + x * S);
     }
-    fx += cd.coul * E[g];
-    fy += cd.coul * E[ntot + g];
-    fz += cd.coul * E[2 * ntot + g];
+    double ex = E[g], ey = E[ntot + g], ez = E[2 * ntot + g];
+    if (kp.part) {
+        const int2 po = kp.poff[g];
+        if (kp.f32) {
+            const float *pp = static_cast<const float *>(kp.part) + (size_t)po.x * 3;
+            for (int j = 0; j < po.y; ++j, pp += 64 * 3) {
+                ex += (double)pp[0];
+                ey += (double)pp[1];
+                ez += (double)pp[2];
+            }
+        } else {
+            const double *pp = static_cast<const double *>(kp.part) + (size_t)po.x * 3;
+            for (int j = 0; j < po.y; ++j, pp += 64 * 3) {
+                ex += pp[0];
+                ey += pp[1];
+                ez += pp[2];
+            }
+        }
+    }
+    fx += cd.coul * ex;
+    fy += cd.coul * ey;
+    fz += cd.coul * ez;
     const double vmx = vx, vmy = vy, vmz = vz;  // midpoint velocity, before the kick (beam rates)
     const double kdt = cd.dt * cd.inv_m;
     vx += fx * kdt;
@@ -553,25 +575,27 @@ void launch_keys(const CrystalDev *cs, const int32_t *ion_crystal, const RootCub
 }
 
 void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
-                       bool beams, TreeSummary *sum, int call_k, const NextDrift *next, hipStream_t st)
+                       bool beams, TreeSummary *sum, int call_k, const NextDrift *next, const KickPartials *kp,
+                       hipStream_t st)
 {
     if (ntot <= 0) return;
     const int grid = ceil_div(ntot, 256);
+    const KickPartials k = kp ? *kp : KickPartials{nullptr, nullptr, 0};
     if (next) {
         const int bs = bbox_stride(next->nc);
         if (beams)
             k_kick_drift<true, true><<<grid, 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k, next->zr,
-                                                           next->bbox, bs);
+                                                           next->bbox, bs, k);
         else
             k_kick_drift<false, true><<<grid, 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k, next->zr,
-                                                            next->bbox, bs);
+                                                            next->bbox, bs, k);
     } else {
         if (beams)
             k_kick_drift<true, false><<<grid, 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k,
-                                                            ZeroRegions{}, nullptr, 0);
+                                                            ZeroRegions{}, nullptr, 0, k);
         else
             k_kick_drift<false, false><<<grid, 256, 0, st>>>(cs, ion_crystal, ntot, kstep, E, sum, call_k,
-                                                             ZeroRegions{}, nullptr, 0);
+                                                             ZeroRegions{}, nullptr, 0, k);
     }
 }
 

@@ -182,8 +182,19 @@ struct NextDrift {
     int nc;
     ZeroRegions zr;
 };
+// Near-field item partials the kick adds to E itself (in place of launch_far
+// mode 2, with the same values and order of additions): part (FP32 when f32,
+// else FP64; 3 components), and per ion (batch order) poff = {first partial
+// row, number of source items}, the rows 64 apart.
+struct KickPartials {
+    const void *part;
+    const int2 *poff;
+    int f32;
+};
+// kp (nullable): E holds the far field only, and the kick adds the partials.
 void launch_kick_drift(const CrystalDev *cs, const int32_t *ion_crystal, int ntot, int kstep, const double *E,
-                       bool beams, TreeSummary *sum, int call_k, const NextDrift *next, hipStream_t st);
+                       bool beams, TreeSummary *sum, int call_k, const NextDrift *next, const KickPartials *kp,
+                       hipStream_t st);
 // Direct field into E (3 x ntot); with phi non-null also the potential per
 // unit charge sum_{j != i} 1/r_ij into phi (ntot).  tab: the nblk blocks of
 // the batch (direct_chunks); part: the crystals' partials, 4 x chunks x n
@@ -337,11 +348,12 @@ size_t near_lds_bytes();
 // Far field (L2P) + the item partials per ion into E (batch order); with phi
 // non-null also the potential per unit charge (part then holds 4 components).
 // mode 0: both; 1: the far field only (into E / phi); 2: adds the partials to
-// what mode 1 stored (the same values as mode 0).
+// what mode 1 stored (the same values as mode 0).  poff (nullable, mode 1):
+// each ion's partial rows for a kick that adds them (KickPartials).
 template <typename T>
 void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, int p, int nbox, const T *L,
                 const T *rec, const uint32_t *item_off, const int32_t *src_items, const T *part, const uint32_t *vals,
-                double *E, double *phi, int leaf_size, int mode, hipStream_t st);
+                double *E, double *phi, int leaf_size, int mode, hipStream_t st, int2 *poff = nullptr);
 // Starts a run: halt = 0, fail_step = -1.
 void launch_run_reset(TreeSummary *sum, hipStream_t st);
 

@@ -600,9 +600,10 @@ static Caps grow_caps(const Caps &m, double slack)
 // back, and a count above its capacity halts the run on the device (the
 // step's kick then leaves the state as it was, see TreeSummary).
 static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, double *E, double *phi,
-                            const Caps *queued, int drift, bool halt_aware)
+                            const Caps *queued, int drift, bool halt_aware, KickPartials *leave = nullptr)
 {
     hipStream_t st = ctx->stream;
+    if (leave) *leave = KickPartials{nullptr, nullptr, 0};
     const int ntot = b.ntot, nc = (int)b.cs.size();
     unsigned long long *bbox;
     PT_TRY(ws_get(ctx, "bbox", sizeof(unsigned long long) * bbox_words(nc), &bbox));
@@ -855,6 +856,17 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         // stream.
         const bool concurrent = ctx->near_concurrent > 0 || (ctx->near_concurrent < 0 && s >= kConcurrentLeaf);
         const bool early = concurrent && (ctx->near_early >= 0 ? ctx->near_early > 0 : f);
+        // beside the near field, a kick that follows can add the near-field
+        // partials itself (the last far-field launch then falls away)
+        int2 *poff = nullptr;
+        if (leave && concurrent && !phi) PT_TRY(ws_get(ctx, "poff", sizeof(int2) * (size_t)ntot, &poff));
+        auto finish = [&]() {
+            if (poff)
+                *leave = KickPartials{ppart, poff, f ? 1 : 0};
+            else
+                launch_far<T>(bt, dsum, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart,
+                              v0, E, phi, s, concurrent ? 2 : 0, st);
+        };
         const int near_cap = ctx->near_per_cu > 0 ? ctx->near_per_cu : early ? kNearPerCUEarly : kNearPerCUConcurrent;
         hipStream_t ns = concurrent ? ctx->near_stream : st;
         // translations that leave room for their waves beside a large near field
@@ -891,13 +903,12 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             launch_downward<T>(bt, dsum, p, cap, l2l, tb.oct_slots, parent_oct, l2l_cnt, l2l_list, (T *)L, narrow, ns);
             mark(ctx, 4, ns);
             launch_far<T>(bt, dsum, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E,
-                          phi, s, 1, ns);
+                          phi, s, 1, ns, poff);
             mark(ctx, 5, ns);
             PT_HIP(hipEventRecord(ctx->ev_join, ns));
             PT_TRY(near_field(st));
             PT_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
-            launch_far<T>(bt, dsum, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E,
-                          phi, s, 2, st);
+            finish();
             return PT_OK;
         }
         auto fork = [&]() -> pt_status {
@@ -928,12 +939,11 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             // beside the near field, the far field of every ion is evaluated
             // before the join and the near-field partials added after it
             launch_far<T>(bt, dsum, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0,
-                          E, phi, s, 1, st);
+                          E, phi, s, 1, st, poff);
         }
         mark(ctx, 5);
         if (concurrent) PT_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
-        launch_far<T>(bt, dsum, sp, ntot, p, nbox, (const T *)L, rec, item_off, src_items, (const T *)ppart, v0, E,
-                      phi, s, concurrent ? 2 : 0, st);
+        finish();
         return PT_OK;
     };
     PT_TRY(fp.precision == 1 ? run(float(0)) : run(double(0)));
@@ -1578,7 +1588,8 @@ static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, co
         const bool queued = fmm && ctx->caps_ok && b.ntot <= ctx->caps_ntot && same_force(ctx->caps_force, fp) &&
                             ordered_subset(b.cs, ctx->caps_batch);
         ctx->eval_halted = false;
-        PT_TRY(eval_field(ctx, b, fp, E, nullptr, queued ? &ctx->caps : nullptr, drift, fmm));
+        KickPartials kp{};
+        PT_TRY(eval_field(ctx, b, fp, E, nullptr, queued ? &ctx->caps : nullptr, drift, fmm, &kp));
         if (fmm) (queued ? ctx->n_queued : ctx->n_measured)++;
         if (fmm && !queued && !ctx->eval_halted) {
             // the slack grown by overflows belongs to the batch that overflowed:
@@ -1607,7 +1618,7 @@ static pt_status step_run(pt_ctx *ctx, pt_crystal *const *cs, int n_crystals, co
             nd.zr = ctx->last_zr;
         }
         launch_kick_drift(b.d_desc, b.ion_crystal, b.ntot, (int)(k - group_start), E, b.beams, dsum, (int)k,
-                          fuse ? &nd : nullptr, ctx->stream);
+                          fuse ? &nd : nullptr, kp.part ? &kp : nullptr, ctx->stream);
         drift = fuse ? 2 : 1;
         for (pt_crystal *c : b.cs) c->step++;
     }
