@@ -47,7 +47,11 @@ PHASES = ["tree_lists_p2m", "m2m", "m2l_kernel", "m2l_reduce_l2l", "p2p_kernel",
 # then the fastest): step time depends on where a crystal's boxes are split,
 # not monotonically on the leaf size
 LEAF_CANDIDATES = (32, 64, 128, 192, 224, 256, 320, 384)
-NEAR_SHARE_CANDIDATES = (0, 4, 5)
+# (near-field workgroups per CU, fork direction) pairs the schedule tuner tries:
+# share 0 = the library default, fork -1 = by the measured balance, 0 = the
+# near field forks to the second stream (schedule parameters: no effect on the
+# results)
+SCHEDULE_CANDIDATES = ((0, -1), (4, -1), (5, -1), (4, 0), (5, 0))
 # the timed steps record the phase events of every TIMING_EVERY-th evaluation
 # (each recorded event is a packet in the stream; recording all of them slowed
 # the step by 12-35%)
@@ -368,6 +372,32 @@ def tune_batch(ctx, cs, leaves, p_fixed, p0, precision, sync, time_it=True, targ
     return best[0], best[1], best[2]
 
 
+def tune_schedule(ctx, a, run, work, what):
+    """The fastest (near share, fork direction) of SCHEDULE_CANDIDATES, set on
+    the context; run(share, fork) returns the seconds of `work` ion-steps.
+    Given shares or fork directions are kept (a fork of -2 means tuned, or -1
+    when the share is given)."""
+    if a.near_share >= 0:
+        cands = [(a.near_share, a.fork if a.fork >= -1 else -1)]
+    elif a.fork >= -1:
+        cands = [(s, a.fork) for s in sorted({s for s, _ in SCHEDULE_CANDIDATES})]
+    else:
+        cands = list(SCHEDULE_CANDIDATES)
+    best = None
+    for share, fork in cands:
+        ctx.set_near_share(share)
+        ctx.set_fork(fork)
+        if len(cands) == 1:
+            return share, fork
+        el = run(share, fork)
+        log(f"  {what} near share {share} fork {fork}: {work / el:.4g} ion-steps/s")
+        if best is None or el < best[2]:
+            best = (share, fork, el)
+    ctx.set_near_share(best[0])
+    ctx.set_fork(best[1])
+    return best[0], best[1]
+
+
 def bench_ensemble(a, ctx, sync):
     """Batched ensemble: independent crystals stepped together, one launch per
     phase per step for all of them."""
@@ -385,8 +415,24 @@ def bench_ensemble(a, ctx, sync):
     leaves = (a.leaf,) if a.leaf else BATCH_LEAVES
     a.leaf, a.p, errs = tune_batch(ctx, cs, leaves, a.p, a.p0, a.precision, sync, time_it=len(leaves) > 1)
     for c, cr in zip(cs, crs):
-        c.set_state(cr.pos, cr.vel, 0)
         c.set_force("fmm", a.p, a.leaf, a.precision)
+
+    def run(share, fork):
+        best = 1e30
+        for _ in range(2):
+            for c, cr in zip(cs, crs):
+                c.set_state(cr.pos, cr.vel, 0)
+            native.step_batch(cs, [2] * len(cs))
+            sync()
+            t0 = time.perf_counter()
+            native.step_batch(cs, [10] * len(cs))
+            sync()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    share, fork = tune_schedule(ctx, a, run, 10 * ntot, "ensemble")
+    for c, cr in zip(cs, crs):
+        c.set_state(cr.pos, cr.vel, 0)
     native.step_batch(cs, [a.warmup] * len(cs))
     ctx.synchronize()
     sync()
@@ -413,7 +459,8 @@ def bench_ensemble(a, ctx, sync):
         "dtype": "f32+f64" if a.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": f"{len(crs)} crystals, {ntot} ions, spheres at 1000 ions/(100 um)^3, B~U[2,5] T, "
                                f"f_z~U[1,2] MHz, photon mean~U[0,0.05], FMM p={a.p} leaf {a.leaf} ({a.precision})",
-                   "crystals": len(crs), "ions": ntot, "p": a.p, "leaf_size": a.leaf,
+                   "crystals": len(crs), "ions": ntot, "p": a.p, "leaf_size": a.leaf, "near_share": share,
+                   "fork": fork,
                    "max_rms_rel_force_err_largest3": max(errs)},
         "details": {"phase_ms": {k: float(v) for k, v in zip(PHASES, phases)}, "step_evaluations": stats},
     }
@@ -528,6 +575,9 @@ def main():
     ap.add_argument("--p0", type=int, default=10, help="first p tried when choosing p")
     ap.add_argument("--near-share", type=int, default=-1,
                     help="near-field workgroups per compute unit beside the far field (-1: tuned; 0: default)")
+    ap.add_argument("--fork", type=int, default=-2,
+                    help="branch that keeps the stream at an early fork (1 near field, 0 far field, -1 by the "
+                         "measured balance; -2: tuned with the share, or -1 when --near-share is given)")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
@@ -604,23 +654,17 @@ def main():
         return best[:3]
 
     def tune_share(prec, leaf, p):
-        """Near-field workgroups per compute unit beside the far field (a
-        schedule parameter, no effect on the results): the fastest of the
-        candidates over two runs of 20 steps each, unless given."""
-        if a.near_share >= 0:
-            ctx.set_near_share(a.near_share)
-            return a.near_share
-        best = None
-        for share in NEAR_SHARE_CANDIDATES:
-            ctx.set_near_share(share)
+        """Near-field workgroups per compute unit beside the far field and the
+        fork direction (schedule parameters, no effect on the results): the
+        fastest of the candidates over two runs of 20 steps each, unless
+        given."""
+        def run(share, fork):
             c.set_state(cr.pos, cr.vel, 0)
             c.set_force("fmm", p, leaf, prec)
-            el = min(timed_steps(ctx, c, 20, 2, sync, phases_too=False)[0] for _ in range(2))
-            log(f"  {prec} leaf {leaf} near share {share}: {20 * cr.n / el:.4g} ion-steps/s")
-            if best is None or el < best[1]:
-                best = (share, el)
-        ctx.set_near_share(best[0])
-        return best[0]
+            return min(timed_steps(ctx, c, 20, 2, sync, phases_too=False)[0] for _ in range(2))
+
+        share, fork = tune_schedule(ctx, a, run, 20 * cr.n, f"{prec} leaf {leaf}")
+        return share, fork
 
     results = {}
     forms = [a.precision] + ([] if a.no_fp64_compare or a.precision == "fp64" else ["fp64"])
@@ -628,7 +672,7 @@ def main():
         # each form at its own best leaf size (the same candidates, the same bound)
         leaves = (a.leaf,) if a.leaf else LEAF_CANDIDATES
         leaf, p, err = tune(prec, leaves)
-        share = tune_share(prec, leaf, p)
+        share, fork = tune_share(prec, leaf, p)
         c.set_state(cr.pos, cr.vel, 0)
         c.set_force("fmm", p, leaf, prec)
         sync()
@@ -639,7 +683,7 @@ def main():
         F_end = c.compute_forces()
         c.set_force("fmm", p, leaf, prec)
         err_end = rms_rel(c.compute_forces(), F_end)
-        results[prec] = dict(p=p, leaf=leaf, share=share, err=err, err_end=err_end, seconds=el, phases=phases,
+        results[prec] = dict(p=p, leaf=leaf, share=share, fork=fork, err=err, err_end=err_end, seconds=el, phases=phases,
                              count=count, wc=wc, plain=plain)
         log(f"  {prec}: p={p} leaf={leaf} {a.steps} steps in {el * 1e3:.2f} ms -> {cr.n * a.steps / el:.4g} "
             f"ion-steps/s (without events {plain * 1e3:.2f} ms); rms err start {err:.2e} end {err_end:.2e}; "
@@ -659,6 +703,7 @@ def main():
     main_r = results[a.precision]
     p, leaf = main_r["p"], main_r["leaf"]
     ctx.set_near_share(main_r["share"])  # the legs on the same crystal below
+    ctx.set_fork(main_r["fork"])
     K = (p + 1) ** 2
     ph = main_r["phases"]
     fp32 = a.precision == "mixed"
@@ -710,6 +755,7 @@ def main():
             "workload": f"{cr.n} ions, 5%-jittered cubic lattice in a (400,400,800) um prolate ellipsoid, "
                         f"B=4.5 T, f_z=1.5 MHz, dt=1 ns, FMM p={p} leaf {leaf} ({a.precision})",
             "n_ions": cr.n, "p": p, "leaf_size": leaf, "precision": a.precision, "near_share": main_r["share"],
+            "fork": main_r["fork"],
             "rms_rel_force_err": main_r["err"], "rms_rel_force_err_after_timed_steps": main_r["err_end"],
         },
         "roofline": rooflines[kernel],
@@ -731,6 +777,7 @@ def main():
         out["details"]["fp64_p"] = f["p"]
         out["details"]["fp64_leaf_size"] = f["leaf"]
         out["details"]["fp64_near_share"] = f["share"]
+        out["details"]["fp64_fork"] = f["fork"]
         out["details"]["fp64_rms_rel_force_err"] = f["err"]
         out["details"]["fp64_rms_rel_force_err_after_timed_steps"] = f["err_end"]
         out["details"]["mixed_speedup_vs_fp64"] = f["seconds"] / main_r["seconds"]
@@ -749,8 +796,8 @@ def main():
         out["potential"]["gpu_over_cpu"] = (out["potential"]["ion_evals_per_s"] /
                                             out["cpu_baseline"]["potential_ion_evals_per_s"])
     c.destroy()
-    # the batched workloads run in a context of their own (as with --workload),
-    # on the library's default schedule
+    # the batched workloads run in a context of their own (as with --workload);
+    # serving keeps the schedule the ensemble tuner set on it
     ctx.close()
     ctx = native.Context(0, hbm_budget=(a.budget_gb << 30) + (4 << 30), stream=stream.cuda_stream)
     if not a.no_ensemble:

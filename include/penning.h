@@ -296,6 +296,17 @@ pt_status pt_ctx_phase_times(pt_ctx *ctx, double ms[7], int64_t *count);
  * waits for pending steps. */
 pt_status pt_ctx_set_near_share(pt_ctx *ctx, int per_cu);
 
+/* Which branch keeps the context's stream when the FMM evaluation forks the
+ * near field off before the upward pass (the mixed form with leaves of 128
+ * ions or more; a schedule parameter, which changes no result): 1 = the near
+ * field stays and the far field (upward pass, M2L, L2L, far-field L2P) goes
+ * to the second stream, 0 = the near field goes there, -1 (the default) =
+ * chosen from the last measured batch's balance (the near field stays when
+ * it has more than 2000 ordered pairs per V pair or the batch has fewer than
+ * 1e6 V pairs).  The environment variable PT_NEAR_MAIN sets it at context
+ * creation.  PT_EINVAL for another value; waits for pending steps. */
+pt_status pt_ctx_set_fork(pt_ctx *ctx, int mode);
+
 /* Work counts of the last FMM evaluation: [0] boxes, [1] leaves, [2] M2L
  * pairs, [3] P2P pairs (ordered, i != j counted), [4] levels, [5] ions. */
 pt_status pt_ctx_work_counts(pt_ctx *ctx, int64_t counts[6]);

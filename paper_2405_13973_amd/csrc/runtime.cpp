@@ -1732,6 +1732,15 @@ pt_status pt_ctx_set_near_share(pt_ctx *ctx, int per_cu)
     return PT_OK;
 }
 
+pt_status pt_ctx_set_fork(pt_ctx *ctx, int mode)
+{
+    PT_REQUIRE(ctx, "ctx is NULL");
+    PT_REQUIRE(mode >= -1 && mode <= 1, "fork direction must be -1 (by the measured balance), 0 or 1");
+    PT_TRY(settle(ctx));
+    ctx->near_main = mode;
+    return PT_OK;
+}
+
 pt_status pt_ctx_set_timing(pt_ctx *ctx, int enable)
 {
     PT_REQUIRE(ctx, "ctx is NULL");

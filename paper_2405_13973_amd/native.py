@@ -102,6 +102,7 @@ def load():
         "pt_debug_export_tree": [_vp, C.POINTER(C.c_int64)] + [_vp] * 13,
         "pt_ctx_set_timing": [_vp, C.c_int],
         "pt_ctx_set_near_share": [_vp, C.c_int],
+        "pt_ctx_set_fork": [_vp, C.c_int],
         "pt_ctx_phase_times": [_vp, _dp, C.POINTER(C.c_int64)],
         "pt_ctx_work_counts": [_vp, C.POINTER(C.c_int64)],
         "pt_ctx_step_stats": [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
@@ -181,6 +182,11 @@ class Context:
     def set_near_share(self, per_cu):
         """Near-field workgroups per compute unit beside the far field (0: default)."""
         _check(load().pt_ctx_set_near_share(self.h, int(per_cu)))
+
+    def set_fork(self, mode):
+        """Branch that keeps the stream at an early fork: 1 the near field, 0 the
+        far field, -1 by the measured balance (the default)."""
+        _check(load().pt_ctx_set_fork(self.h, int(mode)))
 
     def work_counts(self):
         c = np.zeros(6, np.int64)

@@ -226,6 +226,8 @@ def test_invalid_inputs_return_status_codes(ctx):
     expect(native.PT_EINVAL, native.step_batch, [c], [-1])
     expect(native.PT_EINVAL, ctx.set_near_share, -1)
     expect(native.PT_EINVAL, ctx.set_near_share, 9)
+    expect(native.PT_EINVAL, ctx.set_fork, -2)
+    expect(native.PT_EINVAL, ctx.set_fork, 2)
     # the parameters in force before the rejected calls still work
     c.step(2)
     assert c.read_state()["step"] == 2
@@ -331,6 +333,8 @@ def test_near_field_schedules_are_bit_identical(leaf, monkeypatch):
                 "beside, early fork, 5 per CU": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1"}, 5),
                 "beside, early fork, near field forked": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1",
                                                            "PT_NEAR_MAIN": "0"}, 0),
+                "beside, early fork, near field forked, 4 per CU (set on the context)": (
+                    {"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "1"}, (4, 0)),
                 "beside, late fork": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "0"}, 0),
                 "beside, late fork, 2 per CU": ({"PT_NEAR_CONCURRENT": "1", "PT_NEAR_EARLY": "0"}, 2)}
     out = {}
@@ -340,7 +344,10 @@ def test_near_field_schedules_are_bit_identical(leaf, monkeypatch):
         for k, v in env.items():
             monkeypatch.setenv(k, v)
         with native.Context(0) as c:
+            share, fork = share if isinstance(share, tuple) else (share, None)
             c.set_near_share(share)
+            if fork is not None:
+                c.set_fork(fork)
             for prec in ("mixed", "fp64"):
                 k = make(c, cr, "fmm", 11, leaf, prec)
                 F = k.compute_forces()
