@@ -579,12 +579,12 @@ __global__ __launch_bounds__(256) void k_tree_emit(const CrystalDev *__restrict_
     }
 }
 
-// Parent / children by binary search over the neighbouring levels (boxes of
-// one level are ordered by their first ion).
-__global__ void k_tree_links(BoxTable bt, const TreeSummary *__restrict__ sum)
+// Parent / children of box b by binary search over the neighbouring levels
+// (boxes of one level are ordered by their first ion), written to the box
+// table and returned.
+__device__ inline void box_links(BoxTable bt, const TreeSummary *__restrict__ sum, int b, int &parent_out,
+                                 int &child_out, int &nch_out)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (sum->halt || b >= sum->nbox) return;
     const int l = bt.level[b];
     const int beg = bt.begin[b];
     int parent = -1;
@@ -619,27 +619,33 @@ __global__ void k_tree_links(BoxTable bt, const TreeSummary *__restrict__ sum)
     }
     bt.child[b] = child;
     bt.nchild[b] = nch;
+    parent_out = parent;
+    child_out = child;
+    nch_out = nch;
 }
 
-// Source maps of the M2M / L2L translation GEMMs, 8 slots per box indexed by
-// octant: child_oct[b][o] = child of b in octant o, parent_oct[b][o] = parent
-// of b in b's own octant slot (-1 elsewhere); and the L2L buckets (boxes of
-// levels >= 3 by level and octant, l2l_cnt zeroed beforehand).
-// Thread b of nthreads (b: the box); the regions of zr are zeroed on the
-// way (grid-stride over the nthreads).
-__device__ void oct_tables(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ child_oct,
-                           int32_t *__restrict__ parent_oct, uint32_t *__restrict__ l2l_cnt,
-                           int32_t *__restrict__ l2l_list, int list_stride, const ZeroRegions &zr, int b, int nthreads)
+// The links of box b (box_links) and the source maps of the M2M / L2L
+// translation GEMMs, 8 slots per box indexed by octant: child_oct[b][o] =
+// child of b in octant o, parent_oct[b][o] = parent of b in b's own octant
+// slot (-1 elsewhere); and the L2L buckets (boxes of levels >= 3 by level and
+// octant, l2l_cnt zeroed beforehand).  Thread b of nthreads (b: the box); the
+// regions of zr are zeroed on the way (grid-stride over the nthreads).
+__device__ void links_oct_tables(BoxTable bt, const TreeSummary *__restrict__ sum, int32_t *__restrict__ child_oct,
+                                 int32_t *__restrict__ parent_oct, uint32_t *__restrict__ l2l_cnt,
+                                 int32_t *__restrict__ l2l_list, int list_stride, const ZeroRegions &zr, int b,
+                                 int nthreads)
 {
     for (int r = 0; r < kZeroRegions; ++r)  // words the later kernels need zeroed
         for (int i = b; i < zr.n[r]; i += nthreads) zr.p[r][i] = 0ull;
     if (sum->halt || b >= sum->nbox) return;
+    int parent, child, nch;
+    box_links(bt, sum, b, parent, child, nch);
     int32_t ch[8], pa[8];
     for (int o = 0; o < 8; ++o) ch[o] = pa[o] = -1;
-    for (int c = bt.child[b], e = c + bt.nchild[b]; c < e; ++c)
+    for (int c = child, e = child + nch; c < e; ++c)
         ch[((bt.ix[c] & 1) << 2) | ((bt.iy[c] & 1) << 1) | (bt.iz[c] & 1)] = c;
     const int oct = ((bt.ix[b] & 1) << 2) | ((bt.iy[b] & 1) << 1) | (bt.iz[b] & 1);
-    pa[oct] = bt.parent[b];
+    pa[oct] = parent;
     for (int o = 0; o < 8; ++o) {
         child_oct[(size_t)b * 8 + o] = ch[o];
         parent_oct[(size_t)b * 8 + o] = pa[o];
@@ -679,8 +685,9 @@ __device__ void colleagues(BoxTable bt, const TreeSummary *__restrict__ sum, int
 }
 
 // Colleagues (the first ncb workgroups, one thread per (box, slot)) and the
-// octant tables (the rest, one thread per box) in one launch: both read only
-// the box table.
+// links with the octant tables (the rest, one thread per box) in one launch:
+// both read only the box table the tree emitter wrote (the links of a box are
+// computed by its own thread before its octant tables use them).
 __global__ __launch_bounds__(256) void k_oct_colleagues(BoxTable bt, const TreeSummary *__restrict__ sum,
                                                         int32_t *__restrict__ coll, int ncb,
                                                         int32_t *__restrict__ child_oct,
@@ -692,8 +699,8 @@ __global__ __launch_bounds__(256) void k_oct_colleagues(BoxTable bt, const TreeS
         colleagues(bt, sum, coll, blockIdx.x * 256 + threadIdx.x);
         return;
     }
-    oct_tables(bt, sum, child_oct, parent_oct, l2l_cnt, l2l_list, list_stride, zr,
-               ((int)blockIdx.x - ncb) * 256 + threadIdx.x, ((int)gridDim.x - ncb) * 256);
+    links_oct_tables(bt, sum, child_oct, parent_oct, l2l_cnt, l2l_list, list_stride, zr,
+                     ((int)blockIdx.x - ncb) * 256 + threadIdx.x, ((int)gridDim.x - ncb) * 256);
 }
 
 // Near lists of the leaves: ion ranges, stride entries per box.  The near
@@ -970,7 +977,6 @@ void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64
 {
     const int nblk = tree_blocks(ntot);
     k_tree_emit<<<nblk, 256, 0, st>>>(cs, roots, keys, ntot, leaf_size, rep_mask, box_end, scanned, nblk, bt, sum);
-    k_tree_links<<<ceil_div(nbox, 128), 128, 0, st>>>(bt, sum);
 }
 
 void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t *coll, int32_t *vtab, int stride,

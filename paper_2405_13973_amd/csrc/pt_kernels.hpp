@@ -270,9 +270,12 @@ void launch_tree_count(const CrystalDev *cs, const uint64_t *keys, int ntot, int
                        int32_t *box_end, uint32_t *blockcnt, uint32_t *partial, uint32_t *total,
                        const uint32_t *sort_err, TreeSummary *sum, const Caps *check, unsigned long long *bbox,
                        int nc, hipStream_t st);
+// launch_tree_build writes the box table except its links (parent, child,
+// nchild), which launch_lists adds.
 void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64_t *keys, int ntot, int leaf_size,
                        const uint32_t *rep_mask, const int32_t *box_end, const uint32_t *scanned, const BoxTable &bt,
                        const TreeSummary *sum, int nbox, hipStream_t st);
+// The tree links, the colleagues, the octant tables, the V and near lists.
 // Also counts the near-field work items {leaf, first target, range begin,
 // range end}: item_off (nbox, scanned in place to offsets), src_items (nbox),
 // n_items (device total).  launch_p2p_items then writes them into work.
