@@ -10,9 +10,11 @@ the leaf size is tuned too: for each candidate leaf size the smallest such
 p, then the fastest pair.
 
 Prints one JSON line: value = ion-steps/s of the mixed-precision form (or
---precision fp64), roofline of the dominant kernel (M2L on the matrix
-cores, or the P2P kernel on the vector ALUs) from HIP events over the timed
-region, and the CPU oracle timed on a bounded sample of the same workload.
+--precision fp64) over the timed steps as the library runs them (no
+instrumentation), roofline of the dominant kernel (M2L on the matrix cores,
+or the P2P kernel on the vector ALUs) from HIP events over a second timed
+run of the same steps from the same state that records the phase events,
+and the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -685,8 +687,8 @@ def main():
         err_end = rms_rel(c.compute_forces(), F_end)
         results[prec] = dict(p=p, leaf=leaf, share=share, fork=fork, err=err, err_end=err_end, seconds=el, phases=phases,
                              count=count, wc=wc, plain=plain)
-        log(f"  {prec}: p={p} leaf={leaf} {a.steps} steps in {el * 1e3:.2f} ms -> {cr.n * a.steps / el:.4g} "
-            f"ion-steps/s (without events {plain * 1e3:.2f} ms); rms err start {err:.2e} end {err_end:.2e}; "
+        log(f"  {prec}: p={p} leaf={leaf} {a.steps} steps in {plain * 1e3:.2f} ms -> {cr.n * a.steps / plain:.4g} "
+            f"ion-steps/s (with phase events {el * 1e3:.2f} ms); rms err start {err:.2e} end {err_end:.2e}; "
             f"phases(ms) " + " ".join(f"{k} {v:.3f}" for k, v in zip(PHASES, phases)) + f" over {count} evals")
 
     # direct-sum rate on the same crystal, for the FMM/direct comparison and
@@ -737,7 +739,9 @@ def main():
     rooflines["direct"]["frac"] = rooflines["direct"]["achieved"] / rooflines["direct"]["peak"]
     log(f"  direct sum: {dir_ms:.3f} ms per evaluation, {rooflines['direct']['achieved']:.1f} TFLOP/s "
         f"({100 * rooflines['direct']['frac']:.1f}% of the FP64 vector peak)")
-    value = cr.n * a.steps / main_r["seconds"]
+    # the library's throughput: the timed steps without phase events (the
+    # instrumented run of the same steps gives the phases and the rooflines)
+    value = cr.n * a.steps / main_r["plain"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -745,7 +749,7 @@ def main():
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": main_r["seconds"] * 1e3 / a.steps,
+        "ms_per_step": main_r["plain"] * 1e3 / a.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -763,7 +767,7 @@ def main():
             "force_evals_per_s": 1e3 / ph[6],
             "phase_ms": {k: float(v) for k, v in zip(PHASES, ph)},
             "rooflines": rooflines,
-            "ms_per_step_without_events": main_r["plain"] * 1e3 / a.steps,
+            "ms_per_step_with_phase_events": main_r["seconds"] * 1e3 / a.steps,
             "direct_sum_ms": float(dir_ms),
             "boxes": int(main_r["wc"][0]), "leaves": int(main_r["wc"][1]), "m2l_pairs": int(main_r["wc"][2]),
             "p2p_pairs": int(main_r["wc"][3]),
@@ -773,19 +777,19 @@ def main():
     }
     if "fp64" in results and a.precision == "mixed":
         f = results["fp64"]
-        out["details"]["fp64_ion_steps_per_s"] = cr.n * a.steps / f["seconds"]
+        out["details"]["fp64_ion_steps_per_s"] = cr.n * a.steps / f["plain"]
         out["details"]["fp64_p"] = f["p"]
         out["details"]["fp64_leaf_size"] = f["leaf"]
         out["details"]["fp64_near_share"] = f["share"]
         out["details"]["fp64_fork"] = f["fork"]
         out["details"]["fp64_rms_rel_force_err"] = f["err"]
         out["details"]["fp64_rms_rel_force_err_after_timed_steps"] = f["err_end"]
-        out["details"]["mixed_speedup_vs_fp64"] = f["seconds"] / main_r["seconds"]
+        out["details"]["mixed_speedup_vs_fp64"] = f["plain"] / main_r["plain"]
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cr, p, leaf, F_dir)
         out["details"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
     if not a.no_beams:
-        out["beams"] = bench_beams(ctx, c, cr, p, leaf, a.precision, a.steps, a.warmup, sync, main_r["seconds"])
+        out["beams"] = bench_beams(ctx, c, cr, p, leaf, a.precision, a.steps, a.warmup, sync, main_r["plain"])
     if not a.no_potential:
         out["potential"] = bench_potential(ctx, c, cr, p, leaf, a.precision)
     if not a.no_diagnostics:

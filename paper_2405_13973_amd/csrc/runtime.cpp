@@ -892,6 +892,10 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             // near field on the second stream, which is faster there)
             PT_HIP(hipEventRecord(ctx->ev_fork, st));
             PT_HIP(hipStreamWaitEvent(ns, ctx->ev_fork, 0));
+            // the near field is submitted first, so that a host slower than
+            // the device (a profiler, say) does not hold it back behind the
+            // far branch's launches
+            PT_TRY(near_field(st));
             launch_m2m<T>(bt, dsum, p, cap, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, narrow, ns);
             launch_m2l_emit(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, m2l_bucket, ns);
             mark(ctx, 2, ns);
@@ -906,7 +910,6 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
                           phi, s, 1, ns, poff);
             mark(ctx, 5, ns);
             PT_HIP(hipEventRecord(ctx->ev_join, ns));
-            PT_TRY(near_field(st));
             PT_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
             finish();
             return PT_OK;
