@@ -443,10 +443,10 @@ def bench_ensemble(a, ctx, sync):
     ctx.synchronize()
     sync()
     el = time.perf_counter() - t0
-    # per-phase times from a few more, instrumented steps (phase timing waits
-    # for each evaluation's events, so it stays out of the timed region)
-    ctx.set_timing(True)
-    native.step_batch(cs, [3] * len(cs))
+    # per-phase times from a few more, instrumented steps (the events of every
+    # TIMING_EVERY-th evaluation, as for config 3), outside the timed region
+    ctx.set_timing(True, every=TIMING_EVERY)
+    native.step_batch(cs, [2 * TIMING_EVERY] * len(cs))
     sync()
     phases = ctx.phase_times()
     ctx.set_timing(False)
