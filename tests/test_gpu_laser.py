@@ -93,6 +93,26 @@ def test_beam_mode_with_fmm_and_batch_equals_alone(ctx):
         assert np.array_equal(a["photons"], b["photons"])
 
 
+def test_beam_kick_adds_near_partials_beside_the_far_field(monkeypatch):
+    """Leaves of 128 ions: the near field runs beside the far field and the beam
+    variant of the kick adds the near-field partials to the far field itself;
+    the states and photon counts equal those of the schedule with the near
+    field after the far field (the partials added by the far-field kernel), bit
+    for bit."""
+    say("beam mode: kick-side near-field partials vs the serial schedule")
+    cr = crystal(3000, 61, strong_beams())
+    out = {}
+    for conc in ("0", "1"):
+        monkeypatch.setenv("PT_NEAR_CONCURRENT", conc)
+        with native.Context(0) as c2:
+            k = make(c2, cr, "fmm", 8, 128, "mixed")
+            k.step(3)
+            out[conc] = k.read_state()
+    a, b = out["0"], out["1"]
+    assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+    assert np.array_equal(a["photons"], b["photons"]) and int(a["photons"].sum()) > 0
+
+
 def test_invalid_beam_parameters(ctx):
     say("beam mode: invalid parameters")
     cr = crystal(10, 7, strong_beams())
