@@ -15,6 +15,8 @@
 //   near(T)     for a leaf T: the ion ranges of T's colleagues (leaf or not) and
 //               of the leaf colleagues of T's ancestors -- every ion pair not
 //               served by a multipole-to-local conversion
+#include <type_traits>
+
 #include "pt_common.hpp"
 #include "pt_kernels.hpp"
 
@@ -88,6 +90,7 @@ __device__ void scan_down_chunk(uint32_t *__restrict__ a, int n, const uint32_t 
 constexpr int kSortTB = 256;
 constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortTB * kSortItems;
+constexpr int kSortWideN = 400000;  // keys from which a pass takes 2 kSortItems keys per thread
 
 __global__ __launch_bounds__(kSortTB) void k_radix_hist(const uint64_t *__restrict__ keys, int n, int shift,
                                                         uint32_t *__restrict__ hist, int nblk)
@@ -172,7 +175,7 @@ constexpr int kSpinMax = 1 << 20;
 
 // KEYS: the keys (and values) are computed here from the root cubes and
 // written out, rather than read.
-template <bool KEYS>
+template <bool KEYS, int ITEMS>
 __global__ __launch_bounds__(kSortTB) void k_radix_prepare(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                            KeySource src, int n, int passes, int first,
                                                            uint32_t *__restrict__ ghist,
@@ -189,13 +192,13 @@ __global__ __launch_bounds__(kSortTB) void k_radix_prepare(uint64_t *__restrict_
     if constexpr (KEYS) {
         // the root cubes of the crystals of this tile (batch ions are in
         // crystal order), before any key of the tile needs them
-        const int i0 = blockIdx.x * kSortTile, i1 = min(n, i0 + kSortTile) - 1;
+        const int i0 = blockIdx.x * kSortTB * ITEMS, i1 = min(n, i0 + kSortTB * ITEMS) - 1;
         const int c0 = src.ion_crystal[i0], c1 = src.ion_crystal[i1];
         for (int c = c0 + tid; c <= c1; c += kSortTB) src.roots[c] = root_of(src.bbox, bbox_stride(src.nc), c);
     }
     __syncthreads();
-    for (int r = 0; r < kSortItems; ++r) {
-        const int i = blockIdx.x * kSortTile + r * kSortTB + tid;
+    for (int r = 0; r < ITEMS; ++r) {
+        const int i = (blockIdx.x * ITEMS + r) * kSortTB + tid;
         if (i < n) {
             uint64_t key;
             if constexpr (KEYS) {
@@ -261,6 +264,7 @@ __global__ void k_sort_refine(uint64_t *__restrict__ keys, uint32_t *__restrict_
     for (int i = k; i < e; ++i) gather_slot(cs, ion_crystal, n, sp, i, vals[i]);
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kSortTB) void k_radix_pass(const uint64_t *__restrict__ kin,
                                                         const uint32_t *__restrict__ vin,
                                                         uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
@@ -271,25 +275,25 @@ __global__ __launch_bounds__(kSortTB) void k_radix_pass(const uint64_t *__restri
 {
     if (halt && *halt) return;  // set before the sort starts: every workgroup returns, none waits
     constexpr int NW = kSortTB / 64;
-    __shared__ uint32_t wcnt[kSortItems][NW][256];  // digit counts per (round, wave), then their prefixes
+    __shared__ uint32_t wcnt[ITEMS][NW][256];  // digit counts per (round, wave), then their prefixes
     __shared__ uint32_t base_s[256];
     __shared__ uint32_t lds_w[NW + 1];
     __shared__ int tile_s;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int shift = 8 * pass;
     if (tid == 0) tile_s = (int)atomicAdd(&ctr[pass], 1u);
-    for (int r = 0; r < kSortItems; ++r)
+    for (int r = 0; r < ITEMS; ++r)
         for (int q = 0; q < NW; ++q) wcnt[r][q][tid] = 0;
     __syncthreads();
     const int tile = tile_s;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    uint64_t key[kSortItems];
-    uint32_t val[kSortItems], dig[kSortItems];
-    int rnk[kSortItems];
-    bool ok[kSortItems];
+    uint64_t key[ITEMS];
+    uint32_t val[ITEMS], dig[ITEMS];
+    int rnk[ITEMS];
+    bool ok[ITEMS];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const int i = tile * kSortTile + r * kSortTB + tid;
+    for (int r = 0; r < ITEMS; ++r) {
+        const int i = (tile * ITEMS + r) * kSortTB + tid;
         ok[r] = i < n;
         key[r] = ok[r] ? kin[i] : 0ull;
         val[r] = ok[r] ? vin[i] : 0u;
@@ -307,7 +311,7 @@ __global__ __launch_bounds__(kSortTB) void k_radix_pass(const uint64_t *__restri
     __syncthreads();
     // thread d: exclusive prefix of digit d over (round, wave), tile total
     uint32_t run = 0;
-    for (int r = 0; r < kSortItems; ++r)
+    for (int r = 0; r < ITEMS; ++r)
         for (int q = 0; q < NW; ++q) {
             const uint32_t c = wcnt[r][q][tid];
             wcnt[r][q][tid] = run;
@@ -343,7 +347,7 @@ __global__ __launch_bounds__(kSortTB) void k_radix_pass(const uint64_t *__restri
     base_s[tid] = gex + (uint32_t)excl;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r)
+    for (int r = 0; r < ITEMS; ++r)
         if (ok[r]) {
             const uint32_t pos = base_s[dig[r]] + wcnt[r][w][dig[r]] + rnk[r];
             kout[pos] = key[r];
@@ -929,19 +933,29 @@ int launch_radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, in
                       uint32_t *state, const int32_t *halt, const KeySource *keys, hipStream_t st)
 {
     if (passes > kMaxPasses || first < 0 || first > passes || n <= 0) return -1;
-    const int ntile = sort_blocks(n);
-    uint32_t *ghist = state, *ctr = state + kMaxPasses * 256, *err = ctr + kMaxPasses;
-    uint64_t *flags = (uint64_t *)(state + kMaxPasses * 256 + kMaxPasses + 2);  // 8-byte aligned
-    if (keys)
-        k_radix_prepare<true><<<ntile, kSortTB, 0, st>>>(k0, v0, *keys, n, passes, first, ghist, flags, ntile, halt);
+    auto run = [&](auto items_tag) {
+        constexpr int ITEMS = decltype(items_tag)::value;
+        const int ntile = ceil_div(n, kSortTB * ITEMS);  // at most sort_blocks(n): the workspace fits
+        uint32_t *ghist = state, *ctr = state + kMaxPasses * 256, *err = ctr + kMaxPasses;
+        uint64_t *flags = (uint64_t *)(state + kMaxPasses * 256 + kMaxPasses + 2);  // 8-byte aligned
+        if (keys)
+            k_radix_prepare<true, ITEMS>
+                <<<ntile, kSortTB, 0, st>>>(k0, v0, *keys, n, passes, first, ghist, flags, ntile, halt);
+        else
+            k_radix_prepare<false, ITEMS>
+                <<<ntile, kSortTB, 0, st>>>(k0, v0, KeySource{}, n, passes, first, ghist, flags, ntile, halt);
+        for (int p = first; p < passes; ++p) {
+            const bool odd = (p - first) % 2;
+            k_radix_pass<ITEMS><<<ntile, kSortTB, 0, st>>>(odd ? k1 : k0, odd ? v1 : v0, odd ? k0 : k1,
+                                                           odd ? v0 : v1, n, p, ghist, flags, ntile, ctr, err, halt);
+        }
+    };
+    // large batches take tiles of 8 keys per thread: fewer tiles in each
+    // pass's look-back; below that, 4 keep more workgroups on the chip
+    if (n >= kSortWideN)
+        run(std::integral_constant<int, 2 * kSortItems>{});
     else
-        k_radix_prepare<false><<<ntile, kSortTB, 0, st>>>(k0, v0, KeySource{}, n, passes, first, ghist, flags, ntile,
-                                                          halt);
-    for (int p = first; p < passes; ++p) {
-        const bool odd = (p - first) % 2;
-        k_radix_pass<<<ntile, kSortTB, 0, st>>>(odd ? k1 : k0, odd ? v1 : v0, odd ? k0 : k1, odd ? v0 : v1, n, p, ghist,
-                                                flags, ntile, ctr, err, halt);
-    }
+        run(std::integral_constant<int, kSortItems>{});
     return (passes - first) % 2;  // 1: the result is in (k1, v1)
 }
 

@@ -161,6 +161,31 @@ def test_tree_bit_exact(ctx, n, s):
         assert np.array_equal(T[k], R[k]), k
 
 
+def test_large_batch_sort_bit_exact_and_ordered_after_queued_steps(ctx):
+    """450,000 ions, above the size from which the radix passes take tiles of 8
+    keys per thread: the measured evaluation's tree equals the oracle's bit for
+    bit; after queued steps (the top-digit sort and its refinement) the
+    permutation is one and orders the ions' keys by (key, ion)."""
+    n = 450000
+    say(f"large-batch sort n={n}")
+    cr = ball(n, 901, R=1e-3)
+    c = make(ctx, cr, "fmm", 4, 64, "mixed")
+    c.compute_forces()
+    T = c.export_tree()
+    R = O.tree(cr.pos, 64)
+    assert np.array_equal(T["key"], R["key"]) and np.array_equal(T["perm"], R["perm"])
+    assert np.array_equal(T["ion_begin"], R["ion_begin"]) and np.array_equal(T["level"], R["level"])
+    c.step(3)
+    T = c.export_tree()
+    c.destroy()
+    perm = T["perm"].astype(np.int64)  # ion at each sorted slot; keys are per ion
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    ks = T["key"][perm]
+    up = ks[1:] > ks[:-1]
+    tie = ks[1:] == ks[:-1]
+    assert np.all(up | (tie & (perm[1:] > perm[:-1])))
+
+
 def test_tree_bit_exact_clumps(ctx):
     say("tree clumps")
     g = inputs.rng(31)
