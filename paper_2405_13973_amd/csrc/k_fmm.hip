@@ -434,15 +434,20 @@ __global__ void k_xlate_reduce(const TreeSummary *__restrict__ sum, int level, i
 // Near field (P2P) of one work item per 256-thread workgroup (grid-stride
 // over the items): up to 64 targets of a leaf against the sources of a run of
 // its near ranges.  The ranges are concatenated and staged through LDS
-// kP2PStage sources at a time as FP64 positions, so the pair loop reads only
-// LDS and a barrier pair serves hundreds of sources rather than one leaf.
-// Each pair's separation is an FP64 difference rounded once to T: close
-// pairs keep full relative precision (offsets rounded to FP32 first would
-// carry an absolute error of order 1e-7 of the box size into every
-// separation, and the rare very close pairs of random crystals dominate an
-// RMS force error).  r^-3 is the FP32 hardware reciprocal square root (1
-// ulp) cubed in the mixed form, and the hardware FP64 estimate refined as in
-// the direct sum in the FP64 form.  An item with nt targets gives each
+// kP2PStage sources at a time, so the pair loop reads only LDS and a barrier
+// pair serves hundreds of sources rather than one leaf.  FP64 form: staged
+// FP64 positions, FP64 separations.  Mixed form: staged as 31-bit fixed-point
+// coordinates in the crystal's root cube (offsets from the cube's corner made
+// in FP64, one quantum = W / 2^31), so that a separation is an exact integer
+// difference converted once to FP32: its error is at most a quantum (about
+// 4e-10 of the root side) whatever the pair's distance, where offsets from a
+// leaf centre rounded to FP32 would carry ~1e-7 of the box size into every
+// separation (the rare very close pairs of random crystals then dominate the
+// RMS force error).  The loop works in quanta (r^2 offset by the softening
+// in quanta^2) and the partials are scaled back to metres when written.
+// r^-3 is the FP32 hardware reciprocal square root (1 ulp) cubed in the mixed
+// form, and the hardware FP64 estimate refined as in the direct sum in the
+// FP64 form.  An item with nt targets gives each
 // target floor(256 / nt) threads (phases), which take source blocks round
 // robin; within a block sources are summed plainly and each block is added
 // to the phase's total, with Kahan compensation in FP32 (plainly in FP64).
@@ -454,9 +459,17 @@ __global__ void k_xlate_reduce(const TreeSummary *__restrict__ sum, int level, i
 constexpr int kP2PStage = 512;
 constexpr int kP2PThreads = 256;  // four waves share one staged source tile
 
-// Added to every FP32 near-field r^2 (m^2): 1/r^3 <= 1e36 stays finite; at
-// 0.1 micrometre the relative change is 1e-10, far below FP32 rounding.
+// Added to every FP32 near-field r^2 (m^2, in quanta^2 in the loop): 1/r^3
+// stays finite; at 0.1 micrometre the relative change is 1e-10, far below
+// FP32 rounding.
 constexpr double kSoft2 = 1e-24;
+
+// A coordinate offset d >= 0 within the root cube as a 31-bit fixed-point
+// integer (s = 2^31 / W quanta per metre; truncated, clamped to the cube).
+__device__ inline uint32_t p2p_quant(double d, double s)
+{
+    return (uint32_t)fmin(fmax(d * s, 0.0), 2147483647.0);
+}
 // Added to every FP64 near-field r^2 (m^2): below the rounding of any r^2
 // above 2^-626, and the weight at r = 0 (about 2^1020) stays finite.
 constexpr double kSoft2F64 = 0x1p-680;
@@ -466,7 +479,8 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
                                                      const double *__restrict__ sp, int ntot,
                                                      const int2 *__restrict__ near, int stride,
                                                      const int4 *__restrict__ work, const uint32_t *__restrict__ n_items_p,
-                                                     T *__restrict__ part, int *__restrict__ queue)
+                                                     T *__restrict__ part, int *__restrict__ queue,
+                                                     const RootCube *__restrict__ roots)
 {
     if (sum->halt) return;
     const int n_items = (int)*n_items_p;
@@ -478,6 +492,8 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
     // unit's LDS when the two kernels run side by side
     __shared__ double2 sxy[kP2PStage];
     __shared__ double szz[kP2PStage];
+    // the mixed form's staged fixed-point coordinates reuse the (x, y) pairs' space
+    uint4 *const sq = reinterpret_cast<uint4 *>(sxy);
     __shared__ int pre_s[kNearMax + 1];  // prefix of the item's range lengths
     __shared__ int beg_s[kNearMax];      // first ion of each range minus its prefix
     __shared__ int total_s;
@@ -506,6 +522,25 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
         const int ti = tid % nt, ph = tid / nt;             // ph >= nph: idle thread
         const int k = w.y + ti;
         const double xi = sp[k], yi = sp[ntot + k], zi = sp[2 * ntot + k];
+        // Mixed form: separations are differences of 31-bit fixed-point
+        // coordinates in the crystal's root cube (one quantum is W / 2^31; the
+        // difference of two such integers is exact), converted to FP32 and
+        // kept in quanta until the partials are scaled back to metres.
+        RootCube rc{};
+        double qs = 0.0;
+        uint32_t qx = 0, qy = 0, qz = 0;
+        float soft_q = 0.0f, back2 = 0.0f, back1 = 0.0f;
+        if constexpr (sizeof(T) == 4) {
+            rc = roots[bt.crystal[b]];
+            qs = 2147483648.0 / rc.W;
+            qx = p2p_quant(xi - rc.o[0], qs);
+            qy = p2p_quant(yi - rc.o[1], qs);
+            qz = p2p_quant(zi - rc.o[2], qs);
+            const double qm = rc.W / 2147483648.0;  // metres per quantum
+            soft_q = (float)(kSoft2 / (qm * qm));
+            back2 = (float)(1.0 / (qm * qm));
+            back1 = (float)(1.0 / qm);
+        }
         const int nr = min(w.w - w.z, kNearMax);
         if (tid < 64) {  // prefix of the range lengths, by the first wave
             int total = 0;
@@ -568,8 +603,13 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
 #pragma unroll
             for (int u = 0; u < kU; ++u)
                 if (js[u] >= 0) {
-                    sxy[tid + NT * u] = make_double2(sx[u], sy[u]);
-                    szz[tid + NT * u] = sz[u];
+                    if constexpr (sizeof(T) == 4) {
+                        sq[tid + NT * u] = make_uint4(p2p_quant(sx[u] - rc.o[0], qs), p2p_quant(sy[u] - rc.o[1], qs),
+                                                      p2p_quant(sz[u] - rc.o[2], qs), 0u);
+                    } else {
+                        sxy[tid + NT * u] = make_double2(sx[u], sy[u]);
+                        szz[tid + NT * u] = sz[u];
+                    }
                 }
             __syncthreads();
             for (int q0 = ph < nph ? ph * blk : n; q0 < n; q0 += nph * blk) {
@@ -577,8 +617,18 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
                 T px = 0, py = 0, pz = 0, pv = 0;
 #pragma unroll 4
                 for (int q = q0; q < q1; ++q) {
-                    const double2 v = sxy[q];
-                    const T dx = (T)(xi - v.x), dy = (T)(yi - v.y), dz = (T)(zi - szz[q]);
+                    T dx, dy, dz;
+                    if constexpr (sizeof(T) == 4) {
+                        const uint4 v = sq[q];
+                        dx = (float)(int32_t)(qx - v.x);
+                        dy = (float)(int32_t)(qy - v.y);
+                        dz = (float)(int32_t)(qz - v.z);
+                    } else {
+                        const double2 v = sxy[q];
+                        dx = xi - v.x;
+                        dy = yi - v.y;
+                        dz = zi - szz[q];
+                    }
                     // r = 0 (the target itself or a coincident ion) must give a
                     // finite 1/r^3, whose contribution is then exactly zero since
                     // dx = dy = dz = 0: r^2 carries a tiny offset (folded into
@@ -587,10 +637,10 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
                     T rinv = T(0), ww;
                     bool apart = true;
                     if constexpr (sizeof(T) == 4) {
-                        const T r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, float(kSoft2))));
+                        const T r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, soft_q)));
                         rinv = __builtin_amdgcn_rsqf(r2);  // 1 ulp
                         ww = rinv * rinv * rinv;
-                        if constexpr (POT) apart = r2 > float(kSoft2);
+                        if constexpr (POT) apart = r2 > soft_q;
                     } else {
                         // r^-3 = y0^3 (1 + 3/2 e + 15/8 e^2), r^-1 = y0 (1 + e/2 + 3/8 e^2),
                         // e = 1 - r2 y0^2, from the hardware estimate y0 (relative
@@ -651,6 +701,12 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
                 if constexpr (POT) av += hp[h * nt + ti];
             }
             T *dst = part + ((size_t)it * 64 + ti) * NC;
+            if constexpr (sizeof(T) == 4) {  // quanta back to metres
+                ax *= back2;
+                ay *= back2;
+                az *= back2;
+                if constexpr (POT) av *= back1;
+            }
             dst[0] = ax;
             dst[1] = ay;
             dst[2] = az;
@@ -837,14 +893,16 @@ void launch_downward(const BoxTable &bt, const TreeSummary *sum, int p, const Ca
 template <typename T>
 void launch_near(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, const int2 *near, int stride,
                  const int4 *work, const uint32_t *n_items, int cap_items, T *part, bool pot, int max_grid, int *queue,
-                 hipStream_t st)
+                 const RootCube *roots, hipStream_t st)
 {
     if (cap_items <= 0) return;
     const int grid = std::min(cap_items, max_grid);
     if (pot)
-        k_p2p<T, true><<<grid, kP2PThreads, 0, st>>>(bt, sum, sp, ntot, near, stride, work, n_items, part, queue);
+        k_p2p<T, true>
+            <<<grid, kP2PThreads, 0, st>>>(bt, sum, sp, ntot, near, stride, work, n_items, part, queue, roots);
     else
-        k_p2p<T, false><<<grid, kP2PThreads, 0, st>>>(bt, sum, sp, ntot, near, stride, work, n_items, part, queue);
+        k_p2p<T, false>
+            <<<grid, kP2PThreads, 0, st>>>(bt, sum, sp, ntot, near, stride, work, n_items, part, queue, roots);
 }
 
 size_t near_lds_bytes()
@@ -886,7 +944,8 @@ void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, in
                                      const int2 *, const int32_t *, const uint32_t *, const int32_t *, T *, bool,    \
                                      hipStream_t);                                                                 \
     template void launch_near<T>(const BoxTable &, const TreeSummary *, const double *, int, const int2 *, int,      \
-                                 const int4 *, const uint32_t *, int, T *, bool, int, int *, hipStream_t);         \
+                                 const int4 *, const uint32_t *, int, T *, bool, int, int *, const RootCube *,     \
+                                 hipStream_t);                                                                     \
     template void launch_far<T>(const BoxTable &, const TreeSummary *, const double *, int, int, int, const T *,     \
                                 const T *, const uint32_t *, const int32_t *, const T *, const uint32_t *, double *, \
                                 double *, int, int, hipStream_t, int2 *);

@@ -336,9 +336,10 @@ void launch_downward(const BoxTable &bt, const TreeSummary *sum, int p, const Ca
 // items from *queue (zero before the launch) or, with queue NULL, stride over
 // them.
 template <typename T>
+// roots: the crystals' root cubes (the mixed form's fixed-point coordinates).
 void launch_near(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, const int2 *near, int stride,
                  const int4 *work, const uint32_t *n_items, int cap_items, T *part, bool pot, int max_grid, int *queue,
-                 hipStream_t st);
+                 const RootCube *roots, hipStream_t st);
 // Near-field workgroups per compute unit while the far field runs beside the
 // near field: with four, two M2L GEMM workgroups still fit in every compute
 // unit's LDS, whichever kernel reaches the unit first.  When the near field

@@ -878,7 +878,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             // items from a queue; alone, one workgroup per item (no queue: its
             // atomics would serialise over the many small items of small leaves)
             launch_near<T>(bt, dsum, sp, ntot, near, stride, work, total + 1, n_items, (T *)ppart, phi != nullptr,
-                           max_grid, concurrent ? p2p_queue : nullptr, on);
+                           max_grid, concurrent ? p2p_queue : nullptr, roots, on);
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][1], on));
             ctx->near_timed[ctx->ring_cur] = ctx->timing;
             return PT_OK;
