@@ -437,13 +437,13 @@ __global__ void k_xlate_reduce(const TreeSummary *__restrict__ sum, int level, i
 // kP2PStage sources at a time, so the pair loop reads only LDS and a barrier
 // pair serves hundreds of sources rather than one leaf.  FP64 form: staged
 // FP64 positions, FP64 separations.  Mixed form: staged as 31-bit fixed-point
-// coordinates in the crystal's root cube (offsets from the cube's corner made
-// in FP64, one quantum = W / 2^31), so that a separation is an exact integer
-// difference converted once to FP32: its error is at most a quantum (about
-// 4e-10 of the root side) whatever the pair's distance, where offsets from a
-// leaf centre rounded to FP32 would carry ~1e-7 of the box size into every
-// separation (the rare very close pairs of random crystals then dominate the
-// RMS force error).  The loop works in quanta (r^2 offset by the softening
+// coordinates in the target leaf's near frame (a cube about the leaf's centre
+// that holds all its near sources; offsets made in FP64, one quantum = the
+// frame side / 2^31), so that a separation is an exact integer difference
+// converted once to FP32: its error is at most a quantum (about 1e-9 of the
+// leaf's side) whatever the pair's distance, where offsets rounded to FP32
+// would carry ~1e-7 of the box size into every separation (the rare very
+// close pairs of random crystals then dominate the RMS force error).  The loop works in quanta (r^2 offset by the softening
 // in quanta^2) and the partials are scaled back to metres when written.
 // r^-3 is the FP32 hardware reciprocal square root (1 ulp) cubed in the mixed
 // form, and the hardware FP64 estimate refined as in the direct sum in the
@@ -464,8 +464,8 @@ constexpr int kP2PThreads = 256;  // four waves share one staged source tile
 // FP32 rounding.
 constexpr double kSoft2 = 1e-24;
 
-// A coordinate offset d >= 0 within the root cube as a 31-bit fixed-point
-// integer (s = 2^31 / W quanta per metre; truncated, clamped to the cube).
+// A coordinate offset d >= 0 within a frame of side 2^31 / s as a 31-bit
+// fixed-point integer (s quanta per metre; truncated, clamped to the frame).
 __device__ inline uint32_t p2p_quant(double d, double s)
 {
     return (uint32_t)fmin(fmax(d * s, 0.0), 2147483647.0);
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
                                                      const int2 *__restrict__ near, int stride,
                                                      const int4 *__restrict__ work, const uint32_t *__restrict__ n_items_p,
                                                      T *__restrict__ part, int *__restrict__ queue,
-                                                     const RootCube *__restrict__ roots)
+                                                     const double *__restrict__ near_ext)
 {
     if (sum->halt) return;
     const int n_items = (int)*n_items_p;
@@ -523,20 +523,23 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
         const int k = w.y + ti;
         const double xi = sp[k], yi = sp[ntot + k], zi = sp[2 * ntot + k];
         // Mixed form: separations are differences of 31-bit fixed-point
-        // coordinates in the crystal's root cube (one quantum is W / 2^31; the
-        // difference of two such integers is exact), converted to FP32 and
-        // kept in quanta until the partials are scaled back to metres.
-        RootCube rc{};
+        // coordinates in the leaf's near frame (the cube of half side
+        // near_ext[b] about the leaf's centre, which holds every near source;
+        // one quantum is 2 near_ext / 2^31, and the difference of two such
+        // integers is exact), converted to FP32 and kept in quanta until the
+        // partials are scaled back to metres.
+        double4 fc{};
         double qs = 0.0;
         uint32_t qx = 0, qy = 0, qz = 0;
         float soft_q = 0.0f, back2 = 0.0f, back1 = 0.0f;
         if constexpr (sizeof(T) == 4) {
-            rc = roots[bt.crystal[b]];
-            qs = 2147483648.0 / rc.W;
-            qx = p2p_quant(xi - rc.o[0], qs);
-            qy = p2p_quant(yi - rc.o[1], qs);
-            qz = p2p_quant(zi - rc.o[2], qs);
-            const double qm = rc.W / 2147483648.0;  // metres per quantum
+            fc = bt.geo[b];
+            fc.w = near_ext[b];  // half side of the frame
+            qs = 1073741824.0 / fc.w;
+            qx = p2p_quant(xi - fc.x + fc.w, qs);
+            qy = p2p_quant(yi - fc.y + fc.w, qs);
+            qz = p2p_quant(zi - fc.z + fc.w, qs);
+            const double qm = fc.w / 1073741824.0;  // metres per quantum
             soft_q = (float)(kSoft2 / (qm * qm));
             back2 = (float)(1.0 / (qm * qm));
             back1 = (float)(1.0 / qm);
@@ -604,8 +607,9 @@ __global__ __launch_bounds__(kP2PThreads) void k_p2p(BoxTable bt, const TreeSumm
             for (int u = 0; u < kU; ++u)
                 if (js[u] >= 0) {
                     if constexpr (sizeof(T) == 4) {
-                        sq[tid + NT * u] = make_uint4(p2p_quant(sx[u] - rc.o[0], qs), p2p_quant(sy[u] - rc.o[1], qs),
-                                                      p2p_quant(sz[u] - rc.o[2], qs), 0u);
+                        sq[tid + NT * u] =
+                            make_uint4(p2p_quant(sx[u] - fc.x + fc.w, qs), p2p_quant(sy[u] - fc.y + fc.w, qs),
+                                       p2p_quant(sz[u] - fc.z + fc.w, qs), 0u);
                     } else {
                         sxy[tid + NT * u] = make_double2(sx[u], sy[u]);
                         szz[tid + NT * u] = sz[u];
@@ -893,16 +897,16 @@ void launch_downward(const BoxTable &bt, const TreeSummary *sum, int p, const Ca
 template <typename T>
 void launch_near(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, const int2 *near, int stride,
                  const int4 *work, const uint32_t *n_items, int cap_items, T *part, bool pot, int max_grid, int *queue,
-                 const RootCube *roots, hipStream_t st)
+                 const double *near_ext, hipStream_t st)
 {
     if (cap_items <= 0) return;
     const int grid = std::min(cap_items, max_grid);
     if (pot)
         k_p2p<T, true>
-            <<<grid, kP2PThreads, 0, st>>>(bt, sum, sp, ntot, near, stride, work, n_items, part, queue, roots);
+            <<<grid, kP2PThreads, 0, st>>>(bt, sum, sp, ntot, near, stride, work, n_items, part, queue, near_ext);
     else
         k_p2p<T, false>
-            <<<grid, kP2PThreads, 0, st>>>(bt, sum, sp, ntot, near, stride, work, n_items, part, queue, roots);
+            <<<grid, kP2PThreads, 0, st>>>(bt, sum, sp, ntot, near, stride, work, n_items, part, queue, near_ext);
 }
 
 size_t near_lds_bytes()
@@ -944,7 +948,7 @@ void launch_far(const BoxTable &bt, const TreeSummary *sum, const double *sp, in
                                      const int2 *, const int32_t *, const uint32_t *, const int32_t *, T *, bool,    \
                                      hipStream_t);                                                                 \
     template void launch_near<T>(const BoxTable &, const TreeSummary *, const double *, int, const int2 *, int,      \
-                                 const int4 *, const uint32_t *, int, T *, bool, int, int *, const RootCube *,     \
+                                 const int4 *, const uint32_t *, int, T *, bool, int, int *, const double *,       \
                                  hipStream_t);                                                                     \
     template void launch_far<T>(const BoxTable &, const TreeSummary *, const double *, int, int, int, const T *,     \
                                 const T *, const uint32_t *, const int32_t *, const T *, const uint32_t *, double *, \

@@ -742,7 +742,9 @@ __device__ inline int p2p_src_items(const int2 *row, int cnt, int32_t *cut)
 // included), then the leaf colleagues of each ancestor from the parent up
 // (slot order, the ancestor itself excluded) -- compacted with ballots,
 // staged in LDS and written out coalesced; then its near-field work items
-// are counted.
+// are counted, and near_ext gets the largest per-axis distance from the
+// leaf's centre to a point of its near boxes (the frame of the mixed near
+// field's fixed-point coordinates).
 __global__ __launch_bounds__(256) void k_box_lists(BoxTable bt, const TreeSummary *__restrict__ sum,
                                                    const int32_t *__restrict__ coll,
                                                    const int32_t *__restrict__ child_oct, int32_t *__restrict__ vtab,
@@ -750,7 +752,8 @@ __global__ __launch_bounds__(256) void k_box_lists(BoxTable bt, const TreeSummar
                                                    uint32_t *__restrict__ cnt_ob, uint32_t *__restrict__ op_total,
                                                    int stride, int2 *__restrict__ near, int32_t *__restrict__ near_cnt,
                                                    uint32_t *__restrict__ items, int32_t *__restrict__ src_items,
-                                                   int32_t *__restrict__ cuts, int64_t *__restrict__ pairs)
+                                                   int32_t *__restrict__ cuts, int64_t *__restrict__ pairs,
+                                                   double *__restrict__ near_ext)
 {
     __shared__ int32_t win_s[kWin];
     __shared__ uint32_t per_op[kM2LOps];
@@ -807,9 +810,11 @@ __global__ __launch_bounds__(256) void k_box_lists(BoxTable bt, const TreeSummar
     const int lane = tid & 63;
     int cnt = 0;
     long long srcs = 0;
+    double ext = 0.0;  // largest per-axis distance from b's centre to a point of a near box
     if (leaf && tid < 64) {
         const int nanc = nanc_s;
         const uint64_t below = (1ull << lane) - 1ull;
+        const double4 gb = bt.geo[b];
         auto append = [&](int Q) {
             const bool v = Q >= 0;
             const uint64_t m = __ballot(v);
@@ -818,6 +823,8 @@ __global__ __launch_bounds__(256) void k_box_lists(BoxTable bt, const TreeSummar
                 const int2 rg = make_int2(bt.begin[Q], bt.end[Q]);
                 row_s[at] = rg;
                 srcs += rg.y - rg.x;
+                const double4 gq = bt.geo[Q];
+                ext = fmax(ext, fmax(fmax(fabs(gq.x - gb.x), fabs(gq.y - gb.y)), fabs(gq.z - gb.z)) + 0.5 * gq.w);
             }
             cnt += __popcll(m);
         };
@@ -833,7 +840,10 @@ __global__ __launch_bounds__(256) void k_box_lists(BoxTable bt, const TreeSummar
         }
         cnt = min(cnt, min(stride, kNearMax));  // stride = 27 + 26 x (levels - 1) bounds cnt
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) srcs += __shfl_xor(srcs, off);
+        for (int off = 32; off > 0; off >>= 1) {
+            srcs += __shfl_xor(srcs, off);
+            ext = fmax(ext, __shfl_xor(ext, off));
+        }
     }
     __syncthreads();
     if (tid < kM2LOps) {
@@ -860,6 +870,7 @@ __global__ __launch_bounds__(256) void k_box_lists(BoxTable bt, const TreeSummar
             src_items[b] = si;
             items[b] = (uint32_t)(si * ((nt + 63) / 64));
             pairs[b] = nt * srcs - nt;  // near-field pairs of the leaf (self excluded)
+            near_ext[b] = ext;
         }
     }
 }
@@ -997,13 +1008,13 @@ void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t 
                   int2 *near, int32_t *near_cnt, int64_t *near_pairs, int32_t *child_oct, int32_t *parent_oct,
                   uint32_t *l2l_cnt, int32_t *l2l_list, const ZeroRegions &zr, uint32_t *item_off,
                   int32_t *src_items, int32_t *cuts, const int2 *slots, uint32_t *pcnt, uint32_t *cnt_ob,
-                  uint32_t *op_total, hipStream_t st)
+                  uint32_t *op_total, double *near_ext, hipStream_t st)
 {
     const int ncb = ceil_div(nbox * kNeigh, 256);
     k_oct_colleagues<<<ncb + ceil_div(nbox, 256), 256, 0, st>>>(bt, sum, coll, ncb, child_oct, parent_oct, l2l_cnt,
                                                                 l2l_list, nbox, zr);
     k_box_lists<<<nbox, 256, 0, st>>>(bt, sum, coll, child_oct, vtab, slots, pcnt, cnt_ob, op_total, stride, near,
-                                      near_cnt, item_off, src_items, cuts, near_pairs);
+                                      near_cnt, item_off, src_items, cuts, near_pairs, near_ext);
 }
 
 void launch_p2p_items(const BoxTable &bt, TreeSummary *sum, int nbox, const int32_t *near_cnt, int stride,

@@ -279,7 +279,9 @@ void launch_tree_build(const CrystalDev *cs, const RootCube *roots, const uint64
 // Also counts the near-field work items {leaf, first target, range begin,
 // range end}: item_off (nbox, scanned in place to offsets), src_items (nbox),
 // n_items (device total).  launch_p2p_items then writes them into work.
-// Work counts: near_pairs (nbox) = near-field pairs per leaf.
+// Work counts: near_pairs (nbox) = near-field pairs per leaf.  near_ext
+// (nbox, leaves only): the largest per-axis distance from a leaf's centre to
+// a point of its near boxes.
 // L2L buckets: the boxes of levels >= 3 by tree level and octant,
 // l2l_list[o * nbox + level_start[l] + i] for i < l2l_cnt[8 l + o] (order
 // within a bucket unspecified: every box's result is computed alone);
@@ -298,7 +300,7 @@ void launch_lists(const BoxTable &bt, const TreeSummary *sum, int nbox, int32_t 
                   int2 *near, int32_t *near_cnt, int64_t *near_pairs, int32_t *child_oct, int32_t *parent_oct,
                   uint32_t *l2l_cnt, int32_t *l2l_list, const ZeroRegions &zr, uint32_t *item_off,
                   int32_t *src_items, int32_t *cuts, const int2 *slots, uint32_t *pcnt, uint32_t *cnt_ob,
-                  uint32_t *op_total, hipStream_t st);
+                  uint32_t *op_total, double *near_ext, hipStream_t st);
 // cuts (stride per box): first near range of each source item of a leaf.
 // check (nullable, a queued evaluation): near-field items (total[1]) and M2L
 // pairs (total[2]) must fit their capacities, else the run halts here and no
@@ -336,10 +338,11 @@ void launch_downward(const BoxTable &bt, const TreeSummary *sum, int p, const Ca
 // items from *queue (zero before the launch) or, with queue NULL, stride over
 // them.
 template <typename T>
-// roots: the crystals' root cubes (the mixed form's fixed-point coordinates).
+// near_ext: per leaf the half side of the frame of the mixed form's
+// fixed-point coordinates (launch_lists).
 void launch_near(const BoxTable &bt, const TreeSummary *sum, const double *sp, int ntot, const int2 *near, int stride,
                  const int4 *work, const uint32_t *n_items, int cap_items, T *part, bool pot, int max_grid, int *queue,
-                 const RootCube *roots, hipStream_t st);
+                 const double *near_ext, hipStream_t st);
 // Near-field workgroups per compute unit while the far field runs beside the
 // near field: with four, two M2L GEMM workgroups still fit in every compute
 // unit's LDS, whichever kernel reaches the unit first.  When the near field

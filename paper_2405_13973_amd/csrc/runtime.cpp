@@ -769,6 +769,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
     PT_TRY(ws_get(ctx, "src_items", sizeof(int32_t) * (size_t)nbox, &src_items));
     int64_t *near_pairs;
     PT_TRY(ws_get(ctx, "near_pairs", sizeof(int64_t) * (size_t)nbox, &near_pairs));
+    double *near_ext;
+    PT_TRY(ws_get(ctx, "near_ext", sizeof(double) * (size_t)nbox, &near_ext));
     int32_t *cuts;
     PT_TRY(ws_get(ctx, "p2p_cuts", sizeof(int32_t) * (size_t)stride * nbox, &cuts));
     uint32_t *m2l_pcnt, *m2l_cnt_ob, *m2l_op_total;
@@ -794,7 +796,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         zr.n[3] = m2l_op_total_words() / 2;
         launch_lists(bt, dsum, nbox, coll, vtab, stride, near, near_cnt, near_pairs, child_oct, parent_oct, l2l_cnt,
                      l2l_list, zr, item_off, src_items, cuts, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, m2l_op_total,
-                     st);
+                     near_ext, st);
     }
     // M2L pairs: counted with the lists and scanned here, so that their
     // number comes back with the near-field item count
@@ -878,7 +880,7 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             // items from a queue; alone, one workgroup per item (no queue: its
             // atomics would serialise over the many small items of small leaves)
             launch_near<T>(bt, dsum, sp, ntot, near, stride, work, total + 1, n_items, (T *)ppart, phi != nullptr,
-                           max_grid, concurrent ? p2p_queue : nullptr, roots, on);
+                           max_grid, concurrent ? p2p_queue : nullptr, near_ext, on);
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][1], on));
             ctx->near_timed[ctx->ring_cur] = ctx->timing;
             return PT_OK;
