@@ -434,41 +434,41 @@ void launch_m2l_emit(const BoxTable &bt, const TreeSummary *sum, int nbox, const
 }
 
 // Row blocks of 16 per workgroup: as many as fit the LDS share of one
-// workgroup (two per compute unit beside the near field), balanced over the
-// row groups.
+// workgroup (two per compute unit beside the near field), at most max_rb,
+// balanced over the row groups.
 template <typename T>
-static int m2l_row_blocks(int Kp, int &nrg)
+static int m2l_row_blocks(int Kp, int max_rb, int &nrg)
 {
     const int blocks = Kp / 16;
     const size_t per_block = (size_t)16 * (Kp + 16 / sizeof(T)) * sizeof(T);
     const int fit = std::max(1, (int)(kM2LLdsBudget / per_block));
-    nrg = ceil_div(blocks, std::min(fit, kM2LMaxRowBlocks));
+    nrg = ceil_div(blocks, std::max(1, std::min({fit, kM2LMaxRowBlocks, max_rb})));
     return ceil_div(blocks, nrg);
 }
 
 template <typename T>
-size_t m2l_gemm_lds(int Kp)
+size_t m2l_gemm_lds(int Kp, int max_rb)
 {
     int nrg;
-    const int nrb = m2l_row_blocks<T>(Kp, nrg);
+    const int nrb = m2l_row_blocks<T>(Kp, max_rb, nrg);
     return (size_t)nrb * 16 * (Kp + 16 / sizeof(T)) * sizeof(T) + (size_t)8 * Kp;
 }
 
 template <typename T>
-int m2l_per_cu(int Kp, size_t lds_beside)
+int m2l_per_cu(int Kp, int max_rb, size_t lds_beside)
 {
-    const size_t lds = m2l_gemm_lds<T>(Kp) + 2 * (kOps + 1) * sizeof(int32_t);
+    const size_t lds = m2l_gemm_lds<T>(Kp, max_rb) + 2 * (kOps + 1) * sizeof(int32_t);
     const size_t room = kLdsPerCU > lds_beside ? kLdsPerCU - lds_beside : 0;
     return std::max(1, std::min(kM2LMaxPerCU, (int)(room / lds)));
 }
 
 template <typename T>
-void launch_m2l_gemm(const TreeSummary *sum, int Kp, int nbox, int grid, const int32_t *chunk_off,
+void launch_m2l_gemm(const TreeSummary *sum, int Kp, int max_rb, int nbox, int grid, const int32_t *chunk_off,
                      const int32_t *op_beg, const int4 *bucket, const T *A, const T *M, T *R, hipStream_t st)
 {
     int nrg;
-    const int nrb = m2l_row_blocks<T>(Kp, nrg);
-    const size_t lds = m2l_gemm_lds<T>(Kp);
+    const int nrb = m2l_row_blocks<T>(Kp, max_rb, nrg);
+    const size_t lds = m2l_gemm_lds<T>(Kp, max_rb);
     const int steps = Kp / (4 * (16 / (int)sizeof(T)));
     // order 11 (144 coefficients) runs with its step count fixed at compile time
     constexpr int kFixed = 144 / (4 * (16 / (int)sizeof(T)));
@@ -498,13 +498,13 @@ void launch_m2l_sum(const TreeSummary *sum, int nbox, int Kp, const uint32_t *pa
                                                                                       L);
 }
 
-template int m2l_per_cu<float>(int, size_t);
-template int m2l_per_cu<double>(int, size_t);
-template size_t m2l_gemm_lds<float>(int);
-template size_t m2l_gemm_lds<double>(int);
-template void launch_m2l_gemm<float>(const TreeSummary *, int, int, int, const int32_t *, const int32_t *,
+template int m2l_per_cu<float>(int, int, size_t);
+template int m2l_per_cu<double>(int, int, size_t);
+template size_t m2l_gemm_lds<float>(int, int);
+template size_t m2l_gemm_lds<double>(int, int);
+template void launch_m2l_gemm<float>(const TreeSummary *, int, int, int, int, const int32_t *, const int32_t *,
                                      const int4 *, const float *, const float *, float *, hipStream_t);
-template void launch_m2l_gemm<double>(const TreeSummary *, int, int, int, const int32_t *, const int32_t *,
+template void launch_m2l_gemm<double>(const TreeSummary *, int, int, int, int, const int32_t *, const int32_t *,
                                       const int4 *, const double *, const double *, double *, hipStream_t);
 template void launch_m2l_sum<float>(const TreeSummary *, int, int, const uint32_t *, const uint32_t *,
                                     const float *, float *, hipStream_t);

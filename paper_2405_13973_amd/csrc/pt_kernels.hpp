@@ -383,15 +383,19 @@ void launch_list_scans(const TreeSummary *sum, int nbox, uint32_t *pcnt, uint32_
 void launch_m2l_emit(const BoxTable &bt, const TreeSummary *sum, int nbox, const int32_t *vtab, const int2 *slots,
                      const uint32_t *pair_off, const uint32_t *ob_off, int4 *bucket, hipStream_t st);
 // LDS of one GEMM workgroup: at most this much for the operator rows, and at
-// most this many row blocks of 16 (compiled variants).
+// most this many row blocks of 16 (compiled variants).  max_rb caps the row
+// blocks further: kM2LSmallRowBlocks for batches whose near field outweighs
+// M2L (three workgroups then fit a compute unit beside the near field),
+// kM2LMaxRowBlocks otherwise (fewer operator reloads per product).
 constexpr size_t kM2LLdsBudget = 48 << 10;
 constexpr int kM2LMaxRowBlocks = 6;
+constexpr int kM2LSmallRowBlocks = 3;
 template <typename T>
-size_t m2l_gemm_lds(int Kp);
+size_t m2l_gemm_lds(int Kp, int max_rb);
 // A: the 64 base operators, row-major Kp x Kp each (row = output coefficient),
 // zero padded; M: nbox + 1 expansion rows (row nbox zero); R: npairs x Kp.
 template <typename T>
-void launch_m2l_gemm(const TreeSummary *sum, int Kp, int nbox, int grid, const int32_t *chunk_off,
+void launch_m2l_gemm(const TreeSummary *sum, int Kp, int max_rb, int nbox, int grid, const int32_t *chunk_off,
                      const int32_t *op_beg, const int4 *bucket, const T *A, const T *M, T *R, hipStream_t st);
 // L = per box the sum of its rows of R in order (pair_off: the scanned pcnt).
 template <typename T>
@@ -404,7 +408,7 @@ void launch_m2l_sum(const TreeSummary *sum, int nbox, int Kp, const uint32_t *pa
 constexpr size_t kLdsPerCU = 160 << 10;
 constexpr int kM2LMaxPerCU = 4;
 template <typename T>
-int m2l_per_cu(int Kp, size_t lds_beside);
+int m2l_per_cu(int Kp, int max_rb, size_t lds_beside);
 
 // noalloc.hip: the fixed scratch of pt_compute_forces_noalloc (direct sum of
 // one crystal of at most kNoAllocMaxIons ions).

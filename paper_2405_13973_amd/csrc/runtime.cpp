@@ -873,6 +873,12 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         hipStream_t ns = concurrent ? ctx->near_stream : st;
         // translations that leave room for their waves beside a large near field
         const bool narrow = f && concurrent && near_cap >= 4;
+        // M2L workgroups of fewer row blocks beside a near field that
+        // outweighs M2L (the batch has fewer than kNearFirstPairs V pairs):
+        // three fit a compute unit beside it and keep pace at any share;
+        // with many V pairs M2L is the longer branch and the larger row
+        // groups reload each operator fewer times (measured both ways)
+        const int m2l_rb = concurrent && (double)n_pairs < kNearFirstPairs ? kM2LSmallRowBlocks : kM2LMaxRowBlocks;
         auto near_field = [&](hipStream_t on) -> pt_status {
             if (ctx->timing) PT_HIP(hipEventRecord(ctx->ev_near[ctx->ring_cur][0], on));
             const int max_grid = concurrent ? near_cap * ctx->num_cu : 16384;
@@ -901,8 +907,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
             launch_m2m<T>(bt, dsum, p, cap, m2m, tb.oct_slots, child_oct, (T *)M, (T *)xl_part, narrow, ns);
             launch_m2l_emit(bt, dsum, nbox, vtab, ctx->tables.slots, m2l_pcnt, m2l_cnt_ob, m2l_bucket, ns);
             mark(ctx, 2, ns);
-            const int m2l_grid = ctx->num_cu * m2l_per_cu<T>(Kp, near_cap * near_lds_bytes());
-            launch_m2l_gemm<T>(dsum, Kp, nbox, m2l_grid, m2l_chunk_off, m2l_op_beg, m2l_bucket, m2l, (const T *)M,
+            const int m2l_grid = ctx->num_cu * m2l_per_cu<T>(Kp, m2l_rb, near_cap * near_lds_bytes());
+            launch_m2l_gemm<T>(dsum, Kp, m2l_rb, nbox, m2l_grid, m2l_chunk_off, m2l_op_beg, m2l_bucket, m2l, (const T *)M,
                                (T *)m2l_R, ns);
             mark(ctx, 3, ns);
             launch_m2l_sum<T>(dsum, nbox, Kp, m2l_pcnt, total + 2, (const T *)m2l_R, (T *)L, ns);
@@ -931,8 +937,8 @@ static pt_status eval_field(pt_ctx *ctx, Batch &b, const pt_force_params &fp, do
         if (concurrent && !early) PT_TRY(fork());
         mark(ctx, 2);
         const int m2l_grid =
-            ctx->num_cu * m2l_per_cu<T>(Kp, concurrent ? near_cap * near_lds_bytes() : 0);
-        launch_m2l_gemm<T>(dsum, Kp, nbox, m2l_grid, m2l_chunk_off, m2l_op_beg, m2l_bucket, m2l, (const T *)M,
+            ctx->num_cu * m2l_per_cu<T>(Kp, m2l_rb, concurrent ? near_cap * near_lds_bytes() : 0);
+        launch_m2l_gemm<T>(dsum, Kp, m2l_rb, nbox, m2l_grid, m2l_chunk_off, m2l_op_beg, m2l_bucket, m2l, (const T *)M,
                            (T *)m2l_R, st);
         mark(ctx, 3);
         launch_m2l_sum<T>(dsum, nbox, Kp, m2l_pcnt, total + 2, (const T *)m2l_R, (T *)L, st);
