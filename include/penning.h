@@ -121,8 +121,10 @@ typedef struct {
  * maximum expansion degree p (1 <= p <= 20) and leaf size leaf_size (a box
  * is divided while it holds more than leaf_size ions, down to level 16).
  * precision 0: FP64 throughout.  precision 1: mixed -- FP32 expansions,
- * FP32 matrix-core M2L, FP32 near field with compensated sums; positions,
- * box-centre offsets and the integrator stay FP64. */
+ * FP32 matrix-core M2L, FP32 near field with compensated sums (separations
+ * from 31-bit fixed-point offsets in each leaf's near frame, exact to a
+ * quantum of about 1e-9 of the leaf side); positions, box-centre offsets and
+ * the integrator stay FP64. */
 typedef struct {
     int method;
     int p;
